@@ -1,0 +1,348 @@
+"""Seeded synthetic problems for the SA-AMG solver: matrices and right-hand sides.
+
+This module builds inputs only.  It holds none of the method's arithmetic and is the one
+module that both the GPU path and the CPU oracle receive their inputs from.
+
+All matrices are CSR with int32 row pointers and column indices (columns strictly ascending
+within each row, diagonal always stored) and float64 values.  Unknowns are numbered in
+natural lexicographic order with x running fastest.  Dirichlet boundary nodes are
+eliminated: only interior unknowns are kept, and couplings to boundary nodes contribute to
+the diagonal only.
+
+Problem families (the paper's test families are FE cubes with stretched or perturbed
+meshes, a heterogeneous reservoir model and wind-turbine pressure systems, Sec. 4; none of
+their meshes or data are available, so these are synthetic stand-ins of the same character):
+
+* ``fd5_stretched``  2-D 5-point finite-volume Laplacian, y spacing graded geometrically.
+* ``fd7_stretched``  3-D 7-point finite-volume Laplacian, z spacing graded geometrically
+  (the character of the stretched cube of Sec. 4.2 and the stretched wind meshes of Sec. 4.4).
+* ``q1_hex``         3-D 27-point trilinear (Q1) hexahedral stiffness matrix on a tensor mesh
+  with per-element coefficient kappa (the 27-point stencil of Sec. 1.2; random kappa over six
+  decades stands in for the heterogeneous permeability of Sec. 4.3).
+* ``periodic_*``     small periodic stencils used by the tests (circulant examples of Sec. 2.1).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from fractions import Fraction
+import itertools
+
+import numpy as np
+
+
+@dataclass
+class CsrProblem:
+    """A square sparse matrix in CSR form plus a description of how it was made."""
+
+    n: int
+    rp: np.ndarray   # int32 [n+1]
+    col: np.ndarray  # int32 [nnz]
+    val: np.ndarray  # float64 [nnz]
+    name: str = ""
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rp[-1])
+
+    def to_dense(self) -> np.ndarray:
+        d = np.zeros((self.n, self.n))
+        rows = np.repeat(np.arange(self.n), np.diff(self.rp))
+        d[rows, self.col] = self.val
+        return d
+
+
+def _csr_from_offsets(shape, offsets, coeffs, name):
+    """Assemble CSR from a structured stencil.
+
+    ``shape`` = unknowns per axis (x first).  ``offsets`` is a list of integer offset tuples
+    and ``coeffs[t]`` an array of the grid's shape holding the coefficient that couples each
+    unknown to its neighbour at ``offsets[t]``.  Entries whose neighbour falls outside the
+    grid are not stored.  Offsets must be listed so that the linear index offset ascends,
+    which makes the columns of every row ascend.
+    """
+    dims = len(shape)
+    n = int(np.prod(shape))
+    strides = [1]
+    for d in range(dims - 1):
+        strides.append(strides[-1] * shape[d])
+    lin = [sum(o[d] * strides[d] for d in range(dims)) for o in offsets]
+    order = np.argsort(lin, kind="stable")
+    offsets = [offsets[t] for t in order]
+    coeffs = [coeffs[t] for t in order]
+    # grid coordinates of every unknown, C order over reversed axes so x is fastest
+    grids = np.meshgrid(*[np.arange(s) for s in reversed(shape)], indexing="ij")
+    coords = [g.reshape(-1) for g in reversed(grids)]  # coords[d] for axis d, x fastest
+    valid = []
+    for o in offsets:
+        ok = np.ones(n, dtype=bool)
+        for d in range(dims):
+            c = coords[d] + o[d]
+            ok &= (c >= 0) & (c < shape[d])
+        valid.append(ok)
+    counts = np.zeros(n, dtype=np.int64)
+    for ok in valid:
+        counts += ok
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rp[1:])
+    nnz = int(rp[-1])
+    if nnz >= 2**31:
+        raise ValueError("nnz too large for int32 indices")
+    col = np.empty(nnz, dtype=np.int32)
+    val = np.empty(nnz, dtype=np.float64)
+    pos = rp[:-1].copy()
+    idx = np.arange(n, dtype=np.int64)
+    for t, o in enumerate(offsets):
+        ok = valid[t]
+        dst = pos[ok]
+        col[dst] = (idx[ok] + lin[order[t]]).astype(np.int32)
+        val[dst] = np.asarray(coeffs[t]).reshape(-1)[ok]
+        pos[ok] += 1
+    return CsrProblem(n, rp.astype(np.int32), col, val, name)
+
+
+def graded_spacing(nint: int, aspect: float) -> np.ndarray:
+    """Cell widths h_k = h * aspect**(k/nint - 1), k = 0..nint, with h = 1/(nint+1).
+
+    The interval below interior node k (1-based) is h_{k-1}, the one above is h_k.  The
+    finest cell, at the low boundary, has aspect 1:aspect against the uniform spacing h;
+    the last one is 1:1.
+    """
+    h = 1.0 / (nint + 1)
+    k = np.arange(nint + 1, dtype=np.float64)
+    return h * aspect ** (k / nint - 1.0)
+
+
+def fd5_stretched(nx: int = 64, ny: int = 64, aspect: float = 100.0) -> CsrProblem:
+    """2-D 5-point finite-volume Laplacian, x uniform (h = 1/(nx+1)), y graded.
+
+    Row (i, j): west/east coupling -dy_j/h, south -h/h_{j-1}, north -h/h_j with
+    dy_j = (h_{j-1} + h_j)/2; the diagonal is the sum of the magnitudes of all couplings,
+    including those to eliminated boundary nodes.  Symmetric by construction.
+    """
+    h = 1.0 / (nx + 1)
+    hy = graded_spacing(ny, aspect)                 # ny+1 widths
+    dy = 0.5 * (hy[:-1] + hy[1:])                   # ny interior control-volume heights
+    cx = dy / h                                     # per row j
+    cs = h / hy[:-1]                                # coupling to j-1 (below)
+    cn = h / hy[1:]                                 # coupling to j+1 (above)
+    shape = (nx, ny)
+    J = np.broadcast_to(np.arange(ny)[:, None], (ny, nx))  # [y, x] layout
+    cxg = cx[J]
+    csg = cs[J]
+    cng = cn[J]
+    diag = ((cxg + cxg) + csg) + cng
+    offs = [(0, -1), (-1, 0), (0, 0), (1, 0), (0, 1)]
+    coeffs = [-csg, -cxg, diag, -cxg, -cng]
+    return _csr_from_offsets(shape, offs, coeffs, f"fd5_stretched_{nx}x{ny}_a{aspect:g}")
+
+
+def fd7_stretched(n: int = 128, aspect: float = 1000.0, nx: int | None = None,
+                  ny: int | None = None) -> CsrProblem:
+    """3-D 7-point finite-volume Laplacian on n^3 unknowns, x/y uniform, z graded.
+
+    x/y couplings in layer k: -dz_k (face area h*dz_k over distance h); z couplings:
+    -h^2/h_{k-1} (below), -h^2/h_k (above); diagonal = sum of coupling magnitudes including
+    those to the eliminated boundary.  Symmetric by construction.
+    """
+    nx = n if nx is None else nx
+    ny = n if ny is None else ny
+    nz = n
+    h = 1.0 / (nx + 1)
+    hz = graded_spacing(nz, aspect)
+    dz = 0.5 * (hz[:-1] + hz[1:])
+    cxy = dz                                        # (h*dz)/h, kept exact as dz
+    cdn = (h * h) / hz[:-1]
+    cup = (h * h) / hz[1:]
+    K = np.broadcast_to(np.arange(nz)[:, None, None], (nz, ny, nx))
+    cxyg = cxy[K]
+    cdng = cdn[K]
+    cupg = cup[K]
+    diag = ((((cxyg + cxyg) + cxyg) + cxyg) + cdng) + cupg
+    offs = [(0, 0, -1), (0, -1, 0), (-1, 0, 0), (0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    coeffs = [-cdng, -cxyg, -cxyg, diag, -cxyg, -cxyg, -cupg]
+    return _csr_from_offsets((nx, ny, nz), offs, coeffs,
+                             f"fd7_stretched_{nx}x{ny}x{nz}_a{aspect:g}")
+
+
+def q1_element_matrix(hx, hy, hz):
+    """Trilinear hex element stiffness for -div(grad u) on an hx*hy*hz brick (kappa = 1).
+
+    K = (hy*hz/hx) k(x)m(x)m + (hx*hz/hy) m(x)k(x)m + (hx*hy/hz) m(x)m(x)k with the 1-D
+    stiffness k = [[1,-1],[-1,1]] and mass m = [[1/3,1/6],[1/6,1/3]].  Local node index
+    a = ax + 2*ay + 4*az.  Arguments may be Fractions (exact) or floats.
+    """
+    one = Fraction(1) if isinstance(hx, Fraction) else 1.0
+    k1 = [[one, -one], [-one, one]]
+    m1 = [[one / 3, one / 6], [one / 6, one / 3]]
+    K = [[None] * 8 for _ in range(8)]
+    for a in range(8):
+        ax, ay, az = a & 1, (a >> 1) & 1, (a >> 2) & 1
+        for b in range(8):
+            bx, by, bz = b & 1, (b >> 1) & 1, (b >> 2) & 1
+            K[a][b] = ((hy * hz / hx) * k1[ax][bx] * m1[ay][by] * m1[az][bz]
+                       + (hx * hz / hy) * m1[ax][bx] * k1[ay][by] * m1[az][bz]
+                       + (hx * hy / hz) * m1[ax][bx] * m1[ay][by] * k1[az][bz])
+    return K
+
+
+def q1_hex(ne: int = 100, kappa: np.ndarray | None = None, hx=None, hy=None, hz=None,
+           nex: int | None = None, ney: int | None = None) -> CsrProblem:
+    """27-point Q1 stiffness on an ne^3 element tensor mesh, Dirichlet boundary eliminated.
+
+    ``kappa`` holds one coefficient per element (element index x fastest); default 1.
+    Element sizes default to 1/ne (the unit cube).  The element matrix is formed exactly in
+    rational arithmetic when the sizes are Fractions, so entries that vanish exactly (the
+    axis neighbours of the isotropic cube) are stored as exact zeros.  The unknowns are the
+    (ne-1)^3 interior nodes, so the matrix has (3(ne-1)-2)^3 stored entries.
+    """
+    nex = ne if nex is None else nex
+    ney = ne if ney is None else ney
+    nez = ne
+    if hx is None:
+        hx = hy = hz = Fraction(1, ne)
+    K = q1_element_matrix(hx, hy, hz)
+    Kf = np.array([[float(K[a][b]) for b in range(8)] for a in range(8)])
+    if kappa is None:
+        kappa = np.ones(nex * ney * nez)
+    kap = np.asarray(kappa, dtype=np.float64).reshape(nez, ney, nex)   # [z, y, x]
+    nix, niy, niz = nex - 1, ney - 1, nez - 1
+    # interior node (i,j,k) 1-based; element (ex,ey,ez) 0-based spans nodes ex..ex+1
+    offs = list(itertools.product((-1, 0, 1), repeat=3))             # (dx,dy,dz)
+    coeffs = []
+    ii = np.arange(1, nix + 1)
+    jj = np.arange(1, niy + 1)
+    kk = np.arange(1, niz + 1)
+    for (dx, dy, dz) in offs:
+        c = np.zeros((niz, niy, nix))
+        for (a, b, cc) in itertools.product((0, 1), repeat=3):
+            # element with lower corner (i-1+a, j-1+b, k-1+cc); node local coords (1-a,..)
+            lx, ly, lz = 1 - a, 1 - b, 1 - cc
+            mx, my, mz = lx + dx, ly + dy, lz + dz
+            if not (0 <= mx <= 1 and 0 <= my <= 1 and 0 <= mz <= 1):
+                continue
+            la = lx + 2 * ly + 4 * lz
+            lb = mx + 2 * my + 4 * mz
+            kv = kap[np.ix_(kk - 1 + cc, jj - 1 + b, ii - 1 + a)]
+            c = c + kv * Kf[la, lb]
+        coeffs.append(c)
+    # coeffs arrays are [z,y,x]; _csr_from_offsets wants arrays in its own x-fastest layout
+    offs_xyz = [(dx, dy, dz) for (dx, dy, dz) in offs]
+    return _csr_from_offsets((nix, niy, niz), offs_xyz, coeffs,
+                             f"q1_hex_{nex}x{ney}x{nez}")
+
+
+def q1_random_kappa(ne: int = 100, seed: int = 3, lo: float = -3.0, hi: float = 3.0):
+    """Q1 cube with kappa_e = 10**u_e, u_e ~ U[lo, hi] i.i.d. from numpy PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u = rng.uniform(lo, hi, size=ne ** 3)
+    p = q1_hex(ne, kappa=10.0 ** u)
+    p.name = f"q1_randkappa_{ne}_s{seed}"
+    return p
+
+
+def q1_stretched_box(nint: int = 24, hz=Fraction(2)) -> CsrProblem:
+    """Q1 Poisson on 1 x 1 x hz elements (kappa = 1), nint^3 interior unknowns."""
+    ne = nint + 1
+    p = q1_hex(ne, hx=Fraction(1), hy=Fraction(1), hz=hz)
+    p.name = f"q1_box_{nint}_hz{hz}"
+    return p
+
+
+def periodic_stencil_2d(nx: int, ny: int, stencil: dict) -> CsrProblem:
+    """Periodic 2-D stencil (circulant); ``stencil`` maps (dx, dy) -> value."""
+    n = nx * ny
+    rows = []
+    for j in range(ny):
+        for i in range(nx):
+            ent = {}
+            for (dx, dy), v in stencil.items():
+                c = ((j + dy) % ny) * nx + (i + dx) % nx
+                ent[c] = ent.get(c, 0.0) + v
+            rows.append(sorted(ent.items()))
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    col = np.array([c for r in rows for c, _ in r], dtype=np.int32)
+    val = np.array([v for r in rows for _, v in r], dtype=np.float64)
+    return CsrProblem(n, rp, col, val, f"periodic_{nx}x{ny}")
+
+
+def from_dense(d: np.ndarray, keep_zero_pattern: np.ndarray | None = None) -> CsrProblem:
+    """CSR of a dense matrix; stores nonzeros, the diagonal, and any pattern entries given."""
+    d = np.asarray(d, dtype=np.float64)
+    n = d.shape[0]
+    pat = d != 0
+    pat[np.arange(n), np.arange(n)] = True
+    if keep_zero_pattern is not None:
+        pat |= keep_zero_pattern
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum(pat.sum(axis=1))
+    rr, cc = np.nonzero(pat)
+    return CsrProblem(n, rp, cc.astype(np.int32), d[rr, cc].astype(np.float64), "dense")
+
+
+def random_rhs(n: int, seed: int) -> np.ndarray:
+    """b_i ~ U(-1, 1) from numpy PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(-1.0, 1.0, size=n)
+
+
+# ---------------------------------------------------------------------------------------
+# Named workloads
+# ---------------------------------------------------------------------------------------
+
+def workload(name: str) -> CsrProblem:
+    """The named synthetic workloads.
+
+    * ``fd5_64x64_a100``   2-D 5-pt, 64x64 unknowns, aspect 1:100 (n = 4,096).
+    * ``fd7_128_a1000``    3-D 7-pt, 128^3 unknowns, aspect 1:1000 (n = 2,097,152).
+    * ``q1_100_randkappa`` 27-pt Q1, 100^3 elements, kappa = 10^U[-3,3] (n = 970,299).
+    * ``fd7_160_a1000``    3-D 7-pt, 160^3 unknowns, aspect 1:1000 (n = 4,096,000).
+    * ``q1_box24_hz2``     27-pt Q1 on 1x1x2 boxes, 24^3 unknowns (stress problem).
+    Any ``fd7_<n>_a<aspect>`` and ``fd5_<n>x<n>_a<aspect>`` is also accepted.
+    """
+    if name == "q1_100_randkappa":
+        return q1_random_kappa(100, seed=3)
+    if name == "q1_box24_hz2":
+        return q1_stretched_box(24, Fraction(2))
+    if name.startswith("fd7_"):
+        _, n, a = name.split("_")
+        return fd7_stretched(int(n), float(a[1:]))
+    if name.startswith("fd5_"):
+        _, nn, a = name.split("_")
+        nx, ny = nn.split("x")
+        return fd5_stretched(int(nx), int(ny), float(a[1:]))
+    if name.startswith("q1_") and name.endswith("_randkappa"):
+        return q1_random_kappa(int(name.split("_")[1]), seed=3)
+    raise KeyError(name)
+
+
+RHS_SEED = {"fd5_64x64_a100": 1, "fd7_128_a1000": 2, "q1_100_randkappa": 4,
+            "fd7_160_a1000": 5, "q1_box24_hz2": 7}
+
+
+def serving_requests(count: int = 256, seed: int = 6, smin: int = 16, smax: int = 96):
+    """Seeded request descriptions for the serving workload.
+
+    Each request is a 7-point z-stretched cube with aspect 10**U[1,3] or a 27-point random
+    kappa cube (u ~ U[-3,3]), chosen with probability 1/2, with side s ~ U{smin..smax}
+    unknowns per dimension (the 27-point cube then has s+1 elements per dimension).
+    Returns a list of dicts; ``build_request`` turns one into (CsrProblem, rhs).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for r in range(count):
+        kind = "fd7" if rng.uniform() < 0.5 else "q1"
+        s = int(rng.integers(smin, smax + 1))
+        aspect = float(10.0 ** rng.uniform(1.0, 3.0))
+        sub = int(rng.integers(0, 2**31 - 1))
+        out.append({"id": r, "kind": kind, "side": s, "aspect": aspect, "seed": sub})
+    return out
+
+
+def build_request(req: dict):
+    if req["kind"] == "fd7":
+        p = fd7_stretched(req["side"], req["aspect"])
+    else:
+        p = q1_random_kappa(req["side"] + 1, seed=req["seed"])
+    b = random_rhs(p.n, req["seed"] + 1)
+    return p, b
