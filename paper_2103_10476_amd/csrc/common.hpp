@@ -1,0 +1,121 @@
+// Internal definitions shared by the library's translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/saamg.h"
+
+namespace sa {
+
+// Failure inside the library: carries a status code; converted to the return value at the
+// C boundary.
+struct Error : std::runtime_error {
+  sa_status code;
+  Error(sa_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define SA_HIP(call)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      throw ::sa::Error(e_ == hipErrorOutOfMemory ? SA_ERR_OOM : SA_ERR_HIP,                \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                \
+  } while (0)
+
+#define SA_LAUNCH_CHECK() SA_HIP(hipGetLastError())
+
+constexpr int kBlock = 256;
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline unsigned grid_for(int64_t n, int block = kBlock) {
+  int64_t g = ceil_div(n, block);
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+// Stream-ordered device allocation (hipMallocAsync from the device's default pool, whose
+// release threshold is raised at first use so freed blocks are reused, not returned).
+void *dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void *p, hipStream_t s);
+
+// A typed device buffer owned by an Arena or held as a temporary.
+template <class T>
+struct DBuf {
+  T *p = nullptr;
+  int64_t n = 0;
+};
+
+// Owns a set of device allocations; frees them in its destructor (stream ordered).
+struct Arena {
+  hipStream_t stream = nullptr;
+  std::vector<void *> ptrs;
+  int64_t bytes = 0;
+  template <class T>
+  T *alloc(int64_t count) {
+    size_t b = (size_t)(count > 0 ? count : 1) * sizeof(T);
+    T *p = (T *)dev_alloc(b, stream);
+    ptrs.push_back(p);
+    bytes += (int64_t)b;
+    return p;
+  }
+  void release() {
+    for (void *p : ptrs) dev_free(p, stream);
+    ptrs.clear();
+    bytes = 0;
+  }
+  ~Arena() {
+    try {
+      release();
+    } catch (...) {
+    }
+  }
+};
+
+// Device CSR view.
+struct Csr {
+  int32_t n = 0, ncols = 0;
+  int64_t nnz = 0;
+  int32_t *rp = nullptr;
+  int32_t *col = nullptr;
+  double *val = nullptr;
+};
+
+struct CsrF {  // float copy of the values for the FP32 V-cycle
+  int32_t n = 0, ncols = 0;
+  int64_t nnz = 0;
+  const int32_t *rp = nullptr;
+  const int32_t *col = nullptr;
+  float *val = nullptr;
+};
+
+// Blocking readback of one value.
+template <class T>
+T read1(const T *dptr, hipStream_t s) {
+  T v;
+  SA_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
+  SA_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+// ---- primitives (scan.hip) ------------------------------------------------------------
+// out[0..n] = exclusive prefix sums of in[0..n-1], out[n] = total (out may alias in only
+// when in has n+1 slots).  Deterministic (integer).
+void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s);
+void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
+void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+void fill_f64(double *p, double v, int64_t n, hipStream_t s);
+void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
+
+// ---- vector kernels and the canonical inner product (blas.hip) --------------------------
+// dot: canonical tree (blocks of 4096, 256 lanes x 16 sequential, then pairwise halving),
+// result written to *res (device).  ws must hold ceil(n/4096) + ceil(n/4096^2) + 8 doubles.
+void dot_f64(const double *x, const double *y, int64_t n, double *res, double *ws,
+             hipStream_t s);
+int64_t dot_ws_size(int64_t n);
+
+}  // namespace sa

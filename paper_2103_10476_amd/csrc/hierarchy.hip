@@ -1,0 +1,751 @@
+// Host runtime and C ABI: hierarchy setup (Sec. 1.1 with the adaptations of Sec. 2), the
+// V-cycle of Algorithm 1 with Chebyshev/Jacobi smoothing (Sec. 4.1), and preconditioned CG.
+//
+// Control crosses to the host only at size readbacks (aggregate count, nnz of each new
+// matrix), the root-selection termination flags, error checks, and once per CG iteration
+// for the stopping test.  Level data never leaves the device.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace sa {
+
+thread_local std::string g_last_error;
+
+enum ErrBits {
+  E_STRUCT = 1,
+  E_NODIAG = 2,
+  E_NONFINITE = 4,
+  E_ZERO_FDIAG = 8,
+  E_LAMBDA = 16,
+  E_DIAG = 32,
+  E_CHOL = 64
+};
+
+constexpr int32_t kMaxDense = 8192;
+
+struct Level {
+  Csr A;                  // operator of this level
+  Csr As;                 // matrix the prolongator is built from (A, or D_B A D_B on level 0)
+  uint8_t *mask = nullptr;
+  int32_t *agg = nullptr;
+  uint8_t *is_root = nullptr;
+  int32_t nc = 0;
+  int32_t mis_rounds = 0;
+  Csr Abar;
+  double *invD = nullptr;
+  double *lam_d = nullptr, *omega_d = nullptr;
+  double lam = 0.0, omega = 0.0;
+  Csr P, R;
+  double *sm_invD = nullptr;
+  double *sm_lam_d = nullptr;
+  double sm_lam = 0.0;
+  double cheb_theta = 0.0;
+  std::vector<double> cheb_c1, cheb_c2;  // per Chebyshev step m = 1..deg-1
+  double jac_w = 0.0;
+  double *Ainv = nullptr;  // coarsest only: dense inverse, row-major
+  // FP32 copies (FP32 V-cycle)
+  float *Af = nullptr, *Pf = nullptr, *Rf = nullptr, *sm_invDf = nullptr;
+  // work vectors
+  double *f = nullptr, *u = nullptr, *r = nullptr, *d1 = nullptr, *d2 = nullptr;
+  float *ff = nullptr, *uf = nullptr, *rf = nullptr, *d1f = nullptr, *d2f = nullptr;
+};
+
+}  // namespace sa
+
+struct sa_hierarchy {
+  hipStream_t stream = nullptr;
+  sa_options opt{};
+  sa::Arena ar;
+  std::vector<sa::Level> lv;
+  int32_t *err = nullptr;
+  double setup_seconds = 0.0;
+  // solve workspace
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *zold = nullptr,
+         *w = nullptr, *dws = nullptr, *tmp64 = nullptr;
+  sa::PcgScalars *S = nullptr;
+  sa::PcgScalars *hS = nullptr;  // pinned host mirror
+  int32_t n = 0;
+  ~sa_hierarchy() {
+    if (hS) (void)hipHostFree(hS);
+  }
+};
+
+namespace sa {
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+static int32_t read_err(sa_hierarchy *h) { return read1(h->err, h->stream); }
+
+static void check_err(sa_hierarchy *h, int32_t mask_bits, sa_status code, const char *what) {
+  const int32_t e = read_err(h);
+  if (e & mask_bits) throw Error(code, what);
+}
+
+static double safeguard_mult(double sigma) {
+  return (sigma == 1.0 / 3.0) ? 2.0 : 4.0 / (3.0 * (1.0 - sigma));
+}
+
+static void validate_options(const sa_options &o) {
+  if (o.struct_size != sizeof(sa_options)) throw Error(SA_ERR_INVALID_ARG, "bad struct_size");
+  if (!(o.theta >= 0.0 && o.theta <= 1.0)) throw Error(SA_ERR_INVALID_ARG, "theta not in [0,1]");
+  if (o.max_levels < 1 || o.max_levels > 16) throw Error(SA_ERR_INVALID_ARG, "max_levels");
+  if (o.degree < 1 || o.degree > 16) throw Error(SA_ERR_INVALID_ARG, "degree");
+  if (o.power_iters < 1) throw Error(SA_ERR_INVALID_ARG, "power_iters");
+  if (!(o.cheb_ratio > 1.0)) throw Error(SA_ERR_INVALID_ARG, "cheb_ratio must exceed 1");
+  if (!(o.rtol > 0.0) || o.max_iter < 0) throw Error(SA_ERR_INVALID_ARG, "rtol/max_iter");
+  if (o.precision != SA_FP64 && o.precision != SA_FP32_VCYCLE)
+    throw Error(SA_ERR_INVALID_ARG, "precision");
+  if (o.variants & ~15u) throw Error(SA_ERR_INVALID_ARG, "unknown variant bits");
+}
+
+static void copy_in(void *dst, const void *src, size_t bytes, sa_location loc, hipStream_t s) {
+  if (!bytes) return;
+  SA_HIP(hipMemcpyAsync(dst, src, bytes,
+                        loc == SA_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+}
+
+static void chebyshev_scalars(Level &L, const sa_options &o) {
+  const double lam = L.sm_lam;
+  const double lo = lam / o.cheb_ratio;
+  const double thc = (lam + lo) * 0.5;
+  const double dlc = (lam - lo) * 0.5;
+  const double s1 = thc / dlc;
+  double rho = 1.0 / s1;
+  L.cheb_theta = thc;
+  L.cheb_c1.clear();
+  L.cheb_c2.clear();
+  for (int m = 1; m < o.degree; ++m) {
+    const double rho1 = 1.0 / (2.0 * s1 - rho);
+    L.cheb_c1.push_back(rho1 * rho);
+    L.cheb_c2.push_back((2.0 * rho1) / dlc);
+    rho = rho1;
+  }
+  L.jac_w = 4.0 / (3.0 * lam);
+}
+
+static Csr copy_csr(const Csr &a, Arena &ar, hipStream_t s) {
+  Csr c = a;
+  c.rp = ar.alloc<int32_t>(a.n + 1);
+  c.col = ar.alloc<int32_t>(a.nnz);
+  c.val = ar.alloc<double>(a.nnz);
+  SA_HIP(hipMemcpyAsync(c.rp, a.rp, sizeof(int32_t) * (a.n + 1), hipMemcpyDeviceToDevice, s));
+  SA_HIP(hipMemcpyAsync(c.col, a.col, sizeof(int32_t) * a.nnz, hipMemcpyDeviceToDevice, s));
+  SA_HIP(hipMemcpyAsync(c.val, a.val, sizeof(double) * a.nnz, hipMemcpyDeviceToDevice, s));
+  return c;
+}
+
+// Builds level l's prolongator and the next operator.  Returns false when the level has no
+// strong connection left (it becomes the coarsest).
+static bool build_level(sa_hierarchy *h, int l) {
+  const hipStream_t s = h->stream;
+  const sa_options &o = h->opt;
+  Level &L = h->lv[l];
+  Arena &ar = h->ar;
+  const int32_t n = L.A.n;
+  Arena tmp;
+  tmp.stream = s;
+  double *dval = tmp.alloc<double>(n);
+  find_diag(n, L.As.rp, L.As.col, L.As.val, dval, s);
+  L.mask = ar.alloc<uint8_t>(L.As.nnz);
+  int32_t *scount = tmp.alloc<int32_t>(n + 1);
+  strength(n, L.As.rp, L.As.col, L.As.val, dval, o.theta * o.theta, L.mask, scount, s);
+  int32_t *grp = nullptr, *gcol = nullptr;
+  strength_graph(n, L.As.rp, L.As.col, L.mask, scount, tmp, &grp, &gcol, s);
+  L.agg = ar.alloc<int32_t>(n);
+  L.is_root = ar.alloc<uint8_t>(n);
+  int32_t *root_vertex = nullptr;
+  L.nc = aggregate(n, grp, gcol, o.agg_order, o.seed, l, L.agg, L.is_root, tmp, &root_vertex,
+                   &L.mis_rounds, s);
+  if (L.nc == 0) return false;
+  if (L.nc >= n) throw Error(SA_ERR_COARSEN_STALLED, "coarsening stalled");
+  if (o.variants & SA_SPRSFY) sprsfy(n, L.As.rp, L.As.col, L.mask, L.agg, root_vertex, L.nc, s);
+  const bool one_norm = (o.variants & SA_1NORM) != 0;
+  L.invD = ar.alloc<double>(n);
+  lump(n, L.As.rp, L.As.col, L.As.val, L.mask, (o.variants & SA_OFFLMP) != 0, o.tau, one_norm,
+       safeguard_mult(o.sigma), ar, L.Abar, L.invD, h->err, s);
+  check_err(h, E_ZERO_FDIAG, SA_ERR_NONPOSITIVE_DIAG, "zero diagonal in the filtered matrix");
+  L.lam_d = ar.alloc<double>(2);
+  L.omega_d = L.lam_d + 1;
+  const bool unit = one_norm && o.one_norm_power == 0;
+  if (!unit) power_method(L.Abar, L.invD, o.power_iters, o.seed, l, 0, L.lam_d, s);
+  damping(L.lam_d, L.omega_d, unit, h->err, s);
+  check_err(h, E_LAMBDA, SA_ERR_NEGATIVE_EIGENVALUE, "eigenvalue estimate not positive");
+  prolongator(L.Abar, L.invD, L.agg, L.nc, L.omega_d, ar, L.P, s);
+  if (o.variants & SA_CNSTRNT) cnstrnt(L.P, L.agg, s);
+  return true;
+}
+
+static void setup_impl(sa_hierarchy *h, const sa_csr *A, const double *B) {
+  const double t0 = now_s();
+  const hipStream_t s = h->stream;
+  sa_options &o = h->opt;
+  validate_options(o);
+  if (!A || A->n < 0 || A->nnz < 0 || A->nnz >= (int64_t)INT32_MAX || !A->row_ptr ||
+      (A->nnz > 0 && (!A->col || !A->val)))
+    throw Error(SA_ERR_INVALID_ARG, "bad matrix argument");
+  if (A->n == 0) throw Error(SA_ERR_INVALID_ARG, "empty matrix");
+  const int32_t n = A->n;
+  h->n = n;
+  h->err = h->ar.alloc<int32_t>(4);
+  fill_i32(h->err, 0, 4, s);
+  h->lv.emplace_back();
+  Level &L0 = h->lv[0];
+  L0.A.n = L0.A.ncols = n;
+  L0.A.nnz = A->nnz;
+  L0.A.rp = h->ar.alloc<int32_t>(n + 1);
+  L0.A.col = h->ar.alloc<int32_t>(A->nnz);
+  L0.A.val = h->ar.alloc<double>(A->nnz);
+  copy_in(L0.A.rp, A->row_ptr, sizeof(int32_t) * (n + 1), A->loc, s);
+  copy_in(L0.A.col, A->col, sizeof(int32_t) * A->nnz, A->loc, s);
+  copy_in(L0.A.val, A->val, sizeof(double) * A->nnz, A->loc, s);
+  const int32_t rp0 = read1(L0.A.rp, s), rpn = read1(L0.A.rp + n, s);
+  if (rp0 != 0 || (int64_t)rpn != A->nnz) throw Error(SA_ERR_BAD_CSR, "row pointers do not span nnz");
+  validate_csr(n, L0.A.rp, L0.A.col, L0.A.val, h->err, s);
+  {
+    const int32_t e = read_err(h);
+    if (e & E_NONFINITE) throw Error(SA_ERR_INVALID_ARG, "non-finite matrix value");
+    if (e & E_STRUCT) throw Error(SA_ERR_BAD_CSR, "columns out of range or not ascending");
+    if (e & E_NODIAG) throw Error(SA_ERR_BAD_CSR, "missing diagonal");
+  }
+  L0.As = L0.A;
+  double *dB = nullptr;
+  if (B) {
+    std::vector<double> hb(n);
+    SA_HIP(hipMemcpyAsync(hb.data(), B, sizeof(double) * n,
+                          A->loc == SA_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost, s));
+    SA_HIP(hipStreamSynchronize(s));
+    bool scaled = false;
+    for (double v : hb) {
+      if (!(v != 0.0) || !std::isfinite(v))
+        throw Error(SA_ERR_INVALID_ARG, "nullspace entry zero or non-finite");
+      if (v != 1.0) scaled = true;
+    }
+    if (scaled) {
+      dB = h->ar.alloc<double>(n);
+      SA_HIP(hipMemcpyAsync(dB, hb.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+      L0.As.val = h->ar.alloc<double>(A->nnz);
+      scale_sym(n, L0.A.rp, L0.A.col, L0.A.val, dB, L0.As.val, s);
+      SA_HIP(hipStreamSynchronize(s));  // hb goes out of scope
+    }
+  }
+  for (int l = 0;; ++l) {
+    if (h->lv[l].A.n <= o.max_coarse || l + 1 >= o.max_levels) break;
+    if (!build_level(h, l)) {
+      Level &Lc = h->lv[l];
+      Lc.nc = 0;
+      Lc.mask = nullptr;
+      Lc.agg = nullptr;
+      Lc.is_root = nullptr;
+      break;
+    }
+    Level &L = h->lv[l];
+    if (l == 0 && dB) scale_rows(L.P, dB, s);
+    transpose(L.P, h->ar, L.R, s);
+    Csr Ac;
+    {
+      Arena tmp;
+      tmp.stream = s;
+      Csr AP;
+      spgemm(L.A, L.P, tmp, AP, s);
+      spgemm(L.R, AP, h->ar, Ac, s);
+    }
+    h->lv.emplace_back();
+    h->lv[l + 1].A = Ac;
+    h->lv[l + 1].As = Ac;
+  }
+  const int nl = (int)h->lv.size();
+  for (int l = 0; l + 1 < nl; ++l) {
+    Level &L = h->lv[l];
+    Arena tmp;
+    tmp.stream = s;
+    double *dval = tmp.alloc<double>(L.A.n);
+    find_diag(L.A.n, L.A.rp, L.A.col, L.A.val, dval, s);
+    L.sm_invD = h->ar.alloc<double>(L.A.n);
+    inv_diag(L.A.n, dval, L.sm_invD, h->err, s);
+    check_err(h, E_DIAG, SA_ERR_NONPOSITIVE_DIAG, "non-positive diagonal in a level operator");
+    L.sm_lam_d = h->ar.alloc<double>(1);
+    power_method(L.A, L.sm_invD, o.power_iters, o.seed, l, 1, L.sm_lam_d, s);
+    const double lam = read1(L.sm_lam_d, s);
+    if (!(lam > 0.0) || !std::isfinite(lam))
+      throw Error(SA_ERR_NEGATIVE_EIGENVALUE, "smoother eigenvalue estimate not positive");
+    L.sm_lam = lam * o.cheb_boost;
+    chebyshev_scalars(L, o);
+    if (L.lam_d) {
+      double lo[2];
+      SA_HIP(hipMemcpyAsync(lo, L.lam_d, sizeof(lo), hipMemcpyDeviceToHost, s));
+      SA_HIP(hipStreamSynchronize(s));
+      L.lam = lo[0];
+      L.omega = lo[1];
+    }
+  }
+  Level &Lc = h->lv[nl - 1];
+  if (Lc.A.n > kMaxDense)
+    throw Error(SA_ERR_COARSE_FACTOR, "coarsest level too large for the dense solver");
+  Lc.Ainv = h->ar.alloc<double>((int64_t)Lc.A.n * Lc.A.n);
+  coarse_inverse(Lc.A, Lc.Ainv, h->err, s);
+  check_err(h, E_CHOL, SA_ERR_COARSE_FACTOR, "coarse Cholesky pivot not positive");
+  // FP32 copies of the hierarchy for the FP32 V-cycle
+  const bool f32 = o.precision == SA_FP32_VCYCLE;
+  for (int l = 0; l < nl; ++l) {
+    Level &L = h->lv[l];
+    const int32_t m = L.A.n;
+    L.f = h->ar.alloc<double>(m);
+    L.u = h->ar.alloc<double>(m);
+    L.r = h->ar.alloc<double>(m);
+    L.d1 = h->ar.alloc<double>(m);
+    L.d2 = h->ar.alloc<double>(m);
+    if (f32) {
+      L.ff = h->ar.alloc<float>(m);
+      L.uf = h->ar.alloc<float>(m);
+      L.rf = h->ar.alloc<float>(m);
+      L.d1f = h->ar.alloc<float>(m);
+      L.d2f = h->ar.alloc<float>(m);
+      if (l + 1 < nl) {
+        L.Af = h->ar.alloc<float>(L.A.nnz);
+        cast_f64_to_f32(L.A.val, L.Af, L.A.nnz, s);
+        L.Pf = h->ar.alloc<float>(L.P.nnz);
+        cast_f64_to_f32(L.P.val, L.Pf, L.P.nnz, s);
+        L.Rf = h->ar.alloc<float>(L.R.nnz);
+        cast_f64_to_f32(L.R.val, L.Rf, L.R.nnz, s);
+        L.sm_invDf = h->ar.alloc<float>(m);
+        cast_f64_to_f32(L.sm_invD, L.sm_invDf, m, s);
+      }
+    }
+  }
+  h->x = h->ar.alloc<double>(n);
+  h->r = h->ar.alloc<double>(n);
+  h->z = h->ar.alloc<double>(n);
+  h->p = h->ar.alloc<double>(n);
+  h->q = h->ar.alloc<double>(n);
+  h->zold = h->ar.alloc<double>(n);
+  h->w = h->ar.alloc<double>(n);
+  h->tmp64 = h->ar.alloc<double>(std::max<int64_t>(n, kMaxDense));
+  h->dws = h->ar.alloc<double>(dot_ws_size(n));
+  h->S = h->ar.alloc<PcgScalars>(1);
+  SA_HIP(hipHostMalloc((void **)&h->hS, sizeof(PcgScalars), hipHostMallocDefault));
+  SA_HIP(hipStreamSynchronize(s));
+  h->setup_seconds = now_s() - t0;
+}
+
+// ---- V-cycle ---------------------------------------------------------------------------------
+template <class T>
+struct LevelView {
+  SpmvArgs<T> A, P, R;
+  const T *invD;
+  T *f, *u, *r, *d1, *d2;
+};
+
+static LevelView<double> view64(Level &L) {
+  LevelView<double> v;
+  v.A = {L.A.n, L.A.rp, L.A.col, L.A.val, nullptr};
+  v.P = {L.P.n, L.P.rp, L.P.col, L.P.val, nullptr};
+  v.R = {L.R.n, L.R.rp, L.R.col, L.R.val, nullptr};
+  v.invD = L.sm_invD;
+  v.f = L.f;
+  v.u = L.u;
+  v.r = L.r;
+  v.d1 = L.d1;
+  v.d2 = L.d2;
+  return v;
+}
+static LevelView<float> view32(Level &L) {
+  LevelView<float> v;
+  v.A = {L.A.n, L.A.rp, L.A.col, L.Af, nullptr};
+  v.P = {L.P.n, L.P.rp, L.P.col, L.Pf, nullptr};
+  v.R = {L.R.n, L.R.rp, L.R.col, L.Rf, nullptr};
+  v.invD = L.sm_invDf;
+  v.f = L.ff;
+  v.u = L.uf;
+  v.r = L.rf;
+  v.d1 = L.d1f;
+  v.d2 = L.d2f;
+  return v;
+}
+
+template <class T>
+static void smooth(sa_hierarchy *h, Level &L, LevelView<T> &v, const T *f, T *u, bool uzero) {
+  const hipStream_t s = h->stream;
+  const sa_options &o = h->opt;
+  const int32_t n = L.A.n;
+  SpmvArgs<T> A = v.A;
+  if (o.smoother == SA_JACOBI) {
+    const T w = (T)L.jac_w;
+    int sweep = 0;
+    if (uzero) {
+      jacobi_first<T>(n, f, v.invD, w, u, s);
+      sweep = 1;
+    }
+    for (; sweep < o.degree; ++sweep) {
+      A.x = u;
+      spmv_jacobi<T>(A, f, v.invD, w, v.d1, s);
+      SA_HIP(hipMemcpyAsync(u, v.d1, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+    }
+    return;
+  }
+  const T theta = (T)L.cheb_theta;
+  T *dc = v.d1, *dn = v.d2;
+  const T *rin;
+  if (uzero) {
+    cheb_first<T>(n, f, v.invD, theta, dc, u, o.degree == 1, s);
+    rin = f;
+  } else {
+    A.x = u;
+    spmv_cheb_start<T>(A, f, v.invD, theta, v.r, dc, s);
+    if (o.degree == 1) vec_add<T>(n, u, dc, s);
+    rin = v.r;
+  }
+  for (int m = 1; m < o.degree; ++m) {
+    A.x = dc;
+    const bool last = (m == o.degree - 1);
+    spmv_cheb_step<T>(A, rin, v.r, v.invD, (T)L.cheb_c1[m - 1], (T)L.cheb_c2[m - 1], u,
+                      uzero && m == 1, dn, last, s);
+    rin = v.r;
+    std::swap(dc, dn);
+  }
+}
+
+template <class T>
+static void coarse_apply(sa_hierarchy *h, Level &L, const T *f, T *u);
+template <>
+void coarse_apply<double>(sa_hierarchy *h, Level &L, const double *f, double *u) {
+  gemv_f64(L.A.n, L.Ainv, f, u, h->stream);
+}
+template <>
+void coarse_apply<float>(sa_hierarchy *h, Level &L, const float *f, float *u) {
+  double *f64 = h->tmp64;
+  double *u64 = L.u;
+  cast_f32_to_f64(f, f64, L.A.n, h->stream);
+  gemv_f64(L.A.n, L.Ainv, f64, u64, h->stream);
+  cast_f64_to_f32(u64, u, L.A.n, h->stream);
+}
+
+template <class T>
+static void vcycle(sa_hierarchy *h, int l, const T *f, T *u) {
+  Level &L = h->lv[l];
+  const int nl = (int)h->lv.size();
+  if (l + 1 == nl) {
+    coarse_apply<T>(h, L, f, u);
+    return;
+  }
+  LevelView<T> v;
+  if constexpr (sizeof(T) == 8) v = view64(L);
+  else v = view32(L);
+  LevelView<T> vc;
+  if constexpr (sizeof(T) == 8) vc = view64(h->lv[l + 1]);
+  else vc = view32(h->lv[l + 1]);
+  const hipStream_t s = h->stream;
+  smooth<T>(h, L, v, f, u, true);
+  SpmvArgs<T> A = v.A;
+  A.x = u;
+  spmv_resid<T>(A, f, v.r, s);
+  SpmvArgs<T> R = v.R;
+  R.x = v.r;
+  spmv_store<T>(R, vc.f, s);
+  vcycle<T>(h, l + 1, vc.f, vc.u);
+  SpmvArgs<T> P = v.P;
+  P.x = vc.u;
+  spmv_add<T>(P, u, s);
+  smooth<T>(h, L, v, f, u, false);
+}
+
+// z = M^{-1} r at the fine level, in the hierarchy's precision.
+static void precondition(sa_hierarchy *h, const double *r, double *z) {
+  Level &L0 = h->lv[0];
+  if (h->opt.precision == SA_FP32_VCYCLE && h->lv.size() > 1) {
+    cast_f64_to_f32(r, L0.ff, h->n, h->stream);
+    vcycle<float>(h, 0, L0.ff, L0.uf);
+    cast_f32_to_f64(L0.uf, z, h->n, h->stream);
+  } else {
+    vcycle<double>(h, 0, r, z);
+  }
+}
+
+static sa_status solve_impl(sa_hierarchy *h, const double *b, double *x, sa_location loc,
+                            int32_t *iterations, double *relres) {
+  const hipStream_t s = h->stream;
+  const sa_options &o = h->opt;
+  const int32_t n = h->n;
+  const bool pr = (o.pcg_beta == SA_BETA_PR) ||
+                  (o.pcg_beta < 0 && o.precision == SA_FP32_VCYCLE);
+  copy_in(h->r, b, sizeof(double) * n, loc, s);
+  fill_f64(h->x, 0.0, n, s);
+  PcgScalars *S = h->S;
+  SA_HIP(hipMemsetAsync(S, 0, sizeof(PcgScalars), s));
+  dot_f64(h->r, h->r, n, &S->rr, h->dws, s);
+  const double g0 = read1(&S->rr, s);
+  int32_t its = 0;
+  double rr = g0;
+  sa_status st = SA_NOT_CONVERGED;
+  auto finish = [&]() {
+    if (loc == SA_DEVICE)
+      SA_HIP(hipMemcpyAsync(x, h->x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    else
+      SA_HIP(hipMemcpyAsync(x, h->x, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    SA_HIP(hipStreamSynchronize(s));
+  };
+  if (!std::isfinite(g0)) throw Error(SA_ERR_INVALID_ARG, "non-finite right-hand side");
+  if (g0 == 0.0) {
+    finish();
+    if (iterations) *iterations = 0;
+    if (relres) *relres = 0.0;
+    return SA_OK;
+  }
+  const double thr = (o.rtol * o.rtol) * g0;
+  precondition(h, h->r, h->z);
+  SA_HIP(hipMemcpyAsync(h->p, h->z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  dot_f64(h->r, h->z, n, &S->rho1, h->dws, s);
+  pcg_init_rho(S, s);
+  SpmvArgs<double> A{n, h->lv[0].A.rp, h->lv[0].A.col, h->lv[0].A.val, h->p};
+  for (int32_t k = 1; k <= o.max_iter; ++k) {
+    spmv_store<double>(A, h->q, s);
+    dot_f64(h->p, h->q, n, &S->pq, h->dws, s);
+    pcg_alpha(S, s);
+    pcg_update_xr(n, h->x, h->r, h->p, h->q, S, s);
+    dot_f64(h->r, h->r, n, &S->rr, h->dws, s);
+    SA_HIP(hipMemcpyAsync(h->hS, S, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
+    SA_HIP(hipStreamSynchronize(s));
+    if (h->hS->err) return SA_ERR_BREAKDOWN;
+    rr = h->hS->rr;
+    its = k;
+    if (rr <= thr) {
+      st = SA_OK;
+      break;
+    }
+    if (pr) SA_HIP(hipMemcpyAsync(h->zold, h->z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    precondition(h, h->r, h->z);
+    dot_f64(h->r, h->z, n, &S->rho1, h->dws, s);
+    if (pr) {
+      vec_sub(n, h->z, h->zold, h->w, s);
+      dot_f64(h->r, h->w, n, &S->rw, h->dws, s);
+    }
+    pcg_beta(S, pr, s);
+    pcg_update_p(n, h->p, h->z, S, s);
+  }
+  if (st != SA_OK) {
+    SA_HIP(hipMemcpyAsync(h->hS, S, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
+    SA_HIP(hipStreamSynchronize(s));
+    if (h->hS->err) return SA_ERR_BREAKDOWN;
+    its = o.max_iter;
+  }
+  finish();
+  if (iterations) *iterations = its;
+  if (relres) *relres = std::sqrt(rr / g0);
+  return st;
+}
+
+template <class F>
+static sa_status guarded(F &&fn) {
+  try {
+    return fn();
+  } catch (const Error &e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return SA_ERR_OOM;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return SA_ERR_HIP;
+  } catch (...) {
+    g_last_error = "unknown failure";
+    return SA_ERR_HIP;
+  }
+}
+
+}  // namespace sa
+
+using namespace sa;
+
+extern "C" {
+
+void sa_default_options(sa_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(sa_options);
+  o->variants = 0;
+  o->theta = 0.02;
+  o->tau = 1.1;
+  o->sigma = 1.0 / 3.0;
+  o->one_norm_power = 0;
+  o->power_iters = 10;
+  o->seed = 12345;
+  o->agg_order = SA_AGG_NATURAL;
+  o->max_levels = 10;
+  o->max_coarse = 1000;
+  o->smoother = SA_CHEBYSHEV;
+  o->degree = 2;
+  o->precision = SA_FP64;
+  o->cheb_ratio = 10.0;
+  o->cheb_boost = 1.0;
+  o->rtol = 1e-8;
+  o->max_iter = 500;
+  o->pcg_beta = -1;
+}
+
+sa_status sa_setup(const sa_context *ctx, const sa_csr *A, const double *nullspace,
+                   const sa_options *o, sa_hierarchy **out) {
+  if (!out) return SA_ERR_INVALID_ARG;
+  *out = nullptr;
+  return guarded([&]() -> sa_status {
+    std::unique_ptr<sa_hierarchy> h(new sa_hierarchy());
+    h->stream = ctx ? (hipStream_t)ctx->stream : nullptr;
+    h->ar.stream = h->stream;
+    if (o) h->opt = *o;
+    else sa_default_options(&h->opt);
+    try {
+      setup_impl(h.get(), A, nullspace);
+    } catch (...) {
+      (void)hipStreamSynchronize(h->stream);
+      throw;
+    }
+    *out = h.release();
+    return SA_OK;
+  });
+}
+
+sa_status sa_solve(sa_hierarchy *h, const double *b, double *x, sa_location loc,
+                   int32_t *iterations, double *rel_residual) {
+  if (!h || !b || !x) return SA_ERR_INVALID_ARG;
+  return guarded([&]() -> sa_status {
+    sa_status st = solve_impl(h, b, x, loc, iterations, rel_residual);
+    if (st < 0) {
+      (void)hipStreamSynchronize(h->stream);
+      g_last_error = "CG breakdown (p'Ap <= 0 or r'z <= 0)";
+    }
+    return st;
+  });
+}
+
+sa_status sa_vcycle(sa_hierarchy *h, const double *f, double *z) {
+  if (!h || !f || !z) return SA_ERR_INVALID_ARG;
+  return guarded([&]() -> sa_status {
+    precondition(h, f, z);
+    SA_HIP(hipStreamSynchronize(h->stream));
+    return SA_OK;
+  });
+}
+
+sa_status sa_hierarchy_info(const sa_hierarchy *h, sa_info *info) {
+  if (!h || !info) return SA_ERR_INVALID_ARG;
+  std::memset(info, 0, sizeof(*info));
+  info->levels = (int32_t)h->lv.size();
+  double tot = 0.0;
+  for (size_t l = 0; l < h->lv.size() && l < 16; ++l) {
+    const Level &L = h->lv[l];
+    info->n[l] = L.A.n;
+    info->nnz[l] = L.A.nnz;
+    info->nnz_p[l] = (l + 1 < h->lv.size()) ? L.P.nnz : 0;
+    info->lambda[l] = L.lam;
+    info->omega[l] = L.omega;
+    info->smoother_lambda[l] = L.sm_lam;
+    info->mis_rounds[l] = L.mis_rounds;
+    tot += (double)L.A.nnz;
+  }
+  info->operator_complexity = tot / (double)h->lv[0].A.nnz;
+  info->device_bytes = h->ar.bytes;
+  info->setup_seconds = h->setup_seconds;
+  return SA_OK;
+}
+
+static bool part_info(const sa_hierarchy *h, int32_t level, sa_part what, const void **ptr,
+                      int64_t *count, int *esize) {
+  if (!h || level < 0 || level >= (int32_t)h->lv.size()) return false;
+  const Level &L = h->lv[level];
+  const bool has_p = level + 1 < (int32_t)h->lv.size();
+  *ptr = nullptr;
+  *count = 0;
+  *esize = 4;
+  switch (what) {
+    case SA_PART_A_RP: *ptr = L.A.rp; *count = L.A.n + 1; break;
+    case SA_PART_A_COL: *ptr = L.A.col; *count = L.A.nnz; break;
+    case SA_PART_A_VAL: *ptr = L.A.val; *count = L.A.nnz; *esize = 8; break;
+    case SA_PART_MASK: *ptr = L.mask; *count = L.mask ? L.A.nnz : 0; *esize = 1; break;
+    case SA_PART_AGG: *ptr = L.agg; *count = L.agg ? L.A.n : 0; break;
+    case SA_PART_ROOT: *ptr = L.is_root; *count = L.is_root ? L.A.n : 0; *esize = 1; break;
+    case SA_PART_ABAR_RP: *ptr = L.Abar.rp; *count = has_p ? L.Abar.n + 1 : 0; break;
+    case SA_PART_ABAR_COL: *ptr = L.Abar.col; *count = has_p ? L.Abar.nnz : 0; break;
+    case SA_PART_ABAR_VAL: *ptr = L.Abar.val; *count = has_p ? L.Abar.nnz : 0; *esize = 8; break;
+    case SA_PART_INVD: *ptr = L.invD; *count = has_p ? L.A.n : 0; *esize = 8; break;
+    case SA_PART_P_RP: *ptr = L.P.rp; *count = has_p ? L.P.n + 1 : 0; break;
+    case SA_PART_P_COL: *ptr = L.P.col; *count = has_p ? L.P.nnz : 0; break;
+    case SA_PART_P_VAL: *ptr = L.P.val; *count = has_p ? L.P.nnz : 0; *esize = 8; break;
+    case SA_PART_R_RP: *ptr = L.R.rp; *count = has_p ? L.R.n + 1 : 0; break;
+    case SA_PART_R_COL: *ptr = L.R.col; *count = has_p ? L.R.nnz : 0; break;
+    case SA_PART_R_VAL: *ptr = L.R.val; *count = has_p ? L.R.nnz : 0; *esize = 8; break;
+    case SA_PART_SM_INVD: *ptr = L.sm_invD; *count = has_p ? L.A.n : 0; *esize = 8; break;
+    case SA_PART_COARSE_INV:
+      *ptr = L.Ainv;
+      *count = has_p ? 0 : (int64_t)L.A.n * L.A.n;
+      *esize = 8;
+      break;
+    default: return false;
+  }
+  if (!*ptr) *count = 0;
+  return true;
+}
+
+sa_status sa_export_size(const sa_hierarchy *h, int32_t level, sa_part what, int64_t *count) {
+  const void *p;
+  int es;
+  if (!count || !part_info(h, level, what, &p, count, &es)) return SA_ERR_INVALID_ARG;
+  return SA_OK;
+}
+
+sa_status sa_export_level(const sa_hierarchy *h, int32_t level, sa_part what, void *host_buf,
+                          size_t bytes) {
+  return guarded([&]() -> sa_status {
+    const void *p;
+    int64_t count;
+    int es;
+    if (!part_info(h, level, what, &p, &count, &es)) return SA_ERR_INVALID_ARG;
+    if ((size_t)count * es > bytes || (count > 0 && !host_buf)) return SA_ERR_INVALID_ARG;
+    if (count > 0) {
+      SA_HIP(hipMemcpyAsync(host_buf, p, (size_t)count * es, hipMemcpyDeviceToHost, h->stream));
+      SA_HIP(hipStreamSynchronize(h->stream));
+    }
+    return SA_OK;
+  });
+}
+
+void sa_destroy(sa_hierarchy *h) {
+  if (!h) return;
+  try {
+    (void)hipStreamSynchronize(h->stream);
+    h->ar.release();
+    (void)hipStreamSynchronize(h->stream);
+  } catch (...) {
+  }
+  delete h;
+}
+
+const char *sa_status_string(sa_status s) {
+  switch (s) {
+    case SA_OK: return "ok";
+    case SA_NOT_CONVERGED: return "not converged";
+    case SA_PENDING: return "pending";
+    case SA_ERR_INVALID_ARG: return "invalid argument";
+    case SA_ERR_BAD_CSR: return "malformed CSR matrix";
+    case SA_ERR_NONPOSITIVE_DIAG: return "zero or non-positive diagonal";
+    case SA_ERR_NEGATIVE_EIGENVALUE: return "non-positive eigenvalue estimate";
+    case SA_ERR_COARSEN_STALLED: return "coarsening stalled";
+    case SA_ERR_COARSE_FACTOR: return "coarse factorisation failed";
+    case SA_ERR_OOM: return "out of device memory";
+    case SA_ERR_HIP: return "HIP runtime error";
+    case SA_ERR_BREAKDOWN: return "CG breakdown";
+  }
+  return "unknown status";
+}
+
+const char *sa_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// Host-side launchers of the library's kernels (internal).
+#pragma once
+#include "common.hpp"
+
+namespace sa {
+
+// ---------------- solve-phase kernels (solve_kernels.hip) ------------------------------
+// y = A x with every row summed sequentially in ascending column order from 0 (products
+// staged through LDS; bit-identical to the row-by-row definition).  Variants fuse the
+// row-local epilogue used by the smoother, residual and transfer steps.
+template <class T>
+struct SpmvArgs {
+  int32_t n;
+  const int32_t *rp;
+  const int32_t *col;
+  const T *val;
+  const T *x;
+};
+
+template <class T> void spmv_store(const SpmvArgs<T> &a, T *y, hipStream_t s);
+template <class T> void spmv_scale(const SpmvArgs<T> &a, const T *d, T *y, hipStream_t s);
+template <class T> void spmv_resid(const SpmvArgs<T> &a, const T *f, T *r, hipStream_t s);
+template <class T> void spmv_add(const SpmvArgs<T> &a, T *u, hipStream_t s);
+// r = f - A u; d = (invD .* r) / theta
+template <class T>
+void spmv_cheb_start(const SpmvArgs<T> &a, const T *f, const T *invD, T theta, T *r, T *d,
+                     hipStream_t s);
+// x = d: rout = rin - A d; dn = c1 d + c2 (invD .* rout); u = (uzero ? 0 : u) + d, and when
+// `last` also u += dn.  dout must differ from d (= a.x).
+template <class T>
+void spmv_cheb_step(const SpmvArgs<T> &a, const T *rin, T *rout, const T *invD, T c1, T c2,
+                    T *u, bool uzero, T *dout, bool last, hipStream_t s);
+// x = u: u2 = u + w (invD .* (f - A u))
+template <class T>
+void spmv_jacobi(const SpmvArgs<T> &a, const T *f, const T *invD, T w, T *u2, hipStream_t s);
+
+// d = (invD .* f) / theta; if write_u: u = 0 + d
+template <class T>
+void cheb_first(int32_t n, const T *f, const T *invD, T theta, T *d, T *u, bool write_u,
+                hipStream_t s);
+// u = u + d
+template <class T> void vec_add(int32_t n, T *u, const T *d, hipStream_t s);
+// u = 0 + w (invD .* f)
+template <class T>
+void jacobi_first(int32_t n, const T *f, const T *invD, T w, T *u, hipStream_t s);
+
+void cast_f64_to_f32(const double *a, float *b, int64_t n, hipStream_t s);
+void cast_f32_to_f64(const float *a, double *b, int64_t n, hipStream_t s);
+
+// Dense y = M x for the coarsest level (M row-major n x n, float64).
+void gemv_f64(int32_t n, const double *M, const double *x, double *y, hipStream_t s);
+
+// PCG device scalars.
+struct PcgScalars {
+  double rho, pq, alpha, rr, rho1, beta, rw, spare;
+  int32_t err, pad;
+};
+// x = x + alpha p; r = r - alpha q  (alpha = S->alpha)
+void pcg_update_xr(int32_t n, double *x, double *r, const double *p, const double *q,
+                   const PcgScalars *S, hipStream_t s);
+// p = z + beta p
+void pcg_update_p(int32_t n, double *p, const double *z, const PcgScalars *S, hipStream_t s);
+// w = z - zold
+void vec_sub(int32_t n, const double *z, const double *zold, double *w, hipStream_t s);
+// alpha = rho / pq (err on pq <= 0)
+void pcg_alpha(PcgScalars *S, hipStream_t s);
+// beta (FR: rho1/rho; PR: rw/rho), err on rho1 <= 0, then rho = rho1
+void pcg_beta(PcgScalars *S, bool pr, hipStream_t s);
+// rho = rho1 (initial), err on <= 0
+void pcg_init_rho(PcgScalars *S, hipStream_t s);
+
+// ---------------- setup kernels (setup_kernels.hip) ------------------------------------
+// Validates a CSR (ascending in-range columns, diagonal present, finite values); flags
+// bits in *err: 1 bad structure, 2 missing diagonal, 4 non-finite value.
+void validate_csr(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                  int32_t *err, hipStream_t s);
+// dval[i] = A_ii.
+void find_diag(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+               double *dval, hipStream_t s);
+// mask per entry (0 weak, 1 strong, 3 diagonal) and scount[i] = strong entries in row i.
+void strength(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+              const double *dval, double th2, uint8_t *mask, int32_t *scount, hipStream_t s);
+// Symmetrised strength graph G = S u S^T as CSR (grp[n+1], gcol[nnzG]); returns nnzG.
+int64_t strength_graph(int32_t n, const int32_t *rp, const int32_t *col, const uint8_t *mask,
+                       const int32_t *scount, Arena &ar, int32_t **grp, int32_t **gcol,
+                       hipStream_t s);
+// Aggregation (roots = lexicographically-first distance-2 MIS in priority order; phase-2
+// join; isolated vertices unaggregated).  Returns nc; agg[n], is_root[n], root_vertex[nc].
+int32_t aggregate(int32_t n, const int32_t *grp, const int32_t *gcol, int32_t order,
+                  uint64_t seed, int32_t level, int32_t *agg, uint8_t *is_root, Arena &ar,
+                  int32_t **root_vertex, int32_t *rounds, hipStream_t s);
+// Sprsfy: marks dropped strong entries (mask 1 -> 2).
+void sprsfy(int32_t n, const int32_t *rp, const int32_t *col, uint8_t *mask,
+            const int32_t *agg, const int32_t *root_vertex, int32_t nc, hipStream_t s);
+// Filtered matrix (plain or OffLmp) and the smoothing diagonal inverse; returns nnz(Abar).
+// err bit 8: zero filtered diagonal with the plain diagonal.
+int64_t lump(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+             const uint8_t *mask, bool offlmp, double tau, bool one_norm, double mult,
+             Arena &ar, Csr &abar, double *invD, int32_t *err, hipStream_t s);
+// Power method; writes the estimate to *lam (device).  ws: 3n doubles + dot workspace.
+void power_method(const Csr &M, const double *invD, int32_t iters, uint64_t seed,
+                  int32_t level, int32_t stream_id, double *lam, hipStream_t s);
+// omega = 4/(3 lambda) (or lambda = 1 first when `unit`), err bit 16 if lambda <= 0.
+void damping(double *lam, double *omega, bool unit, int32_t *err, hipStream_t s);
+// P = (I - omega invD Abar) Ptent; returns nnz(P).
+int64_t prolongator(const Csr &abar, const double *invD, const int32_t *agg, int32_t nc,
+                    const double *omega, Arena &ar, Csr &P, hipStream_t s);
+void cnstrnt(const Csr &P, const int32_t *agg, hipStream_t s);
+void scale_rows(const Csr &P, const double *B, hipStream_t s);
+// R = P^T with ascending columns per row.
+void transpose(const Csr &P, Arena &ar, Csr &R, hipStream_t s);
+// 1/A_ii with err bit 32 when A_ii <= 0.
+void inv_diag(int32_t n, const double *dval, double *invD, int32_t *err, hipStream_t s);
+// Ahat = D_B A D_B
+void scale_sym(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+               const double *B, double *out, hipStream_t s);
+
+// ---------------- SpGEMM (spgemm.hip) --------------------------------------------------
+// C = X * Y with Gustavson-order accumulation per output entry (ascending inner index);
+// output rows sorted; cancellations stored.  C's arrays are allocated from `ar`.
+void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s);
+
+// ---------------- coarsest level (coarse.hip) ------------------------------------------
+// Dense inverse of the coarsest operator via Cholesky (err bit 64 on a pivot <= 0).
+void coarse_inverse(const Csr &A, double *Ainv, int32_t *err, hipStream_t s);
+
+}  // namespace sa

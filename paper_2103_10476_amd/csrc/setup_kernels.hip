@@ -1,0 +1,875 @@
+// Setup kernels: CSR validation, strength of connection, the aggregation graph, parallel
+// root selection, aggregation, Sprsfy, filtered matrix with its smoothing diagonal, power
+// method, prolongator smoothing, Cnstrnt, transpose.
+//
+// Every floating-point reduction runs in the order the method's definition fixes (row sums
+// sequential in ascending column order from 0), with FMA contraction disabled at compile
+// time, so the setup is deterministic and equal to the sequential definition bit for bit.
+// Setup kernels are one thread per row (rows hold 5-30 entries on the fine levels); they
+// run once per level and are bound by HBM traffic or by the level's size.
+#include <climits>
+
+#include "kernels.hpp"
+
+namespace sa {
+
+#define SA_ROW_KERNEL_BEGIN(n)                                    \
+  const int64_t i64_ = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; \
+  if (i64_ >= (n)) return;                                        \
+  const int32_t i = (int32_t)i64_;
+
+// ---- validation -----------------------------------------------------------------------
+__global__ void k_validate(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
+                           const double *val, int32_t *err) {
+  SA_ROW_KERNEL_BEGIN(n)
+  const int32_t b = rp[i], e = rp[i + 1];
+  if (b < 0 || e < b || (int64_t)e > nnz) {
+    atomicOr(err, 1);
+    return;
+  }
+  int32_t flags = 0;
+  bool diag = false;
+  for (int32_t k = b; k < e; ++k) {
+    const int32_t c = col[k];
+    if (c < 0 || c >= n) flags |= 1;
+    if (k > b && c <= col[k - 1]) flags |= 1;
+    if (c == i) diag = true;
+    if (val && !isfinite(val[k])) flags |= 4;
+  }
+  if (!diag) flags |= 2;
+  if (flags) atomicOr(err, flags);
+}
+
+void validate_csr(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                  int32_t *err, hipStream_t s) {
+  // rp[0] == 0 and rp[n] == nnz are checked by the caller before this launch.
+  int32_t nnz = read1(rp + n, s);
+  k_validate<<<grid_for(n), kBlock, 0, s>>>(n, nnz, rp, col, val, err);
+  SA_LAUNCH_CHECK();
+}
+
+__global__ void k_find_diag(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                            double *dval) {
+  SA_ROW_KERNEL_BEGIN(n)
+  int32_t lo = rp[i], hi = rp[i + 1] - 1;
+  double d = 0.0;
+  while (lo <= hi) {
+    int32_t mid = (lo + hi) >> 1;
+    int32_t c = col[mid];
+    if (c == i) {
+      d = val[mid];
+      break;
+    }
+    if (c < i) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  dval[i] = d;
+}
+void find_diag(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+               double *dval, hipStream_t s) {
+  if (n <= 0) return;
+  k_find_diag<<<grid_for(n), kBlock, 0, s>>>(n, rp, col, val, dval);
+  SA_LAUNCH_CHECK();
+}
+
+// ---- strength (Sec. 1.1 criterion, evaluated squared) ----------------------------------
+__global__ void k_strength(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                           const double *dval, double th2, uint8_t *mask, int32_t *scount) {
+  SA_ROW_KERNEL_BEGIN(n)
+  const double di = dval[i];
+  int32_t cnt = 0;
+  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+    const int32_t j = col[k];
+    if (j == i) {
+      mask[k] = 3;
+      continue;
+    }
+    const double a = val[k];
+    const double p = di * dval[j];
+    const bool strong = (p > 0.0) && (a * a >= th2 * p);
+    mask[k] = strong ? 1 : 0;
+    cnt += strong;
+  }
+  scount[i] = cnt;
+}
+void strength(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+              const double *dval, double th2, uint8_t *mask, int32_t *scount, hipStream_t s) {
+  if (n <= 0) return;
+  k_strength<<<grid_for(n), kBlock, 0, s>>>(n, rp, col, val, dval, th2, mask, scount);
+  SA_LAUNCH_CHECK();
+}
+
+// ---- aggregation graph G = S u S^T ------------------------------------------------------
+__global__ void k_fill_strong(int32_t n, const int32_t *rp, const int32_t *col,
+                              const uint8_t *mask, const int32_t *srp, int32_t *scol,
+                              int32_t *tcnt) {
+  SA_ROW_KERNEL_BEGIN(n)
+  int32_t w = srp[i];
+  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+    const uint8_t m = mask[k];
+    if (m == 1 || m == 2) {
+      scol[w++] = col[k];
+      atomicAdd(&tcnt[col[k]], 1);
+    }
+  }
+}
+__global__ void k_scatter_t(int32_t n, const int32_t *srp, const int32_t *scol, int32_t *tpos,
+                            int32_t *tcol) {
+  SA_ROW_KERNEL_BEGIN(n)
+  for (int32_t k = srp[i]; k < srp[i + 1]; ++k) {
+    int32_t p = atomicAdd(&tpos[scol[k]], 1);
+    tcol[p] = i;
+  }
+}
+// Insertion sort of every row's columns (rows are short; the result does not depend on the
+// order the atomic scatter produced).
+__global__ void k_sort_rows_i32(int32_t n, const int32_t *rp, int32_t *c) {
+  SA_ROW_KERNEL_BEGIN(n)
+  const int32_t b = rp[i], e = rp[i + 1];
+  for (int32_t k = b + 1; k < e; ++k) {
+    int32_t v = c[k];
+    int32_t q = k - 1;
+    while (q >= b && c[q] > v) {
+      c[q + 1] = c[q];
+      --q;
+    }
+    c[q + 1] = v;
+  }
+}
+__global__ void k_union(int32_t n, const int32_t *arp, const int32_t *acol, const int32_t *brp,
+                        const int32_t *bcol, const int32_t *orp, int32_t *ocol, int32_t *ocnt) {
+  SA_ROW_KERNEL_BEGIN(n)
+  int32_t a = arp[i], ae = arp[i + 1], b = brp[i], be = brp[i + 1];
+  int32_t w = orp ? orp[i] : 0;
+  int32_t cnt = 0;
+  while (a < ae || b < be) {
+    int32_t v;
+    if (b >= be || (a < ae && acol[a] < bcol[b])) v = acol[a++];
+    else if (a >= ae || bcol[b] < acol[a]) v = bcol[b++];
+    else {
+      v = acol[a++];
+      ++b;
+    }
+    if (ocol) ocol[w + cnt] = v;
+    ++cnt;
+  }
+  if (ocnt) ocnt[i] = cnt;
+}
+
+int64_t strength_graph(int32_t n, const int32_t *rp, const int32_t *col, const uint8_t *mask,
+                       const int32_t *scount, Arena &ar, int32_t **grp_out, int32_t **gcol_out,
+                       hipStream_t s) {
+  Arena tmp;
+  tmp.stream = s;
+  int32_t *srp = tmp.alloc<int32_t>(n + 1);
+  exclusive_scan_i32(scount, srp, n, s);
+  const int32_t nnzS = read1(srp + n, s);
+  int32_t *scol = tmp.alloc<int32_t>(nnzS);
+  int32_t *tcnt = tmp.alloc<int32_t>(n + 1);
+  fill_i32(tcnt, 0, n + 1, s);
+  k_fill_strong<<<grid_for(n), kBlock, 0, s>>>(n, rp, col, mask, srp, scol, tcnt);
+  SA_LAUNCH_CHECK();
+  int32_t *trp = tmp.alloc<int32_t>(n + 1);
+  exclusive_scan_i32(tcnt, trp, n, s);
+  int32_t *tpos = tmp.alloc<int32_t>(n + 1);
+  SA_HIP(hipMemcpyAsync(tpos, trp, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
+  int32_t *tcol = tmp.alloc<int32_t>(nnzS);
+  k_scatter_t<<<grid_for(n), kBlock, 0, s>>>(n, srp, scol, tpos, tcol);
+  SA_LAUNCH_CHECK();
+  k_sort_rows_i32<<<grid_for(n), kBlock, 0, s>>>(n, trp, tcol);
+  SA_LAUNCH_CHECK();
+  int32_t *gcnt = tmp.alloc<int32_t>(n + 1);
+  k_union<<<grid_for(n), kBlock, 0, s>>>(n, srp, scol, trp, tcol, nullptr, nullptr, gcnt);
+  SA_LAUNCH_CHECK();
+  int32_t *grp = ar.alloc<int32_t>(n + 1);
+  exclusive_scan_i32(gcnt, grp, n, s);
+  const int32_t nnzG = read1(grp + n, s);
+  int32_t *gcol = ar.alloc<int32_t>(nnzG);
+  k_union<<<grid_for(n), kBlock, 0, s>>>(n, srp, scol, trp, tcol, grp, gcol, nullptr);
+  SA_LAUNCH_CHECK();
+  *grp_out = grp;
+  *gcol_out = gcol;
+  return nnzG;
+}
+
+// ---- root selection: lexicographically-first distance-2 maximal independent set -----------
+// key = (state << 62) | priority with state IN = 0, UNDECIDED = 1, OUT = 2.  Per round:
+// k1(v) = min key over N[v]; k2(v) = min k1 over N[v] (= min over the distance-2 ball).  An
+// undecided v leaves as OUT when k2 is an IN key (a root within distance 2) and enters as IN
+// when k2 is its own key (best priority among undecided vertices within distance 2).  This
+// reproduces the sequential greedy root choice in priority order exactly.
+constexpr uint64_t kIn = 0, kUnd = 1ull << 62, kOut = 2ull << 62;
+constexpr uint64_t kStateMask = 3ull << 62;
+
+__device__ inline uint64_t splitmix64_dev(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ inline uint64_t stream_key_dev(int stream, int level, int64_t i) {
+  return ((uint64_t)stream << 56) | ((uint64_t)level << 40) | (uint64_t)i;
+}
+
+__global__ void k_mis_init(int32_t n, const int32_t *grp, int32_t order, uint64_t seed,
+                           int32_t level, uint64_t *key) {
+  SA_ROW_KERNEL_BEGIN(n)
+  uint64_t pri = (uint64_t)i;
+  if (order == 1) pri = ((splitmix64_dev(seed, stream_key_dev(2, level, i)) >> 34) << 32) | pri;
+  key[i] = (grp[i + 1] == grp[i] ? kOut : kUnd) | pri;
+}
+__global__ void k_mis_min1(int32_t n, const int32_t *grp, const int32_t *gcol,
+                           const uint64_t *key, uint64_t *k1) {
+  SA_ROW_KERNEL_BEGIN(n)
+  uint64_t m = key[i];
+  for (int32_t k = grp[i]; k < grp[i + 1]; ++k) {
+    uint64_t v = key[gcol[k]];
+    m = v < m ? v : m;
+  }
+  k1[i] = m;
+}
+__global__ void k_mis_decide(int32_t n, const int32_t *grp, const int32_t *gcol,
+                             const uint64_t *k1, uint64_t *key, int32_t *flag) {
+  SA_ROW_KERNEL_BEGIN(n)
+  const uint64_t me = key[i];
+  if ((me & kStateMask) != kUnd) return;
+  uint64_t m = k1[i];
+  for (int32_t k = grp[i]; k < grp[i + 1]; ++k) {
+    uint64_t v = k1[gcol[k]];
+    m = v < m ? v : m;
+  }
+  const uint64_t pri = me & ~kStateMask;
+  if ((m & kStateMask) == kIn) key[i] = kOut | pri;
+  else if (m == me) key[i] = kIn | pri;
+  else *flag = 1;
+}
+__global__ void k_roots(int32_t n, const uint64_t *key, int32_t *isr) {
+  SA_ROW_KERNEL_BEGIN(n)
+  isr[i] = ((key[i] & kStateMask) == kIn) ? 1 : 0;
+}
+__global__ void k_agg_phase1(int32_t n, const int32_t *grp, const int32_t *gcol,
+                             const uint64_t *key, const int32_t *rid, int32_t *agg1,
+                             uint8_t *is_root, int32_t *root_vertex) {
+  SA_ROW_KERNEL_BEGIN(n)
+  int32_t a = -1;
+  if ((key[i] & kStateMask) == kIn) {
+    a = rid[i];
+    root_vertex[a] = i;
+  } else {
+    for (int32_t k = grp[i]; k < grp[i + 1]; ++k) {
+      int32_t u = gcol[k];
+      if ((key[u] & kStateMask) == kIn) {
+        a = rid[u];
+        break;
+      }
+    }
+  }
+  agg1[i] = a;
+  is_root[i] = ((key[i] & kStateMask) == kIn) ? 1 : 0;
+}
+// Leftover vertices join the phase-1 aggregate with the most strong connections to them,
+// ties to the smaller aggregate number.
+__global__ void k_agg_phase2(int32_t n, const int32_t *grp, const int32_t *gcol,
+                             const int32_t *agg1, int32_t *agg) {
+  SA_ROW_KERNEL_BEGIN(n)
+  int32_t a = agg1[i];
+  const int32_t b = grp[i], e = grp[i + 1];
+  if (a < 0 && e > b) {
+    int32_t best = -1, bestc = 0;
+    for (int32_t k = b; k < e; ++k) {
+      const int32_t c = agg1[gcol[k]];
+      if (c < 0) continue;
+      int32_t cnt = 0;
+      for (int32_t q = b; q < e; ++q) cnt += (agg1[gcol[q]] == c);
+      if (cnt > bestc || (cnt == bestc && c < best)) {
+        best = c;
+        bestc = cnt;
+      }
+    }
+    a = best;
+  }
+  agg[i] = a;
+}
+
+int32_t aggregate(int32_t n, const int32_t *grp, const int32_t *gcol, int32_t order,
+                  uint64_t seed, int32_t level, int32_t *agg, uint8_t *is_root, Arena &ar,
+                  int32_t **root_vertex, int32_t *rounds_out, hipStream_t s) {
+  Arena tmp;
+  tmp.stream = s;
+  uint64_t *key = tmp.alloc<uint64_t>(n);
+  uint64_t *k1 = tmp.alloc<uint64_t>(n);
+  k_mis_init<<<grid_for(n), kBlock, 0, s>>>(n, grp, order, seed, level, key);
+  SA_LAUNCH_CHECK();
+  // Rounds run in batches between flag checks; an extra round on a finished state changes
+  // nothing.  flags[r] = 1 iff some vertex was still undecided after round r.
+  const int batch = 8;
+  int64_t cap = (int64_t)n + batch + 2;
+  int32_t *flags = tmp.alloc<int32_t>(cap);
+  fill_i32(flags, 0, cap, s);
+  int32_t *hflags = nullptr;
+  SA_HIP(hipHostMalloc((void **)&hflags, sizeof(int32_t) * batch, hipHostMallocDefault));
+  int64_t r = 0;
+  int32_t used = 0;
+  bool done = false;
+  while (!done) {
+    for (int q = 0; q < batch; ++q, ++r) {
+      if (r >= cap) throw Error(SA_ERR_COARSEN_STALLED, "root selection did not terminate");
+      k_mis_min1<<<grid_for(n), kBlock, 0, s>>>(n, grp, gcol, key, k1);
+      k_mis_decide<<<grid_for(n), kBlock, 0, s>>>(n, grp, gcol, k1, key, flags + r);
+    }
+    SA_LAUNCH_CHECK();
+    SA_HIP(hipMemcpyAsync(hflags, flags + r - batch, sizeof(int32_t) * batch,
+                          hipMemcpyDeviceToHost, s));
+    SA_HIP(hipStreamSynchronize(s));
+    for (int q = 0; q < batch; ++q)
+      if (hflags[q] == 0) {
+        used = (int32_t)(r - batch + q + 1);
+        done = true;
+        break;
+      }
+  }
+  (void)hipHostFree(hflags);
+  if (rounds_out) *rounds_out = used;
+  int32_t *isr = tmp.alloc<int32_t>(n + 1);
+  k_roots<<<grid_for(n), kBlock, 0, s>>>(n, key, isr);
+  SA_LAUNCH_CHECK();
+  int32_t *rid = tmp.alloc<int32_t>(n + 1);
+  exclusive_scan_i32(isr, rid, n, s);
+  const int32_t nc = read1(rid + n, s);
+  int32_t *rv = ar.alloc<int32_t>(nc > 0 ? nc : 1);
+  int32_t *agg1 = tmp.alloc<int32_t>(n);
+  k_agg_phase1<<<grid_for(n), kBlock, 0, s>>>(n, grp, gcol, key, rid, agg1, is_root, rv);
+  SA_LAUNCH_CHECK();
+  k_agg_phase2<<<grid_for(n), kBlock, 0, s>>>(n, grp, gcol, agg1, agg);
+  SA_LAUNCH_CHECK();
+  *root_vertex = rv;
+  return nc;
+}
+
+// ---- Sprsfy (Sec. 2.5) --------------------------------------------------------------------
+__global__ void k_count_members(int32_t n, const int32_t *agg, int32_t *cnt) {
+  SA_ROW_KERNEL_BEGIN(n)
+  if (agg[i] >= 0) atomicAdd(&cnt[agg[i]], 1);
+}
+__global__ void k_scatter_members(int32_t n, const int32_t *agg, int32_t *pos, int32_t *mem) {
+  SA_ROW_KERNEL_BEGIN(n)
+  if (agg[i] >= 0) mem[atomicAdd(&pos[agg[i]], 1)] = i;
+}
+// One thread per aggregate J with root r.  Candidates: aggregates reached by r's weak
+// connections but by none of its strong ones, J excluded.  For a candidate c, a single strong
+// connection from a non-root member of J into c is dropped with its transpose.  Decisions read
+// "strong" as mask 1 or 2, so concurrent drops by other aggregates do not change them; the
+// result does not depend on member order.
+__global__ void k_sprsfy(int32_t nc, const int32_t *rp, const int32_t *col, uint8_t *mask,
+                         const int32_t *agg, const int32_t *root_vertex, const int32_t *mrp,
+                         const int32_t *mem) {
+  const int64_t J64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (J64 >= nc) return;
+  const int32_t J = (int32_t)J64;
+  const int32_t r = root_vertex[J];
+  const int32_t rb = rp[r], re = rp[r + 1];
+  for (int32_t k = rb; k < re; ++k) {
+    const int32_t u0 = col[k];
+    if (u0 == r || mask[k] != 0) continue;  // weak connections of the root only
+    const int32_t c = agg[u0];
+    if (c < 0 || c == J) continue;
+    bool first = true, strong_reached = false;
+    for (int32_t q = rb; q < re; ++q) {
+      const int32_t uq = col[q];
+      if (uq == r || agg[uq] != c) continue;
+      const uint8_t mq = mask[q];
+      if (mq == 1 || mq == 2) strong_reached = true;
+      else if (q < k) first = false;  // an earlier weak connection already reached c
+    }
+    if (!first || strong_reached) continue;
+    // count strong connections from non-root members of J into c
+    int32_t count = 0, ev = -1, vv = -1;
+    for (int32_t m = mrp[J]; m < mrp[J + 1] && count < 2; ++m) {
+      const int32_t v = mem[m];
+      if (v == r) continue;
+      for (int32_t q = rp[v]; q < rp[v + 1]; ++q) {
+        const int32_t u = col[q];
+        if (u == v) continue;
+        const uint8_t mq = mask[q];
+        if ((mq == 1 || mq == 2) && agg[u] == c) {
+          ++count;
+          ev = q;
+          vv = v;
+        }
+      }
+    }
+    if (count != 1) continue;
+    mask[ev] = 2;
+    const int32_t u = col[ev];
+    int32_t lo = rp[u], hi = rp[u + 1] - 1;
+    while (lo <= hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      const int32_t cm = col[mid];
+      if (cm == vv) {
+        if (mask[mid] == 1) mask[mid] = 2;
+        break;
+      }
+      if (cm < vv) lo = mid + 1;
+      else hi = mid - 1;
+    }
+  }
+}
+
+void sprsfy(int32_t n, const int32_t *rp, const int32_t *col, uint8_t *mask, const int32_t *agg,
+            const int32_t *root_vertex, int32_t nc, hipStream_t s) {
+  if (nc <= 0) return;
+  Arena tmp;
+  tmp.stream = s;
+  int32_t *cnt = tmp.alloc<int32_t>(nc + 1);
+  fill_i32(cnt, 0, nc + 1, s);
+  k_count_members<<<grid_for(n), kBlock, 0, s>>>(n, agg, cnt);
+  SA_LAUNCH_CHECK();
+  int32_t *mrp = tmp.alloc<int32_t>(nc + 1);
+  exclusive_scan_i32(cnt, mrp, nc, s);
+  int32_t *pos = tmp.alloc<int32_t>(nc + 1);
+  SA_HIP(hipMemcpyAsync(pos, mrp, sizeof(int32_t) * (nc + 1), hipMemcpyDeviceToDevice, s));
+  int32_t *mem = tmp.alloc<int32_t>(n);
+  k_scatter_members<<<grid_for(n), kBlock, 0, s>>>(n, agg, pos, mem);
+  SA_LAUNCH_CHECK();
+  k_sprsfy<<<grid_for(nc), kBlock, 0, s>>>(nc, rp, col, mask, agg, root_vertex, mrp, mem);
+  SA_LAUNCH_CHECK();
+}
+
+// ---- filtered matrix (Sec. 1.1 plain lumping; Sec. 2.3 Algorithm 2) and its diagonal -----
+__global__ void k_lump_count(int32_t n, const int32_t *rp, const int32_t *col,
+                             const uint8_t *mask, int32_t *cnt) {
+  SA_ROW_KERNEL_BEGIN(n)
+  int32_t c = 0;
+  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) c += (col[k] == i || mask[k] == 1);
+  cnt[i] = c;
+}
+
+__global__ void k_lump_fill(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                            const uint8_t *mask, const int32_t *arp, int32_t *acol,
+                            double *aval, bool offlmp, double tau, bool one_norm, double mult,
+                            double *invD, int32_t *err) {
+  SA_ROW_KERNEL_BEGIN(n)
+  const int32_t b = rp[i], e = rp[i + 1];
+  const int32_t o = arp[i];
+  int32_t w = o, ds = o;
+  double aii = 0.0, r = 0.0;
+  for (int32_t k = b; k < e; ++k) {
+    const int32_t j = col[k];
+    if (j == i) {
+      aii = val[k];
+      ds = w;
+      acol[w] = j;
+      aval[w] = val[k];
+      ++w;
+    } else if (mask[k] == 1) {
+      acol[w] = j;
+      aval[w] = val[k];
+      ++w;
+    } else {
+      r += val[k];
+    }
+  }
+  const int32_t wend = w;
+  if (!offlmp || r >= 0.0 || !(aii > 0.0)) {
+    aval[ds] = aii + r;
+  } else {
+    double kp = 0.0, km = 0.0;
+    bool has_kp = false, has_km = false;
+    for (int32_t t = o; t < wend; ++t) {
+      if (t == ds) continue;
+      const double v = aval[t];
+      if (v > 0.0) {
+        kp += v;
+        has_kp = true;
+      } else if (v < 0.0) {
+        km += v;
+        has_km = true;
+      }
+    }
+    if (-r <= kp) {
+      const double delta = r / kp;
+      for (int32_t t = o; t < wend; ++t)
+        if (t != ds && aval[t] > 0.0) aval[t] = aval[t] * (1.0 + delta);
+    } else {
+      double offsum = 0.0;
+      for (int32_t k = b; k < e; ++k)
+        if (col[k] != i) offsum += fabs(val[k]);
+      const double T = tau * (offsum / aii);
+      const double rhat = r + kp;
+      if (!has_km) {
+        if (has_kp && fabs(r + kp) / aii <= T) {
+          const double delta = r / kp;
+          for (int32_t t = o; t < wend; ++t)
+            if (t != ds && aval[t] > 0.0) aval[t] = aval[t] * (1.0 + delta);
+        }
+      } else {
+        const double a = aii;
+        const double c = -km - rhat;
+        const double U = fmin(fabs(rhat), a);
+        const double bnd = T * a - c;
+        double rs = 0.0;
+        bool feasible;
+        if (T > 1.0) {
+          const double ub = bnd / (T - 1.0);
+          feasible = ub >= 0.0;
+          if (feasible) rs = fmin(U, ub);
+        } else if (T < 1.0) {
+          const double lb = bnd / (T - 1.0);
+          feasible = lb <= U;
+          if (feasible) rs = U;
+        } else {
+          feasible = bnd >= 0.0;
+          if (feasible) rs = U;
+        }
+        if (!feasible) rs = (c <= a) ? U : 0.0;
+        const double delta = (rhat + rs) / km;
+        for (int32_t t = o; t < wend; ++t) {
+          if (t == ds) continue;
+          const double v = aval[t];
+          if (v > 0.0) aval[t] = 0.0;
+          else if (v < 0.0) aval[t] = v * (1.0 + delta);
+        }
+        aval[ds] = a - rs;
+      }
+    }
+  }
+  double D;
+  if (one_norm) {
+    D = 0.0;
+    for (int32_t t = o; t < wend; ++t) D += fabs(aval[t]);
+    if (D == 0.0) {
+      D = 1.0;
+    } else {
+      double sum = 0.0;
+      for (int32_t t = o; t < wend; ++t) sum += aval[t];
+      if (D < mult * sum) D = mult * sum;
+    }
+  } else {
+    D = aval[ds];
+    if (D == 0.0) atomicOr(err, 8);
+  }
+  invD[i] = 1.0 / D;
+}
+
+int64_t lump(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+             const uint8_t *mask, bool offlmp, double tau, bool one_norm, double mult,
+             Arena &ar, Csr &abar, double *invD, int32_t *err, hipStream_t s) {
+  int32_t *cnt = (int32_t *)dev_alloc(sizeof(int32_t) * (n + 1), s);
+  k_lump_count<<<grid_for(n), kBlock, 0, s>>>(n, rp, col, mask, cnt);
+  SA_LAUNCH_CHECK();
+  abar.n = abar.ncols = n;
+  abar.rp = ar.alloc<int32_t>(n + 1);
+  exclusive_scan_i32(cnt, abar.rp, n, s);
+  dev_free(cnt, s);
+  abar.nnz = read1(abar.rp + n, s);
+  abar.col = ar.alloc<int32_t>(abar.nnz);
+  abar.val = ar.alloc<double>(abar.nnz);
+  k_lump_fill<<<grid_for(n), kBlock, 0, s>>>(n, rp, col, val, mask, abar.rp, abar.col, abar.val,
+                                             offlmp, tau, one_norm, mult, invD, err);
+  SA_LAUNCH_CHECK();
+  return abar.nnz;
+}
+
+// ---- power method (Sec. 1.1 damping; Sec. 4.1 ten sweeps) --------------------------------
+__global__ void k_power_init(int32_t n, uint64_t seed, int32_t level, int32_t stream,
+                             double *x) {
+  SA_ROW_KERNEL_BEGIN(n)
+  const uint64_t z = splitmix64_dev(seed, stream_key_dev(stream, level, i));
+  const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+  x[i] = 2.0 * u - 1.0;
+}
+// max |y| as the bit pattern of a non-negative double (monotone for non-negative values).
+__global__ void k_absmax(int32_t n, const double *y, unsigned long long *out) {
+  __shared__ unsigned long long sh[kBlock];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long m = 0;
+  if (i < n) {
+    const double a = fabs(y[i]);
+    m = (a == a) ? (unsigned long long)__double_as_longlong(a) : 0ull;  // NaN ignored
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = kBlock / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w && sh[threadIdx.x + w] > sh[threadIdx.x])
+      sh[threadIdx.x] = sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(out, sh[0]);
+}
+__global__ void k_normalize(int32_t n, const double *y, const unsigned long long *mx,
+                            double *x, int32_t *dead) {
+  SA_ROW_KERNEL_BEGIN(n)
+  const double m = __longlong_as_double((long long)*mx);
+  if (!(m > 0.0) || !isfinite(m)) {
+    if (i == 0) *dead = 1;
+    return;
+  }
+  x[i] = ldexp(y[i], -ilogb(m));
+}
+__global__ void k_rayleigh(const double *xy, const double *xx, const int32_t *dead,
+                           double *lam) {
+  *lam = (*dead) ? 0.0 : (*xy / *xx);
+}
+
+void power_method(const Csr &M, const double *invD, int32_t iters, uint64_t seed, int32_t level,
+                  int32_t stream_id, double *lam, hipStream_t s) {
+  const int32_t n = M.n;
+  Arena tmp;
+  tmp.stream = s;
+  double *x = tmp.alloc<double>(n);
+  double *y = tmp.alloc<double>(n);
+  double *ws = tmp.alloc<double>(dot_ws_size(n));
+  double *sc = tmp.alloc<double>(4);
+  unsigned long long *mx = tmp.alloc<unsigned long long>(1);
+  int32_t *dead = tmp.alloc<int32_t>(1);
+  fill_i32(dead, 0, 1, s);
+  k_power_init<<<grid_for(n), kBlock, 0, s>>>(n, seed, level, stream_id, x);
+  SA_LAUNCH_CHECK();
+  SpmvArgs<double> a{n, M.rp, M.col, M.val, x};
+  for (int32_t t = 1; t <= iters; ++t) {
+    spmv_scale<double>(a, invD, y, s);
+    if (t == iters) {
+      dot_f64(x, y, n, sc + 0, ws, s);
+      dot_f64(x, x, n, sc + 1, ws, s);
+      k_rayleigh<<<1, 1, 0, s>>>(sc + 0, sc + 1, dead, lam);
+      SA_LAUNCH_CHECK();
+      break;
+    }
+    SA_HIP(hipMemsetAsync(mx, 0, sizeof(unsigned long long), s));
+    k_absmax<<<grid_for(n), kBlock, 0, s>>>(n, y, mx);
+    k_normalize<<<grid_for(n), kBlock, 0, s>>>(n, y, mx, x, dead);
+    SA_LAUNCH_CHECK();
+  }
+}
+
+__global__ void k_damping(double *lam, double *omega, bool unit, int32_t *err) {
+  if (unit) *lam = 1.0;
+  const double l = *lam;
+  if (!(l > 0.0) || !isfinite(l)) atomicOr(err, 16);
+  *omega = 4.0 / (3.0 * l);
+}
+void damping(double *lam, double *omega, bool unit, int32_t *err, hipStream_t s) {
+  k_damping<<<1, 1, 0, s>>>(lam, omega, unit, err);
+  SA_LAUNCH_CHECK();
+}
+
+// ---- prolongator smoothing (Sec. 1.1) -------------------------------------------------------
+// Row i: for each aggregate J reached by the filtered row (ascending J), acc = sum of the
+// entries with agg(k) = J in ascending k from 0; P_iJ = [J == agg_i] - (omega invD_i) acc.
+__global__ void k_P_count(int32_t n, const int32_t *rp, const int32_t *col, const int32_t *agg,
+                          int32_t *cnt) {
+  SA_ROW_KERNEL_BEGIN(n)
+  int32_t prev = -1, c = 0;
+  for (;;) {
+    int32_t J = INT_MAX;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+      const int32_t a = agg[col[k]];
+      if (a > prev && a < J) J = a;
+    }
+    if (J == INT_MAX) break;
+    ++c;
+    prev = J;
+  }
+  cnt[i] = c;
+}
+__global__ void k_P_fill(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                         const double *invD, const int32_t *agg, const double *omega,
+                         const int32_t *prp, int32_t *pcol, double *pval) {
+  SA_ROW_KERNEL_BEGIN(n)
+  const double t = (*omega) * invD[i];
+  const int32_t ai = agg[i];
+  int32_t prev = -1, w = prp[i];
+  for (;;) {
+    int32_t J = INT_MAX;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+      const int32_t a = agg[col[k]];
+      if (a > prev && a < J) J = a;
+    }
+    if (J == INT_MAX) break;
+    double acc = 0.0;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+      if (agg[col[k]] == J) acc += val[k];
+    pcol[w] = J;
+    pval[w] = ((J == ai) ? 1.0 : 0.0) - t * acc;
+    ++w;
+    prev = J;
+  }
+}
+int64_t prolongator(const Csr &abar, const double *invD, const int32_t *agg, int32_t nc,
+                    const double *omega, Arena &ar, Csr &P, hipStream_t s) {
+  const int32_t n = abar.n;
+  int32_t *cnt = (int32_t *)dev_alloc(sizeof(int32_t) * (n + 1), s);
+  k_P_count<<<grid_for(n), kBlock, 0, s>>>(n, abar.rp, abar.col, agg, cnt);
+  SA_LAUNCH_CHECK();
+  P.n = n;
+  P.ncols = nc;
+  P.rp = ar.alloc<int32_t>(n + 1);
+  exclusive_scan_i32(cnt, P.rp, n, s);
+  dev_free(cnt, s);
+  P.nnz = read1(P.rp + n, s);
+  P.col = ar.alloc<int32_t>(P.nnz);
+  P.val = ar.alloc<double>(P.nnz);
+  k_P_fill<<<grid_for(n), kBlock, 0, s>>>(n, abar.rp, abar.col, abar.val, invD, agg, omega, P.rp,
+                                          P.col, P.val);
+  SA_LAUNCH_CHECK();
+  return P.nnz;
+}
+
+// ---- Cnstrnt (Sec. 2.4, Algorithm 3, with the loop run while any bound is violated) ------
+__global__ void k_cnstrnt(int32_t n, const int32_t *rp, const int32_t *col, double *v,
+                          const int32_t *agg, uint8_t *inw) {
+  SA_ROW_KERNEL_BEGIN(n)
+  const int32_t b = rp[i], e = rp[i + 1];
+  bool viol = false;
+  for (int32_t k = b; k < e; ++k)
+    if (v[k] < 0.0 || v[k] > 1.0) viol = true;
+  if (!viol) return;
+  int32_t cnt = 0;
+  double sum = 0.0;
+  for (int32_t k = b; k < e; ++k) {
+    inw[k] = v[k] != 0.0;
+    if (inw[k]) {
+      ++cnt;
+      sum += v[k];
+    }
+  }
+  const int32_t ai = agg[i];
+  bool tent = false;
+  if (sum < 0.0 || sum > (double)cnt) {
+    tent = true;
+  } else if (sum == 0.0) {
+    for (int32_t k = b; k < e; ++k) v[k] = 0.0;
+    return;
+  } else {
+    while (cnt > 0) {
+      int32_t kmin = -1, kmax = -1;
+      for (int32_t k = b; k < e; ++k) {
+        if (!inw[k]) continue;
+        if (kmin < 0 || v[k] < v[kmin]) kmin = k;
+        if (kmax < 0 || v[k] > v[kmax]) kmax = k;
+      }
+      if (!(v[kmin] < 0.0 || v[kmax] > 1.0)) break;
+      double delta = 0.0;
+      if (v[kmin] < 0.0) {
+        delta += v[kmin];
+        v[kmin] = 0.0;
+        inw[kmin] = 0;
+        --cnt;
+      }
+      if (v[kmax] > 1.0) {
+        delta += v[kmax] - 1.0;
+        v[kmax] = 1.0;
+        inw[kmax] = 0;
+        --cnt;
+      }
+      if (cnt == 0) {
+        if (delta != 0.0) tent = true;
+        break;
+      }
+      const double q = delta / (double)cnt;
+      for (int32_t k = b; k < e; ++k)
+        if (inw[k]) v[k] += q;
+    }
+  }
+  if (tent)
+    for (int32_t k = b; k < e; ++k) v[k] = (col[k] == ai) ? 1.0 : 0.0;
+}
+void cnstrnt(const Csr &P, const int32_t *agg, hipStream_t s) {
+  if (P.n <= 0) return;
+  uint8_t *inw = (uint8_t *)dev_alloc(P.nnz > 0 ? P.nnz : 1, s);
+  k_cnstrnt<<<grid_for(P.n), kBlock, 0, s>>>(P.n, P.rp, P.col, P.val, agg, inw);
+  SA_LAUNCH_CHECK();
+  dev_free(inw, s);
+}
+
+__global__ void k_scale_rows(int32_t n, const int32_t *rp, double *val, const double *B) {
+  SA_ROW_KERNEL_BEGIN(n)
+  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) val[k] = B[i] * val[k];
+}
+void scale_rows(const Csr &P, const double *B, hipStream_t s) {
+  if (P.n <= 0) return;
+  k_scale_rows<<<grid_for(P.n), kBlock, 0, s>>>(P.n, P.rp, P.val, B);
+  SA_LAUNCH_CHECK();
+}
+
+__global__ void k_scale_sym(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                            const double *B, double *out) {
+  SA_ROW_KERNEL_BEGIN(n)
+  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) out[k] = (B[i] * val[k]) * B[col[k]];
+}
+void scale_sym(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+               const double *B, double *out, hipStream_t s) {
+  if (n <= 0) return;
+  k_scale_sym<<<grid_for(n), kBlock, 0, s>>>(n, rp, col, val, B, out);
+  SA_LAUNCH_CHECK();
+}
+
+// ---- transpose with values ---------------------------------------------------------------
+__global__ void k_count_cols(int64_t nnz, const int32_t *col, int32_t *cnt) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) atomicAdd(&cnt[col[e]], 1);
+}
+__global__ void k_scatter_tv(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                             int32_t *pos, int32_t *tcol, double *tval) {
+  SA_ROW_KERNEL_BEGIN(n)
+  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+    const int32_t p = atomicAdd(&pos[col[k]], 1);
+    tcol[p] = i;
+    tval[p] = val[k];
+  }
+}
+__global__ void k_sort_rows_iv(int32_t n, const int32_t *rp, int32_t *c, double *v) {
+  SA_ROW_KERNEL_BEGIN(n)
+  const int32_t b = rp[i], e = rp[i + 1];
+  for (int32_t k = b + 1; k < e; ++k) {
+    const int32_t ck = c[k];
+    const double vk = v[k];
+    int32_t q = k - 1;
+    while (q >= b && c[q] > ck) {
+      c[q + 1] = c[q];
+      v[q + 1] = v[q];
+      --q;
+    }
+    c[q + 1] = ck;
+    v[q + 1] = vk;
+  }
+}
+void transpose(const Csr &P, Arena &ar, Csr &R, hipStream_t s) {
+  const int32_t m = P.ncols;
+  int32_t *cnt = (int32_t *)dev_alloc(sizeof(int32_t) * (m + 1), s);
+  fill_i32(cnt, 0, m + 1, s);
+  if (P.nnz > 0) {
+    k_count_cols<<<grid_for(P.nnz), kBlock, 0, s>>>(P.nnz, P.col, cnt);
+    SA_LAUNCH_CHECK();
+  }
+  R.n = m;
+  R.ncols = P.n;
+  R.nnz = P.nnz;
+  R.rp = ar.alloc<int32_t>(m + 1);
+  exclusive_scan_i32(cnt, R.rp, m, s);
+  SA_HIP(hipMemcpyAsync(cnt, R.rp, sizeof(int32_t) * (m + 1), hipMemcpyDeviceToDevice, s));
+  R.col = ar.alloc<int32_t>(P.nnz);
+  R.val = ar.alloc<double>(P.nnz);
+  if (P.n > 0) {
+    k_scatter_tv<<<grid_for(P.n), kBlock, 0, s>>>(P.n, P.rp, P.col, P.val, cnt, R.col, R.val);
+    SA_LAUNCH_CHECK();
+  }
+  if (m > 0) {
+    k_sort_rows_iv<<<grid_for(m), kBlock, 0, s>>>(m, R.rp, R.col, R.val);
+    SA_LAUNCH_CHECK();
+  }
+  dev_free(cnt, s);
+}
+
+__global__ void k_inv_diag(int32_t n, const double *d, double *inv, int32_t *err) {
+  SA_ROW_KERNEL_BEGIN(n)
+  if (!(d[i] > 0.0)) atomicOr(err, 32);
+  inv[i] = 1.0 / d[i];
+}
+void inv_diag(int32_t n, const double *dval, double *invD, int32_t *err, hipStream_t s) {
+  if (n <= 0) return;
+  k_inv_diag<<<grid_for(n), kBlock, 0, s>>>(n, dval, invD, err);
+  SA_LAUNCH_CHECK();
+}
+
+}  // namespace sa

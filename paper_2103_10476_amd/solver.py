@@ -1,0 +1,197 @@
+"""Python front end of the SA-AMG library: options, setup, solve, exports.
+
+PyTorch provides device memory and the stream; every computation runs in libsaamg.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import Sequence
+
+import numpy as np
+
+from . import _lib
+
+VARIANT_BITS = {"sprsfy": 1, "offlmp": 2, "1norm": 4, "cnstrnt": 8}
+
+
+@dataclass
+class Options:
+    """Mirror of sa_options (include/saamg.h); defaults follow the paper where it states them."""
+
+    theta: float = 0.02
+    variants: Sequence[str] = field(default_factory=tuple)
+    tau: float = 1.1
+    sigma: float = 1.0 / 3.0
+    one_norm_power: int = 0
+    power_iters: int = 10
+    seed: int = 12345
+    agg_order: str = "natural"
+    max_levels: int = 10
+    max_coarse: int = 1000
+    smoother: str = "chebyshev"
+    degree: int = 2
+    precision: str = "fp64"
+    cheb_ratio: float = 10.0
+    cheb_boost: float = 1.0
+    rtol: float = 1e-8
+    max_iter: int = 500
+    pcg_beta: str = "auto"
+
+    def to_c(self) -> _lib.SaOptions:
+        o = _lib.SaOptions()
+        _lib.lib().sa_default_options(C.byref(o))
+        bits = 0
+        for v in self.variants:
+            bits |= VARIANT_BITS[v.lower()]
+        o.variants = bits
+        o.theta = self.theta
+        o.tau = self.tau
+        o.sigma = self.sigma
+        o.one_norm_power = self.one_norm_power
+        o.power_iters = self.power_iters
+        o.seed = self.seed
+        o.agg_order = 1 if self.agg_order in ("hashed", 1) else 0
+        o.max_levels = self.max_levels
+        o.max_coarse = self.max_coarse
+        o.smoother = 1 if self.smoother in ("jacobi", 1) else 0
+        o.degree = self.degree
+        o.precision = 1 if self.precision in ("fp32", "fp32_vcycle", 1) else 0
+        o.cheb_ratio = self.cheb_ratio
+        o.cheb_boost = self.cheb_boost
+        o.rtol = self.rtol
+        o.max_iter = self.max_iter
+        o.pcg_beta = {"auto": -1, "fr": 0, "pr": 1}[self.pcg_beta]
+        return o
+
+    def as_dict(self) -> dict:
+        d = dict(self.__dict__)
+        d["variants"] = list(self.variants)
+        return d
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(a, dtype):
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        t = a.to(device="cuda", dtype=dtype)
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+    return t.contiguous()
+
+
+class Hierarchy:
+    """A device-resident SA-AMG hierarchy (sa_hierarchy)."""
+
+    def __init__(self, n, rp, col, val, nullspace=None, options: Options | None = None,
+                 stream=None):
+        torch = _torch()
+        self.options = options or Options()
+        self.n = int(n)
+        self._stream = stream
+        L = _lib.lib()
+        drp = _dev(rp, torch.int32)
+        dcol = _dev(col, torch.int32)
+        dval = _dev(val, torch.float64)
+        csr = _lib.SaCsr(self.n, int(dcol.numel()), drp.data_ptr(), dcol.data_ptr(),
+                         dval.data_ptr(), _lib.SA_DEVICE)
+        dB = None if nullspace is None else _dev(nullspace, torch.float64)
+        ctx = _lib.SaContext(_stream_handle(stream))
+        opts = self.options.to_c()
+        h = C.c_void_p()
+        code = L.sa_setup(C.byref(ctx), C.byref(csr),
+                          None if dB is None else C.c_void_p(dB.data_ptr()), C.byref(opts),
+                          C.byref(h))
+        _lib.check(code, "sa_setup")
+        self._h = h
+
+    @classmethod
+    def from_problem(cls, p, nullspace=None, options=None, stream=None):
+        return cls(p.n, p.rp, p.col, p.val, nullspace=nullspace, options=options, stream=stream)
+
+    # ---- solve ------------------------------------------------------------------------
+    def solve(self, b, x=None):
+        """CG + V-cycle; b may be numpy or a CUDA tensor.  Returns (x, iterations, relres,
+        status) with x a float64 CUDA tensor."""
+        torch = _torch()
+        db = _dev(b, torch.float64)
+        if x is None:
+            x = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        it = C.c_int32()
+        rr = C.c_double()
+        code = _lib.lib().sa_solve(self._h, C.c_void_p(db.data_ptr()), C.c_void_p(x.data_ptr()),
+                                   _lib.SA_DEVICE, C.byref(it), C.byref(rr))
+        _lib.check(code, "sa_solve")
+        return x, it.value, rr.value, _lib.STATUS_NAMES[code]
+
+    def vcycle(self, f):
+        torch = _torch()
+        df = _dev(f, torch.float64)
+        z = torch.empty_like(df)
+        _lib.check(_lib.lib().sa_vcycle(self._h, C.c_void_p(df.data_ptr()),
+                                        C.c_void_p(z.data_ptr())), "sa_vcycle")
+        return z
+
+    # ---- inspection -----------------------------------------------------------------------
+    def info(self) -> dict:
+        inf = _lib.SaInfo()
+        _lib.check(_lib.lib().sa_hierarchy_info(self._h, C.byref(inf)), "sa_hierarchy_info")
+        nl = inf.levels
+        return {"levels": nl, "n": list(inf.n[:nl]), "nnz": list(inf.nnz[:nl]),
+                "nnz_p": list(inf.nnz_p[:nl]), "lambda": list(inf.lambda_[:nl]),
+                "omega": list(inf.omega[:nl]), "smoother_lambda": list(inf.smoother_lambda[:nl]),
+                "mis_rounds": list(inf.mis_rounds[:nl]),
+                "operator_complexity": inf.operator_complexity,
+                "device_bytes": inf.device_bytes, "setup_seconds": inf.setup_seconds}
+
+    def export(self, level: int, what: str) -> np.ndarray:
+        L = _lib.lib()
+        cnt = C.c_int64()
+        _lib.check(L.sa_export_size(self._h, level, _lib.PARTS[what], C.byref(cnt)),
+                   "sa_export_size")
+        out = np.empty(cnt.value, dtype=_lib.PART_DTYPE[what])
+        if cnt.value:
+            _lib.check(L.sa_export_level(self._h, level, _lib.PARTS[what],
+                                         out.ctypes.data_as(C.c_void_p), out.nbytes),
+                       "sa_export_level")
+        return out
+
+    def export_csr(self, level: int, name: str):
+        return (self.export(level, f"{name}_rp"), self.export(level, f"{name}_col"),
+                self.export(level, f"{name}_val"))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().sa_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def setup(A, nullspace=None, options: Options | None = None, stream=None) -> Hierarchy:
+    """setup(A, nullspace, options) -> hierarchy.  A is a CsrProblem or an (n, rp, col, val)
+    tuple (numpy or CUDA tensors)."""
+    if hasattr(A, "rp"):
+        return Hierarchy.from_problem(A, nullspace, options, stream)
+    n, rp, col, val = A
+    return Hierarchy(n, rp, col, val, nullspace, options, stream)
+
+
+def solve(h: Hierarchy, b):
+    """solve(hierarchy, b) -> (x, iterations)."""
+    x, it, _, _ = h.solve(b)
+    return x, it

@@ -1,0 +1,132 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same seeded
+inputs.  Setup arrays (strength masks, aggregates, roots, filtered matrices, diagonals,
+prolongators, restrictions, every coarse operator) and the eigenvalue/damping scalars must be
+bit-identical; the coarsest dense inverse agrees to rounding; the solve gives equal CG
+iteration counts and x within 1e-12 relative (the only source of difference is the coarsest
+solve: dense inverse on the GPU, Cholesky substitution in the oracle)."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2103_10476_amd import problems as pb
+from parity import compare_setup, compare_solve, log, run_both
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [[], ["sprsfy"], ["offlmp"], ["1norm"], ["cnstrnt"],
+            ["1norm", "offlmp", "cnstrnt", "sprsfy"]]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+
+
+@pytest.mark.parametrize("var", VARIANTS, ids=lambda v: "+".join(v) or "plain")
+def test_fd5_64x64_full_size(var):
+    """The 2-D 64x64 workload (aspect 1:100) at its full size, every variant."""
+    p = pb.workload("fd5_64x64_a100")
+    g, h = run_both(p, theta=0.02, variants=var, rtol=1e-8)
+    compare_setup(g, h)
+    compare_solve(g, h, pb.random_rhs(p.n, 1))
+
+
+@pytest.mark.parametrize("n", [9, 17, 24])
+@pytest.mark.parametrize("var", VARIANTS, ids=lambda v: "+".join(v) or "plain")
+def test_fd7_small_cubes(n, var):
+    """7-point stretched cubes spanning several SpMV row blocks and ragged tails."""
+    p = pb.fd7_stretched(n, 1000.0)
+    g, h = run_both(p, theta=0.02, variants=var, max_coarse=50, rtol=1e-10)
+    compare_setup(g, h)
+    compare_solve(g, h, pb.random_rhs(p.n, 2))
+
+
+@pytest.mark.parametrize("var", [["offlmp", "1norm"], ["1norm"], ["offlmp", "sprsfy"],
+                                 ["1norm", "cnstrnt"]], ids=lambda v: "+".join(v))
+def test_q1_random_kappa_small(var):
+    """27-point random-coefficient cube (long rows; SpGEMM block path)."""
+    p = pb.q1_random_kappa(14, seed=3)
+    g, h = run_both(p, theta=0.02, variants=var, max_coarse=40, rtol=1e-10)
+    compare_setup(g, h)
+    compare_solve(g, h, pb.random_rhs(p.n, 4))
+
+
+@pytest.mark.parametrize("var", [[], ["1norm"], ["offlmp"], ["offlmp", "1norm", "cnstrnt"]],
+                         ids=lambda v: "+".join(v) or "plain")
+def test_stress_box_theta015(var):
+    """Sec. 1.2 stress problem: Q1 on 1x1x2 boxes, theta = 0.15 (negative plain diagonals,
+    OffLmp branches with empty K-)."""
+    p = pb.q1_stretched_box(16, Fraction(2))
+    g, h = run_both(p, theta=0.15, variants=var, max_coarse=30, rtol=1e-10)
+    compare_setup(g, h)
+    compare_solve(g, h, pb.random_rhs(p.n, 7))
+
+
+def test_hashed_order_and_jacobi():
+    p = pb.fd7_stretched(20, 100.0)
+    g, h = run_both(p, theta=0.05, agg_order="hashed", seed=99, smoother="jacobi", degree=3,
+                    max_coarse=30, rtol=1e-9)
+    compare_setup(g, h)
+    compare_solve(g, h, pb.random_rhs(p.n, 3))
+
+
+def test_power_mode_and_pr_beta():
+    p = pb.fd7_stretched(16, 1000.0)
+    g, h = run_both(p, theta=0.02, variants=["1norm"], one_norm_power=1, pcg_beta="pr",
+                    max_coarse=30, rtol=1e-10)
+    compare_setup(g, h)
+    compare_solve(g, h, pb.random_rhs(p.n, 5))
+
+
+def test_nullspace_scaling():
+    p = pb.fd7_stretched(12, 100.0)
+    B = 1.0 + 0.5 * np.sin(np.arange(p.n))
+    g, h = run_both(p, nullspace=B, theta=0.02, max_coarse=30, rtol=1e-10)
+    compare_setup(g, h)
+    compare_solve(g, h, pb.random_rhs(p.n, 6))
+
+
+def test_single_level_direct():
+    p = pb.fd5_stretched(20, 20, 100.0)
+    g, h = run_both(p, max_coarse=1000)
+    assert g.info()["levels"] == 1
+    compare_setup(g, h)
+    compare_solve(g, h, pb.random_rhs(p.n, 8))
+
+
+def test_empty_strength_level_becomes_coarsest():
+    p = pb.q1_stretched_box(8, Fraction(2))
+    g, h = run_both(p, theta=0.15, max_coarse=20)
+    compare_setup(g, h)
+    compare_solve(g, h, pb.random_rhs(p.n, 7))
+
+
+def test_plain_q1_random_kappa_fails_like_oracle():
+    """Plain SA on the random-coefficient Q1 cube: zero filtered diagonals (Sec. 1.2)."""
+    from oracle import oracle as orc
+    from paper_2103_10476_amd import solver
+    from paper_2103_10476_amd._lib import SaError
+    p = pb.q1_random_kappa(20, seed=3)
+    with pytest.raises(orc.OracleError) as eo:
+        orc.OracleHierarchy(p.n, p.rp, p.col, p.val, theta=0.02)
+    with pytest.raises(SaError) as eg:
+        solver.Hierarchy.from_problem(p, options=solver.Options(theta=0.02))
+    assert eg.value.code == eo.value.code == -3
+
+
+def test_determinism_run_to_run():
+    p = pb.fd7_stretched(24, 1000.0)
+    from paper_2103_10476_amd import solver
+    o = solver.Options(variants=["sprsfy", "offlmp"], max_coarse=30)
+    a = solver.Hierarchy.from_problem(p, options=o)
+    b = solver.Hierarchy.from_problem(p, options=o)
+    for l in range(a.info()["levels"]):
+        for part in ("A_val", "A_col"):
+            assert np.array_equal(a.export(l, part), b.export(l, part))
+    xa = a.solve(pb.random_rhs(p.n, 1))[0].cpu().numpy()
+    xb = b.solve(pb.random_rhs(p.n, 1))[0].cpu().numpy()
+    assert np.array_equal(xa, xb)
