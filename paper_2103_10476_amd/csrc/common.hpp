@@ -76,13 +76,15 @@ struct Arena {
   }
 };
 
-// Device CSR view.
+// Device CSR view.  bstart/nblk: the SpMV row partition (see spmv_plan).
 struct Csr {
   int32_t n = 0, ncols = 0;
   int64_t nnz = 0;
   int32_t *rp = nullptr;
   int32_t *col = nullptr;
   double *val = nullptr;
+  int32_t *bstart = nullptr;
+  int32_t nblk = 0;
 };
 
 struct CsrF {  // float copy of the values for the FP32 V-cycle

@@ -160,11 +160,11 @@ static bool build_level(sa_hierarchy *h, int l) {
   int32_t *scount = tmp.alloc<int32_t>(n + 1);
   strength(n, L.As.rp, L.As.col, L.As.val, dval, o.theta * o.theta, L.mask, scount, s);
   int32_t *grp = nullptr, *gcol = nullptr;
-  strength_graph(n, L.As.rp, L.As.col, L.mask, scount, tmp, &grp, &gcol, s);
+  const int64_t nnzG = strength_graph(n, L.As.rp, L.As.col, L.mask, scount, tmp, &grp, &gcol, s);
   L.agg = ar.alloc<int32_t>(n);
   L.is_root = ar.alloc<uint8_t>(n);
   int32_t *root_vertex = nullptr;
-  L.nc = aggregate(n, grp, gcol, o.agg_order, o.seed, l, L.agg, L.is_root, tmp, &root_vertex,
+  L.nc = aggregate(n, nnzG, grp, gcol, o.agg_order, o.seed, l, L.agg, L.is_root, tmp, &root_vertex,
                    &L.mis_rounds, s);
   if (L.nc == 0) return false;
   if (L.nc >= n) throw Error(SA_ERR_COARSEN_STALLED, "coarsening stalled");
@@ -174,6 +174,7 @@ static bool build_level(sa_hierarchy *h, int l) {
   lump(n, L.As.rp, L.As.col, L.As.val, L.mask, (o.variants & SA_OFFLMP) != 0, o.tau, one_norm,
        safeguard_mult(o.sigma), ar, L.Abar, L.invD, h->err, s);
   check_err(h, E_ZERO_FDIAG, SA_ERR_NONPOSITIVE_DIAG, "zero diagonal in the filtered matrix");
+  spmv_plan(L.Abar, ar, s);
   L.lam_d = ar.alloc<double>(2);
   L.omega_d = L.lam_d + 1;
   const bool unit = one_norm && o.one_norm_power == 0;
@@ -182,6 +183,7 @@ static bool build_level(sa_hierarchy *h, int l) {
   check_err(h, E_LAMBDA, SA_ERR_NEGATIVE_EIGENVALUE, "eigenvalue estimate not positive");
   prolongator(L.Abar, L.invD, L.agg, L.nc, L.omega_d, ar, L.P, s);
   if (o.variants & SA_CNSTRNT) cnstrnt(L.P, L.agg, s);
+  spmv_plan(L.P, ar, s);
   return true;
 }
 
@@ -217,6 +219,7 @@ static void setup_impl(sa_hierarchy *h, const sa_csr *A, const double *B) {
     if (e & E_STRUCT) throw Error(SA_ERR_BAD_CSR, "columns out of range or not ascending");
     if (e & E_NODIAG) throw Error(SA_ERR_BAD_CSR, "missing diagonal");
   }
+  spmv_plan(L0.A, h->ar, s);
   L0.As = L0.A;
   double *dB = nullptr;
   if (B) {
@@ -251,6 +254,7 @@ static void setup_impl(sa_hierarchy *h, const sa_csr *A, const double *B) {
     Level &L = h->lv[l];
     if (l == 0 && dB) scale_rows(L.P, dB, s);
     transpose(L.P, h->ar, L.R, s);
+    spmv_plan(L.R, h->ar, s);
     Csr Ac;
     {
       Arena tmp;
@@ -259,6 +263,7 @@ static void setup_impl(sa_hierarchy *h, const sa_csr *A, const double *B) {
       spgemm(L.A, L.P, tmp, AP, s);
       spgemm(L.R, AP, h->ar, Ac, s);
     }
+    spmv_plan(Ac, h->ar, s);
     h->lv.emplace_back();
     h->lv[l + 1].A = Ac;
     h->lv[l + 1].As = Ac;
@@ -347,9 +352,9 @@ struct LevelView {
 
 static LevelView<double> view64(Level &L) {
   LevelView<double> v;
-  v.A = {L.A.n, L.A.rp, L.A.col, L.A.val, nullptr};
-  v.P = {L.P.n, L.P.rp, L.P.col, L.P.val, nullptr};
-  v.R = {L.R.n, L.R.rp, L.R.col, L.R.val, nullptr};
+  v.A = spmv_args<double>(L.A, L.A.val, nullptr);
+  v.P = spmv_args<double>(L.P, L.P.val, nullptr);
+  v.R = spmv_args<double>(L.R, L.R.val, nullptr);
   v.invD = L.sm_invD;
   v.f = L.f;
   v.u = L.u;
@@ -360,9 +365,9 @@ static LevelView<double> view64(Level &L) {
 }
 static LevelView<float> view32(Level &L) {
   LevelView<float> v;
-  v.A = {L.A.n, L.A.rp, L.A.col, L.Af, nullptr};
-  v.P = {L.P.n, L.P.rp, L.P.col, L.Pf, nullptr};
-  v.R = {L.R.n, L.R.rp, L.R.col, L.Rf, nullptr};
+  v.A = spmv_args<float>(L.A, L.Af, nullptr);
+  v.P = spmv_args<float>(L.P, L.Pf, nullptr);
+  v.R = spmv_args<float>(L.R, L.Rf, nullptr);
   v.invD = L.sm_invDf;
   v.f = L.ff;
   v.u = L.uf;
@@ -505,7 +510,7 @@ static sa_status solve_impl(sa_hierarchy *h, const double *b, double *x, sa_loca
   SA_HIP(hipMemcpyAsync(h->p, h->z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   dot_f64(h->r, h->z, n, &S->rho1, h->dws, s);
   pcg_init_rho(S, s);
-  SpmvArgs<double> A{n, h->lv[0].A.rp, h->lv[0].A.col, h->lv[0].A.val, h->p};
+  SpmvArgs<double> A = spmv_args<double>(h->lv[0].A, h->lv[0].A.val, h->p);
   for (int32_t k = 1; k <= o.max_iter; ++k) {
     spmv_store<double>(A, h->q, s);
     dot_f64(h->p, h->q, n, &S->pq, h->dws, s);

@@ -15,7 +15,19 @@ struct SpmvArgs {
   const int32_t *col;
   const T *val;
   const T *x;
+  const int32_t *bstart;  // row partition from spmv_plan
+  int32_t nblk;
 };
+// Row partition for the SpMV kernels: block b owns the rows whose cost rp[r] + 8 r lies in
+// [2048 b, 2048 (b+1)), i.e. at most 256 rows and (long rows aside) at most 2048 entries.
+void spmv_plan(Csr &A, Arena &ar, hipStream_t s);
+template <class T>
+inline SpmvArgs<T> spmv_args(const Csr &A, const T *val, const T *x) {
+  return SpmvArgs<T>{A.n, A.rp, A.col, val, x, A.bstart, A.nblk};
+}
+// Sorts the entries of every row by column (values follow when val != nullptr); keys within a
+// row must be distinct.  Short rows per thread, long rows per block (bitonic in LDS).
+void sort_rows(int32_t n, const int32_t *rp, int32_t *col, double *val, hipStream_t s);
 
 template <class T> void spmv_store(const SpmvArgs<T> &a, T *y, hipStream_t s);
 template <class T> void spmv_scale(const SpmvArgs<T> &a, const T *d, T *y, hipStream_t s);
@@ -86,7 +98,7 @@ int64_t strength_graph(int32_t n, const int32_t *rp, const int32_t *col, const u
                        hipStream_t s);
 // Aggregation (roots = lexicographically-first distance-2 MIS in priority order; phase-2
 // join; isolated vertices unaggregated).  Returns nc; agg[n], is_root[n], root_vertex[nc].
-int32_t aggregate(int32_t n, const int32_t *grp, const int32_t *gcol, int32_t order,
+int32_t aggregate(int32_t n, int64_t nnzG, const int32_t *grp, const int32_t *gcol, int32_t order,
                   uint64_t seed, int32_t level, int32_t *agg, uint8_t *is_root, Arena &ar,
                   int32_t **root_vertex, int32_t *rounds, hipStream_t s);
 // Sprsfy: marks dropped strong entries (mask 1 -> 2).

@@ -121,21 +121,6 @@ __global__ void k_scatter_t(int32_t n, const int32_t *srp, const int32_t *scol, 
     tcol[p] = i;
   }
 }
-// Insertion sort of every row's columns (rows are short; the result does not depend on the
-// order the atomic scatter produced).
-__global__ void k_sort_rows_i32(int32_t n, const int32_t *rp, int32_t *c) {
-  SA_ROW_KERNEL_BEGIN(n)
-  const int32_t b = rp[i], e = rp[i + 1];
-  for (int32_t k = b + 1; k < e; ++k) {
-    int32_t v = c[k];
-    int32_t q = k - 1;
-    while (q >= b && c[q] > v) {
-      c[q + 1] = c[q];
-      --q;
-    }
-    c[q + 1] = v;
-  }
-}
 __global__ void k_union(int32_t n, const int32_t *arp, const int32_t *acol, const int32_t *brp,
                         const int32_t *bcol, const int32_t *orp, int32_t *ocol, int32_t *ocnt) {
   SA_ROW_KERNEL_BEGIN(n)
@@ -176,8 +161,7 @@ int64_t strength_graph(int32_t n, const int32_t *rp, const int32_t *col, const u
   int32_t *tcol = tmp.alloc<int32_t>(nnzS);
   k_scatter_t<<<grid_for(n), kBlock, 0, s>>>(n, srp, scol, tpos, tcol);
   SA_LAUNCH_CHECK();
-  k_sort_rows_i32<<<grid_for(n), kBlock, 0, s>>>(n, trp, tcol);
-  SA_LAUNCH_CHECK();
+  sort_rows(n, trp, tcol, nullptr, s);
   int32_t *gcnt = tmp.alloc<int32_t>(n + 1);
   k_union<<<grid_for(n), kBlock, 0, s>>>(n, srp, scol, trp, tcol, nullptr, nullptr, gcnt);
   SA_LAUNCH_CHECK();
@@ -193,13 +177,28 @@ int64_t strength_graph(int32_t n, const int32_t *rp, const int32_t *col, const u
 }
 
 // ---- root selection: lexicographically-first distance-2 maximal independent set -----------
-// key = (state << 62) | priority with state IN = 0, UNDECIDED = 1, OUT = 2.  Per round:
-// k1(v) = min key over N[v]; k2(v) = min k1 over N[v] (= min over the distance-2 ball).  An
-// undecided v leaves as OUT when k2 is an IN key (a root within distance 2) and enters as IN
-// when k2 is its own key (best priority among undecided vertices within distance 2).  This
+// key = (state, priority) with state IN < UNDECIDED < OUT in the top two bits, so the
+// minimum key of a neighbourhood is its best vertex.  Per round: k1(v) = min key over N[v];
+// then an undecided v with m = min k1 over N[v] (the minimum over the distance-2 ball)
+// leaves as OUT when m is an IN key (a root within distance 2) and enters as IN when m is its
+// own key (it has the best priority among undecided vertices within distance 2).  This
 // reproduces the sequential greedy root choice in priority order exactly.
-constexpr uint64_t kIn = 0, kUnd = 1ull << 62, kOut = 2ull << 62;
-constexpr uint64_t kStateMask = 3ull << 62;
+//
+// Each round touches only open work: a vertex is "active" while it or a neighbour is
+// undecided (once inactive it stays inactive, so pass 1 skips it after a 1-byte read) and pass
+// 2 skips decided vertices.  Natural order uses 32-bit keys (state << 30 | index); hashed
+// order 64-bit keys (state << 62 | hash30 << 32 | index).  Levels with high average degree
+// use one wavefront per vertex.
+template <class K>
+struct KeyT;
+template <>
+struct KeyT<uint32_t> {
+  static constexpr uint32_t In = 0, Und = 1u << 30, Out = 2u << 30, Mask = 3u << 30;
+};
+template <>
+struct KeyT<uint64_t> {
+  static constexpr uint64_t In = 0, Und = 1ull << 62, Out = 2ull << 62, Mask = 3ull << 62;
+};
 
 __device__ inline uint64_t splitmix64_dev(uint64_t seed, uint64_t k) {
   uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
@@ -211,61 +210,126 @@ __device__ inline uint64_t stream_key_dev(int stream, int level, int64_t i) {
   return ((uint64_t)stream << 56) | ((uint64_t)level << 40) | (uint64_t)i;
 }
 
+template <class K>
 __global__ void k_mis_init(int32_t n, const int32_t *grp, int32_t order, uint64_t seed,
-                           int32_t level, uint64_t *key) {
+                           int32_t level, K *key, uint8_t *act) {
   SA_ROW_KERNEL_BEGIN(n)
-  uint64_t pri = (uint64_t)i;
-  if (order == 1) pri = ((splitmix64_dev(seed, stream_key_dev(2, level, i)) >> 34) << 32) | pri;
-  key[i] = (grp[i + 1] == grp[i] ? kOut : kUnd) | pri;
+  K pri = (K)i;
+  if (order == 1)
+    pri = (K)((((uint64_t)splitmix64_dev(seed, stream_key_dev(2, level, i)) >> 34) << 32) |
+              (uint64_t)i);
+  const bool open = grp[i + 1] > grp[i];
+  key[i] = (open ? KeyT<K>::Und : KeyT<K>::Out) | pri;
+  act[i] = open ? 1 : 0;
 }
-__global__ void k_mis_min1(int32_t n, const int32_t *grp, const int32_t *gcol,
-                           const uint64_t *key, uint64_t *k1) {
-  SA_ROW_KERNEL_BEGIN(n)
-  uint64_t m = key[i];
-  for (int32_t k = grp[i]; k < grp[i + 1]; ++k) {
-    uint64_t v = key[gcol[k]];
-    m = v < m ? v : m;
+
+template <class K, bool WAVE>
+__global__ void k_mis_pass1(int32_t n, const int32_t *grp, const int32_t *gcol, const K *key,
+                            K *k1, uint8_t *act) {
+  if (WAVE) {
+    const int lane = threadIdx.x & 63;
+    const int64_t v64 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (v64 >= n) return;
+    const int32_t v = (int32_t)v64;
+    if (!act[v]) return;  // wave-uniform
+    K m = (lane == 0) ? key[v] : ~(K)0;
+    bool und = (lane == 0) && ((key[v] & KeyT<K>::Mask) == KeyT<K>::Und);
+    for (int32_t k = grp[v] + lane; k < grp[v + 1]; k += 64) {
+      const K ku = key[gcol[k]];
+      m = ku < m ? ku : m;
+      und |= (ku & KeyT<K>::Mask) == KeyT<K>::Und;
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+      const K o = __shfl_xor(m, off, 64);
+      m = o < m ? o : m;
+    }
+    const bool anyund = __ballot(und) != 0;
+    if (lane == 0) {
+      k1[v] = m;
+      if (!anyund) act[v] = 0;
+    }
+  } else {
+    SA_ROW_KERNEL_BEGIN(n)
+    if (!act[i]) return;
+    K m = key[i];
+    bool und = (m & KeyT<K>::Mask) == KeyT<K>::Und;
+    for (int32_t k = grp[i]; k < grp[i + 1]; ++k) {
+      const K ku = key[gcol[k]];
+      m = ku < m ? ku : m;
+      und |= (ku & KeyT<K>::Mask) == KeyT<K>::Und;
+    }
+    k1[i] = m;
+    if (!und) act[i] = 0;
   }
-  k1[i] = m;
 }
-__global__ void k_mis_decide(int32_t n, const int32_t *grp, const int32_t *gcol,
-                             const uint64_t *k1, uint64_t *key, int32_t *flag) {
-  SA_ROW_KERNEL_BEGIN(n)
-  const uint64_t me = key[i];
-  if ((me & kStateMask) != kUnd) return;
-  uint64_t m = k1[i];
-  for (int32_t k = grp[i]; k < grp[i + 1]; ++k) {
-    uint64_t v = k1[gcol[k]];
-    m = v < m ? v : m;
+
+template <class K, bool WAVE>
+__global__ void k_mis_pass2(int32_t n, const int32_t *grp, const int32_t *gcol, const K *k1,
+                            K *key, int32_t *flag) {
+  if (WAVE) {
+    const int lane = threadIdx.x & 63;
+    const int64_t v64 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (v64 >= n) return;
+    const int32_t v = (int32_t)v64;
+    const K me = key[v];
+    if ((me & KeyT<K>::Mask) != KeyT<K>::Und) return;  // wave-uniform
+    K m = (lane == 0) ? k1[v] : ~(K)0;
+    for (int32_t k = grp[v] + lane; k < grp[v + 1]; k += 64) {
+      const K ku = k1[gcol[k]];
+      m = ku < m ? ku : m;
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+      const K o = __shfl_xor(m, off, 64);
+      m = o < m ? o : m;
+    }
+    if (lane == 0) {
+      const K pri = me & ~KeyT<K>::Mask;
+      if ((m & KeyT<K>::Mask) == KeyT<K>::In) key[v] = KeyT<K>::Out | pri;
+      else if (m == me) key[v] = KeyT<K>::In | pri;
+      else *flag = 1;
+    }
+  } else {
+    SA_ROW_KERNEL_BEGIN(n)
+    const K me = key[i];
+    if ((me & KeyT<K>::Mask) != KeyT<K>::Und) return;
+    K m = k1[i];
+    for (int32_t k = grp[i]; k < grp[i + 1]; ++k) {
+      const K ku = k1[gcol[k]];
+      m = ku < m ? ku : m;
+    }
+    const K pri = me & ~KeyT<K>::Mask;
+    if ((m & KeyT<K>::Mask) == KeyT<K>::In) key[i] = KeyT<K>::Out | pri;
+    else if (m == me) key[i] = KeyT<K>::In | pri;
+    else *flag = 1;
   }
-  const uint64_t pri = me & ~kStateMask;
-  if ((m & kStateMask) == kIn) key[i] = kOut | pri;
-  else if (m == me) key[i] = kIn | pri;
-  else *flag = 1;
 }
-__global__ void k_roots(int32_t n, const uint64_t *key, int32_t *isr) {
+
+template <class K>
+__global__ void k_roots(int32_t n, const K *key, int32_t *isr) {
   SA_ROW_KERNEL_BEGIN(n)
-  isr[i] = ((key[i] & kStateMask) == kIn) ? 1 : 0;
+  isr[i] = ((key[i] & KeyT<K>::Mask) == KeyT<K>::In) ? 1 : 0;
 }
-__global__ void k_agg_phase1(int32_t n, const int32_t *grp, const int32_t *gcol,
-                             const uint64_t *key, const int32_t *rid, int32_t *agg1,
-                             uint8_t *is_root, int32_t *root_vertex) {
+template <class K>
+__global__ void k_agg_phase1(int32_t n, const int32_t *grp, const int32_t *gcol, const K *key,
+                             const int32_t *rid, int32_t *agg1, uint8_t *is_root,
+                             int32_t *root_vertex) {
   SA_ROW_KERNEL_BEGIN(n)
   int32_t a = -1;
-  if ((key[i] & kStateMask) == kIn) {
+  const bool root = (key[i] & KeyT<K>::Mask) == KeyT<K>::In;
+  if (root) {
     a = rid[i];
     root_vertex[a] = i;
   } else {
     for (int32_t k = grp[i]; k < grp[i + 1]; ++k) {
-      int32_t u = gcol[k];
-      if ((key[u] & kStateMask) == kIn) {
+      const int32_t u = gcol[k];
+      if ((key[u] & KeyT<K>::Mask) == KeyT<K>::In) {
         a = rid[u];
         break;
       }
     }
   }
   agg1[i] = a;
-  is_root[i] = ((key[i] & kStateMask) == kIn) ? 1 : 0;
+  is_root[i] = root ? 1 : 0;
 }
 // Leftover vertices join the phase-1 aggregate with the most strong connections to them,
 // ties to the smaller aggregate number.
@@ -291,59 +355,84 @@ __global__ void k_agg_phase2(int32_t n, const int32_t *grp, const int32_t *gcol,
   agg[i] = a;
 }
 
-int32_t aggregate(int32_t n, const int32_t *grp, const int32_t *gcol, int32_t order,
-                  uint64_t seed, int32_t level, int32_t *agg, uint8_t *is_root, Arena &ar,
-                  int32_t **root_vertex, int32_t *rounds_out, hipStream_t s) {
+template <class K>
+static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const int32_t *gcol,
+                              int32_t order, uint64_t seed, int32_t level, int32_t *agg,
+                              uint8_t *is_root, Arena &ar, int32_t **root_vertex,
+                              int32_t *rounds_out, hipStream_t s) {
   Arena tmp;
   tmp.stream = s;
-  uint64_t *key = tmp.alloc<uint64_t>(n);
-  uint64_t *k1 = tmp.alloc<uint64_t>(n);
-  k_mis_init<<<grid_for(n), kBlock, 0, s>>>(n, grp, order, seed, level, key);
+  K *key = tmp.alloc<K>(n);
+  K *k1 = tmp.alloc<K>(n);
+  uint8_t *act = tmp.alloc<uint8_t>(n);
+  k_mis_init<K><<<grid_for(n), kBlock, 0, s>>>(n, grp, order, seed, level, key, act);
   SA_LAUNCH_CHECK();
-  // Rounds run in batches between flag checks; an extra round on a finished state changes
-  // nothing.  flags[r] = 1 iff some vertex was still undecided after round r.
-  const int batch = 8;
-  int64_t cap = (int64_t)n + batch + 2;
+  // Rounds run in batches between flag checks; a round on a finished state changes nothing.
+  // flags[r] = 1 iff some vertex was still undecided after round r.
+  const int batch = 16;
+  const int64_t cap = (int64_t)n + batch + 2;
   int32_t *flags = tmp.alloc<int32_t>(cap);
   fill_i32(flags, 0, cap, s);
+  const bool wave = nnzG > 24 * (int64_t)n;
+  const unsigned g = wave ? grid_for((int64_t)n * 64) : grid_for(n);
   int32_t *hflags = nullptr;
   SA_HIP(hipHostMalloc((void **)&hflags, sizeof(int32_t) * batch, hipHostMallocDefault));
   int64_t r = 0;
   int32_t used = 0;
-  bool done = false;
-  while (!done) {
-    for (int q = 0; q < batch; ++q, ++r) {
-      if (r >= cap) throw Error(SA_ERR_COARSEN_STALLED, "root selection did not terminate");
-      k_mis_min1<<<grid_for(n), kBlock, 0, s>>>(n, grp, gcol, key, k1);
-      k_mis_decide<<<grid_for(n), kBlock, 0, s>>>(n, grp, gcol, k1, key, flags + r);
-    }
-    SA_LAUNCH_CHECK();
-    SA_HIP(hipMemcpyAsync(hflags, flags + r - batch, sizeof(int32_t) * batch,
-                          hipMemcpyDeviceToHost, s));
-    SA_HIP(hipStreamSynchronize(s));
-    for (int q = 0; q < batch; ++q)
-      if (hflags[q] == 0) {
-        used = (int32_t)(r - batch + q + 1);
-        done = true;
-        break;
+  bool done = nnzG == 0;
+  try {
+    while (!done) {
+      for (int q = 0; q < batch; ++q, ++r) {
+        if (r >= cap) throw Error(SA_ERR_COARSEN_STALLED, "root selection did not end");
+        if (wave) {
+          k_mis_pass1<K, true><<<g, kBlock, 0, s>>>(n, grp, gcol, key, k1, act);
+          k_mis_pass2<K, true><<<g, kBlock, 0, s>>>(n, grp, gcol, k1, key, flags + r);
+        } else {
+          k_mis_pass1<K, false><<<g, kBlock, 0, s>>>(n, grp, gcol, key, k1, act);
+          k_mis_pass2<K, false><<<g, kBlock, 0, s>>>(n, grp, gcol, k1, key, flags + r);
+        }
       }
+      SA_LAUNCH_CHECK();
+      SA_HIP(hipMemcpyAsync(hflags, flags + r - batch, sizeof(int32_t) * batch,
+                            hipMemcpyDeviceToHost, s));
+      SA_HIP(hipStreamSynchronize(s));
+      for (int q = 0; q < batch; ++q)
+        if (hflags[q] == 0) {
+          used = (int32_t)(r - batch + q + 1);
+          done = true;
+          break;
+        }
+    }
+  } catch (...) {
+    (void)hipHostFree(hflags);
+    throw;
   }
   (void)hipHostFree(hflags);
   if (rounds_out) *rounds_out = used;
   int32_t *isr = tmp.alloc<int32_t>(n + 1);
-  k_roots<<<grid_for(n), kBlock, 0, s>>>(n, key, isr);
+  k_roots<K><<<grid_for(n), kBlock, 0, s>>>(n, key, isr);
   SA_LAUNCH_CHECK();
   int32_t *rid = tmp.alloc<int32_t>(n + 1);
   exclusive_scan_i32(isr, rid, n, s);
   const int32_t nc = read1(rid + n, s);
   int32_t *rv = ar.alloc<int32_t>(nc > 0 ? nc : 1);
   int32_t *agg1 = tmp.alloc<int32_t>(n);
-  k_agg_phase1<<<grid_for(n), kBlock, 0, s>>>(n, grp, gcol, key, rid, agg1, is_root, rv);
+  k_agg_phase1<K><<<grid_for(n), kBlock, 0, s>>>(n, grp, gcol, key, rid, agg1, is_root, rv);
   SA_LAUNCH_CHECK();
   k_agg_phase2<<<grid_for(n), kBlock, 0, s>>>(n, grp, gcol, agg1, agg);
   SA_LAUNCH_CHECK();
   *root_vertex = rv;
   return nc;
+}
+
+int32_t aggregate(int32_t n, int64_t nnzG, const int32_t *grp, const int32_t *gcol,
+                  int32_t order, uint64_t seed, int32_t level, int32_t *agg, uint8_t *is_root,
+                  Arena &ar, int32_t **root_vertex, int32_t *rounds, hipStream_t s) {
+  if (order == 0 && n < (1 << 30))
+    return aggregate_impl<uint32_t>(n, nnzG, grp, gcol, order, seed, level, agg, is_root, ar,
+                                    root_vertex, rounds, s);
+  return aggregate_impl<uint64_t>(n, nnzG, grp, gcol, order, seed, level, agg, is_root, ar,
+                                  root_vertex, rounds, s);
 }
 
 // ---- Sprsfy (Sec. 2.5) --------------------------------------------------------------------
@@ -625,7 +714,7 @@ void power_method(const Csr &M, const double *invD, int32_t iters, uint64_t seed
   fill_i32(dead, 0, 1, s);
   k_power_init<<<grid_for(n), kBlock, 0, s>>>(n, seed, level, stream_id, x);
   SA_LAUNCH_CHECK();
-  SpmvArgs<double> a{n, M.rp, M.col, M.val, x};
+  SpmvArgs<double> a = spmv_args<double>(M, M.val, x);
   for (int32_t t = 1; t <= iters; ++t) {
     spmv_scale<double>(a, invD, y, s);
     if (t == iters) {
@@ -804,6 +893,140 @@ void scale_sym(int32_t n, const int32_t *rp, const int32_t *col, const double *v
   SA_LAUNCH_CHECK();
 }
 
+
+// ---- per-row sort by column --------------------------------------------------------------
+// Rows of up to kSortShort entries: insertion sort by one thread.  Longer rows: one block per
+// row, bitonic sort in LDS (kSortLds entries) or, beyond that, in a global scratch region
+// sized for the row.  Keys within a row are distinct, so the order is unique.
+constexpr int32_t kSortShort = 32;
+constexpr int32_t kSortLds = 4096;
+
+__device__ inline void wave_append(bool pred, int32_t *counter, int32_t *list, int32_t value) {
+  const unsigned long long m = __ballot(pred);
+  if (!m) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)m) - 1;
+  int32_t base = 0;
+  if (lane == leader) base = atomicAdd(counter, __popcll(m));
+  base = __shfl(base, leader, 64);
+  if (pred) list[base + __popcll(m & ((1ull << lane) - 1ull))] = value;
+}
+
+__global__ void k_sort_short(int32_t n, const int32_t *rp, int32_t *c, double *v,
+                             int32_t *nlong, int32_t *longrows) {
+  const int64_t i64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i64 < n;
+  const int32_t i = live ? (int32_t)i64 : 0;
+  const int32_t b = live ? rp[i] : 0, e = live ? rp[i + 1] : 0;
+  const bool is_long = live && (e - b > kSortShort);
+  wave_append(is_long, nlong, longrows, i);
+  if (!live || is_long) return;
+  for (int32_t k = b + 1; k < e; ++k) {
+    const int32_t ck = c[k];
+    const double vk = v ? v[k] : 0.0;
+    int32_t q = k - 1;
+    while (q >= b && c[q] > ck) {
+      c[q + 1] = c[q];
+      if (v) v[q + 1] = v[q];
+      --q;
+    }
+    c[q + 1] = ck;
+    if (v) v[q + 1] = vk;
+  }
+}
+
+__device__ inline void bitonic_kv_any(int32_t *k, double *v, int32_t L) {
+  for (int32_t kk = 2; kk <= L; kk <<= 1) {
+    for (int32_t j = kk >> 1; j > 0; j >>= 1) {
+      for (int32_t idx = threadIdx.x; idx < L; idx += blockDim.x) {
+        const int32_t ixj = idx ^ j;
+        if (ixj > idx) {
+          const int32_t x = k[idx], y = k[ixj];
+          const bool up = (idx & kk) == 0;
+          if ((x > y) == up) {
+            k[idx] = y;
+            k[ixj] = x;
+            if (v) {
+              const double t = v[idx];
+              v[idx] = v[ixj];
+              v[ixj] = t;
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// One block per long row; rows longer than kSortLds use gk/gv at goff[slot].
+__global__ __launch_bounds__(kBlock) void k_sort_long(const int32_t *rows, int32_t nrows,
+                                                      const int32_t *rp, int32_t *c, double *v,
+                                                      int32_t *gk, double *gv,
+                                                      const int64_t *goff) {
+  __shared__ int32_t sk[kSortLds];
+  __shared__ double sv[kSortLds];
+  const int32_t slot = blockIdx.x;
+  if (slot >= nrows) return;
+  const int32_t i = rows[slot];
+  const int32_t b = rp[i], len = rp[i + 1] - b;
+  int32_t L = 1;
+  while (L < len) L <<= 1;
+  int32_t *kk;
+  double *vv;
+  if (L <= kSortLds) {
+    kk = sk;
+    vv = v ? sv : nullptr;
+  } else {
+    kk = gk + goff[slot];
+    vv = v ? gv + goff[slot] : nullptr;
+  }
+  for (int32_t q = threadIdx.x; q < L; q += blockDim.x) {
+    kk[q] = q < len ? c[b + q] : INT_MAX;
+    if (vv) vv[q] = q < len ? v[b + q] : 0.0;
+  }
+  __syncthreads();
+  bitonic_kv_any(kk, vv, L);
+  for (int32_t q = threadIdx.x; q < len; q += blockDim.x) {
+    c[b + q] = kk[q];
+    if (v) v[b + q] = vv[q];
+  }
+}
+
+__global__ void k_sort_caps(int32_t nrows, const int32_t *rows, const int32_t *rp,
+                            int64_t *caps) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows) return;
+  const int32_t i = rows[t];
+  const int32_t len = rp[i + 1] - rp[i];
+  int64_t L = 1;
+  while (L < len) L <<= 1;
+  caps[t] = (L <= kSortLds) ? 0 : L;
+}
+
+void sort_rows(int32_t n, const int32_t *rp, int32_t *col, double *val, hipStream_t s) {
+  if (n <= 0) return;
+  Arena tmp;
+  tmp.stream = s;
+  int32_t *nlong = tmp.alloc<int32_t>(1);
+  int32_t *rows = tmp.alloc<int32_t>(n);
+  fill_i32(nlong, 0, 1, s);
+  k_sort_short<<<grid_for(n), kBlock, 0, s>>>(n, rp, col, val, nlong, rows);
+  SA_LAUNCH_CHECK();
+  const int32_t nl = read1(nlong, s);
+  if (nl == 0) return;
+  int64_t *caps = tmp.alloc<int64_t>(nl + 1);
+  int64_t *goff = tmp.alloc<int64_t>(nl + 1);
+  k_sort_caps<<<grid_for(nl), kBlock, 0, s>>>(nl, rows, rp, caps);
+  SA_LAUNCH_CHECK();
+  exclusive_scan_i64(caps, goff, nl, s);
+  const int64_t gtot = read1(goff + nl, s);
+  int32_t *gk = tmp.alloc<int32_t>(gtot > 0 ? gtot : 1);
+  double *gv = tmp.alloc<double>(gtot > 0 ? gtot : 1);
+  k_sort_long<<<(unsigned)nl, kBlock, 0, s>>>(rows, nl, rp, col, val, gk, gv, goff);
+  SA_LAUNCH_CHECK();
+}
+
 // ---- transpose with values ---------------------------------------------------------------
 __global__ void k_count_cols(int64_t nnz, const int32_t *col, int32_t *cnt) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -816,22 +1039,6 @@ __global__ void k_scatter_tv(int32_t n, const int32_t *rp, const int32_t *col, c
     const int32_t p = atomicAdd(&pos[col[k]], 1);
     tcol[p] = i;
     tval[p] = val[k];
-  }
-}
-__global__ void k_sort_rows_iv(int32_t n, const int32_t *rp, int32_t *c, double *v) {
-  SA_ROW_KERNEL_BEGIN(n)
-  const int32_t b = rp[i], e = rp[i + 1];
-  for (int32_t k = b + 1; k < e; ++k) {
-    const int32_t ck = c[k];
-    const double vk = v[k];
-    int32_t q = k - 1;
-    while (q >= b && c[q] > ck) {
-      c[q + 1] = c[q];
-      v[q + 1] = v[q];
-      --q;
-    }
-    c[q + 1] = ck;
-    v[q + 1] = vk;
   }
 }
 void transpose(const Csr &P, Arena &ar, Csr &R, hipStream_t s) {
@@ -854,10 +1061,7 @@ void transpose(const Csr &P, Arena &ar, Csr &R, hipStream_t s) {
     k_scatter_tv<<<grid_for(P.n), kBlock, 0, s>>>(P.n, P.rp, P.col, P.val, cnt, R.col, R.val);
     SA_LAUNCH_CHECK();
   }
-  if (m > 0) {
-    k_sort_rows_iv<<<grid_for(m), kBlock, 0, s>>>(m, R.rp, R.col, R.val);
-    SA_LAUNCH_CHECK();
-  }
+  sort_rows(m, R.rp, R.col, R.val, s);
   dev_free(cnt, s);
 }
 

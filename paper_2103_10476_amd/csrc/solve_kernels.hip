@@ -15,20 +15,24 @@ struct Chunk {
   static constexpr int value = sizeof(T) == 8 ? 2048 : 4096;
 };
 
+constexpr int32_t kPlanWindow = 2048;  // cost units per SpMV block
+constexpr int32_t kPlanRowCost = 8;     // cost of a row besides its entries
+
 template <class T, class Epi>
-__global__ __launch_bounds__(kBlock) void k_spmv(int32_t n, const int32_t *__restrict__ rp,
+__global__ __launch_bounds__(kBlock) void k_spmv(const int32_t *__restrict__ bstart,
+                                                 const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ col,
                                                  const T *__restrict__ val,
                                                  const T *__restrict__ x, Epi epi) {
   constexpr int CH = Chunk<T>::value;
   __shared__ T prod[CH];
   const int t = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * kBlock;
-  const int64_t row = r0 + t;
-  const int64_t rl = min((int64_t)n, r0 + kBlock);
-  const int32_t e0 = rp[r0], e1 = rp[rl];
+  const int32_t r0 = bstart[blockIdx.x], r1 = bstart[blockIdx.x + 1];
+  if (r0 >= r1) return;  // block-uniform
+  const int32_t row = r0 + t;
+  const int32_t e0 = rp[r0], e1 = rp[r1];
   int32_t mb = 0, me = 0;
-  if (row < n) {
+  if (row < r1) {
     mb = rp[row];
     me = rp[row + 1];
   }
@@ -38,11 +42,46 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int32_t n, const int32_t *__res
 #pragma unroll 8
     for (int32_t e = c0 + t; e < c1; e += kBlock) prod[e - c0] = val[e] * x[col[e]];
     __syncthreads();
-    const int32_t b = max(mb, c0), en = min(me, c1);
-    for (int32_t e = b; e < en; ++e) s += prod[e - c0];
+    // in-order sum of the row's products in this chunk; loads are issued 8 at a time ahead
+    // of the (sequential) adds so long rows are bound by the add chain, not LDS latency
+    int32_t e = max(mb, c0);
+    const int32_t en = min(me, c1);
+    for (; e + 8 <= en; e += 8) {
+      T v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = prod[e - c0 + q];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += v[q];
+    }
+    for (; e < en; ++e) s += prod[e - c0];
     __syncthreads();
   }
-  if (row < n) epi((int32_t)row, s);
+  if (row < r1) epi(row, s);
+}
+
+__global__ void k_spmv_plan(int32_t n, const int32_t *rp, int32_t nblk, int32_t *bstart) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b > nblk) return;
+  if (b == nblk) {
+    bstart[b] = n;
+    return;
+  }
+  const int64_t target = b * kPlanWindow;
+  int32_t lo = 0, hi = n;  // first r in [0, n] with rp[r] + 8 r >= target
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if ((int64_t)rp[mid] + (int64_t)kPlanRowCost * mid >= target) hi = mid;
+    else lo = mid + 1;
+  }
+  bstart[b] = lo;
+}
+
+void spmv_plan(Csr &A, Arena &ar, hipStream_t s) {
+  const int64_t cost = A.nnz + (int64_t)kPlanRowCost * A.n;
+  A.nblk = (int32_t)ceil_div(cost + 1, kPlanWindow);
+  A.bstart = ar.alloc<int32_t>(A.nblk + 1);
+  k_spmv_plan<<<grid_for(A.nblk + 1), kBlock, 0, s>>>(A.n, A.rp, A.nblk, A.bstart);
+  SA_LAUNCH_CHECK();
 }
 
 template <class T>
@@ -112,7 +151,7 @@ struct EpJacobi {
 template <class T, class Epi>
 static void launch_spmv(const SpmvArgs<T> &a, const Epi &epi, hipStream_t s) {
   if (a.n <= 0) return;
-  k_spmv<T, Epi><<<grid_for(a.n), kBlock, 0, s>>>(a.n, a.rp, a.col, a.val, a.x, epi);
+  k_spmv<T, Epi><<<(unsigned)a.nblk, kBlock, 0, s>>>(a.bstart, a.rp, a.col, a.val, a.x, epi);
   SA_LAUNCH_CHECK();
 }
 

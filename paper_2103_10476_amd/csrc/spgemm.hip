@@ -14,13 +14,14 @@
 //                in global memory sized for the row.
 // Results go to per-row slots at the row's product offset (room for T >= distinct entries)
 // and are compacted into CSR afterwards.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace sa {
 
 constexpr int kWave = 64;
 constexpr int kChunk = 1024;  // products per block-level chunk
-constexpr int kHash = 4096;   // LDS hash capacity (entries)
 
 __global__ void k_count_products(int32_t m, const int32_t *xrp, const int32_t *xcol,
                                  const int32_t *yrp, int64_t *cnt, int32_t *xpref) {
@@ -36,14 +37,16 @@ __global__ void k_count_products(int32_t m, const int32_t *xrp, const int32_t *x
   cnt[i] = t;
 }
 
-__global__ void k_bin_rows(int32_t m, const int64_t *poff, int32_t *small, int32_t *big,
-                           int32_t *counters) {
-  const int64_t i64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i64 >= m) return;
-  const int32_t i = (int32_t)i64;
-  const int64_t T = poff[i + 1] - poff[i];
-  if (T <= kWave) small[atomicAdd(&counters[0], 1)] = i;
-  else big[atomicAdd(&counters[1], 1)] = i;
+// One atomic per wavefront and bin (ballot + popcount), not per row.
+__device__ inline void wave_push(bool pred, int32_t *counter, int32_t *list, int32_t value) {
+  const unsigned long long msk = __ballot(pred);
+  if (!msk) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)msk) - 1;
+  int32_t base = 0;
+  if (lane == leader) base = atomicAdd(counter, __popcll(msk));
+  base = __shfl(base, leader, 64);
+  if (pred) list[base + __popcll(msk & ((1ull << lane) - 1ull))] = value;
 }
 
 // ---- one wavefront per row (T <= 64) ------------------------------------------------------
@@ -119,7 +122,7 @@ __global__ __launch_bounds__(kWave) void k_esc_wave(
   if (lane == 0) ucnt[i] = __popcll(hm);
 }
 
-// ---- one block per row (T > 64) -----------------------------------------------------------
+// ---- block-level rows (T > 64) -------------------------------------------------------------
 __device__ inline int32_t find_entry(const int32_t *xpref, int32_t xb, int32_t xe, int32_t p) {
   // last e in [xb, xe) with xpref[e] <= p (entries with no products share a prefix value;
   // the last one holding p is the one whose Y row contains it).
@@ -184,102 +187,116 @@ __device__ inline uint32_t hash_slot(int32_t key, uint32_t mask) {
   return ((uint32_t)key * 2654435761u) & mask;
 }
 
-// GLOBAL = false: hash table in LDS (capacity kHash); rows that overflow half of it are
-// recorded in `ovf` and left for the GLOBAL = true pass, whose table lives in gk/gv at
-// goff[row slot] with capacity goff[s+1] - goff[s].
-template <bool GLOBAL>
-__global__ __launch_bounds__(kBlock) void k_esc_block(
+// Loads products c0 .. c0+L-1 of row i into sk (column << 32 | position) / sv and sorts sk;
+// after it, equal columns are adjacent in position (= Gustavson) order.
+__device__ inline void load_sorted_chunk(int32_t c0, int32_t L, int32_t xb, int32_t xe,
+                                         const int32_t *xpref, const int32_t *xcol,
+                                         const double *xval, const int32_t *yrp,
+                                         const int32_t *ycol, const double *yval, uint64_t *sk,
+                                         double *sv) {
+  const int32_t Lp = next_pow2(L);
+  for (int32_t q = threadIdx.x; q < Lp; q += blockDim.x) {
+    if (q < L) {
+      const int32_t p = c0 + q;
+      const int32_t e = find_entry(xpref, xb, xe, p);
+      const int32_t k = xcol[e];
+      const int32_t yy = yrp[k] + (p - xpref[e]);
+      sk[q] = ((uint64_t)(uint32_t)ycol[yy] << 32) | (uint32_t)q;
+      sv[q] = xval[e] * yval[yy];
+    } else {
+      sk[q] = ~0ull;
+    }
+  }
+  __syncthreads();
+  bitonic_u64(sk, Lp);
+}
+
+__device__ inline uint32_t key_of(uint64_t x) { return (uint32_t)(x >> 32); }
+
+// Single chunk: T <= 4*BS products, one block of BS threads per row; each run of equal columns
+// is summed in position order by its first lane and written at the run's rank.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_esc_single(
+    const int32_t *rows, int32_t nrows, const int32_t *xrp, const int32_t *xcol,
+    const double *xval, const int32_t *xpref, const int32_t *yrp, const int32_t *ycol,
+    const double *yval, const int64_t *poff, int32_t *ocol, double *oval, int32_t *ucnt) {
+  constexpr int CH = 4 * BS;
+  __shared__ uint64_t sk[CH];
+  __shared__ double sv[CH];
+  __shared__ int32_t s_scan[BS];
+  const int tid = threadIdx.x;
+  if ((int32_t)blockIdx.x >= nrows) return;
+  const int32_t i = rows[blockIdx.x];
+  const int64_t base = poff[i];
+  const int32_t L = (int32_t)(poff[i + 1] - base);
+  load_sorted_chunk(0, L, xrp[i], xrp[i + 1], xpref, xcol, xval, yrp, ycol, yval, sk, sv);
+  int32_t nh = 0;
+  for (int32_t r = tid * 4; r < tid * 4 + 4; ++r)
+    if (r < L && (r == 0 || key_of(sk[r]) != key_of(sk[r - 1]))) ++nh;
+  s_scan[tid] = nh;
+  __syncthreads();
+  for (int off = 1; off < BS; off <<= 1) {
+    const int32_t add = (tid >= off) ? s_scan[tid - off] : 0;
+    __syncthreads();
+    s_scan[tid] += add;
+    __syncthreads();
+  }
+  int32_t idx = s_scan[tid] - nh;
+  for (int32_t r = tid * 4; r < tid * 4 + 4; ++r) {
+    if (r < L && (r == 0 || key_of(sk[r]) != key_of(sk[r - 1]))) {
+      const uint32_t key = key_of(sk[r]);
+      double sum = 0.0;
+      for (int32_t q = r; q < L && key_of(sk[q]) == key; ++q) sum += sv[(uint32_t)sk[q]];
+      ocol[base + idx] = (int32_t)key;
+      oval[base + idx] = sum;
+      ++idx;
+    }
+  }
+  if (tid == BS - 1) ucnt[i] = s_scan[BS - 1];
+}
+
+// Long rows (T > kChunk): chunks of kChunk products; each distinct column of a chunk is
+// accumulated in position order by its first lane into an LDS hash table (one lane per key per
+// chunk, so per key the adds follow position order across chunks too); the table is sorted
+// by column at the end.  Rows whose distinct columns pass half the table are left to
+// k_esc_dense.
+constexpr int kHashL = 4096;
+__global__ __launch_bounds__(kBlock) void k_esc_hash(
     const int32_t *rows, int32_t nrows, const int32_t *xrp, const int32_t *xcol,
     const double *xval, const int32_t *xpref, const int32_t *yrp, const int32_t *ycol,
     const double *yval, const int64_t *poff, int32_t *ocol, double *oval, int32_t *ucnt,
-    int32_t *ovf, int32_t *novf, int32_t *gk, double *gv, const int64_t *goff) {
-  __shared__ uint64_t sk[kChunk];
-  __shared__ double sv[kChunk];
-  __shared__ int32_t lhk[GLOBAL ? 1 : kHash];
-  __shared__ double lhv[GLOBAL ? 1 : kHash];
-  __shared__ int32_t s_cnt, s_ovf;
+    int32_t *ovf, int32_t *novf) {
+  // sk/sv hold a chunk (kChunk) while accumulating and up to kHashL/2 distinct entries for
+  // the final sort (rows with more go to k_esc_dense)
+  static_assert(kHashL / 2 >= kChunk, "final sort area must hold a chunk");
+  __shared__ uint64_t sk[kHashL / 2];
+  __shared__ double sv[kHashL / 2];
+  __shared__ int32_t hk[kHashL];
+  __shared__ double hv[kHashL];
   __shared__ int32_t s_scan[kBlock];
+  __shared__ int32_t s_cnt, s_ovf;
   const int tid = threadIdx.x;
-  const int32_t slot = blockIdx.x;
-  if (slot >= nrows) return;  // block-uniform
-  const int32_t i = rows[slot];
+  if ((int32_t)blockIdx.x >= nrows) return;
+  const int32_t i = rows[blockIdx.x];
   const int32_t xb = xrp[i], xe = xrp[i + 1];
   const int64_t base = poff[i];
   const int32_t T = (int32_t)(poff[i + 1] - base);
-  const bool single = T <= kChunk;
-  int32_t *hk;
-  double *hv;
-  int32_t cap;
-  if (GLOBAL) {
-    hk = gk + goff[slot];
-    hv = gv + goff[slot];
-    cap = (int32_t)(goff[slot + 1] - goff[slot]);
-  } else {
-    hk = lhk;
-    hv = lhv;
-    cap = kHash;
-  }
   if (tid == 0) {
     s_cnt = 0;
     s_ovf = 0;
   }
-  if (!single)
-    for (int32_t q = tid; q < cap; q += kBlock) hk[q] = -1;
+  for (int32_t q = tid; q < kHashL; q += kBlock) hk[q] = -1;
   __syncthreads();
-
+  const uint32_t msk = kHashL - 1;
   for (int32_t c0 = 0; c0 < T; c0 += kChunk) {
     const int32_t L = min(kChunk, T - c0);
-    const int32_t Lp = next_pow2(L);
-    for (int32_t q = tid; q < Lp; q += kBlock) {
-      if (q < L) {
-        const int32_t p = c0 + q;
-        const int32_t e = find_entry(xpref, xb, xe, p);
-        const int32_t k = xcol[e];
-        const int32_t yy = yrp[k] + (p - xpref[e]);
-        sk[q] = ((uint64_t)(uint32_t)ycol[yy] << 32) | (uint32_t)q;
-        sv[q] = xval[e] * yval[yy];
-      } else {
-        sk[q] = ~0ull;
-      }
-    }
-    __syncthreads();
-    bitonic_u64(sk, Lp);
-    if (single) {
-      // heads of equal-column runs; each head sums its run in position order
-      int32_t nh = 0;
-      for (int32_t r = tid * 4; r < tid * 4 + 4; ++r)
-        if (r < L && (r == 0 || (sk[r] >> 32) != (sk[r - 1] >> 32))) ++nh;
-      s_scan[tid] = nh;
-      __syncthreads();
-      for (int off = 1; off < kBlock; off <<= 1) {
-        const int32_t add = (tid >= off) ? s_scan[tid - off] : 0;
-        __syncthreads();
-        s_scan[tid] += add;
-        __syncthreads();
-      }
-      int32_t idx = s_scan[tid] - nh;
-      for (int32_t r = tid * 4; r < tid * 4 + 4; ++r) {
-        if (r < L && (r == 0 || (sk[r] >> 32) != (sk[r - 1] >> 32))) {
-          const uint32_t key = (uint32_t)(sk[r] >> 32);
-          double sum = 0.0;
-          for (int32_t q = r; q < L && (uint32_t)(sk[q] >> 32) == key; ++q)
-            sum += sv[(uint32_t)sk[q]];
-          ocol[base + idx] = (int32_t)key;
-          oval[base + idx] = sum;
-          ++idx;
-        }
-      }
-      if (tid == kBlock - 1) ucnt[i] = s_scan[kBlock - 1];
-      return;  // single chunk: done (block-uniform)
-    }
-    // chunked: each distinct column of the chunk is accumulated by its head into the table
+    load_sorted_chunk(c0, L, xb, xe, xpref, xcol, xval, yrp, ycol, yval, sk, sv);
     for (int32_t r = tid; r < L; r += kBlock) {
-      const uint32_t key = (uint32_t)(sk[r] >> 32);
-      if (r > 0 && (uint32_t)(sk[r - 1] >> 32) == key) continue;
-      const uint32_t msk = (uint32_t)cap - 1;
+      const uint32_t key = key_of(sk[r]);
+      if (r > 0 && key_of(sk[r - 1]) == key) continue;
       uint32_t h = hash_slot((int32_t)key, msk);
       bool fresh = false;
-      for (int32_t probe = 0; probe < cap; ++probe) {
+      for (int32_t probe = 0; probe < kHashL; ++probe) {
         const int32_t old = atomicCAS(&hk[h], -1, (int32_t)key);
         if (old == -1) {
           fresh = true;
@@ -289,12 +306,11 @@ __global__ __launch_bounds__(kBlock) void k_esc_block(
         h = (h + 1) & msk;
       }
       double acc = fresh ? 0.0 : hv[h];
-      for (int32_t q = r; q < L && (uint32_t)(sk[q] >> 32) == key; ++q)
-        acc += sv[(uint32_t)sk[q]];
+      for (int32_t q = r; q < L && key_of(sk[q]) == key; ++q) acc += sv[(uint32_t)sk[q]];
       hv[h] = acc;
       if (fresh) {
         const int32_t c = atomicAdd(&s_cnt, 1);
-        if (2 * (c + 1) > cap) s_ovf = 1;
+        if (2 * (c + 1) > kHashL) s_ovf = 1;
       }
     }
     __syncthreads();
@@ -304,39 +320,126 @@ __global__ __launch_bounds__(kBlock) void k_esc_block(
     if (tid == 0) ovf[atomicAdd(novf, 1)] = i;
     return;
   }
-  bitonic_kv(hk, hv, cap);
+  // compact the occupied slots (slot order) into sk/sv, then sort only those U entries
   const int32_t U = s_cnt;
+  constexpr int per = kHashL / kBlock;
+  int32_t nloc = 0;
+  for (int q = 0; q < per; ++q) nloc += hk[tid * per + q] >= 0;
+  s_scan[tid] = nloc;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const int32_t add = (tid >= off) ? s_scan[tid - off] : 0;
+    __syncthreads();
+    s_scan[tid] += add;
+    __syncthreads();
+  }
+  int32_t w = s_scan[tid] - nloc;
+  for (int q = 0; q < per; ++q) {
+    const int32_t slot = tid * per + q;
+    if (hk[slot] >= 0) {
+      sk[w] = ((uint64_t)(uint32_t)hk[slot] << 32) | (uint32_t)w;
+      sv[w] = hv[slot];
+      ++w;
+    }
+  }
+  __syncthreads();
+  const int32_t Up = next_pow2(U);
+  for (int32_t q = U + tid; q < Up; q += kBlock) sk[q] = ~0ull;
+  __syncthreads();
+  bitonic_u64(sk, Up);
   for (int32_t r = tid; r < U; r += kBlock) {
-    ocol[base + r] = hk[r];
-    oval[base + r] = hv[r];
+    ocol[base + r] = (int32_t)key_of(sk[r]);
+    oval[base + r] = sv[(uint32_t)sk[r]];
   }
   if (tid == 0) ucnt[i] = U;
 }
 
-__global__ void k_ovf_caps(int32_t nov, const int32_t *rows, const int64_t *poff, int32_t ncols,
-                           int64_t *caps) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nov) return;
-  const int32_t i = rows[s];
-  int64_t b = poff[i + 1] - poff[i];
-  if (b > ncols) b = ncols;
-  int64_t c = 2 * kHash;
-  while (c < 2 * b) c <<= 1;
-  caps[s] = c;
+// Rows with more distinct columns than the LDS table holds: a dense accumulator of ncols
+// entries per block in global memory (first touch starts from 0, adds in position order as
+// above); the result is extracted in column order by a block-wide scan of the touched flags.
+__global__ __launch_bounds__(kBlock) void k_esc_dense(
+    const int32_t *rows, int32_t nrows, const int32_t *xrp, const int32_t *xcol,
+    const double *xval, const int32_t *xpref, const int32_t *yrp, const int32_t *ycol,
+    const double *yval, int32_t ncols, const int64_t *poff, int32_t *ocol, double *oval,
+    int32_t *ucnt, double *dacc, int32_t *dflag) {
+  __shared__ uint64_t sk[kChunk];
+  __shared__ double sv[kChunk];
+  __shared__ int32_t s_scan[kBlock];
+  __shared__ int32_t s_base;
+  const int tid = threadIdx.x;
+  double *acc = dacc + (int64_t)blockIdx.x * ncols;
+  int32_t *flag = dflag + (int64_t)blockIdx.x * ncols;
+  for (int32_t slot = blockIdx.x; slot < nrows; slot += gridDim.x) {
+    const int32_t i = rows[slot];
+    const int32_t xb = xrp[i], xe = xrp[i + 1];
+    const int64_t base = poff[i];
+    const int32_t T = (int32_t)(poff[i + 1] - base);
+    for (int32_t q = tid; q < ncols; q += kBlock) flag[q] = 0;
+    __syncthreads();
+    for (int32_t c0 = 0; c0 < T; c0 += kChunk) {
+      const int32_t L = min(kChunk, T - c0);
+      load_sorted_chunk(c0, L, xb, xe, xpref, xcol, xval, yrp, ycol, yval, sk, sv);
+      for (int32_t r = tid; r < L; r += kBlock) {
+        const uint32_t key = key_of(sk[r]);
+        if (r > 0 && key_of(sk[r - 1]) == key) continue;
+        double a = flag[key] ? acc[key] : 0.0;
+        for (int32_t q = r; q < L && key_of(sk[q]) == key; ++q) a += sv[(uint32_t)sk[q]];
+        acc[key] = a;
+        flag[key] = 1;
+      }
+      __syncthreads();
+    }
+    if (tid == 0) s_base = 0;
+    __syncthreads();
+    for (int32_t c0 = 0; c0 < ncols; c0 += kBlock) {
+      const int32_t c = c0 + tid;
+      const int32_t f = (c < ncols) ? flag[c] : 0;
+      s_scan[tid] = f;
+      __syncthreads();
+      for (int off = 1; off < kBlock; off <<= 1) {
+        const int32_t add = (tid >= off) ? s_scan[tid - off] : 0;
+        __syncthreads();
+        s_scan[tid] += add;
+        __syncthreads();
+      }
+      if (f) {
+        const int32_t pos = s_base + s_scan[tid] - 1;
+        ocol[base + pos] = c;
+        oval[base + pos] = acc[c];
+      }
+      __syncthreads();
+      if (tid == kBlock - 1) s_base += s_scan[kBlock - 1];
+      __syncthreads();
+    }
+    if (tid == 0) ucnt[i] = s_base;
+    __syncthreads();
+  }
 }
 
-__global__ void k_compact(int32_t m, const int64_t *poff, const int32_t *ucnt,
-                          const int32_t *crp, const int32_t *ocol, const double *oval,
-                          int32_t *ccol, double *cval) {
-  const int64_t i64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i64 >= m) return;
-  const int32_t i = (int32_t)i64;
-  const int64_t src = poff[i];
-  const int32_t dst = crp[i];
-  for (int32_t q = 0; q < ucnt[i]; ++q) {
-    ccol[dst + q] = ocol[src + q];
-    cval[dst + q] = oval[src + q];
+// One thread per output entry: find the entry's row by binary search over C's row pointers
+// and copy from the row's slot area (coalesced writes).
+__global__ void k_compact(int32_t m, int64_t nnz, const int64_t *poff, const int32_t *crp,
+                          const int32_t *ocol, const double *oval, int32_t *ccol, double *cval) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  int32_t lo = 0, hi = m - 1;  // last row with crp[row] <= e
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if ((int64_t)crp[mid] <= e) lo = mid;
+    else hi = mid - 1;
   }
+  const int64_t src = poff[lo] + (e - crp[lo]);
+  ccol[e] = ocol[src];
+  cval[e] = oval[src];
+}
+
+__global__ void k_bin_rows4(int32_t m, const int64_t *poff, int32_t *lists, int32_t *counters) {
+  const int64_t i64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i64 < m;
+  const int32_t i = live ? (int32_t)i64 : 0;
+  const int64_t T = live ? poff[i + 1] - poff[i] : 0;
+  const int bin = T <= kWave ? 0 : T <= 256 ? 1 : T <= kChunk ? 2 : 3;
+  for (int b = 0; b < 4; ++b) wave_push(live && bin == b, &counters[b], lists + (int64_t)b * m, i);
 }
 
 void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
@@ -357,43 +460,51 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
   int32_t *ocol = tmp.alloc<int32_t>(total > 0 ? total : 1);
   double *oval = tmp.alloc<double>(total > 0 ? total : 1);
   int32_t *ucnt = tmp.alloc<int32_t>(m + 1);
-  int32_t *small = tmp.alloc<int32_t>(m > 0 ? m : 1);
-  int32_t *big = tmp.alloc<int32_t>(m > 0 ? m : 1);
-  int32_t *counters = tmp.alloc<int32_t>(4);
-  fill_i32(counters, 0, 4, s);
+  int32_t *lists = tmp.alloc<int32_t>(4 * (int64_t)(m > 0 ? m : 1));
+  int32_t *counters = tmp.alloc<int32_t>(8);
+  fill_i32(counters, 0, 8, s);
   if (m > 0) {
-    k_bin_rows<<<grid_for(m), kBlock, 0, s>>>(m, poff, small, big, counters);
+    k_bin_rows4<<<grid_for(m), kBlock, 0, s>>>(m, poff, lists, counters);
     SA_LAUNCH_CHECK();
   }
-  int32_t hc[4];
+  int32_t hc[8];
   SA_HIP(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, s));
   SA_HIP(hipStreamSynchronize(s));
-  const int32_t nsmall = hc[0], nbig = hc[1];
-  if (nsmall > 0) {
-    k_esc_wave<<<(unsigned)nsmall, kWave, 0, s>>>(small, nsmall, X.rp, X.col, X.val, Y.rp,
-                                                   Y.col, Y.val, poff, ocol, oval, ucnt);
+  const int32_t *l0 = lists, *l1 = lists + m, *l2 = lists + 2 * (int64_t)m,
+                *l3 = lists + 3 * (int64_t)m;
+  if (hc[0] > 0) {
+    k_esc_wave<<<(unsigned)hc[0], kWave, 0, s>>>(l0, hc[0], X.rp, X.col, X.val, Y.rp, Y.col,
+                                                  Y.val, poff, ocol, oval, ucnt);
     SA_LAUNCH_CHECK();
   }
-  if (nbig > 0) {
-    int32_t *ovf = tmp.alloc<int32_t>(nbig);
-    int32_t *novf = counters + 2;
-    k_esc_block<false><<<(unsigned)nbig, kBlock, 0, s>>>(
-        big, nbig, X.rp, X.col, X.val, xpref, Y.rp, Y.col, Y.val, poff, ocol, oval, ucnt, ovf,
-        novf, nullptr, nullptr, nullptr);
+  if (hc[1] > 0) {
+    k_esc_single<64><<<(unsigned)hc[1], 64, 0, s>>>(l1, hc[1], X.rp, X.col, X.val, xpref, Y.rp,
+                                                    Y.col, Y.val, poff, ocol, oval, ucnt);
     SA_LAUNCH_CHECK();
-    const int32_t nov = read1(novf, s);
+  }
+  if (hc[2] > 0) {
+    k_esc_single<256><<<(unsigned)hc[2], 256, 0, s>>>(l2, hc[2], X.rp, X.col, X.val, xpref,
+                                                      Y.rp, Y.col, Y.val, poff, ocol, oval,
+                                                      ucnt);
+    SA_LAUNCH_CHECK();
+  }
+  if (hc[3] > 0) {
+    int32_t *ovf = tmp.alloc<int32_t>(hc[3]);
+    k_esc_hash<<<(unsigned)hc[3], kBlock, 0, s>>>(l3, hc[3], X.rp, X.col, X.val, xpref, Y.rp,
+                                                  Y.col, Y.val, poff, ocol, oval, ucnt, ovf,
+                                                  counters + 4);
+    SA_LAUNCH_CHECK();
+    const int32_t nov = read1(counters + 4, s);
     if (nov > 0) {
-      int64_t *caps = tmp.alloc<int64_t>(nov + 1);
-      int64_t *goff = tmp.alloc<int64_t>(nov + 1);
-      k_ovf_caps<<<grid_for(nov), kBlock, 0, s>>>(nov, ovf, poff, Y.ncols, caps);
-      SA_LAUNCH_CHECK();
-      exclusive_scan_i64(caps, goff, nov, s);
-      const int64_t gtot = read1(goff + nov, s);
-      int32_t *gk = tmp.alloc<int32_t>(gtot);
-      double *gv = tmp.alloc<double>(gtot);
-      k_esc_block<true><<<(unsigned)nov, kBlock, 0, s>>>(
-          ovf, nov, X.rp, X.col, X.val, xpref, Y.rp, Y.col, Y.val, poff, ocol, oval, ucnt,
-          ovf, counters + 3, gk, gv, goff);
+      // dense accumulators: at most ~2 GiB of them at once
+      const int64_t per = (int64_t)Y.ncols * 12;
+      int64_t nb = std::min<int64_t>(nov, std::max<int64_t>(1, (int64_t(2) << 30) / per));
+      nb = std::min<int64_t>(nb, 1024);
+      double *dacc = tmp.alloc<double>(nb * (int64_t)Y.ncols);
+      int32_t *dflag = tmp.alloc<int32_t>(nb * (int64_t)Y.ncols);
+      k_esc_dense<<<(unsigned)nb, kBlock, 0, s>>>(ovf, nov, X.rp, X.col, X.val, xpref, Y.rp,
+                                                  Y.col, Y.val, Y.ncols, poff, ocol, oval, ucnt,
+                                                  dacc, dflag);
       SA_LAUNCH_CHECK();
     }
   }
@@ -402,8 +513,9 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
   C.nnz = read1(C.rp + m, s);
   C.col = ar.alloc<int32_t>(C.nnz);
   C.val = ar.alloc<double>(C.nnz);
-  if (m > 0) {
-    k_compact<<<grid_for(m), kBlock, 0, s>>>(m, poff, ucnt, C.rp, ocol, oval, C.col, C.val);
+  if (C.nnz > 0) {
+    k_compact<<<grid_for(C.nnz), kBlock, 0, s>>>(m, C.nnz, poff, C.rp, ocol, oval, C.col,
+                                                 C.val);
     SA_LAUNCH_CHECK();
   }
 }
