@@ -79,7 +79,10 @@ def main():
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the FP32/variant/roofline legs (profiling runs)")
+                    help="skip the FP32 and variant legs (profiling runs)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="first run a plain device copy of BYTES (3 times): the reference "
+                         "kernel that calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1 "
@@ -90,6 +93,13 @@ def main():
     from paper_2103_10476_amd import problems, solver
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {args.copy_probe} bytes read and written per copy")
     p = problems.workload(args.workload)
     b = problems.random_rhs(p.n, problems.RHS_SEED.get(args.workload, 2))
     drp = torch.from_numpy(p.rp).cuda()
@@ -100,12 +110,21 @@ def main():
     torch.cuda.synchronize()
     opts = solver.Options(theta=0.02, rtol=1e-8)
 
-    def step(o=opts):
+    prof_totals = {"launches": 0, "ms": 0.0, "bytes": 0.0}
+
+    def step(o=opts, profile=False):
         h = solver.Hierarchy(p.n, drp, dcol, dval, options=o)
+        if profile:
+            h.profile(True)
         ts = time.perf_counter()
         _, it, rr, st = h.solve(db, x)
         torch.cuda.synchronize()
-        return h, it, rr, st, time.perf_counter() - ts
+        te = time.perf_counter() - ts
+        if profile:
+            pr = h.profile_read()
+            for k in prof_totals:
+                prof_totals[k] += pr[k]
+        return h, it, rr, st, te
 
     log(f"[bench] {p.name} n={p.n} nnz={p.nnz}: warmup {args.warmup}")
     for _ in range(args.warmup):
@@ -117,7 +136,7 @@ def main():
     for k in range(args.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        h, it, rr, st, tsolve = step()
+        h, it, rr, st, tsolve = step(profile=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         times.append(dt)
@@ -158,7 +177,115 @@ def main():
     }
     sb = solve_bytes_model(info) * (it + 1)
     result["solve_hbm_gbs"] = round(sb / pct(solves, 50) / 1e9, 1)
+    result["roofline"] = roofline(prof_totals)
+    if not args.no_extras:
+        result["fp32_vcycle_vs_fp64"] = precision_leg(solver, p, drp, dcol, dval, db)
+        result["variants"] = variants_leg(solver, p, drp, dcol, dval, db)
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(p, b)
     print(json.dumps(result), flush=True)
+
+
+def roofline(tot):
+    """Fine-level CSR SpMV (the kernel with the largest share of the step): algorithmic bytes
+    per launch (12 B per entry + row pointers + the vectors its fused epilogue reads/writes)
+    over the launch duration from HIP events recorded around every such launch of the timed
+    steps, on the library's stream."""
+    if not tot["launches"]:
+        return None
+    avg_ms = tot["ms"] / tot["launches"]
+    bytes_per = tot["bytes"] / tot["launches"]
+    achieved = bytes_per / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": "k_spmv (fine-level operator, all fused epilogues)",
+            "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "launches": tot["launches"], "avg_us": round(avg_ms * 1e3, 2),
+            "algorithmic_bytes_per_launch": round(bytes_per)}
+
+
+def precision_leg(solver, p, drp, dcol, dval, db):
+    """FP32-stored/applied V-cycle inside FP64 PCG vs the all-FP64 solve, same GPU, same
+    input, relative residual 1e-10 for both."""
+    import torch
+    out = {}
+    xs = {}
+    for prec in ("fp64", "fp32"):
+        o = solver.Options(theta=0.02, rtol=1e-10, precision=prec)
+        t0 = time.perf_counter()
+        h = solver.Hierarchy(p.n, drp, dcol, dval, options=o)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x, it, rr, st = h.solve(db)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        # repeat the solve for a steadier time
+        ts = []
+        for _ in range(3):
+            ta = time.perf_counter()
+            h.solve(db)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - ta)
+        xs[prec] = x.clone()
+        # true residual ||b - A x|| / ||b|| (host check, scipy)
+        import scipy.sparse as sp
+        A = sp.csr_matrix((p.val, p.col, p.rp), shape=(p.n, p.n))
+        xh = x.cpu().numpy()
+        bh = db.cpu().numpy()
+        res = np.linalg.norm(bh - A @ xh) / np.linalg.norm(bh)
+        out[prec] = {"setup_s": round(t1 - t0, 5), "solve_s": round(min(ts), 5),
+                     "setup_plus_solve_s": round(t1 - t0 + min(ts), 5), "iterations": it,
+                     "status": st, "true_rel_residual": float(res)}
+        h.close()
+    out["rel_err_fp32_vs_fp64"] = float(torch.linalg.norm(xs["fp32"] - xs["fp64"]) /
+                                        torch.linalg.norm(xs["fp64"]))
+    out["solve_speedup_fp32"] = round(out["fp64"]["solve_s"] / out["fp32"]["solve_s"], 3)
+    return out
+
+
+def variants_leg(solver, p, drp, dcol, dval, db):
+    """One setup per variant (plain, Sprsfy, OffLmp, 1Norm, Cnstrnt) with the solve to 1e-8."""
+    import torch
+    out = {}
+    for name, var in (("plain", []), ("sprsfy", ["sprsfy"]), ("offlmp", ["offlmp"]),
+                      ("1norm", ["1norm"]), ("cnstrnt", ["cnstrnt"])):
+        o = solver.Options(theta=0.02, rtol=1e-8, variants=var)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            h = solver.Hierarchy(p.n, drp, dcol, dval, options=o)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, it, rr, st = h.solve(db)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            inf = h.info()
+            out[name] = {"setup_s": round(t1 - t0, 5), "solve_s": round(t2 - t1, 5),
+                         "iterations": it, "status": st, "levels": inf["levels"],
+                         "operator_complexity": round(inf["operator_complexity"], 4)}
+            h.close()
+        except Exception as e:  # a variant may fail on a problem (reported, not fatal)
+            out[name] = {"status": str(e)[:120]}
+    return out
+
+
+def cpu_baseline(p, b):
+    """The CPU oracle (plain single-threaded C++) on the same workload: one full setup and
+    solve (about 10-15 s on one core), in seconds per setup+solve."""
+    from oracle import oracle as orc
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        cores = os.cpu_count()
+    t0 = time.perf_counter()
+    h = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, theta=0.02, rtol=1e-8)
+    t1 = time.perf_counter()
+    r = h.solve(b)
+    t2 = time.perf_counter()
+    return {"value": round(t2 - t0, 3), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"one full setup + PCG solve of the same workload on one thread "
+                      f"({cores} host cores available); setup {t1 - t0:.2f} s, solve "
+                      f"{t2 - t1:.2f} s, {r['iterations']} iterations",
+            "higher_is_better": False}
 
 
 if __name__ == "__main__":

@@ -158,6 +158,14 @@ sa_status sa_export_size(const sa_hierarchy *h, int32_t level, sa_part what, int
 sa_status sa_export_level(const sa_hierarchy *h, int32_t level, sa_part what, void *host_buf,
                           size_t bytes);
 
+/* Kernel timing for roofline reports: while enabled, every launch of the SpMV kernel on the
+ * fine-level operator during sa_solve is bracketed with HIP events on the hierarchy's
+ * stream.  sa_profile_read returns the number of such launches, their summed device time
+ * (ms) and their summed algorithmic HBM bytes (entries x 12 B + row pointers + every vector
+ * the fused epilogue reads or writes, each once), accumulated since enabling. */
+sa_status sa_profile_enable(sa_hierarchy *h, int32_t on);
+sa_status sa_profile_read(const sa_hierarchy *h, int64_t *launches, double *ms, double *bytes);
+
 /* Releases the hierarchy and all its device memory (NULL is ignored). */
 void sa_destroy(sa_hierarchy *h);
 

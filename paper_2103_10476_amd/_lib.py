@@ -31,7 +31,7 @@ PART_DTYPE = {"A_rp": "int32", "A_col": "int32", "A_val": "float64", "mask": "ui
 
 EXPORTED = ["sa_default_options", "sa_setup", "sa_solve", "sa_vcycle", "sa_hierarchy_info",
             "sa_export_size", "sa_export_level", "sa_destroy", "sa_status_string",
-            "sa_last_error"]
+            "sa_last_error", "sa_profile_enable", "sa_profile_read"]
 
 
 class SaOptions(C.Structure):
@@ -92,6 +92,11 @@ def lib():
         L.sa_export_size.restype = C.c_int
         L.sa_export_level.argtypes = [P, C.c_int32, C.c_int32, P, C.c_size_t]
         L.sa_export_level.restype = C.c_int
+        L.sa_profile_enable.argtypes = [P, C.c_int32]
+        L.sa_profile_enable.restype = C.c_int
+        L.sa_profile_read.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double)]
+        L.sa_profile_read.restype = C.c_int
         L.sa_destroy.argtypes = [P]
         L.sa_destroy.restype = None
         L.sa_status_string.argtypes = [C.c_int]

@@ -72,8 +72,16 @@ struct sa_hierarchy {
   sa::PcgScalars *S = nullptr;
   sa::PcgScalars *hS = nullptr;  // pinned host mirror
   int32_t n = 0;
+  // fine-level SpMV timing (sa_profile_enable)
+  bool prof = false;
+  std::vector<hipEvent_t> ev;   // event pool, pairs (start, stop)
+  std::vector<double> ev_bytes; // algorithmic bytes of each recorded pair
+  int32_t nev = 0;
+  int64_t prof_launches = 0;
+  double prof_ms = 0.0, prof_bytes = 0.0;
   ~sa_hierarchy() {
     if (hS) (void)hipHostFree(hS);
+    for (auto e : ev) (void)hipEventDestroy(e);
   }
 };
 
@@ -156,11 +164,15 @@ static bool build_level(sa_hierarchy *h, int l) {
   tmp.stream = s;
   double *dval = tmp.alloc<double>(n);
   find_diag(n, L.As.rp, L.As.col, L.As.val, dval, s);
+  // rows long enough to leave thread-per-row kernels serial: one wavefront per row instead
+  const bool wave_rows = max_row_length(n, L.As.rp, s) > 64 || L.As.nnz > 24 * (int64_t)n;
   L.mask = ar.alloc<uint8_t>(L.As.nnz);
   int32_t *scount = tmp.alloc<int32_t>(n + 1);
-  strength(n, L.As.rp, L.As.col, L.As.val, dval, o.theta * o.theta, L.mask, scount, s);
+  strength(n, L.As.rp, L.As.col, L.As.val, dval, o.theta * o.theta, L.mask, scount, wave_rows,
+           s);
   int32_t *grp = nullptr, *gcol = nullptr;
-  const int64_t nnzG = strength_graph(n, L.As.rp, L.As.col, L.mask, scount, tmp, &grp, &gcol, s);
+  const int64_t nnzG = strength_graph(n, L.As.rp, L.As.col, L.mask, scount, wave_rows, tmp,
+                                      &grp, &gcol, s);
   L.agg = ar.alloc<int32_t>(n);
   L.is_root = ar.alloc<uint8_t>(n);
   int32_t *root_vertex = nullptr;
@@ -172,7 +184,7 @@ static bool build_level(sa_hierarchy *h, int l) {
   const bool one_norm = (o.variants & SA_1NORM) != 0;
   L.invD = ar.alloc<double>(n);
   lump(n, L.As.rp, L.As.col, L.As.val, L.mask, (o.variants & SA_OFFLMP) != 0, o.tau, one_norm,
-       safeguard_mult(o.sigma), ar, L.Abar, L.invD, h->err, s);
+       safeguard_mult(o.sigma), wave_rows, ar, L.Abar, L.invD, h->err, s);
   check_err(h, E_ZERO_FDIAG, SA_ERR_NONPOSITIVE_DIAG, "zero diagonal in the filtered matrix");
   spmv_plan(L.Abar, ar, s);
   L.lam_d = ar.alloc<double>(2);
@@ -342,6 +354,41 @@ static void setup_impl(sa_hierarchy *h, const sa_csr *A, const double *B) {
   h->setup_seconds = now_s() - t0;
 }
 
+// ---- fine-level SpMV timing ------------------------------------------------------------------
+static void prof_begin(sa_hierarchy *h, int l) {
+  if (!h->prof || l != 0) return;
+  if (h->nev + 2 > (int32_t)h->ev.size()) {
+    for (int k = 0; k < 64; ++k) {
+      hipEvent_t e;
+      SA_HIP(hipEventCreate(&e));
+      h->ev.push_back(e);
+    }
+    h->ev_bytes.resize(h->ev.size() / 2);
+  }
+  SA_HIP(hipEventRecord(h->ev[h->nev], h->stream));
+}
+// `vec` = number of n-vectors the launch's epilogue and input read or write (x included).
+static void prof_end(sa_hierarchy *h, int l, int vec, int elem) {
+  if (!h->prof || l != 0) return;
+  SA_HIP(hipEventRecord(h->ev[h->nev + 1], h->stream));
+  const Csr &A = h->lv[0].A;
+  h->ev_bytes[h->nev / 2] = (double)A.nnz * (4 + elem) + 4.0 * (A.n + 1) +
+                            (double)vec * elem * A.n;
+  h->nev += 2;
+}
+// After a synchronisation: fold the recorded pairs into the totals.
+static void prof_collect(sa_hierarchy *h) {
+  if (!h->prof) return;
+  for (int32_t k = 0; k < h->nev; k += 2) {
+    float ms = 0.f;
+    SA_HIP(hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]));
+    h->prof_ms += ms;
+    h->prof_bytes += h->ev_bytes[k / 2];
+    ++h->prof_launches;
+  }
+  h->nev = 0;
+}
+
 // ---- V-cycle ---------------------------------------------------------------------------------
 template <class T>
 struct LevelView {
@@ -378,7 +425,9 @@ static LevelView<float> view32(Level &L) {
 }
 
 template <class T>
-static void smooth(sa_hierarchy *h, Level &L, LevelView<T> &v, const T *f, T *u, bool uzero) {
+static void smooth(sa_hierarchy *h, int l, Level &L, LevelView<T> &v, const T *f, T *u,
+                   bool uzero) {
+  const int es = (int)sizeof(T);
   const hipStream_t s = h->stream;
   const sa_options &o = h->opt;
   const int32_t n = L.A.n;
@@ -392,7 +441,9 @@ static void smooth(sa_hierarchy *h, Level &L, LevelView<T> &v, const T *f, T *u,
     }
     for (; sweep < o.degree; ++sweep) {
       A.x = u;
+      prof_begin(h, l);
       spmv_jacobi<T>(A, f, v.invD, w, v.d1, s);
+      prof_end(h, l, 4, es);
       SA_HIP(hipMemcpyAsync(u, v.d1, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
     }
     return;
@@ -405,15 +456,20 @@ static void smooth(sa_hierarchy *h, Level &L, LevelView<T> &v, const T *f, T *u,
     rin = f;
   } else {
     A.x = u;
+    prof_begin(h, l);
     spmv_cheb_start<T>(A, f, v.invD, theta, v.r, dc, s);
+    prof_end(h, l, 5, es);
     if (o.degree == 1) vec_add<T>(n, u, dc, s);
     rin = v.r;
   }
   for (int m = 1; m < o.degree; ++m) {
     A.x = dc;
     const bool last = (m == o.degree - 1);
+    prof_begin(h, l);
     spmv_cheb_step<T>(A, rin, v.r, v.invD, (T)L.cheb_c1[m - 1], (T)L.cheb_c2[m - 1], u,
                       uzero && m == 1, dn, last, s);
+    // x = d, rin, invD, rout, u (read unless from zero), u written, dout unless last
+    prof_end(h, l, 5 + ((uzero && m == 1) ? 0 : 1) + (last ? 0 : 1), es);
     rin = v.r;
     std::swap(dc, dn);
   }
@@ -449,10 +505,12 @@ static void vcycle(sa_hierarchy *h, int l, const T *f, T *u) {
   if constexpr (sizeof(T) == 8) vc = view64(h->lv[l + 1]);
   else vc = view32(h->lv[l + 1]);
   const hipStream_t s = h->stream;
-  smooth<T>(h, L, v, f, u, true);
+  smooth<T>(h, l, L, v, f, u, true);
   SpmvArgs<T> A = v.A;
   A.x = u;
+  prof_begin(h, l);
   spmv_resid<T>(A, f, v.r, s);
+  prof_end(h, l, 3, (int)sizeof(T));
   SpmvArgs<T> R = v.R;
   R.x = v.r;
   spmv_store<T>(R, vc.f, s);
@@ -460,7 +518,7 @@ static void vcycle(sa_hierarchy *h, int l, const T *f, T *u) {
   SpmvArgs<T> P = v.P;
   P.x = vc.u;
   spmv_add<T>(P, u, s);
-  smooth<T>(h, L, v, f, u, false);
+  smooth<T>(h, l, L, v, f, u, false);
 }
 
 // z = M^{-1} r at the fine level, in the hierarchy's precision.
@@ -512,13 +570,16 @@ static sa_status solve_impl(sa_hierarchy *h, const double *b, double *x, sa_loca
   pcg_init_rho(S, s);
   SpmvArgs<double> A = spmv_args<double>(h->lv[0].A, h->lv[0].A.val, h->p);
   for (int32_t k = 1; k <= o.max_iter; ++k) {
+    prof_begin(h, 0);
     spmv_store<double>(A, h->q, s);
+    prof_end(h, 0, 2, 8);
     dot_f64(h->p, h->q, n, &S->pq, h->dws, s);
     pcg_alpha(S, s);
     pcg_update_xr(n, h->x, h->r, h->p, h->q, S, s);
     dot_f64(h->r, h->r, n, &S->rr, h->dws, s);
     SA_HIP(hipMemcpyAsync(h->hS, S, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
     SA_HIP(hipStreamSynchronize(s));
+    prof_collect(h);
     if (h->hS->err) return SA_ERR_BREAKDOWN;
     rr = h->hS->rr;
     its = k;
@@ -543,6 +604,7 @@ static sa_status solve_impl(sa_hierarchy *h, const double *b, double *x, sa_loca
     its = o.max_iter;
   }
   finish();
+  prof_collect(h);
   if (iterations) *iterations = its;
   if (relres) *relres = std::sqrt(rr / g0);
   return st;
@@ -720,6 +782,27 @@ sa_status sa_export_level(const sa_hierarchy *h, int32_t level, sa_part what, vo
     }
     return SA_OK;
   });
+}
+
+sa_status sa_profile_enable(sa_hierarchy *h, int32_t on) {
+  if (!h) return SA_ERR_INVALID_ARG;
+  return guarded([&]() -> sa_status {
+    SA_HIP(hipStreamSynchronize(h->stream));
+    prof_collect(h);
+    h->prof = on != 0;
+    h->prof_launches = 0;
+    h->prof_ms = 0.0;
+    h->prof_bytes = 0.0;
+    return SA_OK;
+  });
+}
+
+sa_status sa_profile_read(const sa_hierarchy *h, int64_t *launches, double *ms, double *bytes) {
+  if (!h) return SA_ERR_INVALID_ARG;
+  if (launches) *launches = h->prof_launches;
+  if (ms) *ms = h->prof_ms;
+  if (bytes) *bytes = h->prof_bytes;
+  return SA_OK;
 }
 
 void sa_destroy(sa_hierarchy *h) {

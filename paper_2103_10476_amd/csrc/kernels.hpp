@@ -90,12 +90,15 @@ void validate_csr(int32_t n, const int32_t *rp, const int32_t *col, const double
 void find_diag(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
                double *dval, hipStream_t s);
 // mask per entry (0 weak, 1 strong, 3 diagonal) and scount[i] = strong entries in row i.
+// `wave`: one wavefront per row (levels whose rows are long); same results.
 void strength(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
-              const double *dval, double th2, uint8_t *mask, int32_t *scount, hipStream_t s);
+              const double *dval, double th2, uint8_t *mask, int32_t *scount, bool wave,
+              hipStream_t s);
+int32_t max_row_length(int32_t n, const int32_t *rp, hipStream_t s);
 // Symmetrised strength graph G = S u S^T as CSR (grp[n+1], gcol[nnzG]); returns nnzG.
 int64_t strength_graph(int32_t n, const int32_t *rp, const int32_t *col, const uint8_t *mask,
-                       const int32_t *scount, Arena &ar, int32_t **grp, int32_t **gcol,
-                       hipStream_t s);
+                       const int32_t *scount, bool wave, Arena &ar, int32_t **grp,
+                       int32_t **gcol, hipStream_t s);
 // Aggregation (roots = lexicographically-first distance-2 MIS in priority order; phase-2
 // join; isolated vertices unaggregated).  Returns nc; agg[n], is_root[n], root_vertex[nc].
 int32_t aggregate(int32_t n, int64_t nnzG, const int32_t *grp, const int32_t *gcol, int32_t order,
@@ -108,7 +111,7 @@ void sprsfy(int32_t n, const int32_t *rp, const int32_t *col, uint8_t *mask,
 // err bit 8: zero filtered diagonal with the plain diagonal.
 int64_t lump(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
              const uint8_t *mask, bool offlmp, double tau, bool one_norm, double mult,
-             Arena &ar, Csr &abar, double *invD, int32_t *err, hipStream_t s);
+             bool wave, Arena &ar, Csr &abar, double *invD, int32_t *err, hipStream_t s);
 // Power method; writes the estimate to *lam (device).  ws: 3n doubles + dot workspace.
 void power_method(const Csr &M, const double *invD, int32_t iters, uint64_t seed,
                   int32_t level, int32_t stream_id, double *lam, hipStream_t s);

@@ -18,6 +18,44 @@ namespace sa {
   if (i64_ >= (n)) return;                                        \
   const int32_t i = (int32_t)i64_;
 
+// ---- one wavefront per row (levels with long rows) ------------------------------------------
+// Kernels below with a _w suffix process one row per 64-thread block (one wavefront), lanes
+// striding over the row.  Floating-point sums keep the sequential order: terms are staged in
+// LDS 64 at a time and lane 0 adds them in ascending entry order from 0.  A term outside the
+// summed subset contributes +0.0, which leaves a sum that started from +0.0 unchanged bit for
+// bit (such a sum is never -0.0), so the result equals the sequential sum over the subset.
+constexpr int kW = 64;
+#define SA_WAVE_ROW_BEGIN(n)                        \
+  const int32_t i = (int32_t)blockIdx.x;            \
+  if (i >= (n)) return;                             \
+  const int lane = threadIdx.x;
+
+template <class F>
+__device__ inline double wave_seq_sum(int32_t b, int32_t e, F term, double *lds) {
+  const int lane = threadIdx.x;
+  double acc = 0.0;
+  for (int32_t c = b; c < e; c += kW) {
+    const int32_t k = c + lane;
+    lds[lane] = (k < e) ? term(k) : 0.0;
+    __syncthreads();
+    if (lane == 0) {
+      const int32_t lim = min(kW, e - c);
+      for (int32_t q = 0; q < lim; ++q) acc += lds[q];
+    }
+    __syncthreads();
+  }
+  if (lane == 0) lds[0] = acc;
+  __syncthreads();
+  const double r = lds[0];
+  __syncthreads();
+  return r;
+}
+__device__ inline int32_t wave_sum_i32(int32_t v) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ inline bool wave_any(bool p) { return __ballot(p) != 0; }
+
 // ---- validation -----------------------------------------------------------------------
 __global__ void k_validate(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
                            const double *val, int32_t *err) {
@@ -92,10 +130,34 @@ __global__ void k_strength(int32_t n, const int32_t *rp, const int32_t *col, con
   }
   scount[i] = cnt;
 }
+__global__ __launch_bounds__(kW) void k_strength_w(int32_t n, const int32_t *rp,
+                                                   const int32_t *col, const double *val,
+                                                   const double *dval, double th2,
+                                                   uint8_t *mask, int32_t *scount) {
+  SA_WAVE_ROW_BEGIN(n)
+  const double di = dval[i];
+  int32_t cnt = 0;
+  for (int32_t k = rp[i] + lane; k < rp[i + 1]; k += kW) {
+    const int32_t j = col[k];
+    if (j == i) {
+      mask[k] = 3;
+      continue;
+    }
+    const double a = val[k];
+    const double p = di * dval[j];
+    const bool strong = (p > 0.0) && (a * a >= th2 * p);
+    mask[k] = strong ? 1 : 0;
+    cnt += strong;
+  }
+  cnt = wave_sum_i32(cnt);
+  if (lane == 0) scount[i] = cnt;
+}
 void strength(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
-              const double *dval, double th2, uint8_t *mask, int32_t *scount, hipStream_t s) {
+              const double *dval, double th2, uint8_t *mask, int32_t *scount, bool wave,
+              hipStream_t s) {
   if (n <= 0) return;
-  k_strength<<<grid_for(n), kBlock, 0, s>>>(n, rp, col, val, dval, th2, mask, scount);
+  if (wave) k_strength_w<<<(unsigned)n, kW, 0, s>>>(n, rp, col, val, dval, th2, mask, scount);
+  else k_strength<<<grid_for(n), kBlock, 0, s>>>(n, rp, col, val, dval, th2, mask, scount);
   SA_LAUNCH_CHECK();
 }
 
@@ -111,6 +173,29 @@ __global__ void k_fill_strong(int32_t n, const int32_t *rp, const int32_t *col,
       scol[w++] = col[k];
       atomicAdd(&tcnt[col[k]], 1);
     }
+  }
+}
+__global__ __launch_bounds__(kW) void k_fill_strong_w(int32_t n, const int32_t *rp,
+                                                      const int32_t *col, const uint8_t *mask,
+                                                      const int32_t *srp, int32_t *scol,
+                                                      int32_t *tcnt) {
+  SA_WAVE_ROW_BEGIN(n)
+  int32_t w = srp[i];
+  for (int32_t c = rp[i]; c < rp[i + 1]; c += kW) {
+    const int32_t k = c + lane;
+    bool st = false;
+    int32_t j = 0;
+    if (k < rp[i + 1]) {
+      const uint8_t m = mask[k];
+      st = (m == 1 || m == 2);
+      j = col[k];
+    }
+    const unsigned long long bm = __ballot(st);
+    if (st) {
+      scol[w + __popcll(bm & ((1ull << lane) - 1ull))] = j;
+      atomicAdd(&tcnt[j], 1);
+    }
+    w += __popcll(bm);
   }
 }
 __global__ void k_scatter_t(int32_t n, const int32_t *srp, const int32_t *scol, int32_t *tpos,
@@ -142,8 +227,8 @@ __global__ void k_union(int32_t n, const int32_t *arp, const int32_t *acol, cons
 }
 
 int64_t strength_graph(int32_t n, const int32_t *rp, const int32_t *col, const uint8_t *mask,
-                       const int32_t *scount, Arena &ar, int32_t **grp_out, int32_t **gcol_out,
-                       hipStream_t s) {
+                       const int32_t *scount, bool wave, Arena &ar, int32_t **grp_out,
+                       int32_t **gcol_out, hipStream_t s) {
   Arena tmp;
   tmp.stream = s;
   int32_t *srp = tmp.alloc<int32_t>(n + 1);
@@ -152,7 +237,8 @@ int64_t strength_graph(int32_t n, const int32_t *rp, const int32_t *col, const u
   int32_t *scol = tmp.alloc<int32_t>(nnzS);
   int32_t *tcnt = tmp.alloc<int32_t>(n + 1);
   fill_i32(tcnt, 0, n + 1, s);
-  k_fill_strong<<<grid_for(n), kBlock, 0, s>>>(n, rp, col, mask, srp, scol, tcnt);
+  if (wave) k_fill_strong_w<<<(unsigned)n, kW, 0, s>>>(n, rp, col, mask, srp, scol, tcnt);
+  else k_fill_strong<<<grid_for(n), kBlock, 0, s>>>(n, rp, col, mask, srp, scol, tcnt);
   SA_LAUNCH_CHECK();
   int32_t *trp = tmp.alloc<int32_t>(n + 1);
   exclusive_scan_i32(tcnt, trp, n, s);
@@ -304,6 +390,42 @@ __global__ void k_mis_pass2(int32_t n, const int32_t *grp, const int32_t *gcol, 
   }
 }
 
+// Largest row length of a CSR (two-stage maximum, no contended atomics).
+__global__ void k_rowlen_max_stage(int32_t n, const int32_t *rp, int32_t *part) {
+  __shared__ int32_t sh[kBlock];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  sh[threadIdx.x] = (i < n) ? rp[i + 1] - rp[i] : 0;
+  __syncthreads();
+  for (int w = kBlock / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+__global__ void k_max_i32(int32_t n, const int32_t *a, int32_t *out) {
+  __shared__ int32_t sh[kBlock];
+  int32_t m = 0;
+  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) m = max(m, a[i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = kBlock / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+int32_t max_row_length(int32_t n, const int32_t *rp, hipStream_t s) {
+  if (n <= 0) return 0;
+  const unsigned nb = grid_for(n);
+  int32_t *part = (int32_t *)dev_alloc(sizeof(int32_t) * (nb + 1), s);
+  k_rowlen_max_stage<<<nb, kBlock, 0, s>>>(n, rp, part);
+  k_max_i32<<<1, kBlock, 0, s>>>((int32_t)nb, part, part + nb);
+  SA_LAUNCH_CHECK();
+  const int32_t m = read1(part + nb, s);
+  dev_free(part, s);
+  return m;
+}
+
 template <class K>
 __global__ void k_roots(int32_t n, const K *key, int32_t *isr) {
   SA_ROW_KERNEL_BEGIN(n)
@@ -370,10 +492,11 @@ static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const
   // Rounds run in batches between flag checks; a round on a finished state changes nothing.
   // flags[r] = 1 iff some vertex was still undecided after round r.
   const int batch = 16;
-  const int64_t cap = (int64_t)n + batch + 2;
-  int32_t *flags = tmp.alloc<int32_t>(cap);
-  fill_i32(flags, 0, cap, s);
-  const bool wave = nnzG > 24 * (int64_t)n;
+  // every batch decides at least one vertex, so this bound is never reached
+  const int64_t cap = (int64_t)batch * ((int64_t)n + 2) + 64;
+  int32_t *flags = tmp.alloc<int32_t>(batch);
+  const int32_t maxdeg = max_row_length(n, grp, s);
+  const bool wave = maxdeg > 64 || nnzG > 24 * (int64_t)n;
   const unsigned g = wave ? grid_for((int64_t)n * 64) : grid_for(n);
   int32_t *hflags = nullptr;
   SA_HIP(hipHostMalloc((void **)&hflags, sizeof(int32_t) * batch, hipHostMallocDefault));
@@ -382,19 +505,19 @@ static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const
   bool done = nnzG == 0;
   try {
     while (!done) {
+      fill_i32(flags, 0, batch, s);
       for (int q = 0; q < batch; ++q, ++r) {
         if (r >= cap) throw Error(SA_ERR_COARSEN_STALLED, "root selection did not end");
         if (wave) {
           k_mis_pass1<K, true><<<g, kBlock, 0, s>>>(n, grp, gcol, key, k1, act);
-          k_mis_pass2<K, true><<<g, kBlock, 0, s>>>(n, grp, gcol, k1, key, flags + r);
+          k_mis_pass2<K, true><<<g, kBlock, 0, s>>>(n, grp, gcol, k1, key, flags + q);
         } else {
           k_mis_pass1<K, false><<<g, kBlock, 0, s>>>(n, grp, gcol, key, k1, act);
-          k_mis_pass2<K, false><<<g, kBlock, 0, s>>>(n, grp, gcol, k1, key, flags + r);
+          k_mis_pass2<K, false><<<g, kBlock, 0, s>>>(n, grp, gcol, k1, key, flags + q);
         }
       }
       SA_LAUNCH_CHECK();
-      SA_HIP(hipMemcpyAsync(hflags, flags + r - batch, sizeof(int32_t) * batch,
-                            hipMemcpyDeviceToHost, s));
+      SA_HIP(hipMemcpyAsync(hflags, flags, sizeof(int32_t) * batch, hipMemcpyDeviceToHost, s));
       SA_HIP(hipStreamSynchronize(s));
       for (int q = 0; q < batch; ++q)
         if (hflags[q] == 0) {
@@ -402,6 +525,7 @@ static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const
           done = true;
           break;
         }
+
     }
   } catch (...) {
     (void)hipHostFree(hflags);
@@ -436,6 +560,8 @@ int32_t aggregate(int32_t n, int64_t nnzG, const int32_t *grp, const int32_t *gc
 }
 
 // ---- Sprsfy (Sec. 2.5) --------------------------------------------------------------------
+constexpr int32_t kSprsfyShort = 32;   // root rows up to this length: one thread per aggregate
+constexpr int32_t kSprsfyLds = 4096;   // longer root rows (up to this): one block per aggregate
 __global__ void k_count_members(int32_t n, const int32_t *agg, int32_t *cnt) {
   SA_ROW_KERNEL_BEGIN(n)
   if (agg[i] >= 0) atomicAdd(&cnt[agg[i]], 1);
@@ -457,6 +583,7 @@ __global__ void k_sprsfy(int32_t nc, const int32_t *rp, const int32_t *col, uint
   const int32_t J = (int32_t)J64;
   const int32_t r = root_vertex[J];
   const int32_t rb = rp[r], re = rp[r + 1];
+  if (re - rb > kSprsfyShort) return;  // long root rows: k_sprsfy_block
   for (int32_t k = rb; k < re; ++k) {
     const int32_t u0 = col[k];
     if (u0 == r || mask[k] != 0) continue;  // weak connections of the root only
@@ -504,6 +631,149 @@ __global__ void k_sprsfy(int32_t nc, const int32_t *rp, const int32_t *col, uint
   }
 }
 
+// Aggregates whose root row is long: the root row's (aggregate, strong) pairs are sorted in
+// LDS; a candidate is an aggregate reached only through weak entries (not J, not unaggregated).
+// Strong entries of the non-root members are counted per candidate (binary search in the
+// sorted candidate list); a count of 1 drops that entry and its transpose.  Same decisions
+// as k_sprsfy.
+__device__ inline void bitonic_u64_blk(uint64_t *a, int32_t L) {
+  for (int32_t k = 2; k <= L; k <<= 1) {
+    for (int32_t j = k >> 1; j > 0; j >>= 1) {
+      for (int32_t idx = threadIdx.x; idx < L; idx += blockDim.x) {
+        const int32_t ixj = idx ^ j;
+        if (ixj > idx) {
+          const uint64_t x = a[idx], y = a[ixj];
+          const bool up = (idx & k) == 0;
+          if ((x > y) == up) {
+            a[idx] = y;
+            a[ixj] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+__global__ __launch_bounds__(kBlock) void k_sprsfy_block(int32_t nc, const int32_t *rp,
+                                                         const int32_t *col, uint8_t *mask,
+                                                         const int32_t *agg,
+                                                         const int32_t *root_vertex,
+                                                         const int32_t *mrp, const int32_t *mem,
+                                                         int32_t *overflow) {
+  __shared__ uint64_t pairs[kSprsfyLds];
+  __shared__ int32_t cand[kSprsfyLds];
+  __shared__ int32_t cnt[kSprsfyLds];
+  __shared__ int32_t edge[kSprsfyLds];
+  __shared__ int32_t s_nc;
+  const int32_t J = blockIdx.x;
+  if (J >= nc) return;
+  const int32_t r = root_vertex[J];
+  const int32_t rb = rp[r], re = rp[r + 1];
+  const int32_t len = re - rb;
+  if (len <= kSprsfyShort) return;
+  if (len > kSprsfyLds) {
+    if (threadIdx.x == 0) atomicOr(overflow, 1);
+    return;
+  }
+  int32_t L = 1;
+  while (L < len) L <<= 1;
+  // key = (aggregate + 1) << 1 | strong ; entries that cannot be candidates sort first as 0
+  for (int32_t q = threadIdx.x; q < L; q += blockDim.x) {
+    uint64_t key = ~0ull;
+    if (q < len) {
+      const int32_t k = rb + q;
+      const int32_t u = col[k];
+      const int32_t c = (u == r) ? -1 : agg[u];
+      const uint8_t m = mask[k];
+      const bool strong = (m == 1 || m == 2);
+      key = (c < 0) ? 0ull : (((uint64_t)(c + 1) << 1) | (strong ? 1u : 0u));
+    }
+    pairs[q] = key;
+  }
+  if (threadIdx.x == 0) s_nc = 0;
+  __syncthreads();
+  bitonic_u64_blk(pairs, L);
+  // run heads: first entry of each aggregate; candidate if no strong entry in its run
+  for (int32_t q = threadIdx.x; q < len; q += blockDim.x) {
+    const uint64_t x = pairs[q];
+    if (x == 0ull || x == ~0ull) continue;
+    const int32_t c = (int32_t)(x >> 1) - 1;
+    const bool head = q == 0 || (pairs[q - 1] >> 1) != (x >> 1);
+    if (!head) continue;
+    int32_t t = q;
+    bool strong = false;
+    while (t < len && (pairs[t] >> 1) == (x >> 1)) strong |= (pairs[t++] & 1) != 0;
+    if (!strong && c != J) {
+      const int32_t slot = atomicAdd(&s_nc, 1);
+      cand[slot] = c;
+    }
+  }
+  __syncthreads();
+  const int32_t ncand = s_nc;
+  if (ncand == 0) return;  // block-uniform
+  // sort the candidate list (small) for binary search
+  for (int32_t q = threadIdx.x; q < L; q += blockDim.x)
+    pairs[q] = q < ncand ? (uint64_t)(uint32_t)cand[q] : ~0ull;
+  __syncthreads();
+  bitonic_u64_blk(pairs, L);
+  for (int32_t q = threadIdx.x; q < ncand; q += blockDim.x) {
+    cand[q] = (int32_t)pairs[q];
+    cnt[q] = 0;
+    edge[q] = -1;
+  }
+  __syncthreads();
+  for (int32_t mm = mrp[J]; mm < mrp[J + 1]; ++mm) {
+    const int32_t v = mem[mm];
+    if (v == r) continue;
+    for (int32_t k = rp[v] + threadIdx.x; k < rp[v + 1]; k += blockDim.x) {
+      const int32_t u = col[k];
+      if (u == v) continue;
+      const uint8_t m = mask[k];
+      if (!(m == 1 || m == 2)) continue;
+      const int32_t c = agg[u];
+      if (c < 0) continue;
+      int32_t lo = 0, hi = ncand - 1;
+      while (lo <= hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (cand[mid] == c) {
+          atomicAdd(&cnt[mid], 1);
+          edge[mid] = k;
+          break;
+        }
+        if (cand[mid] < c) lo = mid + 1;
+        else hi = mid - 1;
+      }
+    }
+  }
+  __syncthreads();
+  for (int32_t q = threadIdx.x; q < ncand; q += blockDim.x) {
+    if (cnt[q] != 1) continue;
+    const int32_t ev = edge[q];
+    mask[ev] = 2;
+    const int32_t u = col[ev];
+    // the row holding ev: search the members for the one whose row range contains it
+    int32_t vv = -1;
+    for (int32_t mm = mrp[J]; mm < mrp[J + 1]; ++mm) {
+      const int32_t v = mem[mm];
+      if (ev >= rp[v] && ev < rp[v + 1]) {
+        vv = v;
+        break;
+      }
+    }
+    int32_t lo = rp[u], hi = rp[u + 1] - 1;
+    while (lo <= hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      const int32_t cm = col[mid];
+      if (cm == vv) {
+        if (mask[mid] == 1) mask[mid] = 2;
+        break;
+      }
+      if (cm < vv) lo = mid + 1;
+      else hi = mid - 1;
+    }
+  }
+}
+
 void sprsfy(int32_t n, const int32_t *rp, const int32_t *col, uint8_t *mask, const int32_t *agg,
             const int32_t *root_vertex, int32_t nc, hipStream_t s) {
   if (nc <= 0) return;
@@ -520,8 +790,17 @@ void sprsfy(int32_t n, const int32_t *rp, const int32_t *col, uint8_t *mask, con
   int32_t *mem = tmp.alloc<int32_t>(n);
   k_scatter_members<<<grid_for(n), kBlock, 0, s>>>(n, agg, pos, mem);
   SA_LAUNCH_CHECK();
+  int32_t *ovf = tmp.alloc<int32_t>(1);
+  fill_i32(ovf, 0, 1, s);
   k_sprsfy<<<grid_for(nc), kBlock, 0, s>>>(nc, rp, col, mask, agg, root_vertex, mrp, mem);
   SA_LAUNCH_CHECK();
+  if (max_row_length(n, rp, s) > kSprsfyShort) {
+    k_sprsfy_block<<<(unsigned)nc, kBlock, 0, s>>>(nc, rp, col, mask, agg, root_vertex, mrp,
+                                                   mem, ovf);
+    SA_LAUNCH_CHECK();
+  }
+  if (read1(ovf, s))
+    throw Error(SA_ERR_INVALID_ARG, "Sprsfy: a root row exceeds the supported length");
 }
 
 // ---- filtered matrix (Sec. 1.1 plain lumping; Sec. 2.3 Algorithm 2) and its diagonal -----
@@ -640,11 +919,150 @@ __global__ void k_lump_fill(int32_t n, const int32_t *rp, const int32_t *col, co
   invD[i] = 1.0 / D;
 }
 
+__global__ __launch_bounds__(kW) void k_lump_count_w(int32_t n, const int32_t *rp,
+                                                     const int32_t *col, const uint8_t *mask,
+                                                     int32_t *cnt) {
+  SA_WAVE_ROW_BEGIN(n)
+  int32_t c = 0;
+  for (int32_t k = rp[i] + lane; k < rp[i + 1]; k += kW) c += (col[k] == i || mask[k] == 1);
+  c = wave_sum_i32(c);
+  if (lane == 0) cnt[i] = c;
+}
+
+// Same arithmetic as k_lump_fill, one wavefront per row: the kept entries are compacted in
+// parallel; every floating-point sum (removed entries, kept positives/negatives, original
+// off-diagonal magnitudes, the 1-norm and the row sum) runs sequentially through
+// wave_seq_sum; the scalar decisions are taken identically by all lanes.
+__global__ __launch_bounds__(kW) void k_lump_fill_w(int32_t n, const int32_t *rp,
+                                                    const int32_t *col, const double *val,
+                                                    const uint8_t *mask, const int32_t *arp,
+                                                    int32_t *acol, double *aval, bool offlmp,
+                                                    double tau, bool one_norm, double mult,
+                                                    double *invD, int32_t *err) {
+  __shared__ double lds[kW];
+  SA_WAVE_ROW_BEGIN(n)
+  const int32_t b = rp[i], e = rp[i + 1];
+  const int32_t o = arp[i], oe = arp[i + 1];
+  int32_t w = o;
+  int32_t ds = o;
+  double aii = 0.0;
+  for (int32_t c = b; c < e; c += kW) {
+    const int32_t k = c + lane;
+    bool kept = false, isd = false;
+    int32_t j = 0;
+    double v = 0.0;
+    if (k < e) {
+      j = col[k];
+      v = val[k];
+      isd = (j == i);
+      kept = isd || mask[k] == 1;
+    }
+    const unsigned long long bm = __ballot(kept);
+    const int32_t pos = w + __popcll(bm & ((1ull << lane) - 1ull));
+    if (kept) {
+      acol[pos] = j;
+      aval[pos] = v;
+    }
+    const unsigned long long dm = __ballot(isd);
+    if (dm) {
+      const int dl = __ffsll((long long)dm) - 1;
+      ds = __shfl(pos, dl, 64);
+      aii = __shfl(v, dl, 64);
+    }
+    w += __popcll(bm);
+  }
+  __syncthreads();
+  const double r = wave_seq_sum(b, e, [&](int32_t k) {
+    return (col[k] != i && mask[k] != 1) ? val[k] : 0.0;
+  }, lds);
+  if (!offlmp || r >= 0.0 || !(aii > 0.0)) {
+    if (lane == 0) aval[ds] = aii + r;
+  } else {
+    const double kp = wave_seq_sum(o, oe, [&](int32_t t) {
+      return (t != ds && aval[t] > 0.0) ? aval[t] : 0.0;
+    }, lds);
+    const double km = wave_seq_sum(o, oe, [&](int32_t t) {
+      return (t != ds && aval[t] < 0.0) ? aval[t] : 0.0;
+    }, lds);
+    bool hp = false, hm = false;
+    for (int32_t t = o + lane; t < oe; t += kW) {
+      if (t == ds) continue;
+      hp |= aval[t] > 0.0;
+      hm |= aval[t] < 0.0;
+    }
+    const bool has_kp = wave_any(hp), has_km = wave_any(hm);
+    __syncthreads();
+    if (-r <= kp) {
+      const double delta = r / kp;
+      for (int32_t t = o + lane; t < oe; t += kW)
+        if (t != ds && aval[t] > 0.0) aval[t] = aval[t] * (1.0 + delta);
+    } else {
+      const double offsum = wave_seq_sum(b, e, [&](int32_t k) {
+        return col[k] != i ? fabs(val[k]) : 0.0;
+      }, lds);
+      const double T = tau * (offsum / aii);
+      const double rhat = r + kp;
+      if (!has_km) {
+        if (has_kp && fabs(r + kp) / aii <= T) {
+          const double delta = r / kp;
+          for (int32_t t = o + lane; t < oe; t += kW)
+            if (t != ds && aval[t] > 0.0) aval[t] = aval[t] * (1.0 + delta);
+        }
+      } else {
+        const double a = aii;
+        const double c = -km - rhat;
+        const double U = fmin(fabs(rhat), a);
+        const double bnd = T * a - c;
+        double rs = 0.0;
+        bool feasible;
+        if (T > 1.0) {
+          const double ub = bnd / (T - 1.0);
+          feasible = ub >= 0.0;
+          if (feasible) rs = fmin(U, ub);
+        } else if (T < 1.0) {
+          const double lb = bnd / (T - 1.0);
+          feasible = lb <= U;
+          if (feasible) rs = U;
+        } else {
+          feasible = bnd >= 0.0;
+          if (feasible) rs = U;
+        }
+        if (!feasible) rs = (c <= a) ? U : 0.0;
+        const double delta = (rhat + rs) / km;
+        for (int32_t t = o + lane; t < oe; t += kW) {
+          if (t == ds) continue;
+          const double v = aval[t];
+          if (v > 0.0) aval[t] = 0.0;
+          else if (v < 0.0) aval[t] = v * (1.0 + delta);
+        }
+        __syncthreads();
+        if (lane == 0) aval[ds] = a - rs;
+      }
+    }
+  }
+  __syncthreads();
+  double D;
+  if (one_norm) {
+    D = wave_seq_sum(o, oe, [&](int32_t t) { return fabs(aval[t]); }, lds);
+    if (D == 0.0) {
+      D = 1.0;
+    } else {
+      const double sum = wave_seq_sum(o, oe, [&](int32_t t) { return aval[t]; }, lds);
+      if (D < mult * sum) D = mult * sum;
+    }
+  } else {
+    D = aval[ds];
+    if (D == 0.0 && lane == 0) atomicOr(err, 8);
+  }
+  if (lane == 0) invD[i] = 1.0 / D;
+}
+
 int64_t lump(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
              const uint8_t *mask, bool offlmp, double tau, bool one_norm, double mult,
-             Arena &ar, Csr &abar, double *invD, int32_t *err, hipStream_t s) {
+             bool wave, Arena &ar, Csr &abar, double *invD, int32_t *err, hipStream_t s) {
   int32_t *cnt = (int32_t *)dev_alloc(sizeof(int32_t) * (n + 1), s);
-  k_lump_count<<<grid_for(n), kBlock, 0, s>>>(n, rp, col, mask, cnt);
+  if (wave) k_lump_count_w<<<(unsigned)n, kW, 0, s>>>(n, rp, col, mask, cnt);
+  else k_lump_count<<<grid_for(n), kBlock, 0, s>>>(n, rp, col, mask, cnt);
   SA_LAUNCH_CHECK();
   abar.n = abar.ncols = n;
   abar.rp = ar.alloc<int32_t>(n + 1);
@@ -653,8 +1071,12 @@ int64_t lump(int32_t n, const int32_t *rp, const int32_t *col, const double *val
   abar.nnz = read1(abar.rp + n, s);
   abar.col = ar.alloc<int32_t>(abar.nnz);
   abar.val = ar.alloc<double>(abar.nnz);
-  k_lump_fill<<<grid_for(n), kBlock, 0, s>>>(n, rp, col, val, mask, abar.rp, abar.col, abar.val,
+  if (wave)
+    k_lump_fill_w<<<(unsigned)n, kW, 0, s>>>(n, rp, col, val, mask, abar.rp, abar.col, abar.val,
                                              offlmp, tau, one_norm, mult, invD, err);
+  else
+    k_lump_fill<<<grid_for(n), kBlock, 0, s>>>(n, rp, col, val, mask, abar.rp, abar.col,
+                                               abar.val, offlmp, tau, one_norm, mult, invD, err);
   SA_LAUNCH_CHECK();
   return abar.nnz;
 }
@@ -667,8 +1089,9 @@ __global__ void k_power_init(int32_t n, uint64_t seed, int32_t level, int32_t st
   const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
   x[i] = 2.0 * u - 1.0;
 }
-// max |y| as the bit pattern of a non-negative double (monotone for non-negative values).
-__global__ void k_absmax(int32_t n, const double *y, unsigned long long *out) {
+// max |y| as the bit pattern of a non-negative double (monotone for non-negative values);
+// per-block partials, then one block reduces them (no contended atomics).
+__global__ void k_absmax(int32_t n, const double *y, unsigned long long *part) {
   __shared__ unsigned long long sh[kBlock];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long m = 0;
@@ -683,7 +1106,21 @@ __global__ void k_absmax(int32_t n, const double *y, unsigned long long *out) {
       sh[threadIdx.x] = sh[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicMax(out, sh[0]);
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+__global__ void k_absmax_final(int32_t nb, const unsigned long long *part,
+                               unsigned long long *out) {
+  __shared__ unsigned long long sh[kBlock];
+  unsigned long long m = 0;
+  for (int32_t i = threadIdx.x; i < nb; i += blockDim.x) m = part[i] > m ? part[i] : m;
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = kBlock / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w && sh[threadIdx.x + w] > sh[threadIdx.x])
+      sh[threadIdx.x] = sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
 }
 __global__ void k_normalize(int32_t n, const double *y, const unsigned long long *mx,
                             double *x, int32_t *dead) {
@@ -709,7 +1146,8 @@ void power_method(const Csr &M, const double *invD, int32_t iters, uint64_t seed
   double *y = tmp.alloc<double>(n);
   double *ws = tmp.alloc<double>(dot_ws_size(n));
   double *sc = tmp.alloc<double>(4);
-  unsigned long long *mx = tmp.alloc<unsigned long long>(1);
+  const unsigned nbmax = grid_for(n);
+  unsigned long long *mx = tmp.alloc<unsigned long long>(nbmax + 1);
   int32_t *dead = tmp.alloc<int32_t>(1);
   fill_i32(dead, 0, 1, s);
   k_power_init<<<grid_for(n), kBlock, 0, s>>>(n, seed, level, stream_id, x);
@@ -724,8 +1162,8 @@ void power_method(const Csr &M, const double *invD, int32_t iters, uint64_t seed
       SA_LAUNCH_CHECK();
       break;
     }
-    SA_HIP(hipMemsetAsync(mx, 0, sizeof(unsigned long long), s));
-    k_absmax<<<grid_for(n), kBlock, 0, s>>>(n, y, mx);
+    k_absmax<<<nbmax, kBlock, 0, s>>>(n, y, mx + 1);
+    k_absmax_final<<<1, kBlock, 0, s>>>((int32_t)nbmax, mx + 1, mx);
     k_normalize<<<grid_for(n), kBlock, 0, s>>>(n, y, mx, x, dead);
     SA_LAUNCH_CHECK();
   }

@@ -37,6 +37,33 @@ __global__ void k_count_products(int32_t m, const int32_t *xrp, const int32_t *x
   cnt[i] = t;
 }
 
+// One wavefront per row of X (long rows): xpref by a wavefront prefix sum.
+__global__ __launch_bounds__(64) void k_count_products_w(int32_t m, const int32_t *xrp,
+                                                         const int32_t *xcol,
+                                                         const int32_t *yrp, int64_t *cnt,
+                                                         int32_t *xpref) {
+  const int32_t i = blockIdx.x;
+  if (i >= m) return;
+  const int lane = threadIdx.x;
+  int64_t base = 0;
+  for (int32_t c = xrp[i]; c < xrp[i + 1]; c += 64) {
+    const int32_t e = c + lane;
+    int32_t len = 0;
+    if (e < xrp[i + 1]) {
+      const int32_t k = xcol[e];
+      len = yrp[k + 1] - yrp[k];
+    }
+    int32_t incl = len;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t v = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += v;
+    }
+    if (e < xrp[i + 1]) xpref[e] = (int32_t)(base + incl - len);
+    base += __shfl(incl, 63, 64);
+  }
+  if (lane == 0) cnt[i] = base;
+}
+
 // One atomic per wavefront and bin (ballot + popcount), not per row.
 __device__ inline void wave_push(bool pred, int32_t *counter, int32_t *list, int32_t value) {
   const unsigned long long msk = __ballot(pred);
@@ -452,7 +479,10 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
   int32_t *xpref = tmp.alloc<int32_t>(X.nnz > 0 ? X.nnz : 1);
   int64_t *poff = tmp.alloc<int64_t>(m + 1);
   if (m > 0) {
-    k_count_products<<<grid_for(m), kBlock, 0, s>>>(m, X.rp, X.col, Y.rp, cnt, xpref);
+    if (max_row_length(m, X.rp, s) > 64)
+      k_count_products_w<<<(unsigned)m, 64, 0, s>>>(m, X.rp, X.col, Y.rp, cnt, xpref);
+    else
+      k_count_products<<<grid_for(m), kBlock, 0, s>>>(m, X.rp, X.col, Y.rp, cnt, xpref);
     SA_LAUNCH_CHECK();
   }
   exclusive_scan_i64(cnt, poff, m, s);

@@ -170,6 +170,18 @@ class Hierarchy:
         return (self.export(level, f"{name}_rp"), self.export(level, f"{name}_col"),
                 self.export(level, f"{name}_val"))
 
+    def profile(self, on: bool = True):
+        """Enable/disable HIP-event timing of the fine-level SpMV launches in solve()."""
+        _lib.check(_lib.lib().sa_profile_enable(self._h, 1 if on else 0), "sa_profile_enable")
+
+    def profile_read(self) -> dict:
+        n = C.c_int64()
+        ms = C.c_double()
+        by = C.c_double()
+        _lib.check(_lib.lib().sa_profile_read(self._h, C.byref(n), C.byref(ms), C.byref(by)),
+                   "sa_profile_read")
+        return {"launches": n.value, "ms": ms.value, "bytes": by.value}
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.lib().sa_destroy(self._h)
