@@ -1,0 +1,188 @@
+// Device memory for the library: a stream-ordered caching allocator, and pinned host staging
+// for small readbacks.
+//
+// Setup allocates and frees a few hundred buffers per level; done with hipMallocAsync /
+// hipFreeAsync each call costs tens of microseconds of host time and leaves the GPU idle.
+// Blocks are instead taken from hipMalloc once, rounded to a size class, and kept in a free
+// list per (device, stream) when released.  A block freed on stream s is only handed out
+// again for work on the same stream s, so stream order alone guarantees that every kernel
+// that used it has finished before its next owner's kernels start; no event is needed.
+// When hipMalloc fails, every cached block is returned to the driver (after a device
+// synchronisation) and the allocation is retried once.
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <unordered_map>
+
+#include "common.hpp"
+
+namespace sa {
+
+namespace {
+
+struct Cache {
+  std::mutex mu;
+  // (device, stream) -> size -> free blocks of that size
+  std::map<std::pair<int, hipStream_t>, std::multimap<size_t, void *>> free_lists;
+  std::unordered_map<void *, std::pair<size_t, int>> live;  // block -> (size, device)
+  size_t cached = 0, in_use = 0;
+};
+
+Cache &cache() {
+  static Cache *c = new Cache;  // never destroyed: blocks may be released at process exit
+  return *c;
+}
+
+// Size classes: multiples of 256 B up to 4 KiB, then 8 classes per power of two (at most
+// 12.5% over the request).
+size_t size_class(size_t b) {
+  if (b <= 4096) return (b + 255) & ~size_t(255);
+  size_t p = size_t(1) << (63 - __builtin_clzll(b));
+  const size_t step = p / 8;
+  return (b + step - 1) / step * step;
+}
+
+void release_cached_locked(Cache &c) {
+  for (auto &kv : c.free_lists)
+    for (auto &blk : kv.second) (void)hipFree(blk.second);
+  c.free_lists.clear();
+  c.cached = 0;
+}
+
+}  // namespace
+
+void *dev_alloc(size_t bytes, hipStream_t s) {
+  Cache &c = cache();
+  int dev = 0;
+  SA_HIP(hipGetDevice(&dev));
+  const size_t sz = size_class(bytes ? bytes : 1);
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto fl = c.free_lists.find({dev, s});
+    if (fl != c.free_lists.end()) {
+      // the same class, or the next one up (at most ~25% larger)
+      auto it = fl->second.lower_bound(sz);
+      if (it != fl->second.end() && it->first <= sz + sz / 4) {
+        void *p = it->second;
+        const size_t got = it->first;
+        fl->second.erase(it);
+        c.cached -= got;
+        c.in_use += got;
+        c.live[p] = {got, dev};
+        return p;
+      }
+    }
+  }
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, sz);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    std::lock_guard<std::mutex> lk(c.mu);
+    (void)hipDeviceSynchronize();
+    release_cached_locked(c);
+    e = hipMalloc(&p, sz);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(SA_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  std::lock_guard<std::mutex> lk(c.mu);
+  c.in_use += sz;
+  c.live[p] = {sz, dev};
+  return p;
+}
+
+void dev_free(void *p, hipStream_t s) {
+  if (!p) return;
+  Cache &c = cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  auto it = c.live.find(p);
+  if (it == c.live.end()) return;  // not ours: ignore
+  const size_t sz = it->second.first;
+  const int dev = it->second.second;
+  c.live.erase(it);
+  c.in_use -= sz;
+  c.cached += sz;
+  c.free_lists[{dev, s}].emplace(sz, p);
+}
+
+void dev_release_cached() {
+  Cache &c = cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  (void)hipDeviceSynchronize();
+  release_cached_locked(c);
+}
+
+void dev_cache_stats(size_t *in_use, size_t *cached) {
+  Cache &c = cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  if (in_use) *in_use = c.in_use;
+  if (cached) *cached = c.cached;
+}
+
+// ---- pinned staging for readbacks ---------------------------------------------------------
+// Copies into pageable host memory go through a driver bounce buffer and cost ~100 us each;
+// each thread stages readbacks in a pinned buffer of its own instead.  Buffers are recycled
+// through a process-wide list when their thread ends (no HIP call at thread exit).
+namespace {
+struct PinnedPool {
+  std::mutex mu;
+  std::vector<std::pair<void *, size_t>> spare;
+};
+PinnedPool &pinned_pool() {
+  static PinnedPool *p = new PinnedPool;
+  return *p;
+}
+struct PinnedHolder {
+  void *p = nullptr;
+  size_t n = 0;
+  ~PinnedHolder() {
+    if (!p) return;
+    PinnedPool &pp = pinned_pool();
+    std::lock_guard<std::mutex> lk(pp.mu);
+    pp.spare.emplace_back(p, n);
+  }
+};
+thread_local PinnedHolder t_pinned;
+}  // namespace
+
+void *pinned_staging(size_t bytes) {
+  PinnedHolder &h = t_pinned;
+  if (h.p && h.n >= bytes) return h.p;
+  {
+    PinnedPool &pp = pinned_pool();
+    std::lock_guard<std::mutex> lk(pp.mu);
+    if (h.p) pp.spare.emplace_back(h.p, h.n);
+    h.p = nullptr;
+    h.n = 0;
+    for (size_t i = 0; i < pp.spare.size(); ++i)
+      if (pp.spare[i].second >= bytes) {
+        h.p = pp.spare[i].first;
+        h.n = pp.spare[i].second;
+        pp.spare.erase(pp.spare.begin() + (ptrdiff_t)i);
+        return h.p;
+      }
+  }
+  size_t n = 4096;
+  while (n < bytes) n *= 2;
+  void *p = nullptr;
+  SA_HIP(hipHostMalloc(&p, n, hipHostMallocDefault));
+  h.p = p;
+  h.n = n;
+  return p;
+}
+
+void readback(void *host, const void *dev, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return;
+  if (bytes > (size_t(1) << 20)) {  // bulk copies: straight into the caller's memory
+    SA_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s));
+    SA_HIP(hipStreamSynchronize(s));
+    return;
+  }
+  void *st = pinned_staging(bytes);
+  SA_HIP(hipMemcpyAsync(st, dev, bytes, hipMemcpyDeviceToHost, s));
+  SA_HIP(hipStreamSynchronize(s));
+  std::memcpy(host, st, bytes);
+}
+
+}  // namespace sa

@@ -38,10 +38,16 @@ inline unsigned grid_for(int64_t n, int block = kBlock) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
-// Stream-ordered device allocation (hipMallocAsync from the device's default pool, whose
-// release threshold is raised at first use so freed blocks are reused, not returned).
+// Stream-ordered device allocation from the library's caching allocator (alloc.hip): a
+// block released on stream s is reused only for later work on s.
 void *dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void *p, hipStream_t s);
+// Returns every cached (free) block to the driver; synchronises the device.
+void dev_release_cached();
+// Bytes held by live allocations and by cached free blocks.
+void dev_cache_stats(size_t *in_use, size_t *cached);
+// Blocking device-to-host copy staged through a per-thread pinned buffer.
+void readback(void *host, const void *dev, size_t bytes, hipStream_t s);
 
 // A typed device buffer owned by an Arena or held as a temporary.
 template <class T>
@@ -99,8 +105,7 @@ struct CsrF {  // float copy of the values for the FP32 V-cycle
 template <class T>
 T read1(const T *dptr, hipStream_t s) {
   T v;
-  SA_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
-  SA_HIP(hipStreamSynchronize(s));
+  readback(&v, dptr, sizeof(T), s);
   return v;
 }
 

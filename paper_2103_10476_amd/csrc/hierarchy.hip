@@ -299,8 +299,7 @@ static void setup_impl(sa_hierarchy *h, const sa_csr *A, const double *B) {
     chebyshev_scalars(L, o);
     if (L.lam_d) {
       double lo[2];
-      SA_HIP(hipMemcpyAsync(lo, L.lam_d, sizeof(lo), hipMemcpyDeviceToHost, s));
-      SA_HIP(hipStreamSynchronize(s));
+      readback(lo, L.lam_d, sizeof(lo), s);
       L.lam = lo[0];
       L.omega = lo[1];
     }

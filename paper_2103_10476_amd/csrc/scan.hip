@@ -1,35 +1,7 @@
-// Device memory helpers, fills and exclusive prefix sums.
-#include <mutex>
-
+// Fills and exclusive prefix sums.
 #include "common.hpp"
 
 namespace sa {
-
-namespace {
-std::once_flag g_pool_once;
-
-void configure_pool() {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return;
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess) return;
-  uint64_t thr = UINT64_MAX;  // keep freed blocks in the pool
-  (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-}
-}  // namespace
-
-void *dev_alloc(size_t bytes, hipStream_t s) {
-  std::call_once(g_pool_once, configure_pool);
-  void *p = nullptr;
-  hipError_t e = hipMallocAsync(&p, bytes, s);
-  if (e != hipSuccess || !p)
-    throw Error(SA_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-  return p;
-}
-
-void dev_free(void *p, hipStream_t s) {
-  if (p) (void)hipFreeAsync(p, s);
-}
 
 template <class T>
 __global__ void k_fill(T *p, T v, int64_t n) {
@@ -112,9 +84,7 @@ __global__ void k_scan_apply(const T *in, T *out, int64_t n, const T *offsets) {
 template <class T>
 static void scan_impl(const T *in, T *out, int64_t n, hipStream_t s) {
   if (n <= 0) {
-    T zero = 0;
-    SA_HIP(hipMemcpyAsync(out, &zero, sizeof(T), hipMemcpyHostToDevice, s));
-    SA_HIP(hipStreamSynchronize(s));  // zero lives on the stack
+    fill(out, T(0), 1, s);
     return;
   }
   int64_t nb = ceil_div(n, kScanTile);

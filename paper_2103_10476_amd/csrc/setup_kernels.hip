@@ -311,7 +311,8 @@ __global__ void k_mis_init(int32_t n, const int32_t *grp, int32_t order, uint64_
 
 template <class K, bool WAVE>
 __global__ void k_mis_pass1(int32_t n, const int32_t *grp, const int32_t *gcol, const K *key,
-                            K *k1, uint8_t *act) {
+                            K *k1, uint8_t *act, const int32_t *prev) {
+  if (prev && *prev == 0) return;  // the previous round left nothing undecided
   if (WAVE) {
     const int lane = threadIdx.x & 63;
     const int64_t v64 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -351,7 +352,8 @@ __global__ void k_mis_pass1(int32_t n, const int32_t *grp, const int32_t *gcol, 
 
 template <class K, bool WAVE>
 __global__ void k_mis_pass2(int32_t n, const int32_t *grp, const int32_t *gcol, const K *k1,
-                            K *key, int32_t *flag) {
+                            K *key, int32_t *flag, const int32_t *prev) {
+  if (prev && *prev == 0) return;
   if (WAVE) {
     const int lane = threadIdx.x & 63;
     const int64_t v64 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -489,49 +491,46 @@ static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const
   uint8_t *act = tmp.alloc<uint8_t>(n);
   k_mis_init<K><<<grid_for(n), kBlock, 0, s>>>(n, grp, order, seed, level, key, act);
   SA_LAUNCH_CHECK();
-  // Rounds run in batches between flag checks; a round on a finished state changes nothing.
-  // flags[r] = 1 iff some vertex was still undecided after round r.
-  const int batch = 16;
-  // every batch decides at least one vertex, so this bound is never reached
-  const int64_t cap = (int64_t)batch * ((int64_t)n + 2) + 64;
-  int32_t *flags = tmp.alloc<int32_t>(batch);
+  // Rounds run in batches between flag checks: flags[q] = 1 iff some vertex was still
+  // undecided after round q of the batch.  A round whose predecessor left nothing undecided
+  // exits at once, so rounds past the end of the selection cost only their launch; batches
+  // grow 16, 32, 64, 64, ... to bound both the readbacks and that overshoot.
+  constexpr int kMaxBatch = 64;
+  // every round decides at least one vertex, so this bound is never reached
+  const int64_t cap = (int64_t)n + 2 + 2 * kMaxBatch;
+  int32_t *flags = tmp.alloc<int32_t>(kMaxBatch);
   const int32_t maxdeg = max_row_length(n, grp, s);
   const bool wave = maxdeg > 64 || nnzG > 24 * (int64_t)n;
   const unsigned g = wave ? grid_for((int64_t)n * 64) : grid_for(n);
-  int32_t *hflags = nullptr;
-  SA_HIP(hipHostMalloc((void **)&hflags, sizeof(int32_t) * batch, hipHostMallocDefault));
+  int32_t hflags[kMaxBatch];
   int64_t r = 0;
   int32_t used = 0;
+  int batch = 16;
   bool done = nnzG == 0;
-  try {
-    while (!done) {
-      fill_i32(flags, 0, batch, s);
-      for (int q = 0; q < batch; ++q, ++r) {
-        if (r >= cap) throw Error(SA_ERR_COARSEN_STALLED, "root selection did not end");
-        if (wave) {
-          k_mis_pass1<K, true><<<g, kBlock, 0, s>>>(n, grp, gcol, key, k1, act);
-          k_mis_pass2<K, true><<<g, kBlock, 0, s>>>(n, grp, gcol, k1, key, flags + q);
-        } else {
-          k_mis_pass1<K, false><<<g, kBlock, 0, s>>>(n, grp, gcol, key, k1, act);
-          k_mis_pass2<K, false><<<g, kBlock, 0, s>>>(n, grp, gcol, k1, key, flags + q);
-        }
+  while (!done) {
+    if (r >= cap) throw Error(SA_ERR_COARSEN_STALLED, "root selection did not end");
+    fill_i32(flags, 0, batch, s);
+    for (int q = 0; q < batch; ++q) {
+      const int32_t *prev = q > 0 ? flags + q - 1 : nullptr;
+      if (wave) {
+        k_mis_pass1<K, true><<<g, kBlock, 0, s>>>(n, grp, gcol, key, k1, act, prev);
+        k_mis_pass2<K, true><<<g, kBlock, 0, s>>>(n, grp, gcol, k1, key, flags + q, prev);
+      } else {
+        k_mis_pass1<K, false><<<g, kBlock, 0, s>>>(n, grp, gcol, key, k1, act, prev);
+        k_mis_pass2<K, false><<<g, kBlock, 0, s>>>(n, grp, gcol, k1, key, flags + q, prev);
       }
-      SA_LAUNCH_CHECK();
-      SA_HIP(hipMemcpyAsync(hflags, flags, sizeof(int32_t) * batch, hipMemcpyDeviceToHost, s));
-      SA_HIP(hipStreamSynchronize(s));
-      for (int q = 0; q < batch; ++q)
-        if (hflags[q] == 0) {
-          used = (int32_t)(r - batch + q + 1);
-          done = true;
-          break;
-        }
-
     }
-  } catch (...) {
-    (void)hipHostFree(hflags);
-    throw;
+    SA_LAUNCH_CHECK();
+    readback(hflags, flags, sizeof(int32_t) * batch, s);
+    for (int q = 0; q < batch; ++q)
+      if (hflags[q] == 0) {
+        used = (int32_t)(r + q + 1);
+        done = true;
+        break;
+      }
+    r += batch;
+    batch = batch * 2 > kMaxBatch ? kMaxBatch : batch * 2;
   }
-  (void)hipHostFree(hflags);
   if (rounds_out) *rounds_out = used;
   int32_t *isr = tmp.alloc<int32_t>(n + 1);
   k_roots<K><<<grid_for(n), kBlock, 0, s>>>(n, key, isr);

@@ -18,6 +18,17 @@ struct Chunk {
 constexpr int32_t kPlanWindow = 2048;  // cost units per SpMV block
 constexpr int32_t kPlanRowCost = 8;     // cost of a row besides its entries
 
+// Workgroups are handed to the 8 XCDs round-robin (workgroup b runs on XCD b mod 8), and
+// each XCD has its own L2.  Renumbering so that XCD x takes one contiguous run of row blocks
+// keeps the x entries a block gathers from neighbouring rows (stencil planes) in that XCD's
+// L2 instead of fetching them once per XCD.  A bijection on [0, nb).
+__device__ __forceinline__ int32_t xcd_block(uint32_t b, uint32_t nb) {
+  constexpr uint32_t kXcd = 8;
+  const uint32_t q = nb / kXcd, r = nb % kXcd;
+  const uint32_t x = b % kXcd, k = b / kXcd;
+  return (int32_t)(x * q + (x < r ? x : r) + k);
+}
+
 template <class T, class Epi>
 __global__ __launch_bounds__(kBlock) void k_spmv(const int32_t *__restrict__ bstart,
                                                  const int32_t *__restrict__ rp,
@@ -27,7 +38,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int32_t *__restrict__ bst
   constexpr int CH = Chunk<T>::value;
   __shared__ T prod[CH];
   const int t = threadIdx.x;
-  const int32_t r0 = bstart[blockIdx.x], r1 = bstart[blockIdx.x + 1];
+  const int32_t b = xcd_block(blockIdx.x, gridDim.x);
+  const int32_t r0 = bstart[b], r1 = bstart[b + 1];
   if (r0 >= r1) return;  // block-uniform
   const int32_t row = r0 + t;
   const int32_t e0 = rp[r0], e1 = rp[r1];

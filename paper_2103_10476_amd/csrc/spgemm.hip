@@ -498,8 +498,7 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
     SA_LAUNCH_CHECK();
   }
   int32_t hc[8];
-  SA_HIP(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, s));
-  SA_HIP(hipStreamSynchronize(s));
+  readback(hc, counters, sizeof(hc), s);
   const int32_t *l0 = lists, *l1 = lists + m, *l2 = lists + 2 * (int64_t)m,
                 *l3 = lists + 3 * (int64_t)m;
   if (hc[0] > 0) {
