@@ -166,8 +166,81 @@ sa_status sa_export_level(const sa_hierarchy *h, int32_t level, sa_part what, vo
 sa_status sa_profile_enable(sa_hierarchy *h, int32_t on);
 sa_status sa_profile_read(const sa_hierarchy *h, int64_t *launches, double *ms, double *bytes);
 
-/* Releases the hierarchy and all its device memory (NULL is ignored). */
+/* Releases the hierarchy and all its device memory (NULL is ignored).  Device blocks go back
+ * to the library's per-stream cache for reuse by later work on the same stream. */
 void sa_destroy(sa_hierarchy *h);
+
+/* ---- serving: many independent setup + solve requests on one GPU ------------------------
+ * A server owns max_slots worker threads, each with its own HIP stream (default priority).
+ * Requests are admitted in submission order (FIFO) while the sum of the admitted requests'
+ * device-byte estimates (sa_estimate_bytes) stays within hbm_budget; an admitted request runs
+ * sa_setup + sa_solve on its slot's stream, its result is copied to host memory and all its
+ * device memory is released before the next request takes the slot (continuous batching at
+ * request granularity: a slot is refilled as soon as its request completes).  Requests share
+ * nothing but the GPU, and each runs exactly the code path of a standalone sa_setup +
+ * sa_solve, so a request's x, iteration count and residual are bitwise the same alone or in
+ * any mix.  The server serves the paper's use case of many SA-AMG solves (Sec. 4) on one
+ * device; it adds no numerical method of its own. */
+typedef struct sa_server sa_server;
+
+typedef struct {
+  int32_t status;          /* the request's own status: SA_OK, SA_NOT_CONVERGED or an error */
+  int32_t n;               /* rows                                                           */
+  int32_t iterations;      /* CG iterations                                                  */
+  int32_t levels;          /* hierarchy levels                                               */
+  double rel_residual;     /* sqrt(r.r / b.b) at exit                                        */
+  double queue_seconds;    /* submission -> admission                                        */
+  double setup_seconds;    /* sa_setup                                                       */
+  double solve_seconds;    /* sa_solve                                                       */
+  double latency_seconds;  /* submission -> result ready                                     */
+  int64_t reserved_bytes;  /* estimate charged against the budget at admission               */
+  int64_t peak_bytes;      /* device bytes the request actually held at its peak             */
+} sa_result;
+
+typedef struct {
+  int64_t submitted, completed, failed, queued, running;
+  int64_t budget_bytes;
+  int64_t reserved_bytes;       /* estimates of the running requests                         */
+  int64_t peak_reserved_bytes;  /* maximum of reserved_bytes so far                          */
+  int64_t peak_measured_bytes;  /* maximum over time of the summed measured live bytes       */
+} sa_server_stats;
+
+/* Device bytes a request on an n x n matrix with nnz entries is charged at admission: an
+ * upper bound on its peak device memory (hierarchy + setup temporaries + solve workspace)
+ * for operator complexities up to about 3. */
+int64_t sa_estimate_bytes(int32_t n, int64_t nnz);
+
+/* Creates a server.  ctx may be NULL (current device).  hbm_budget: bytes (> 0);
+ * max_slots: concurrent requests, 1..32.  Errors: SA_ERR_INVALID_ARG, SA_ERR_HIP. */
+sa_status sa_server_create(const sa_context *ctx, size_t hbm_budget, int32_t max_slots,
+                           sa_server **out);
+
+/* Queues a request: A (validated by sa_setup when the request runs), b (n values) and the
+ * options (NULL = defaults) are copied to host memory before the call returns (A->loc gives
+ * where A and b live).  *ticket receives the request's id.  Errors: SA_ERR_INVALID_ARG
+ * (bad arguments, or a request whose estimate alone exceeds the budget), SA_ERR_HIP. */
+sa_status sa_server_submit(sa_server *s, const sa_csr *A, const double *b, const sa_options *o,
+                           uint64_t *ticket);
+
+/* Non-blocking: SA_PENDING while the request is queued or running.  Once it has finished,
+ * writes x (n values in `loc` memory; may be NULL) and *r (may be NULL), forgets the ticket
+ * and returns the request's status (SA_OK, SA_NOT_CONVERGED or its error; sa_last_error then
+ * gives the request's message).  Unknown ticket: SA_ERR_INVALID_ARG. */
+sa_status sa_server_poll(sa_server *s, uint64_t ticket, double *x, sa_location loc,
+                         sa_result *r);
+
+/* As sa_server_poll, but blocks until the request has finished. */
+sa_status sa_server_wait(sa_server *s, uint64_t ticket, double *x, sa_location loc,
+                         sa_result *r);
+
+/* Blocks until no request is queued or running (results stay available to poll). */
+sa_status sa_server_drain(sa_server *s);
+
+sa_status sa_server_get_stats(const sa_server *s, sa_server_stats *st);
+
+/* Finishes the running requests, drops the queued ones, joins the workers and releases the
+ * server (NULL is ignored). */
+void sa_server_destroy(sa_server *s);
 
 const char *sa_status_string(sa_status s);
 const char *sa_last_error(void);

@@ -31,7 +31,9 @@ PART_DTYPE = {"A_rp": "int32", "A_col": "int32", "A_val": "float64", "mask": "ui
 
 EXPORTED = ["sa_default_options", "sa_setup", "sa_solve", "sa_vcycle", "sa_hierarchy_info",
             "sa_export_size", "sa_export_level", "sa_destroy", "sa_status_string",
-            "sa_last_error", "sa_profile_enable", "sa_profile_read"]
+            "sa_last_error", "sa_profile_enable", "sa_profile_read", "sa_estimate_bytes",
+            "sa_server_create", "sa_server_submit", "sa_server_poll", "sa_server_wait",
+            "sa_server_drain", "sa_server_get_stats", "sa_server_destroy"]
 
 
 class SaOptions(C.Structure):
@@ -59,6 +61,29 @@ class SaInfo(C.Structure):
                 ("omega", C.c_double * 16), ("smoother_lambda", C.c_double * 16),
                 ("mis_rounds", C.c_int32 * 16), ("operator_complexity", C.c_double),
                 ("device_bytes", C.c_int64), ("setup_seconds", C.c_double)]
+
+
+class SaResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n", C.c_int32), ("iterations", C.c_int32),
+                ("levels", C.c_int32), ("rel_residual", C.c_double),
+                ("queue_seconds", C.c_double), ("setup_seconds", C.c_double),
+                ("solve_seconds", C.c_double), ("latency_seconds", C.c_double),
+                ("reserved_bytes", C.c_int64), ("peak_bytes", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["status"] = STATUS_NAMES.get(self.status, str(self.status))
+        return d
+
+
+class SaServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("queued", C.c_int64), ("running", C.c_int64), ("budget_bytes", C.c_int64),
+                ("reserved_bytes", C.c_int64), ("peak_reserved_bytes", C.c_int64),
+                ("peak_measured_bytes", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -97,6 +122,23 @@ def lib():
         L.sa_profile_read.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]
         L.sa_profile_read.restype = C.c_int
+        L.sa_estimate_bytes.argtypes = [C.c_int32, C.c_int64]
+        L.sa_estimate_bytes.restype = C.c_int64
+        L.sa_server_create.argtypes = [C.POINTER(SaContext), C.c_size_t, C.c_int32,
+                                       C.POINTER(C.c_void_p)]
+        L.sa_server_create.restype = C.c_int
+        L.sa_server_submit.argtypes = [P, C.POINTER(SaCsr), P, C.POINTER(SaOptions),
+                                       C.POINTER(C.c_uint64)]
+        L.sa_server_submit.restype = C.c_int
+        for f in (L.sa_server_poll, L.sa_server_wait):
+            f.argtypes = [P, C.c_uint64, P, C.c_int32, C.POINTER(SaResult)]
+            f.restype = C.c_int
+        L.sa_server_drain.argtypes = [P]
+        L.sa_server_drain.restype = C.c_int
+        L.sa_server_get_stats.argtypes = [P, C.POINTER(SaServerStats)]
+        L.sa_server_get_stats.restype = C.c_int
+        L.sa_server_destroy.argtypes = [P]
+        L.sa_server_destroy.restype = None
         L.sa_destroy.argtypes = [P]
         L.sa_destroy.restype = None
         L.sa_status_string.argtypes = [C.c_int]

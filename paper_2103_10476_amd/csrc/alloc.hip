@@ -24,7 +24,12 @@ struct Cache {
   std::mutex mu;
   // (device, stream) -> size -> free blocks of that size
   std::map<std::pair<int, hipStream_t>, std::multimap<size_t, void *>> free_lists;
-  std::unordered_map<void *, std::pair<size_t, int>> live;  // block -> (size, device)
+  struct Live {
+    size_t size;
+    int dev;
+    Meter *meter;
+  };
+  std::unordered_map<void *, Live> live;
   size_t cached = 0, in_use = 0;
 };
 
@@ -49,7 +54,19 @@ void release_cached_locked(Cache &c) {
   c.cached = 0;
 }
 
+thread_local Meter *t_meter = nullptr;
+
+void meter_add(Meter *m, int64_t sz) {
+  for (; m; m = m->parent) {
+    m->live += sz;
+    if (m->live > m->peak) m->peak = m->live;
+  }
+}
+
 }  // namespace
+
+void meter_begin(Meter *m) { t_meter = m; }
+void meter_end() { t_meter = nullptr; }
 
 void *dev_alloc(size_t bytes, hipStream_t s) {
   Cache &c = cache();
@@ -68,7 +85,8 @@ void *dev_alloc(size_t bytes, hipStream_t s) {
         fl->second.erase(it);
         c.cached -= got;
         c.in_use += got;
-        c.live[p] = {got, dev};
+        c.live[p] = {got, dev, t_meter};
+        meter_add(t_meter, (int64_t)got);
         return p;
       }
     }
@@ -88,7 +106,8 @@ void *dev_alloc(size_t bytes, hipStream_t s) {
   }
   std::lock_guard<std::mutex> lk(c.mu);
   c.in_use += sz;
-  c.live[p] = {sz, dev};
+  c.live[p] = {sz, dev, t_meter};
+  meter_add(t_meter, (int64_t)sz);
   return p;
 }
 
@@ -98,12 +117,35 @@ void dev_free(void *p, hipStream_t s) {
   std::lock_guard<std::mutex> lk(c.mu);
   auto it = c.live.find(p);
   if (it == c.live.end()) return;  // not ours: ignore
-  const size_t sz = it->second.first;
-  const int dev = it->second.second;
+  const size_t sz = it->second.size;
+  const int dev = it->second.dev;
+  meter_add(it->second.meter, -(int64_t)sz);
   c.live.erase(it);
   c.in_use -= sz;
   c.cached += sz;
   c.free_lists[{dev, s}].emplace(sz, p);
+}
+
+void meter_read(const Meter *m, int64_t *live, int64_t *peak) {
+  Cache &c = cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  if (live) *live = m->live;
+  if (peak) *peak = m->peak;
+}
+
+void dev_release_stream(hipStream_t s) {
+  Cache &c = cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  auto fl = c.free_lists.find({dev, s});
+  if (fl == c.free_lists.end()) return;
+  (void)hipStreamSynchronize(s);
+  for (auto &blk : fl->second) {
+    (void)hipFree(blk.second);
+    c.cached -= blk.first;
+  }
+  c.free_lists.erase(fl);
 }
 
 void dev_release_cached() {

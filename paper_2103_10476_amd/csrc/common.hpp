@@ -44,8 +44,20 @@ void *dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void *p, hipStream_t s);
 // Returns every cached (free) block to the driver; synchronises the device.
 void dev_release_cached();
+// Returns the cached blocks of stream s (before s is destroyed).
+void dev_release_stream(hipStream_t s);
 // Bytes held by live allocations and by cached free blocks.
 void dev_cache_stats(size_t *in_use, size_t *cached);
+// Per-request accounting: while a Meter is installed on a thread, the device bytes (size
+// classes) allocated by that thread are charged to it until freed, from any thread.  The
+// Meter must outlive every block charged to it.
+struct Meter {
+  int64_t live = 0, peak = 0;
+  Meter *parent = nullptr;  // also charged (e.g. a server's total)
+};
+void meter_begin(Meter *m);
+void meter_end();
+void meter_read(const Meter *m, int64_t *live, int64_t *peak);  // consistent snapshot
 // Blocking device-to-host copy staged through a per-thread pinned buffer.
 void readback(void *host, const void *dev, size_t bytes, hipStream_t s);
 

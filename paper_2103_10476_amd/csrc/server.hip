@@ -1,0 +1,328 @@
+// Serving runtime: many independent SA-AMG setup + solve requests on one GPU.
+//
+// Each slot is a host worker thread with a HIP stream of its own.  Workers take requests in
+// submission order while the admitted requests' device-byte estimates fit the budget; a
+// request runs the ordinary sa_setup / sa_solve / sa_destroy on its slot's stream, so the
+// GPU overlaps the kernels of up to max_slots requests, and a slot is refilled as soon as
+// its request completes.  Requests never share device memory (the caching allocator keeps
+// blocks per stream), which makes every result independent of the mix it ran in.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "common.hpp"
+
+namespace sa {
+extern thread_local std::string g_last_error;
+}
+
+namespace {
+
+using sa::Error;
+
+// Admission estimate (sa_estimate_bytes): bytes per stored entry of A, per row, and fixed.
+constexpr int64_t kEstBytesPerEntry = 96;
+constexpr int64_t kEstBytesPerRow = 560;
+constexpr int64_t kEstBytesFixed = 64ll << 20;
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+struct Request {
+  uint64_t ticket = 0;
+  int32_t n = 0;
+  int64_t nnz = 0;
+  std::vector<int32_t> rp, col;
+  std::vector<double> val, b;
+  sa_options opt{};
+  std::vector<double> x;
+  sa_result res{};
+  std::string err;
+  double t_submit = 0.0;
+  bool done = false;
+  sa::Meter meter;
+};
+
+}  // namespace
+
+struct sa_server {
+  std::mutex mu;
+  std::condition_variable cv_work;  // workers: queue, budget or stop changed
+  std::condition_variable cv_done;  // waiters: a request finished
+  std::deque<std::shared_ptr<Request>> queue;
+  std::unordered_map<uint64_t, std::shared_ptr<Request>> all;  // not yet collected
+  std::vector<std::thread> workers;
+  std::vector<hipStream_t> streams;
+  int device = 0;
+  int64_t budget = 0, reserved = 0, peak_reserved = 0;
+  int64_t submitted = 0, completed = 0, failed = 0, running = 0;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  sa::Meter total;  // measured device bytes of all running requests
+};
+
+namespace {
+
+void run_request(sa_server *s, hipStream_t stream, Request &q) {
+  const double t_admit = now_s();
+  q.res.queue_seconds = t_admit - q.t_submit;
+  q.res.n = q.n;
+  q.meter.parent = &s->total;
+  sa::meter_begin(&q.meter);
+  sa_context ctx{stream};
+  sa_csr A{q.n, q.nnz, q.rp.data(), q.col.data(), q.val.data(), SA_HOST};
+  sa_hierarchy *h = nullptr;
+  sa_status st = sa_setup(&ctx, &A, nullptr, &q.opt, &h);
+  const double t_setup = now_s();
+  q.res.setup_seconds = t_setup - t_admit;
+  if (st == SA_OK) {
+    sa_info info;
+    if (sa_hierarchy_info(h, &info) == SA_OK) q.res.levels = info.levels;
+    q.x.assign((size_t)q.n, 0.0);
+    int32_t it = 0;
+    double rr = 0.0;
+    st = sa_solve(h, q.b.data(), q.x.data(), SA_HOST, &it, &rr);
+    q.res.iterations = it;
+    q.res.rel_residual = rr;
+  }
+  if (st < 0) q.err = sa_last_error();
+  q.res.solve_seconds = now_s() - t_setup;
+  sa_destroy(h);
+  sa::meter_end();
+  q.res.status = st;
+  q.res.peak_bytes = q.meter.peak;
+  // the request's inputs are no longer needed
+  std::vector<int32_t>().swap(q.rp);
+  std::vector<int32_t>().swap(q.col);
+  std::vector<double>().swap(q.val);
+  std::vector<double>().swap(q.b);
+}
+
+void worker_main(sa_server *s, int slot) {
+  (void)hipSetDevice(s->device);
+  hipStream_t stream = s->streams[(size_t)slot];
+  for (;;) {
+    std::shared_ptr<Request> q;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_work.wait(lk, [&] {
+        if (s->stop) return true;
+        if (s->queue.empty()) return false;
+        const int64_t need = s->queue.front()->res.reserved_bytes;
+        return s->running == 0 || s->reserved + need <= s->budget;
+      });
+      if (s->stop) return;
+      q = s->queue.front();
+      s->queue.pop_front();
+      s->reserved += q->res.reserved_bytes;
+      if (s->reserved > s->peak_reserved) s->peak_reserved = s->reserved;
+      ++s->running;
+    }
+    run_request(s, stream, *q);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->reserved -= q->res.reserved_bytes;
+      --s->running;
+      if (q->res.status < 0) ++s->failed;
+      else ++s->completed;
+      q->res.latency_seconds = now_s() - q->t_submit;
+      q->done = true;
+    }
+    s->cv_done.notify_all();
+    s->cv_work.notify_all();
+  }
+}
+
+template <class F>
+sa_status guarded_server(F &&f) {
+  try {
+    return f();
+  } catch (const Error &e) {
+    sa::g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    sa::g_last_error = "host allocation failed";
+    return SA_ERR_OOM;
+  } catch (const std::exception &e) {
+    sa::g_last_error = e.what();
+    return SA_ERR_HIP;
+  }
+}
+
+template <class T>
+void copy_host(std::vector<T> &dst, const T *src, size_t count, sa_location loc) {
+  dst.resize(count);
+  if (count == 0) return;
+  if (!src) throw Error(SA_ERR_INVALID_ARG, "null array");
+  if (loc == SA_DEVICE) {
+    SA_HIP(hipMemcpy(dst.data(), src, sizeof(T) * count, hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(dst.data(), src, sizeof(T) * count);
+  }
+}
+
+// Writes a finished request's result and returns its status; the caller holds s->mu and
+// removes the ticket afterwards.
+sa_status collect(Request &q, double *x, sa_location loc, sa_result *r) {
+  if (r) *r = q.res;
+  if (q.res.status < 0) {
+    sa::g_last_error = q.err;
+    return (sa_status)q.res.status;
+  }
+  if (x && q.n > 0) {
+    if (loc == SA_DEVICE) {
+      SA_HIP(hipMemcpy(x, q.x.data(), sizeof(double) * (size_t)q.n, hipMemcpyHostToDevice));
+    } else {
+      std::memcpy(x, q.x.data(), sizeof(double) * (size_t)q.n);
+    }
+  }
+  return (sa_status)q.res.status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t sa_estimate_bytes(int32_t n, int64_t nnz) {
+  if (n < 0 || nnz < 0) return 0;
+  // per stored entry of A and per row, with head-room for operator complexity ~3 and for
+  // the Galerkin products' temporaries; plus a fixed allowance for small problems
+  return (int64_t)kEstBytesPerEntry * nnz + (int64_t)kEstBytesPerRow * n + kEstBytesFixed;
+}
+
+sa_status sa_server_create(const sa_context *ctx, size_t hbm_budget, int32_t max_slots,
+                           sa_server **out) {
+  if (!out) return SA_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (hbm_budget == 0 || max_slots < 1 || max_slots > 32) return SA_ERR_INVALID_ARG;
+  (void)ctx;
+  return guarded_server([&]() -> sa_status {
+    std::unique_ptr<sa_server> s(new sa_server());
+    SA_HIP(hipGetDevice(&s->device));
+    s->budget = (int64_t)std::min<size_t>(hbm_budget, (size_t)INT64_MAX);
+    for (int i = 0; i < max_slots; ++i) {
+      hipStream_t st = nullptr;
+      if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        for (auto x : s->streams) (void)hipStreamDestroy(x);
+        throw Error(SA_ERR_HIP, "hipStreamCreateWithFlags failed");
+      }
+      s->streams.push_back(st);
+    }
+    for (int i = 0; i < max_slots; ++i) s->workers.emplace_back(worker_main, s.get(), i);
+    *out = s.release();
+    return SA_OK;
+  });
+}
+
+sa_status sa_server_submit(sa_server *s, const sa_csr *A, const double *b, const sa_options *o,
+                           uint64_t *ticket) {
+  if (!s || !A || !b || !ticket) return SA_ERR_INVALID_ARG;
+  if (A->n <= 0 || A->nnz < 0 || A->nnz >= (int64_t)INT32_MAX || !A->row_ptr)
+    return SA_ERR_INVALID_ARG;
+  if (o && o->struct_size != sizeof(sa_options)) return SA_ERR_INVALID_ARG;
+  return guarded_server([&]() -> sa_status {
+    auto q = std::make_shared<Request>();
+    q->n = A->n;
+    q->nnz = A->nnz;
+    if (o) q->opt = *o;
+    else sa_default_options(&q->opt);
+    q->res.reserved_bytes = sa_estimate_bytes(A->n, A->nnz);
+    if (q->res.reserved_bytes > s->budget)
+      throw Error(SA_ERR_INVALID_ARG, "request estimate exceeds the server's memory budget");
+    copy_host(q->rp, A->row_ptr, (size_t)A->n + 1, A->loc);
+    copy_host(q->col, A->col, (size_t)A->nnz, A->loc);
+    copy_host(q->val, A->val, (size_t)A->nnz, A->loc);
+    copy_host(q->b, b, (size_t)A->n, A->loc);
+    q->t_submit = now_s();
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (s->stop) throw Error(SA_ERR_INVALID_ARG, "server is shutting down");
+      q->ticket = s->next_ticket++;
+      s->all[q->ticket] = q;
+      s->queue.push_back(q);
+      ++s->submitted;
+      *ticket = q->ticket;
+    }
+    s->cv_work.notify_all();
+    return SA_OK;
+  });
+}
+
+sa_status sa_server_poll(sa_server *s, uint64_t ticket, double *x, sa_location loc,
+                         sa_result *r) {
+  if (!s) return SA_ERR_INVALID_ARG;
+  return guarded_server([&]() -> sa_status {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) throw Error(SA_ERR_INVALID_ARG, "unknown ticket");
+    if (!it->second->done) return SA_PENDING;
+    std::shared_ptr<Request> q = it->second;
+    s->all.erase(it);
+    return collect(*q, x, loc, r);
+  });
+}
+
+sa_status sa_server_wait(sa_server *s, uint64_t ticket, double *x, sa_location loc,
+                         sa_result *r) {
+  if (!s) return SA_ERR_INVALID_ARG;
+  return guarded_server([&]() -> sa_status {
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) throw Error(SA_ERR_INVALID_ARG, "unknown ticket");
+    std::shared_ptr<Request> q = it->second;
+    s->cv_done.wait(lk, [&] { return q->done; });
+    s->all.erase(ticket);
+    return collect(*q, x, loc, r);
+  });
+}
+
+sa_status sa_server_drain(sa_server *s) {
+  if (!s) return SA_ERR_INVALID_ARG;
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] { return s->queue.empty() && s->running == 0; });
+  return SA_OK;
+}
+
+sa_status sa_server_get_stats(const sa_server *cs, sa_server_stats *st) {
+  if (!cs || !st) return SA_ERR_INVALID_ARG;
+  sa_server *s = const_cast<sa_server *>(cs);
+  std::lock_guard<std::mutex> lk(s->mu);
+  st->submitted = s->submitted;
+  st->completed = s->completed;
+  st->failed = s->failed;
+  st->queued = (int64_t)s->queue.size();
+  st->running = s->running;
+  st->budget_bytes = s->budget;
+  st->reserved_bytes = s->reserved;
+  st->peak_reserved_bytes = s->peak_reserved;
+  sa::meter_read(&s->total, nullptr, &st->peak_measured_bytes);
+  return SA_OK;
+}
+
+void sa_server_destroy(sa_server *s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->queue.clear();
+  }
+  s->cv_work.notify_all();
+  for (auto &t : s->workers) t.join();
+  for (auto st : s->streams) {
+    sa::dev_release_stream(st);
+    (void)hipStreamDestroy(st);
+  }
+  delete s;
+}
+
+}  // extern "C"

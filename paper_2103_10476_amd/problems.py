@@ -339,6 +339,14 @@ def serving_requests(count: int = 256, seed: int = 6, smin: int = 16, smax: int 
     return out
 
 
+def serving_method(req: dict) -> dict:
+    """Method settings of a serving request: plain SA for the 7-point cubes; OffLmp + 1Norm
+    for the random-coefficient 27-point cubes, where plain SA's filtered diagonal can vanish
+    (the failure the adaptations of Sec. 2 address).  FP32 V-cycle inside FP64 CG to 1e-10."""
+    variants = ("offlmp", "1norm") if req["kind"] == "q1" else ()
+    return {"variants": variants, "precision": "fp32", "rtol": 1e-10}
+
+
 def build_request(req: dict):
     if req["kind"] == "fd7":
         p = fd7_stretched(req["side"], req["aspect"])

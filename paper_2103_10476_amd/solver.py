@@ -194,6 +194,82 @@ class Hierarchy:
             pass
 
 
+def estimate_bytes(n: int, nnz: int) -> int:
+    """Device bytes a serving request is charged at admission (sa_estimate_bytes)."""
+    return int(_lib.lib().sa_estimate_bytes(int(n), int(nnz)))
+
+
+class Server:
+    """Many independent setup+solve requests on one GPU (sa_server_*): FIFO admission under
+    an HBM budget, max_slots requests in flight, each on its own stream.  Inputs are host
+    numpy arrays (copied at submit); results come back as host numpy arrays."""
+
+    def __init__(self, hbm_budget: int = 8 << 30, max_slots: int = 4):
+        h = C.c_void_p()
+        _lib.check(_lib.lib().sa_server_create(None, int(hbm_budget), int(max_slots),
+                                               C.byref(h)), "sa_server_create")
+        self._s = h
+
+    def submit(self, A, b, options: Options | None = None) -> int:
+        """A: CsrProblem or (n, rp, col, val) of host arrays; returns the ticket."""
+        if hasattr(A, "rp"):
+            n, rp, col, val = A.n, A.rp, A.col, A.val
+        else:
+            n, rp, col, val = A
+        rp = np.ascontiguousarray(rp, dtype=np.int32)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        csr = _lib.SaCsr(int(n), int(col.size), rp.ctypes.data, col.ctypes.data,
+                         val.ctypes.data, _lib.SA_HOST)
+        opts = (options or Options()).to_c()
+        t = C.c_uint64()
+        _lib.check(_lib.lib().sa_server_submit(self._s, C.byref(csr),
+                                               C.c_void_p(b.ctypes.data), C.byref(opts),
+                                               C.byref(t)), "sa_server_submit")
+        return t.value
+
+    def _collect(self, fn, ticket, n):
+        x = np.empty(n, dtype=np.float64)
+        r = _lib.SaResult()
+        code = fn(self._s, C.c_uint64(ticket), C.c_void_p(x.ctypes.data), _lib.SA_HOST,
+                  C.byref(r))
+        return code, x, r
+
+    def wait(self, ticket: int, n: int):
+        """Blocks until the request is done: (x, result dict).  A failed request raises."""
+        code, x, r = self._collect(_lib.lib().sa_server_wait, ticket, n)
+        _lib.check(code, "sa_server_wait")
+        return x, r.as_dict()
+
+    def poll(self, ticket: int, n: int):
+        """None while pending, else (x, result dict).  A failed request raises."""
+        code, x, r = self._collect(_lib.lib().sa_server_poll, ticket, n)
+        if code == _lib.SA_PENDING:
+            return None
+        _lib.check(code, "sa_server_poll")
+        return x, r.as_dict()
+
+    def drain(self):
+        _lib.check(_lib.lib().sa_server_drain(self._s), "sa_server_drain")
+
+    def stats(self) -> dict:
+        st = _lib.SaServerStats()
+        _lib.check(_lib.lib().sa_server_get_stats(self._s, C.byref(st)), "sa_server_get_stats")
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_s", None):
+            _lib.lib().sa_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def setup(A, nullspace=None, options: Options | None = None, stream=None) -> Hierarchy:
     """setup(A, nullspace, options) -> hierarchy.  A is a CsrProblem or an (n, rp, col, val)
     tuple (numpy or CUDA tensors)."""
