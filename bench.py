@@ -88,6 +88,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP32 and variant legs (profiling runs)")
+    ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--serving-rates", default="0.35,0.7,1.0",
+                    help="open-loop arrival rates as fractions of the closed-loop rate")
+    ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--serving-budget-gib", type=float, default=8.0)
+    ap.add_argument("--only-serving", action="store_true",
+                    help="run only the serving leg (prints its JSON object)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="first run a plain device copy of BYTES (3 times): the reference "
                          "kernel that calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE counters")
@@ -101,6 +108,9 @@ def main():
     from paper_2103_10476_amd import problems, solver
 
     torch.cuda.set_device(0)
+    if args.only_serving:
+        print(json.dumps(serving_leg(solver, problems, args)), flush=True)
+        return
     if args.copy_probe:
         src = torch.ones(args.copy_probe // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -189,6 +199,7 @@ def main():
     if not args.no_extras:
         result["fp32_vcycle_vs_fp64"] = precision_leg(solver, problems, PRECISION_WORKLOAD)
         result["variants"] = variants_leg(solver, p, drp, dcol, dval, db)
+        result["serving"] = serving_leg(solver, problems, args)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(p, b)
     print(json.dumps(result), flush=True)
@@ -326,6 +337,102 @@ def variants_leg(solver, p, drp, dcol, dval, db):
             h.close()
         except Exception as e:  # a variant may fail on a problem (reported, not fatal)
             out[name] = {"status": str(e)[:120]}
+    return out
+
+
+def _build_requests(problems, count):
+    """The serving workload's requests (seeded), built on host worker processes."""
+    from concurrent.futures import ProcessPoolExecutor
+    reqs = problems.serving_requests(count)
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        built = list(ex.map(problems.build_request, reqs, chunksize=4))
+    return reqs, built
+
+
+def _serve_run(solver, problems, reqs, built, budget, slots, arrivals=None):
+    """Submits every request (all at once, or at the given arrival offsets in seconds) and
+    collects the results.  Latency = completion - scheduled arrival."""
+    srv = solver.Server(hbm_budget=budget, max_slots=slots)
+    tickets, lat_base = [], []
+    t0 = time.perf_counter()
+    for i, (req, (p, b)) in enumerate(zip(reqs, built)):
+        if arrivals is not None:
+            wait = t0 + arrivals[i] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+        sched = t0 + (arrivals[i] if arrivals is not None else 0.0)
+        o = solver.Options(**problems.serving_method(req))
+        tickets.append(srv.submit(p, b, o))
+        lat_base.append(time.perf_counter() - sched)  # submission delay (host copy)
+    lat, queue, its, fails, peaks, ests = [], [], [], [], [], []
+    worst = (0.0, None)
+    for t, req, (p, _), base in zip(tickets, reqs, built, lat_base):
+        try:
+            _, r = srv.wait(t, p.n)
+        except Exception as e:
+            fails.append({"request": req, "n": p.n, "nnz": p.nnz, "error": str(e)[:160]})
+            continue
+        ratio = r["peak_bytes"] / r["reserved_bytes"]
+        if ratio > worst[0]:
+            worst = (ratio, {"request": req, "n": p.n, "nnz": p.nnz, "peak": r["peak_bytes"],
+                             "estimate": r["reserved_bytes"], "levels": r["levels"]})
+        lat.append(base + r["latency_seconds"])
+        queue.append(r["queue_seconds"])
+        its.append(r["iterations"])
+        peaks.append(r["peak_bytes"])
+        ests.append(r["reserved_bytes"])
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    return {"requests": len(reqs), "failed": len(fails), "failures": fails,
+            "wall_s": round(wall, 3),
+            "solves_per_s": round((len(reqs) - len(fails)) / wall, 2),
+            "latency_s": {"p50": round(pct(lat, 50), 4), "p99": round(pct(lat, 99), 4)},
+            "queue_s": {"p50": round(pct(queue, 50), 4), "p99": round(pct(queue, 99), 4)},
+            "iterations": {"p50": pct(its, 50), "max": int(max(its))},
+            "budget_bytes": budget, "peak_reserved_bytes": st["peak_reserved_bytes"],
+            "peak_measured_bytes": st["peak_measured_bytes"],
+            "max_peak_over_estimate": round(worst[0], 3), "max_peak_request": worst[1]}
+
+
+def serving_leg(solver, problems, args):
+    """Serving workload: seeded requests (7-point z-stretched cubes with aspect 10^U[1,3] or
+    27-point random-kappa cubes, side 16..96), FP32 V-cycle in FP64 CG to 1e-10, on one GPU
+    with `slots` concurrent requests under an HBM budget.  Closed loop (all submitted at
+    t=0) gives the throughput; open loop runs use Poisson arrivals at the given fractions of
+    it; a final closed-loop run uses a budget of 1.5 times the largest request's estimate."""
+    t = time.perf_counter()
+    reqs, built = _build_requests(problems, args.serving_requests)
+    log(f"[bench] serving: {len(reqs)} requests built in {time.perf_counter() - t:.1f} s")
+    budget = int(args.serving_budget_gib * 2**30)
+    slots = args.serving_slots
+    # warm-up: one pass over a few requests (allocator cache, code paths)
+    _serve_run(solver, problems, reqs[:8], built[:8], budget, slots)
+    out = {"workload": f"{len(reqs)} seeded requests: 7-point z-stretched cube (aspect "
+                       "10^U[1,3]) or 27-point random-kappa cube (u ~ U[-3,3]), side "
+                       "U{16..96}; OffLmp+1Norm SA, Chebyshev(2) with the eigenvalue "
+                       "estimate x1.1, FP32 V-cycle, FP64 CG, rtol 1e-10",
+           "slots": slots,
+           "nnz_total": int(sum(p.nnz for p, _ in built))}
+    closed = _serve_run(solver, problems, reqs, built, budget, slots)
+    log(f"[bench] serving closed loop: {closed['solves_per_s']} solves/s, latency p50 "
+        f"{closed['latency_s']['p50']} s")
+    out["closed_loop"] = closed
+    rng = np.random.Generator(np.random.PCG64(60))
+    gaps = rng.exponential(1.0, size=len(reqs))
+    for frac in [float(f) for f in args.serving_rates.split(",") if f]:
+        rate = frac * closed["solves_per_s"]
+        arr = np.concatenate([[0.0], np.cumsum(gaps[:-1] / rate)])
+        r = _serve_run(solver, problems, reqs, built, budget, slots, arrivals=arr)
+        r["arrival_rate_per_s"] = round(rate, 2)
+        log(f"[bench] serving open loop at {frac} x: latency p50 {r['latency_s']['p50']} s "
+            f"p99 {r['latency_s']['p99']} s")
+        out[f"open_loop_{frac:g}x"] = r
+    big = max(solver.estimate_bytes(p.n, p.nnz) for p, _ in built)
+    tight = _serve_run(solver, problems, reqs, built, int(1.5 * big), slots)
+    log(f"[bench] serving tight budget: {tight['solves_per_s']} solves/s")
+    out["closed_loop_tight_budget"] = tight
     return out
 
 

@@ -29,8 +29,8 @@ namespace {
 using sa::Error;
 
 // Admission estimate (sa_estimate_bytes): bytes per stored entry of A, per row, and fixed.
-constexpr int64_t kEstBytesPerEntry = 96;
-constexpr int64_t kEstBytesPerRow = 560;
+constexpr int64_t kEstBytesPerEntry = 64;
+constexpr int64_t kEstBytesPerRow = 1200;
 constexpr int64_t kEstBytesFixed = 64ll << 20;
 
 double now_s() {

@@ -23,9 +23,8 @@ def log(msg):
 
 
 def _requests(count, smin, smax, seed=11):
-    """Small-side members of the serving workload.  27-point requests use OffLmp + 1Norm
-    (plain SA's filtered diagonal can vanish on them); the rest rotate through other method
-    settings so that the mix holds several code paths."""
+    """Small-side members of the serving workload with the serving method (OffLmp + 1Norm),
+    plus other settings in rotation so that the mix holds several code paths."""
     from paper_2103_10476_amd import solver
     extra = [{"precision": "fp32"}, {}, {"variants": ("sprsfy", "cnstrnt"), "max_coarse": 200},
              {"smoother": "jacobi", "rtol": 1e-8}]
@@ -34,8 +33,7 @@ def _requests(count, smin, smax, seed=11):
         p, b = pb.build_request(req)
         kw = dict(pb.serving_method(req))
         kw.update(extra[i % len(extra)])
-        if req["kind"] == "q1":
-            kw["variants"] = tuple(sorted(set(kw.get("variants", ())) | {"offlmp", "1norm"}))
+        kw["variants"] = tuple(sorted(set(kw.get("variants", ())) | {"offlmp", "1norm"}))
         out.append((req, p, b, solver.Options(**kw)))
     return out
 
@@ -83,8 +81,9 @@ def test_served_requests_match_oracle():
         reqs.append((req, p, b, solver.Options(**kw)))
     served, _ = _serve(reqs, budget=8 << 30, slots=3)
     for (req, p, b, o), (x, r) in zip(reqs, served):
-        h = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, theta=0.02, rtol=1e-10,
-                                variants=pb.serving_method(req)["variants"])
+        m = pb.serving_method(req)
+        h = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, theta=0.02, rtol=m["rtol"],
+                                variants=m["variants"], cheb_boost=m["cheb_boost"])
         ref = h.solve(b)
         err = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"])
         log(f"[serving] {req['kind']} s={req['side']} its {r['iterations']} "
