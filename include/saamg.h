@@ -6,7 +6,7 @@
  * Algorithm 2), Cnstrnt (Sec. 2.4, Algorithm 3) and Sprsfy (Sec. 2.5).  Setup builds the
  * hierarchy of Sec. 1.1 (strength criterion, aggregates, tentative prolongator, prolongator
  * smoothing, Galerkin coarse operators); solve runs CG preconditioned by the V-cycle of
- * Algorithm 1 with the degree-2 Chebyshev smoother of Sec. 4.1.
+ * Algorithm 1 with the degree-2 Chebyshev smoother of Sec. 3.1.
  *
  * Conventions
  *  - Matrices are CSR: int32 row pointers (n+1) and column indices (nnz < 2^31), columns
@@ -39,7 +39,7 @@ typedef enum {
   SA_ERR_INVALID_ARG = -1,   /* bad argument, bad options, non-finite input               */
   SA_ERR_BAD_CSR = -2,       /* unsorted/duplicate/out-of-range column, missing diagonal  */
   SA_ERR_NONPOSITIVE_DIAG = -3, /* zero filtered diagonal (plain SA) or A_ii <= 0         */
-  SA_ERR_NEGATIVE_EIGENVALUE = -4, /* eigenvalue estimate <= 0 or not finite (Sec. 4.1)   */
+  SA_ERR_NEGATIVE_EIGENVALUE = -4, /* eigenvalue estimate <= 0 or not finite (Sec. 3.1)   */
   SA_ERR_COARSEN_STALLED = -5,     /* an aggregation did not reduce the size              */
   SA_ERR_COARSE_FACTOR = -6,       /* coarsest Cholesky pivot <= 0 or coarsest too large  */
   SA_ERR_OOM = -7,                 /* device allocation failed / over the memory budget   */
@@ -73,11 +73,11 @@ typedef struct {
   uint64_t seed;          /* counter-based generator seed (start vectors, hashed order)     */
   int32_t agg_order;      /* SA_AGG_NATURAL | SA_AGG_HASHED [natural]                       */
   int32_t max_levels;     /* [10]                                                           */
-  int32_t max_coarse;     /* coarsen until n <= max_coarse, Sec. 4.1 [1000]                 */
+  int32_t max_coarse;     /* coarsen until n <= max_coarse, Sec. 3.1 [1000]                 */
   int32_t smoother;       /* SA_CHEBYSHEV | SA_JACOBI [Chebyshev]                           */
-  int32_t degree;         /* smoother degree / sweeps, Sec. 4.1 [2]                         */
+  int32_t degree;         /* smoother degree / sweeps, Sec. 3.1 [2]                         */
   int32_t precision;      /* SA_FP64 | SA_FP32_VCYCLE [FP64]                                */
-  double cheb_ratio;      /* Chebyshev interval [lambda/ratio, lambda], Sec. 4.1 [10]       */
+  double cheb_ratio;      /* Chebyshev interval [lambda/ratio, lambda], Sec. 3.1 [10]       */
   double cheb_boost;      /* multiplier on the smoother eigenvalue estimate [1]             */
   double rtol;            /* CG stops when ||r|| <= rtol ||b|| (recurrence residual) [1e-8] */
   int32_t max_iter;       /* CG iteration cap [500]                                         */
@@ -108,7 +108,7 @@ typedef struct {
   double omega[16];         /* damping 4/(3 lambda), Sec. 1.1                              */
   double smoother_lambda[16];
   int32_t mis_rounds[16];   /* rounds of the parallel root selection per level             */
-  double operator_complexity; /* sum_l nnz(A_l) / nnz(A_1), Sec. 4.1                       */
+  double operator_complexity; /* sum_l nnz(A_l) / nnz(A_1), Sec. 3.1                       */
   int64_t device_bytes;     /* device memory held by the hierarchy                         */
   double setup_seconds;
 } sa_info;
@@ -179,7 +179,7 @@ void sa_destroy(sa_hierarchy *h);
  * request granularity: a slot is refilled as soon as its request completes).  Requests share
  * nothing but the GPU, and each runs exactly the code path of a standalone sa_setup +
  * sa_solve, so a request's x, iteration count and residual are bitwise the same alone or in
- * any mix.  The server serves the paper's use case of many SA-AMG solves (Sec. 4) on one
+ * any mix.  The server serves the paper's use case of many SA-AMG solves (Sec. 3) on one
  * device; it adds no numerical method of its own. */
 typedef struct sa_server sa_server;
 

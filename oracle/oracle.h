@@ -24,13 +24,13 @@ typedef struct {
   double theta;           /* strength threshold (Sec. 1.1, strength criterion)          */
   int32_t variants;       /* bit0 Sprsfy, bit1 OffLmp, bit2 1Norm, bit3 Cnstrnt           */
   int32_t one_norm_power; /* 0: use 1 for the 1Norm eigenvalue (Sec. 2.1); 1: power method */
-  double tau;             /* OffLmp ddom growth bound (Sec. 2.3), 1.1 in Sec. 4.1          */
+  double tau;             /* OffLmp ddom growth bound (Sec. 2.3), 1.1 in Sec. 3.1          */
   double sigma;           /* 1Norm safeguard root value (Sec. 2.2), 1/3                    */
   int32_t power_iters;    /* power-method steps for eigenvalue estimates, 10               */
   int32_t agg_order;      /* 0 natural vertex order, 1 hashed order                        */
   uint64_t seed;          /* seed of the counter-based generator                           */
   int32_t max_levels;     /* 10                                                            */
-  int32_t max_coarse;     /* stop coarsening at <= this many unknowns (Sec. 4.1), 1000      */
+  int32_t max_coarse;     /* stop coarsening at <= this many unknowns (Sec. 3.1), 1000      */
   int32_t smoother;       /* 0 Chebyshev, 1 Jacobi                                         */
   int32_t degree;         /* smoother degree / sweeps, 2                                   */
   double cheb_ratio;      /* Chebyshev interval [lambda/ratio, lambda], 10                 */

@@ -481,11 +481,11 @@ int diag(const Csr &Ab, bool one_norm, double sigma, std::vector<double> &invD) 
 }
 
 // ------------------------------------------------------------------------------------
-// Power method for the largest eigenvalue of invD*M (Sec. 1.1 damping; Sec. 4.1 uses 10
+// Power method for the largest eigenvalue of invD*M (Sec. 1.1 damping; Sec. 3.1 uses 10
 // power sweeps).  Reading: start x_i = 2u-1 with u in [0,1) the top 53 bits of splitmix64;
 // each step y = invD .* (M x) (row sums ascending, then the multiply); the estimate is the
 // Rayleigh quotient (x.y)/(x.x) of the last step, which can come out negative (the failure
-// mode reported in Sec. 4.1); iterates are rescaled by an exact power of two,
+// mode reported in Sec. 3.1); iterates are rescaled by an exact power of two,
 // x = y * 2^(-ilogb(max|y_i|)).
 // ------------------------------------------------------------------------------------
 int power_method(const Csr &M, const std::vector<double> &invD, int iters, uint64_t seed,
@@ -703,7 +703,7 @@ struct Hier {
 };
 
 // Dense Cholesky of the coarsest operator, textbook order: L_jj = sqrt(A_jj - sum_k<j L_jk^2),
-// L_ij = (A_ij - sum_k<j L_ik L_jk)/L_jj, sums ascending in k (Sec. 4.1: direct solve on
+// L_ij = (A_ij - sum_k<j L_ik L_jk)/L_jj, sums ascending in k (Sec. 3.1: direct solve on
 // the coarsest level).
 int cholesky(const Csr &A, std::vector<double> &L) {
   int n = A.nr;
@@ -877,7 +877,7 @@ int orc_setup(int32_t n, const int32_t *rp, const int32_t *col, const double *va
     H->lv[l + 1].A = std::move(Ac);
     H->lv[l + 1].As = H->lv[l + 1].A;
   }
-  // Smoothers on every level but the coarsest (Sec. 4.1: Chebyshev of degree 2 on
+  // Smoothers on every level but the coarsest (Sec. 3.1: Chebyshev of degree 2 on
   // [lambda/10, lambda], lambda from 10 power sweeps on invD*A).
   int nl = (int)H->lv.size();
   for (int l = 0; l + 1 < nl; ++l) {
@@ -971,7 +971,7 @@ int orc_export(const void *h, int l, int what, void *buf) {
 namespace {
 
 // ------------------------------------------------------------------------------------
-// Smoothers (Sec. 4.1: degree-2 Chebyshev on [lambda/10, lambda]; Jacobi is an option).
+// Smoothers (Sec. 3.1: degree-2 Chebyshev on [lambda/10, lambda]; Jacobi is an option).
 // Chebyshev semi-iteration in invD*A with theta_c = (lam + lam/ratio)/2,
 // delta_c = (lam - lam/ratio)/2, sigma1 = theta_c/delta_c:
 //   r = f - A u (r = f when u = 0), rho = 1/sigma1, d = (invD.*r)/theta_c;
@@ -1060,7 +1060,7 @@ int orc_vcycle(const void *h, const double *f, double *u) {
   return ST_OK;
 }
 
-// Preconditioned CG (Sec. 4.1-4.3 use CG with the multigrid preconditioner).  Readings:
+// Preconditioned CG (Sec. 3.1-3.3 use CG with the multigrid preconditioner).  Readings:
 // x0 = 0; the recurrence residual is tested, dot(r,r) <= (rtol*rtol)*dot(b,b); iteration
 // count = k at the first pass; beta Fletcher-Reeves (rho'/rho) or flexible Polak-Ribiere
 // (dot(r, z - z_old)/rho).

@@ -1,4 +1,4 @@
-// Coarsest level (Sec. 4.1: a direct solve once the hierarchy reaches <= 1000 unknowns):
+// Coarsest level (Sec. 3.1: a direct solve once the hierarchy reaches <= 1000 unknowns):
 // dense Cholesky A_L = L L^T in one workgroup, L^{-1} by forward substitution (one column per
 // thread), and A_L^{-1} = L^{-T} L^{-1} on the FP64 matrix cores (v_mfma_f64_16x16x4f64).
 // The V-cycle then applies A_L^{-1} as a dense GEMV.  The factor's rounding order differs

@@ -1,5 +1,5 @@
 // Host runtime and C ABI: hierarchy setup (Sec. 1.1 with the adaptations of Sec. 2), the
-// V-cycle of Algorithm 1 with Chebyshev/Jacobi smoothing (Sec. 4.1), and preconditioned CG.
+// V-cycle of Algorithm 1 with Chebyshev/Jacobi smoothing (Sec. 3.1), and preconditioned CG.
 //
 // Control crosses to the host only at size readbacks (aggregate count, nnz of each new
 // matrix), the root-selection termination flags, error checks, and once per CG iteration

@@ -1080,7 +1080,7 @@ int64_t lump(int32_t n, const int32_t *rp, const int32_t *col, const double *val
   return abar.nnz;
 }
 
-// ---- power method (Sec. 1.1 damping; Sec. 4.1 ten sweeps) --------------------------------
+// ---- power method (Sec. 1.1 damping; Sec. 3.1 ten sweeps) --------------------------------
 __global__ void k_power_init(int32_t n, uint64_t seed, int32_t level, int32_t stream,
                              double *x) {
   SA_ROW_KERNEL_BEGIN(n)

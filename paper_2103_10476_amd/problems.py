@@ -10,15 +10,15 @@ eliminated: only interior unknowns are kept, and couplings to boundary nodes con
 the diagonal only.
 
 Problem families (the paper's test families are FE cubes with stretched or perturbed
-meshes, a heterogeneous reservoir model and wind-turbine pressure systems, Sec. 4; none of
+meshes, a heterogeneous reservoir model and wind-turbine pressure systems, Sec. 3; none of
 their meshes or data are available, so these are synthetic stand-ins of the same character):
 
 * ``fd5_stretched``  2-D 5-point finite-volume Laplacian, y spacing graded geometrically.
 * ``fd7_stretched``  3-D 7-point finite-volume Laplacian, z spacing graded geometrically
-  (the character of the stretched cube of Sec. 4.2 and the stretched wind meshes of Sec. 4.4).
+  (the character of the stretched cube of Sec. 3.2 and the stretched wind meshes of Sec. 3.4).
 * ``q1_hex``         3-D 27-point trilinear (Q1) hexahedral stiffness matrix on a tensor mesh
   with per-element coefficient kappa (the 27-point stencil of Sec. 1.2; random kappa over six
-  decades stands in for the heterogeneous permeability of Sec. 4.3).
+  decades stands in for the heterogeneous permeability of Sec. 3.3).
 * ``periodic_*``     small periodic stencils used by the tests (circulant examples of Sec. 2.1).
 """
 from __future__ import annotations

@@ -239,7 +239,7 @@ def test_sprsfy_keeps_multiple_links(orc):
 
 
 def test_sprsfy_reduces_coarse_nnz(orc):
-    """Sec. 4.1/4.3: Sprsfy lowers operator complexity."""
+    """Sec. 3.1/3.3: Sprsfy lowers operator complexity."""
     p = pb.workload("fd7_16_a1000")
     h0 = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, theta=0.02, max_coarse=50)
     h1 = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, theta=0.02, max_coarse=50,

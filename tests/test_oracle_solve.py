@@ -2,7 +2,7 @@
 inner-product convention.
 
 Sources: Sec. 1.1 (Galerkin coarse operator; Algorithm 1 V-cycle), Sec. 2.5 (coarse fill-in
-pattern), Sec. 4.1 (Chebyshev degree 2 on [lambda/10, lambda]; direct coarse solve; CG).
+pattern), Sec. 3.1 (Chebyshev degree 2 on [lambda/10, lambda]; direct coarse solve; CG).
 """
 import math
 from fractions import Fraction
@@ -145,7 +145,7 @@ def test_two_level_error_propagator(orc, smoother):
 
 
 def test_single_level_is_direct_solve(orc):
-    """n <= max_coarse: the V-cycle is the dense direct solve (Sec. 4.1)."""
+    """n <= max_coarse: the V-cycle is the dense direct solve (Sec. 3.1)."""
     p = pb.workload("fd5_16x16_a100")
     h = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, max_coarse=1000)
     assert len(h.levels) == 1
@@ -179,7 +179,7 @@ def _dense_pcg(A, M, b, rtol, max_iter):
 
 @pytest.mark.parametrize("name", ["fd5_16x16_a100", "fd7_8_a1000"])
 def test_pcg_matches_dense_pcg(orc, name):
-    """CG preconditioned by the V-cycle (Sec. 4.1): the same iteration count as dense CG with
+    """CG preconditioned by the V-cycle (Sec. 3.1): the same iteration count as dense CG with
     the V-cycle as an explicit matrix, and the true residual meets the tolerance."""
     p = pb.workload(name)
     h = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, theta=0.02, max_coarse=20, rtol=1e-10)
