@@ -144,6 +144,20 @@ sa_status sa_setup(const sa_context *ctx, const sa_csr *A, const double *nullspa
 sa_status sa_solve(sa_hierarchy *h, const double *b, double *x, sa_location loc,
                    int32_t *iterations, double *rel_residual);
 
+/* Solves count systems A_k x_k = b_k, each on its own hierarchy hs[k], in lockstep: each CG
+ * iteration of every still-running system is advanced by grouped launches (one launch per
+ * step for all systems: V-cycle levels, inner products, updates) on hs[0]'s stream.  Each
+ * system's arithmetic is exactly that of sa_solve on it alone, so x[k], iterations[k] and
+ * rel_residual[k] equal what sa_solve returns for it.  b[k], x[k]: n_k-vectors in `loc`
+ * memory.  status[k] receives each system's status (SA_OK, SA_NOT_CONVERGED or an error,
+ * with x[k] unspecified on SA_ERR_BREAKDOWN); iterations and rel_residual may be NULL.
+ * The hierarchies must be distinct and not in use by another call.  Returns SA_OK when
+ * every system was run (whatever their statuses), otherwise SA_ERR_INVALID_ARG, SA_ERR_OOM or
+ * SA_ERR_HIP. */
+sa_status sa_solve_many(sa_hierarchy *const *hs, int32_t count, const double *const *b,
+                        double *const *x, sa_location loc, int32_t *iterations,
+                        double *rel_residual, sa_status *status);
+
 /* Applies one V-cycle z = M^{-1} f (f, z device vectors of the fine size). */
 sa_status sa_vcycle(sa_hierarchy *h, const double *f, double *z);
 

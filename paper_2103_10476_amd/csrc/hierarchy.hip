@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "kernels.hpp"
+#include "hierarchy.hpp"
 
 namespace sa {
 
@@ -27,65 +27,6 @@ enum ErrBits {
   E_DIAG = 32,
   E_CHOL = 64
 };
-
-constexpr int32_t kMaxDense = 8192;
-
-struct Level {
-  Csr A;                  // operator of this level
-  Csr As;                 // matrix the prolongator is built from (A, or D_B A D_B on level 0)
-  uint8_t *mask = nullptr;
-  int32_t *agg = nullptr;
-  uint8_t *is_root = nullptr;
-  int32_t nc = 0;
-  int32_t mis_rounds = 0;
-  Csr Abar;
-  double *invD = nullptr;
-  double *lam_d = nullptr, *omega_d = nullptr;
-  double lam = 0.0, omega = 0.0;
-  Csr P, R;
-  double *sm_invD = nullptr;
-  double *sm_lam_d = nullptr;
-  double sm_lam = 0.0;
-  double cheb_theta = 0.0;
-  std::vector<double> cheb_c1, cheb_c2;  // per Chebyshev step m = 1..deg-1
-  double jac_w = 0.0;
-  double *Ainv = nullptr;  // coarsest only: dense inverse, row-major
-  // FP32 copies (FP32 V-cycle)
-  float *Af = nullptr, *Pf = nullptr, *Rf = nullptr, *sm_invDf = nullptr;
-  // work vectors
-  double *f = nullptr, *u = nullptr, *r = nullptr, *d1 = nullptr, *d2 = nullptr;
-  float *ff = nullptr, *uf = nullptr, *rf = nullptr, *d1f = nullptr, *d2f = nullptr;
-};
-
-}  // namespace sa
-
-struct sa_hierarchy {
-  hipStream_t stream = nullptr;
-  sa_options opt{};
-  sa::Arena ar;
-  std::vector<sa::Level> lv;
-  int32_t *err = nullptr;
-  double setup_seconds = 0.0;
-  // solve workspace
-  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *zold = nullptr,
-         *w = nullptr, *dws = nullptr, *tmp64 = nullptr;
-  sa::PcgScalars *S = nullptr;
-  sa::PcgScalars *hS = nullptr;  // pinned host mirror
-  int32_t n = 0;
-  // fine-level SpMV timing (sa_profile_enable)
-  bool prof = false;
-  std::vector<hipEvent_t> ev;   // event pool, pairs (start, stop)
-  std::vector<double> ev_bytes; // algorithmic bytes of each recorded pair
-  int32_t nev = 0;
-  int64_t prof_launches = 0;
-  double prof_ms = 0.0, prof_bytes = 0.0;
-  ~sa_hierarchy() {
-    if (hS) (void)hipHostFree(hS);
-    for (auto e : ev) (void)hipEventDestroy(e);
-  }
-};
-
-namespace sa {
 
 static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())

@@ -1,0 +1,221 @@
+// Device-side bodies of the solve-phase kernels (internal).
+//
+// Every solve kernel exists twice: a standalone launch over one vector or matrix
+// (solve_kernels.hip) and a grouped launch over a table of segments, one per hierarchy
+// (solve_batch.hip).  Both call the functions below with the segment's own arguments, so a
+// hierarchy's arithmetic is the same whichever way its work was launched.
+#pragma once
+#include "kernels.hpp"
+
+namespace sa {
+
+template <class T>
+struct Chunk {
+  static constexpr int value = sizeof(T) == 8 ? 2048 : 4096;
+};
+
+constexpr int32_t kPlanWindow = 2048;  // cost units per SpMV block
+constexpr int32_t kPlanRowCost = 8;     // cost of a row besides its entries
+
+// Workgroups are handed to the 8 XCDs round-robin (workgroup b runs on XCD b mod 8), and
+// each XCD has its own L2.  Renumbering so that XCD x takes one contiguous run of row blocks
+// keeps the x entries a block gathers from neighbouring rows (stencil planes) in that XCD's
+// L2 instead of fetching them once per XCD.  A bijection on [0, nb).
+__device__ __forceinline__ int32_t xcd_block(uint32_t b, uint32_t nb) {
+  constexpr uint32_t kXcd = 8;
+  const uint32_t q = nb / kXcd, r = nb % kXcd;
+  const uint32_t x = b % kXcd, k = b / kXcd;
+  return (int32_t)(x * q + (x < r ? x : r) + k);
+}
+
+// One SpMV row block b (rows bstart[b] .. bstart[b+1]-1): the block streams the rows' entries
+// through LDS in coalesced chunks, forming each product val*x[col] once; then every thread
+// adds the products of its own row in ascending column order, starting from 0, and hands the
+// sum to the epilogue.  The sum order is the sequential row sum's.
+template <class T, class Epi>
+__device__ __forceinline__ void spmv_block(int32_t b, const int32_t *__restrict__ bstart,
+                                           const int32_t *__restrict__ rp,
+                                           const int32_t *__restrict__ col,
+                                           const T *__restrict__ val,
+                                           const T *__restrict__ x, const Epi &epi,
+                                           T *prod) {
+  constexpr int CH = Chunk<T>::value;
+  const int t = threadIdx.x;
+  const int32_t r0 = bstart[b], r1 = bstart[b + 1];
+  if (r0 >= r1) return;  // block-uniform
+  const int32_t row = r0 + t;
+  const int32_t e0 = rp[r0], e1 = rp[r1];
+  int32_t mb = 0, me = 0;
+  if (row < r1) {
+    mb = rp[row];
+    me = rp[row + 1];
+  }
+  T s = T(0);
+  for (int32_t c0 = e0; c0 < e1; c0 += CH) {
+    const int32_t c1 = min(c0 + CH, e1);
+#pragma unroll 8
+    for (int32_t e = c0 + t; e < c1; e += kBlock) prod[e - c0] = val[e] * x[col[e]];
+    __syncthreads();
+    // in-order sum of the row's products in this chunk; loads are issued 8 at a time ahead
+    // of the (sequential) adds so long rows are bound by the add chain, not LDS latency
+    int32_t e = max(mb, c0);
+    const int32_t en = min(me, c1);
+    for (; e + 8 <= en; e += 8) {
+      T v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = prod[e - c0 + q];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += v[q];
+    }
+    for (; e < en; ++e) s += prod[e - c0];
+    __syncthreads();
+  }
+  if (row < r1) epi(row, s);
+}
+
+// ---- fused SpMV epilogues: row i receives s = (A x)_i -------------------------------------
+template <class T>
+struct EpStore {
+  T *y;
+  __device__ void operator()(int32_t i, T s) const { y[i] = s; }
+};
+template <class T>
+struct EpScale {
+  const T *d;
+  T *y;
+  __device__ void operator()(int32_t i, T s) const { y[i] = d[i] * s; }
+};
+template <class T>
+struct EpResid {
+  const T *f;
+  T *r;
+  __device__ void operator()(int32_t i, T s) const { r[i] = f[i] - s; }
+};
+template <class T>
+struct EpAdd {
+  T *u;
+  __device__ void operator()(int32_t i, T s) const { u[i] = u[i] + s; }
+};
+template <class T>
+struct EpChebStart {
+  const T *f, *invD;
+  T theta;
+  T *r, *d;
+  __device__ void operator()(int32_t i, T s) const {
+    T ri = f[i] - s;
+    r[i] = ri;
+    d[i] = (invD[i] * ri) / theta;
+  }
+};
+template <class T>
+struct EpChebStep {
+  const T *d, *rin, *invD;
+  T *rout, *u, *dout;
+  T c1, c2;
+  bool uzero, last;
+  __device__ void operator()(int32_t i, T s) const {
+    T di = d[i];
+    T ui = (uzero ? T(0) : u[i]) + di;
+    T ri = rin[i] - s;
+    rout[i] = ri;
+    T dn = c1 * di + c2 * (invD[i] * ri);
+    if (last) {
+      u[i] = ui + dn;
+    } else {
+      u[i] = ui;
+      dout[i] = dn;
+    }
+  }
+};
+template <class T>
+struct EpJacobi {
+  const T *u, *f, *invD;
+  T w;
+  T *u2;
+  __device__ void operator()(int32_t i, T s) const {
+    T r = f[i] - s;
+    u2[i] = u[i] + w * (invD[i] * r);
+  }
+};
+
+// ---- element-wise bodies -----------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void cheb_first_at(int32_t i, const T *f, const T *invD, T theta,
+                                              T *d, T *u, bool write_u) {
+  T di = (invD[i] * f[i]) / theta;
+  d[i] = di;
+  if (write_u) u[i] = T(0) + di;
+}
+template <class T>
+__device__ __forceinline__ void vec_add_at(int32_t i, T *u, const T *d) {
+  u[i] = u[i] + d[i];
+}
+template <class T>
+__device__ __forceinline__ void jacobi_first_at(int32_t i, const T *f, const T *invD, T w,
+                                                T *u) {
+  u[i] = T(0) + w * (invD[i] * f[i]);
+}
+__device__ __forceinline__ void update_xr_at(int32_t i, double *x, double *r, const double *p,
+                                             const double *q, double a) {
+  x[i] = x[i] + a * p[i];
+  r[i] = r[i] - a * q[i];
+}
+__device__ __forceinline__ void update_p_at(int32_t i, double *p, const double *z, double beta) {
+  p[i] = z[i] + beta * p[i];
+}
+__device__ __forceinline__ void vec_sub_at(int32_t i, const double *z, const double *zo,
+                                           double *w) {
+  w[i] = z[i] - zo[i];
+}
+
+// ---- canonical inner product: one block of 4096 terms --------------------------------------
+// Lane t of 256 sums terms t + 256 m (m = 0..15) sequentially from 0 (products x[i]*y[i], or
+// x[i] alone when y is null), then s[t] += s[t + w] for w = 128 ... 1.
+__device__ __forceinline__ void dot_block(int64_t blk, const double *__restrict__ x,
+                                          const double *__restrict__ y, int64_t n,
+                                          double *__restrict__ out, double *sh) {
+  const int t = threadIdx.x;
+  const int64_t base = blk * 4096 + t;
+  double acc = 0.0;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    int64_t i = base + 256 * m;
+    if (i < n) acc += (y ? x[i] * y[i] : x[i]);
+  }
+  sh[t] = acc;
+  __syncthreads();
+  for (int w = kBlock / 2; w >= 1; w >>= 1) {
+    if (t < w) sh[t] = sh[t] + sh[t + w];
+    __syncthreads();
+  }
+  if (t == 0) *out = sh[0];
+}
+
+// ---- dense GEMV row (coarsest level): one wavefront per row --------------------------------
+__device__ __forceinline__ void gemv_row(int64_t row, int32_t n, const double *__restrict__ M,
+                                         const double *__restrict__ x,
+                                         double *__restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const double *m = M + row * n;
+  double acc = 0.0;
+  for (int32_t j = lane; j < n; j += 64) acc += m[j] * x[j];
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) y[row] = acc;
+}
+
+// ---- PCG scalar steps ------------------------------------------------------------------------
+__device__ __forceinline__ void pcg_alpha_on(PcgScalars *S) {
+  if (!(S->pq > 0.0)) S->err = 1;
+  S->alpha = S->rho / S->pq;
+}
+__device__ __forceinline__ void pcg_beta_on(PcgScalars *S, bool pr) {
+  if (!(S->rho1 > 0.0)) S->err = 2;
+  S->beta = (pr ? S->rw : S->rho1) / S->rho;
+  S->rho = S->rho1;
+}
+__device__ __forceinline__ void pcg_init_on(PcgScalars *S) {
+  if (!(S->rho1 > 0.0)) S->err = 2;
+  S->rho = S->rho1;
+}
+
+}  // namespace sa

@@ -6,28 +6,9 @@
 // every thread adds the products of its own row in ascending column order.  The sum order
 // equals the sequential row sum, so results are bit-identical to it, while the global loads
 // stay fully coalesced (HBM-bound: ~12 B/entry for FP64, ~8 B/entry for FP32).
-#include "kernels.hpp"
+#include "solve_device.hpp"
 
 namespace sa {
-
-template <class T>
-struct Chunk {
-  static constexpr int value = sizeof(T) == 8 ? 2048 : 4096;
-};
-
-constexpr int32_t kPlanWindow = 2048;  // cost units per SpMV block
-constexpr int32_t kPlanRowCost = 8;     // cost of a row besides its entries
-
-// Workgroups are handed to the 8 XCDs round-robin (workgroup b runs on XCD b mod 8), and
-// each XCD has its own L2.  Renumbering so that XCD x takes one contiguous run of row blocks
-// keeps the x entries a block gathers from neighbouring rows (stencil planes) in that XCD's
-// L2 instead of fetching them once per XCD.  A bijection on [0, nb).
-__device__ __forceinline__ int32_t xcd_block(uint32_t b, uint32_t nb) {
-  constexpr uint32_t kXcd = 8;
-  const uint32_t q = nb / kXcd, r = nb % kXcd;
-  const uint32_t x = b % kXcd, k = b / kXcd;
-  return (int32_t)(x * q + (x < r ? x : r) + k);
-}
 
 template <class T, class Epi>
 __global__ __launch_bounds__(kBlock) void k_spmv(const int32_t *__restrict__ bstart,
@@ -35,40 +16,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int32_t *__restrict__ bst
                                                  const int32_t *__restrict__ col,
                                                  const T *__restrict__ val,
                                                  const T *__restrict__ x, Epi epi) {
-  constexpr int CH = Chunk<T>::value;
-  __shared__ T prod[CH];
-  const int t = threadIdx.x;
-  const int32_t b = xcd_block(blockIdx.x, gridDim.x);
-  const int32_t r0 = bstart[b], r1 = bstart[b + 1];
-  if (r0 >= r1) return;  // block-uniform
-  const int32_t row = r0 + t;
-  const int32_t e0 = rp[r0], e1 = rp[r1];
-  int32_t mb = 0, me = 0;
-  if (row < r1) {
-    mb = rp[row];
-    me = rp[row + 1];
-  }
-  T s = T(0);
-  for (int32_t c0 = e0; c0 < e1; c0 += CH) {
-    const int32_t c1 = min(c0 + CH, e1);
-#pragma unroll 8
-    for (int32_t e = c0 + t; e < c1; e += kBlock) prod[e - c0] = val[e] * x[col[e]];
-    __syncthreads();
-    // in-order sum of the row's products in this chunk; loads are issued 8 at a time ahead
-    // of the (sequential) adds so long rows are bound by the add chain, not LDS latency
-    int32_t e = max(mb, c0);
-    const int32_t en = min(me, c1);
-    for (; e + 8 <= en; e += 8) {
-      T v[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = prod[e - c0 + q];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) s += v[q];
-    }
-    for (; e < en; ++e) s += prod[e - c0];
-    __syncthreads();
-  }
-  if (row < r1) epi(row, s);
+  __shared__ T prod[Chunk<T>::value];
+  spmv_block<T, Epi>(xcd_block(blockIdx.x, gridDim.x), bstart, rp, col, val, x, epi, prod);
 }
 
 __global__ void k_spmv_plan(int32_t n, const int32_t *rp, int32_t nblk, int32_t *bstart) {
@@ -95,70 +44,6 @@ void spmv_plan(Csr &A, Arena &ar, hipStream_t s) {
   k_spmv_plan<<<grid_for(A.nblk + 1), kBlock, 0, s>>>(A.n, A.rp, A.nblk, A.bstart);
   SA_LAUNCH_CHECK();
 }
-
-template <class T>
-struct EpStore {
-  T *y;
-  __device__ void operator()(int32_t i, T s) const { y[i] = s; }
-};
-template <class T>
-struct EpScale {
-  const T *d;
-  T *y;
-  __device__ void operator()(int32_t i, T s) const { y[i] = d[i] * s; }
-};
-template <class T>
-struct EpResid {
-  const T *f;
-  T *r;
-  __device__ void operator()(int32_t i, T s) const { r[i] = f[i] - s; }
-};
-template <class T>
-struct EpAdd {
-  T *u;
-  __device__ void operator()(int32_t i, T s) const { u[i] = u[i] + s; }
-};
-template <class T>
-struct EpChebStart {
-  const T *f, *invD;
-  T theta;
-  T *r, *d;
-  __device__ void operator()(int32_t i, T s) const {
-    T ri = f[i] - s;
-    r[i] = ri;
-    d[i] = (invD[i] * ri) / theta;
-  }
-};
-template <class T>
-struct EpChebStep {
-  const T *d, *rin, *invD;
-  T *rout, *u, *dout;
-  T c1, c2;
-  bool uzero, last;
-  __device__ void operator()(int32_t i, T s) const {
-    T di = d[i];
-    T ui = (uzero ? T(0) : u[i]) + di;
-    T ri = rin[i] - s;
-    rout[i] = ri;
-    T dn = c1 * di + c2 * (invD[i] * ri);
-    if (last) {
-      u[i] = ui + dn;
-    } else {
-      u[i] = ui;
-      dout[i] = dn;
-    }
-  }
-};
-template <class T>
-struct EpJacobi {
-  const T *u, *f, *invD;
-  T w;
-  T *u2;
-  __device__ void operator()(int32_t i, T s) const {
-    T r = f[i] - s;
-    u2[i] = u[i] + w * (invD[i] * r);
-  }
-};
 
 template <class T, class Epi>
 static void launch_spmv(const SpmvArgs<T> &a, const Epi &epi, hipStream_t s) {
@@ -216,10 +101,7 @@ template <class T>
 __global__ void k_cheb_first(int32_t n, const T *f, const T *invD, T theta, T *d, T *u,
                              bool write_u) {
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  T di = (invD[i] * f[i]) / theta;
-  d[i] = di;
-  if (write_u) u[i] = T(0) + di;
+  if (i < n) cheb_first_at<T>(i, f, invD, theta, d, u, write_u);
 }
 template <class T>
 void cheb_first(int32_t n, const T *f, const T *invD, T theta, T *d, T *u, bool write_u,
@@ -231,7 +113,7 @@ void cheb_first(int32_t n, const T *f, const T *invD, T theta, T *d, T *u, bool 
 template <class T>
 __global__ void k_vec_add(int32_t n, T *u, const T *d) {
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) u[i] = u[i] + d[i];
+  if (i < n) vec_add_at<T>(i, u, d);
 }
 template <class T>
 void vec_add(int32_t n, T *u, const T *d, hipStream_t s) {
@@ -242,7 +124,7 @@ void vec_add(int32_t n, T *u, const T *d, hipStream_t s) {
 template <class T>
 __global__ void k_jacobi_first(int32_t n, const T *f, const T *invD, T w, T *u) {
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) u[i] = T(0) + w * (invD[i] * f[i]);
+  if (i < n) jacobi_first_at<T>(i, f, invD, w, u);
 }
 template <class T>
 void jacobi_first(int32_t n, const T *f, const T *invD, T w, T *u, hipStream_t s) {
@@ -283,21 +165,7 @@ __global__ __launch_bounds__(kBlock) void k_dot_stage(const double *__restrict__
                                                       const double *__restrict__ y,
                                                       int64_t n, double *__restrict__ part) {
   __shared__ double sh[kBlock];
-  const int t = threadIdx.x;
-  const int64_t base = (int64_t)blockIdx.x * 4096 + t;
-  double acc = 0.0;
-#pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    int64_t i = base + 256 * m;
-    if (i < n) acc += (y ? x[i] * y[i] : x[i]);
-  }
-  sh[t] = acc;
-  __syncthreads();
-  for (int w = kBlock / 2; w >= 1; w >>= 1) {
-    if (t < w) sh[t] = sh[t] + sh[t + w];
-    __syncthreads();
-  }
-  if (t == 0) part[blockIdx.x] = sh[0];
+  dot_block(blockIdx.x, x, y, n, part + blockIdx.x, sh);
 }
 
 int64_t dot_ws_size(int64_t n) {
@@ -336,14 +204,8 @@ void dot_f64(const double *x, const double *y, int64_t n, double *res, double *w
 __global__ __launch_bounds__(kBlock) void k_gemv(int32_t n, const double *__restrict__ M,
                                                  const double *__restrict__ x,
                                                  double *__restrict__ y) {
-  const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  if (row >= n) return;
-  const double *m = M + row * n;
-  double acc = 0.0;
-  for (int32_t j = lane; j < n; j += 64) acc += m[j] * x[j];
-  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) y[row] = acc;
+  if (row < n) gemv_row(row, n, M, x, y);
 }
 void gemv_f64(int32_t n, const double *M, const double *x, double *y, hipStream_t s) {
   if (n <= 0) return;
@@ -355,10 +217,7 @@ void gemv_f64(int32_t n, const double *M, const double *x, double *y, hipStream_
 __global__ void k_update_xr(int32_t n, double *x, double *r, const double *p, const double *q,
                             const PcgScalars *S) {
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double a = S->alpha;
-  x[i] = x[i] + a * p[i];
-  r[i] = r[i] - a * q[i];
+  if (i < n) update_xr_at(i, x, r, p, q, S->alpha);
 }
 void pcg_update_xr(int32_t n, double *x, double *r, const double *p, const double *q,
                    const PcgScalars *S, hipStream_t s) {
@@ -367,7 +226,7 @@ void pcg_update_xr(int32_t n, double *x, double *r, const double *p, const doubl
 }
 __global__ void k_update_p(int32_t n, double *p, const double *z, const PcgScalars *S) {
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = z[i] + S->beta * p[i];
+  if (i < n) update_p_at(i, p, z, S->beta);
 }
 void pcg_update_p(int32_t n, double *p, const double *z, const PcgScalars *S, hipStream_t s) {
   k_update_p<<<grid_for(n), kBlock, 0, s>>>(n, p, z, S);
@@ -375,33 +234,23 @@ void pcg_update_p(int32_t n, double *p, const double *z, const PcgScalars *S, hi
 }
 __global__ void k_vec_sub(int32_t n, const double *z, const double *zo, double *w) {
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) w[i] = z[i] - zo[i];
+  if (i < n) vec_sub_at(i, z, zo, w);
 }
 void vec_sub(int32_t n, const double *z, const double *zold, double *w, hipStream_t s) {
   k_vec_sub<<<grid_for(n), kBlock, 0, s>>>(n, z, zold, w);
   SA_LAUNCH_CHECK();
 }
-__global__ void k_pcg_alpha(PcgScalars *S) {
-  if (!(S->pq > 0.0)) S->err = 1;
-  S->alpha = S->rho / S->pq;
-}
+__global__ void k_pcg_alpha(PcgScalars *S) { pcg_alpha_on(S); }
 void pcg_alpha(PcgScalars *S, hipStream_t s) {
   k_pcg_alpha<<<1, 1, 0, s>>>(S);
   SA_LAUNCH_CHECK();
 }
-__global__ void k_pcg_beta(PcgScalars *S, bool pr) {
-  if (!(S->rho1 > 0.0)) S->err = 2;
-  S->beta = (pr ? S->rw : S->rho1) / S->rho;
-  S->rho = S->rho1;
-}
+__global__ void k_pcg_beta(PcgScalars *S, bool pr) { pcg_beta_on(S, pr); }
 void pcg_beta(PcgScalars *S, bool pr, hipStream_t s) {
   k_pcg_beta<<<1, 1, 0, s>>>(S, pr);
   SA_LAUNCH_CHECK();
 }
-__global__ void k_pcg_init(PcgScalars *S) {
-  if (!(S->rho1 > 0.0)) S->err = 2;
-  S->rho = S->rho1;
-}
+__global__ void k_pcg_init(PcgScalars *S) { pcg_init_on(S); }
 void pcg_init_rho(PcgScalars *S, hipStream_t s) {
   k_pcg_init<<<1, 1, 0, s>>>(S);
   SA_LAUNCH_CHECK();

@@ -194,6 +194,25 @@ class Hierarchy:
             pass
 
 
+def solve_many(hierarchies, rhs):
+    """Solves every (hierarchy, b) pair in lockstep (sa_solve_many): one grouped launch per
+    CG/V-cycle step for all of them.  Returns a list of (x, iterations, rel_residual, status),
+    each equal to what Hierarchy.solve gives for that system alone."""
+    torch = _torch()
+    k = len(hierarchies)
+    bs = [_dev(b, torch.float64) for b in rhs]
+    xs = [torch.empty(h.n, dtype=torch.float64, device="cuda") for h in hierarchies]
+    H = (C.c_void_p * k)(*[h._h.value for h in hierarchies])
+    B = (C.c_void_p * k)(*[b.data_ptr() for b in bs])
+    X = (C.c_void_p * k)(*[x.data_ptr() for x in xs])
+    its = (C.c_int32 * k)()
+    rr = (C.c_double * k)()
+    st = (C.c_int * k)()
+    _lib.check(_lib.lib().sa_solve_many(H, k, B, X, _lib.SA_DEVICE, its, rr, st),
+               "sa_solve_many")
+    return [(xs[i], its[i], rr[i], _lib.STATUS_NAMES[st[i]]) for i in range(k)]
+
+
 def estimate_bytes(n: int, nnz: int) -> int:
     """Device bytes a serving request is charged at admission (sa_estimate_bytes)."""
     return int(_lib.lib().sa_estimate_bytes(int(n), int(nnz)))
