@@ -393,6 +393,8 @@ def _serve_run(solver, problems, reqs, built, budget, slots, arrivals=None):
             "iterations": {"p50": pct(its, 50), "max": int(max(its))},
             "budget_bytes": budget, "peak_reserved_bytes": st["peak_reserved_bytes"],
             "peak_measured_bytes": st["peak_measured_bytes"],
+            "solve_ticks": st["solve_ticks"], "mean_requests_per_tick": round(st["mean_group"], 2),
+            "max_requests_per_tick": st["max_group"],
             "max_peak_over_estimate": round(worst[0], 3), "max_peak_request": worst[1]}
 
 
@@ -401,7 +403,9 @@ def serving_leg(solver, problems, args):
     27-point random-kappa cubes, side 16..96), FP32 V-cycle in FP64 CG to 1e-10, on one GPU
     with `slots` concurrent requests under an HBM budget.  Closed loop (all submitted at
     t=0) gives the throughput; open loop runs use Poisson arrivals at the given fractions of
-    it; a final closed-loop run uses a budget of 1.5 times the largest request's estimate."""
+    it; a final closed-loop run uses a budget of 1.5 times the largest request's estimate.
+    Setups overlap on `slots` streams; the solves of all set-up requests advance together,
+    one grouped launch per CG/V-cycle step per tick."""
     t = time.perf_counter()
     reqs, built = _build_requests(problems, args.serving_requests)
     log(f"[bench] serving: {len(reqs)} requests built in {time.perf_counter() - t:.1f} s")

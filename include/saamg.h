@@ -185,16 +185,21 @@ sa_status sa_profile_read(const sa_hierarchy *h, int64_t *launches, double *ms, 
 void sa_destroy(sa_hierarchy *h);
 
 /* ---- serving: many independent setup + solve requests on one GPU ------------------------
- * A server owns max_slots worker threads, each with its own HIP stream (default priority).
- * Requests are admitted in submission order (FIFO) while the sum of the admitted requests'
- * device-byte estimates (sa_estimate_bytes) stays within hbm_budget; an admitted request runs
- * sa_setup + sa_solve on its slot's stream, its result is copied to host memory and all its
- * device memory is released before the next request takes the slot (continuous batching at
- * request granularity: a slot is refilled as soon as its request completes).  Requests share
- * nothing but the GPU, and each runs exactly the code path of a standalone sa_setup +
- * sa_solve, so a request's x, iteration count and residual are bitwise the same alone or in
- * any mix.  The server serves the paper's use case of many SA-AMG solves (Sec. 3) on one
- * device; it adds no numerical method of its own. */
+ * A server owns max_slots setup workers, each a host thread with its own HIP stream (default
+ * priority), and one solve batcher with its own stream.  Requests are admitted in submission
+ * order (FIFO) while the sum of the admitted requests' device-byte estimates
+ * (sa_estimate_bytes) stays within hbm_budget.  An admitted request runs sa_setup on a free
+ * slot's stream (up to max_slots setups overlap on the GPU), then joins the solve group: each
+ * tick of the batcher advances every request in the group by one CG iteration with grouped
+ * launches, as sa_solve_many does, and a request leaves the group, with its result copied to
+ * host memory and all its device memory released, as soon as it converges, fails or reaches
+ * its iteration cap.  A slot takes its next request as soon as its setup is done (continuous
+ * batching: requests arriving while others are on the GPU are admitted as slots and memory
+ * free up, and their work overlaps on the device).  Requests share nothing but the GPU and
+ * the grouped kernels run each request's standalone arithmetic, so a request's x, iteration
+ * count and residual are bitwise the same alone (sa_setup + sa_solve) or in any mix.  The
+ * server serves the use of many SA-AMG solves (Sec. 3) on one device; it adds no numerical
+ * method of its own. */
 typedef struct sa_server sa_server;
 
 typedef struct {
@@ -217,6 +222,9 @@ typedef struct {
   int64_t reserved_bytes;       /* estimates of the running requests                         */
   int64_t peak_reserved_bytes;  /* maximum of reserved_bytes so far                          */
   int64_t peak_measured_bytes;  /* maximum over time of the summed measured live bytes       */
+  int64_t solve_ticks;          /* grouped CG iterations run                                 */
+  double mean_group;            /* requests advanced per tick, on average                    */
+  int64_t max_group;            /* most requests advanced by one tick                        */
 } sa_server_stats;
 
 /* Device bytes a request on an n x n matrix with nnz entries is charged at admission: an

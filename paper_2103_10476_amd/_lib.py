@@ -81,7 +81,8 @@ class SaServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
                 ("queued", C.c_int64), ("running", C.c_int64), ("budget_bytes", C.c_int64),
                 ("reserved_bytes", C.c_int64), ("peak_reserved_bytes", C.c_int64),
-                ("peak_measured_bytes", C.c_int64)]
+                ("peak_measured_bytes", C.c_int64), ("solve_ticks", C.c_int64),
+                ("mean_group", C.c_double), ("max_group", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

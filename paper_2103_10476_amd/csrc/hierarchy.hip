@@ -289,7 +289,6 @@ static void setup_impl(sa_hierarchy *h, const sa_csr *A, const double *B) {
   h->tmp64 = h->ar.alloc<double>(std::max<int64_t>(n, kMaxDense));
   h->dws = h->ar.alloc<double>(dot_ws_size(n));
   h->S = h->ar.alloc<PcgScalars>(1);
-  SA_HIP(hipHostMalloc((void **)&h->hS, sizeof(PcgScalars), hipHostMallocDefault));
   SA_HIP(hipStreamSynchronize(s));
   h->setup_seconds = now_s() - t0;
 }
@@ -517,11 +516,11 @@ static sa_status solve_impl(sa_hierarchy *h, const double *b, double *x, sa_loca
     pcg_alpha(S, s);
     pcg_update_xr(n, h->x, h->r, h->p, h->q, S, s);
     dot_f64(h->r, h->r, n, &S->rr, h->dws, s);
-    SA_HIP(hipMemcpyAsync(h->hS, S, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
-    SA_HIP(hipStreamSynchronize(s));
+    PcgScalars hs;
+    readback(&hs, S, sizeof(PcgScalars), s);
     prof_collect(h);
-    if (h->hS->err) return SA_ERR_BREAKDOWN;
-    rr = h->hS->rr;
+    if (hs.err) return SA_ERR_BREAKDOWN;
+    rr = hs.rr;
     its = k;
     if (rr <= thr) {
       st = SA_OK;
@@ -538,9 +537,9 @@ static sa_status solve_impl(sa_hierarchy *h, const double *b, double *x, sa_loca
     pcg_update_p(n, h->p, h->z, S, s);
   }
   if (st != SA_OK) {
-    SA_HIP(hipMemcpyAsync(h->hS, S, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
-    SA_HIP(hipStreamSynchronize(s));
-    if (h->hS->err) return SA_ERR_BREAKDOWN;
+    PcgScalars hs;
+    readback(&hs, S, sizeof(PcgScalars), s);
+    if (hs.err) return SA_ERR_BREAKDOWN;
     its = o.max_iter;
   }
   finish();
@@ -569,6 +568,16 @@ static sa_status guarded(F &&fn) {
   }
 }
 
+}  // namespace sa
+
+namespace sa {
+// Frees a hierarchy whose stream has no pending work that uses it, without synchronising
+// that stream (its blocks return to the stream's cache).
+void hierarchy_release_nosync(sa_hierarchy *h) {
+  if (!h) return;
+  h->ar.release();
+  delete h;
+}
 }  // namespace sa
 
 using namespace sa;

@@ -48,7 +48,6 @@ struct sa_hierarchy {
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *zold = nullptr,
          *w = nullptr, *dws = nullptr, *tmp64 = nullptr;
   sa::PcgScalars *S = nullptr;
-  sa::PcgScalars *hS = nullptr;  // pinned host mirror
   int32_t n = 0;
   // fine-level SpMV timing (sa_profile_enable)
   bool prof = false;
@@ -58,8 +57,10 @@ struct sa_hierarchy {
   int64_t prof_launches = 0;
   double prof_ms = 0.0, prof_bytes = 0.0;
   ~sa_hierarchy() {
-    if (hS) (void)hipHostFree(hS);
     for (auto e : ev) (void)hipEventDestroy(e);
   }
 };
 
+namespace sa {
+void hierarchy_release_nosync(sa_hierarchy *h);
+}  // namespace sa

@@ -1,11 +1,16 @@
 // Serving runtime: many independent SA-AMG setup + solve requests on one GPU.
 //
-// Each slot is a host worker thread with a HIP stream of its own.  Workers take requests in
-// submission order while the admitted requests' device-byte estimates fit the budget; a
-// request runs the ordinary sa_setup / sa_solve / sa_destroy on its slot's stream, so the
-// GPU overlaps the kernels of up to max_slots requests, and a slot is refilled as soon as
-// its request completes.  Requests never share device memory (the caching allocator keeps
-// blocks per stream), which makes every result independent of the mix it ran in.
+// Setup: each slot is a host worker thread with a HIP stream of its own.  Workers take
+// requests in submission order while the admitted requests' device-byte estimates fit the
+// budget, and run sa_setup on their slot's stream, so up to max_slots setups overlap on the
+// GPU; a slot takes the next request as soon as its setup is done.
+// Solve: one batcher thread owns every set-up request's solve.  Each tick advances all of
+// them by one CG iteration with grouped launches (one kernel per V-cycle/CG step for all
+// requests, solve_batch.hip); requests join at the next tick after their setup and leave when
+// they converge, fail or hit the cap, and their device memory is released at once.
+// Requests never share device memory (the caching allocator keeps blocks per stream, and
+// each hierarchy keeps its own vectors and scalars), and the grouped kernels run each
+// request's exact standalone arithmetic, so every result is independent of the mix.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -18,7 +23,7 @@
 #include <unordered_map>
 #include <vector>
 
-#include "common.hpp"
+#include "batch.hpp"
 
 namespace sa {
 extern thread_local std::string g_last_error;
@@ -48,32 +53,67 @@ struct Request {
   std::vector<double> x;
   sa_result res{};
   std::string err;
-  double t_submit = 0.0;
+  double t_submit = 0.0, t_solve = 0.0;
   bool done = false;
   sa::Meter meter;
+  sa_hierarchy *h = nullptr;
+  sa::BatchSystem sys;
 };
 
 }  // namespace
 
 struct sa_server {
   std::mutex mu;
-  std::condition_variable cv_work;  // workers: queue, budget or stop changed
-  std::condition_variable cv_done;  // waiters: a request finished
+  std::condition_variable cv_work;   // workers: queue, budget or stop changed
+  std::condition_variable cv_done;   // waiters: a request finished
+  std::condition_variable cv_batch;  // batcher: a request is set up, or stop
   std::deque<std::shared_ptr<Request>> queue;
+  std::vector<std::shared_ptr<Request>> ready;  // set up, waiting to join the solve group
   std::unordered_map<uint64_t, std::shared_ptr<Request>> all;  // not yet collected
   std::vector<std::thread> workers;
+  std::thread batcher;
   std::vector<hipStream_t> streams;
+  hipStream_t bstream = nullptr;
   int device = 0;
   int64_t budget = 0, reserved = 0, peak_reserved = 0;
   int64_t submitted = 0, completed = 0, failed = 0, running = 0;
+  int64_t ticks = 0, tick_systems = 0, max_group = 0;
   uint64_t next_ticket = 1;
-  bool stop = false;
-  sa::Meter total;  // measured device bytes of all running requests
+  bool stop = false, stop_batch = false;
+  sa::Meter total;  // measured device bytes of all admitted requests
 };
 
 namespace {
 
-void run_request(sa_server *s, hipStream_t stream, Request &q) {
+void drop_inputs(Request &q) {
+  std::vector<int32_t>().swap(q.rp);
+  std::vector<int32_t>().swap(q.col);
+  std::vector<double>().swap(q.val);
+  std::vector<double>().swap(q.b);
+}
+
+// Marks a request finished (its memory already released) and wakes waiters and workers.
+void finalize(sa_server *s, Request &q) {
+  int64_t peak = 0;
+  sa::meter_read(&q.meter, nullptr, &peak);
+  q.res.peak_bytes = peak;
+  drop_inputs(q);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->reserved -= q.res.reserved_bytes;
+    --s->running;
+    if (q.res.status < 0) ++s->failed;
+    else ++s->completed;
+    q.res.latency_seconds = now_s() - q.t_submit;
+    q.done = true;
+  }
+  s->cv_done.notify_all();
+  s->cv_work.notify_all();
+}
+
+// Setup on the slot's stream; a set-up request goes to the batcher.
+void run_setup(sa_server *s, hipStream_t stream, const std::shared_ptr<Request> &qp) {
+  Request &q = *qp;
   const double t_admit = now_s();
   q.res.queue_seconds = t_admit - q.t_submit;
   q.res.n = q.n;
@@ -82,30 +122,33 @@ void run_request(sa_server *s, hipStream_t stream, Request &q) {
   sa_context ctx{stream};
   sa_csr A{q.n, q.nnz, q.rp.data(), q.col.data(), q.val.data(), SA_HOST};
   sa_hierarchy *h = nullptr;
-  sa_status st = sa_setup(&ctx, &A, nullptr, &q.opt, &h);
-  const double t_setup = now_s();
-  q.res.setup_seconds = t_setup - t_admit;
-  if (st == SA_OK) {
-    sa_info info;
-    if (sa_hierarchy_info(h, &info) == SA_OK) q.res.levels = info.levels;
-    q.x.assign((size_t)q.n, 0.0);
-    int32_t it = 0;
-    double rr = 0.0;
-    st = sa_solve(h, q.b.data(), q.x.data(), SA_HOST, &it, &rr);
-    q.res.iterations = it;
-    q.res.rel_residual = rr;
-  }
-  if (st < 0) q.err = sa_last_error();
-  q.res.solve_seconds = now_s() - t_setup;
-  sa_destroy(h);
+  const sa_status st = sa_setup(&ctx, &A, nullptr, &q.opt, &h);
   sa::meter_end();
-  q.res.status = st;
-  q.res.peak_bytes = q.meter.peak;
-  // the request's inputs are no longer needed
-  std::vector<int32_t>().swap(q.rp);
+  q.t_solve = now_s();
+  q.res.setup_seconds = q.t_solve - t_admit;
+  if (st != SA_OK) {
+    q.err = sa_last_error();
+    q.res.status = st;
+    finalize(s, q);
+    return;
+  }
+  sa_info info;
+  if (sa_hierarchy_info(h, &info) == SA_OK) q.res.levels = info.levels;
+  std::vector<int32_t>().swap(q.rp);  // the matrix now lives in the hierarchy
   std::vector<int32_t>().swap(q.col);
   std::vector<double>().swap(q.val);
-  std::vector<double>().swap(q.b);
+  q.h = h;
+  q.x.assign((size_t)q.n, 0.0);
+  q.sys.h = h;
+  q.sys.b = q.b.data();
+  q.sys.x = q.x.data();
+  q.sys.loc = SA_HOST;
+  q.sys.user = &q;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->ready.push_back(qp);
+  }
+  s->cv_batch.notify_all();
 }
 
 void worker_main(sa_server *s, int slot) {
@@ -128,18 +171,71 @@ void worker_main(sa_server *s, int slot) {
       if (s->reserved > s->peak_reserved) s->peak_reserved = s->reserved;
       ++s->running;
     }
-    run_request(s, stream, *q);
+    run_setup(s, stream, q);
+  }
+}
+
+const char *solve_message(sa_status st) {
+  switch (st) {
+    case SA_ERR_BREAKDOWN: return "CG breakdown (p'Ap <= 0 or r'z <= 0)";
+    case SA_ERR_INVALID_ARG: return "non-finite right-hand side";
+    default: return "solve failed";
+  }
+}
+
+void batcher_main(sa_server *s) {
+  (void)hipSetDevice(s->device);
+  std::unique_ptr<sa::BatchSolver> bs(new sa::BatchSolver(s->bstream));
+  std::vector<std::shared_ptr<Request>> inflight;
+  for (;;) {
+    std::vector<std::shared_ptr<Request>> fresh;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_batch.wait(lk, [&] { return !s->ready.empty() || !bs->idle() || s->stop_batch; });
+      if (s->ready.empty() && bs->idle()) return;  // stop_batch with nothing left
+      fresh.swap(s->ready);
+    }
+    std::vector<sa::BatchSystem *> fin;
+    try {
+      for (auto &q : fresh) {
+        bs->add(&q->sys);
+        inflight.push_back(q);
+      }
+      bs->tick(fin);
+    } catch (const std::exception &e) {
+      // a runtime failure: every request in the group fails with it
+      for (auto &q : inflight) {
+        q->res.status = SA_ERR_HIP;
+        q->err = e.what();
+        (void)hipStreamSynchronize(s->bstream);
+        sa::hierarchy_release_nosync(q->h);
+        q->h = nullptr;
+        finalize(s, *q);
+      }
+      inflight.clear();
+      bs.reset(new sa::BatchSolver(s->bstream));
+      continue;
+    }
     {
       std::lock_guard<std::mutex> lk(s->mu);
-      s->reserved -= q->res.reserved_bytes;
-      --s->running;
-      if (q->res.status < 0) ++s->failed;
-      else ++s->completed;
-      q->res.latency_seconds = now_s() - q->t_submit;
-      q->done = true;
+      ++s->ticks;
+      const int64_t g = (int64_t)(bs->active() + fin.size());
+      s->tick_systems += g;
+      s->max_group = std::max(s->max_group, g);
     }
-    s->cv_done.notify_all();
-    s->cv_work.notify_all();
+    for (sa::BatchSystem *b : fin) {
+      Request &q = *(Request *)b->user;
+      q.res.status = b->status;
+      q.res.iterations = b->its;
+      q.res.rel_residual = b->relres;
+      q.res.solve_seconds = now_s() - q.t_solve;
+      if (b->status < 0) q.err = solve_message(b->status);
+      sa::hierarchy_release_nosync(q.h);  // the batcher's stream is idle after a tick
+      q.h = nullptr;
+      finalize(s, q);
+      inflight.erase(std::find_if(inflight.begin(), inflight.end(),
+                                  [&](const std::shared_ptr<Request> &r) { return r.get() == &q; }));
+    }
   }
 }
 
@@ -218,7 +314,12 @@ sa_status sa_server_create(const sa_context *ctx, size_t hbm_budget, int32_t max
       }
       s->streams.push_back(st);
     }
+    if (hipStreamCreateWithFlags(&s->bstream, hipStreamNonBlocking) != hipSuccess) {
+      for (auto x : s->streams) (void)hipStreamDestroy(x);
+      throw Error(SA_ERR_HIP, "hipStreamCreateWithFlags failed");
+    }
     for (int i = 0; i < max_slots; ++i) s->workers.emplace_back(worker_main, s.get(), i);
+    s->batcher = std::thread(batcher_main, s.get());
     *out = s.release();
     return SA_OK;
   });
@@ -306,6 +407,9 @@ sa_status sa_server_get_stats(const sa_server *cs, sa_server_stats *st) {
   st->reserved_bytes = s->reserved;
   st->peak_reserved_bytes = s->peak_reserved;
   sa::meter_read(&s->total, nullptr, &st->peak_measured_bytes);
+  st->solve_ticks = s->ticks;
+  st->mean_group = s->ticks ? (double)s->tick_systems / (double)s->ticks : 0.0;
+  st->max_group = s->max_group;
   return SA_OK;
 }
 
@@ -317,10 +421,20 @@ void sa_server_destroy(sa_server *s) {
     s->queue.clear();
   }
   s->cv_work.notify_all();
-  for (auto &t : s->workers) t.join();
+  for (auto &t : s->workers) t.join();  // setups in progress finish and go to the batcher
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop_batch = true;
+  }
+  s->cv_batch.notify_all();
+  if (s->batcher.joinable()) s->batcher.join();  // solves in progress finish
   for (auto st : s->streams) {
     sa::dev_release_stream(st);
     (void)hipStreamDestroy(st);
+  }
+  if (s->bstream) {
+    sa::dev_release_stream(s->bstream);
+    (void)hipStreamDestroy(s->bstream);
   }
   delete s;
 }
