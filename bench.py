@@ -26,9 +26,10 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 counter summary of the SpMV kernel on the default workload; its traffic figure is
 # reported only while the kernel's sources still hash to the value recorded with it
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_spmv_fd7_128_a1000_hbm_traffic.md")
-# the SpMV kernel, its epilogues and row partition live in solve_kernels.hip; build.py holds
-# the compile flags
-KERNEL_SOURCES = ["paper_2103_10476_amd/csrc/solve_kernels.hip",
+# the SpMV kernel body and epilogues live in solve_device.hpp, its launch and row partition in
+# solve_kernels.hip; build.py holds the compile flags
+KERNEL_SOURCES = ["paper_2103_10476_amd/csrc/solve_device.hpp",
+                  "paper_2103_10476_amd/csrc/solve_kernels.hip",
                   "paper_2103_10476_amd/build.py"]
 
 

@@ -101,7 +101,7 @@ struct Csr {
   int32_t *rp = nullptr;
   int32_t *col = nullptr;
   double *val = nullptr;
-  int32_t *bstart = nullptr;
+  int32_t *bstart = nullptr;  // SpMV plan: nblk+1 pairs (first row, first entry)
   int32_t nblk = 0;
 };
 

@@ -15,11 +15,12 @@ struct SpmvArgs {
   const int32_t *col;
   const T *val;
   const T *x;
-  const int32_t *bstart;  // row partition from spmv_plan
+  const int32_t *bstart;  // row partition from spmv_plan: (first row, first entry) pairs
   int32_t nblk;
 };
 // Row partition for the SpMV kernels: block b owns the rows whose cost rp[r] + 8 r lies in
-// [2048 b, 2048 (b+1)), i.e. at most 256 rows and (long rows aside) at most 2048 entries.
+// [2048 b, 2048 (b+1)), i.e. at most 256 rows and (long rows aside) at most 2048 entries;
+// stored as nblk+1 (first row, first entry) pairs, 8-byte aligned.
 void spmv_plan(Csr &A, Arena &ar, hipStream_t s);
 template <class T>
 inline SpmvArgs<T> spmv_args(const Csr &A, const T *val, const T *x) {

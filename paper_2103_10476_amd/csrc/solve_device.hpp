@@ -28,12 +28,13 @@ __device__ __forceinline__ int32_t xcd_block(uint32_t b, uint32_t nb) {
   return (int32_t)(x * q + (x < r ? x : r) + k);
 }
 
-// One SpMV row block b (rows bstart[b] .. bstart[b+1]-1): the block streams the rows' entries
-// through LDS in coalesced chunks, forming each product val*x[col] once; then every thread
-// adds the products of its own row in ascending column order, starting from 0, and hands the
-// sum to the epilogue.  The sum order is the sequential row sum's.
+// One SpMV row block b (rows plan[2b] .. plan[2b+2]-1, entries from plan[2b+1]): the block
+// streams the rows' entries through LDS in coalesced chunks, forming each product
+// val*x[col] once; then every thread adds the products of its own row in ascending column
+// order, starting from 0, and hands the sum to the epilogue.  The sum order is the
+// sequential row sum's.
 template <class T, class Epi>
-__device__ __forceinline__ void spmv_block(int32_t b, const int32_t *__restrict__ bstart,
+__device__ __forceinline__ void spmv_block(int32_t b, const int32_t *__restrict__ plan,
                                            const int32_t *__restrict__ rp,
                                            const int32_t *__restrict__ col,
                                            const T *__restrict__ val,
@@ -41,14 +42,17 @@ __device__ __forceinline__ void spmv_block(int32_t b, const int32_t *__restrict_
                                            T *prod) {
   constexpr int CH = Chunk<T>::value;
   const int t = threadIdx.x;
-  const int32_t r0 = bstart[b], r1 = bstart[b + 1];
+  // row and entry ranges: two independent 8-byte loads (one round trip)
+  const int2 p0 = ((const int2 *)plan)[b], p1 = ((const int2 *)plan)[b + 1];
+  const int32_t r0 = p0.x, e0 = p0.y, r1 = p1.x, e1 = p1.y;
   if (r0 >= r1) return;  // block-uniform
   const int32_t row = r0 + t;
-  const int32_t e0 = rp[r0], e1 = rp[r1];
   int32_t mb = 0, me = 0;
+  typename Epi::Pre pre{};
   if (row < r1) {
     mb = rp[row];
     me = rp[row + 1];
+    pre = epi.load(row);  // the epilogue's vector reads overlap the entry loads
   }
   T s = T(0);
   for (int32_t c0 = e0; c0 < e1; c0 += CH) {
@@ -70,41 +74,62 @@ __device__ __forceinline__ void spmv_block(int32_t b, const int32_t *__restrict_
     for (; e < en; ++e) s += prod[e - c0];
     __syncthreads();
   }
-  if (row < r1) epi(row, s);
+  if (row < r1) epi.store(row, s, pre);
 }
 
-// ---- fused SpMV epilogues: row i receives s = (A x)_i -------------------------------------
+// ---- fused SpMV epilogues: row i receives s = (A x)_i ------------------------------------
+// load(i) reads the row's other inputs (issued before the row's entries are gathered, so
+// their latency overlaps); store(i, s, pre) computes and writes.  Inputs are never vectors
+// the same launch writes at another row.
 template <class T>
 struct EpStore {
   T *y;
-  __device__ void operator()(int32_t i, T s) const { y[i] = s; }
+  struct Pre {};
+  __device__ Pre load(int32_t) const { return {}; }
+  __device__ void store(int32_t i, T s, const Pre &) const { y[i] = s; }
 };
 template <class T>
 struct EpScale {
   const T *d;
   T *y;
-  __device__ void operator()(int32_t i, T s) const { y[i] = d[i] * s; }
+  struct Pre {
+    T d;
+  };
+  __device__ Pre load(int32_t i) const { return {d[i]}; }
+  __device__ void store(int32_t i, T s, const Pre &p) const { y[i] = p.d * s; }
 };
 template <class T>
 struct EpResid {
   const T *f;
   T *r;
-  __device__ void operator()(int32_t i, T s) const { r[i] = f[i] - s; }
+  struct Pre {
+    T f;
+  };
+  __device__ Pre load(int32_t i) const { return {f[i]}; }
+  __device__ void store(int32_t i, T s, const Pre &p) const { r[i] = p.f - s; }
 };
 template <class T>
 struct EpAdd {
   T *u;
-  __device__ void operator()(int32_t i, T s) const { u[i] = u[i] + s; }
+  struct Pre {
+    T u;
+  };
+  __device__ Pre load(int32_t i) const { return {u[i]}; }
+  __device__ void store(int32_t i, T s, const Pre &p) const { u[i] = p.u + s; }
 };
 template <class T>
 struct EpChebStart {
   const T *f, *invD;
   T theta;
   T *r, *d;
-  __device__ void operator()(int32_t i, T s) const {
-    T ri = f[i] - s;
+  struct Pre {
+    T f, invD;
+  };
+  __device__ Pre load(int32_t i) const { return {f[i], invD[i]}; }
+  __device__ void store(int32_t i, T s, const Pre &p) const {
+    T ri = p.f - s;
     r[i] = ri;
-    d[i] = (invD[i] * ri) / theta;
+    d[i] = (p.invD * ri) / theta;
   }
 };
 template <class T>
@@ -113,12 +138,18 @@ struct EpChebStep {
   T *rout, *u, *dout;
   T c1, c2;
   bool uzero, last;
-  __device__ void operator()(int32_t i, T s) const {
-    T di = d[i];
-    T ui = (uzero ? T(0) : u[i]) + di;
-    T ri = rin[i] - s;
+  struct Pre {
+    T d, rin, invD, u;
+  };
+  __device__ Pre load(int32_t i) const {
+    return {d[i], rin[i], invD[i], uzero ? T(0) : u[i]};
+  }
+  __device__ void store(int32_t i, T s, const Pre &p) const {
+    T di = p.d;
+    T ui = p.u + di;
+    T ri = p.rin - s;
     rout[i] = ri;
-    T dn = c1 * di + c2 * (invD[i] * ri);
+    T dn = c1 * di + c2 * (p.invD * ri);
     if (last) {
       u[i] = ui + dn;
     } else {
@@ -132,9 +163,13 @@ struct EpJacobi {
   const T *u, *f, *invD;
   T w;
   T *u2;
-  __device__ void operator()(int32_t i, T s) const {
-    T r = f[i] - s;
-    u2[i] = u[i] + w * (invD[i] * r);
+  struct Pre {
+    T u, f, invD;
+  };
+  __device__ Pre load(int32_t i) const { return {u[i], f[i], invD[i]}; }
+  __device__ void store(int32_t i, T s, const Pre &p) const {
+    T r = p.f - s;
+    u2[i] = p.u + w * (p.invD * r);
   }
 };
 

@@ -20,27 +20,31 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int32_t *__restrict__ bst
   spmv_block<T, Epi>(xcd_block(blockIdx.x, gridDim.x), bstart, rp, col, val, x, epi, prod);
 }
 
-__global__ void k_spmv_plan(int32_t n, const int32_t *rp, int32_t nblk, int32_t *bstart) {
+// Row partition: block b owns rows plan[2b] .. plan[2b+2]-1, whose entries start at
+// plan[2b+1]; the pairs are stored side by side so a block reads its row and entry ranges
+// with one load.
+__global__ void k_spmv_plan(int32_t n, const int32_t *rp, int32_t nblk, int32_t *plan) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b > nblk) return;
-  if (b == nblk) {
-    bstart[b] = n;
-    return;
+  int32_t lo = n;
+  if (b < nblk) {
+    const int64_t target = b * kPlanWindow;
+    int32_t hi = n;  // first r in [0, n] with rp[r] + 8 r >= target
+    lo = 0;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      if ((int64_t)rp[mid] + (int64_t)kPlanRowCost * mid >= target) hi = mid;
+      else lo = mid + 1;
+    }
   }
-  const int64_t target = b * kPlanWindow;
-  int32_t lo = 0, hi = n;  // first r in [0, n] with rp[r] + 8 r >= target
-  while (lo < hi) {
-    const int32_t mid = (lo + hi) >> 1;
-    if ((int64_t)rp[mid] + (int64_t)kPlanRowCost * mid >= target) hi = mid;
-    else lo = mid + 1;
-  }
-  bstart[b] = lo;
+  plan[2 * b] = lo;
+  plan[2 * b + 1] = rp[lo];
 }
 
 void spmv_plan(Csr &A, Arena &ar, hipStream_t s) {
   const int64_t cost = A.nnz + (int64_t)kPlanRowCost * A.n;
   A.nblk = (int32_t)ceil_div(cost + 1, kPlanWindow);
-  A.bstart = ar.alloc<int32_t>(A.nblk + 1);
+  A.bstart = ar.alloc<int32_t>(2 * ((int64_t)A.nblk + 1));
   k_spmv_plan<<<grid_for(A.nblk + 1), kBlock, 0, s>>>(A.n, A.rp, A.nblk, A.bstart);
   SA_LAUNCH_CHECK();
 }

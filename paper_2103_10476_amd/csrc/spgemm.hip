@@ -293,12 +293,13 @@ __global__ __launch_bounds__(kBlock) void k_esc_hash(
     const double *xval, const int32_t *xpref, const int32_t *yrp, const int32_t *ycol,
     const double *yval, const int64_t *poff, int32_t *ocol, double *oval, int32_t *ucnt,
     int32_t *ovf, int32_t *novf) {
-  // sk/sv hold a chunk (kChunk) while accumulating and up to kHashL/2 distinct entries for
-  // the final sort (rows with more go to k_esc_dense)
-  static_assert(kHashL / 2 >= kChunk, "final sort area must hold a chunk");
-  __shared__ uint64_t sk[kHashL / 2];
-  __shared__ double sv[kHashL / 2];
-  __shared__ int32_t hk[kHashL];
+  // sk/sv hold one chunk while accumulating; the final sort of the (at most kHashL/2)
+  // distinct entries reuses the table's own storage: hk as 64-bit sort keys, hv for values
+  // (rows with more distinct entries go to k_esc_dense).  65 KB of LDS: two blocks per CU.
+  __shared__ uint64_t sk[kChunk];
+  __shared__ double sv[kChunk];
+  __shared__ uint64_t hk64[kHashL / 2];
+  int32_t *hk = reinterpret_cast<int32_t *>(hk64);
   __shared__ double hv[kHashL];
   __shared__ int32_t s_scan[kBlock];
   __shared__ int32_t s_cnt, s_ovf;
@@ -347,11 +348,20 @@ __global__ __launch_bounds__(kBlock) void k_esc_hash(
     if (tid == 0) ovf[atomicAdd(novf, 1)] = i;
     return;
   }
-  // compact the occupied slots (slot order) into sk/sv, then sort only those U entries
+  // compact the occupied slots (slot order) into the table's storage, then sort only those
+  // U entries: every thread first takes its slots into registers, so the compacted writes
+  // cannot overwrite a slot not yet read
   const int32_t U = s_cnt;
   constexpr int per = kHashL / kBlock;
+  int32_t kk[per];
+  double vv[per];
   int32_t nloc = 0;
-  for (int q = 0; q < per; ++q) nloc += hk[tid * per + q] >= 0;
+#pragma unroll
+  for (int q = 0; q < per; ++q) {
+    kk[q] = hk[tid * per + q];
+    vv[q] = hv[tid * per + q];
+    nloc += kk[q] >= 0;
+  }
   s_scan[tid] = nloc;
   __syncthreads();
   for (int off = 1; off < kBlock; off <<= 1) {
@@ -361,22 +371,22 @@ __global__ __launch_bounds__(kBlock) void k_esc_hash(
     __syncthreads();
   }
   int32_t w = s_scan[tid] - nloc;
+#pragma unroll
   for (int q = 0; q < per; ++q) {
-    const int32_t slot = tid * per + q;
-    if (hk[slot] >= 0) {
-      sk[w] = ((uint64_t)(uint32_t)hk[slot] << 32) | (uint32_t)w;
-      sv[w] = hv[slot];
+    if (kk[q] >= 0) {
+      hk64[w] = ((uint64_t)(uint32_t)kk[q] << 32) | (uint32_t)w;
+      hv[w] = vv[q];
       ++w;
     }
   }
   __syncthreads();
-  const int32_t Up = next_pow2(U);
-  for (int32_t q = U + tid; q < Up; q += kBlock) sk[q] = ~0ull;
+  const int32_t Up = next_pow2(U);  // U <= kHashL / 2 (overflowing rows left above)
+  for (int32_t q = U + tid; q < Up; q += kBlock) hk64[q] = ~0ull;
   __syncthreads();
-  bitonic_u64(sk, Up);
+  bitonic_u64(hk64, Up);
   for (int32_t r = tid; r < U; r += kBlock) {
-    ocol[base + r] = (int32_t)key_of(sk[r]);
-    oval[base + r] = sv[(uint32_t)sk[r]];
+    ocol[base + r] = (int32_t)key_of(hk64[r]);
+    oval[base + r] = hv[(uint32_t)hk64[r]];
   }
   if (tid == 0) ucnt[i] = U;
 }
