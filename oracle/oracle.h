@@ -46,6 +46,9 @@ const char *orc_last_error(void);
 /* ---- whole method ---- */
 int orc_setup(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
               const double *nullspace /* NULL = ones */, const orc_options *o, void **h);
+/* numeric re-setup: new values (nnz of the setup's matrix, its CSR order), same symbolic
+ * decisions (strength labels, Sprsfy drops, aggregates, patterns) */
+int orc_resetup(void *h, const double *val, const double *nullspace /* NULL = ones */);
 int orc_num_levels(const void *h);
 /* sizes[0..7] = n, nnz(A), nc, nnz(Abar), nnz(P), nnz(R), nnz(S graph), is_coarsest */
 int orc_level_sizes(const void *h, int lvl, int64_t *sizes);

@@ -44,6 +44,8 @@ def _setup_prototypes(L):
     L.orc_default_options.argtypes = [C.POINTER(OrcOptions)]
     L.orc_last_error.restype = C.c_char_p
     L.orc_setup.argtypes = [C.c_int32, P, P, P, P, C.POINTER(OrcOptions), C.POINTER(C.c_void_p)]
+    L.orc_resetup.argtypes = [P, P, P]
+    L.orc_resetup.restype = C.c_int
     L.orc_num_levels.argtypes = [P]
     L.orc_level_sizes.argtypes = [P, C.c_int, P]
     L.orc_level_scalars.argtypes = [P, C.c_int, P]
@@ -181,6 +183,15 @@ class OracleHierarchy:
         u = np.empty_like(f)
         _check(lib().orc_vcycle(self.h, _p(f), _p(u)))
         return u
+
+    def resetup(self, val, nullspace=None):
+        """Numeric re-setup (orc_resetup): new values on the setup's pattern, the setup's
+        symbolic decisions kept; every level is exported again."""
+        v = _f64(val)
+        B = None if nullspace is None else _f64(nullspace)
+        self._keep = (self._keep[0], self._keep[1], v)
+        _check(lib().orc_resetup(self.h, _p(v), None if B is None else _p(B)))
+        self.levels = [self._export(l) for l in range(lib().orc_num_levels(self.h))]
 
     def solve(self, b, history=False):
         b = _f64(b)

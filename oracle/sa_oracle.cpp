@@ -700,6 +700,7 @@ struct Hier {
   orc_options o;
   std::vector<Level> lv;
   bool scaled = false;
+  bool valid = true;  // false after a failed re-setup
 };
 
 // Dense Cholesky of the coarsest operator, textbook order: L_jj = sqrt(A_jj - sum_k<j L_jk^2),
@@ -743,6 +744,8 @@ void chol_solve(const std::vector<double> &L, int n, const std::vector<double> &
   }
 }
 
+int numeric_level(Hier &H, int l);
+
 int build_level(Hier &H, int l) {
   Level &L = H.lv[l];
   const orc_options &o = H.o;
@@ -756,6 +759,15 @@ int build_level(Hier &H, int l) {
   if (nc == 0) return 1;  // no strong connection left: this level becomes the coarsest
   if (nc >= L.A.nr) return fail(ST_STALLED, "coarsening stalled");
   if (o.variants & V_SPRSFY) sprsfy(L.As, L.mask, L.agg, L.is_root, nc);
+  return numeric_level(H, l);
+}
+
+// Level l from its strength labels (mask, Sprsfy drops included) and aggregates on: filtered
+// matrix, smoothing diagonal, eigenvalue estimate, damping, smoothed prolongator, Cnstrnt.
+int numeric_level(Hier &H, int l) {
+  Level &L = H.lv[l];
+  const orc_options &o = H.o;
+  const int nc = L.nc;
   L.Abar = lump(L.As, L.mask, (o.variants & V_OFFLMP) != 0, o.tau);
   bool one_norm = (o.variants & V_1NORM) != 0;
   int st = diag(L.Abar, one_norm, o.sigma, L.invD);
@@ -773,6 +785,64 @@ int build_level(Hier &H, int l) {
       cnstrnt_row(&L.P.col[L.P.rp[i]], &L.P.val[L.P.rp[i]], L.P.rp[i + 1] - L.P.rp[i],
                   L.agg[i]);
   return ST_OK;
+}
+
+// Reading: a general nullspace vector B is handled by the exact symmetric scaling
+// Ahat = D_B A D_B (Ahat_ij = (B_i*A_ij)*B_j), building the hierarchy with constant B on
+// Ahat and returning P_1 = D_B Phat_1.  Sets level 0's As (A itself when B is null or ones).
+int apply_nullspace(Hier &H, const double *B) {
+  Level &L0 = H.lv[0];
+  const int n = L0.A.nr;
+  L0.As = L0.A;
+  H.scaled = false;
+  if (!B) return ST_OK;
+  bool scaled = false;
+  for (int i = 0; i < n; ++i) {
+    if (!(B[i] != 0.0) || !std::isfinite(B[i]))
+      return fail(ST_INVALID, "nullspace entry zero or non-finite");
+    if (B[i] != 1.0) scaled = true;
+  }
+  if (!scaled) return ST_OK;
+  Csr &S = L0.As;
+  for (int i = 0; i < n; ++i)
+    for (int32_t e = S.rp[i]; e < S.rp[i + 1]; ++e) S.val[e] = (B[i] * S.val[e]) * B[S.col[e]];
+  H.scaled = true;
+  return ST_OK;
+}
+
+// P_1 = D_B Phat_1 (scaled case), R_l = P_l^T, A_{l+1} = R_l (A_l P_l) into level l+1.
+void galerkin(Hier &H, int l, const double *B) {
+  Level &L = H.lv[l];
+  if (l == 0 && H.scaled) {
+    Csr &P = L.P;
+    for (int i = 0; i < P.nr; ++i)
+      for (int32_t e = P.rp[i]; e < P.rp[i + 1]; ++e) P.val[e] = B[i] * P.val[e];
+  }
+  L.R = transpose(L.P);
+  Csr AP = spgemm(L.A, L.P);
+  Level &Ln = H.lv[l + 1];
+  Ln.A = spgemm(L.R, AP);
+  Ln.As = Ln.A;
+}
+
+// Smoothers on every level but the coarsest (Sec. 3.1: Chebyshev of degree 2 on
+// [lambda/10, lambda], lambda from 10 power sweeps on invD*A), and the coarsest factor.
+int finish(Hier &H) {
+  const orc_options &o = H.o;
+  const int nl = (int)H.lv.size();
+  for (int l = 0; l + 1 < nl; ++l) {
+    Level &L = H.lv[l];
+    L.sm_invD.assign(L.A.nr, 0.0);
+    for (int i = 0; i < L.A.nr; ++i) {
+      double d = diag_of(L.A, i);
+      if (!(d > 0.0)) return fail(ST_NONPOS_DIAG, "non-positive diagonal in a level operator");
+      L.sm_invD[i] = 1.0 / d;
+    }
+    int st = power_method(L.A, L.sm_invD, o.power_iters, o.seed, l, 1, L.sm_lambda);
+    if (st) return st;
+    L.sm_lambda = L.sm_lambda * o.cheb_boost;
+  }
+  return cholesky(H.lv[nl - 1].A, H.lv[nl - 1].chol);
 }
 
 }  // namespace
@@ -825,25 +895,10 @@ int orc_setup(int32_t n, const int32_t *rp, const int32_t *col, const double *va
   H->o = *o;
   H->lv.emplace_back();
   H->lv[0].A = make_csr(n, n, rp, col, val);
-  H->lv[0].As = H->lv[0].A;
-  bool scaled = false;
-  if (B) {
-    for (int i = 0; i < n; ++i) {
-      if (!(B[i] != 0.0) || !std::isfinite(B[i])) {
-        delete H;
-        return fail(ST_INVALID, "nullspace entry zero or non-finite");
-      }
-      if (B[i] != 1.0) scaled = true;
-    }
-  }
-  // Reading: a general nullspace vector B is handled by the exact symmetric scaling
-  // Ahat = D_B A D_B (Ahat_ij = (B_i*A_ij)*B_j), building the hierarchy with constant B on
-  // Ahat and returning P_1 = D_B Phat_1.
-  if (scaled) {
-    Csr &S = H->lv[0].As;
-    for (int i = 0; i < n; ++i)
-      for (int32_t e = S.rp[i]; e < S.rp[i + 1]; ++e) S.val[e] = (B[i] * S.val[e]) * B[S.col[e]];
-    H->scaled = true;
+  st = apply_nullspace(*H, B);
+  if (st) {
+    delete H;
+    return st;
   }
   for (int l = 0;; ++l) {
     Level &L = H->lv[l];
@@ -864,46 +919,42 @@ int orc_setup(int32_t n, const int32_t *rp, const int32_t *col, const double *va
       Lc.nc = 0;
       break;
     }
-    if (l == 0 && scaled) {
-      Csr &P = H->lv[0].P;
-      for (int i = 0; i < n; ++i)
-        for (int32_t e = P.rp[i]; e < P.rp[i + 1]; ++e) P.val[e] = B[i] * P.val[e];
-    }
-    Level &Lc = H->lv[l];
-    Lc.R = transpose(Lc.P);
-    Csr AP = spgemm(Lc.A, Lc.P);
-    Csr Ac = spgemm(Lc.R, AP);
     H->lv.emplace_back();
-    H->lv[l + 1].A = std::move(Ac);
-    H->lv[l + 1].As = H->lv[l + 1].A;
+    galerkin(*H, l, B);
   }
-  // Smoothers on every level but the coarsest (Sec. 3.1: Chebyshev of degree 2 on
-  // [lambda/10, lambda], lambda from 10 power sweeps on invD*A).
-  int nl = (int)H->lv.size();
-  for (int l = 0; l + 1 < nl; ++l) {
-    Level &L = H->lv[l];
-    L.sm_invD.assign(L.A.nr, 0.0);
-    for (int i = 0; i < L.A.nr; ++i) {
-      double d = diag_of(L.A, i);
-      if (!(d > 0.0)) {
-        delete H;
-        return fail(ST_NONPOS_DIAG, "non-positive diagonal in a level operator");
-      }
-      L.sm_invD[i] = 1.0 / d;
-    }
-    st = power_method(L.A, L.sm_invD, o->power_iters, o->seed, l, 1, L.sm_lambda);
-    if (st) {
-      delete H;
-      return st;
-    }
-    L.sm_lambda = L.sm_lambda * o->cheb_boost;
-  }
-  st = cholesky(H->lv[nl - 1].A, H->lv[nl - 1].chol);
+  st = finish(*H);
   if (st) {
     delete H;
     return st;
   }
   *out = H;
+  return ST_OK;
+}
+
+// Numeric re-setup: new values on the setup's pattern, with every symbolic decision of the
+// setup kept (strength labels and Sprsfy drops, aggregates); the numbers are recomputed by
+// the setup's own steps.  On failure the hierarchy is left unusable (solves refuse it).
+int orc_resetup(void *h, const double *val, const double *B) {
+  Hier *H = (Hier *)h;
+  Level &L0 = H->lv[0];
+  const int n = L0.A.nr;
+  H->valid = false;
+  for (int64_t e = 0; e < L0.A.nnz(); ++e) {
+    if (!std::isfinite(val[e])) return fail(ST_INVALID, "non-finite matrix value");
+    L0.A.val[e] = val[e];
+  }
+  (void)n;
+  int st = apply_nullspace(*H, B);
+  if (st) return st;
+  const int nl = (int)H->lv.size();
+  for (int l = 0; l + 1 < nl; ++l) {
+    st = numeric_level(*H, l);
+    if (st) return st;
+    galerkin(*H, l, B);
+  }
+  st = finish(*H);
+  if (st) return st;
+  H->valid = true;
   return ST_OK;
 }
 
@@ -1067,6 +1118,7 @@ int orc_vcycle(const void *h, const double *f, double *u) {
 int orc_solve(const void *h, const double *b, double *x, int32_t *iters, double *relres,
               double *hist) {
   const Hier *H = (const Hier *)h;
+  if (!H->valid) return fail(ST_INVALID, "hierarchy left unusable by a failed re-setup");
   const orc_options &o = H->o;
   const Csr &A = H->lv[0].A;
   int n = A.nr;
