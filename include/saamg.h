@@ -137,6 +137,21 @@ void sa_default_options(sa_options *o);
 sa_status sa_setup(const sa_context *ctx, const sa_csr *A, const double *nullspace,
                    const sa_options *o, sa_hierarchy **out);
 
+/* Numeric re-setup: new values for the matrix given to sa_setup, on the same pattern (val
+ * holds nnz values in that matrix's CSR order; nullspace as in sa_setup, NULL = ones; both in
+ * `loc` memory).  Every symbolic decision of the setup is kept: strength labels and Sprsfy
+ * drops, aggregates, and the sparsity patterns of the filtered matrices, P, R and every level
+ * operator.  The numbers are recomputed in the setup's own order: filtered values (plain or
+ * OffLmp lumping), smoothing diagonal, eigenvalue estimate and damping, P (and Cnstrnt), R,
+ * the Galerkin products, the smoothers and the coarsest inverse.  The result is bit-identical
+ * to what sa_setup gives on the new values whenever that setup would take the same symbolic
+ * decisions.  For a sequence of systems with one pattern (time steps, repeated requests) this
+ * skips the strength test and root selection.  Errors as for sa_setup (values only); after a
+ * failure the hierarchy can only be destroyed or re-set up again (solves return
+ * SA_ERR_INVALID_ARG). */
+sa_status sa_resetup(sa_hierarchy *h, const double *val, const double *nullspace,
+                     sa_location loc);
+
 /* Solves A x = b with CG preconditioned by one V-cycle (Algorithm 1) per iteration, from
  * x0 = 0, until dot(r,r) <= rtol^2 dot(b,b) or max_iter.  b and x are n-vectors in `loc`
  * memory (x is written).  iterations and rel_residual = sqrt(dot(r,r)/dot(b,b)) may be

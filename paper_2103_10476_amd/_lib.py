@@ -32,7 +32,7 @@ PART_DTYPE = {"A_rp": "int32", "A_col": "int32", "A_val": "float64", "mask": "ui
 EXPORTED = ["sa_default_options", "sa_setup", "sa_solve", "sa_vcycle", "sa_hierarchy_info",
             "sa_export_size", "sa_export_level", "sa_destroy", "sa_status_string",
             "sa_last_error", "sa_profile_enable", "sa_profile_read", "sa_estimate_bytes",
-            "sa_solve_many",
+            "sa_solve_many", "sa_resetup",
             "sa_server_create", "sa_server_submit", "sa_server_poll", "sa_server_wait",
             "sa_server_drain", "sa_server_get_stats", "sa_server_destroy"]
 
@@ -108,6 +108,8 @@ def lib():
         L.sa_setup.argtypes = [C.POINTER(SaContext), C.POINTER(SaCsr), P, C.POINTER(SaOptions),
                                C.POINTER(C.c_void_p)]
         L.sa_setup.restype = C.c_int
+        L.sa_resetup.argtypes = [P, P, P, C.c_int32]
+        L.sa_resetup.restype = C.c_int
         L.sa_solve.argtypes = [P, P, P, C.c_int32, C.POINTER(C.c_int32),
                                C.POINTER(C.c_double)]
         L.sa_solve.restype = C.c_int

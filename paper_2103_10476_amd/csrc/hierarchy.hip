@@ -93,8 +93,62 @@ static Csr copy_csr(const Csr &a, Arena &ar, hipStream_t s) {
   return c;
 }
 
-// Builds level l's prolongator and the next operator.  Returns false when the level has no
-// strong connection left (it becomes the coarsest).
+// Copies the values of a freshly computed matrix into an existing one of the same pattern.
+static void take_values(const Csr &src, Csr &dst, hipStream_t s) {
+  if (src.nnz != dst.nnz || src.n != dst.n)
+    throw Error(SA_ERR_INVALID_ARG, "re-setup produced a different sparsity pattern");
+  if (src.nnz > 0)
+    SA_HIP(hipMemcpyAsync(dst.val, src.val, sizeof(double) * src.nnz, hipMemcpyDeviceToDevice,
+                          s));
+}
+
+// The numeric part of level l, from the strength labels and aggregates on: filtered matrix
+// (plain or OffLmp lumping) and smoothing diagonal, eigenvalue estimate and damping,
+// prolongator smoothing and Cnstrnt.  fresh: allocate the level's arrays (setup); otherwise
+// overwrite the values of the existing ones, whose patterns do not change (re-setup).
+static void numeric_level(sa_hierarchy *h, int l, bool fresh) {
+  const hipStream_t s = h->stream;
+  const sa_options &o = h->opt;
+  Level &L = h->lv[l];
+  Arena &ar = h->ar;
+  const int32_t n = L.A.n;
+  Arena tmp;
+  tmp.stream = s;
+  const bool one_norm = (o.variants & SA_1NORM) != 0;
+  if (fresh) {
+    L.invD = ar.alloc<double>(n);
+    L.lam_d = ar.alloc<double>(2);
+    L.omega_d = L.lam_d + 1;
+  }
+  {
+    Csr abar;
+    lump(n, L.As.rp, L.As.col, L.As.val, L.mask, (o.variants & SA_OFFLMP) != 0, o.tau, one_norm,
+         safeguard_mult(o.sigma), L.wave_rows, fresh ? ar : tmp, abar, L.invD, h->err, s);
+    check_err(h, E_ZERO_FDIAG, SA_ERR_NONPOSITIVE_DIAG, "zero diagonal in the filtered matrix");
+    if (fresh) {
+      L.Abar = abar;
+      spmv_plan(L.Abar, ar, s);
+    } else {
+      take_values(abar, L.Abar, s);
+    }
+  }
+  const bool unit = one_norm && o.one_norm_power == 0;
+  if (!unit) power_method(L.Abar, L.invD, o.power_iters, o.seed, l, 0, L.lam_d, s);
+  damping(L.lam_d, L.omega_d, unit, h->err, s);
+  check_err(h, E_LAMBDA, SA_ERR_NEGATIVE_EIGENVALUE, "eigenvalue estimate not positive");
+  if (fresh) {
+    prolongator(L.Abar, L.invD, L.agg, L.nc, L.omega_d, ar, L.P, s);
+  } else {
+    Csr P;
+    prolongator(L.Abar, L.invD, L.agg, L.nc, L.omega_d, tmp, P, s);
+    take_values(P, L.P, s);
+  }
+  if (o.variants & SA_CNSTRNT) cnstrnt(L.P, L.agg, s);
+  if (fresh) spmv_plan(L.P, ar, s);
+}
+
+// Builds level l's strength labels and aggregates, then its numeric part.  Returns false when
+// the level has no strong connection left (it becomes the coarsest).
 static bool build_level(sa_hierarchy *h, int l) {
   const hipStream_t s = h->stream;
   const sa_options &o = h->opt;
@@ -106,13 +160,13 @@ static bool build_level(sa_hierarchy *h, int l) {
   double *dval = tmp.alloc<double>(n);
   find_diag(n, L.As.rp, L.As.col, L.As.val, dval, s);
   // rows long enough to leave thread-per-row kernels serial: one wavefront per row instead
-  const bool wave_rows = max_row_length(n, L.As.rp, s) > 64 || L.As.nnz > 24 * (int64_t)n;
+  L.wave_rows = max_row_length(n, L.As.rp, s) > 64 || L.As.nnz > 24 * (int64_t)n;
   L.mask = ar.alloc<uint8_t>(L.As.nnz);
   int32_t *scount = tmp.alloc<int32_t>(n + 1);
-  strength(n, L.As.rp, L.As.col, L.As.val, dval, o.theta * o.theta, L.mask, scount, wave_rows,
-           s);
+  strength(n, L.As.rp, L.As.col, L.As.val, dval, o.theta * o.theta, L.mask, scount,
+           L.wave_rows, s);
   int32_t *grp = nullptr, *gcol = nullptr;
-  const int64_t nnzG = strength_graph(n, L.As.rp, L.As.col, L.mask, scount, wave_rows, tmp,
+  const int64_t nnzG = strength_graph(n, L.As.rp, L.As.col, L.mask, scount, L.wave_rows, tmp,
                                       &grp, &gcol, s);
   L.agg = ar.alloc<int32_t>(n);
   L.is_root = ar.alloc<uint8_t>(n);
@@ -122,22 +176,162 @@ static bool build_level(sa_hierarchy *h, int l) {
   if (L.nc == 0) return false;
   if (L.nc >= n) throw Error(SA_ERR_COARSEN_STALLED, "coarsening stalled");
   if (o.variants & SA_SPRSFY) sprsfy(n, L.As.rp, L.As.col, L.mask, L.agg, root_vertex, L.nc, s);
-  const bool one_norm = (o.variants & SA_1NORM) != 0;
-  L.invD = ar.alloc<double>(n);
-  lump(n, L.As.rp, L.As.col, L.As.val, L.mask, (o.variants & SA_OFFLMP) != 0, o.tau, one_norm,
-       safeguard_mult(o.sigma), wave_rows, ar, L.Abar, L.invD, h->err, s);
-  check_err(h, E_ZERO_FDIAG, SA_ERR_NONPOSITIVE_DIAG, "zero diagonal in the filtered matrix");
-  spmv_plan(L.Abar, ar, s);
-  L.lam_d = ar.alloc<double>(2);
-  L.omega_d = L.lam_d + 1;
-  const bool unit = one_norm && o.one_norm_power == 0;
-  if (!unit) power_method(L.Abar, L.invD, o.power_iters, o.seed, l, 0, L.lam_d, s);
-  damping(L.lam_d, L.omega_d, unit, h->err, s);
-  check_err(h, E_LAMBDA, SA_ERR_NEGATIVE_EIGENVALUE, "eigenvalue estimate not positive");
-  prolongator(L.Abar, L.invD, L.agg, L.nc, L.omega_d, ar, L.P, s);
-  if (o.variants & SA_CNSTRNT) cnstrnt(L.P, L.agg, s);
-  spmv_plan(L.P, ar, s);
+  numeric_level(h, l, true);
   return true;
+}
+
+// R_l = P_l^T and A_{l+1} = R_l (A_l P_l); P_1 first gets the nullspace scaling.  fresh:
+// allocate level l+1; otherwise overwrite the values of R_l and A_{l+1}.
+static void galerkin(sa_hierarchy *h, int l, bool fresh, const double *dB) {
+  const hipStream_t s = h->stream;
+  Level &L = h->lv[l];
+  if (l == 0 && dB) scale_rows(L.P, dB, s);
+  Arena tmp;
+  tmp.stream = s;
+  if (fresh) {
+    transpose(L.P, h->ar, L.R, s);
+    spmv_plan(L.R, h->ar, s);
+  } else {
+    Csr R;
+    transpose(L.P, tmp, R, s);
+    take_values(R, L.R, s);
+  }
+  Csr AP, Ac;
+  spgemm(L.A, L.P, tmp, AP, s);
+  if (fresh) {
+    spgemm(L.R, AP, h->ar, Ac, s);
+    spmv_plan(Ac, h->ar, s);
+    h->lv.emplace_back();
+    h->lv[l + 1].A = Ac;
+    h->lv[l + 1].As = Ac;
+  } else {
+    spgemm(L.R, AP, tmp, Ac, s);
+    take_values(Ac, h->lv[l + 1].A, s);  // As shares A's arrays on coarse levels
+  }
+}
+
+// Smoothers of every level but the coarsest, the coarsest level's dense inverse, the FP32
+// copies and the solve workspace.  fresh: allocate; otherwise recompute in place.
+static void finish_setup(sa_hierarchy *h, bool fresh) {
+  const hipStream_t s = h->stream;
+  const sa_options &o = h->opt;
+  const int nl = (int)h->lv.size();
+  const int32_t n = h->n;
+  for (int l = 0; l + 1 < nl; ++l) {
+    Level &L = h->lv[l];
+    Arena tmp;
+    tmp.stream = s;
+    double *dval = tmp.alloc<double>(L.A.n);
+    find_diag(L.A.n, L.A.rp, L.A.col, L.A.val, dval, s);
+    if (fresh) {
+      L.sm_invD = h->ar.alloc<double>(L.A.n);
+      L.sm_lam_d = h->ar.alloc<double>(1);
+    }
+    inv_diag(L.A.n, dval, L.sm_invD, h->err, s);
+    check_err(h, E_DIAG, SA_ERR_NONPOSITIVE_DIAG, "non-positive diagonal in a level operator");
+    power_method(L.A, L.sm_invD, o.power_iters, o.seed, l, 1, L.sm_lam_d, s);
+    const double lam = read1(L.sm_lam_d, s);
+    if (!(lam > 0.0) || !std::isfinite(lam))
+      throw Error(SA_ERR_NEGATIVE_EIGENVALUE, "smoother eigenvalue estimate not positive");
+    L.sm_lam = lam * o.cheb_boost;
+    chebyshev_scalars(L, o);
+    if (L.lam_d) {
+      double lo[2];
+      readback(lo, L.lam_d, sizeof(lo), s);
+      L.lam = lo[0];
+      L.omega = lo[1];
+    }
+  }
+  Level &Lc = h->lv[nl - 1];
+  if (Lc.A.n > kMaxDense)
+    throw Error(SA_ERR_COARSE_FACTOR, "coarsest level too large for the dense solver");
+  if (fresh) Lc.Ainv = h->ar.alloc<double>((int64_t)Lc.A.n * Lc.A.n);
+  coarse_inverse(Lc.A, Lc.Ainv, h->err, s);
+  check_err(h, E_CHOL, SA_ERR_COARSE_FACTOR, "coarse Cholesky pivot not positive");
+  // FP32 copies of the hierarchy for the FP32 V-cycle
+  const bool f32 = o.precision == SA_FP32_VCYCLE;
+  for (int l = 0; l < nl; ++l) {
+    Level &L = h->lv[l];
+    const int32_t m = L.A.n;
+    if (fresh) {
+      L.f = h->ar.alloc<double>(m);
+      L.u = h->ar.alloc<double>(m);
+      L.r = h->ar.alloc<double>(m);
+      L.d1 = h->ar.alloc<double>(m);
+      L.d2 = h->ar.alloc<double>(m);
+    }
+    if (f32) {
+      if (fresh) {
+        L.ff = h->ar.alloc<float>(m);
+        L.uf = h->ar.alloc<float>(m);
+        L.rf = h->ar.alloc<float>(m);
+        L.d1f = h->ar.alloc<float>(m);
+        L.d2f = h->ar.alloc<float>(m);
+      }
+      if (l + 1 < nl) {
+        if (fresh) {
+          L.Af = h->ar.alloc<float>(L.A.nnz);
+          L.Pf = h->ar.alloc<float>(L.P.nnz);
+          L.Rf = h->ar.alloc<float>(L.R.nnz);
+          L.sm_invDf = h->ar.alloc<float>(m);
+        }
+        cast_f64_to_f32(L.A.val, L.Af, L.A.nnz, s);
+        cast_f64_to_f32(L.P.val, L.Pf, L.P.nnz, s);
+        cast_f64_to_f32(L.R.val, L.Rf, L.R.nnz, s);
+        cast_f64_to_f32(L.sm_invD, L.sm_invDf, m, s);
+      }
+    }
+  }
+  if (fresh) {
+    h->x = h->ar.alloc<double>(n);
+    h->r = h->ar.alloc<double>(n);
+    h->z = h->ar.alloc<double>(n);
+    h->p = h->ar.alloc<double>(n);
+    h->q = h->ar.alloc<double>(n);
+    h->zold = h->ar.alloc<double>(n);
+    h->w = h->ar.alloc<double>(n);
+    h->tmp64 = h->ar.alloc<double>(std::max<int64_t>(n, kMaxDense));
+    h->dws = h->ar.alloc<double>(dot_ws_size(n));
+    h->S = h->ar.alloc<PcgScalars>(1);
+  }
+  SA_HIP(hipStreamSynchronize(s));
+}
+
+// Nullspace: checks B (n values in `loc` memory); when some entry differs from 1, loads it
+// into h->dB and sets As = D_B A D_B on level 0, otherwise As = A.  Returns h->dB or null.
+static double *apply_nullspace(sa_hierarchy *h, const double *B, sa_location loc) {
+  const hipStream_t s = h->stream;
+  const int32_t n = h->n;
+  Level &L0 = h->lv[0];
+  L0.As = L0.A;
+  if (!B) return nullptr;
+  std::vector<double> hb(n);
+  SA_HIP(hipMemcpyAsync(hb.data(), B, sizeof(double) * n,
+                        loc == SA_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost, s));
+  SA_HIP(hipStreamSynchronize(s));
+  bool scaled = false;
+  for (double v : hb) {
+    if (!(v != 0.0) || !std::isfinite(v))
+      throw Error(SA_ERR_INVALID_ARG, "nullspace entry zero or non-finite");
+    if (v != 1.0) scaled = true;
+  }
+  if (!scaled) return nullptr;
+  if (!h->dB) h->dB = h->ar.alloc<double>(n);
+  if (!h->As0) h->As0 = h->ar.alloc<double>(L0.A.nnz);
+  SA_HIP(hipMemcpyAsync(h->dB, hb.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+  L0.As.val = h->As0;
+  scale_sym(n, L0.A.rp, L0.A.col, L0.A.val, h->dB, L0.As.val, s);
+  SA_HIP(hipStreamSynchronize(s));  // hb goes out of scope
+  return h->dB;
+}
+
+static void validate_values(sa_hierarchy *h) {
+  Level &L0 = h->lv[0];
+  validate_csr(h->n, L0.A.rp, L0.A.col, L0.A.val, h->err, h->stream);
+  const int32_t e = read_err(h);
+  if (e & E_NONFINITE) throw Error(SA_ERR_INVALID_ARG, "non-finite matrix value");
+  if (e & E_STRUCT) throw Error(SA_ERR_BAD_CSR, "columns out of range or not ascending");
+  if (e & E_NODIAG) throw Error(SA_ERR_BAD_CSR, "missing diagonal");
 }
 
 static void setup_impl(sa_hierarchy *h, const sa_csr *A, const double *B) {
@@ -165,35 +359,9 @@ static void setup_impl(sa_hierarchy *h, const sa_csr *A, const double *B) {
   copy_in(L0.A.val, A->val, sizeof(double) * A->nnz, A->loc, s);
   const int32_t rp0 = read1(L0.A.rp, s), rpn = read1(L0.A.rp + n, s);
   if (rp0 != 0 || (int64_t)rpn != A->nnz) throw Error(SA_ERR_BAD_CSR, "row pointers do not span nnz");
-  validate_csr(n, L0.A.rp, L0.A.col, L0.A.val, h->err, s);
-  {
-    const int32_t e = read_err(h);
-    if (e & E_NONFINITE) throw Error(SA_ERR_INVALID_ARG, "non-finite matrix value");
-    if (e & E_STRUCT) throw Error(SA_ERR_BAD_CSR, "columns out of range or not ascending");
-    if (e & E_NODIAG) throw Error(SA_ERR_BAD_CSR, "missing diagonal");
-  }
+  validate_values(h);
   spmv_plan(L0.A, h->ar, s);
-  L0.As = L0.A;
-  double *dB = nullptr;
-  if (B) {
-    std::vector<double> hb(n);
-    SA_HIP(hipMemcpyAsync(hb.data(), B, sizeof(double) * n,
-                          A->loc == SA_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost, s));
-    SA_HIP(hipStreamSynchronize(s));
-    bool scaled = false;
-    for (double v : hb) {
-      if (!(v != 0.0) || !std::isfinite(v))
-        throw Error(SA_ERR_INVALID_ARG, "nullspace entry zero or non-finite");
-      if (v != 1.0) scaled = true;
-    }
-    if (scaled) {
-      dB = h->ar.alloc<double>(n);
-      SA_HIP(hipMemcpyAsync(dB, hb.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
-      L0.As.val = h->ar.alloc<double>(A->nnz);
-      scale_sym(n, L0.A.rp, L0.A.col, L0.A.val, dB, L0.As.val, s);
-      SA_HIP(hipStreamSynchronize(s));  // hb goes out of scope
-    }
-  }
+  const double *dB = apply_nullspace(h, B, A->loc);
   for (int l = 0;; ++l) {
     if (h->lv[l].A.n <= o.max_coarse || l + 1 >= o.max_levels) break;
     if (!build_level(h, l)) {
@@ -204,93 +372,32 @@ static void setup_impl(sa_hierarchy *h, const sa_csr *A, const double *B) {
       Lc.is_root = nullptr;
       break;
     }
-    Level &L = h->lv[l];
-    if (l == 0 && dB) scale_rows(L.P, dB, s);
-    transpose(L.P, h->ar, L.R, s);
-    spmv_plan(L.R, h->ar, s);
-    Csr Ac;
-    {
-      Arena tmp;
-      tmp.stream = s;
-      Csr AP;
-      spgemm(L.A, L.P, tmp, AP, s);
-      spgemm(L.R, AP, h->ar, Ac, s);
-    }
-    spmv_plan(Ac, h->ar, s);
-    h->lv.emplace_back();
-    h->lv[l + 1].A = Ac;
-    h->lv[l + 1].As = Ac;
+    galerkin(h, l, true, dB);
   }
+  finish_setup(h, true);
+  h->setup_seconds = now_s() - t0;
+}
+
+// New values on the setup's pattern: every symbolic decision is kept (strength labels and
+// Sprsfy drops, aggregates, the patterns of the filtered matrices, P, R and every A_l) and
+// the numbers are recomputed in the setup's order, each into the existing arrays.
+static void resetup_impl(sa_hierarchy *h, const double *val, const double *B, sa_location loc) {
+  const double t0 = now_s();
+  const hipStream_t s = h->stream;
+  Level &L0 = h->lv[0];
+  h->valid = false;
+  fill_i32(h->err, 0, 4, s);
+  copy_in(L0.A.val, val, sizeof(double) * L0.A.nnz, loc, s);
+  validate_values(h);
+  const double *dB = apply_nullspace(h, B, loc);
   const int nl = (int)h->lv.size();
   for (int l = 0; l + 1 < nl; ++l) {
-    Level &L = h->lv[l];
-    Arena tmp;
-    tmp.stream = s;
-    double *dval = tmp.alloc<double>(L.A.n);
-    find_diag(L.A.n, L.A.rp, L.A.col, L.A.val, dval, s);
-    L.sm_invD = h->ar.alloc<double>(L.A.n);
-    inv_diag(L.A.n, dval, L.sm_invD, h->err, s);
-    check_err(h, E_DIAG, SA_ERR_NONPOSITIVE_DIAG, "non-positive diagonal in a level operator");
-    L.sm_lam_d = h->ar.alloc<double>(1);
-    power_method(L.A, L.sm_invD, o.power_iters, o.seed, l, 1, L.sm_lam_d, s);
-    const double lam = read1(L.sm_lam_d, s);
-    if (!(lam > 0.0) || !std::isfinite(lam))
-      throw Error(SA_ERR_NEGATIVE_EIGENVALUE, "smoother eigenvalue estimate not positive");
-    L.sm_lam = lam * o.cheb_boost;
-    chebyshev_scalars(L, o);
-    if (L.lam_d) {
-      double lo[2];
-      readback(lo, L.lam_d, sizeof(lo), s);
-      L.lam = lo[0];
-      L.omega = lo[1];
-    }
+    numeric_level(h, l, false);
+    galerkin(h, l, false, dB);
   }
-  Level &Lc = h->lv[nl - 1];
-  if (Lc.A.n > kMaxDense)
-    throw Error(SA_ERR_COARSE_FACTOR, "coarsest level too large for the dense solver");
-  Lc.Ainv = h->ar.alloc<double>((int64_t)Lc.A.n * Lc.A.n);
-  coarse_inverse(Lc.A, Lc.Ainv, h->err, s);
-  check_err(h, E_CHOL, SA_ERR_COARSE_FACTOR, "coarse Cholesky pivot not positive");
-  // FP32 copies of the hierarchy for the FP32 V-cycle
-  const bool f32 = o.precision == SA_FP32_VCYCLE;
-  for (int l = 0; l < nl; ++l) {
-    Level &L = h->lv[l];
-    const int32_t m = L.A.n;
-    L.f = h->ar.alloc<double>(m);
-    L.u = h->ar.alloc<double>(m);
-    L.r = h->ar.alloc<double>(m);
-    L.d1 = h->ar.alloc<double>(m);
-    L.d2 = h->ar.alloc<double>(m);
-    if (f32) {
-      L.ff = h->ar.alloc<float>(m);
-      L.uf = h->ar.alloc<float>(m);
-      L.rf = h->ar.alloc<float>(m);
-      L.d1f = h->ar.alloc<float>(m);
-      L.d2f = h->ar.alloc<float>(m);
-      if (l + 1 < nl) {
-        L.Af = h->ar.alloc<float>(L.A.nnz);
-        cast_f64_to_f32(L.A.val, L.Af, L.A.nnz, s);
-        L.Pf = h->ar.alloc<float>(L.P.nnz);
-        cast_f64_to_f32(L.P.val, L.Pf, L.P.nnz, s);
-        L.Rf = h->ar.alloc<float>(L.R.nnz);
-        cast_f64_to_f32(L.R.val, L.Rf, L.R.nnz, s);
-        L.sm_invDf = h->ar.alloc<float>(m);
-        cast_f64_to_f32(L.sm_invD, L.sm_invDf, m, s);
-      }
-    }
-  }
-  h->x = h->ar.alloc<double>(n);
-  h->r = h->ar.alloc<double>(n);
-  h->z = h->ar.alloc<double>(n);
-  h->p = h->ar.alloc<double>(n);
-  h->q = h->ar.alloc<double>(n);
-  h->zold = h->ar.alloc<double>(n);
-  h->w = h->ar.alloc<double>(n);
-  h->tmp64 = h->ar.alloc<double>(std::max<int64_t>(n, kMaxDense));
-  h->dws = h->ar.alloc<double>(dot_ws_size(n));
-  h->S = h->ar.alloc<PcgScalars>(1);
-  SA_HIP(hipStreamSynchronize(s));
+  finish_setup(h, false);
   h->setup_seconds = now_s() - t0;
+  h->valid = true;
 }
 
 // ---- fine-level SpMV timing ------------------------------------------------------------------
@@ -474,6 +581,7 @@ static void precondition(sa_hierarchy *h, const double *r, double *z) {
 
 static sa_status solve_impl(sa_hierarchy *h, const double *b, double *x, sa_location loc,
                             int32_t *iterations, double *relres) {
+  if (!h->valid) throw Error(SA_ERR_INVALID_ARG, "hierarchy left unusable by a failed re-setup");
   const hipStream_t s = h->stream;
   const sa_options &o = h->opt;
   const int32_t n = h->n;
@@ -625,6 +733,20 @@ sa_status sa_setup(const sa_context *ctx, const sa_csr *A, const double *nullspa
       throw;
     }
     *out = h.release();
+    return SA_OK;
+  });
+}
+
+sa_status sa_resetup(sa_hierarchy *h, const double *val, const double *nullspace,
+                     sa_location loc) {
+  if (!h || !val || h->lv.empty()) return SA_ERR_INVALID_ARG;
+  return guarded([&]() -> sa_status {
+    try {
+      resetup_impl(h, val, nullspace, loc);
+    } catch (...) {
+      (void)hipStreamSynchronize(h->stream);
+      throw;
+    }
     return SA_OK;
   });
 }

@@ -16,6 +16,7 @@ struct Level {
   uint8_t *is_root = nullptr;
   int32_t nc = 0;
   int32_t mis_rounds = 0;
+  bool wave_rows = false;  // rows long enough for the wavefront-per-row setup kernels
   Csr Abar;
   double *invD = nullptr;
   double *lam_d = nullptr, *omega_d = nullptr;
@@ -44,6 +45,9 @@ struct sa_hierarchy {
   std::vector<sa::Level> lv;
   int32_t *err = nullptr;
   double setup_seconds = 0.0;
+  bool valid = true;            // false after a failed re-setup
+  double *dB = nullptr;         // nullspace vector (when it is not all ones)
+  double *As0 = nullptr;        // D_B A D_B values on level 0 (when scaled)
   // solve workspace
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *zold = nullptr,
          *w = nullptr, *dws = nullptr, *tmp64 = nullptr;

@@ -776,7 +776,7 @@ extern "C" sa_status sa_solve_many(sa_hierarchy *const *hs, int32_t count,
   if (count < 0 || (count > 0 && (!hs || !b || !x || !status))) return SA_ERR_INVALID_ARG;
   if (count == 0) return SA_OK;
   for (int32_t k = 0; k < count; ++k)
-    if (!hs[k] || !b[k] || !x[k]) return SA_ERR_INVALID_ARG;
+    if (!hs[k] || !b[k] || !x[k] || !hs[k]->valid) return SA_ERR_INVALID_ARG;
   try {
     sa::BatchSolver bs(hs[0]->stream);
     std::vector<sa::BatchSystem> sys((size_t)count);

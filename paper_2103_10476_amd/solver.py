@@ -119,6 +119,17 @@ class Hierarchy:
     def from_problem(cls, p, nullspace=None, options=None, stream=None):
         return cls(p.n, p.rp, p.col, p.val, nullspace=nullspace, options=options, stream=stream)
 
+    # ---- numeric re-setup ---------------------------------------------------------------
+    def resetup(self, val, nullspace=None):
+        """New matrix values on the setup's pattern (sa_resetup): keeps strength labels,
+        aggregates and every sparsity pattern, recomputes all numbers."""
+        torch = _torch()
+        dval = _dev(val, torch.float64)
+        dB = None if nullspace is None else _dev(nullspace, torch.float64)
+        _lib.check(_lib.lib().sa_resetup(self._h, C.c_void_p(dval.data_ptr()),
+                                         None if dB is None else C.c_void_p(dB.data_ptr()),
+                                         _lib.SA_DEVICE), "sa_resetup")
+
     # ---- solve ------------------------------------------------------------------------
     def solve(self, b, x=None):
         """CG + V-cycle; b may be numpy or a CUDA tensor.  Returns (x, iterations, relres,
