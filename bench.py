@@ -200,6 +200,7 @@ def main():
     if not args.no_extras:
         result["fp32_vcycle_vs_fp64"] = precision_leg(solver, problems, PRECISION_WORKLOAD)
         result["variants"] = variants_leg(solver, p, drp, dcol, dval, db)
+        result["numeric_resetup"] = resetup_leg(solver, p, drp, dcol, dval, db)
         result["serving"] = serving_leg(solver, problems, args)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(p, b)
@@ -339,6 +340,47 @@ def variants_leg(solver, p, drp, dcol, dval, db):
         except Exception as e:  # a variant may fail on a problem (reported, not fatal)
             out[name] = {"status": str(e)[:120]}
     return out
+
+
+def resetup_leg(solver, p, drp, dcol, dval, db, reps=5):
+    """Numeric re-setup on the same workload: new values D A D (D a seeded positive diagonal)
+    on the setup's pattern, every symbolic decision of the setup kept; p50/p99 of the
+    re-setup and of the following solve, next to a fresh setup on the same new values."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(31))
+    d = rng.uniform(0.5, 2.0, size=p.n)
+    rows = np.repeat(np.arange(p.n), np.diff(p.rp))
+    val2 = torch.from_numpy((d[rows] * p.val) * d[p.col]).cuda()
+    o = solver.Options(theta=0.02, rtol=1e-8)
+    h = solver.Hierarchy(p.n, drp, dcol, dval, options=o)
+    h.resetup(val2)  # warm-up
+    re, so = [], []
+    for k in range(reps):
+        h.resetup(dval if k % 2 else val2)  # alternate between the two value sets
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.resetup(val2)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, it, _, st = h.solve(db)
+        torch.cuda.synchronize()
+        re.append(t1 - t0)
+        so.append(time.perf_counter() - t1)
+    h.close()
+    fr = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = solver.Hierarchy(p.n, drp, dcol, val2, options=o)
+        torch.cuda.synchronize()
+        fr.append(time.perf_counter() - t0)
+        g.close()
+    return {"values": "D A D, D_i ~ U(0.5, 2) seeded", "iterations": it, "status": st,
+            "resetup_s": {"p50": round(pct(re, 50), 5), "p99": round(pct(re, 99), 5)},
+            "solve_s": {"p50": round(pct(so, 50), 5), "p99": round(pct(so, 99), 5)},
+            "fresh_setup_same_values_s": {"p50": round(pct(fr, 50), 5),
+                                          "p99": round(pct(fr, 99), 5)},
+            "speedup_vs_setup": round(pct(fr, 50) / pct(re, 50), 3)}
 
 
 def _build_requests(problems, count):
