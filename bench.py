@@ -197,14 +197,41 @@ def main():
     sb = solve_bytes_model(info) * (it + 1)
     result["solve_hbm_gbs"] = round(sb / pct(solves, 50) / 1e9, 1)
     result["roofline"] = roofline(prof_totals, args.workload)
+    if result["roofline"] is not None:
+        result["roofline"]["stream_probe_gbs"] = stream_probe()
     if not args.no_extras:
         result["fp32_vcycle_vs_fp64"] = precision_leg(solver, problems, PRECISION_WORKLOAD)
         result["variants"] = variants_leg(solver, p, drp, dcol, dval, db)
         result["numeric_resetup"] = resetup_leg(solver, p, drp, dcol, dval, db)
+        result["variant_sweep"] = variant_sweep_leg(solver, problems)
         result["serving"] = serving_leg(solver, problems, args)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(p, b)
     print(json.dumps(result), flush=True)
+
+
+def stream_probe(nbytes=512 << 20, reps=10):
+    """Achievable HBM bandwidth on this device, for context beside the 8 TB/s spec: a device
+    copy of 512 MiB (bytes read + written) and a full read (a sum over 512 MiB), timed with
+    events on the current stream."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    out = {}
+    for name, fn, moved in (("copy_read_write", lambda: b.copy_(a), 2 * nbytes),
+                            ("read", lambda: a.sum(), nbytes)):
+        fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        out[name] = round(moved * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    return out
 
 
 def kernel_source_hash():
@@ -339,6 +366,54 @@ def variants_leg(solver, p, drp, dcol, dval, db):
             h.close()
         except Exception as e:  # a variant may fail on a problem (reported, not fatal)
             out[name] = {"status": str(e)[:120]}
+    return out
+
+
+def variant_sweep_leg(solver, problems):
+    """The 16 combinations of Sprsfy, OffLmp, 1Norm and Cnstrnt (the paper's Table 1 layout:
+    CG iterations and operator complexity per combination), rtol 1e-10, on the Sec. 1.2
+    stress problem (Q1 on 1x1x2 boxes, 24^3 unknowns, theta 0.15), the 128^3 z-stretched
+    cube and the 100^3 random-kappa Q1 cube (theta 0.02).  A failing combination is reported
+    with its status (the paper's negative-eigenvalue / small-diagonal failures)."""
+    import itertools
+    from fractions import Fraction
+    import torch
+    names = ("sprsfy", "offlmp", "1norm", "cnstrnt")
+    cases = [("stress_box_24_theta0.15", problems.q1_stretched_box(24, Fraction(2)), 0.15, 7),
+             ("fd7_128_a1000", problems.workload("fd7_128_a1000"), 0.02, 2),
+             ("q1_100_randkappa", problems.workload("q1_100_randkappa"), 0.02, 4)]
+    out = {}
+    for cname, p, theta, seed in cases:
+        b = torch.from_numpy(problems.random_rhs(p.n, seed)).cuda()
+        drp = torch.from_numpy(p.rp).cuda()
+        dcol = torch.from_numpy(p.col).cuda()
+        dval = torch.from_numpy(p.val).cuda()
+        table = {}
+        for bits in itertools.product((0, 1), repeat=4):
+            var = tuple(n for n, on in zip(names, bits) if on)
+            key = "+".join(var) or "plain"
+            o = solver.Options(theta=theta, rtol=1e-10, variants=var)
+            try:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                h = solver.Hierarchy(p.n, drp, dcol, dval, options=o)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                _, it, _, st = h.solve(b)
+                torch.cuda.synchronize()
+                inf = h.info()
+                table[key] = {"iterations": it, "operator_complexity":
+                              round(inf["operator_complexity"], 4), "levels": inf["levels"],
+                              "status": st, "setup_s": round(t1 - t0, 4),
+                              "solve_s": round(time.perf_counter() - t1, 4)}
+                h.close()
+            except Exception as e:
+                table[key] = {"status": str(e).split(":")[1].split("(")[0].strip()
+                              if ":" in str(e) else str(e)[:80]}
+        out[cname] = {"n": p.n, "nnz": p.nnz, "table": table}
+        log(f"[bench] variant sweep {cname}: " + ", ".join(
+            f"{k} {v.get('iterations', v['status'])}" for k, v in table.items()))
+        del drp, dcol, dval, b
     return out
 
 

@@ -1,6 +1,7 @@
-// Coarsest level (Sec. 3.1: a direct solve once the hierarchy reaches <= 1000 unknowns):
-// dense Cholesky A_L = L L^T in one workgroup, L^{-1} by forward substitution (one column per
-// thread), and A_L^{-1} = L^{-T} L^{-1} on the FP64 matrix cores (v_mfma_f64_16x16x4f64).
+// Coarsest level (Sec. 3.1: a direct solve once the hierarchy reaches <= 1000 unknowns, or
+// a level left without strong connections): blocked dense Cholesky A_L = L L^T with the
+// trailing updates on the FP64 matrix cores, L^{-1} by blocks (the off-diagonal blocks on
+// the matrix cores), and A_L^{-1} = L^{-T} L^{-1} on the matrix cores (v_mfma_f64_16x16x4f64).
 // The V-cycle then applies A_L^{-1} as a dense GEMV.  The factor's rounding order differs
 // from a sequential Cholesky, so this is the one setup result that matches a CPU reference
 // to rounding (~1e-16 relative) rather than bit for bit.
@@ -18,49 +19,215 @@ __global__ void k_dense_scatter(int32_t n, int32_t ld, const int32_t *rp, const 
   for (int32_t k = rp[i]; k < rp[i + 1]; ++k) D[(int64_t)i * ld + col[k]] = val[k];
 }
 
-// Right-looking Cholesky on the lower triangle of D (row-major, leading dimension ld).
-__global__ __launch_bounds__(1024) void k_cholesky(int32_t n, int32_t ld, double *D,
-                                                   int32_t *err) {
-  __shared__ double s_ljj;
+// ---- blocked right-looking Cholesky, 64 x 64 blocks ---------------------------------------
+// D is ld x ld row-major (ld a multiple of 64) and holds the matrix in its lower triangle;
+// rows and columns n..ld-1 are an identity pad, so every block is full.  Step kb factors the
+// diagonal block, solves the panel below it, and updates the trailing lower triangle on the
+// FP64 matrix cores.  The factor's rounding order differs from the sequential textbook
+// Cholesky; the result is checked against a dense inverse to ~1e-16 relative.
+constexpr int kNB = 64;
+
+__global__ void k_pad_identity(int32_t n, int32_t ld, double *D) {
+  const int32_t i = n + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ld) D[(int64_t)i * ld + i] = 1.0;
+}
+
+// Diagonal block at (k0, k0): unblocked right-looking Cholesky in LDS (err bit 64 on a
+// pivot <= 0).
+__global__ __launch_bounds__(256) void k_potrf_diag(int32_t ld, int32_t k0, double *D,
+                                                    int32_t *err) {
+  __shared__ double a[kNB][kNB + 1];
   const int tid = threadIdx.x;
-  for (int32_t j = 0; j < n; ++j) {
+  for (int q = tid; q < kNB * kNB; q += 256) {
+    const int i = q / kNB, j = q % kNB;
+    a[i][j] = (j <= i) ? D[(int64_t)(k0 + i) * ld + k0 + j] : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < kNB; ++j) {
     if (tid == 0) {
-      const double d = D[(int64_t)j * ld + j];
+      const double d = a[j][j];
       if (!(d > 0.0)) atomicOr(err, 64);
-      s_ljj = sqrt(d);
-      D[(int64_t)j * ld + j] = s_ljj;
+      a[j][j] = sqrt(d);
     }
     __syncthreads();
-    const double ljj = s_ljj;
-    for (int32_t i = j + 1 + tid; i < n; i += blockDim.x) D[(int64_t)i * ld + j] /= ljj;
+    const double ljj = a[j][j];
+    for (int i = j + 1 + tid; i < kNB; i += 256) a[i][j] /= ljj;
     __syncthreads();
-    // trailing update of the lower triangle: D[i][k] -= D[i][j] * D[k][j], j < k <= i
-    const int32_t m = n - j - 1;
-    const int64_t tri = (int64_t)m * (m + 1) / 2;
-    for (int64_t t = tid; t < tri; t += blockDim.x) {
-      // t -> (a, b) with 0 <= b <= a < m, row-major over the triangle
-      int32_t a = (int32_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-      while ((int64_t)a * (a + 1) / 2 > t) --a;
-      while ((int64_t)(a + 1) * (a + 2) / 2 <= t) ++a;
-      const int32_t b = (int32_t)(t - (int64_t)a * (a + 1) / 2);
-      const int32_t i = j + 1 + a, k = j + 1 + b;
-      D[(int64_t)i * ld + k] -= D[(int64_t)i * ld + j] * D[(int64_t)k * ld + j];
+    for (int q = tid; q < kNB * kNB; q += 256) {
+      const int i = q / kNB, k = q % kNB;
+      if (k > j && k <= i) a[i][k] -= a[i][j] * a[k][j];
     }
     __syncthreads();
+  }
+  for (int q = tid; q < kNB * kNB; q += 256) {
+    const int i = q / kNB, j = q % kNB;
+    if (j <= i) D[(int64_t)(k0 + i) * ld + k0 + j] = a[i][j];
   }
 }
 
-// Column c of L^{-1} (lower triangular), written into Li (row-major, leading dim ld).
-__global__ void k_trinv(int32_t n, int32_t ld, const double *L, double *Li) {
-  const int64_t c64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c64 >= n) return;
-  const int32_t c = (int32_t)c64;
-  Li[(int64_t)c * ld + c] = 1.0 / L[(int64_t)c * ld + c];
-  for (int32_t i = c + 1; i < n; ++i) {
-    double s = 0.0;
-    for (int32_t k = c; k < i; ++k) s += L[(int64_t)i * ld + k] * Li[(int64_t)k * ld + c];
-    Li[(int64_t)i * ld + c] = -s / L[(int64_t)i * ld + i];
+// Panel below the diagonal block: row i of L in columns k0..k0+63 solves x L_kk^T = d by
+// forward substitution (one thread per row, the 64 unknowns in registers).
+__global__ __launch_bounds__(256) void k_trsm_panel(int32_t ld, int32_t k0, double *D) {
+  __shared__ double lk[kNB][kNB + 1];
+  const int tid = threadIdx.x;
+  for (int q = tid; q < kNB * kNB; q += 256) {
+    const int i = q / kNB, j = q % kNB;
+    lk[i][j] = (j <= i) ? D[(int64_t)(k0 + i) * ld + k0 + j] : 0.0;
   }
+  __syncthreads();
+  const int64_t i = (int64_t)k0 + kNB + (int64_t)blockIdx.x * 256 + tid;
+  if (i >= ld) return;
+  double *row = D + i * ld + k0;
+  double x[kNB];
+#pragma unroll
+  for (int j = 0; j < kNB; ++j) x[j] = row[j];
+#pragma unroll
+  for (int j = 0; j < kNB; ++j) {
+    double t = x[j];
+#pragma unroll
+    for (int m = 0; m < j; ++m) t -= x[m] * lk[j][m];
+    x[j] = t / lk[j][j];
+  }
+#pragma unroll
+  for (int j = 0; j < kNB; ++j) row[j] = x[j];
+}
+
+// Trailing update after step kb: D[ib][jb] -= L[ib][kb] L[jb][kb]^T for every block pair
+// kb < jb <= ib < nbk (workgroup t = the t-th pair, row-major over the lower triangle).  The
+// two 64 x 64 panels are staged in LDS; each of the 4 wavefronts computes a 16 x 64 strip
+// as four 16 x 16 tiles with v_mfma_f64_16x16x4f64 (lane l supplies A[l%16][l/16] and
+// B[l/16][l%16] and receives D[4v + l/16][l%16] in result register v).  Diagonal blocks are
+// updated whole; their upper parts are never read.
+__global__ __launch_bounds__(256) void k_syrk_mfma(int32_t ld, int32_t kb, int32_t nbk,
+                                                   double *D) {
+  __shared__ double As[kNB][kNB + 1];
+  __shared__ double Bs[kNB][kNB + 1];
+  const int64_t t = blockIdx.x;
+  int32_t a = (int32_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((int64_t)a * (a + 1) / 2 > t) --a;
+  while ((int64_t)(a + 1) * (a + 2) / 2 <= t) ++a;
+  const int32_t b = (int32_t)(t - (int64_t)a * (a + 1) / 2);
+  const int32_t ib = kb + 1 + a, jb = kb + 1 + b;
+  if (ib >= nbk || jb > ib) return;  // block-uniform; the grid holds exactly the pairs
+  const int64_t r0 = (int64_t)ib * kNB, c0 = (int64_t)jb * kNB, k0 = (int64_t)kb * kNB;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < kNB * kNB; q += 256) {
+    const int r = q / kNB, k = q % kNB;
+    As[r][k] = D[(r0 + r) * ld + k0 + k];
+    Bs[r][k] = D[(c0 + r) * ld + k0 + k];
+  }
+  __syncthreads();
+  const int w = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < kNB; kk += 4) {
+      const double av = As[16 * w + lr][kk + lk];
+      const double bv = Bs[16 * ct + lr][kk + lk];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = r0 + 16 * w + 4 * v + lk;
+      const int64_t col = c0 + 16 * ct + lr;
+      D[row * ld + col] -= acc[v];
+    }
+  }
+}
+
+// ---- blocked inverse of the triangular factor, Li = L^{-1} ------------------------------------
+// Step 0 inverts every 64 x 64 diagonal block; step d computes every block at distance d below
+// the diagonal, Li[ib][kb] = -Li[ib][ib] * sum_{kb <= jb < ib} L[ib][jb] Li[jb][kb] (ib = kb+d),
+// from blocks of earlier steps: all column blocks advance together, one launch per step.
+
+// 64 x 64 product on the matrix cores: wavefront w accumulates rows 16w..16w+15 of As * Bs
+// (As[r][k] = A[r][k], Bs[k][c] = B[k][c]) into acc[ct] for column tile ct.
+__device__ __forceinline__ void mfma_64(const double (*As)[kNB + 1], const double (*Bs)[kNB + 1],
+                                        v4d *acc) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+#pragma unroll
+    for (int kk = 0; kk < kNB; kk += 4) {
+      const double av = As[16 * w + lr][kk + lk];
+      const double bv = Bs[kk + lk][16 * ct + lr];
+      acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[ct], 0, 0, 0);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_trtri_diag(int32_t ld, const double *L, double *Li) {
+  __shared__ double l[kNB][kNB + 1];
+  __shared__ double x[kNB][kNB + 1];
+  const int tid = threadIdx.x;
+  const int64_t k0 = (int64_t)blockIdx.x * kNB;
+  for (int q = tid; q < kNB * kNB; q += 256) {
+    const int i = q / kNB, j = q % kNB;
+    l[i][j] = (j <= i) ? L[(k0 + i) * ld + k0 + j] : 0.0;
+    x[i][j] = 0.0;
+  }
+  __syncthreads();
+  if (tid < kNB) {  // column c of the block's inverse by forward substitution
+    const int c = tid;
+    x[c][c] = 1.0 / l[c][c];
+    for (int i = c + 1; i < kNB; ++i) {
+      double t = 0.0;
+      for (int k = c; k < i; ++k) t += l[i][k] * x[k][c];
+      x[i][c] = -t / l[i][i];
+    }
+  }
+  __syncthreads();
+  for (int q = tid; q < kNB * kNB; q += 256) {
+    const int i = q / kNB, j = q % kNB;
+    Li[(k0 + i) * ld + k0 + j] = x[i][j];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_trinv_step(int32_t ld, int32_t d, const double *L,
+                                                    double *Li) {
+  __shared__ double As[kNB][kNB + 1];
+  __shared__ double Bs[kNB][kNB + 1];
+  const int tid = threadIdx.x;
+  const int32_t kb = blockIdx.x, ib = kb + d;  // the grid holds kb = 0 .. nbk-d-1
+  const int64_t r0 = (int64_t)ib * kNB, c0 = (int64_t)kb * kNB;
+  v4d acc[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int32_t jb = kb; jb < ib; ++jb) {
+    const int64_t j0 = (int64_t)jb * kNB;
+    for (int q = tid; q < kNB * kNB; q += 256) {
+      const int r = q / kNB, k = q % kNB;
+      As[r][k] = L[(r0 + r) * ld + j0 + k];   // L[ib][jb]
+      Bs[r][k] = Li[(j0 + r) * ld + c0 + k];  // Li[jb][kb]
+    }
+    __syncthreads();
+    mfma_64(As, Bs, acc);
+    __syncthreads();
+  }
+  // T = the sum, into Bs; then Li[ib][kb] = -Li[ib][ib] T
+  const int w = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Bs[16 * w + 4 * v + lk][16 * ct + lr] = acc[ct][v];
+  for (int q = tid; q < kNB * kNB; q += 256) {
+    const int r = q / kNB, k = q % kNB;
+    As[r][k] = Li[(r0 + r) * ld + r0 + k];  // Li[ib][ib] (zero above its diagonal)
+  }
+  __syncthreads();
+  v4d out[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) out[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+  mfma_64(As, Bs, out);
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      Li[(r0 + 16 * w + 4 * v + lk) * ld + c0 + 16 * ct + lr] = -out[ct][v];
 }
 
 // C = Li^T Li on 16x16 tiles, one wavefront per tile, K in steps of 4.  Operand layout of
@@ -90,17 +257,32 @@ __global__ __launch_bounds__(64) void k_gram_mfma(int32_t n, int32_t ld, const d
 void coarse_inverse(const Csr &A, double *Ainv, int32_t *err, hipStream_t s) {
   const int32_t n = A.n;
   if (n <= 0) return;
-  const int32_t ld = (int32_t)ceil_div(n, 16) * 16;
-  const size_t sz = sizeof(double) * (size_t)ld * ld;
-  double *D = (double *)dev_alloc(sz, s);
-  double *Li = (double *)dev_alloc(sz, s);
-  SA_HIP(hipMemsetAsync(D, 0, sz, s));
-  SA_HIP(hipMemsetAsync(Li, 0, sz, s));
+  const int32_t ld = (int32_t)ceil_div(n, kNB) * kNB;
+  const int32_t nbk = ld / kNB;
+  const int64_t cnt = (int64_t)ld * ld;
+  double *D = (double *)dev_alloc(sizeof(double) * (size_t)cnt, s);
+  double *Li = (double *)dev_alloc(sizeof(double) * (size_t)cnt, s);
+  fill_f64(D, 0.0, cnt, s);
+  fill_f64(Li, 0.0, cnt, s);
   k_dense_scatter<<<grid_for(n), kBlock, 0, s>>>(n, ld, A.rp, A.col, A.val, D);
   SA_LAUNCH_CHECK();
-  k_cholesky<<<1, 1024, 0, s>>>(n, ld, D, err);
-  SA_LAUNCH_CHECK();
-  k_trinv<<<grid_for(n, 64), 64, 0, s>>>(n, ld, D, Li);
+  if (ld > n) {
+    k_pad_identity<<<grid_for(ld - n), kBlock, 0, s>>>(n, ld, D);
+    SA_LAUNCH_CHECK();
+  }
+  for (int32_t kb = 0; kb < nbk; ++kb) {
+    const int32_t k0 = kb * kNB;
+    k_potrf_diag<<<1, 256, 0, s>>>(ld, k0, D, err);
+    const int32_t below = ld - k0 - kNB;
+    if (below > 0) {
+      k_trsm_panel<<<(unsigned)ceil_div(below, 256), 256, 0, s>>>(ld, k0, D);
+      const int64_t m = nbk - kb - 1;
+      k_syrk_mfma<<<(unsigned)(m * (m + 1) / 2), 256, 0, s>>>(ld, kb, nbk, D);
+    }
+    SA_LAUNCH_CHECK();
+  }
+  k_trtri_diag<<<(unsigned)nbk, 256, 0, s>>>(ld, D, Li);
+  for (int32_t d = 1; d < nbk; ++d) k_trinv_step<<<(unsigned)(nbk - d), 256, 0, s>>>(ld, d, D, Li);
   SA_LAUNCH_CHECK();
   dim3 g(ld / 16, ld / 16);
   k_gram_mfma<<<g, 64, 0, s>>>(n, ld, Li, Ainv);

@@ -130,3 +130,42 @@ def test_determinism_run_to_run():
     xa = a.solve(pb.random_rhs(p.n, 1))[0].cpu().numpy()
     xb = b.solve(pb.random_rhs(p.n, 1))[0].cpu().numpy()
     assert np.array_equal(xa, xb)
+
+
+def test_large_coarsest_level_blocked_factor():
+    """A single-level hierarchy of 1331 unknowns: the dense coarsest solve runs the blocked
+    Cholesky over 21 64-wide blocks plus an identity pad; one iteration solves."""
+    p = pb.fd7_stretched(11, 100.0)
+    g, h = run_both(p, theta=0.02, max_coarse=2000, rtol=1e-10)
+    compare_setup(g, h)
+    compare_solve(g, h, pb.random_rhs(p.n, 3))
+
+
+def test_no_strong_level_of_4608_becomes_dense_coarsest():
+    """Stress box 24^3, theta 0.15, 1Norm + Cnstrnt: level 1 (4608 unknowns) has no strong
+    connection and becomes the coarsest; its dense factor must be fast and exact to rounding
+    (checked against numpy's inverse of the exported operator)."""
+    import time
+    from fractions import Fraction
+    import numpy as np
+    from paper_2103_10476_amd import solver
+    p = pb.q1_stretched_box(24, Fraction(2))
+    t0 = time.perf_counter()
+    g = solver.Hierarchy.from_problem(
+        p, options=solver.Options(theta=0.15, variants=("1norm", "cnstrnt"), rtol=1e-10))
+    t = time.perf_counter() - t0
+    info = g.info()
+    assert info["levels"] == 2 and info["n"][1] == 4608, info["n"]
+    rp, col, val = g.export_csr(1, "A")
+    n = info["n"][1]
+    A = np.zeros((n, n))
+    A[np.repeat(np.arange(n), np.diff(rp)), col] = val
+    inv = g.export(1, "coarse_inv").reshape(n, n)
+    ref = np.linalg.inv(A)
+    err = np.abs(inv - ref).max() / np.abs(ref).max()
+    x, it, rr, st = g.solve(pb.random_rhs(p.n, 7))
+    log(f"[parity] 4608 dense coarsest: setup {t * 1e3:.0f} ms, inverse err {err:.1e}, "
+        f"{it} its {st}")
+    assert err <= 1e-11 * max(1.0, np.linalg.cond(A) / 1e4)
+    assert st == "SA_OK"
+    assert t < 2.0
