@@ -46,6 +46,12 @@ const char *orc_last_error(void);
 /* ---- whole method ---- */
 int orc_setup(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
               const double *nullspace /* NULL = ones */, const orc_options *o, void **h);
+/* the same with the distance-Laplacian strength (Sec. 3.1): coords[n*dim] node coordinates
+ * (row-major, dim 1..3); coarse levels take their aggregates' centroids; coords == NULL is
+ * orc_setup */
+int orc_setup_coords(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                     const double *nullspace, const double *coords, int32_t dim,
+                     const orc_options *o, void **h);
 /* numeric re-setup: new values (nnz of the setup's matrix, its CSR order), same symbolic
  * decisions (strength labels, Sprsfy drops, aggregates, patterns) */
 int orc_resetup(void *h, const double *val, const double *nullspace /* NULL = ones */);
@@ -56,7 +62,8 @@ int orc_level_sizes(const void *h, int lvl, int64_t *sizes);
 int orc_level_scalars(const void *h, int lvl, double *scal);
 /* what: 0 A.rp 1 A.col 2 A.val 3 mask(u8) 4 agg(i32) 5 is_root(u8) 6 Abar.rp 7 Abar.col
  *       8 Abar.val 9 invD(f64) 10 P.rp 11 P.col 12 P.val 13 R.rp 14 R.col 15 R.val
- *       16 smoother invD(f64) 17 setup matrix (scaled) .val                              */
+ *       16 smoother invD(f64) 17 setup matrix (scaled) .val 18 coordinates (n*dim f64,
+ *       distance strength only)                                                          */
 int orc_export(const void *h, int lvl, int what, void *buf);
 int orc_vcycle(const void *h, const double *f, double *u);
 int orc_solve(const void *h, const double *b, double *x, int32_t *iters, double *relres,
@@ -66,6 +73,8 @@ void orc_destroy(void *h);
 /* ---- single steps (inputs given explicitly) ---- */
 int orc_strength(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
                  double theta, uint8_t *mask);
+int orc_distance_strength(int32_t n, const int32_t *rp, const int32_t *col,
+                          const double *coords, int32_t dim, double theta, uint8_t *mask);
 int orc_aggregate(int32_t n, const int32_t *rp, const int32_t *col, const uint8_t *mask,
                   int32_t order, uint64_t seed, int32_t level, int32_t *agg, uint8_t *is_root,
                   int32_t *nc);

@@ -44,6 +44,8 @@ def _setup_prototypes(L):
     L.orc_default_options.argtypes = [C.POINTER(OrcOptions)]
     L.orc_last_error.restype = C.c_char_p
     L.orc_setup.argtypes = [C.c_int32, P, P, P, P, C.POINTER(OrcOptions), C.POINTER(C.c_void_p)]
+    L.orc_setup_coords.argtypes = [C.c_int32, P, P, P, P, P, C.c_int32,
+                                   C.POINTER(OrcOptions), C.POINTER(C.c_void_p)]
     L.orc_resetup.argtypes = [P, P, P]
     L.orc_resetup.restype = C.c_int
     L.orc_num_levels.argtypes = [P]
@@ -54,6 +56,7 @@ def _setup_prototypes(L):
     L.orc_solve.argtypes = [P, P, P, P, P, P]
     L.orc_destroy.argtypes = [P]
     L.orc_strength.argtypes = [C.c_int32, P, P, P, C.c_double, P]
+    L.orc_distance_strength.argtypes = [C.c_int32, P, P, P, C.c_int32, C.c_double, P]
     L.orc_aggregate.argtypes = [C.c_int32, P, P, P, C.c_int32, C.c_uint64, C.c_int32, P, P, P]
     L.orc_sprsfy.argtypes = [C.c_int32, P, P, P, P, P, C.c_int32]
     L.orc_lump.argtypes = [C.c_int32, P, P, P, P, C.c_int32, C.c_double, P, P, P]
@@ -133,13 +136,20 @@ class Level:
 class OracleHierarchy:
     """Runs the oracle setup; every level's arrays are exported into numpy."""
 
-    def __init__(self, n, rp, col, val, nullspace=None, **opts):
+    def __init__(self, n, rp, col, val, nullspace=None, coords=None, **opts):
+        """``coords`` (n x dim, dim 1..3) selects the distance-Laplacian strength."""
         self.opts = make_options(**opts)
         self._keep = (_i32(rp), _i32(col), _f64(val))
         B = None if nullspace is None else _f64(nullspace)
+        X, self.dim = None, 0
+        if coords is not None:
+            X = _f64(coords).reshape(n, -1)
+            self.dim = X.shape[1]
         h = C.c_void_p()
-        _check(lib().orc_setup(n, _p(self._keep[0]), _p(self._keep[1]), _p(self._keep[2]),
-                               None if B is None else _p(B), C.byref(self.opts), C.byref(h)))
+        _check(lib().orc_setup_coords(n, _p(self._keep[0]), _p(self._keep[1]),
+                                      _p(self._keep[2]), None if B is None else _p(B),
+                                      None if X is None else _p(X), self.dim,
+                                      C.byref(self.opts), C.byref(h)))
         self.h = h
         self.levels = [self._export(l) for l in range(lib().orc_num_levels(h))]
 
@@ -172,6 +182,8 @@ class OracleHierarchy:
             lv.sm_invD = ex(16, n, np.float64)
             lv.As_val = ex(17, nnz, np.float64)
             lv.lam, lv.omega, lv.sm_lam = float(sc[0]), float(sc[1]), float(sc[2])
+        if self.dim:
+            lv.coords = ex(18, n * self.dim, np.float64).reshape(n, self.dim)
         return lv
 
     @property
@@ -222,6 +234,13 @@ def strength(n, rp, col, val, theta):
     m = np.empty(int(rp[n]), dtype=np.uint8)
     rp, col, val = _i32(rp), _i32(col), _f64(val)
     _check(lib().orc_strength(n, _p(rp), _p(col), _p(val), theta, _p(m)))
+    return m
+
+
+def distance_strength(n, rp, col, coords, theta):
+    rp, col, X = _i32(rp), _i32(col), _f64(coords).reshape(n, -1)
+    m = np.empty(int(rp[n]), dtype=np.uint8)
+    _check(lib().orc_distance_strength(n, _p(rp), _p(col), _p(X), X.shape[1], theta, _p(m)))
     return m
 
 

@@ -184,6 +184,66 @@ void strength(const Csr &A, double theta, std::vector<uint8_t> &mask) {
   }
 }
 
+// ------------------------------------------------------------------------------------
+// Distance-Laplacian strength (Sec. 3.1): the labels come from a matrix L with A's pattern,
+// off-diagonals -w_ij with w_ij from the distance between the coordinates of i and j, and
+// the diagonal making each row sum zero; (i,j) is strong iff |L_ij| >= theta sqrt(L_ii L_jj).
+// Readings: w_ij = 1/|x_i - x_j|^2 (the reciprocal of the squared Euclidean distance, so no
+// square root enters the labels), the squared distance summed over the coordinates in order
+// from 0.0; every stored off-diagonal of A counts, explicit zeros included; L_ii = the sum of
+// the row's w_ij in ascending column order from 0.0; the test is evaluated squared as for
+// A; coincident coordinates of two connected nodes are an error.
+// ------------------------------------------------------------------------------------
+int distance_strength(const Csr &A, const std::vector<double> &xyz, int dim, double theta,
+                      std::vector<uint8_t> &mask) {
+  std::vector<double> w(A.nnz(), 0.0), Ld(A.nr, 0.0);
+  for (int i = 0; i < A.nr; ++i) {
+    double s = 0.0;
+    for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+      const int j = A.col[e];
+      if (j == i) continue;
+      double d2 = 0.0;
+      for (int k = 0; k < dim; ++k) {
+        const double t = xyz[(size_t)i * dim + k] - xyz[(size_t)j * dim + k];
+        d2 += t * t;
+      }
+      if (!(d2 > 0.0)) return fail(ST_INVALID, "coincident coordinates of connected nodes");
+      w[e] = 1.0 / d2;
+      s += w[e];
+    }
+    Ld[i] = s;
+  }
+  const double th2 = theta * theta;
+  mask.assign(A.nnz(), M_WEAK);
+  for (int i = 0; i < A.nr; ++i)
+    for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+      const int j = A.col[e];
+      if (j == i) {
+        mask[e] = M_DIAG;
+        continue;
+      }
+      const double p = Ld[i] * Ld[j];
+      mask[e] = ((p > 0.0) && (w[e] * w[e] >= th2 * p)) ? M_STRONG : M_WEAK;
+    }
+  return ST_OK;
+}
+
+// Coarse coordinates: the centroid of each aggregate's members (Reading: the members'
+// coordinates summed in ascending vertex order from 0.0, divided by the member count).
+std::vector<double> coarse_coords(const std::vector<double> &xyz, int dim,
+                                  const std::vector<int32_t> &agg, int nc) {
+  std::vector<double> sum((size_t)nc * dim, 0.0);
+  std::vector<int64_t> cnt(nc, 0);
+  for (size_t i = 0; i < agg.size(); ++i) {
+    if (agg[i] < 0) continue;
+    for (int k = 0; k < dim; ++k) sum[(size_t)agg[i] * dim + k] += xyz[i * dim + k];
+    ++cnt[agg[i]];
+  }
+  for (int J = 0; J < nc; ++J)
+    for (int k = 0; k < dim; ++k) sum[(size_t)J * dim + k] = sum[(size_t)J * dim + k] / (double)cnt[J];
+  return sum;
+}
+
 // Aggregation graph G: the strong off-diagonals, symmetrised (G = S u S^T).  Reading: the
 // paper treats symmetric matrices; the union keeps the graph undirected when rounding makes
 // a coarse matrix's strength pattern slightly unsymmetric.
@@ -694,6 +754,7 @@ struct Level {
   std::vector<double> sm_invD;
   double sm_lambda = 0.0;
   std::vector<double> chol;  // coarsest only: dense Cholesky factor (row-major, lower)
+  std::vector<double> xyz;   // node coordinates (n x dim) when the distance strength is used
 };
 
 struct Hier {
@@ -701,6 +762,7 @@ struct Hier {
   std::vector<Level> lv;
   bool scaled = false;
   bool valid = true;  // false after a failed re-setup
+  int dim = 0;        // > 0: distance-Laplacian strength from coordinates
 };
 
 // Dense Cholesky of the coarsest operator, textbook order: L_jj = sqrt(A_jj - sum_k<j L_jk^2),
@@ -749,7 +811,12 @@ int numeric_level(Hier &H, int l);
 int build_level(Hier &H, int l) {
   Level &L = H.lv[l];
   const orc_options &o = H.o;
-  strength(L.As, o.theta, L.mask);
+  if (H.dim > 0) {
+    int st = distance_strength(L.As, L.xyz, H.dim, o.theta, L.mask);
+    if (st) return st;
+  } else {
+    strength(L.As, o.theta, L.mask);
+  }
   auto G = strength_graph(L.As, L.mask);
   L.nnzG = 0;
   for (auto &g : G) L.nnzG += (int64_t)g.size();
@@ -823,6 +890,7 @@ void galerkin(Hier &H, int l, const double *B) {
   Level &Ln = H.lv[l + 1];
   Ln.A = spgemm(L.R, AP);
   Ln.As = Ln.A;
+  if (H.dim > 0) Ln.xyz = coarse_coords(L.xyz, H.dim, L.agg, L.nc);
 }
 
 // Smoothers on every level but the coarsest (Sec. 3.1: Chebyshev of degree 2 on
@@ -885,16 +953,27 @@ double orc_dot(int64_t n, const double *x, const double *y) {
 
 int orc_setup(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
               const double *B, const orc_options *o, void **out) {
+  return orc_setup_coords(n, rp, col, val, B, nullptr, 0, o, out);
+}
+
+int orc_setup_coords(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                     const double *B, const double *coords, int32_t dim, const orc_options *o,
+                     void **out) {
   *out = nullptr;
   int st = check_csr(n, rp, col, val);
   if (st) return st;
   if (o->theta < 0.0 || o->theta > 1.0 || o->max_levels < 1 || o->degree < 1 ||
       o->power_iters < 1)
     return fail(ST_INVALID, "bad options");
+  if (coords && (dim < 1 || dim > 3)) return fail(ST_INVALID, "coordinate dimension");
+  for (int64_t k = 0; coords && k < (int64_t)n * dim; ++k)
+    if (!std::isfinite(coords[k])) return fail(ST_INVALID, "non-finite coordinate");
   Hier *H = new Hier();
   H->o = *o;
+  H->dim = coords ? dim : 0;
   H->lv.emplace_back();
   H->lv[0].A = make_csr(n, n, rp, col, val);
+  if (coords) H->lv[0].xyz.assign(coords, coords + (size_t)n * dim);
   st = apply_nullspace(*H, B);
   if (st) {
     delete H;
@@ -1013,6 +1092,7 @@ int orc_export(const void *h, int l, int what, void *buf) {
     case 15: return cp(L.R.val.data(), L.R.val.size() * 8);
     case 16: return cp(L.sm_invD.data(), L.sm_invD.size() * 8);
     case 17: return cp(L.As.val.data(), L.As.val.size() * 8);
+    case 18: return cp(L.xyz.data(), L.xyz.size() * 8);
     default: return fail(ST_INVALID, "bad export selector");
   }
 }
@@ -1176,6 +1256,17 @@ int orc_solve(const void *h, const double *b, double *x, int32_t *iters, double 
 void orc_destroy(void *h) { delete (Hier *)h; }
 
 // ---- single steps ----------------------------------------------------------------------
+
+int orc_distance_strength(int32_t n, const int32_t *rp, const int32_t *col,
+                          const double *coords, int32_t dim, double theta, uint8_t *mask) {
+  Csr A = make_csr(n, n, rp, col, nullptr);
+  std::vector<double> xyz(coords, coords + (size_t)n * dim);
+  std::vector<uint8_t> m;
+  int st = distance_strength(A, xyz, dim, theta, m);
+  if (st) return st;
+  std::copy(m.begin(), m.end(), mask);
+  return ST_OK;
+}
 
 int orc_strength(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
                  double theta, uint8_t *mask) {

@@ -280,6 +280,59 @@ def from_dense(d: np.ndarray, keep_zero_pattern: np.ndarray | None = None) -> Cs
     return CsrProblem(n, rp, cc.astype(np.int32), d[rr, cc].astype(np.float64), "dense")
 
 
+# ---------------------------------------------------------------------------------------
+# Node coordinates (for the distance-Laplacian strength of Sec. 3.1)
+# ---------------------------------------------------------------------------------------
+
+def grid_coords(*axes) -> np.ndarray:
+    """Coordinates of a tensor grid's nodes, (n, dim) float64, x fastest (the unknown order
+    of every generator here); ``axes[d]`` holds the node positions along axis d."""
+    mesh = np.meshgrid(*[np.asarray(a, dtype=np.float64) for a in reversed(axes)],
+                       indexing="ij")
+    return np.stack([g.reshape(-1) for g in reversed(mesh)], axis=1)
+
+
+def _graded_nodes(nint: int, aspect: float) -> np.ndarray:
+    """Interior node positions of a graded axis: node k (1-based) sits at h_0 + ... + h_{k-1}
+    (summed in that order from 0.0) with the widths of ``graded_spacing``."""
+    h = graded_spacing(nint, aspect)
+    z = np.empty(nint)
+    acc = 0.0
+    for k in range(nint):
+        acc = acc + h[k]
+        z[k] = acc
+    return z
+
+
+def fd5_coords(nx: int = 64, ny: int = 64, aspect: float = 100.0) -> np.ndarray:
+    """Node coordinates of ``fd5_stretched(nx, ny, aspect)``."""
+    h = 1.0 / (nx + 1)
+    return grid_coords(h * np.arange(1, nx + 1), _graded_nodes(ny, aspect))
+
+
+def fd7_coords(n: int = 128, aspect: float = 1000.0, nx: int | None = None,
+               ny: int | None = None) -> np.ndarray:
+    """Node coordinates of ``fd7_stretched(n, aspect, nx, ny)``."""
+    nx = n if nx is None else nx
+    ny = n if ny is None else ny
+    h = 1.0 / (nx + 1)
+    return grid_coords(h * np.arange(1, nx + 1), h * np.arange(1, ny + 1),
+                       _graded_nodes(n, aspect))
+
+
+def q1_coords(ne: int = 100, hx=None, hy=None, hz=None, nex: int | None = None,
+              ney: int | None = None) -> np.ndarray:
+    """Node coordinates of ``q1_hex`` with the same mesh arguments (interior nodes)."""
+    nex = ne if nex is None else nex
+    ney = ne if ney is None else ney
+    if hx is None:
+        hx = hy = hz = Fraction(1, ne)
+    ax = [float(hx * i) for i in range(1, nex)]
+    ay = [float(hy * j) for j in range(1, ney)]
+    az = [float(hz * k) for k in range(1, ne)]
+    return grid_coords(ax, ay, az)
+
+
 def random_rhs(n: int, seed: int) -> np.ndarray:
     """b_i ~ U(-1, 1) from numpy PCG64(seed)."""
     rng = np.random.Generator(np.random.PCG64(seed))
