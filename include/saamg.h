@@ -119,7 +119,8 @@ typedef enum {
   SA_PART_AGG = 4, SA_PART_ROOT = 5, SA_PART_ABAR_RP = 6, SA_PART_ABAR_COL = 7,
   SA_PART_ABAR_VAL = 8, SA_PART_INVD = 9, SA_PART_P_RP = 10, SA_PART_P_COL = 11,
   SA_PART_P_VAL = 12, SA_PART_R_RP = 13, SA_PART_R_COL = 14, SA_PART_R_VAL = 15,
-  SA_PART_SM_INVD = 16, SA_PART_COARSE_INV = 17
+  SA_PART_SM_INVD = 16, SA_PART_COARSE_INV = 17,
+  SA_PART_COORDS = 18       /* node coordinates, n x dim (sa_setup_coords only)            */
 } sa_part;
 
 /* Fills *o with the defaults listed above (struct_size included). */
@@ -136,6 +137,22 @@ void sa_default_options(sa_options *o);
  * SA_ERR_HIP.  On failure *out is NULL and nothing is leaked. */
 sa_status sa_setup(const sa_context *ctx, const sa_csr *A, const double *nullspace,
                    const sa_options *o, sa_hierarchy **out);
+
+/* sa_setup with the strength test of Sec. 3.1 taken on a distance Laplacian instead of on
+ * the level operator.  L^(d) has the operator's pattern; an off-diagonal entry is -1/|x_i -
+ * x_j|^2 (the reciprocal of the squared Euclidean distance between the two nodes, so the
+ * labels involve no square root) and the diagonal makes every row sum zero; entry (i,j) is
+ * strong iff |L_ij| >= theta sqrt(L_ii L_jj).  Coarse levels take as coordinates the
+ * centroids of their aggregates (members summed in ascending order, divided by the count).
+ * Everything else is sa_setup's.
+ *  coords  n x dim float64 node coordinates, row-major (node i at coords[i*dim .. i*dim+dim-1]),
+ *          in A->loc memory, finite; NULL makes this sa_setup.
+ *  dim     1, 2 or 3.
+ * Errors: those of sa_setup; SA_ERR_INVALID_ARG also for a bad dim, a non-finite coordinate
+ * or two nodes connected by a stored entry of some level's operator at zero distance. */
+sa_status sa_setup_coords(const sa_context *ctx, const sa_csr *A, const double *nullspace,
+                          const double *coords, int32_t dim, const sa_options *o,
+                          sa_hierarchy **out);
 
 /* Numeric re-setup: new values for the matrix given to sa_setup, on the same pattern (val
  * holds nnz values in that matrix's CSR order; nullspace as in sa_setup, NULL = ones; both in

@@ -25,7 +25,8 @@ enum ErrBits {
   E_ZERO_FDIAG = 8,
   E_LAMBDA = 16,
   E_DIAG = 32,
-  E_CHOL = 64
+  E_CHOL = 64,
+  E_COORD = 128
 };
 
 static double now_s() {
@@ -158,13 +159,21 @@ static bool build_level(sa_hierarchy *h, int l) {
   Arena tmp;
   tmp.stream = s;
   double *dval = tmp.alloc<double>(n);
-  find_diag(n, L.As.rp, L.As.col, L.As.val, dval, s);
+  const double *sval = L.As.val;  // the matrix the strength test reads: A, or L^(d)
+  if (h->dim > 0) {
+    double *w = tmp.alloc<double>(L.As.nnz);
+    distance_weights(n, L.As.rp, L.As.col, L.xyz, h->dim, w, dval, h->err, E_COORD, s);
+    check_err(h, E_COORD, SA_ERR_INVALID_ARG, "coincident coordinates of connected nodes");
+    sval = w;
+  } else {
+    find_diag(n, L.As.rp, L.As.col, L.As.val, dval, s);
+  }
   // rows long enough to leave thread-per-row kernels serial: one wavefront per row instead
   L.wave_rows = max_row_length(n, L.As.rp, s) > 64 || L.As.nnz > 24 * (int64_t)n;
   L.mask = ar.alloc<uint8_t>(L.As.nnz);
   int32_t *scount = tmp.alloc<int32_t>(n + 1);
-  strength(n, L.As.rp, L.As.col, L.As.val, dval, o.theta * o.theta, L.mask, scount,
-           L.wave_rows, s);
+  strength(n, L.As.rp, L.As.col, sval, dval, o.theta * o.theta, L.mask, scount, L.wave_rows,
+           s);
   int32_t *grp = nullptr, *gcol = nullptr;
   const int64_t nnzG = strength_graph(n, L.As.rp, L.As.col, L.mask, scount, L.wave_rows, tmp,
                                       &grp, &gcol, s);
@@ -201,9 +210,15 @@ static void galerkin(sa_hierarchy *h, int l, bool fresh, const double *dB) {
   if (fresh) {
     spgemm(L.R, AP, h->ar, Ac, s);
     spmv_plan(Ac, h->ar, s);
-    h->lv.emplace_back();
+    double *cxyz = nullptr;  // coarse coordinates: the aggregates' centroids
+    if (h->dim > 0) {
+      cxyz = h->ar.alloc<double>((int64_t)L.nc * h->dim);
+      aggregate_centroids(L.A.n, L.agg, L.nc, L.xyz, h->dim, cxyz, s);
+    }
+    h->lv.emplace_back();  // invalidates L
     h->lv[l + 1].A = Ac;
     h->lv[l + 1].As = Ac;
+    h->lv[l + 1].xyz = cxyz;
   } else {
     spgemm(L.R, AP, tmp, Ac, s);
     take_values(Ac, h->lv[l + 1].A, s);  // As shares A's arrays on coarse levels
@@ -334,7 +349,8 @@ static void validate_values(sa_hierarchy *h) {
   if (e & E_NODIAG) throw Error(SA_ERR_BAD_CSR, "missing diagonal");
 }
 
-static void setup_impl(sa_hierarchy *h, const sa_csr *A, const double *B) {
+static void setup_impl(sa_hierarchy *h, const sa_csr *A, const double *B,
+                       const double *coords, int32_t dim) {
   const double t0 = now_s();
   const hipStream_t s = h->stream;
   sa_options &o = h->opt;
@@ -360,6 +376,14 @@ static void setup_impl(sa_hierarchy *h, const sa_csr *A, const double *B) {
   const int32_t rp0 = read1(L0.A.rp, s), rpn = read1(L0.A.rp + n, s);
   if (rp0 != 0 || (int64_t)rpn != A->nnz) throw Error(SA_ERR_BAD_CSR, "row pointers do not span nnz");
   validate_values(h);
+  if (coords) {
+    if (dim < 1 || dim > 3) throw Error(SA_ERR_INVALID_ARG, "coordinate dimension not 1..3");
+    h->dim = dim;
+    L0.xyz = h->ar.alloc<double>((int64_t)n * dim);
+    copy_in(L0.xyz, coords, sizeof(double) * n * dim, A->loc, s);
+    check_finite(L0.xyz, (int64_t)n * dim, h->err, E_COORD, s);
+    check_err(h, E_COORD, SA_ERR_INVALID_ARG, "non-finite coordinate");
+  }
   spmv_plan(L0.A, h->ar, s);
   const double *dB = apply_nullspace(h, B, A->loc);
   for (int l = 0;; ++l) {
@@ -716,8 +740,9 @@ void sa_default_options(sa_options *o) {
   o->pcg_beta = -1;
 }
 
-sa_status sa_setup(const sa_context *ctx, const sa_csr *A, const double *nullspace,
-                   const sa_options *o, sa_hierarchy **out) {
+sa_status sa_setup_coords(const sa_context *ctx, const sa_csr *A, const double *nullspace,
+                          const double *coords, int32_t dim, const sa_options *o,
+                          sa_hierarchy **out) {
   if (!out) return SA_ERR_INVALID_ARG;
   *out = nullptr;
   return guarded([&]() -> sa_status {
@@ -727,7 +752,7 @@ sa_status sa_setup(const sa_context *ctx, const sa_csr *A, const double *nullspa
     if (o) h->opt = *o;
     else sa_default_options(&h->opt);
     try {
-      setup_impl(h.get(), A, nullspace);
+      setup_impl(h.get(), A, nullspace, coords, dim);
     } catch (...) {
       (void)hipStreamSynchronize(h->stream);
       throw;
@@ -735,6 +760,11 @@ sa_status sa_setup(const sa_context *ctx, const sa_csr *A, const double *nullspa
     *out = h.release();
     return SA_OK;
   });
+}
+
+sa_status sa_setup(const sa_context *ctx, const sa_csr *A, const double *nullspace,
+                   const sa_options *o, sa_hierarchy **out) {
+  return sa_setup_coords(ctx, A, nullspace, nullptr, 0, o, out);
 }
 
 sa_status sa_resetup(sa_hierarchy *h, const double *val, const double *nullspace,
@@ -821,6 +851,11 @@ static bool part_info(const sa_hierarchy *h, int32_t level, sa_part what, const 
     case SA_PART_R_COL: *ptr = L.R.col; *count = has_p ? L.R.nnz : 0; break;
     case SA_PART_R_VAL: *ptr = L.R.val; *count = has_p ? L.R.nnz : 0; *esize = 8; break;
     case SA_PART_SM_INVD: *ptr = L.sm_invD; *count = has_p ? L.A.n : 0; *esize = 8; break;
+    case SA_PART_COORDS:
+      *ptr = L.xyz;
+      *count = (int64_t)L.A.n * h->dim;
+      *esize = 8;
+      break;
     case SA_PART_COARSE_INV:
       *ptr = L.Ainv;
       *count = has_p ? 0 : (int64_t)L.A.n * L.A.n;

@@ -17,6 +17,7 @@ struct Level {
   int32_t nc = 0;
   int32_t mis_rounds = 0;
   bool wave_rows = false;  // rows long enough for the wavefront-per-row setup kernels
+  double *xyz = nullptr;   // node coordinates (n x dim) when the distance strength is used
   Csr Abar;
   double *invD = nullptr;
   double *lam_d = nullptr, *omega_d = nullptr;
@@ -46,6 +47,7 @@ struct sa_hierarchy {
   int32_t *err = nullptr;
   double setup_seconds = 0.0;
   bool valid = true;            // false after a failed re-setup
+  int32_t dim = 0;              // > 0: distance-Laplacian strength from coordinates
   double *dB = nullptr;         // nullspace vector (when it is not all ones)
   double *As0 = nullptr;        // D_B A D_B values on level 0 (when scaled)
   // solve workspace

@@ -161,6 +161,123 @@ void strength(int32_t n, const int32_t *rp, const int32_t *col, const double *va
   SA_LAUNCH_CHECK();
 }
 
+// ---- distance-Laplacian weights (Sec. 3.1) -------------------------------------------------
+// The strength test can be taken on a Laplacian built from node coordinates instead of on A:
+// same pattern, off-diagonal weight w = 1/|x_i - x_j|^2 (the squared distance summed over the
+// coordinates in order from 0), diagonal Ld[i] = the row's weights summed in ascending column
+// order from 0.  k_strength then runs on (w, Ld) unchanged: |L_ij| >= theta sqrt(L_ii L_jj)
+// squared is w^2 >= theta^2 Ld_i Ld_j.  A zero (or NaN) distance between two connected nodes
+// sets err bit `ebit`.
+template <int D>
+__device__ inline double dist2(const double *__restrict__ xyz, int32_t i, int32_t j) {
+  double d2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double t = xyz[(int64_t)i * D + k] - xyz[(int64_t)j * D + k];
+    d2 = d2 + t * t;
+  }
+  return d2;
+}
+template <int D>
+__global__ void k_distance_weights(int32_t n, const int32_t *rp, const int32_t *col,
+                                   const double *__restrict__ xyz, double *w, double *Ld,
+                                   int32_t *err, int32_t ebit) {
+  SA_ROW_KERNEL_BEGIN(n)
+  double s = 0.0;
+  bool bad = false;
+  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+    const int32_t j = col[k];
+    if (j == i) {
+      w[k] = 0.0;
+      continue;
+    }
+    const double d2 = dist2<D>(xyz, i, j);
+    bad |= !(d2 > 0.0);
+    const double wk = 1.0 / d2;
+    w[k] = wk;
+    s = s + wk;
+  }
+  Ld[i] = s;
+  if (bad) atomicOr(err, ebit);
+}
+void distance_weights(int32_t n, const int32_t *rp, const int32_t *col, const double *xyz,
+                      int32_t dim, double *w, double *Ld, int32_t *err, int32_t ebit,
+                      hipStream_t s) {
+  if (n <= 0) return;
+  switch (dim) {
+    case 1: k_distance_weights<1><<<grid_for(n), kBlock, 0, s>>>(n, rp, col, xyz, w, Ld, err, ebit); break;
+    case 2: k_distance_weights<2><<<grid_for(n), kBlock, 0, s>>>(n, rp, col, xyz, w, Ld, err, ebit); break;
+    case 3: k_distance_weights<3><<<grid_for(n), kBlock, 0, s>>>(n, rp, col, xyz, w, Ld, err, ebit); break;
+    default: throw Error(SA_ERR_INVALID_ARG, "coordinate dimension");
+  }
+  SA_LAUNCH_CHECK();
+}
+
+__global__ void k_check_finite(int64_t m, const double *x, int32_t *err, int32_t ebit) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m && !isfinite(x[i])) atomicOr(err, ebit);
+}
+void check_finite(const double *x, int64_t m, int32_t *err, int32_t ebit, hipStream_t s) {
+  if (m <= 0) return;
+  k_check_finite<<<grid_for(m), kBlock, 0, s>>>(m, x, err, ebit);
+  SA_LAUNCH_CHECK();
+}
+
+// ---- coarse coordinates: aggregate centroids ---------------------------------------------
+// Member lists by counting sort (count, scan, scatter, then each list sorted ascending), then
+// one thread per aggregate sums its members' coordinates in ascending vertex order from 0
+// and divides by the member count.
+__global__ void k_count_members(int32_t n, const int32_t *agg, int32_t *cnt) {
+  SA_ROW_KERNEL_BEGIN(n)
+  if (agg[i] >= 0) atomicAdd(&cnt[agg[i]], 1);
+}
+__global__ void k_scatter_members(int32_t n, const int32_t *agg, int32_t *pos, int32_t *mem) {
+  SA_ROW_KERNEL_BEGIN(n)
+  if (agg[i] >= 0) mem[atomicAdd(&pos[agg[i]], 1)] = i;
+}
+// Member lists of the nc aggregates: mrp[nc+1] offsets into mem[n] (unaggregated vertices
+// left out); members in scatter order, or ascending when `sorted`.
+static void member_lists(int32_t n, const int32_t *agg, int32_t nc, bool sorted, Arena &ar,
+                         int32_t **mrp_out, int32_t **mem_out, hipStream_t s) {
+  int32_t *cnt = ar.alloc<int32_t>(nc + 1);
+  int32_t *mrp = ar.alloc<int32_t>(nc + 1);
+  int32_t *mem = ar.alloc<int32_t>(n > 0 ? n : 1);
+  fill_i32(cnt, 0, nc + 1, s);
+  if (n > 0) {
+    k_count_members<<<grid_for(n), kBlock, 0, s>>>(n, agg, cnt);
+    SA_LAUNCH_CHECK();
+  }
+  exclusive_scan_i32(cnt, mrp, nc, s);
+  SA_HIP(hipMemcpyAsync(cnt, mrp, sizeof(int32_t) * (nc + 1), hipMemcpyDeviceToDevice, s));
+  if (n > 0) {
+    k_scatter_members<<<grid_for(n), kBlock, 0, s>>>(n, agg, cnt, mem);
+    SA_LAUNCH_CHECK();
+  }
+  if (sorted) sort_rows(nc, mrp, mem, nullptr, s);
+  *mrp_out = mrp;
+  *mem_out = mem;
+}
+__global__ void k_centroids(int32_t nc, int32_t dim, const int32_t *mrp, const int32_t *mem,
+                            const double *__restrict__ xyz, double *cxyz) {
+  SA_ROW_KERNEL_BEGIN(nc)
+  const int32_t b = mrp[i], e = mrp[i + 1];
+  for (int k = 0; k < dim; ++k) {
+    double s = 0.0;
+    for (int32_t q = b; q < e; ++q) s = s + xyz[(int64_t)mem[q] * dim + k];
+    cxyz[(int64_t)i * dim + k] = s / (double)(e - b);
+  }
+}
+void aggregate_centroids(int32_t n, const int32_t *agg, int32_t nc, const double *xyz,
+                         int32_t dim, double *cxyz, hipStream_t s) {
+  if (nc <= 0) return;
+  Arena tmp;
+  tmp.stream = s;
+  int32_t *mrp, *mem;
+  member_lists(n, agg, nc, true, tmp, &mrp, &mem, s);
+  k_centroids<<<grid_for(nc), kBlock, 0, s>>>(nc, dim, mrp, mem, xyz, cxyz);
+  SA_LAUNCH_CHECK();
+}
+
 // ---- aggregation graph G = S u S^T ------------------------------------------------------
 __global__ void k_fill_strong(int32_t n, const int32_t *rp, const int32_t *col,
                               const uint8_t *mask, const int32_t *srp, int32_t *scol,
@@ -561,14 +678,6 @@ int32_t aggregate(int32_t n, int64_t nnzG, const int32_t *grp, const int32_t *gc
 // ---- Sprsfy (Sec. 2.5) --------------------------------------------------------------------
 constexpr int32_t kSprsfyShort = 32;   // root rows up to this length: one thread per aggregate
 constexpr int32_t kSprsfyLds = 4096;   // longer root rows (up to this): one block per aggregate
-__global__ void k_count_members(int32_t n, const int32_t *agg, int32_t *cnt) {
-  SA_ROW_KERNEL_BEGIN(n)
-  if (agg[i] >= 0) atomicAdd(&cnt[agg[i]], 1);
-}
-__global__ void k_scatter_members(int32_t n, const int32_t *agg, int32_t *pos, int32_t *mem) {
-  SA_ROW_KERNEL_BEGIN(n)
-  if (agg[i] >= 0) mem[atomicAdd(&pos[agg[i]], 1)] = i;
-}
 // One thread per aggregate J with root r.  Candidates: aggregates reached by r's weak
 // connections but by none of its strong ones, J excluded.  For a candidate c, a single strong
 // connection from a non-root member of J into c is dropped with its transpose.  Decisions read
@@ -778,17 +887,8 @@ void sprsfy(int32_t n, const int32_t *rp, const int32_t *col, uint8_t *mask, con
   if (nc <= 0) return;
   Arena tmp;
   tmp.stream = s;
-  int32_t *cnt = tmp.alloc<int32_t>(nc + 1);
-  fill_i32(cnt, 0, nc + 1, s);
-  k_count_members<<<grid_for(n), kBlock, 0, s>>>(n, agg, cnt);
-  SA_LAUNCH_CHECK();
-  int32_t *mrp = tmp.alloc<int32_t>(nc + 1);
-  exclusive_scan_i32(cnt, mrp, nc, s);
-  int32_t *pos = tmp.alloc<int32_t>(nc + 1);
-  SA_HIP(hipMemcpyAsync(pos, mrp, sizeof(int32_t) * (nc + 1), hipMemcpyDeviceToDevice, s));
-  int32_t *mem = tmp.alloc<int32_t>(n);
-  k_scatter_members<<<grid_for(n), kBlock, 0, s>>>(n, agg, pos, mem);
-  SA_LAUNCH_CHECK();
+  int32_t *mrp, *mem;
+  member_lists(n, agg, nc, false, tmp, &mrp, &mem, s);  // decisions ignore member order
   int32_t *ovf = tmp.alloc<int32_t>(1);
   fill_i32(ovf, 0, 1, s);
   k_sprsfy<<<grid_for(nc), kBlock, 0, s>>>(nc, rp, col, mask, agg, root_vertex, mrp, mem);

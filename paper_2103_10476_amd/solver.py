@@ -94,7 +94,9 @@ class Hierarchy:
     """A device-resident SA-AMG hierarchy (sa_hierarchy)."""
 
     def __init__(self, n, rp, col, val, nullspace=None, options: Options | None = None,
-                 stream=None):
+                 stream=None, coords=None):
+        """``coords`` (n x dim node coordinates, dim 1..3) selects the distance-Laplacian
+        strength test (sa_setup_coords)."""
         torch = _torch()
         self.options = options or Options()
         self.n = int(n)
@@ -109,15 +111,25 @@ class Hierarchy:
         ctx = _lib.SaContext(_stream_handle(stream))
         opts = self.options.to_c()
         h = C.c_void_p()
-        code = L.sa_setup(C.byref(ctx), C.byref(csr),
-                          None if dB is None else C.c_void_p(dB.data_ptr()), C.byref(opts),
-                          C.byref(h))
-        _lib.check(code, "sa_setup")
+        if coords is None:
+            code = L.sa_setup(C.byref(ctx), C.byref(csr),
+                              None if dB is None else C.c_void_p(dB.data_ptr()),
+                              C.byref(opts), C.byref(h))
+            _lib.check(code, "sa_setup")
+        else:
+            dX = _dev(coords, torch.float64).reshape(self.n, -1).contiguous()
+            self.dim = int(dX.shape[1])
+            code = L.sa_setup_coords(C.byref(ctx), C.byref(csr),
+                                     None if dB is None else C.c_void_p(dB.data_ptr()),
+                                     C.c_void_p(dX.data_ptr()), self.dim, C.byref(opts),
+                                     C.byref(h))
+            _lib.check(code, "sa_setup_coords")
         self._h = h
 
     @classmethod
-    def from_problem(cls, p, nullspace=None, options=None, stream=None):
-        return cls(p.n, p.rp, p.col, p.val, nullspace=nullspace, options=options, stream=stream)
+    def from_problem(cls, p, nullspace=None, options=None, stream=None, coords=None):
+        return cls(p.n, p.rp, p.col, p.val, nullspace=nullspace, options=options, stream=stream,
+                   coords=coords)
 
     # ---- numeric re-setup ---------------------------------------------------------------
     def resetup(self, val, nullspace=None):

@@ -14,8 +14,9 @@ def log(msg):
     sys.stdout.flush()
 
 
-def run_both(p, b=None, nullspace=None, **opts):
-    """Set up (and optionally solve) on the GPU and in the oracle with the same inputs."""
+def run_both(p, b=None, nullspace=None, coords=None, **opts):
+    """Set up on the GPU and in the oracle with the same inputs (``coords``: node
+    coordinates for the distance-Laplacian strength)."""
     from oracle import oracle as orc
     from paper_2103_10476_amd import solver
     log(f"[parity] {p.name} n={p.n} nnz={p.nnz} opts={opts}")
@@ -23,10 +24,11 @@ def run_both(p, b=None, nullspace=None, **opts):
     pcg = g_opts.pop("pcg_beta", "fr")
     o = solver.Options(**g_opts, pcg_beta=pcg)
     t = time.time()
-    g = solver.Hierarchy.from_problem(p, nullspace=nullspace, options=o)
+    g = solver.Hierarchy.from_problem(p, nullspace=nullspace, options=o, coords=coords)
     tg = time.time() - t
     t = time.time()
-    h = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, nullspace=nullspace, **opts)
+    h = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, nullspace=nullspace, coords=coords,
+                            **opts)
     to = time.time() - t
     log(f"[parity]   setup gpu {tg:.3f}s oracle {to:.3f}s levels {len(h.levels)}")
     return g, h
@@ -55,6 +57,8 @@ def compare_setup(g, h, check_values=True):
         assert info["n"][l] == L.n and info["nnz"][l] == L.nnz, (tag, info["n"][l], L.n)
         for name, arr in zip(("A_rp", "A_col", "A_val"), L.A):
             assert_same(g.export(l, name), arr, f"{tag} {name}")
+        if getattr(h, "dim", 0):
+            assert_same(g.export(l, "coords"), L.coords.reshape(-1), f"{tag} coords")
         if L.coarsest:
             inv = g.export(l, "coarse_inv").reshape(L.n, L.n)
             A = np.zeros((L.n, L.n))
