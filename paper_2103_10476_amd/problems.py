@@ -248,6 +248,177 @@ def q1_stretched_box(nint: int = 24, hz=Fraction(2)) -> CsrProblem:
     return p
 
 
+# ---------------------------------------------------------------------------------------
+# Q1 on general hexahedral meshes (the test families of Sec. 3.2-3.3 and App. A-B)
+# ---------------------------------------------------------------------------------------
+
+def _q1_reference():
+    """Trilinear shape functions at the 2x2x2 Gauss points of [-1,1]^3 (weights 1).
+
+    Returns (N [8 gp, 8 nodes], dN [8 gp, 8 nodes, 3]); local node a = ax + 2 ay + 4 az sits
+    at reference corner (2ax-1, 2ay-1, 2az-1)."""
+    g = 1.0 / np.sqrt(3.0)
+    corners = np.array([[2 * (a & 1) - 1, 2 * ((a >> 1) & 1) - 1, 2 * ((a >> 2) & 1) - 1]
+                        for a in range(8)], dtype=np.float64)
+    pts = np.array([[sx * g, sy * g, sz * g] for sz in (-1, 1) for sy in (-1, 1)
+                    for sx in (-1, 1)])
+    N = np.empty((8, 8))
+    dN = np.empty((8, 8, 3))
+    for q, (x, y, z) in enumerate(pts):
+        fx = 1.0 + corners[:, 0] * x
+        fy = 1.0 + corners[:, 1] * y
+        fz = 1.0 + corners[:, 2] * z
+        N[q] = fx * fy * fz / 8.0
+        dN[q, :, 0] = corners[:, 0] * fy * fz / 8.0
+        dN[q, :, 1] = fx * corners[:, 1] * fz / 8.0
+        dN[q, :, 2] = fx * fy * corners[:, 2] / 8.0
+    return N, dN
+
+
+def q1_mesh(nodes: np.ndarray, reaction: float = 0.0, u_dirichlet=None, name: str = "q1_mesh"):
+    """Q1 (trilinear) finite elements for reaction*u - div(grad u) = 0 on a structured
+    hexahedral mesh, Dirichlet data on the whole boundary eliminated.
+
+    ``nodes`` has shape (nz+1, ny+1, nx+1, 3): the position of every mesh node (x index
+    fastest); elements are the cells of this logical grid and may be any non-degenerate
+    hexahedra.  Element matrices use 2x2x2 Gauss quadrature of the stiffness and of
+    ``reaction`` times the mass (exact on axis-aligned bricks).  Element contributions are added
+    element by element in element order (x fastest), local pairs in (a, b) order.  The unknowns
+    are the interior nodes in x-fastest order; the pattern is the 27-point stencil, every
+    entry stored.  ``u_dirichlet(x, y, z)`` gives the boundary values; the right-hand side is
+    then -A_IB u_D (zero forcing), otherwise the returned rhs is zero.
+
+    Returns (CsrProblem, rhs, coords) with coords the interior nodes' positions (n x 3)."""
+    nodes = np.asarray(nodes, dtype=np.float64)
+    nz1, ny1, nx1, _ = nodes.shape
+    nx, ny, nz = nx1 - 1, ny1 - 1, nz1 - 1
+    if min(nx, ny, nz) < 2:
+        raise ValueError("need at least 2 elements per direction")
+    flat = nodes.reshape(-1, 3)
+    gid = np.arange(nx1 * ny1 * nz1).reshape(nz1, ny1, nx1)
+    interior = np.full(gid.size, -1, dtype=np.int64)
+    inner = gid[1:-1, 1:-1, 1:-1].reshape(-1)
+    interior[inner] = np.arange(inner.size)
+    # element -> 8 global nodes, local a = ax + 2 ay + 4 az
+    ez, ey, ex = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ex, ey, ez = ex.reshape(-1), ey.reshape(-1), ez.reshape(-1)
+    conn = np.stack([gid[ez + ((a >> 2) & 1), ey + ((a >> 1) & 1), ex + (a & 1)]
+                     for a in range(8)], axis=1)                        # (E, 8)
+    X = flat[conn]                                                      # (E, 8, 3)
+    Nq, dNq = _q1_reference()
+    E = conn.shape[0]
+    XT = np.ascontiguousarray(X.transpose(0, 2, 1))                     # (E, 3, 8)
+    K = np.zeros((E, 8, 8))
+    for q in range(8):
+        J = XT @ dNq[q]                                                 # dx_i / dxi_j
+        det = np.linalg.det(J)
+        if not np.all(det > 0.0):
+            raise ValueError("inverted or degenerate element")
+        G = dNq[q] @ np.linalg.inv(J)                                   # grad N_a (E, 8, 3)
+        K += det[:, None, None] * (G @ G.transpose(0, 2, 1))
+        if reaction != 0.0:
+            K += (reaction * det)[:, None, None] * np.outer(Nq[q], Nq[q])[None]
+    # the interior pattern and, per row, the position of each of the 27 offsets
+    nix, niy, niz = nx - 1, ny - 1, nz - 1
+    offs = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+    dummy = [np.zeros((niz, niy, nix)) for _ in offs]
+    pat = _csr_from_offsets((nix, niy, niz), offs, dummy, name)
+    n = pat.n
+    ii = np.arange(n)
+    cx, cy, cz = ii % nix, (ii // nix) % niy, ii // (nix * niy)
+    slot = np.full((n, 27), -1, dtype=np.int64)
+    cnt = np.zeros(n, dtype=np.int64)
+    for t, (dx, dy, dz) in enumerate(offs):   # offsets in ascending linear order
+        ok = ((cx + dx >= 0) & (cx + dx < nix) & (cy + dy >= 0) & (cy + dy < niy)
+              & (cz + dz >= 0) & (cz + dz < niz))
+        slot[ok, t] = pat.rp[:-1][ok] + cnt[ok]
+        cnt += ok
+    gpos = flat  # node positions by global id
+    gi = np.repeat(conn[:, :, None], 8, axis=2).reshape(-1)             # row node of (e,a,b)
+    gj = np.repeat(conn[:, None, :], 8, axis=1).reshape(-1)             # column node
+    kv = K.reshape(-1)
+    ri, cj = interior[gi], interior[gj]
+    both = (ri >= 0) & (cj >= 0)
+    # offset of the column node from the row node, in grid steps
+    def grid_xyz(g):
+        return g % nx1, (g // nx1) % ny1, g // (nx1 * ny1)
+    ax_, ay_, az_ = grid_xyz(gi[both])
+    bx_, by_, bz_ = grid_xyz(gj[both])
+    t = (bx_ - ax_ + 1) + 3 * (by_ - ay_ + 1) + 9 * (bz_ - az_ + 1)
+    pos = slot[ri[both], t]
+    val = np.bincount(pos, weights=kv[both], minlength=pat.nnz)
+    rhs = np.zeros(n)
+    if u_dirichlet is not None:
+        bnd = (ri >= 0) & (cj < 0)
+        xb = gpos[gj[bnd]]
+        ub = u_dirichlet(xb[:, 0], xb[:, 1], xb[:, 2])
+        rhs = -np.bincount(ri[bnd], weights=kv[bnd] * ub, minlength=n)
+    prob = CsrProblem(n, pat.rp, pat.col, val, name)
+    return prob, rhs, flat[inner].copy()
+
+
+def u_trilinear(x, y, z):
+    """Boundary data of Sec. 3.2-3.3: 1 + x + y + z + xy + xz + yz + xyz."""
+    return 1.0 + x + y + z + x * y + x * z + y * z + x * y * z
+
+
+def perturbed_cube_nodes(ne: int = 60, seed: int = 0, amp: float = 0.2,
+                         lengths=(1.0, 1.0, 100.0)) -> np.ndarray:
+    """Mesh nodes of the randomly perturbed cube (Sec. 3.2, App. A).
+
+    A uniform grid of ne elements per direction on [0,1]^3; every node coordinate is moved by
+    amp * u / ne with u ~ U[0,1) (three draws per node, in node order x fastest, x then y
+    then z, from numpy PCG64(seed)); then each axis is scaled by ``lengths`` (z by 100, the
+    100:1 stretching).  The paper's meshes come from a mesh generator's random stream that is
+    not available; this reproduces the recipe, not those meshes."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g = np.arange(ne + 1, dtype=np.float64) / ne
+    Z, Y, Xg = np.meshgrid(g, g, g, indexing="ij")
+    base = np.stack([Xg, Y, Z], axis=-1)                               # (z, y, x, 3)
+    u = rng.uniform(0.0, 1.0, size=base.shape)
+    pts = (base + amp * u / ne) * np.asarray(lengths, dtype=np.float64)
+    return pts
+
+
+def linear_sizes(ne: int, first: float, last: float) -> np.ndarray:
+    """Node positions along an axis of ne elements whose sizes vary linearly from ``first``
+    to ``last`` (summed from 0.0 in element order)."""
+    h = first + (last - first) * np.arange(ne, dtype=np.float64) / (ne - 1)
+    x = np.empty(ne + 1)
+    acc = 0.0
+    x[0] = 0.0
+    for e in range(ne):
+        acc = acc + h[e]
+        x[e + 1] = acc
+    return x
+
+
+def stretched_cube_nodes(kx: int, ky: int, kz: int, ne: int = 60) -> np.ndarray:
+    """Mesh nodes of the triaxially stretched cube (Sec. 3.3, App. B): along axis d the ne
+    element sizes vary linearly from 0.1 to k_d/10, so the axis spans 3(k_d + 1)."""
+    ax = [linear_sizes(ne, 0.1, k / 10.0) for k in (kx, ky, kz)]
+    Z, Y, Xg = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return np.stack([Xg, Y, Z], axis=-1)
+
+
+def perturbed_cube(ne: int = 60, seed: int = 0):
+    """The randomly perturbed cube problem: (CsrProblem, rhs, coords)."""
+    return q1_mesh(perturbed_cube_nodes(ne, seed), 0.0, u_trilinear,
+                   f"q1_perturbed_{ne}_s{seed}")
+
+
+def stretched_cube(kx: int, ky: int, kz: int, sigma: float, ne: int = 60):
+    """The triaxially stretched reaction-diffusion cube (reaction 1/sigma): (CsrProblem, rhs,
+    coords)."""
+    return q1_mesh(stretched_cube_nodes(kx, ky, kz, ne), 1.0 / sigma, u_trilinear,
+                   f"q1_stretch_{kx}_{ky}_{kz}_sig{sigma:g}_{ne}")
+
+
+STRETCH_CONFIGS = [(kx, ky, kz) for kx in (1, 5, 10) for ky in (1, 5, 10) for kz in (1, 5, 10)
+                   if kx <= ky <= kz]
+STRETCH_SIGMAS = (1e1, 1e2, 1e3, 1e4, 1e5)
+
+
 def periodic_stencil_2d(nx: int, ny: int, stencil: dict) -> CsrProblem:
     """Periodic 2-D stencil (circulant); ``stencil`` maps (dx, dy) -> value."""
     n = nx * ny

@@ -151,3 +151,87 @@ def test_serving_requests_seeded():
     assert r1 == r2
     assert all(16 <= r["side"] <= 96 for r in r1)
     assert {r["kind"] for r in r1} == {"fd7", "q1"}
+
+
+# ---- general hexahedral Q1 meshes (Sec. 3.2-3.3, App. A-B) --------------------------------
+
+def _dense(p):
+    d = np.zeros((p.n, p.n))
+    d[np.repeat(np.arange(p.n), np.diff(p.rp)), p.col] = p.val
+    return d
+
+
+def _uniform_nodes(ne, lengths=(1.0, 1.0, 1.0)):
+    axes = [np.arange(ne + 1) * (L / ne) for L in lengths]
+    Z, Y, X = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    return np.stack([X, Y, Z], axis=-1)
+
+
+def test_q1_mesh_on_uniform_bricks_is_the_exact_stiffness():
+    # Gauss quadrature is exact on bricks: the rational-arithmetic Q1 cube, to rounding
+    p0 = pb.q1_hex(6)
+    p, rhs, X = pb.q1_mesh(_uniform_nodes(6))
+    assert np.array_equal(p.rp, p0.rp) and np.array_equal(p.col, p0.col)
+    assert np.abs(p.val - p0.val).max() <= 4e-15 * np.abs(p0.val).max()
+    assert np.all(rhs == 0.0)
+    assert np.allclose(X, pb.q1_coords(6), rtol=0, atol=1e-15)
+    # a 2 x 1 x 3 brick mesh against the closed-form element of q1_element_matrix
+    p1 = pb.q1_hex(5, hx=Fraction(2, 5), hy=Fraction(1, 5), hz=Fraction(3, 5))
+    q, _, _ = pb.q1_mesh(_uniform_nodes(5, (2.0, 1.0, 3.0)))
+    assert np.abs(q.val - p1.val).max() <= 4e-15 * np.abs(p1.val).max()
+
+
+def test_q1_mesh_patch_test_on_perturbed_mesh():
+    """Isoparametric Q1 reproduces linear fields on any hexahedral mesh: with linear boundary
+    data and no forcing the discrete solution is the linear field at every interior node."""
+    nodes = pb.perturbed_cube_nodes(7, seed=3, lengths=(1.0, 2.0, 5.0))
+    lin = lambda x, y, z: 1.0 + 2.0 * x - 0.5 * y + 0.25 * z
+    p, rhs, X = pb.q1_mesh(nodes, 0.0, lin)
+    u = np.linalg.solve(_dense(p), rhs)
+    assert np.abs(u - lin(X[:, 0], X[:, 1], X[:, 2])).max() <= 1e-11
+    # trilinear data is reproduced only on bricks (the stretched-cube meshes)
+    q, rb, Y = pb.q1_mesh(pb.stretched_cube_nodes(1, 5, 10, ne=6), 0.0, pb.u_trilinear)
+    v = np.linalg.solve(_dense(q), rb)
+    assert np.abs(v - pb.u_trilinear(Y[:, 0], Y[:, 1], Y[:, 2])).max() <= 1e-10
+
+
+def test_q1_mesh_reaction_row_sums_are_lumped_masses():
+    """With u = 1 everywhere the stiffness part vanishes row by row, so each interior row of
+    [A_II A_IB] sums to reaction * integral of the node's hat function, which on a tensor mesh of
+    bricks is the product of half the neighbouring widths per axis."""
+    r = 1.0  # (a tiny reaction would leave the row sums inside the stiffness's rounding)
+    nodes = pb.stretched_cube_nodes(5, 5, 10, ne=6)
+    p, rhs, X = pb.q1_mesh(nodes, r, lambda x, y, z: np.ones_like(x))
+    rows = _dense(p).sum(axis=1) - rhs          # A_II 1 + A_IB 1
+    ax = [pb.linear_sizes(6, 0.1, k / 10.0) for k in (5, 5, 10)]
+    half = [0.5 * (a[2:] - a[:-2]) for a in ax]  # interior nodes 1..5 of each axis
+    want = r * np.einsum("k,j,i->kji", half[2], half[1], half[0]).reshape(-1)
+    assert np.allclose(rows, want, rtol=1e-11, atol=0)
+
+
+def test_q1_mesh_spd_and_symmetric():
+    p, _, _ = pb.perturbed_cube(5, seed=1)
+    d = _dense(p)
+    assert np.array_equal(d, d.T)
+    assert np.linalg.eigvalsh(d).min() > 0
+    q, _, _ = pb.stretched_cube(1, 1, 10, 1e2, ne=5)
+    e = _dense(q)
+    assert np.abs(e - e.T).max() <= 1e-15 * np.abs(e).max()
+    assert np.linalg.eigvalsh(e).min() > 0
+
+
+def test_perturbed_and_stretched_node_recipes():
+    ne = 12
+    nodes = pb.perturbed_cube_nodes(ne, seed=7)
+    base = _uniform_nodes(ne)
+    dev = (nodes / np.array([1.0, 1.0, 100.0]) - base) * ne
+    assert dev.min() >= 0.0 and dev.max() < 0.2 + 1e-12
+    assert np.array_equal(nodes, pb.perturbed_cube_nodes(ne, seed=7))
+    assert not np.array_equal(nodes, pb.perturbed_cube_nodes(ne, seed=8))
+    for k in (1, 5, 10):
+        x = pb.linear_sizes(60, 0.1, k / 10.0)
+        h = np.diff(x)
+        assert abs(h[0] - 0.1) < 1e-15 and abs(h[-1] - k / 10.0) < 1e-15
+        assert abs(x[-1] - 3.0 * (k + 1)) < 1e-12   # the App. B domain length
+        assert np.allclose(np.diff(h), (k / 10.0 - 0.1) / 59, atol=1e-15)
+    assert len(pb.STRETCH_CONFIGS) == 10 and len(pb.STRETCH_SIGMAS) == 5
