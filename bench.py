@@ -94,6 +94,10 @@ def main():
                     help="open-loop arrival rates as fractions of the closed-loop rate")
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--serving-budget-gib", type=float, default=8.0)
+    ap.add_argument("--family-seeds", type=int, default=10,
+                    help="perturbed-cube meshes in the mesh-family leg")
+    ap.add_argument("--only-families", action="store_true",
+                    help="run only the mesh-family leg (perturbed and stretched cubes)")
     ap.add_argument("--only-serving", action="store_true",
                     help="run only the serving leg (prints its JSON object)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -109,6 +113,9 @@ def main():
     from paper_2103_10476_amd import problems, solver
 
     torch.cuda.set_device(0)
+    if args.only_families:
+        print(json.dumps(families_leg(solver, problems, seeds=args.family_seeds)), flush=True)
+        return
     if args.only_serving:
         print(json.dumps(serving_leg(solver, problems, args)), flush=True)
         return
@@ -204,6 +211,7 @@ def main():
         result["variants"] = variants_leg(solver, p, drp, dcol, dval, db)
         result["numeric_resetup"] = resetup_leg(solver, p, drp, dcol, dval, db)
         result["variant_sweep"] = variant_sweep_leg(solver, problems)
+        result["mesh_families"] = families_leg(solver, problems, seeds=args.family_seeds)
         result["serving"] = serving_leg(solver, problems, args)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(p, b)
@@ -414,6 +422,152 @@ def variant_sweep_leg(solver, problems):
         log(f"[bench] variant sweep {cname}: " + ", ".join(
             f"{k} {v.get('iterations', v['status'])}" for k, v in table.items()))
         del drp, dcol, dval, b
+    return out
+
+
+def _to_device(p, b, X):
+    import torch
+    return (p.n, torch.from_numpy(p.rp).cuda(), torch.from_numpy(p.col).cuda(),
+            torch.from_numpy(p.val).cuda(), torch.from_numpy(b).cuda(),
+            torch.from_numpy(np.ascontiguousarray(X)).cuda())
+
+
+def _family_run(solver, dev, var, **kw):
+    """One setup + solve with coordinates on the GPU (inputs already resident): a dict of
+    iterations, operator complexity, times and status (or the failure status)."""
+    import torch
+    n, drp, dcol, dval, b, X = dev
+    o = solver.Options(variants=var, **kw)
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = solver.Hierarchy(n, drp, dcol, dval, options=o, coords=X)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, it, _, st = h.solve(b)
+        torch.cuda.synchronize()
+        inf = h.info()
+        h.close()
+        return {"iterations": it, "oc": inf["operator_complexity"], "status": st,
+                "setup_s": t1 - t0, "solve_s": time.perf_counter() - t1}
+    except Exception as e:  # the method's own failures (negative eigenvalue, zero diagonal)
+        msg = str(e)
+        return {"status": msg.split(":")[1].split("(")[0].strip() if ":" in msg else msg[:80]}
+
+
+def _perturbed_mesh(args):
+    from paper_2103_10476_amd import problems
+    return problems.perturbed_cube(*args)
+
+
+def _stretched_mesh(args):
+    from paper_2103_10476_amd import problems
+    return problems.stretched_cube(*args)
+
+
+def _perturbed_table(runs):
+    table = {}
+    for key, rs in runs.items():
+        ok = [r for r in rs if "iterations" in r]
+        table[key] = {"failures": len(rs) - len(ok),
+                      "failure_status": sorted({r["status"] for r in rs if "iterations" not in r}),
+                      "mean_iterations": round(float(np.mean([r["iterations"] for r in ok])), 2)
+                      if ok else None,
+                      "operator_complexity": round(float(np.mean([r["oc"] for r in ok])), 4)
+                      if ok else None,
+                      "setup_plus_solve_s_p50": round(pct([r["setup_s"] + r["solve_s"]
+                                                           for r in ok], 50), 4) if ok else None}
+    return table
+
+
+def _stretched_summary(res):
+    plain = res["plain"]
+    hist = {}
+    for k, rs in res.items():
+        if k == "plain":
+            continue
+        diffs = [a["iterations"] - r["iterations"] for a, r in zip(plain, rs)
+                 if "iterations" in a and "iterations" in r]
+        hist[k] = {"failures": sum("iterations" not in r for r in rs),
+                   "compared": len(diffs),
+                   "plain_minus_it": {"min": min(diffs), "max": max(diffs),
+                                      "within_3": sum(abs(d) <= 3 for d in diffs),
+                                      "at_least_15_fewer": sum(d >= 15 for d in diffs),
+                                      "more_than_plain": sum(d < 0 for d in diffs)}
+                   if diffs else None}
+    ok = [r["iterations"] for r in plain if "iterations" in r]
+    return {"plain_failures": len(plain) - len(ok),
+            "plain_mean_iterations": round(float(np.mean(ok)), 2) if ok else None,
+            "vs_plain": hist}
+
+
+def families_leg(solver, problems, seeds=10, ne=60):
+    """The paper's two mesh families on the GPU, with the distance-Laplacian strength
+    (theta 0.025) for both weights 1/d (the paper's text) and 1/d^2, coarsening to <= 1000
+    unknowns, Chebyshev(2) and CG to 1e-10 on the Dirichlet right-hand side.
+
+    * Randomly perturbed cube (Table 1 layout): ``seeds`` meshes of ne^3 elements x all 16
+      combinations; per combination the failures, and the mean iterations and operator
+      complexity over the runs that did not fail.
+    * Triaxially stretched reaction-diffusion cube (Fig. 2): the 10 (kx,ky,kz) x 5 sigma = 50
+      problems at ne^3 elements, Chebyshev interval end 1.1 lambda; per adaptation the
+      distribution of (plain SA iterations - its iterations) and its failures.
+    Meshes are built on host worker processes; each is uploaded once."""
+    import itertools
+    from concurrent.futures import ProcessPoolExecutor
+    names = ("sprsfy", "offlmp", "1norm", "cnstrnt")
+    combos = [tuple(n for n, on in zip(names, bits) if on)
+              for bits in itertools.product((0, 1), repeat=4)]
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    paper = dict(theta=0.025, max_coarse=1000, rtol=1e-10)
+    powers = (1, 2)
+    out = {}
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        meshes = list(ex.map(_perturbed_mesh, [(ne, s) for s in range(seeds)]))
+    t_mesh = time.perf_counter() - t0
+    runs = {pw: {"+".join(v) or "plain": [] for v in combos} for pw in powers}
+    t0 = time.perf_counter()
+    for mesh in meshes:
+        dev = _to_device(*mesh)
+        for pw in powers:
+            for v in combos:
+                runs[pw]["+".join(v) or "plain"].append(
+                    _family_run(solver, dev, v, dist_power=pw, **paper))
+        del dev
+    t_gpu = time.perf_counter() - t0
+    pc = {"elements": f"{ne}^3", "n": meshes[0][0].n, "nnz": meshes[0][0].nnz,
+          "seeds": seeds, "mesh_build_s": round(t_mesh, 1), "gpu_runs_s": round(t_gpu, 1)}
+    for pw in powers:
+        pc[f"weight_1/d^{pw}"] = _perturbed_table(runs[pw])
+        log(f"[bench] perturbed cube 1/d^{pw}: " + ", ".join(
+            f"{k} {v['mean_iterations']}/{v['failures']}f"
+            for k, v in pc[f"weight_1/d^{pw}"].items()))
+    out["perturbed_cube"] = pc
+    del meshes
+    cases = [(kx, ky, kz, sg, ne) for (kx, ky, kz) in problems.STRETCH_CONFIGS
+             for sg in problems.STRETCH_SIGMAS]
+    variants = {"plain": (), "1norm": ("1norm",), "offlmp": ("offlmp",),
+                "cnstrnt": ("cnstrnt",), "sprsfy": ("sprsfy",)}
+    res = {pw: {k: [] for k in variants} for pw in powers}
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        for mesh in ex.map(_stretched_mesh, cases):
+            dev = _to_device(*mesh)
+            for pw in powers:
+                for k, v in variants.items():
+                    res[pw][k].append(_family_run(solver, dev, v, cheb_boost=1.1,
+                                                  dist_power=pw, **paper))
+            del dev
+    sc = {"elements": f"{ne}^3", "problems": len(cases),
+          "seconds": round(time.perf_counter() - t0, 1)}
+    for pw in powers:
+        sc[f"weight_1/d^{pw}"] = _stretched_summary(res[pw])
+        log(f"[bench] stretched cube 1/d^{pw}: plain failures "
+            f"{sc[f'weight_1/d^{pw}']['plain_failures']}; " + ", ".join(
+                f"{k} {v['plain_minus_it']}"
+                for k, v in sc[f"weight_1/d^{pw}"]["vs_plain"].items()))
+    out["stretched_cube"] = sc
     return out
 
 

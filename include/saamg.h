@@ -82,6 +82,7 @@ typedef struct {
   double rtol;            /* CG stops when ||r|| <= rtol ||b|| (recurrence residual) [1e-8] */
   int32_t max_iter;       /* CG iteration cap [500]                                         */
   int32_t pcg_beta;       /* SA_BETA_FR | SA_BETA_PR (flexible) [FR; PR in FP32 mode]       */
+  int32_t dist_power;     /* sa_setup_coords weight 1/distance^p, p = 1 or 2, Sec. 3.1 [1]  */
 } sa_options;
 
 typedef struct {
@@ -139,10 +140,11 @@ sa_status sa_setup(const sa_context *ctx, const sa_csr *A, const double *nullspa
                    const sa_options *o, sa_hierarchy **out);
 
 /* sa_setup with the strength test of Sec. 3.1 taken on a distance Laplacian instead of on
- * the level operator.  L^(d) has the operator's pattern; an off-diagonal entry is -1/|x_i -
- * x_j|^2 (the reciprocal of the squared Euclidean distance between the two nodes, so the
- * labels involve no square root) and the diagonal makes every row sum zero; entry (i,j) is
- * strong iff |L_ij| >= theta sqrt(L_ii L_jj).  Coarse levels take as coordinates the
+ * the level operator.  L^(d) has the operator's pattern; an off-diagonal entry is -1/d_ij^p
+ * with d_ij the Euclidean distance between the two nodes (o->dist_power p = 1, the paper's
+ * definition, the default; p = 2 takes the reciprocal of the squared distance and needs no
+ * square root) and the diagonal makes every row sum zero; entry (i,j) is strong iff
+ * |L_ij| >= theta sqrt(L_ii L_jj).  Coarse levels take as coordinates the
  * centroids of their aggregates (members summed in ascending order, divided by the count).
  * Everything else is sa_setup's.
  *  coords  n x dim float64 node coordinates, row-major (node i at coords[i*dim .. i*dim+dim-1]),

@@ -38,6 +38,7 @@ typedef struct {
   double rtol;            /* PCG relative residual reduction                               */
   int32_t max_iter;       /* PCG iteration cap                                             */
   int32_t pcg_beta;       /* 0 Fletcher-Reeves, 1 Polak-Ribiere (flexible)                 */
+  int32_t dist_power;     /* distance-Laplacian weight 1/d^p: 1 (the text of Sec. 3.1) or 2 */
 } orc_options;
 
 void orc_default_options(orc_options *o);
@@ -74,7 +75,8 @@ void orc_destroy(void *h);
 int orc_strength(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
                  double theta, uint8_t *mask);
 int orc_distance_strength(int32_t n, const int32_t *rp, const int32_t *col,
-                          const double *coords, int32_t dim, double theta, uint8_t *mask);
+                          const double *coords, int32_t dim, double theta, int32_t dist_power,
+                          uint8_t *mask);
 int orc_aggregate(int32_t n, const int32_t *rp, const int32_t *col, const uint8_t *mask,
                   int32_t order, uint64_t seed, int32_t level, int32_t *agg, uint8_t *is_root,
                   int32_t *nc);

@@ -22,7 +22,7 @@ class OrcOptions(C.Structure):
                 ("agg_order", C.c_int32), ("seed", C.c_uint64), ("max_levels", C.c_int32),
                 ("max_coarse", C.c_int32), ("smoother", C.c_int32), ("degree", C.c_int32),
                 ("cheb_ratio", C.c_double), ("cheb_boost", C.c_double), ("rtol", C.c_double),
-                ("max_iter", C.c_int32), ("pcg_beta", C.c_int32)]
+                ("max_iter", C.c_int32), ("pcg_beta", C.c_int32), ("dist_power", C.c_int32)]
 
 
 _lib = None
@@ -56,7 +56,8 @@ def _setup_prototypes(L):
     L.orc_solve.argtypes = [P, P, P, P, P, P]
     L.orc_destroy.argtypes = [P]
     L.orc_strength.argtypes = [C.c_int32, P, P, P, C.c_double, P]
-    L.orc_distance_strength.argtypes = [C.c_int32, P, P, P, C.c_int32, C.c_double, P]
+    L.orc_distance_strength.argtypes = [C.c_int32, P, P, P, C.c_int32, C.c_double, C.c_int32,
+                                        P]
     L.orc_aggregate.argtypes = [C.c_int32, P, P, P, C.c_int32, C.c_uint64, C.c_int32, P, P, P]
     L.orc_sprsfy.argtypes = [C.c_int32, P, P, P, P, P, C.c_int32]
     L.orc_lump.argtypes = [C.c_int32, P, P, P, P, C.c_int32, C.c_double, P, P, P]
@@ -103,7 +104,7 @@ def _check(code):
 def make_options(theta=0.02, variants=(), one_norm_power=0, tau=1.1, sigma=1.0 / 3.0,
                  power_iters=10, agg_order=0, seed=12345, max_levels=10, max_coarse=1000,
                  smoother="chebyshev", degree=2, cheb_ratio=10.0, cheb_boost=1.0, rtol=1e-8,
-                 max_iter=500, pcg_beta="fr", **_ignored) -> OrcOptions:
+                 max_iter=500, pcg_beta="fr", dist_power=1, **_ignored) -> OrcOptions:
     o = OrcOptions()
     lib().orc_default_options(C.byref(o))
     o.theta = theta
@@ -126,6 +127,7 @@ def make_options(theta=0.02, variants=(), one_norm_power=0, tau=1.1, sigma=1.0 /
     o.rtol = rtol
     o.max_iter = max_iter
     o.pcg_beta = 1 if pcg_beta in (1, "pr") else 0
+    o.dist_power = dist_power
     return o
 
 
@@ -237,10 +239,11 @@ def strength(n, rp, col, val, theta):
     return m
 
 
-def distance_strength(n, rp, col, coords, theta):
+def distance_strength(n, rp, col, coords, theta, dist_power=1):
     rp, col, X = _i32(rp), _i32(col), _f64(coords).reshape(n, -1)
     m = np.empty(int(rp[n]), dtype=np.uint8)
-    _check(lib().orc_distance_strength(n, _p(rp), _p(col), _p(X), X.shape[1], theta, _p(m)))
+    _check(lib().orc_distance_strength(n, _p(rp), _p(col), _p(X), X.shape[1], theta,
+                                       dist_power, _p(m)))
     return m
 
 

@@ -186,16 +186,16 @@ void strength(const Csr &A, double theta, std::vector<uint8_t> &mask) {
 
 // ------------------------------------------------------------------------------------
 // Distance-Laplacian strength (Sec. 3.1): the labels come from a matrix L with A's pattern,
-// off-diagonals -w_ij with w_ij from the distance between the coordinates of i and j, and
-// the diagonal making each row sum zero; (i,j) is strong iff |L_ij| >= theta sqrt(L_ii L_jj).
-// Readings: w_ij = 1/|x_i - x_j|^2 (the reciprocal of the squared Euclidean distance, so no
-// square root enters the labels), the squared distance summed over the coordinates in order
-// from 0.0; every stored off-diagonal of A counts, explicit zeros included; L_ii = the sum of
-// the row's w_ij in ascending column order from 0.0; the test is evaluated squared as for
-// A; coincident coordinates of two connected nodes are an error.
+// off-diagonals -w_ij with w_ij the reciprocal of the distance between the coordinates of i
+// and j, and the diagonal making each row sum zero; (i,j) is strong iff
+// |L_ij| >= theta sqrt(L_ii L_jj).  Readings: the squared distance d2 is summed over the
+// coordinates in order from 0.0; w_ij = 1/sqrt(d2) (power 1, the paper's text) or 1/d2
+// (power 2, no square root); every stored off-diagonal of A counts, explicit zeros included;
+// L_ii = the sum of the row's w_ij in ascending column order from 0.0; the test is evaluated
+// squared as for A; coincident coordinates of two connected nodes are an error.
 // ------------------------------------------------------------------------------------
 int distance_strength(const Csr &A, const std::vector<double> &xyz, int dim, double theta,
-                      std::vector<uint8_t> &mask) {
+                      int power, std::vector<uint8_t> &mask) {
   std::vector<double> w(A.nnz(), 0.0), Ld(A.nr, 0.0);
   for (int i = 0; i < A.nr; ++i) {
     double s = 0.0;
@@ -208,7 +208,7 @@ int distance_strength(const Csr &A, const std::vector<double> &xyz, int dim, dou
         d2 += t * t;
       }
       if (!(d2 > 0.0)) return fail(ST_INVALID, "coincident coordinates of connected nodes");
-      w[e] = 1.0 / d2;
+      w[e] = power == 1 ? 1.0 / std::sqrt(d2) : 1.0 / d2;
       s += w[e];
     }
     Ld[i] = s;
@@ -812,7 +812,7 @@ int build_level(Hier &H, int l) {
   Level &L = H.lv[l];
   const orc_options &o = H.o;
   if (H.dim > 0) {
-    int st = distance_strength(L.As, L.xyz, H.dim, o.theta, L.mask);
+    int st = distance_strength(L.As, L.xyz, H.dim, o.theta, o.dist_power, L.mask);
     if (st) return st;
   } else {
     strength(L.As, o.theta, L.mask);
@@ -941,6 +941,7 @@ void orc_default_options(orc_options *o) {
   o->rtol = 1e-8;
   o->max_iter = 500;
   o->pcg_beta = 0;
+  o->dist_power = 1;
 }
 
 uint64_t orc_splitmix64(uint64_t seed, uint64_t k) { return splitmix64(seed, k); }
@@ -966,6 +967,7 @@ int orc_setup_coords(int32_t n, const int32_t *rp, const int32_t *col, const dou
       o->power_iters < 1)
     return fail(ST_INVALID, "bad options");
   if (coords && (dim < 1 || dim > 3)) return fail(ST_INVALID, "coordinate dimension");
+  if (o->dist_power != 1 && o->dist_power != 2) return fail(ST_INVALID, "dist_power");
   for (int64_t k = 0; coords && k < (int64_t)n * dim; ++k)
     if (!std::isfinite(coords[k])) return fail(ST_INVALID, "non-finite coordinate");
   Hier *H = new Hier();
@@ -1258,11 +1260,13 @@ void orc_destroy(void *h) { delete (Hier *)h; }
 // ---- single steps ----------------------------------------------------------------------
 
 int orc_distance_strength(int32_t n, const int32_t *rp, const int32_t *col,
-                          const double *coords, int32_t dim, double theta, uint8_t *mask) {
+                          const double *coords, int32_t dim, double theta, int32_t dist_power,
+                          uint8_t *mask) {
+  if (dist_power != 1 && dist_power != 2) return fail(ST_INVALID, "dist_power");
   Csr A = make_csr(n, n, rp, col, nullptr);
   std::vector<double> xyz(coords, coords + (size_t)n * dim);
   std::vector<uint8_t> m;
-  int st = distance_strength(A, xyz, dim, theta, m);
+  int st = distance_strength(A, xyz, dim, theta, dist_power, m);
   if (st) return st;
   std::copy(m.begin(), m.end(), mask);
   return ST_OK;

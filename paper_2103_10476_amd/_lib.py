@@ -45,7 +45,7 @@ class SaOptions(C.Structure):
                 ("max_levels", C.c_int32), ("max_coarse", C.c_int32), ("smoother", C.c_int32),
                 ("degree", C.c_int32), ("precision", C.c_int32), ("cheb_ratio", C.c_double),
                 ("cheb_boost", C.c_double), ("rtol", C.c_double), ("max_iter", C.c_int32),
-                ("pcg_beta", C.c_int32)]
+                ("pcg_beta", C.c_int32), ("dist_power", C.c_int32)]
 
 
 class SaCsr(C.Structure):

@@ -56,6 +56,7 @@ static void validate_options(const sa_options &o) {
   if (o.precision != SA_FP64 && o.precision != SA_FP32_VCYCLE)
     throw Error(SA_ERR_INVALID_ARG, "precision");
   if (o.variants & ~15u) throw Error(SA_ERR_INVALID_ARG, "unknown variant bits");
+  if (o.dist_power != 1 && o.dist_power != 2) throw Error(SA_ERR_INVALID_ARG, "dist_power");
 }
 
 static void copy_in(void *dst, const void *src, size_t bytes, sa_location loc, hipStream_t s) {
@@ -162,7 +163,8 @@ static bool build_level(sa_hierarchy *h, int l) {
   const double *sval = L.As.val;  // the matrix the strength test reads: A, or L^(d)
   if (h->dim > 0) {
     double *w = tmp.alloc<double>(L.As.nnz);
-    distance_weights(n, L.As.rp, L.As.col, L.xyz, h->dim, w, dval, h->err, E_COORD, s);
+    distance_weights(n, L.As.rp, L.As.col, L.xyz, h->dim, o.dist_power, w, dval, h->err,
+                     E_COORD, s);
     check_err(h, E_COORD, SA_ERR_INVALID_ARG, "coincident coordinates of connected nodes");
     sval = w;
   } else {
@@ -738,6 +740,7 @@ void sa_default_options(sa_options *o) {
   o->rtol = 1e-8;
   o->max_iter = 500;
   o->pcg_beta = -1;
+  o->dist_power = 1;
 }
 
 sa_status sa_setup_coords(const sa_context *ctx, const sa_csr *A, const double *nullspace,

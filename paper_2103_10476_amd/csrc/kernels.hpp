@@ -96,12 +96,12 @@ void strength(int32_t n, const int32_t *rp, const int32_t *col, const double *va
               const double *dval, double th2, uint8_t *mask, int32_t *scount, bool wave,
               hipStream_t s);
 int32_t max_row_length(int32_t n, const int32_t *rp, hipStream_t s);
-// Distance-Laplacian weights (Sec. 3.1): w[k] = 1/|x_i - x_j|^2 off the diagonal (0 on it),
-// Ld[i] = sum of row i's weights; xyz is n x dim (dim 1..3).  Sets *err |= ebit when two
-// connected nodes coincide.  strength() on (w, Ld) gives the distance labels.
+// Distance-Laplacian weights (Sec. 3.1): w[k] = 1/|x_i - x_j|^power off the diagonal (0 on
+// it; power 1 or 2), Ld[i] = sum of row i's weights; xyz is n x dim (dim 1..3).  Sets
+// *err |= ebit when two connected nodes coincide.  strength() on (w, Ld) gives the labels.
 void distance_weights(int32_t n, const int32_t *rp, const int32_t *col, const double *xyz,
-                      int32_t dim, double *w, double *Ld, int32_t *err, int32_t ebit,
-                      hipStream_t s);
+                      int32_t dim, int32_t power, double *w, double *Ld, int32_t *err,
+                      int32_t ebit, hipStream_t s);
 // *err |= ebit when some x[0..m) is not finite.
 void check_finite(const double *x, int64_t m, int32_t *err, int32_t ebit, hipStream_t s);
 // cxyz[J] = centroid of aggregate J's members (nc x dim), summed in ascending vertex order.

@@ -163,9 +163,9 @@ void strength(int32_t n, const int32_t *rp, const int32_t *col, const double *va
 
 // ---- distance-Laplacian weights (Sec. 3.1) -------------------------------------------------
 // The strength test can be taken on a Laplacian built from node coordinates instead of on A:
-// same pattern, off-diagonal weight w = 1/|x_i - x_j|^2 (the squared distance summed over the
-// coordinates in order from 0), diagonal Ld[i] = the row's weights summed in ascending column
-// order from 0.  k_strength then runs on (w, Ld) unchanged: |L_ij| >= theta sqrt(L_ii L_jj)
+// same pattern, off-diagonal weight w = 1/d^P with d the distance (the squared distance d2
+// summed over the coordinates in order from 0; P = 1: 1/sqrt(d2), both correctly rounded;
+// P = 2: 1/d2), diagonal Ld[i] = the row's weights summed in ascending column order from 0.  k_strength then runs on (w, Ld) unchanged: |L_ij| >= theta sqrt(L_ii L_jj)
 // squared is w^2 >= theta^2 Ld_i Ld_j.  A zero (or NaN) distance between two connected nodes
 // sets err bit `ebit`.
 template <int D>
@@ -178,7 +178,7 @@ __device__ inline double dist2(const double *__restrict__ xyz, int32_t i, int32_
   }
   return d2;
 }
-template <int D>
+template <int D, int P>
 __global__ void k_distance_weights(int32_t n, const int32_t *rp, const int32_t *col,
                                    const double *__restrict__ xyz, double *w, double *Ld,
                                    int32_t *err, int32_t ebit) {
@@ -193,21 +193,31 @@ __global__ void k_distance_weights(int32_t n, const int32_t *rp, const int32_t *
     }
     const double d2 = dist2<D>(xyz, i, j);
     bad |= !(d2 > 0.0);
-    const double wk = 1.0 / d2;
+    const double wk = P == 1 ? 1.0 / sqrt(d2) : 1.0 / d2;
     w[k] = wk;
     s = s + wk;
   }
   Ld[i] = s;
   if (bad) atomicOr(err, ebit);
 }
+template <int D>
+static void distance_weights_dim(int32_t n, const int32_t *rp, const int32_t *col,
+                                 const double *xyz, int32_t power, double *w, double *Ld,
+                                 int32_t *err, int32_t ebit, hipStream_t s) {
+  if (power == 1)
+    k_distance_weights<D, 1><<<grid_for(n), kBlock, 0, s>>>(n, rp, col, xyz, w, Ld, err, ebit);
+  else
+    k_distance_weights<D, 2><<<grid_for(n), kBlock, 0, s>>>(n, rp, col, xyz, w, Ld, err, ebit);
+}
 void distance_weights(int32_t n, const int32_t *rp, const int32_t *col, const double *xyz,
-                      int32_t dim, double *w, double *Ld, int32_t *err, int32_t ebit,
-                      hipStream_t s) {
+                      int32_t dim, int32_t power, double *w, double *Ld, int32_t *err,
+                      int32_t ebit, hipStream_t s) {
   if (n <= 0) return;
+  if (power != 1 && power != 2) throw Error(SA_ERR_INVALID_ARG, "dist_power");
   switch (dim) {
-    case 1: k_distance_weights<1><<<grid_for(n), kBlock, 0, s>>>(n, rp, col, xyz, w, Ld, err, ebit); break;
-    case 2: k_distance_weights<2><<<grid_for(n), kBlock, 0, s>>>(n, rp, col, xyz, w, Ld, err, ebit); break;
-    case 3: k_distance_weights<3><<<grid_for(n), kBlock, 0, s>>>(n, rp, col, xyz, w, Ld, err, ebit); break;
+    case 1: distance_weights_dim<1>(n, rp, col, xyz, power, w, Ld, err, ebit, s); break;
+    case 2: distance_weights_dim<2>(n, rp, col, xyz, power, w, Ld, err, ebit, s); break;
+    case 3: distance_weights_dim<3>(n, rp, col, xyz, power, w, Ld, err, ebit, s); break;
     default: throw Error(SA_ERR_INVALID_ARG, "coordinate dimension");
   }
   SA_LAUNCH_CHECK();

@@ -37,6 +37,7 @@ class Options:
     rtol: float = 1e-8
     max_iter: int = 500
     pcg_beta: str = "auto"
+    dist_power: int = 1
 
     def to_c(self) -> _lib.SaOptions:
         o = _lib.SaOptions()
@@ -62,6 +63,7 @@ class Options:
         o.rtol = self.rtol
         o.max_iter = self.max_iter
         o.pcg_beta = {"auto": -1, "fr": 0, "pr": 1}[self.pcg_beta]
+        o.dist_power = self.dist_power
         return o
 
     def as_dict(self) -> dict:

@@ -41,12 +41,20 @@ CASES = [
      dict(max_coarse=60, variants=("offlmp", "1norm"), cheb_boost=1.1)),
     ("q1 18 theta .08 hashed order", lambda: (pb.q1_hex(18), _jitter(pb.q1_coords(18), 0.02, 4)),
      dict(theta=0.08, max_coarse=40, agg_order="hashed", seed=77)),
+    # weights 1/d^2 (no square root)
+    ("fd7 17^3 a1000 power 2", lambda: (pb.fd7_stretched(17, 1000.0), pb.fd7_coords(17, 1000.0)),
+     dict(max_coarse=40, dist_power=2)),
+    ("q1 kappa 14 jittered power 2", lambda: (pb.q1_random_kappa(14, seed=9),
+                                              _jitter(pb.q1_coords(14), 0.01, 3)),
+     dict(max_coarse=60, variants=("offlmp", "1norm"), cheb_boost=1.1, dist_power=2)),
+    ("perturbed cube 20 power 2", lambda: pb.perturbed_cube(20, 5)[::2],
+     dict(theta=0.025, max_coarse=100, variants=("offlmp",), dist_power=2)),
 ]
 
 
 @pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
 def test_distance_strength_matches_oracle(name, make, kw):
-    p, X = make()
+    p, X = make()  # (problem, coordinates)
     g, h = run_both(p, coords=X, rtol=1e-10, **kw)
     assert len(h.levels) >= 2, name
     compare_setup(g, h)
@@ -74,11 +82,14 @@ def test_bad_coordinates_fail_like_the_oracle():
     bad_same[9] = bad_same[10]          # x-neighbours at one point
     bad_nan = X.copy()
     bad_nan[5, 2] = np.inf
-    for Y in (bad_same, bad_nan, np.zeros((p.n, 4)) + np.arange(p.n)[:, None]):
+    for Y, pw in ((bad_same, 1), (bad_same, 2), (bad_nan, 1),
+                  (np.zeros((p.n, 4)) + np.arange(p.n)[:, None], 1), (X, 3)):
         with pytest.raises(orc.OracleError) as eo:
-            orc.OracleHierarchy(p.n, p.rp, p.col, p.val, coords=Y, max_coarse=20)
+            orc.OracleHierarchy(p.n, p.rp, p.col, p.val, coords=Y, max_coarse=20,
+                                dist_power=pw)
         with pytest.raises(SaError) as eg:
-            solver.Hierarchy.from_problem(p, options=solver.Options(max_coarse=20), coords=Y)
+            solver.Hierarchy.from_problem(p, options=solver.Options(max_coarse=20,
+                                                                    dist_power=pw), coords=Y)
         assert eg.value.code == eo.value.code == -1
     # the library still works afterwards
     g = solver.Hierarchy.from_problem(p, options=solver.Options(max_coarse=20), coords=X)
@@ -112,10 +123,20 @@ def test_resetup_keeps_distance_labels():
 
 
 def test_full_size_fd7_128_distance():
-    """128^3 graded cube with its node coordinates: every level bitwise, solve to 1e-12."""
+    """128^3 graded cube with its node coordinates.  Weights 1/d: plain SA's prolongator
+    eigenvalue estimate turns negative on both sides (the failure the adaptations address);
+    weights 1/d^2: every level bitwise, solve to 1e-12."""
+    from oracle import oracle as orc
+    from paper_2103_10476_amd import solver
+    from paper_2103_10476_amd._lib import SaError
     p = pb.workload("fd7_128_a1000")
     X = pb.fd7_coords(128, 1000.0)
-    g, h = run_both(p, coords=X)
+    with pytest.raises(SaError) as eg:
+        solver.Hierarchy.from_problem(p, options=solver.Options(), coords=X)
+    with pytest.raises(orc.OracleError) as eo:
+        orc.OracleHierarchy(p.n, p.rp, p.col, p.val, coords=X)
+    assert eg.value.code == eo.value.code == -4
+    g, h = run_both(p, coords=X, dist_power=2)
     compare_setup(g, h)
     it, _ = compare_solve(g, h, pb.random_rhs(p.n, pb.RHS_SEED["fd7_128_a1000"]))
     log(f"[distance] 128^3: levels {g.info()['n']} iterations {it} setup "

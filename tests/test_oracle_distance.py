@@ -1,13 +1,14 @@
 """Oracle pins for the distance-Laplacian strength (Sec. 3.1) and the coarse coordinates.
 
-L^(d) has A's pattern, off-diagonals -1/|x_i - x_j|^2 and a zero row sum; (i,j) is strong iff
-|L_ij| >= theta sqrt(L_ii L_jj).  On integer grids every quantity is an exact small integer
-(or a power-of-two fraction), so the labels have closed forms in the neighbour counts:
+L^(d) has A's pattern, off-diagonals -1/|x_i - x_j|^p (p = 1, the paper's text, or p = 2) and a
+zero row sum; (i,j) is strong iff |L_ij| >= theta sqrt(L_ii L_jj).  On integer grids every
+quantity is an exact small integer (or a power-of-two fraction), so the labels have closed forms
+in the neighbour counts:
 
 * uniform unit grid: w = 1, L_ii = n_i (the number of stored neighbours), so (i,j) is strong
-  iff n_i n_j <= 1/theta^2;
-* unit spacing in x and y, spacing 1/4 in z: w = 1 in-plane, 16 across planes,
-  L_ii = p_i + 16 q_i (p_i in-plane and q_i vertical neighbours);
+  iff n_i n_j <= 1/theta^2, for either power;
+* unit spacing in x and y, spacing 1/4 in z: w = 1 in-plane, 4^p across planes,
+  L_ii = p_i + 4^p q_i (p_i in-plane and q_i vertical neighbours);
 * the labels depend on the coordinates only: any matrix values on the pattern, any power-of-two
   scaling, integer translation or axis permutation of the coordinates give the same labels;
 * when A itself is the weighted graph Laplacian of the coordinates, the classical test on A
@@ -16,6 +17,8 @@ L^(d) has A's pattern, off-diagonals -1/|x_i - x_j|^2 and a zero row sum; (i,j) 
 Coarse coordinates are the aggregates' centroids; a full setup on coordinates builds a
 hierarchy whose every coarse level carries them, and solves the stretched problems.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -31,58 +34,63 @@ def _offdiag(p):
     return rows, p.col, rows != p.col
 
 
+@pytest.mark.parametrize("power", [1, 2])
 @pytest.mark.parametrize("theta", [0.1, 0.19, 0.25, 0.3])
-def test_uniform_grid_closed_form(orc, theta):
+def test_uniform_grid_closed_form(orc, theta, power):
     p = pb.fd7_stretched(6, 1.0)  # pattern of a 6^3 7-point grid (values unused)
     X = pb.grid_coords(np.arange(6.0), np.arange(6.0), np.arange(6.0))
-    m = orc.distance_strength(p.n, p.rp, p.col, X, theta)
+    m = orc.distance_strength(p.n, p.rp, p.col, X, theta, power)
     rows, cols, off = _offdiag(p)
     n = _counts(p)
     want = np.where(off, np.where(n[rows] * n[cols] <= 1.0 / theta ** 2, 1, 0), 3)
     assert np.array_equal(m, want.astype(np.uint8))
     # a smaller theta than 1/6 makes every connection strong
-    m0 = orc.distance_strength(p.n, p.rp, p.col, X, 0.16)
+    m0 = orc.distance_strength(p.n, p.rp, p.col, X, 0.16, power)
     assert np.all(m0[off] == 1)
 
 
+@pytest.mark.parametrize("power", [1, 2])
 @pytest.mark.parametrize("theta", [0.02, 0.05, 0.2, 0.45])
-def test_anisotropic_grid_closed_form(orc, theta):
+def test_anisotropic_grid_closed_form(orc, theta, power):
     nx, nz = 5, 7
     p = pb.fd7_stretched(nz, 1.0, nx=nx, ny=nx)
     X = pb.grid_coords(np.arange(nx, dtype=float), np.arange(nx, dtype=float),
                        0.25 * np.arange(nz))
-    m = orc.distance_strength(p.n, p.rp, p.col, X, theta)
+    m = orc.distance_strength(p.n, p.rp, p.col, X, theta, power)
     rows, cols, off = _offdiag(p)
     vertical = np.abs(cols - rows) == nx * nx
     q = np.zeros(p.n, dtype=np.int64)
     np.add.at(q, rows[vertical], 1)
     pcount = _counts(p) - q
-    Ld = pcount + 16.0 * q
-    w = np.where(vertical, 16.0, 1.0)
+    wz = 4.0 ** power
+    Ld = pcount + wz * q
+    w = np.where(vertical, wz, 1.0)
     strong = w * w >= theta * theta * Ld[rows] * Ld[cols]
     want = np.where(off, strong.astype(np.uint8), 3)
     assert np.array_equal(m, want.astype(np.uint8))
-    if theta == 0.05:  # the interesting regime: vertical strong, in-plane weak inside
+    if theta == 0.05 and power == 2:  # vertical strong, in-plane weak inside
         inner = (pcount[rows] == 4) & (q[rows] == 2) & (pcount[cols] == 4) & (q[cols] == 2)
         assert np.all(m[off & vertical & inner] == 1)
         assert np.all(m[off & ~vertical & inner] == 0)
 
 
-def test_labels_depend_on_coordinates_only(orc):
+@pytest.mark.parametrize("power", [1, 2])
+def test_labels_depend_on_coordinates_only(orc, power):
     p = pb.q1_hex(7)
     X = pb.q1_coords(7)
-    m = orc.distance_strength(p.n, p.rp, p.col, X, 0.05)
+    m = orc.distance_strength(p.n, p.rp, p.col, X, 0.05, power)
     # power-of-two scaling, integer translation (on an integer grid), axis permutation
     Xi = X * 7.0  # integer coordinates 1..6
     for Y in (X * 0.125, X * 1024.0, Xi + 3.0, Xi - 100.0):
-        assert np.array_equal(orc.distance_strength(p.n, p.rp, p.col, Y, 0.05), m)
+        assert np.array_equal(orc.distance_strength(p.n, p.rp, p.col, Y, 0.05, power), m)
     # the full setup ignores A's values for the labels: D A D gives the same fine labels
     rng = np.random.Generator(np.random.PCG64(2))
     d = rng.uniform(0.5, 2.0, size=p.n)
     rows = np.repeat(np.arange(p.n), np.diff(p.rp))
-    h1 = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, coords=X, theta=0.05, max_coarse=20)
+    h1 = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, coords=X, theta=0.05, max_coarse=20,
+                             dist_power=power)
     h2 = orc.OracleHierarchy(p.n, p.rp, p.col, (d[rows] * p.val) * d[p.col], coords=X,
-                             theta=0.05, max_coarse=20)
+                             theta=0.05, max_coarse=20, dist_power=power)
     assert np.array_equal(h1.levels[0].mask, m)
     assert np.array_equal(h2.levels[0].mask, m)
     assert np.array_equal(h1.levels[0].agg, h2.levels[0].agg)
@@ -112,8 +120,9 @@ def test_axis_permutation_of_a_box(orc):
         assert lab[(new_index(int(r)), new_index(int(c)))] == int(v)
 
 
-def test_graph_laplacian_matrix_agrees_with_classical_test(orc):
-    """A = L^(d) of random coordinates (weights 1/d^2, diagonal summed in ascending column
+@pytest.mark.parametrize("power", [1, 2])
+def test_graph_laplacian_matrix_agrees_with_classical_test(orc, power):
+    """A = L^(d) of random coordinates (weights 1/d^p, diagonal summed in ascending column
     order from 0): the classical labels of A are the distance labels."""
     p = pb.q1_hex(6)
     rng = np.random.Generator(np.random.PCG64(11))
@@ -130,12 +139,13 @@ def test_graph_laplacian_matrix_agrees_with_classical_test(orc):
             d2 = 0.0
             for k in range(3):
                 d2 = d2 + t[k] * t[k]
-            val[e] = -(1.0 / d2)
-            s = s + 1.0 / d2
+            w = 1.0 / math.sqrt(d2) if power == 1 else 1.0 / d2
+            val[e] = -w
+            s = s + w
         val[dpos] = s
     for theta in (0.02, 0.08, 0.15):
         assert np.array_equal(orc.strength(p.n, p.rp, p.col, val, theta),
-                              orc.distance_strength(p.n, p.rp, p.col, X, theta))
+                              orc.distance_strength(p.n, p.rp, p.col, X, theta, power))
 
 
 def test_coarse_coordinates_are_centroids(orc):
@@ -188,6 +198,8 @@ def test_distance_setup_errors(orc):
     with pytest.raises(orc.OracleError):
         orc.OracleHierarchy(p.n, p.rp, p.col, p.val, max_coarse=10,
                             coords=np.zeros((p.n, 4)) + np.arange(p.n)[:, None])
+    with pytest.raises(orc.OracleError):
+        orc.OracleHierarchy(p.n, p.rp, p.col, p.val, coords=X, max_coarse=10, dist_power=3)
     # a problem that fits the coarsest level never computes labels: no error
     Y = X.copy()
     Y[7] = Y[8]
