@@ -39,6 +39,7 @@ typedef struct {
   int32_t max_iter;       /* PCG iteration cap                                             */
   int32_t pcg_beta;       /* 0 Fletcher-Reeves, 1 Polak-Ribiere (flexible)                 */
   int32_t dist_power;     /* distance-Laplacian weight 1/d^p: 1 (the text of Sec. 3.1) or 2 */
+  int32_t coarse_solver;  /* 0 Cholesky (symmetric coarsest operator), 1 LU without pivoting */
 } orc_options;
 
 void orc_default_options(orc_options *o);
@@ -69,6 +70,10 @@ int orc_export(const void *h, int lvl, int what, void *buf);
 int orc_vcycle(const void *h, const double *f, double *u);
 int orc_solve(const void *h, const double *b, double *x, int32_t *iters, double *relres,
               double *rr_history /* NULL or max_iter+1 entries */);
+/* restarted flexible GMRES(restart), V-cycle as right preconditioner (Sec. 3.4's solver);
+ * rr_history: NULL or max_iter+1 entries of the residual norm (index 0 = ||b||) */
+int orc_solve_gmres(const void *h, const double *b, double *x, int32_t restart, int32_t *iters,
+                    double *relres, double *rr_history);
 void orc_destroy(void *h);
 
 /* ---- single steps (inputs given explicitly) ---- */

@@ -22,7 +22,8 @@ class OrcOptions(C.Structure):
                 ("agg_order", C.c_int32), ("seed", C.c_uint64), ("max_levels", C.c_int32),
                 ("max_coarse", C.c_int32), ("smoother", C.c_int32), ("degree", C.c_int32),
                 ("cheb_ratio", C.c_double), ("cheb_boost", C.c_double), ("rtol", C.c_double),
-                ("max_iter", C.c_int32), ("pcg_beta", C.c_int32), ("dist_power", C.c_int32)]
+                ("max_iter", C.c_int32), ("pcg_beta", C.c_int32), ("dist_power", C.c_int32),
+                ("coarse_solver", C.c_int32)]
 
 
 _lib = None
@@ -54,6 +55,7 @@ def _setup_prototypes(L):
     L.orc_export.argtypes = [P, C.c_int, C.c_int, P]
     L.orc_vcycle.argtypes = [P, P, P]
     L.orc_solve.argtypes = [P, P, P, P, P, P]
+    L.orc_solve_gmres.argtypes = [P, P, P, C.c_int32, P, P, P]
     L.orc_destroy.argtypes = [P]
     L.orc_strength.argtypes = [C.c_int32, P, P, P, C.c_double, P]
     L.orc_distance_strength.argtypes = [C.c_int32, P, P, P, C.c_int32, C.c_double, C.c_int32,
@@ -104,7 +106,8 @@ def _check(code):
 def make_options(theta=0.02, variants=(), one_norm_power=0, tau=1.1, sigma=1.0 / 3.0,
                  power_iters=10, agg_order=0, seed=12345, max_levels=10, max_coarse=1000,
                  smoother="chebyshev", degree=2, cheb_ratio=10.0, cheb_boost=1.0, rtol=1e-8,
-                 max_iter=500, pcg_beta="fr", dist_power=1, **_ignored) -> OrcOptions:
+                 max_iter=500, pcg_beta="fr", dist_power=1, coarse_solver="cholesky",
+                 **_ignored) -> OrcOptions:
     o = OrcOptions()
     lib().orc_default_options(C.byref(o))
     o.theta = theta
@@ -128,6 +131,7 @@ def make_options(theta=0.02, variants=(), one_norm_power=0, tau=1.1, sigma=1.0 /
     o.max_iter = max_iter
     o.pcg_beta = 1 if pcg_beta in (1, "pr") else 0
     o.dist_power = dist_power
+    o.coarse_solver = 1 if coarse_solver in (1, "lu") else 0
     return o
 
 
@@ -215,6 +219,22 @@ class OracleHierarchy:
         hist = np.zeros(self.opts.max_iter + 1) if history else None
         code = _check(lib().orc_solve(self.h, _p(b), _p(x), C.byref(it), C.byref(rr),
                                       None if hist is None else _p(hist)))
+        out = {"x": x, "iterations": it.value, "rel_residual": rr.value,
+               "converged": code == 0}
+        if history:
+            out["history"] = hist[: it.value + 1]
+        return out
+
+    def solve_gmres(self, b, restart=30, history=False):
+        """Restarted flexible GMRES with the V-cycle as right preconditioner; ``history``
+        holds the residual norm after each Arnoldi step (index 0: ||b||)."""
+        b = _f64(b)
+        x = np.empty_like(b)
+        it = C.c_int32()
+        rr = C.c_double()
+        hist = np.zeros(self.opts.max_iter + 1) if history else None
+        code = _check(lib().orc_solve_gmres(self.h, _p(b), _p(x), restart, C.byref(it),
+                                            C.byref(rr), None if hist is None else _p(hist)))
         out = {"x": x, "iterations": it.value, "rel_residual": rr.value,
                "converged": code == 0}
         if history:

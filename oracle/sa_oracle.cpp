@@ -753,7 +753,8 @@ struct Level {
   Csr P, R;
   std::vector<double> sm_invD;
   double sm_lambda = 0.0;
-  std::vector<double> chol;  // coarsest only: dense Cholesky factor (row-major, lower)
+  std::vector<double> chol;  // coarsest only: dense Cholesky factor (row-major, lower), or
+                             // the LU factors (unit L strictly below, U on and above)
   std::vector<double> xyz;   // node coordinates (n x dim) when the distance strength is used
 };
 
@@ -788,6 +789,67 @@ int cholesky(const Csr &A, std::vector<double> &L) {
     }
   }
   return ST_OK;
+}
+
+// Dense LU of the coarsest operator without pivoting (for nonsymmetric operators, solved by
+// GMRES), Doolittle's order: u_kj = a_kj - sum_{m<k} l_km u_mj, l_ik = (a_ik - sum_{m<k}
+// l_im u_mk)/u_kk, sums ascending in m.  A zero or non-finite pivot is an error.
+int lu_factor(const Csr &A, std::vector<double> &F) {
+  int n = A.nr;
+  if (n > 8192) return fail(ST_COARSE, "coarsest level too large for the dense solver");
+  std::vector<double> D((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) D[(size_t)i * n + A.col[e]] = A.val[e];
+  F.assign((size_t)n * n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    for (int j = k; j < n; ++j) {
+      double t = D[(size_t)k * n + j];
+      for (int m = 0; m < k; ++m) t -= F[(size_t)k * n + m] * F[(size_t)m * n + j];
+      F[(size_t)k * n + j] = t;
+    }
+    const double ukk = F[(size_t)k * n + k];
+    if (!(ukk != 0.0) || !std::isfinite(ukk)) return fail(ST_COARSE, "coarse LU pivot zero");
+    for (int i = k + 1; i < n; ++i) {
+      double t = D[(size_t)i * n + k];
+      for (int m = 0; m < k; ++m) t -= F[(size_t)i * n + m] * F[(size_t)m * n + k];
+      F[(size_t)i * n + k] = t / ukk;
+    }
+  }
+  return ST_OK;
+}
+
+void lu_solve(const std::vector<double> &F, int n, const std::vector<double> &f,
+              std::vector<double> &u) {
+  std::vector<double> y(n);
+  for (int i = 0; i < n; ++i) {
+    double t = f[i];
+    for (int k = 0; k < i; ++k) t -= F[(size_t)i * n + k] * y[k];
+    y[i] = t;
+  }
+  u.assign(n, 0.0);
+  for (int i = n - 1; i >= 0; --i) {
+    double t = y[i];
+    for (int k = i + 1; k < n; ++k) t -= F[(size_t)i * n + k] * u[k];
+    u[i] = t / F[(size_t)i * n + i];
+  }
+}
+
+// The Cholesky factor reads only the lower triangle, so a nonsymmetric coarsest operator
+// would be solved as another matrix; such operators must take the LU solver.  Symmetric
+// here: max |a_ij - a_ji| <= 1e-10 max |a_ij| (Galerkin products of a symmetric matrix are
+// symmetric up to rounding).
+bool nearly_symmetric(const Csr &A) {
+  const int n = A.nr;
+  std::vector<double> D((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) D[(size_t)i * n + A.col[e]] = A.val[e];
+  double amax = 0.0, asym = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      amax = std::max(amax, std::fabs(D[(size_t)i * n + j]));
+      asym = std::max(asym, std::fabs(D[(size_t)i * n + j] - D[(size_t)j * n + i]));
+    }
+  return asym <= 1e-10 * amax;
 }
 
 void chol_solve(const std::vector<double> &L, int n, const std::vector<double> &f,
@@ -910,7 +972,12 @@ int finish(Hier &H) {
     if (st) return st;
     L.sm_lambda = L.sm_lambda * o.cheb_boost;
   }
-  return cholesky(H.lv[nl - 1].A, H.lv[nl - 1].chol);
+  Level &Lc = H.lv[nl - 1];
+  if (Lc.A.nr > 8192) return fail(ST_COARSE, "coarsest level too large for the dense solver");
+  if (o.coarse_solver == 1) return lu_factor(Lc.A, Lc.chol);
+  if (!nearly_symmetric(Lc.A))
+    return fail(ST_COARSE, "coarsest operator not symmetric: use the LU coarse solver");
+  return cholesky(Lc.A, Lc.chol);
 }
 
 }  // namespace
@@ -942,6 +1009,7 @@ void orc_default_options(orc_options *o) {
   o->max_iter = 500;
   o->pcg_beta = 0;
   o->dist_power = 1;
+  o->coarse_solver = 0;
 }
 
 uint64_t orc_splitmix64(uint64_t seed, uint64_t k) { return splitmix64(seed, k); }
@@ -967,6 +1035,7 @@ int orc_setup_coords(int32_t n, const int32_t *rp, const int32_t *col, const dou
       o->power_iters < 1)
     return fail(ST_INVALID, "bad options");
   if (coords && (dim < 1 || dim > 3)) return fail(ST_INVALID, "coordinate dimension");
+  if (o->coarse_solver != 0 && o->coarse_solver != 1) return fail(ST_INVALID, "coarse_solver");
   if (o->dist_power != 1 && o->dist_power != 2) return fail(ST_INVALID, "dist_power");
   for (int64_t k = 0; coords && k < (int64_t)n * dim; ++k)
     if (!std::isfinite(coords[k])) return fail(ST_INVALID, "non-finite coordinate");
@@ -1165,7 +1234,8 @@ void vcycle(const Hier &H, int l, const std::vector<double> &f, std::vector<doub
   const Level &L = H.lv[l];
   int n = L.A.nr;
   if (l + 1 == (int)H.lv.size()) {
-    chol_solve(L.chol, n, f, u);
+    if (H.o.coarse_solver == 1) lu_solve(L.chol, n, f, u);
+    else chol_solve(L.chol, n, f, u);
     return;
   }
   u.assign(n, 0.0);
@@ -1253,6 +1323,125 @@ int orc_solve(const void *h, const double *b, double *x, int32_t *iters, double 
   *relres = std::sqrt(rr / g0);
   std::memcpy(x, xv.data(), sizeof(double) * n);
   return status;
+}
+
+// Restarted GMRES(m) with the V-cycle as a right preconditioner, in the flexible form that
+// keeps the preconditioned vectors Z (so the update is x += Z y).  The paper solves its
+// nonsymmetric wind-turbine pressure systems with GMRES preconditioned by the SA hierarchy
+// (Sec. 3.4); it does not fix the GMRES variant, so this follows Saad's textbook algorithm:
+//  * x0 = 0, r = b, stop when the least-squares residual |g_{j+1}| <= rtol ||b||;
+//  * Arnoldi with classical Gram-Schmidt applied twice (h = V^T w, w -= V h, again, h += h'),
+//    each inner product the canonical dot, each element of w -= V h updated with the terms in
+//    ascending basis order;
+//  * Givens rotations c = a/rho, s = b/rho, rho = sqrt(a*a + b*b) (c = 1, s = 0 when b = 0);
+//  * at a restart the true residual b - A x is formed and tested;
+//  * a zero new basis norm (lucky breakdown) ends the cycle with the exact Krylov solution.
+// Iterations count Arnoldi steps (one V-cycle and one product with A each).
+int orc_solve_gmres(const void *h, const double *b, double *x, int32_t restart, int32_t *iters,
+                    double *relres, double *hist) {
+  const Hier *H = (const Hier *)h;
+  if (!H->valid) return fail(ST_INVALID, "hierarchy left unusable by a failed re-setup");
+  if (restart < 1) return fail(ST_INVALID, "restart must be positive");
+  const orc_options &o = H->o;
+  const Csr &A = H->lv[0].A;
+  const int n = A.nr;
+  const int m = restart;
+  std::vector<double> xv(n, 0.0), r(b, b + n);
+  const double bn = std::sqrt(dot(r, r));
+  *iters = 0;
+  if (hist) hist[0] = bn;
+  if (bn == 0.0) {
+    std::memcpy(x, xv.data(), sizeof(double) * n);
+    *relres = 0.0;
+    return ST_OK;
+  }
+  const double target = o.rtol * bn;
+  std::vector<std::vector<double>> V(m + 1), Z(m);
+  std::vector<double> Hm((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), w, c(m + 1);
+  auto Hij = [&](int i, int j) -> double & { return Hm[(size_t)i * m + j]; };
+  double beta = bn, res = bn;
+  int total = 0;
+  bool converged = false;
+  while (true) {
+    V[0].resize(n);
+    for (int k = 0; k < n; ++k) V[0][k] = r[k] / beta;
+    std::fill(g.begin(), g.end(), 0.0);
+    std::fill(Hm.begin(), Hm.end(), 0.0);
+    g[0] = beta;
+    int kdim = 0;
+    for (int j = 0; j < m && total < o.max_iter; ++j) {
+      vcycle(*H, 0, V[j], Z[j]);
+      spmv(A, Z[j], w);
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int i = 0; i <= j; ++i) c[i] = dot(V[i], w);
+        for (int k = 0; k < n; ++k) {
+          double t = w[k];
+          for (int i = 0; i <= j; ++i) t = t - c[i] * V[i][k];
+          w[k] = t;
+        }
+        for (int i = 0; i <= j; ++i) Hij(i, j) = pass == 0 ? c[i] : Hij(i, j) + c[i];
+      }
+      const double hn = std::sqrt(dot(w, w));
+      Hij(j + 1, j) = hn;
+      if (hn > 0.0) {
+        V[j + 1].resize(n);
+        for (int k = 0; k < n; ++k) V[j + 1][k] = w[k] / hn;
+      }
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
+        Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
+        Hij(i, j) = t;
+      }
+      const double a = Hij(j, j), bb = Hij(j + 1, j);
+      if (bb == 0.0) {
+        cs[j] = 1.0;
+        sn[j] = 0.0;
+      } else {
+        const double rho = std::sqrt(a * a + bb * bb);
+        cs[j] = a / rho;
+        sn[j] = bb / rho;
+      }
+      Hij(j, j) = cs[j] * a + sn[j] * bb;
+      Hij(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++total;
+      kdim = j + 1;
+      res = std::fabs(g[j + 1]);
+      if (hist) hist[total] = res;
+      if (!std::isfinite(res)) return fail(ST_BREAKDOWN, "GMRES residual not finite");
+      if (res <= target || hn == 0.0) {
+        converged = true;
+        break;
+      }
+    }
+    if (kdim == 0) break;
+    // y = H^{-1} g (upper triangular, back substitution with ascending inner sums)
+    for (int i = kdim - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int k = i + 1; k < kdim; ++k) t = t - Hij(i, k) * y[k];
+      if (Hij(i, i) == 0.0) return fail(ST_BREAKDOWN, "singular GMRES least-squares system");
+      y[i] = t / Hij(i, i);
+    }
+    for (int e = 0; e < n; ++e) {
+      double t = xv[e];
+      for (int i = 0; i < kdim; ++i) t = t + y[i] * Z[i][e];
+      xv[e] = t;
+    }
+    if (converged || total >= o.max_iter) break;
+    spmv(A, xv, w);
+    for (int k = 0; k < n; ++k) r[k] = b[k] - w[k];
+    beta = std::sqrt(dot(r, r));
+    res = beta;
+    if (beta <= target) {
+      converged = true;
+      break;
+    }
+  }
+  *iters = total;
+  *relres = res / bn;
+  std::memcpy(x, xv.data(), sizeof(double) * n);
+  return converged ? ST_OK : ST_NOT_CONVERGED;
 }
 
 void orc_destroy(void *h) { delete (Hier *)h; }

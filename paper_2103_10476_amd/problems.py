@@ -164,6 +164,47 @@ def fd7_stretched(n: int = 128, aspect: float = 1000.0, nx: int | None = None,
                              f"fd7_stretched_{nx}x{ny}x{nz}_a{aspect:g}")
 
 
+def cd7_upwind(n: int = 64, aspect: float = 1.0, beta=(1.0, 0.5, 0.25),
+               nx: int | None = None, ny: int | None = None) -> CsrProblem:
+    """3-D convection-diffusion -lap(u) + beta . grad(u), finite volumes on the grid of
+    ``fd7_stretched(n, aspect)`` with first-order upwinding of the constant velocity ``beta``.
+
+    The diffusive couplings are those of ``fd7_stretched``.  A face with flux q = beta . n * area
+    adds q to the diagonal when q > 0 (outflow) and -|q| to the coupling with the neighbour
+    across it when q < 0 (inflow); inflow from an eliminated boundary node is dropped.  The
+    matrix is nonsymmetric with a symmetric pattern, an M-matrix, diagonally dominant.
+    (A synthetic nonsymmetric family standing in for the wind-turbine pressure systems of
+    Sec. 3.4, which are not available.)"""
+    nx = n if nx is None else nx
+    ny = n if ny is None else ny
+    nz = n
+    bx, by, bz = (float(v) for v in beta)
+    h = 1.0 / (nx + 1)
+    hz = graded_spacing(nz, aspect)
+    dz = 0.5 * (hz[:-1] + hz[1:])
+    cxy = dz
+    cdn = (h * h) / hz[:-1]
+    cup = (h * h) / hz[1:]
+    K = np.broadcast_to(np.arange(nz)[:, None, None], (nz, ny, nx))
+    axy = (h * dz)[K]              # area of an x or y face in layer k
+    az = h * h                     # area of a z face
+    qx, qy, qz = bx * axy, by * axy, bz * az
+    # per direction: inflow couplings (to the upstream neighbour) and outflow on the diagonal
+    west = -cxy[K] - np.maximum(qx, 0.0)    # neighbour i-1 is upstream when bx > 0
+    east = -cxy[K] - np.maximum(-qx, 0.0)
+    south = -cxy[K] - np.maximum(qy, 0.0)
+    north = -cxy[K] - np.maximum(-qy, 0.0)
+    down = -cdn[K] - max(qz, 0.0)
+    up = -cup[K] - max(-qz, 0.0)
+    diff = ((((cxy[K] + cxy[K]) + cxy[K]) + cxy[K]) + cdn[K]) + cup[K]
+    conv = (np.abs(qx) + np.abs(qy)) + abs(qz)   # outflow through the downstream faces
+    diag = diff + conv
+    offs = [(0, 0, -1), (0, -1, 0), (-1, 0, 0), (0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    coeffs = [down, south, west, diag, east, north, up]
+    return _csr_from_offsets((nx, ny, nz), offs, coeffs,
+                             f"cd7_upwind_{nx}x{ny}x{nz}_a{aspect:g}_b{bx:g},{by:g},{bz:g}")
+
+
 def q1_element_matrix(hx, hy, hz):
     """Trilinear hex element stiffness for -div(grad u) on an hx*hy*hz brick (kappa = 1).
 
