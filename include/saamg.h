@@ -41,7 +41,8 @@ typedef enum {
   SA_ERR_NONPOSITIVE_DIAG = -3, /* zero filtered diagonal (plain SA) or A_ii <= 0         */
   SA_ERR_NEGATIVE_EIGENVALUE = -4, /* eigenvalue estimate <= 0 or not finite (Sec. 3.1)   */
   SA_ERR_COARSEN_STALLED = -5,     /* an aggregation did not reduce the size              */
-  SA_ERR_COARSE_FACTOR = -6,       /* coarsest Cholesky pivot <= 0 or coarsest too large  */
+  SA_ERR_COARSE_FACTOR = -6,       /* coarsest pivot <= 0 (Cholesky) or 0 (LU), coarsest
+                                      too large, or nonsymmetric under Cholesky            */
   SA_ERR_OOM = -7,                 /* device allocation failed / over the memory budget   */
   SA_ERR_HIP = -8,                 /* a HIP runtime call failed                           */
   SA_ERR_BREAKDOWN = -9            /* CG breakdown: p'Ap <= 0 or r'z <= 0                 */
@@ -59,6 +60,7 @@ enum { SA_AGG_NATURAL = 0, SA_AGG_HASHED = 1 };
 enum { SA_CHEBYSHEV = 0, SA_JACOBI = 1 };
 enum { SA_FP64 = 0, SA_FP32_VCYCLE = 1 };
 enum { SA_BETA_FR = 0, SA_BETA_PR = 1 };
+enum { SA_COARSE_CHOLESKY = 0, SA_COARSE_LU = 1 };
 
 /* Options.  struct_size must be sizeof(sa_options); sa_default_options fills the defaults
  * given in brackets (the paper's settings where it states them). */
@@ -83,6 +85,9 @@ typedef struct {
   int32_t max_iter;       /* CG iteration cap [500]                                         */
   int32_t pcg_beta;       /* SA_BETA_FR | SA_BETA_PR (flexible) [FR; PR in FP32 mode]       */
   int32_t dist_power;     /* sa_setup_coords weight 1/distance^p, p = 1 or 2, Sec. 3.1 [1]  */
+  int32_t coarse_solver;  /* SA_COARSE_CHOLESKY (symmetric coarsest operator; a nonsymmetric
+                             one is SA_ERR_COARSE_FACTOR) | SA_COARSE_LU (no pivoting; for
+                             nonsymmetric matrices solved with GMRES, Sec. 3.4) [Cholesky]     */
 } sa_options;
 
 typedef struct {
@@ -177,6 +182,22 @@ sa_status sa_resetup(sa_hierarchy *h, const double *val, const double *nullspace
  * NULL.  Returns SA_OK, SA_NOT_CONVERGED (last iterate written) or an error. */
 sa_status sa_solve(sa_hierarchy *h, const double *b, double *x, sa_location loc,
                    int32_t *iterations, double *rel_residual);
+
+/* Solves A x = b with restarted flexible GMRES(restart) preconditioned on the right by one
+ * V-cycle per iteration: the paper's solver for its nonsymmetric wind-turbine systems
+ * (Sec. 3.4).  For a nonsymmetric A, set up with coarse_solver = SA_COARSE_LU.
+ *  - x0 = 0; Arnoldi by classical Gram-Schmidt applied twice; Givens rotations; the flexible
+ *    form keeps the preconditioned vectors, so an FP32 V-cycle is a valid preconditioner.
+ *  - Stops when the least-squares residual norm is <= rtol ||b||; at each restart the true
+ *    residual b - A x is formed and tested; max_iter bounds the Arnoldi steps.
+ *  - restart: 1..1024.  Device scratch of (2 restart + 1) n doubles is taken from the
+ *    library's cache for the call.
+ *  - iterations (Arnoldi steps) and rel_residual (the last residual norm over ||b||) may be
+ *    NULL.
+ * Returns SA_OK, SA_NOT_CONVERGED (last iterate written), SA_ERR_BREAKDOWN (non-finite
+ * residual or a singular least-squares system; x unspecified) or another error. */
+sa_status sa_solve_gmres(sa_hierarchy *h, const double *b, double *x, sa_location loc,
+                         int32_t restart, int32_t *iterations, double *rel_residual);
 
 /* Solves count systems A_k x_k = b_k, each on its own hierarchy hs[k], in lockstep: each CG
  * iteration of every still-running system is advanced by grouped launches (one launch per

@@ -2,9 +2,11 @@
 // a level left without strong connections): blocked dense Cholesky A_L = L L^T with the
 // trailing updates on the FP64 matrix cores, L^{-1} by blocks (the off-diagonal blocks on
 // the matrix cores), and A_L^{-1} = L^{-T} L^{-1} on the matrix cores (v_mfma_f64_16x16x4f64).
+// Nonsymmetric operators (GMRES, Sec. 3.4) take a blocked LU without pivoting instead,
+// A_L = L U, and A_L^{-1} = U^{-1} L^{-1} = W^T L^{-1} with W = (U^T)^{-1}.
 // The V-cycle then applies A_L^{-1} as a dense GEMV.  The factor's rounding order differs
-// from a sequential Cholesky, so this is the one setup result that matches a CPU reference
-// to rounding (~1e-16 relative) rather than bit for bit.
+// from a sequential factorization, so this is the one setup result that matches a CPU
+// reference to rounding (~1e-16 relative) rather than bit for bit.
 #include "kernels.hpp"
 
 namespace sa {
@@ -159,14 +161,15 @@ __device__ __forceinline__ void mfma_64(const double (*As)[kNB + 1], const doubl
   }
 }
 
-__global__ __launch_bounds__(256) void k_trtri_diag(int32_t ld, const double *L, double *Li) {
+__global__ __launch_bounds__(256) void k_trtri_diag(int32_t ld, const double *L, double *Li,
+                                                    bool unit) {
   __shared__ double l[kNB][kNB + 1];
   __shared__ double x[kNB][kNB + 1];
   const int tid = threadIdx.x;
   const int64_t k0 = (int64_t)blockIdx.x * kNB;
   for (int q = tid; q < kNB * kNB; q += 256) {
     const int i = q / kNB, j = q % kNB;
-    l[i][j] = (j <= i) ? L[(k0 + i) * ld + k0 + j] : 0.0;
+    l[i][j] = (j < i || (j == i && !unit)) ? L[(k0 + i) * ld + k0 + j] : (j == i ? 1.0 : 0.0);
     x[i][j] = 0.0;
   }
   __syncthreads();
@@ -230,20 +233,21 @@ __global__ __launch_bounds__(256) void k_trinv_step(int32_t ld, int32_t d, const
       Li[(r0 + 16 * w + 4 * v + lk) * ld + c0 + 16 * ct + lr] = -out[ct][v];
 }
 
-// C = Li^T Li on 16x16 tiles, one wavefront per tile, K in steps of 4.  Operand layout of
-// v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and B[l/16][l%16]; it receives
-// D[4v + l/16][l%16] in result register v = 0..3 (checked against a dense inverse on the
-// GPU).  Li is zero-padded to ld (a multiple of 16).
-__global__ __launch_bounds__(64) void k_gram_mfma(int32_t n, int32_t ld, const double *Li,
-                                                  double *C) {
+// C = X^T Y on 16x16 tiles, one wavefront per tile, K in steps of 4 (Cholesky: X = Y = L^{-1};
+// LU: X = (U^T)^{-1}, Y = L^{-1}).  Operand layout of v_mfma_f64_16x16x4f64: lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; it receives D[4v + l/16][l%16] in result register
+// v = 0..3 (checked against a dense inverse on the GPU).  X and Y are zero-padded to ld (a
+// multiple of 16).
+__global__ __launch_bounds__(64) void k_gram_mfma(int32_t n, int32_t ld, const double *X,
+                                                  const double *Y, double *C) {
   const int lane = threadIdx.x;
   const int32_t i = blockIdx.x * 16 + (lane & 15);
   const int32_t j = blockIdx.y * 16 + (lane & 15);
   const int32_t kk = lane >> 4;
   v4d acc = {0.0, 0.0, 0.0, 0.0};
   for (int32_t k0 = 0; k0 < ld; k0 += 4) {
-    const double a = Li[(int64_t)(k0 + kk) * ld + i];  // A[i][k] = Li[k][i]
-    const double b = Li[(int64_t)(k0 + kk) * ld + j];  // B[k][j] = Li[k][j]
+    const double a = X[(int64_t)(k0 + kk) * ld + i];  // A[i][k] = X[k][i]
+    const double b = Y[(int64_t)(k0 + kk) * ld + j];  // B[k][j] = Y[k][j]
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
   }
   const int32_t col = blockIdx.y * 16 + (lane & 15);
@@ -254,7 +258,181 @@ __global__ __launch_bounds__(64) void k_gram_mfma(int32_t n, int32_t ld, const d
   }
 }
 
-void coarse_inverse(const Csr &A, double *Ainv, int32_t *err, hipStream_t s) {
+// ---- blocked right-looking LU without pivoting, 64 x 64 blocks --------------------------------
+// D holds the whole matrix (identity pad).  Step kb factors the diagonal block (unit L below,
+// U on and above), solves the row panel U12 = L11^{-1} A12 and the column panel
+// L21 = A21 U11^{-1}, and updates the whole trailing matrix A22 -= L21 U12 on the matrix
+// cores.  err bit 64 on a zero or non-finite pivot.
+__global__ __launch_bounds__(256) void k_getrf_diag(int32_t ld, int32_t k0, double *D,
+                                                    int32_t *err) {
+  __shared__ double a[kNB][kNB + 1];
+  const int tid = threadIdx.x;
+  for (int q = tid; q < kNB * kNB; q += 256) {
+    const int i = q / kNB, j = q % kNB;
+    a[i][j] = D[(int64_t)(k0 + i) * ld + k0 + j];
+  }
+  __syncthreads();
+  for (int j = 0; j < kNB; ++j) {
+    const double piv = a[j][j];
+    if (tid == 0 && (!(piv != 0.0) || !isfinite(piv))) atomicOr(err, 64);
+    for (int i = j + 1 + tid; i < kNB; i += 256) a[i][j] /= piv;
+    __syncthreads();
+    for (int q = tid; q < kNB * kNB; q += 256) {
+      const int i = q / kNB, k = q % kNB;
+      if (i > j && k > j) a[i][k] -= a[i][j] * a[j][k];
+    }
+    __syncthreads();
+  }
+  for (int q = tid; q < kNB * kNB; q += 256) {
+    const int i = q / kNB, j = q % kNB;
+    D[(int64_t)(k0 + i) * ld + k0 + j] = a[i][j];
+  }
+}
+
+// Row panel right of the diagonal block: column c of U12 solves L11 x = a by forward
+// substitution with the unit diagonal (one thread per column, the 64 unknowns in registers).
+__global__ __launch_bounds__(256) void k_trsm_row_panel(int32_t ld, int32_t k0, double *D) {
+  __shared__ double lk[kNB][kNB + 1];
+  const int tid = threadIdx.x;
+  for (int q = tid; q < kNB * kNB; q += 256) {
+    const int i = q / kNB, j = q % kNB;
+    lk[i][j] = (j < i) ? D[(int64_t)(k0 + i) * ld + k0 + j] : 0.0;
+  }
+  __syncthreads();
+  const int64_t c = (int64_t)k0 + kNB + (int64_t)blockIdx.x * 256 + tid;
+  if (c >= ld) return;
+  double x[kNB];
+#pragma unroll
+  for (int j = 0; j < kNB; ++j) x[j] = D[((int64_t)k0 + j) * ld + c];
+#pragma unroll
+  for (int j = 0; j < kNB; ++j) {
+    double t = x[j];
+#pragma unroll
+    for (int m = 0; m < j; ++m) t -= lk[j][m] * x[m];
+    x[j] = t;
+  }
+#pragma unroll
+  for (int j = 0; j < kNB; ++j) D[((int64_t)k0 + j) * ld + c] = x[j];
+}
+
+// Column panel below the diagonal block: row i of L21 solves x U11 = a (one thread per row).
+__global__ __launch_bounds__(256) void k_trsm_col_panel(int32_t ld, int32_t k0, double *D) {
+  __shared__ double uk[kNB][kNB + 1];
+  const int tid = threadIdx.x;
+  for (int q = tid; q < kNB * kNB; q += 256) {
+    const int i = q / kNB, j = q % kNB;
+    uk[i][j] = (j >= i) ? D[(int64_t)(k0 + i) * ld + k0 + j] : 0.0;
+  }
+  __syncthreads();
+  const int64_t i = (int64_t)k0 + kNB + (int64_t)blockIdx.x * 256 + tid;
+  if (i >= ld) return;
+  double *row = D + i * ld + k0;
+  double x[kNB];
+#pragma unroll
+  for (int j = 0; j < kNB; ++j) x[j] = row[j];
+#pragma unroll
+  for (int j = 0; j < kNB; ++j) {
+    double t = x[j];
+#pragma unroll
+    for (int m = 0; m < j; ++m) t -= x[m] * uk[m][j];
+    x[j] = t / uk[j][j];
+  }
+#pragma unroll
+  for (int j = 0; j < kNB; ++j) row[j] = x[j];
+}
+
+// Trailing update after step kb: D[ib][jb] -= L[ib][kb] U[kb][jb] for every block pair
+// kb < ib, jb < nbk (workgroup t: ib = kb+1 + t/m, jb = kb+1 + t%m, m = nbk-kb-1).
+__global__ __launch_bounds__(256) void k_gemm_update(int32_t ld, int32_t kb, int32_t nbk,
+                                                     double *D) {
+  __shared__ double As[kNB][kNB + 1];
+  __shared__ double Bs[kNB][kNB + 1];
+  const int32_t m = nbk - kb - 1;
+  const int32_t ib = kb + 1 + (int32_t)(blockIdx.x / m), jb = kb + 1 + (int32_t)(blockIdx.x % m);
+  const int64_t r0 = (int64_t)ib * kNB, c0 = (int64_t)jb * kNB, k0 = (int64_t)kb * kNB;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < kNB * kNB; q += 256) {
+    const int r = q / kNB, k = q % kNB;
+    As[r][k] = D[(r0 + r) * ld + k0 + k];  // L21 block (row r, column k)
+    Bs[r][k] = D[(k0 + r) * ld + c0 + k];  // U12 block (row r, column k)
+  }
+  __syncthreads();
+  v4d acc[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+  mfma_64(As, Bs, acc);
+  const int w = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      D[(r0 + 16 * w + 4 * v + lk) * ld + c0 + 16 * ct + lr] -= acc[ct][v];
+}
+
+// Lower forms of the two factors: Lb = unit lower part of D, Ut = U^T (lower).
+__global__ void k_split_lu(int32_t ld, const double *D, double *Lb, double *Ut) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)ld * ld) return;
+  const int64_t i = q / ld, j = q % ld;
+  Lb[q] = (j < i) ? D[q] : (j == i ? 1.0 : 0.0);
+  Ut[q] = (j <= i) ? D[j * ld + i] : 0.0;
+}
+
+// Symmetry of the coarsest operator before a Cholesky solve (which reads only the lower
+// triangle): mx[0] = max |a_ij|, mx[1] = max |a_ij - a_ji| as the bit patterns of
+// non-negative doubles (ordered like the values); err bit 256 when mx[1] > 1e-10 mx[0].
+__global__ void k_sym_max(int32_t ld, const double *D, unsigned long long *mx) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)ld * ld) return;
+  const int64_t i = q / ld, j = q % ld;
+  const double a = fabs(D[q]), d = fabs(D[q] - D[j * ld + i]);
+  if (a > 0.0) atomicMax(&mx[0], (unsigned long long)__double_as_longlong(a));
+  if (d > 0.0) atomicMax(&mx[1], (unsigned long long)__double_as_longlong(d));
+}
+__global__ void k_sym_flag(const unsigned long long *mx, int32_t *err) {
+  const double amax = __longlong_as_double((long long)mx[0]);
+  const double asym = __longlong_as_double((long long)mx[1]);
+  if (!(asym <= 1e-10 * amax)) atomicOr(err, 256);
+}
+
+// LU path of coarse_inverse: D (ld x ld, padded) is factored in place; Li (ld x ld) is
+// scratch.  Ainv = W^T L^{-1} with W = (U^T)^{-1}.
+static void lu_inverse(int32_t ld, int32_t nbk, int32_t n, double *D, double *Li, double *Ainv,
+                       int32_t *err, hipStream_t s) {
+  for (int32_t kb = 0; kb < nbk; ++kb) {
+    const int32_t k0 = kb * kNB;
+    k_getrf_diag<<<1, 256, 0, s>>>(ld, k0, D, err);
+    const int32_t rest = ld - k0 - kNB;
+    if (rest > 0) {
+      k_trsm_row_panel<<<(unsigned)ceil_div(rest, 256), 256, 0, s>>>(ld, k0, D);
+      k_trsm_col_panel<<<(unsigned)ceil_div(rest, 256), 256, 0, s>>>(ld, k0, D);
+      const int64_t m = nbk - kb - 1;
+      k_gemm_update<<<(unsigned)(m * m), 256, 0, s>>>(ld, kb, nbk, D);
+    }
+    SA_LAUNCH_CHECK();
+  }
+  const int64_t cnt = (int64_t)ld * ld;
+  double *Lb = (double *)dev_alloc(sizeof(double) * (size_t)cnt, s);
+  double *Ut = (double *)dev_alloc(sizeof(double) * (size_t)cnt, s);
+  k_split_lu<<<grid_for(cnt), kBlock, 0, s>>>(ld, D, Lb, Ut);
+  SA_LAUNCH_CHECK();
+  // Li = Lb^{-1}; then W = Ut^{-1} into D (the factor is no longer needed)
+  fill_f64(Li, 0.0, cnt, s);
+  k_trtri_diag<<<(unsigned)nbk, 256, 0, s>>>(ld, Lb, Li, true);
+  for (int32_t d = 1; d < nbk; ++d) k_trinv_step<<<(unsigned)(nbk - d), 256, 0, s>>>(ld, d, Lb, Li);
+  fill_f64(D, 0.0, cnt, s);
+  k_trtri_diag<<<(unsigned)nbk, 256, 0, s>>>(ld, Ut, D, false);
+  for (int32_t d = 1; d < nbk; ++d) k_trinv_step<<<(unsigned)(nbk - d), 256, 0, s>>>(ld, d, Ut, D);
+  SA_LAUNCH_CHECK();
+  dim3 g(ld / 16, ld / 16);
+  k_gram_mfma<<<g, 64, 0, s>>>(n, ld, D, Li, Ainv);
+  SA_LAUNCH_CHECK();
+  dev_free(Lb, s);
+  dev_free(Ut, s);
+}
+
+void coarse_inverse(const Csr &A, double *Ainv, int32_t *err, bool lu, hipStream_t s) {
   const int32_t n = A.n;
   if (n <= 0) return;
   const int32_t ld = (int32_t)ceil_div(n, kNB) * kNB;
@@ -270,6 +448,20 @@ void coarse_inverse(const Csr &A, double *Ainv, int32_t *err, hipStream_t s) {
     k_pad_identity<<<grid_for(ld - n), kBlock, 0, s>>>(n, ld, D);
     SA_LAUNCH_CHECK();
   }
+  if (lu) {
+    lu_inverse(ld, nbk, n, D, Li, Ainv, err, s);
+    dev_free(D, s);
+    dev_free(Li, s);
+    return;
+  }
+  {
+    unsigned long long *mx = (unsigned long long *)dev_alloc(2 * sizeof(unsigned long long), s);
+    SA_HIP(hipMemsetAsync(mx, 0, 2 * sizeof(unsigned long long), s));
+    k_sym_max<<<grid_for(cnt), kBlock, 0, s>>>(ld, D, mx);
+    k_sym_flag<<<1, 1, 0, s>>>(mx, err);
+    SA_LAUNCH_CHECK();
+    dev_free(mx, s);
+  }
   for (int32_t kb = 0; kb < nbk; ++kb) {
     const int32_t k0 = kb * kNB;
     k_potrf_diag<<<1, 256, 0, s>>>(ld, k0, D, err);
@@ -281,11 +473,11 @@ void coarse_inverse(const Csr &A, double *Ainv, int32_t *err, hipStream_t s) {
     }
     SA_LAUNCH_CHECK();
   }
-  k_trtri_diag<<<(unsigned)nbk, 256, 0, s>>>(ld, D, Li);
+  k_trtri_diag<<<(unsigned)nbk, 256, 0, s>>>(ld, D, Li, false);
   for (int32_t d = 1; d < nbk; ++d) k_trinv_step<<<(unsigned)(nbk - d), 256, 0, s>>>(ld, d, D, Li);
   SA_LAUNCH_CHECK();
   dim3 g(ld / 16, ld / 16);
-  k_gram_mfma<<<g, 64, 0, s>>>(n, ld, Li, Ainv);
+  k_gram_mfma<<<g, 64, 0, s>>>(n, ld, Li, Li, Ainv);
   SA_LAUNCH_CHECK();
   dev_free(D, s);
   dev_free(Li, s);

@@ -26,8 +26,11 @@ enum ErrBits {
   E_LAMBDA = 16,
   E_DIAG = 32,
   E_CHOL = 64,
-  E_COORD = 128
+  E_COORD = 128,
+  E_ASYM = 256
 };
+
+constexpr int32_t kMaxRestart = 1024;  // GMRES restart length limit
 
 static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
@@ -57,6 +60,8 @@ static void validate_options(const sa_options &o) {
     throw Error(SA_ERR_INVALID_ARG, "precision");
   if (o.variants & ~15u) throw Error(SA_ERR_INVALID_ARG, "unknown variant bits");
   if (o.dist_power != 1 && o.dist_power != 2) throw Error(SA_ERR_INVALID_ARG, "dist_power");
+  if (o.coarse_solver != SA_COARSE_CHOLESKY && o.coarse_solver != SA_COARSE_LU)
+    throw Error(SA_ERR_INVALID_ARG, "coarse_solver");
 }
 
 static void copy_in(void *dst, const void *src, size_t bytes, sa_location loc, hipStream_t s) {
@@ -263,8 +268,12 @@ static void finish_setup(sa_hierarchy *h, bool fresh) {
   if (Lc.A.n > kMaxDense)
     throw Error(SA_ERR_COARSE_FACTOR, "coarsest level too large for the dense solver");
   if (fresh) Lc.Ainv = h->ar.alloc<double>((int64_t)Lc.A.n * Lc.A.n);
-  coarse_inverse(Lc.A, Lc.Ainv, h->err, s);
-  check_err(h, E_CHOL, SA_ERR_COARSE_FACTOR, "coarse Cholesky pivot not positive");
+  coarse_inverse(Lc.A, Lc.Ainv, h->err, o.coarse_solver == SA_COARSE_LU, s);
+  check_err(h, E_ASYM, SA_ERR_COARSE_FACTOR,
+            "coarsest operator not symmetric: use the LU coarse solver");
+  check_err(h, E_CHOL, SA_ERR_COARSE_FACTOR,
+            o.coarse_solver == SA_COARSE_LU ? "coarse LU pivot zero"
+                                            : "coarse Cholesky pivot not positive");
   // FP32 copies of the hierarchy for the FP32 V-cycle
   const bool f32 = o.precision == SA_FP32_VCYCLE;
   for (int l = 0; l < nl; ++l) {
@@ -683,6 +692,109 @@ static sa_status solve_impl(sa_hierarchy *h, const double *b, double *x, sa_loca
   return st;
 }
 
+// Restarted flexible GMRES(m), the V-cycle as right preconditioner (the paper's solver for
+// its nonsymmetric wind-turbine systems, Sec. 3.4).  x0 = 0; Arnoldi by classical
+// Gram-Schmidt applied twice; Givens rotations; stop when the least-squares residual
+// |g_{j+1}| <= rtol ||b||; at a restart the true residual b - A x is formed and tested; a zero
+// new basis norm ends the cycle with the exact Krylov solution.  The flexible form keeps the
+// preconditioned vectors Z and updates x += Z y.  Iterations count Arnoldi steps.
+static sa_status gmres_impl(sa_hierarchy *h, const double *b, double *x, sa_location loc,
+                            int32_t restart, int32_t *iterations, double *relres) {
+  if (!h->valid) throw Error(SA_ERR_INVALID_ARG, "hierarchy left unusable by a failed re-setup");
+  if (restart < 1 || restart > kMaxRestart) throw Error(SA_ERR_INVALID_ARG, "restart not in 1..1024");
+  const hipStream_t s = h->stream;
+  const sa_options &o = h->opt;
+  const int32_t n = h->n;
+  const int32_t m = restart;
+  Arena tmp;
+  tmp.stream = s;
+  double *V = tmp.alloc<double>((int64_t)(m + 1) * n);
+  double *Z = tmp.alloc<double>((int64_t)m * n);
+  double *H = tmp.alloc<double>((int64_t)(m + 1) * m);
+  double *cs = tmp.alloc<double>(m), *sn = tmp.alloc<double>(m);
+  double *g = tmp.alloc<double>(m + 1), *y = tmp.alloc<double>(m), *c = tmp.alloc<double>(m + 1);
+  double *ws = tmp.alloc<double>((int64_t)(m + 1) * dot_ws_size(n));
+  GmresScalars *S = tmp.alloc<GmresScalars>(1);
+  SA_HIP(hipMemsetAsync(S, 0, sizeof(GmresScalars), s));
+  double *r = h->r, *xv = h->x, *bd = h->q;
+  copy_in(bd, b, sizeof(double) * n, loc, s);
+  SA_HIP(hipMemcpyAsync(r, bd, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  fill_f64(xv, 0.0, n, s);
+  dot_f64(r, r, n, &S->nrm2, h->dws, s);
+  gmres_start(S, r, V, n, g, s);  // beta = ||b||, v_0 = b / beta
+  GmresScalars hs;
+  readback(&hs, S, sizeof(GmresScalars), s);
+  const double bn = hs.beta;
+  auto finish = [&]() {
+    SA_HIP(hipMemcpyAsync(x, xv, sizeof(double) * n,
+                          loc == SA_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    SA_HIP(hipStreamSynchronize(s));
+  };
+  if (!std::isfinite(bn)) throw Error(SA_ERR_INVALID_ARG, "non-finite right-hand side");
+  if (bn == 0.0) {
+    finish();
+    if (iterations) *iterations = 0;
+    if (relres) *relres = 0.0;
+    return SA_OK;
+  }
+  const double target = o.rtol * bn;
+  SpmvArgs<double> A = spmv_args<double>(h->lv[0].A, h->lv[0].A.val, nullptr);
+  double res = bn;
+  int32_t total = 0;
+  bool converged = false;
+  for (;;) {
+    int32_t kdim = 0;
+    for (int32_t j = 0; j < m && total < o.max_iter; ++j) {
+      double *vj = V + (int64_t)j * n, *zj = Z + (int64_t)j * n, *w = V + (int64_t)(j + 1) * n;
+      precondition(h, vj, zj);
+      A.x = zj;
+      prof_begin(h, 0);
+      spmv_store<double>(A, w, s);
+      prof_end(h, 0, 2, 8);
+      for (int32_t pass = 0; pass < 2; ++pass) {
+        multi_dot_f64(V, n, j + 1, w, n, c, ws, s);
+        multi_axpy_f64(V, n, j + 1, c, w, n, false, s);
+        gmres_accum(H, m, j, c, pass, s);
+      }
+      dot_f64(w, w, n, &S->hn2, h->dws, s);
+      gmres_normalize(S, H, m, j, w, w, n, s);
+      gmres_givens(H, m, j, cs, sn, g, S, s);
+      readback(&hs, S, sizeof(GmresScalars), s);
+      prof_collect(h);
+      ++total;
+      kdim = j + 1;
+      res = hs.res;
+      if (!std::isfinite(res)) return SA_ERR_BREAKDOWN;
+      if (res <= target || hs.hn == 0.0) {
+        converged = true;
+        break;
+      }
+    }
+    if (kdim == 0) break;
+    gmres_backsolve(H, m, kdim, g, y, S, s);
+    multi_axpy_f64(Z, n, kdim, y, xv, n, true, s);
+    readback(&hs, S, sizeof(GmresScalars), s);
+    if (hs.err) return SA_ERR_BREAKDOWN;
+    if (converged || total >= o.max_iter) break;
+    // restart from the true residual
+    A.x = xv;
+    spmv_resid<double>(A, bd, r, s);
+    dot_f64(r, r, n, &S->nrm2, h->dws, s);
+    gmres_start(S, r, V, n, g, s);
+    readback(&hs, S, sizeof(GmresScalars), s);
+    res = hs.beta;
+    if (res <= target) {
+      converged = true;
+      break;
+    }
+  }
+  finish();
+  prof_collect(h);
+  if (iterations) *iterations = total;
+  if (relres) *relres = res / bn;
+  return converged ? SA_OK : SA_NOT_CONVERGED;
+}
+
 template <class F>
 static sa_status guarded(F &&fn) {
   try {
@@ -741,6 +853,7 @@ void sa_default_options(sa_options *o) {
   o->max_iter = 500;
   o->pcg_beta = -1;
   o->dist_power = 1;
+  o->coarse_solver = SA_COARSE_CHOLESKY;
 }
 
 sa_status sa_setup_coords(const sa_context *ctx, const sa_csr *A, const double *nullspace,
@@ -792,6 +905,19 @@ sa_status sa_solve(sa_hierarchy *h, const double *b, double *x, sa_location loc,
     if (st < 0) {
       (void)hipStreamSynchronize(h->stream);
       g_last_error = "CG breakdown (p'Ap <= 0 or r'z <= 0)";
+    }
+    return st;
+  });
+}
+
+sa_status sa_solve_gmres(sa_hierarchy *h, const double *b, double *x, sa_location loc,
+                         int32_t restart, int32_t *iterations, double *rel_residual) {
+  if (!h || !b || !x) return SA_ERR_INVALID_ARG;
+  return guarded([&]() -> sa_status {
+    sa_status st = gmres_impl(h, b, x, loc, restart, iterations, rel_residual);
+    if (st < 0) {
+      (void)hipStreamSynchronize(h->stream);
+      g_last_error = "GMRES breakdown (non-finite residual or singular least-squares system)";
     }
     return st;
   });

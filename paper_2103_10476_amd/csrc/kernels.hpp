@@ -63,6 +63,41 @@ void cast_f32_to_f64(const float *a, double *b, int64_t n, hipStream_t s);
 // Dense y = M x for the coarsest level (M row-major n x n, float64).
 void gemv_f64(int32_t n, const double *M, const double *x, double *y, hipStream_t s);
 
+// ---- GMRES (solve_kernels.hip) ----------------------------------------------------------
+// Device state of one GMRES cycle with restart length m: the Hessenberg matrix (row-major,
+// (m+1) x m), the rotations, the right-hand side g of the least-squares problem, its
+// solution y, Gram-Schmidt coefficients c and the scalars the host reads after each step.
+struct GmresScalars {
+  double res;  // |g[j+1]| after the step's rotation
+  double hn;   // norm of the new Arnoldi vector
+  double hn2;  // its square (canonical dot)
+  double nrm2; // dot(r, r) of a residual
+  double beta; // its norm
+  int32_t err, pad;
+};
+// c[i] = dot(V_i, w) for i < nv, V_i = V + i * ldv (the canonical dot, each independently);
+// ws holds nv * dot_ws_size(n) doubles.
+void multi_dot_f64(const double *V, int64_t ldv, int32_t nv, const double *w, int64_t n,
+                   double *c, double *ws, hipStream_t s);
+// w[k] = w[k] - c[0] V_0[k] - c[1] V_1[k] - ... (nv terms in ascending order); with add,
+// w[k] = w[k] + c[0] V_0[k] + ... instead.
+void multi_axpy_f64(const double *V, int64_t ldv, int32_t nv, const double *c, double *w,
+                    int64_t n, bool add, hipStream_t s);
+// H[i][j] = c[i] (pass 0) or H[i][j] + c[i] (pass 1), i <= j.
+void gmres_accum(double *H, int32_t m, int32_t j, const double *c, int32_t pass, hipStream_t s);
+// hn = sqrt(hn2), H[j+1][j] = hn; v = w / hn when hn > 0 (elementwise, in place allowed).
+void gmres_normalize(GmresScalars *S, double *H, int32_t m, int32_t j, const double *w,
+                     double *v, int64_t n, hipStream_t s);
+// Rotations of column j and the new one; g updated, S->res = |g[j+1]|.
+void gmres_givens(double *H, int32_t m, int32_t j, double *cs, double *sn, double *g,
+                  GmresScalars *S, hipStream_t s);
+// y = H[0:k,0:k]^{-1} g (back substitution); err 1 on a zero diagonal entry.
+void gmres_backsolve(const double *H, int32_t m, int32_t k, const double *g, double *y,
+                     GmresScalars *S, hipStream_t s);
+// beta = sqrt(nrm2); v = r / beta; g[0] = beta.
+void gmres_start(GmresScalars *S, const double *r, double *v, int64_t n, double *g,
+                 hipStream_t s);
+
 // PCG device scalars.
 struct PcgScalars {
   double rho, pq, alpha, rr, rho1, beta, rw, spare;
@@ -149,6 +184,8 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s);
 
 // ---------------- coarsest level (coarse.hip) ------------------------------------------
 // Dense inverse of the coarsest operator via Cholesky (err bit 64 on a pivot <= 0).
-void coarse_inverse(const Csr &A, double *Ainv, int32_t *err, hipStream_t s);
+// lu: LU without pivoting (any operator); otherwise Cholesky, with err bit 256 when the
+// operator is not symmetric to 1e-10 relative.  err bit 64: a pivot <= 0 (Cholesky) or zero.
+void coarse_inverse(const Csr &A, double *Ainv, int32_t *err, bool lu, hipStream_t s);
 
 }  // namespace sa

@@ -38,6 +38,7 @@ class Options:
     max_iter: int = 500
     pcg_beta: str = "auto"
     dist_power: int = 1
+    coarse_solver: str = "cholesky"
 
     def to_c(self) -> _lib.SaOptions:
         o = _lib.SaOptions()
@@ -64,6 +65,7 @@ class Options:
         o.max_iter = self.max_iter
         o.pcg_beta = {"auto": -1, "fr": 0, "pr": 1}[self.pcg_beta]
         o.dist_power = self.dist_power
+        o.coarse_solver = 1 if self.coarse_solver in ("lu", 1) else 0
         return o
 
     def as_dict(self) -> dict:
@@ -157,6 +159,21 @@ class Hierarchy:
         code = _lib.lib().sa_solve(self._h, C.c_void_p(db.data_ptr()), C.c_void_p(x.data_ptr()),
                                    _lib.SA_DEVICE, C.byref(it), C.byref(rr))
         _lib.check(code, "sa_solve")
+        return x, it.value, rr.value, _lib.STATUS_NAMES[code]
+
+    def solve_gmres(self, b, x=None, restart: int = 30):
+        """Restarted flexible GMRES with the V-cycle as right preconditioner
+        (sa_solve_gmres).  Returns (x, iterations, relres, status)."""
+        torch = _torch()
+        db = _dev(b, torch.float64)
+        if x is None:
+            x = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        it = C.c_int32()
+        rr = C.c_double()
+        code = _lib.lib().sa_solve_gmres(self._h, C.c_void_p(db.data_ptr()),
+                                         C.c_void_p(x.data_ptr()), _lib.SA_DEVICE, restart,
+                                         C.byref(it), C.byref(rr))
+        _lib.check(code, "sa_solve_gmres")
         return x, it.value, rr.value, _lib.STATUS_NAMES[code]
 
     def vcycle(self, f):
