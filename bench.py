@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--serving-budget-gib", type=float, default=8.0)
     ap.add_argument("--family-seeds", type=int, default=10,
                     help="perturbed-cube meshes in the mesh-family leg")
+    ap.add_argument("--only-gmres", action="store_true",
+                    help="run only the GMRES leg (nonsymmetric 128^3 cube, GMRES vs CG)")
     ap.add_argument("--only-families", action="store_true",
                     help="run only the mesh-family leg (perturbed and stretched cubes)")
     ap.add_argument("--only-serving", action="store_true",
@@ -113,6 +115,9 @@ def main():
     from paper_2103_10476_amd import problems, solver
 
     torch.cuda.set_device(0)
+    if args.only_gmres:
+        print(json.dumps(gmres_leg(solver, problems)), flush=True)
+        return
     if args.only_families:
         print(json.dumps(families_leg(solver, problems, seeds=args.family_seeds)), flush=True)
         return
@@ -212,6 +217,7 @@ def main():
         result["numeric_resetup"] = resetup_leg(solver, p, drp, dcol, dval, db)
         result["variant_sweep"] = variant_sweep_leg(solver, problems)
         result["mesh_families"] = families_leg(solver, problems, seeds=args.family_seeds)
+        result["gmres"] = gmres_leg(solver, problems)
         result["serving"] = serving_leg(solver, problems, args)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(p, b)
@@ -568,6 +574,67 @@ def families_leg(solver, problems, seeds=10, ne=60):
                 f"{k} {v['plain_minus_it']}"
                 for k, v in sc[f"weight_1/d^{pw}"]["vs_plain"].items()))
     out["stretched_cube"] = sc
+    return out
+
+
+def gmres_leg(solver, problems, reps=3):
+    """Restarted GMRES(30) with the V-cycle as right preconditioner (the paper's solver for
+    nonsymmetric systems, Sec. 3.4) on a 128^3 graded upwind convection-diffusion cube
+    (nonsymmetric, OffLmp + 1Norm, LU coarse solver), at the wind runs' tolerance 1e-5 and at
+    1e-8, in FP64 and with the FP32 V-cycle; and GMRES next to CG on the symmetric 128^3
+    benchmark cube.  p50 of setup and solve over ``reps`` runs, inputs resident in HBM."""
+    import torch
+    out = {}
+    p = problems.cd7_upwind(128, 1000.0, (1.0, 0.5, 0.25))
+    b = problems.random_rhs(p.n, 2)
+    drp, dcol, dval = (torch.from_numpy(a).cuda() for a in (p.rp, p.col, p.val))
+    db = torch.from_numpy(b).cuda()
+    x = torch.empty_like(db)
+    for prec in ("fp64", "fp32"):
+        for rtol in (1e-5, 1e-8):
+            o = solver.Options(variants=("offlmp", "1norm"), coarse_solver="lu", rtol=rtol,
+                               precision=prec)
+            se, so = [], []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                h = solver.Hierarchy(p.n, drp, dcol, dval, options=o)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                _, it, rr, st = h.solve_gmres(db, x, restart=30)
+                torch.cuda.synchronize()
+                se.append(t1 - t0)
+                so.append(time.perf_counter() - t1)
+                h.close()
+            out[f"cd7_128_nonsym_{prec}_rtol{rtol:g}"] = {
+                "steps": it, "status": st, "rel_residual": rr,
+                "setup_s_p50": round(pct(se, 50), 5), "solve_s_p50": round(pct(so, 50), 5),
+                "solve_ms_per_step": round(pct(so, 50) / max(it, 1) * 1e3, 3)}
+    log("[bench] gmres cd7 128^3: " + ", ".join(
+        f"{k} {v['steps']} steps {v['solve_s_p50'] * 1e3:.1f} ms" for k, v in out.items()))
+    del drp, dcol, dval, db, x
+    q = problems.workload("fd7_128_a1000")
+    bq = torch.from_numpy(problems.random_rhs(q.n, 2)).cuda()
+    h = solver.Hierarchy(q.n, torch.from_numpy(q.rp).cuda(), torch.from_numpy(q.col).cuda(),
+                         torch.from_numpy(q.val).cuda(), options=solver.Options(rtol=1e-8))
+    xq = torch.empty_like(bq)
+    cg, gm = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, itc, _, _ = h.solve(bq, xq)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, itg, _, _ = h.solve_gmres(bq, xq, restart=30)
+        torch.cuda.synchronize()
+        cg.append(t1 - t0)
+        gm.append(time.perf_counter() - t1)
+    h.close()
+    out["fd7_128_sym_cg_vs_gmres"] = {"cg_iterations": itc, "cg_solve_s_p50": round(pct(cg, 50), 5),
+                                      "gmres_steps": itg,
+                                      "gmres_solve_s_p50": round(pct(gm, 50), 5)}
+    log(f"[bench] fd7 128^3: CG {itc} its {pct(cg, 50) * 1e3:.1f} ms, GMRES(30) {itg} steps "
+        f"{pct(gm, 50) * 1e3:.1f} ms")
     return out
 
 
