@@ -54,6 +54,13 @@ int orc_setup(int32_t n, const int32_t *rp, const int32_t *col, const double *va
 int orc_setup_coords(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
                      const double *nullspace, const double *coords, int32_t dim,
                      const orc_options *o, void **h);
+/* systems SA: bs dofs per node (node-major), nullspace B (n x k, row-major, k <= 16), QR
+ * tentative prolongator per aggregate; coords per node (n/bs x dim) or NULL */
+int orc_setup_system(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                     int32_t bs, const double *B, int32_t k, const double *coords, int32_t dim,
+                     const orc_options *o, void **h);
+/* s[0..5] = block size, k, nnz(P_t), nodes, nnz(node graph), size of the level's nullspace */
+int orc_level_block(const void *h, int lvl, int64_t *s);
 /* numeric re-setup: new values (nnz of the setup's matrix, its CSR order), same symbolic
  * decisions (strength labels, Sprsfy drops, aggregates, patterns) */
 int orc_resetup(void *h, const double *val, const double *nullspace /* NULL = ones */);
@@ -65,7 +72,8 @@ int orc_level_scalars(const void *h, int lvl, double *scal);
 /* what: 0 A.rp 1 A.col 2 A.val 3 mask(u8) 4 agg(i32) 5 is_root(u8) 6 Abar.rp 7 Abar.col
  *       8 Abar.val 9 invD(f64) 10 P.rp 11 P.col 12 P.val 13 R.rp 14 R.col 15 R.val
  *       16 smoother invD(f64) 17 setup matrix (scaled) .val 18 coordinates (n*dim f64,
- *       distance strength only)                                                          */
+ *       distance strength only)  systems: 19 P_t.rp 20 P_t.col 21 P_t.val 22 nullspace
+ *       (n x k) 23 node labels (u8) 24 node graph rp 25 node graph col                   */
 int orc_export(const void *h, int lvl, int what, void *buf);
 int orc_vcycle(const void *h, const double *f, double *u);
 int orc_solve(const void *h, const double *b, double *x, int32_t *iters, double *relres,

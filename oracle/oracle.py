@@ -47,6 +47,9 @@ def _setup_prototypes(L):
     L.orc_setup.argtypes = [C.c_int32, P, P, P, P, C.POINTER(OrcOptions), C.POINTER(C.c_void_p)]
     L.orc_setup_coords.argtypes = [C.c_int32, P, P, P, P, P, C.c_int32,
                                    C.POINTER(OrcOptions), C.POINTER(C.c_void_p)]
+    L.orc_setup_system.argtypes = [C.c_int32, P, P, P, C.c_int32, P, C.c_int32, P, C.c_int32,
+                                   C.POINTER(OrcOptions), C.POINTER(C.c_void_p)]
+    L.orc_level_block.argtypes = [P, C.c_int, P]
     L.orc_resetup.argtypes = [P, P, P]
     L.orc_resetup.restype = C.c_int
     L.orc_num_levels.argtypes = [P]
@@ -142,20 +145,32 @@ class Level:
 class OracleHierarchy:
     """Runs the oracle setup; every level's arrays are exported into numpy."""
 
-    def __init__(self, n, rp, col, val, nullspace=None, coords=None, **opts):
-        """``coords`` (n x dim, dim 1..3) selects the distance-Laplacian strength."""
+    def __init__(self, n, rp, col, val, nullspace=None, coords=None, block_size=None, **opts):
+        """``coords`` (points x dim, dim 1..3) selects the distance-Laplacian strength.
+        ``block_size`` selects systems SA: ``nullspace`` is then an n x k matrix (node-major
+        dofs) and coordinates are per node."""
         self.opts = make_options(**opts)
         self._keep = (_i32(rp), _i32(col), _f64(val))
-        B = None if nullspace is None else _f64(nullspace)
+        self.system = block_size is not None
+        npts = n // block_size if self.system else n
         X, self.dim = None, 0
         if coords is not None:
-            X = _f64(coords).reshape(n, -1)
+            X = _f64(coords).reshape(npts, -1)
             self.dim = X.shape[1]
         h = C.c_void_p()
-        _check(lib().orc_setup_coords(n, _p(self._keep[0]), _p(self._keep[1]),
-                                      _p(self._keep[2]), None if B is None else _p(B),
-                                      None if X is None else _p(X), self.dim,
-                                      C.byref(self.opts), C.byref(h)))
+        if self.system:
+            Bm = _f64(nullspace).reshape(n, -1)
+            self.k = Bm.shape[1]
+            _check(lib().orc_setup_system(n, _p(self._keep[0]), _p(self._keep[1]),
+                                          _p(self._keep[2]), block_size, _p(Bm), self.k,
+                                          None if X is None else _p(X), self.dim,
+                                          C.byref(self.opts), C.byref(h)))
+        else:
+            B = None if nullspace is None else _f64(nullspace)
+            _check(lib().orc_setup_coords(n, _p(self._keep[0]), _p(self._keep[1]),
+                                          _p(self._keep[2]), None if B is None else _p(B),
+                                          None if X is None else _p(X), self.dim,
+                                          C.byref(self.opts), C.byref(h)))
         self.h = h
         self.levels = [self._export(l) for l in range(lib().orc_num_levels(h))]
 
@@ -177,19 +192,33 @@ class OracleHierarchy:
             return a
 
         lv.A = (ex(0, n + 1, np.int32), ex(1, nnz, np.int32), ex(2, nnz, np.float64))
+        npts = n
+        lv.bs = 1
+        ncd = nc  # coarse unknowns: aggregates, times k for systems
+        if self.system:
+            bl = np.zeros(6, dtype=np.int64)
+            _check(L.orc_level_block(self.h, l, _p(bl)))
+            lv.bs, k, nPt, nodes, nG, nB = (int(v) for v in bl)
+            npts = n // lv.bs
+            ncd = nc * k
+            lv.B = ex(22, nB, np.float64).reshape(n, k)
+            if not last:
+                lv.Pt = (ex(19, n + 1, np.int32), ex(20, nPt, np.int32), ex(21, nPt, np.float64))
+                lv.nmask = ex(23, nG, np.uint8)
+                lv.Gn = (ex(24, nodes + 1, np.int32), ex(25, nG, np.int32))
         if not last:
             lv.mask = ex(3, nnz, np.uint8)
-            lv.agg = ex(4, n, np.int32)
-            lv.is_root = ex(5, n, np.uint8)
+            lv.agg = ex(4, npts, np.int32)
+            lv.is_root = ex(5, npts, np.uint8)
             lv.Abar = (ex(6, n + 1, np.int32), ex(7, nab, np.int32), ex(8, nab, np.float64))
             lv.invD = ex(9, n, np.float64)
             lv.P = (ex(10, n + 1, np.int32), ex(11, nP, np.int32), ex(12, nP, np.float64))
-            lv.R = (ex(13, nc + 1, np.int32), ex(14, nR, np.int32), ex(15, nR, np.float64))
+            lv.R = (ex(13, ncd + 1, np.int32), ex(14, nR, np.int32), ex(15, nR, np.float64))
             lv.sm_invD = ex(16, n, np.float64)
             lv.As_val = ex(17, nnz, np.float64)
             lv.lam, lv.omega, lv.sm_lam = float(sc[0]), float(sc[1]), float(sc[2])
         if self.dim:
-            lv.coords = ex(18, n * self.dim, np.float64).reshape(n, self.dim)
+            lv.coords = ex(18, npts * self.dim, np.float64).reshape(npts, self.dim)
         return lv
 
     @property

@@ -756,6 +756,14 @@ struct Level {
   std::vector<double> chol;  // coarsest only: dense Cholesky factor (row-major, lower), or
                              // the LU factors (unit L strictly below, U on and above)
   std::vector<double> xyz;   // node coordinates (n x dim) when the distance strength is used
+  // systems SA (block size bs > 1 or a multi-vector nullspace): node-level graph and labels,
+  // the QR tentative prolongator, and this level's nullspace (n x k, row-major)
+  int bs = 1;
+  Csr Gn;
+  std::vector<uint8_t> nmask;
+  Csr Pt;
+  std::vector<double> B;   // this level's nullspace
+  std::vector<double> Bc;  // the next level's (R factors of the aggregates' QR)
 };
 
 struct Hier {
@@ -764,6 +772,7 @@ struct Hier {
   bool scaled = false;
   bool valid = true;  // false after a failed re-setup
   int dim = 0;        // > 0: distance-Laplacian strength from coordinates
+  int k = 0;          // > 0: systems SA with a k-vector nullspace (QR tentative prolongator)
 };
 
 // Dense Cholesky of the coarsest operator, textbook order: L_jj = sqrt(A_jj - sum_k<j L_jk^2),
@@ -870,7 +879,218 @@ void chol_solve(const std::vector<double> &L, int n, const std::vector<double> &
 
 int numeric_level(Hier &H, int l);
 
+// ------------------------------------------------------------------------------------
+// Systems SA.  The paper treats scalar PDEs and names systems as future work; this follows
+// the standard smoothed aggregation for systems (Vanek, Mandel, Brezina) with these
+// readings:
+//  * dofs are numbered node-major (dof = bs * node + component);
+//  * node I is linked to node J when a row of I has an entry in a column of J; the block
+//    strength is F_IJ = sum of a_ij^2 over the bs x bs block (rows ascending, then columns
+//    ascending), and (I,J) is strong iff F_IJ^2 >= theta^4 F_II F_JJ, i.e. ||A_IJ||_F >=
+//    theta sqrt(||A_II||_F ||A_JJ||_F) (the scalar test for bs = 1); with coordinates the
+//    distance Laplacian of the node graph decides instead;
+//  * a dof entry between different nodes takes its node pair's label, entries inside a node
+//    are kept, the diagonal is the diagonal; lumping, the smoothing diagonal and lambda are
+//    the scalar definitions applied to dof rows;
+//  * aggregates are formed on the node graph; aggregate J's dofs (members ascending,
+//    components ascending) take the rows of B, factored B_J = Q_J R_J by Householder
+//    reflections; P_t holds Q_J in columns kJ..kJ+k-1 and the coarse nullspace holds R_J;
+//  * P = P_t - (omega invD_i) (Abar P_t)_i per row, on the pattern of Abar P_t;
+//  * Sprsfy and Cnstrnt (defined for a scalar constant nullspace) are not available.
+// ------------------------------------------------------------------------------------
+Csr node_graph(const Csr &A, int bs) {
+  const int m = A.nr / bs;
+  Csr G;
+  G.nr = G.nc = m;
+  G.rp.assign(m + 1, 0);
+  std::vector<int32_t> cols;
+  for (int I = 0; I < m; ++I) {
+    cols.clear();
+    for (int i = I * bs; i < (I + 1) * bs; ++i)
+      for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) cols.push_back(A.col[e] / bs);
+    std::sort(cols.begin(), cols.end());
+    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+    G.col.insert(G.col.end(), cols.begin(), cols.end());
+    G.rp[I + 1] = (int32_t)G.col.size();
+  }
+  return G;
+}
+
+int32_t slot_of(const Csr &G, int I, int J) {
+  const int32_t *b = &G.col[G.rp[I]], *e = b + (G.rp[I + 1] - G.rp[I]);
+  const int32_t *p = std::lower_bound(b, e, J);
+  return (p != e && *p == J) ? (int32_t)(G.rp[I] + (p - b)) : -1;
+}
+
+void block_strength(const Csr &A, int bs, const Csr &G, double theta,
+                    std::vector<uint8_t> &nmask) {
+  const int m = G.nr;
+  std::vector<double> F(G.col.size(), 0.0);
+  for (int I = 0; I < m; ++I)
+    for (int i = I * bs; i < (I + 1) * bs; ++i)
+      for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+        const int32_t q = slot_of(G, I, A.col[e] / bs);
+        F[q] = F[q] + A.val[e] * A.val[e];
+      }
+  std::vector<double> Fd(m);
+  for (int I = 0; I < m; ++I) Fd[I] = F[slot_of(G, I, I)];
+  const double th4 = (theta * theta) * (theta * theta);
+  nmask.assign(G.col.size(), M_WEAK);
+  for (int I = 0; I < m; ++I)
+    for (int32_t q = G.rp[I]; q < G.rp[I + 1]; ++q) {
+      const int J = G.col[q];
+      if (J == I) {
+        nmask[q] = M_DIAG;
+        continue;
+      }
+      const double p = Fd[I] * Fd[J];
+      nmask[q] = ((p > 0.0) && (F[q] * F[q] >= th4 * p)) ? M_STRONG : M_WEAK;
+    }
+}
+
+void dof_mask(const Csr &A, int bs, const Csr &G, const std::vector<uint8_t> &nmask,
+              std::vector<uint8_t> &mask) {
+  mask.assign(A.nnz(), M_WEAK);
+  for (int i = 0; i < A.nr; ++i)
+    for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+      const int j = A.col[e], I = i / bs, J = j / bs;
+      mask[e] = (i == j) ? M_DIAG : (I == J) ? M_STRONG : nmask[slot_of(G, I, J)];
+    }
+}
+
+// Householder QR of the m x k matrix M (row-major), m >= k: R (k x k, upper) and Q (m x k,
+// orthonormal columns) with R's diagonal made non-negative.  Each reflection: sigma = sum of
+// squares of the column from the diagonal down (ascending), alpha = -sign(a_jj) sqrt(sigma)
+// (+sqrt for a_jj <= 0), v = the column with v_j = a_jj - alpha, H = I - 2 v v^T / (v.v);
+// products v.a ascending; Q = H_0 ... H_{k-1} applied to the first k unit vectors.
+void house_qr(int m, int k, std::vector<double> &M, std::vector<double> &Q,
+              std::vector<double> &R) {
+  std::vector<double> V((size_t)m * k, 0.0), vv(k, 0.0);
+  for (int j = 0; j < k; ++j) {
+    double sigma = 0.0;
+    for (int i = j; i < m; ++i) sigma = sigma + M[(size_t)i * k + j] * M[(size_t)i * k + j];
+    const double nrm = std::sqrt(sigma);
+    if (nrm == 0.0) continue;
+    const double ajj = M[(size_t)j * k + j];
+    const double alpha = ajj > 0.0 ? -nrm : nrm;
+    for (int i = j; i < m; ++i) V[(size_t)i * k + j] = M[(size_t)i * k + j];
+    V[(size_t)j * k + j] = ajj - alpha;
+    double d = 0.0;
+    for (int i = j; i < m; ++i) d = d + V[(size_t)i * k + j] * V[(size_t)i * k + j];
+    vv[j] = d;
+    if (d == 0.0) continue;
+    for (int c = j; c < k; ++c) {
+      double t = 0.0;
+      for (int i = j; i < m; ++i) t = t + V[(size_t)i * k + j] * M[(size_t)i * k + c];
+      const double f = (t + t) / d;
+      for (int i = j; i < m; ++i) M[(size_t)i * k + c] = M[(size_t)i * k + c] - f * V[(size_t)i * k + j];
+    }
+  }
+  R.assign((size_t)k * k, 0.0);
+  for (int r = 0; r < k; ++r)
+    for (int c = r; c < k; ++c) R[(size_t)r * k + c] = M[(size_t)r * k + c];
+  Q.assign((size_t)m * k, 0.0);
+  for (int c = 0; c < k; ++c) Q[(size_t)c * k + c] = 1.0;
+  for (int j = k - 1; j >= 0; --j) {
+    if (vv[j] == 0.0) continue;
+    for (int c = 0; c < k; ++c) {
+      double t = 0.0;
+      for (int i = j; i < m; ++i) t = t + V[(size_t)i * k + j] * Q[(size_t)i * k + c];
+      const double f = (t + t) / vv[j];
+      for (int i = j; i < m; ++i) Q[(size_t)i * k + c] = Q[(size_t)i * k + c] - f * V[(size_t)i * k + j];
+    }
+  }
+  for (int r = 0; r < k; ++r)
+    if (R[(size_t)r * k + r] < 0.0) {
+      for (int c = 0; c < k; ++c) R[(size_t)r * k + c] = -R[(size_t)r * k + c];
+      for (int i = 0; i < m; ++i) Q[(size_t)i * k + r] = -Q[(size_t)i * k + r];
+    }
+}
+
+// P_t and the coarse nullspace of level l from its node aggregates and its nullspace B.
+int tentative_qr(Level &L, int k, std::vector<double> &Bc) {
+  const int bs = L.bs, n = L.A.nr, nc = L.nc;
+  std::vector<std::vector<int>> members(nc);
+  for (int I = 0; I < (int)L.agg.size(); ++I)
+    if (L.agg[I] >= 0) members[L.agg[I]].push_back(I);
+  Csr &P = L.Pt;
+  P.nr = n;
+  P.nc = nc * k;
+  P.rp.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) P.rp[i + 1] = P.rp[i] + (L.agg[i / bs] >= 0 ? k : 0);
+  P.col.assign(P.rp[n], 0);
+  P.val.assign(P.rp[n], 0.0);
+  Bc.assign((size_t)nc * k * k, 0.0);
+  std::vector<double> M, Q, R;
+  for (int J = 0; J < nc; ++J) {
+    const int rows = (int)members[J].size() * bs;
+    if (rows < k) return fail(ST_INVALID, "an aggregate has fewer dofs than nullspace vectors");
+    M.assign((size_t)rows * k, 0.0);
+    for (int q = 0; q < rows; ++q) {
+      const int i = members[J][q / bs] * bs + q % bs;
+      for (int c = 0; c < k; ++c) M[(size_t)q * k + c] = L.B[(size_t)i * k + c];
+    }
+    house_qr(rows, k, M, Q, R);
+    for (int q = 0; q < rows; ++q) {
+      const int i = members[J][q / bs] * bs + q % bs;
+      for (int c = 0; c < k; ++c) {
+        P.col[P.rp[i] + c] = J * k + c;
+        P.val[P.rp[i] + c] = Q[(size_t)q * k + c];
+      }
+    }
+    for (int r = 0; r < k; ++r)
+      for (int c = 0; c < k; ++c) Bc[((size_t)J * k + r) * k + c] = R[(size_t)r * k + c];
+  }
+  return ST_OK;
+}
+
+// P = P_t - (omega invD_i) (Abar P_t)_i on the pattern of Abar P_t.
+Csr smooth_tentative(const Csr &Ab, const Csr &Pt, const std::vector<double> &invD,
+                     double omega) {
+  Csr AP = spgemm(Ab, Pt);
+  Csr P = AP;
+  for (int i = 0; i < AP.nr; ++i) {
+    const double t = omega * invD[i];
+    for (int32_t e = AP.rp[i]; e < AP.rp[i + 1]; ++e) {
+      double pt = 0.0;
+      for (int32_t f = Pt.rp[i]; f < Pt.rp[i + 1]; ++f)
+        if (Pt.col[f] == AP.col[e]) pt = Pt.val[f];
+      P.val[e] = pt - t * AP.val[e];
+    }
+  }
+  return P;
+}
+
+int build_level_system(Hier &H, int l) {
+  Level &L = H.lv[l];
+  const orc_options &o = H.o;
+  L.Gn = node_graph(L.As, L.bs);
+  if (H.dim > 0) {
+    int st = distance_strength(L.Gn, L.xyz, H.dim, o.theta, o.dist_power, L.nmask);
+    if (st) return st;
+  } else {
+    block_strength(L.As, L.bs, L.Gn, o.theta, L.nmask);
+  }
+  dof_mask(L.As, L.bs, L.Gn, L.nmask, L.mask);
+  auto G = strength_graph(L.Gn, L.nmask);
+  L.nnzG = 0;
+  for (auto &g : G) L.nnzG += (int64_t)g.size();
+  int nc = aggregate(G, o.agg_order, o.seed, l, L.agg, L.is_root);
+  if (nc < 0) return nc;
+  L.nc = nc;
+  if (nc == 0) return 1;
+  if ((int64_t)nc * H.k >= L.A.nr) return fail(ST_STALLED, "coarsening stalled");
+  std::vector<double> Bc;
+  int st = tentative_qr(L, H.k, Bc);
+  if (st) return st;
+  st = numeric_level(H, l);
+  if (st) return st;
+  L.Bc.swap(Bc);
+  return ST_OK;
+}
+
 int build_level(Hier &H, int l) {
+  if (H.k > 0) return build_level_system(H, l);
   Level &L = H.lv[l];
   const orc_options &o = H.o;
   if (H.dim > 0) {
@@ -908,6 +1128,10 @@ int numeric_level(Hier &H, int l) {
     if (st) return st;
   }
   L.omega = 4.0 / (3.0 * L.lambda);
+  if (H.k > 0) {
+    L.P = smooth_tentative(L.Abar, L.Pt, L.invD, L.omega);
+    return ST_OK;
+  }
   L.P = prolongator(L.Abar, L.invD, L.agg, nc, L.omega);
   if (o.variants & V_CNSTRNT)
     for (int i = 0; i < L.P.nr; ++i)
@@ -953,6 +1177,10 @@ void galerkin(Hier &H, int l, const double *B) {
   Ln.A = spgemm(L.R, AP);
   Ln.As = Ln.A;
   if (H.dim > 0) Ln.xyz = coarse_coords(L.xyz, H.dim, L.agg, L.nc);
+  if (H.k > 0) {
+    Ln.bs = H.k;
+    Ln.B = L.Bc;
+  }
 }
 
 // Smoothers on every level but the coarsest (Sec. 3.1: Chebyshev of degree 2 on
@@ -1025,26 +1253,43 @@ int orc_setup(int32_t n, const int32_t *rp, const int32_t *col, const double *va
   return orc_setup_coords(n, rp, col, val, B, nullptr, 0, o, out);
 }
 
-int orc_setup_coords(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
-                     const double *B, const double *coords, int32_t dim, const orc_options *o,
-                     void **out) {
+}  // extern "C"
+
+namespace {
+int setup_common(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                 const double *B, int32_t bs, const double *Bm, int32_t k,
+                 const double *coords, int32_t dim, const orc_options *o, void **out) {
   *out = nullptr;
   int st = check_csr(n, rp, col, val);
   if (st) return st;
+  if (k > 0) {
+    if (bs < 1 || bs > 16 || n % bs != 0) return fail(ST_INVALID, "block size");
+    if (k > 16) return fail(ST_INVALID, "nullspace dimension");
+    if (o->variants & (V_SPRSFY | V_CNSTRNT))
+      return fail(ST_INVALID, "Sprsfy and Cnstrnt are not defined for systems");
+    for (int64_t q = 0; q < (int64_t)n * k; ++q)
+      if (!std::isfinite(Bm[q])) return fail(ST_INVALID, "non-finite nullspace entry");
+  }
   if (o->theta < 0.0 || o->theta > 1.0 || o->max_levels < 1 || o->degree < 1 ||
       o->power_iters < 1)
     return fail(ST_INVALID, "bad options");
   if (coords && (dim < 1 || dim > 3)) return fail(ST_INVALID, "coordinate dimension");
   if (o->coarse_solver != 0 && o->coarse_solver != 1) return fail(ST_INVALID, "coarse_solver");
   if (o->dist_power != 1 && o->dist_power != 2) return fail(ST_INVALID, "dist_power");
-  for (int64_t k = 0; coords && k < (int64_t)n * dim; ++k)
-    if (!std::isfinite(coords[k])) return fail(ST_INVALID, "non-finite coordinate");
+  const int64_t npts = k > 0 ? n / bs : n;  // coordinates are per node
+  for (int64_t q = 0; coords && q < npts * dim; ++q)
+    if (!std::isfinite(coords[q])) return fail(ST_INVALID, "non-finite coordinate");
   Hier *H = new Hier();
   H->o = *o;
   H->dim = coords ? dim : 0;
+  H->k = k;
   H->lv.emplace_back();
   H->lv[0].A = make_csr(n, n, rp, col, val);
-  if (coords) H->lv[0].xyz.assign(coords, coords + (size_t)n * dim);
+  if (coords) H->lv[0].xyz.assign(coords, coords + (size_t)npts * dim);
+  if (k > 0) {
+    H->lv[0].bs = bs;
+    H->lv[0].B.assign(Bm, Bm + (size_t)n * k);
+  }
   st = apply_nullspace(*H, B);
   if (st) {
     delete H;
@@ -1080,12 +1325,29 @@ int orc_setup_coords(int32_t n, const int32_t *rp, const int32_t *col, const dou
   *out = H;
   return ST_OK;
 }
+}  // namespace
+
+extern "C" {
+
+int orc_setup_coords(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                     const double *B, const double *coords, int32_t dim, const orc_options *o,
+                     void **out) {
+  return setup_common(n, rp, col, val, B, 1, nullptr, 0, coords, dim, o, out);
+}
+
+int orc_setup_system(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+                     int32_t bs, const double *B, int32_t k, const double *coords, int32_t dim,
+                     const orc_options *o, void **out) {
+  if (!B || k < 1) return fail(ST_INVALID, "systems setup needs a nullspace");
+  return setup_common(n, rp, col, val, nullptr, bs, B, k, coords, dim, o, out);
+}
 
 // Numeric re-setup: new values on the setup's pattern, with every symbolic decision of the
 // setup kept (strength labels and Sprsfy drops, aggregates); the numbers are recomputed by
 // the setup's own steps.  On failure the hierarchy is left unusable (solves refuse it).
 int orc_resetup(void *h, const double *val, const double *B) {
   Hier *H = (Hier *)h;
+  if (H->k > 0 && B) return fail(ST_INVALID, "a systems hierarchy keeps its nullspace");
   Level &L0 = H->lv[0];
   const int n = L0.A.nr;
   H->valid = false;
@@ -1109,6 +1371,19 @@ int orc_resetup(void *h, const double *val, const double *B) {
 }
 
 int orc_num_levels(const void *h) { return (int)((const Hier *)h)->lv.size(); }
+
+int orc_level_block(const void *h, int l, int64_t *s) {
+  const Hier *H = (const Hier *)h;
+  if (l < 0 || l >= (int)H->lv.size()) return fail(ST_INVALID, "bad level");
+  const Level &L = H->lv[l];
+  s[0] = L.bs;
+  s[1] = H->k;
+  s[2] = L.Pt.nnz();
+  s[3] = L.Gn.nr;
+  s[4] = (int64_t)L.Gn.col.size();
+  s[5] = (int64_t)L.B.size();
+  return ST_OK;
+}
 
 int orc_level_sizes(const void *h, int l, int64_t *s) {
   const Hier *H = (const Hier *)h;
@@ -1164,6 +1439,13 @@ int orc_export(const void *h, int l, int what, void *buf) {
     case 16: return cp(L.sm_invD.data(), L.sm_invD.size() * 8);
     case 17: return cp(L.As.val.data(), L.As.val.size() * 8);
     case 18: return cp(L.xyz.data(), L.xyz.size() * 8);
+    case 19: return cp(L.Pt.rp.data(), L.Pt.rp.size() * 4);
+    case 20: return cp(L.Pt.col.data(), L.Pt.col.size() * 4);
+    case 21: return cp(L.Pt.val.data(), L.Pt.val.size() * 8);
+    case 22: return cp(L.B.data(), L.B.size() * 8);
+    case 23: return cp(L.nmask.data(), L.nmask.size());
+    case 24: return cp(L.Gn.rp.data(), L.Gn.rp.size() * 4);
+    case 25: return cp(L.Gn.col.data(), L.Gn.col.size() * 4);
     default: return fail(ST_INVALID, "bad export selector");
   }
 }

@@ -398,6 +398,124 @@ def q1_mesh(nodes: np.ndarray, reaction: float = 0.0, u_dirichlet=None, name: st
     return prob, rhs, flat[inner].copy()
 
 
+def q1_elasticity(nodes: np.ndarray, young: float = 1.0, poisson: float = 0.3,
+                  fixed: np.ndarray | None = None, name: str = "q1_elasticity"):
+    """3-D linear elasticity with trilinear (Q1) hexahedra on a structured mesh: 3 unknowns
+    per node (displacements x, y, z), numbered node-major (dof = 3 node + component) over the
+    free nodes in x-fastest node order.
+
+    Element matrices K_e = sum over the 2x2x2 Gauss points of det(J) B^T C B, C the isotropic
+    elasticity matrix of (young, poisson) in Voigt order (xx, yy, zz, yz, xz, xy) with
+    engineering shear strains.  ``fixed`` (a boolean per mesh node, shape of nodes[..., 0])
+    marks clamped nodes, eliminated with zero displacement; by default the face x = 0.  The
+    pattern holds every 3x3 block between nodes of a common element, all entries stored.
+
+    Returns (CsrProblem, coords of the free nodes (m x 3), rigid-body modes (n x 6): the
+    translations x, y, z and the rotations about z, x, y (-y, x, 0), (0, -z, y), (z, 0, -x))."""
+    nodes = np.asarray(nodes, dtype=np.float64)
+    nz1, ny1, nx1, _ = nodes.shape
+    nx, ny, nz = nx1 - 1, ny1 - 1, nz1 - 1
+    if fixed is None:
+        fixed = np.zeros((nz1, ny1, nx1), dtype=bool)
+        fixed[:, :, 0] = True
+    fixed = np.asarray(fixed, dtype=bool).reshape(-1)
+    flat = nodes.reshape(-1, 3)
+    nn = flat.shape[0]
+    free = np.flatnonzero(~fixed)
+    nid = np.full(nn, -1, dtype=np.int64)
+    nid[free] = np.arange(free.size)
+    gid = np.arange(nn).reshape(nz1, ny1, nx1)
+    ez, ey, ex = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ex, ey, ez = ex.reshape(-1), ey.reshape(-1), ez.reshape(-1)
+    conn = np.stack([gid[ez + ((a >> 2) & 1), ey + ((a >> 1) & 1), ex + (a & 1)]
+                     for a in range(8)], axis=1)
+    X = flat[conn]
+    XT = np.ascontiguousarray(X.transpose(0, 2, 1))
+    lam = young * poisson / ((1.0 + poisson) * (1.0 - 2.0 * poisson))
+    mu = young / (2.0 * (1.0 + poisson))
+    Cm = np.zeros((6, 6))
+    Cm[:3, :3] = lam
+    Cm[[0, 1, 2], [0, 1, 2]] += 2.0 * mu
+    Cm[[3, 4, 5], [3, 4, 5]] = mu
+    _, dNq = _q1_reference()
+    E = conn.shape[0]
+    K = np.zeros((E, 24, 24))
+    for q in range(8):
+        J = XT @ dNq[q]
+        det = np.linalg.det(J)
+        if not np.all(det > 0.0):
+            raise ValueError("inverted or degenerate element")
+        G = dNq[q] @ np.linalg.inv(J)                       # (E, 8, 3) shape gradients
+        B = np.zeros((E, 6, 24))
+        for a in range(8):
+            gx, gy, gz = G[:, a, 0], G[:, a, 1], G[:, a, 2]
+            B[:, 0, 3 * a] = gx
+            B[:, 1, 3 * a + 1] = gy
+            B[:, 2, 3 * a + 2] = gz
+            B[:, 3, 3 * a + 1] = gz
+            B[:, 3, 3 * a + 2] = gy
+            B[:, 4, 3 * a] = gz
+            B[:, 4, 3 * a + 2] = gx
+            B[:, 5, 3 * a] = gy
+            B[:, 5, 3 * a + 1] = gx
+        K += det[:, None, None] * (B.transpose(0, 2, 1) @ (Cm @ B))
+    # node graph: nodes sharing an element; dof pattern = 3x3 blocks
+    gi = np.repeat(conn[:, :, None], 8, axis=2).reshape(-1)
+    gj = np.repeat(conn[:, None, :], 8, axis=1).reshape(-1)
+    keep = (nid[gi] >= 0) & (nid[gj] >= 0)
+    pairs = np.unique(nid[gi[keep]] * free.size + nid[gj[keep]])
+    prow, pcol = pairs // free.size, pairs % free.size
+    m = free.size
+    ncnt = np.bincount(prow, minlength=m)
+    nrp = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(ncnt, out=nrp[1:])
+    n = 3 * m
+    rp = np.zeros(n + 1, dtype=np.int64)
+    rp[1:] = np.repeat(3 * ncnt, 3).cumsum()
+    nnz = int(rp[-1])
+    col = np.empty(nnz, dtype=np.int32)
+    for c in range(3):           # row (node I, component c): blocks J ascending, components
+        r = 3 * np.arange(m) + c
+        base = rp[r]
+        for b in range(3):
+            idx = base[prow] + 3 * (np.arange(pairs.size) - nrp[prow]) + b
+            col[idx] = (3 * pcol + b).astype(np.int32)
+    # scatter element entries: position of (node I comp a, node J comp b)
+    slot_of_pair = np.searchsorted(pairs, nid[gi[keep]] * free.size + nid[gj[keep]])
+    ks = K.reshape(E, 8, 3, 8, 3).transpose(0, 1, 3, 2, 4).reshape(-1, 3, 3)[keep]
+    I = nid[gi[keep]]
+    val = np.zeros(nnz)
+    for a in range(3):
+        for b in range(3):
+            pos = rp[3 * I + a] + 3 * (slot_of_pair - nrp[I]) + b
+            val += np.bincount(pos, weights=ks[:, a, b], minlength=nnz)
+    prob = CsrProblem(n, rp.astype(np.int32), col, val, name)
+    xyz = flat[free]
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    one, zero = np.ones(m), np.zeros(m)
+    modes = [(one, zero, zero), (zero, one, zero), (zero, zero, one),
+             (-y, x, zero), (zero, -z, y), (z, zero, -x)]
+    rbm = np.stack([np.stack(md, axis=1).reshape(-1) for md in modes], axis=1)
+    return prob, xyz.copy(), rbm
+
+
+def elastic_beam(nx: int = 40, ny: int = 8, nz: int = 8, length: float = 5.0,
+                 stretch: float = 1.0, young: float = 1.0, poisson: float = 0.3):
+    """A cantilever: nx x ny x nz Q1 elements on [0, length] x [0, 1] x [0, 1] (the z
+    spacing graded by ``stretch`` like ``graded_spacing``), clamped at x = 0."""
+    ax = np.linspace(0.0, length, nx + 1)
+    ay = np.linspace(0.0, 1.0, ny + 1)
+    if stretch == 1.0:
+        az = np.linspace(0.0, 1.0, nz + 1)
+    else:
+        h = stretch ** (np.arange(nz, dtype=np.float64) / max(nz - 1, 1))
+        az = np.concatenate([[0.0], np.cumsum(h / h.sum())])
+    Z, Y, Xg = np.meshgrid(az, ay, ax, indexing="ij")
+    nodes = np.stack([Xg, Y, Z], axis=-1)
+    return q1_elasticity(nodes, young, poisson,
+                         name=f"elastic_beam_{nx}x{ny}x{nz}_s{stretch:g}")
+
+
 def u_trilinear(x, y, z):
     """Boundary data of Sec. 3.2-3.3: 1 + x + y + z + xy + xz + yz + xyz."""
     return 1.0 + x + y + z + x * y + x * z + y * z + x * y * z
