@@ -126,7 +126,11 @@ typedef enum {
   SA_PART_ABAR_VAL = 8, SA_PART_INVD = 9, SA_PART_P_RP = 10, SA_PART_P_COL = 11,
   SA_PART_P_VAL = 12, SA_PART_R_RP = 13, SA_PART_R_COL = 14, SA_PART_R_VAL = 15,
   SA_PART_SM_INVD = 16, SA_PART_COARSE_INV = 17,
-  SA_PART_COORDS = 18       /* node coordinates, n x dim (sa_setup_coords only)            */
+  SA_PART_COORDS = 18,      /* node coordinates, points x dim (distance strength only)     */
+  /* systems hierarchies (sa_setup_system) only: */
+  SA_PART_PT_RP = 19, SA_PART_PT_COL = 20, SA_PART_PT_VAL = 21, /* QR tentative prolongator */
+  SA_PART_NULLSPACE = 22,   /* the level's nullspace, n x k row-major                        */
+  SA_PART_NODE_MASK = 23, SA_PART_NODE_RP = 24, SA_PART_NODE_COL = 25  /* node graph, labels */
 } sa_part;
 
 /* Fills *o with the defaults listed above (struct_size included). */
@@ -161,6 +165,28 @@ sa_status sa_setup_coords(const sa_context *ctx, const sa_csr *A, const double *
                           const double *coords, int32_t dim, const sa_options *o,
                           sa_hierarchy **out);
 
+/* Smoothed aggregation for systems with a multi-vector nullspace (the paper's algorithms are
+ * scalar; it names systems as future work).  The unknowns are numbered node-major, block_size
+ * per node (1..16, dividing A->n); nullspace is A->n x k row-major (1 <= k <= 16), in A->loc
+ * memory, e.g. the six rigid-body modes of 3-D elasticity.
+ *  - Strength is taken between nodes: with F_IJ the sum of squares of the block A_IJ, (I,J)
+ *    is strong iff F_IJ^2 >= theta^4 F_II F_JJ (the scalar test for block_size 1); with
+ *    coords (one point per node, A->n / block_size x dim) the distance Laplacian of the node
+ *    graph decides instead.  Couplings between two nodes take their pair's label; couplings
+ *    inside a node are kept.  Lumping (plain or OffLmp), the smoothing diagonal (plain or
+ *    1Norm) and lambda are the scalar definitions applied to rows.
+ *  - Aggregates are sets of nodes.  Aggregate J's rows of the nullspace (members ascending,
+ *    components ascending) are factored B_J = Q_J R_J by Householder reflections with R's
+ *    diagonal non-negative; the tentative prolongator holds Q_J in columns kJ..kJ+k-1 and
+ *    the next level's nullspace holds R_J (so the coarse level has k unknowns per node).
+ *  - P = P_t - omega D^-1 Abar P_t; R = P^T; Galerkin products as for sa_setup.
+ *  - Sprsfy and Cnstrnt (defined for a scalar constant nullspace) are refused.
+ * Errors: those of sa_setup; SA_ERR_INVALID_ARG also for a bad block size or k, a
+ * non-finite nullspace entry, or an aggregate with fewer unknowns than k. */
+sa_status sa_setup_system(const sa_context *ctx, const sa_csr *A, int32_t block_size,
+                          const double *nullspace, int32_t k, const double *coords, int32_t dim,
+                          const sa_options *o, sa_hierarchy **out);
+
 /* Numeric re-setup: new values for the matrix given to sa_setup, on the same pattern (val
  * holds nnz values in that matrix's CSR order; nullspace as in sa_setup, NULL = ones; both in
  * `loc` memory).  Every symbolic decision of the setup is kept: strength labels and Sprsfy
@@ -172,7 +198,7 @@ sa_status sa_setup_coords(const sa_context *ctx, const sa_csr *A, const double *
  * decisions.  For a sequence of systems with one pattern (time steps, repeated requests) this
  * skips the strength test and root selection.  Errors as for sa_setup (values only); after a
  * failure the hierarchy can only be destroyed or re-set up again (solves return
- * SA_ERR_INVALID_ARG). */
+ * SA_ERR_INVALID_ARG).  A systems hierarchy keeps its nullspace (nullspace must be NULL). */
 sa_status sa_resetup(sa_hierarchy *h, const double *val, const double *nullspace,
                      sa_location loc);
 

@@ -23,17 +23,20 @@ SA_HOST, SA_DEVICE = 0, 1
 PARTS = {"A_rp": 0, "A_col": 1, "A_val": 2, "mask": 3, "agg": 4, "root": 5, "Abar_rp": 6,
          "Abar_col": 7, "Abar_val": 8, "invD": 9, "P_rp": 10, "P_col": 11, "P_val": 12,
          "R_rp": 13, "R_col": 14, "R_val": 15, "sm_invD": 16, "coarse_inv": 17,
-         "coords": 18}
+         "coords": 18, "Pt_rp": 19, "Pt_col": 20, "Pt_val": 21, "nullspace": 22,
+         "node_mask": 23, "node_rp": 24, "node_col": 25}
 PART_DTYPE = {"A_rp": "int32", "A_col": "int32", "A_val": "float64", "mask": "uint8",
               "agg": "int32", "root": "uint8", "Abar_rp": "int32", "Abar_col": "int32",
               "Abar_val": "float64", "invD": "float64", "P_rp": "int32", "P_col": "int32",
               "P_val": "float64", "R_rp": "int32", "R_col": "int32", "R_val": "float64",
-              "sm_invD": "float64", "coarse_inv": "float64", "coords": "float64"}
+              "sm_invD": "float64", "coarse_inv": "float64", "coords": "float64",
+              "Pt_rp": "int32", "Pt_col": "int32", "Pt_val": "float64", "nullspace": "float64",
+              "node_mask": "uint8", "node_rp": "int32", "node_col": "int32"}
 
 EXPORTED = ["sa_default_options", "sa_setup", "sa_solve", "sa_vcycle", "sa_hierarchy_info",
             "sa_export_size", "sa_export_level", "sa_destroy", "sa_status_string",
             "sa_last_error", "sa_profile_enable", "sa_profile_read", "sa_estimate_bytes",
-            "sa_solve_many", "sa_resetup", "sa_setup_coords", "sa_solve_gmres",
+            "sa_solve_many", "sa_resetup", "sa_setup_coords", "sa_solve_gmres", "sa_setup_system",
             "sa_server_create", "sa_server_submit", "sa_server_poll", "sa_server_wait",
             "sa_server_drain", "sa_server_get_stats", "sa_server_destroy"]
 
@@ -113,6 +116,10 @@ def lib():
         L.sa_setup_coords.argtypes = [C.POINTER(SaContext), C.POINTER(SaCsr), P, P, C.c_int32,
                                       C.POINTER(SaOptions), C.POINTER(C.c_void_p)]
         L.sa_setup_coords.restype = C.c_int
+        L.sa_setup_system.argtypes = [C.POINTER(SaContext), C.POINTER(SaCsr), C.c_int32, P,
+                                      C.c_int32, P, C.c_int32, C.POINTER(SaOptions),
+                                      C.POINTER(C.c_void_p)]
+        L.sa_setup_system.restype = C.c_int
         L.sa_resetup.argtypes = [P, P, P, C.c_int32]
         L.sa_resetup.restype = C.c_int
         L.sa_solve.argtypes = [P, P, P, C.c_int32, C.POINTER(C.c_int32),

@@ -27,7 +27,8 @@ enum ErrBits {
   E_DIAG = 32,
   E_CHOL = 64,
   E_COORD = 128,
-  E_ASYM = 256
+  E_ASYM = 256,
+  E_QR = 512
 };
 
 constexpr int32_t kMaxRestart = 1024;  // GMRES restart length limit
@@ -143,6 +144,17 @@ static void numeric_level(sa_hierarchy *h, int l, bool fresh) {
   if (!unit) power_method(L.Abar, L.invD, o.power_iters, o.seed, l, 0, L.lam_d, s);
   damping(L.lam_d, L.omega_d, unit, h->err, s);
   check_err(h, E_LAMBDA, SA_ERR_NEGATIVE_EIGENVALUE, "eigenvalue estimate not positive");
+  if (h->k > 0) {  // systems: P = P_t - omega D^-1 Abar P_t
+    if (fresh) {
+      smooth_tentative(L.Abar, L.Pt, L.invD, L.omega_d, ar, L.P, s);
+      spmv_plan(L.P, ar, s);
+    } else {
+      Csr P;
+      smooth_tentative(L.Abar, L.Pt, L.invD, L.omega_d, tmp, P, s);
+      take_values(P, L.P, s);
+    }
+    return;
+  }
   if (fresh) {
     prolongator(L.Abar, L.invD, L.agg, L.nc, L.omega_d, ar, L.P, s);
   } else {
@@ -156,7 +168,53 @@ static void numeric_level(sa_hierarchy *h, int l, bool fresh) {
 
 // Builds level l's strength labels and aggregates, then its numeric part.  Returns false when
 // the level has no strong connection left (it becomes the coarsest).
+// Systems SA (k-vector nullspace): labels on the node graph (block norms or the distance
+// Laplacian of node coordinates), dof labels from them, aggregates of nodes, the QR tentative
+// prolongator and the coarse nullspace, then the numeric part.
+static bool build_level_system(sa_hierarchy *h, int l) {
+  const hipStream_t s = h->stream;
+  const sa_options &o = h->opt;
+  Level &L = h->lv[l];
+  Arena &ar = h->ar;
+  const int32_t n = L.A.n, bs = L.bs, m = n / bs;
+  Arena tmp;
+  tmp.stream = s;
+  node_graph(L.As, bs, ar, L.Gn, s);
+  L.nmask = ar.alloc<uint8_t>(L.Gn.nnz > 0 ? L.Gn.nnz : 1);
+  int32_t *scount = tmp.alloc<int32_t>(m + 1);
+  const bool gwave = max_row_length(m, L.Gn.rp, s) > 64 || L.Gn.nnz > 24 * (int64_t)m;
+  if (h->dim > 0) {
+    double *w = tmp.alloc<double>(L.Gn.nnz > 0 ? L.Gn.nnz : 1);
+    double *Ld = tmp.alloc<double>(m);
+    distance_weights(m, L.Gn.rp, L.Gn.col, L.xyz, h->dim, o.dist_power, w, Ld, h->err, E_COORD,
+                     s);
+    check_err(h, E_COORD, SA_ERR_INVALID_ARG, "coincident coordinates of connected nodes");
+    strength(m, L.Gn.rp, L.Gn.col, w, Ld, o.theta * o.theta, L.nmask, scount, gwave, s);
+  } else {
+    block_strength(L.As, bs, L.Gn, o.theta, L.nmask, scount, s);
+  }
+  L.wave_rows = max_row_length(n, L.As.rp, s) > 64 || L.As.nnz > 24 * (int64_t)n;
+  L.mask = ar.alloc<uint8_t>(L.As.nnz);
+  dof_mask(L.As, bs, L.Gn, L.nmask, L.mask, s);
+  int32_t *grp = nullptr, *gcol = nullptr;
+  const int64_t nnzG = strength_graph(m, L.Gn.rp, L.Gn.col, L.nmask, scount, gwave, tmp, &grp,
+                                      &gcol, s);
+  L.agg = ar.alloc<int32_t>(m);
+  L.is_root = ar.alloc<uint8_t>(m);
+  int32_t *root_vertex = nullptr;
+  L.nc = aggregate(m, nnzG, grp, gcol, o.agg_order, o.seed, l, L.agg, L.is_root, tmp,
+                   &root_vertex, &L.mis_rounds, s);
+  if (L.nc == 0) return false;
+  if ((int64_t)L.nc * h->k >= n) throw Error(SA_ERR_COARSEN_STALLED, "coarsening stalled");
+  L.Bc = ar.alloc<double>((int64_t)L.nc * h->k * h->k);
+  tentative_qr(n, bs, h->k, L.agg, L.nc, L.B, ar, L.Pt, L.Bc, h->err, E_QR, s);
+  check_err(h, E_QR, SA_ERR_INVALID_ARG, "an aggregate has fewer dofs than nullspace vectors");
+  numeric_level(h, l, true);
+  return true;
+}
+
 static bool build_level(sa_hierarchy *h, int l) {
+  if (h->k > 0) return build_level_system(h, l);
   const hipStream_t s = h->stream;
   const sa_options &o = h->opt;
   Level &L = h->lv[l];
@@ -220,12 +278,17 @@ static void galerkin(sa_hierarchy *h, int l, bool fresh, const double *dB) {
     double *cxyz = nullptr;  // coarse coordinates: the aggregates' centroids
     if (h->dim > 0) {
       cxyz = h->ar.alloc<double>((int64_t)L.nc * h->dim);
-      aggregate_centroids(L.A.n, L.agg, L.nc, L.xyz, h->dim, cxyz, s);
+      aggregate_centroids(L.A.n / L.bs, L.agg, L.nc, L.xyz, h->dim, cxyz, s);
     }
+    double *Bnext = L.Bc;
     h->lv.emplace_back();  // invalidates L
     h->lv[l + 1].A = Ac;
     h->lv[l + 1].As = Ac;
     h->lv[l + 1].xyz = cxyz;
+    if (h->k > 0) {
+      h->lv[l + 1].bs = h->k;
+      h->lv[l + 1].B = Bnext;
+    }
   } else {
     spgemm(L.R, AP, tmp, Ac, s);
     take_values(Ac, h->lv[l + 1].A, s);  // As shares A's arrays on coarse levels
@@ -361,7 +424,8 @@ static void validate_values(sa_hierarchy *h) {
 }
 
 static void setup_impl(sa_hierarchy *h, const sa_csr *A, const double *B,
-                       const double *coords, int32_t dim) {
+                       const double *coords, int32_t dim, int32_t bs = 1,
+                       const double *Bm = nullptr, int32_t k = 0) {
   const double t0 = now_s();
   const hipStream_t s = h->stream;
   sa_options &o = h->opt;
@@ -387,12 +451,26 @@ static void setup_impl(sa_hierarchy *h, const sa_csr *A, const double *B,
   const int32_t rp0 = read1(L0.A.rp, s), rpn = read1(L0.A.rp + n, s);
   if (rp0 != 0 || (int64_t)rpn != A->nnz) throw Error(SA_ERR_BAD_CSR, "row pointers do not span nnz");
   validate_values(h);
+  if (k > 0) {  // systems SA
+    if (bs < 1 || bs > 16 || n % bs != 0)
+      throw Error(SA_ERR_INVALID_ARG, "block size not in 1..16 or not dividing n");
+    if (k > 16) throw Error(SA_ERR_INVALID_ARG, "nullspace dimension not in 1..16");
+    if (o.variants & (SA_SPRSFY | SA_CNSTRNT))
+      throw Error(SA_ERR_INVALID_ARG, "Sprsfy and Cnstrnt are not defined for systems");
+    h->k = k;
+    L0.bs = bs;
+    L0.B = h->ar.alloc<double>((int64_t)n * k);
+    copy_in(L0.B, Bm, sizeof(double) * (size_t)n * k, A->loc, s);
+    check_finite(L0.B, (int64_t)n * k, h->err, E_NONFINITE, s);
+    check_err(h, E_NONFINITE, SA_ERR_INVALID_ARG, "non-finite nullspace entry");
+  }
   if (coords) {
+    const int64_t npts = n / L0.bs;  // coordinates are per node
     if (dim < 1 || dim > 3) throw Error(SA_ERR_INVALID_ARG, "coordinate dimension not 1..3");
     h->dim = dim;
-    L0.xyz = h->ar.alloc<double>((int64_t)n * dim);
-    copy_in(L0.xyz, coords, sizeof(double) * n * dim, A->loc, s);
-    check_finite(L0.xyz, (int64_t)n * dim, h->err, E_COORD, s);
+    L0.xyz = h->ar.alloc<double>(npts * dim);
+    copy_in(L0.xyz, coords, sizeof(double) * npts * dim, A->loc, s);
+    check_finite(L0.xyz, npts * dim, h->err, E_COORD, s);
     check_err(h, E_COORD, SA_ERR_INVALID_ARG, "non-finite coordinate");
   }
   spmv_plan(L0.A, h->ar, s);
@@ -417,6 +495,7 @@ static void setup_impl(sa_hierarchy *h, const sa_csr *A, const double *B,
 // Sprsfy drops, aggregates, the patterns of the filtered matrices, P, R and every A_l) and
 // the numbers are recomputed in the setup's order, each into the existing arrays.
 static void resetup_impl(sa_hierarchy *h, const double *val, const double *B, sa_location loc) {
+  if (h->k > 0 && B) throw Error(SA_ERR_INVALID_ARG, "a systems hierarchy keeps its nullspace");
   const double t0 = now_s();
   const hipStream_t s = h->stream;
   Level &L0 = h->lv[0];
@@ -883,6 +962,29 @@ sa_status sa_setup(const sa_context *ctx, const sa_csr *A, const double *nullspa
   return sa_setup_coords(ctx, A, nullspace, nullptr, 0, o, out);
 }
 
+sa_status sa_setup_system(const sa_context *ctx, const sa_csr *A, int32_t block_size,
+                          const double *nullspace, int32_t k, const double *coords, int32_t dim,
+                          const sa_options *o, sa_hierarchy **out) {
+  if (!out) return SA_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!nullspace || k < 1) return SA_ERR_INVALID_ARG;
+  return guarded([&]() -> sa_status {
+    std::unique_ptr<sa_hierarchy> h(new sa_hierarchy());
+    h->stream = ctx ? (hipStream_t)ctx->stream : nullptr;
+    h->ar.stream = h->stream;
+    if (o) h->opt = *o;
+    else sa_default_options(&h->opt);
+    try {
+      setup_impl(h.get(), A, nullptr, coords, dim, block_size, nullspace, k);
+    } catch (...) {
+      (void)hipStreamSynchronize(h->stream);
+      throw;
+    }
+    *out = h.release();
+    return SA_OK;
+  });
+}
+
 sa_status sa_resetup(sa_hierarchy *h, const double *val, const double *nullspace,
                      sa_location loc) {
   if (!h || !val || h->lv.empty()) return SA_ERR_INVALID_ARG;
@@ -967,8 +1069,8 @@ static bool part_info(const sa_hierarchy *h, int32_t level, sa_part what, const 
     case SA_PART_A_COL: *ptr = L.A.col; *count = L.A.nnz; break;
     case SA_PART_A_VAL: *ptr = L.A.val; *count = L.A.nnz; *esize = 8; break;
     case SA_PART_MASK: *ptr = L.mask; *count = L.mask ? L.A.nnz : 0; *esize = 1; break;
-    case SA_PART_AGG: *ptr = L.agg; *count = L.agg ? L.A.n : 0; break;
-    case SA_PART_ROOT: *ptr = L.is_root; *count = L.is_root ? L.A.n : 0; *esize = 1; break;
+    case SA_PART_AGG: *ptr = L.agg; *count = L.agg ? L.A.n / L.bs : 0; break;
+    case SA_PART_ROOT: *ptr = L.is_root; *count = L.is_root ? L.A.n / L.bs : 0; *esize = 1; break;
     case SA_PART_ABAR_RP: *ptr = L.Abar.rp; *count = has_p ? L.Abar.n + 1 : 0; break;
     case SA_PART_ABAR_COL: *ptr = L.Abar.col; *count = has_p ? L.Abar.nnz : 0; break;
     case SA_PART_ABAR_VAL: *ptr = L.Abar.val; *count = has_p ? L.Abar.nnz : 0; *esize = 8; break;
@@ -980,9 +1082,16 @@ static bool part_info(const sa_hierarchy *h, int32_t level, sa_part what, const 
     case SA_PART_R_COL: *ptr = L.R.col; *count = has_p ? L.R.nnz : 0; break;
     case SA_PART_R_VAL: *ptr = L.R.val; *count = has_p ? L.R.nnz : 0; *esize = 8; break;
     case SA_PART_SM_INVD: *ptr = L.sm_invD; *count = has_p ? L.A.n : 0; *esize = 8; break;
+    case SA_PART_PT_RP: *ptr = L.Pt.rp; *count = has_p && L.Pt.rp ? L.A.n + 1 : 0; break;
+    case SA_PART_PT_COL: *ptr = L.Pt.col; *count = has_p ? L.Pt.nnz : 0; break;
+    case SA_PART_PT_VAL: *ptr = L.Pt.val; *count = has_p ? L.Pt.nnz : 0; *esize = 8; break;
+    case SA_PART_NULLSPACE: *ptr = L.B; *count = (int64_t)L.A.n * h->k; *esize = 8; break;
+    case SA_PART_NODE_MASK: *ptr = L.nmask; *count = has_p ? L.Gn.nnz : 0; *esize = 1; break;
+    case SA_PART_NODE_RP: *ptr = L.Gn.rp; *count = has_p && L.Gn.rp ? L.Gn.n + 1 : 0; break;
+    case SA_PART_NODE_COL: *ptr = L.Gn.col; *count = has_p ? L.Gn.nnz : 0; break;
     case SA_PART_COORDS:
       *ptr = L.xyz;
-      *count = (int64_t)L.A.n * h->dim;
+      *count = (int64_t)(L.A.n / L.bs) * h->dim;  // one point per node
       *esize = 8;
       break;
     case SA_PART_COARSE_INV:

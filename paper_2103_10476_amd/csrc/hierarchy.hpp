@@ -18,6 +18,13 @@ struct Level {
   int32_t mis_rounds = 0;
   bool wave_rows = false;  // rows long enough for the wavefront-per-row setup kernels
   double *xyz = nullptr;   // node coordinates (n x dim) when the distance strength is used
+  // systems SA: dofs per node, node graph and labels, QR tentative prolongator, this level's
+  // nullspace (n x k) and the next level's (nc k x k)
+  int32_t bs = 1;
+  Csr Gn;
+  uint8_t *nmask = nullptr;
+  Csr Pt;
+  double *B = nullptr, *Bc = nullptr;
   Csr Abar;
   double *invD = nullptr;
   double *lam_d = nullptr, *omega_d = nullptr;
@@ -48,6 +55,7 @@ struct sa_hierarchy {
   double setup_seconds = 0.0;
   bool valid = true;            // false after a failed re-setup
   int32_t dim = 0;              // > 0: distance-Laplacian strength from coordinates
+  int32_t k = 0;                // > 0: systems SA with a k-vector nullspace
   double *dB = nullptr;         // nullspace vector (when it is not all ones)
   double *As0 = nullptr;        // D_B A D_B values on level 0 (when scaled)
   // solve workspace

@@ -137,6 +137,31 @@ int32_t max_row_length(int32_t n, const int32_t *rp, hipStream_t s);
 void distance_weights(int32_t n, const int32_t *rp, const int32_t *col, const double *xyz,
                       int32_t dim, int32_t power, double *w, double *Ld, int32_t *err,
                       int32_t ebit, hipStream_t s);
+// Member lists of the nc aggregates: mrp[nc+1] offsets into mem (unaggregated vertices left
+// out); members in scatter order, or ascending when `sorted`.  Arrays from ar.
+void member_lists(int32_t n, const int32_t *agg, int32_t nc, bool sorted, Arena &ar,
+                  int32_t **mrp_out, int32_t **mem_out, hipStream_t s);
+
+// ---- systems SA (systems.hip) ----------------------------------------------------------
+// Node graph of a node-major block matrix (bs dofs per node): G.rp/G.col over A.n / bs nodes.
+void node_graph(const Csr &A, int32_t bs, Arena &ar, Csr &G, hipStream_t s);
+// Node labels on G from block Frobenius norms (0 weak, 1 strong, 3 diagonal) and the strong
+// count per node.
+void block_strength(const Csr &A, int32_t bs, const Csr &G, double theta, uint8_t *nmask,
+                    int32_t *scount, hipStream_t s);
+// Dof labels of A from node labels (entries inside a node kept).
+void dof_mask(const Csr &A, int32_t bs, const Csr &G, const uint8_t *nmask, uint8_t *mask,
+              hipStream_t s);
+// QR tentative prolongator of n dofs (node aggregates agg, nc of them) for the nullspace B
+// (n x k): Pt (n x nc k) from ar, Bc (nc k x k) the coarse nullspace; *err |= ebit when an
+// aggregate has fewer dofs than k.
+void tentative_qr(int32_t n, int32_t bs, int32_t k, const int32_t *agg, int32_t nc,
+                  const double *B, Arena &ar, Csr &Pt, double *Bc, int32_t *err, int32_t ebit,
+                  hipStream_t s);
+// P = P_t - (omega invD_i) (Abar P_t)_i on the pattern of Abar P_t.
+void smooth_tentative(const Csr &abar, const Csr &Pt, const double *invD, const double *omega,
+                      Arena &ar, Csr &P, hipStream_t s);
+
 // *err |= ebit when some x[0..m) is not finite.
 void check_finite(const double *x, int64_t m, int32_t *err, int32_t ebit, hipStream_t s);
 // cxyz[J] = centroid of aggregate J's members (nc x dim), summed in ascending vertex order.

@@ -247,8 +247,8 @@ __global__ void k_scatter_members(int32_t n, const int32_t *agg, int32_t *pos, i
 }
 // Member lists of the nc aggregates: mrp[nc+1] offsets into mem[n] (unaggregated vertices
 // left out); members in scatter order, or ascending when `sorted`.
-static void member_lists(int32_t n, const int32_t *agg, int32_t nc, bool sorted, Arena &ar,
-                         int32_t **mrp_out, int32_t **mem_out, hipStream_t s) {
+void member_lists(int32_t n, const int32_t *agg, int32_t nc, bool sorted, Arena &ar,
+                  int32_t **mrp_out, int32_t **mem_out, hipStream_t s) {
   int32_t *cnt = ar.alloc<int32_t>(nc + 1);
   int32_t *mrp = ar.alloc<int32_t>(nc + 1);
   int32_t *mem = ar.alloc<int32_t>(n > 0 ? n : 1);

@@ -98,9 +98,10 @@ class Hierarchy:
     """A device-resident SA-AMG hierarchy (sa_hierarchy)."""
 
     def __init__(self, n, rp, col, val, nullspace=None, options: Options | None = None,
-                 stream=None, coords=None):
-        """``coords`` (n x dim node coordinates, dim 1..3) selects the distance-Laplacian
-        strength test (sa_setup_coords)."""
+                 stream=None, coords=None, block_size=None):
+        """``coords`` (points x dim node coordinates, dim 1..3) selects the distance-Laplacian
+        strength test (sa_setup_coords).  ``block_size`` selects systems SA
+        (sa_setup_system): ``nullspace`` is then n x k, node-major unknowns."""
         torch = _torch()
         self.options = options or Options()
         self.n = int(n)
@@ -111,11 +112,24 @@ class Hierarchy:
         dval = _dev(val, torch.float64)
         csr = _lib.SaCsr(self.n, int(dcol.numel()), drp.data_ptr(), dcol.data_ptr(),
                          dval.data_ptr(), _lib.SA_DEVICE)
-        dB = None if nullspace is None else _dev(nullspace, torch.float64)
+        dB = None if (nullspace is None or block_size is not None) else _dev(nullspace,
+                                                                             torch.float64)
         ctx = _lib.SaContext(_stream_handle(stream))
         opts = self.options.to_c()
         h = C.c_void_p()
-        if coords is None:
+        self.block_size = block_size
+        if block_size is not None:
+            dB = _dev(nullspace, torch.float64).reshape(self.n, -1).contiguous()
+            k = int(dB.shape[1])
+            dX = None if coords is None else _dev(coords, torch.float64).reshape(
+                self.n // block_size, -1).contiguous()
+            self.dim = 0 if dX is None else int(dX.shape[1])
+            code = L.sa_setup_system(C.byref(ctx), C.byref(csr), block_size,
+                                     C.c_void_p(dB.data_ptr()), k,
+                                     None if dX is None else C.c_void_p(dX.data_ptr()), self.dim,
+                                     C.byref(opts), C.byref(h))
+            _lib.check(code, "sa_setup_system")
+        elif coords is None:
             code = L.sa_setup(C.byref(ctx), C.byref(csr),
                               None if dB is None else C.c_void_p(dB.data_ptr()),
                               C.byref(opts), C.byref(h))
@@ -131,9 +145,10 @@ class Hierarchy:
         self._h = h
 
     @classmethod
-    def from_problem(cls, p, nullspace=None, options=None, stream=None, coords=None):
+    def from_problem(cls, p, nullspace=None, options=None, stream=None, coords=None,
+                     block_size=None):
         return cls(p.n, p.rp, p.col, p.val, nullspace=nullspace, options=options, stream=stream,
-                   coords=coords)
+                   coords=coords, block_size=block_size)
 
     # ---- numeric re-setup ---------------------------------------------------------------
     def resetup(self, val, nullspace=None):

@@ -14,7 +14,7 @@ def log(msg):
     sys.stdout.flush()
 
 
-def run_both(p, b=None, nullspace=None, coords=None, **opts):
+def run_both(p, b=None, nullspace=None, coords=None, block_size=None, **opts):
     """Set up on the GPU and in the oracle with the same inputs (``coords``: node
     coordinates for the distance-Laplacian strength)."""
     from oracle import oracle as orc
@@ -24,11 +24,12 @@ def run_both(p, b=None, nullspace=None, coords=None, **opts):
     pcg = g_opts.pop("pcg_beta", "fr")
     o = solver.Options(**g_opts, pcg_beta=pcg)
     t = time.time()
-    g = solver.Hierarchy.from_problem(p, nullspace=nullspace, options=o, coords=coords)
+    g = solver.Hierarchy.from_problem(p, nullspace=nullspace, options=o, coords=coords,
+                                      block_size=block_size)
     tg = time.time() - t
     t = time.time()
     h = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, nullspace=nullspace, coords=coords,
-                            **opts)
+                            block_size=block_size, **opts)
     to = time.time() - t
     log(f"[parity]   setup gpu {tg:.3f}s oracle {to:.3f}s levels {len(h.levels)}")
     return g, h
@@ -59,6 +60,8 @@ def compare_setup(g, h, check_values=True):
             assert_same(g.export(l, name), arr, f"{tag} {name}")
         if getattr(h, "dim", 0):
             assert_same(g.export(l, "coords"), L.coords.reshape(-1), f"{tag} coords")
+        if getattr(h, "system", False):
+            assert_same(g.export(l, "nullspace"), L.B.reshape(-1), f"{tag} nullspace")
         if L.coarsest:
             inv = g.export(l, "coarse_inv").reshape(L.n, L.n)
             A = np.zeros((L.n, L.n))
@@ -78,6 +81,12 @@ def compare_setup(g, h, check_values=True):
         for name, arr in zip(("R_rp", "R_col", "R_val"), L.R):
             assert_same(g.export(l, name), arr, f"{tag} {name}")
         assert_same(g.export(l, "sm_invD"), L.sm_invD, f"{tag} sm_invD")
+        if getattr(h, "system", False):
+            for name, arr in zip(("Pt_rp", "Pt_col", "Pt_val"), L.Pt):
+                assert_same(g.export(l, name), arr, f"{tag} {name}")
+            assert_same(g.export(l, "node_mask"), L.nmask, f"{tag} node labels")
+            assert_same(g.export(l, "node_rp"), L.Gn[0], f"{tag} node graph rp")
+            assert_same(g.export(l, "node_col"), L.Gn[1], f"{tag} node graph col")
         assert info["lambda"][l] == L.lam, (tag, "lambda", info["lambda"][l], L.lam)
         assert info["omega"][l] == L.omega, (tag, "omega")
         assert info["smoother_lambda"][l] == L.sm_lam, (tag, "smoother lambda")

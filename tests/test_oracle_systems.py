@@ -132,11 +132,12 @@ def test_systems_distance_strength_and_errors(orc, beam):
     bad[3, 2] = np.nan
     with pytest.raises(orc.OracleError):
         orc.OracleHierarchy(p.n, p.rp, p.col, p.val, nullspace=bad, block_size=3)
-    # an aggregate with fewer dofs than nullspace vectors
-    q = pb.fd7_stretched(12, 1.0, nx=1, ny=1)   # 1-D chain: aggregates of 2-3 nodes
-    with pytest.raises(orc.OracleError):
+    # an aggregate with fewer dofs than nullspace vectors (corner aggregates of a cube)
+    q = pb.fd7_stretched(8, 1.0)
+    with pytest.raises(orc.OracleError) as e:
         orc.OracleHierarchy(q.n, q.rp, q.col, q.val, nullspace=np.random.default_rng(0)
-                            .normal(size=(q.n, 4)), block_size=1, max_coarse=2)
+                            .normal(size=(q.n, 6)), block_size=1, max_coarse=2)
+    assert "fewer" in str(e.value)
     # re-setup keeps the nullspace: same values reproduce the hierarchy; a new one is refused
     h2 = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, nullspace=B, block_size=3, max_coarse=100)
     ref = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, nullspace=B, block_size=3, max_coarse=100)
