@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--serving-budget-gib", type=float, default=8.0)
     ap.add_argument("--family-seeds", type=int, default=10,
                     help="perturbed-cube meshes in the mesh-family leg")
+    ap.add_argument("--only-systems", action="store_true",
+                    help="run only the systems-SA leg (elasticity, rigid-body modes)")
     ap.add_argument("--only-gmres", action="store_true",
                     help="run only the GMRES leg (nonsymmetric 128^3 cube, GMRES vs CG)")
     ap.add_argument("--only-families", action="store_true",
@@ -115,6 +117,9 @@ def main():
     from paper_2103_10476_amd import problems, solver
 
     torch.cuda.set_device(0)
+    if args.only_systems:
+        print(json.dumps(systems_leg(solver, problems)), flush=True)
+        return
     if args.only_gmres:
         print(json.dumps(gmres_leg(solver, problems)), flush=True)
         return
@@ -218,6 +223,7 @@ def main():
         result["variant_sweep"] = variant_sweep_leg(solver, problems)
         result["mesh_families"] = families_leg(solver, problems, seeds=args.family_seeds)
         result["gmres"] = gmres_leg(solver, problems)
+        result["systems"] = systems_leg(solver, problems)
         result["serving"] = serving_leg(solver, problems, args)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(p, b)
@@ -635,6 +641,48 @@ def gmres_leg(solver, problems, reps=3):
                                       "gmres_solve_s_p50": round(pct(gm, 50), 5)}
     log(f"[bench] fd7 128^3: CG {itc} its {pct(cg, 50) * 1e3:.1f} ms, GMRES(30) {itg} steps "
         f"{pct(gm, 50) * 1e3:.1f} ms")
+    return out
+
+
+def systems_leg(solver, problems, reps=3):
+    """Systems SA with a multi-vector nullspace (sa_setup_system) on a 3-D Q1 elasticity
+    cantilever, 96 x 24 x 24 elements clamped at x = 0 (180,000 unknowns, 3 per node): the six
+    rigid-body modes against the three translations, plain and OffLmp + 1Norm, Chebyshev
+    interval end 1.1 lambda, CG to 1e-8; FP32 V-cycle for the rigid-body case.  p50 of setup
+    and solve over ``reps`` runs, inputs resident in HBM."""
+    import torch
+    t0 = time.perf_counter()
+    p, X, B = problems.elastic_beam(96, 24, 24)
+    t_gen = time.perf_counter() - t0
+    drp, dcol, dval = (torch.from_numpy(a).cuda() for a in (p.rp, p.col, p.val))
+    db = torch.from_numpy(problems.random_rhs(p.n, 2)).cuda()
+    x = torch.empty_like(db)
+    out = {"problem": {"elements": "96x24x24", "n": p.n, "nnz": p.nnz, "block_size": 3,
+                       "build_s": round(t_gen, 1)}}
+    cases = [("rbm6_plain", 6, (), "fp64"), ("rbm6_offlmp_1norm", 6, ("offlmp", "1norm"), "fp64"),
+             ("rbm6_plain_fp32", 6, (), "fp32"), ("translations3_plain", 3, (), "fp64")]
+    for key, k, var, prec in cases:
+        dB = torch.from_numpy(np.ascontiguousarray(B[:, :k])).cuda()
+        o = solver.Options(variants=var, cheb_boost=1.1, rtol=1e-8, precision=prec)
+        se, so = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            h = solver.Hierarchy(p.n, drp, dcol, dval, nullspace=dB, options=o, block_size=3)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            _, it, rr, st = h.solve(db, x)
+            torch.cuda.synchronize()
+            se.append(t2 - t1)
+            so.append(time.perf_counter() - t2)
+            inf = h.info()
+            h.close()
+        out[key] = {"iterations": it, "status": st, "levels": inf["n"],
+                    "operator_complexity": round(inf["operator_complexity"], 4),
+                    "setup_s_p50": round(pct(se, 50), 5), "solve_s_p50": round(pct(so, 50), 5)}
+    log("[bench] systems (elastic beam): " + ", ".join(
+        f"{k} {v['iterations']} its setup {v['setup_s_p50'] * 1e3:.1f} ms solve "
+        f"{v['solve_s_p50'] * 1e3:.1f} ms" for k, v in out.items() if k != "problem"))
     return out
 
 

@@ -137,3 +137,15 @@ def test_systems_errors_like_the_oracle():
     with pytest.raises(SaError):
         g.resetup(p.val, nullspace=B)
     g.close()
+
+
+def test_elastic_beam_full_size():
+    """The benchmark's elasticity cantilever (96 x 24 x 24 elements, 180,000 unknowns) with
+    its six rigid-body modes: every level bitwise, CG to 1e-8 with equal iterations."""
+    p, X, B = _beam(96, 24, 24)
+    g, h = run_both(p, nullspace=B, block_size=3, cheb_boost=1.1, rtol=1e-8)
+    compare_setup(g, h)
+    it, _ = compare_solve(g, h, pb.random_rhs(p.n, 2))
+    log(f"[systems] beam 96x24x24: levels {g.info()['n']}, {it} its, setup "
+        f"{g.info()['setup_seconds'] * 1e3:.1f} ms")
+    g.close()
