@@ -46,6 +46,7 @@ def test_default_options_roundtrip():
     assert o.struct_size == ctypes.sizeof(_lib.SaOptions)
     assert o.theta == 0.02 and o.tau == 1.1 and o.max_coarse == 1000 and o.degree == 2
     assert o.cheb_ratio == 10.0 and o.power_iters == 10
+    assert o.dist_power == 1 and o.coarse_solver == 0  # 1/d weights; Cholesky
 
 
 def test_status_strings():
