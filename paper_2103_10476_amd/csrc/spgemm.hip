@@ -453,6 +453,57 @@ __global__ __launch_bounds__(kBlock) void k_esc_dense(
   }
 }
 
+// Long rows whose output has at most kLdsCols columns (the dense coarse levels): one wavefront
+// per row with a dense accumulator of ncols entries in LDS.  The row's entries k are taken in
+// ascending order; for each, the lanes add the products of Y's row k into their own columns
+// (distinct within a row of Y), and a barrier orders the adds of successive k, so every output
+// entry receives its products in ascending k from 0, as in the sort-based bins.  The result is
+// extracted in column order with ballots.
+constexpr int32_t kLdsCols = 6144;  // 9 bytes per column: 54 KB of LDS at most
+__global__ __launch_bounds__(64) void k_esc_lds(const int32_t *rows, int32_t nrows,
+                                                const int32_t *xrp, const int32_t *xcol,
+                                                const double *xval, const int32_t *yrp,
+                                                const int32_t *ycol, const double *yval,
+                                                int32_t ncols, const int64_t *poff,
+                                                int32_t *ocol, double *oval, int32_t *ucnt) {
+  extern __shared__ double lds_acc[];
+  double *acc = lds_acc;
+  uint8_t *flag = (uint8_t *)(acc + ncols);
+  const int lane = threadIdx.x;
+  const int32_t slot = blockIdx.x;
+  if (slot >= nrows) return;  // block-uniform
+  const int32_t i = rows[slot];
+  for (int32_t c = lane; c < ncols; c += 64) {
+    acc[c] = 0.0;
+    flag[c] = 0;
+  }
+  __syncthreads();
+  for (int32_t e = xrp[i]; e < xrp[i + 1]; ++e) {
+    const int32_t k = xcol[e];
+    const double a = xval[e];
+    for (int32_t q = yrp[k] + lane; q < yrp[k + 1]; q += 64) {
+      const int32_t j = ycol[q];
+      acc[j] = acc[j] + a * yval[q];
+      flag[j] = 1;
+    }
+    __syncthreads();
+  }
+  const int64_t base = poff[i];
+  int32_t w = 0;
+  for (int32_t c0 = 0; c0 < ncols; c0 += 64) {
+    const int32_t c = c0 + lane;
+    const bool f = c < ncols && flag[c] != 0;
+    const unsigned long long bm = __ballot(f);
+    if (f) {
+      const int32_t pos = w + __popcll(bm & ((1ull << lane) - 1ull));
+      ocol[base + pos] = c;
+      oval[base + pos] = acc[c];
+    }
+    w += __popcll(bm);
+  }
+  if (lane == 0) ucnt[i] = w;
+}
+
 // One thread per output entry: find the entry's row by binary search over C's row pointers
 // and copy from the row's slot area (coalesced writes).
 __global__ void k_compact(int32_t m, int64_t nnz, const int64_t *poff, const int32_t *crp,
@@ -527,7 +578,12 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
                                                       ucnt);
     SA_LAUNCH_CHECK();
   }
-  if (hc[3] > 0) {
+  if (hc[3] > 0 && Y.ncols <= kLdsCols) {
+    const size_t lds = (size_t)Y.ncols * (sizeof(double) + 1);
+    k_esc_lds<<<(unsigned)hc[3], 64, lds, s>>>(l3, hc[3], X.rp, X.col, X.val, Y.rp, Y.col, Y.val,
+                                              Y.ncols, poff, ocol, oval, ucnt);
+    SA_LAUNCH_CHECK();
+  } else if (hc[3] > 0) {
     int32_t *ovf = tmp.alloc<int32_t>(hc[3]);
     k_esc_hash<<<(unsigned)hc[3], kBlock, 0, s>>>(l3, hc[3], X.rp, X.col, X.val, xpref, Y.rp,
                                                   Y.col, Y.val, poff, ocol, oval, ucnt, ovf,
