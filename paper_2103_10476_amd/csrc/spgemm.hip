@@ -16,6 +16,8 @@
 // and are compacted into CSR afterwards.
 #include <algorithm>
 
+#include <mutex>
+
 #include "kernels.hpp"
 
 namespace sa {
@@ -453,13 +455,19 @@ __global__ __launch_bounds__(kBlock) void k_esc_dense(
   }
 }
 
-// Long rows whose output has at most kLdsCols columns (the dense coarse levels): one wavefront
-// per row with a dense accumulator of ncols entries in LDS.  The row's entries k are taken in
-// ascending order; for each, the lanes add the products of Y's row k into their own columns
-// (distinct within a row of Y), and a barrier orders the adds of successive k, so every output
-// entry receives its products in ascending k from 0, as in the sort-based bins.  The result is
-// extracted in column order with ballots.
-constexpr int32_t kLdsCols = 6144;  // 9 bytes per column: 54 KB of LDS at most
+// Long rows whose output columns fit in LDS (the dense coarse levels): one wavefront per row
+// with a dense accumulator of ncols doubles and a touched-column bitmap in LDS.  The row's
+// entries k are taken in ascending order; for each, the lanes add the products of Y's row k
+// into their own columns (distinct within a row of Y), and the adds of successive k are
+// ordered (one wavefront executes them in program order; a wave barrier separates them), so
+// every output entry receives its products in ascending k from 0, as in the sort-based bins.
+// The row's X entries and Y row ranges are staged in LDS 64 at a time, and the next chunk of
+// Y is loaded before the current one is added, so its latency overlaps the adds.  The result
+// is extracted in column order with ballots.
+__device__ __forceinline__ void lds_add(double *acc, uint32_t *bits, int32_t j, double v) {
+  acc[j] = acc[j] + v;
+  atomicOr(&bits[j >> 5], 1u << (j & 31));
+}
 __global__ __launch_bounds__(64) void k_esc_lds(const int32_t *rows, int32_t nrows,
                                                 const int32_t *xrp, const int32_t *xcol,
                                                 const double *xval, const int32_t *yrp,
@@ -468,31 +476,61 @@ __global__ __launch_bounds__(64) void k_esc_lds(const int32_t *rows, int32_t nro
                                                 int32_t *ocol, double *oval, int32_t *ucnt) {
   extern __shared__ double lds_acc[];
   double *acc = lds_acc;
-  uint8_t *flag = (uint8_t *)(acc + ncols);
+  const int32_t nw = (ncols + 31) >> 5;
+  uint32_t *bits = (uint32_t *)(acc + ncols);
+  __shared__ double s_a[64];
+  __shared__ int32_t s_b[64], s_e[64];
   const int lane = threadIdx.x;
   const int32_t slot = blockIdx.x;
   if (slot >= nrows) return;  // block-uniform
   const int32_t i = rows[slot];
-  for (int32_t c = lane; c < ncols; c += 64) {
-    acc[c] = 0.0;
-    flag[c] = 0;
-  }
-  __syncthreads();
-  for (int32_t e = xrp[i]; e < xrp[i + 1]; ++e) {
-    const int32_t k = xcol[e];
-    const double a = xval[e];
-    for (int32_t q = yrp[k] + lane; q < yrp[k + 1]; q += 64) {
-      const int32_t j = ycol[q];
-      acc[j] = acc[j] + a * yval[q];
-      flag[j] = 1;
+  for (int32_t c = lane; c < ncols; c += 64) acc[c] = 0.0;
+  for (int32_t c = lane; c < nw; c += 64) bits[c] = 0u;
+  const int32_t xb = xrp[i], xe = xrp[i + 1];
+  for (int32_t e0 = xb; e0 < xe; e0 += 64) {
+    const int32_t cnt = min(64, xe - e0);
+    __syncthreads();
+    if (lane < cnt) {
+      const int32_t k = xcol[e0 + lane];
+      s_a[lane] = xval[e0 + lane];
+      s_b[lane] = yrp[k];
+      s_e[lane] = yrp[k + 1];
     }
     __syncthreads();
+    // steps (g, chunk) in order; the loads of the next step are issued before the adds
+    int32_t g = 0, q0 = s_b[0];
+    int32_t jn = -1;
+    double vn = 0.0;
+    if (q0 + lane < s_e[0]) {
+      jn = ycol[q0 + lane];
+      vn = yval[q0 + lane];
+    }
+    while (g < cnt) {
+      const int32_t j = jn;
+      const double v = vn;
+      const double a = s_a[g];
+      int32_t g2 = g, q2 = q0 + 64;
+      if (q2 >= s_e[g2]) {
+        ++g2;
+        q2 = (g2 < cnt) ? s_b[g2] : 0;
+      }
+      jn = -1;
+      if (g2 < cnt && q2 + lane < s_e[g2]) {
+        jn = ycol[q2 + lane];
+        vn = yval[q2 + lane];
+      }
+      if (j >= 0) lds_add(acc, bits, j, a * v);
+      if (g2 != g) __syncthreads();  // (one wavefront) orders row g's adds before row g2's
+      g = g2;
+      q0 = q2;
+    }
   }
+  __syncthreads();
   const int64_t base = poff[i];
   int32_t w = 0;
   for (int32_t c0 = 0; c0 < ncols; c0 += 64) {
     const int32_t c = c0 + lane;
-    const bool f = c < ncols && flag[c] != 0;
+    const bool f = c < ncols && ((bits[c >> 5] >> (c & 31)) & 1u);
     const unsigned long long bm = __ballot(f);
     if (f) {
       const int32_t pos = w + __popcll(bm & ((1ull << lane) - 1ull));
@@ -502,6 +540,35 @@ __global__ __launch_bounds__(64) void k_esc_lds(const int32_t *rows, int32_t nro
     w += __popcll(bm);
   }
   if (lane == 0) ucnt[i] = w;
+}
+
+// Largest output width the LDS bin takes on this device: the opt-in LDS per workgroup less
+// the kernel's static LDS, at 8 bytes plus one bit per column (queried once per device).
+static int32_t lds_cols_max() {
+  static std::mutex mu;
+  static int32_t cache[64];
+  static bool done[64];
+  int dev = 0;
+  SA_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return 0;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!done[dev]) {
+    int optin = 0;
+    if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) !=
+            hipSuccess ||
+        optin <= 0)
+      optin = 64 << 10;
+    const int64_t avail = (int64_t)optin - 2048;  // the kernel's static LDS is 1 KB
+    int32_t cols = (int32_t)((avail * 8) / 65);     // 8 bytes + 1 bit per column
+    cols &= ~31;
+    if (cols > (64 << 10) / 9 &&
+        hipFuncSetAttribute((const void *)k_esc_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(((int64_t)cols * 65 + 7) / 8)) != hipSuccess)
+      cols = (((64 << 10) - 2048) * 8 / 65) & ~31;
+    cache[dev] = cols;
+    done[dev] = true;
+  }
+  return cache[dev];
 }
 
 // One thread per output entry: find the entry's row by binary search over C's row pointers
@@ -578,8 +645,8 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
                                                       ucnt);
     SA_LAUNCH_CHECK();
   }
-  if (hc[3] > 0 && Y.ncols <= kLdsCols) {
-    const size_t lds = (size_t)Y.ncols * (sizeof(double) + 1);
+  if (hc[3] > 0 && Y.ncols <= lds_cols_max()) {
+    const size_t lds = (size_t)Y.ncols * sizeof(double) + (size_t)((Y.ncols + 31) / 32) * 4;
     k_esc_lds<<<(unsigned)hc[3], 64, lds, s>>>(l3, hc[3], X.rp, X.col, X.val, Y.rp, Y.col, Y.val,
                                               Y.ncols, poff, ocol, oval, ucnt);
     SA_LAUNCH_CHECK();
