@@ -102,6 +102,13 @@ def test_gmres_edges_and_errors():
     ref = h.solve_gmres(b, restart=3)
     assert st == "SA_NOT_CONVERGED" and it == 7 and not ref["converged"]
     assert np.linalg.norm(x.cpu().numpy() - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
+    # no iterations allowed: x = 0, not converged, on both sides
+    g0, h0 = run_both(p, **dict(kw, max_iter=0))
+    x, it, rr, st = g0.solve_gmres(b, restart=3)
+    r0 = h0.solve_gmres(b, restart=3)
+    assert it == 0 == r0["iterations"] and st == "SA_NOT_CONVERGED" and not r0["converged"]
+    assert float(x.abs().max()) == 0.0 and np.all(r0["x"] == 0.0)
+    g0.close()
     # zero right-hand side
     x, it, rr, st = g.solve_gmres(np.zeros(p.n), restart=3)
     assert st == "SA_OK" and it == 0 and float(x.abs().max()) == 0.0

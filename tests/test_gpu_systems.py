@@ -149,3 +149,26 @@ def test_elastic_beam_full_size():
     log(f"[systems] beam 96x24x24: levels {g.info()['n']}, {it} its, setup "
         f"{g.info()['setup_seconds'] * 1e3:.1f} ms")
     g.close()
+
+
+def test_grouped_solve_over_systems_and_scalar_hierarchies():
+    """sa_solve_many over a systems hierarchy, a scalar one and a distance-strength one gives
+    each system's sa_solve result bit for bit."""
+    from paper_2103_10476_amd import solver
+    import torch
+    p, X, B = _beam(16, 5, 5)
+    q = pb.fd7_stretched(20, 1000.0)
+    hs = [solver.Hierarchy.from_problem(p, nullspace=B, block_size=3,
+                                        options=solver.Options(max_coarse=100, rtol=1e-10)),
+          solver.Hierarchy.from_problem(q, options=solver.Options(max_coarse=60, rtol=1e-10)),
+          solver.Hierarchy.from_problem(q, coords=pb.fd7_coords(20, 1000.0),
+                                        options=solver.Options(max_coarse=60, rtol=1e-10,
+                                                               precision="fp32"))]
+    bs = [pb.random_rhs(p.n, 1), pb.random_rhs(q.n, 2), pb.random_rhs(q.n, 3)]
+    alone = [h.solve(b) for h, b in zip(hs, bs)]
+    grouped = solver.solve_many(hs, bs)
+    for (xa, ia, ra, sa_), (xg, ig, rg, sg) in zip(alone, grouped):
+        assert ia == ig and ra == rg and sa_ == sg
+        assert torch.equal(xa, xg)
+    for h in hs:
+        h.close()
