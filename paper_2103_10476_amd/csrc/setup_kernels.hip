@@ -467,10 +467,24 @@ __global__ void k_mis_pass1(int32_t n, const int32_t *grp, const int32_t *gcol, 
     if (!act[i]) return;
     K m = key[i];
     bool und = (m & KeyT<K>::Mask) == KeyT<K>::Und;
-    for (int32_t k = grp[i]; k < grp[i + 1]; ++k) {
-      const K ku = key[gcol[k]];
-      m = ku < m ? ku : m;
-      und |= (ku & KeyT<K>::Mask) == KeyT<K>::Und;
+    // neighbours 8 at a time: all indices, then all keys, as independent loads (v itself
+    // past the end of the list, harmless in the minimum)
+    const int32_t b = grp[i], e = grp[i + 1];
+    for (int32_t k = b; k < e; k += 8) {
+      int32_t c[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int32_t g = gcol[min(k + q, e - 1)];  // in bounds even if loaded eagerly
+        c[q] = (k + q < e) ? g : i;
+      }
+      K kv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) kv[q] = key[c[q]];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        m = kv[q] < m ? kv[q] : m;
+        und |= (kv[q] & KeyT<K>::Mask) == KeyT<K>::Und;
+      }
     }
     k1[i] = m;
     if (!und) act[i] = 0;
@@ -508,9 +522,19 @@ __global__ void k_mis_pass2(int32_t n, const int32_t *grp, const int32_t *gcol, 
     const K me = key[i];
     if ((me & KeyT<K>::Mask) != KeyT<K>::Und) return;
     K m = k1[i];
-    for (int32_t k = grp[i]; k < grp[i + 1]; ++k) {
-      const K ku = k1[gcol[k]];
-      m = ku < m ? ku : m;
+    const int32_t b = grp[i], e = grp[i + 1];
+    for (int32_t k = b; k < e; k += 8) {
+      int32_t c[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int32_t g = gcol[min(k + q, e - 1)];  // in bounds even if loaded eagerly
+        c[q] = (k + q < e) ? g : i;
+      }
+      K kv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) kv[q] = k1[c[q]];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) m = kv[q] < m ? kv[q] : m;
     }
     const K pri = me & ~KeyT<K>::Mask;
     if ((m & KeyT<K>::Mask) == KeyT<K>::In) key[i] = KeyT<K>::Out | pri;
@@ -1292,9 +1316,35 @@ void damping(double *lam, double *omega, bool unit, int32_t *err, hipStream_t s)
 // ---- prolongator smoothing (Sec. 1.1) -------------------------------------------------------
 // Row i: for each aggregate J reached by the filtered row (ascending J), acc = sum of the
 // entries with agg(k) = J in ascending k from 0; P_iJ = [J == agg_i] - (omega invD_i) acc.
+// Rows of at most kPRegs entries keep their aggregates (and values) in registers, loaded as
+// independent loads up front; longer rows re-read them per distinct aggregate.
+constexpr int kPRegs = 16;
 __global__ void k_P_count(int32_t n, const int32_t *rp, const int32_t *col, const int32_t *agg,
                           int32_t *cnt) {
   SA_ROW_KERNEL_BEGIN(n)
+  const int32_t b = rp[i], e = rp[i + 1];
+  if (e <= b) {
+    cnt[i] = 0;
+    return;
+  }
+  if (e - b <= kPRegs) {
+    int32_t a[kPRegs];
+#pragma unroll
+    for (int q = 0; q < kPRegs; ++q) a[q] = (b + q < e) ? col[min(b + q, e - 1)] : -1;
+#pragma unroll
+    for (int q = 0; q < kPRegs; ++q) a[q] = (a[q] >= 0) ? agg[a[q]] : -1;
+    // distinct aggregates = entries whose aggregate does not occur earlier in the row
+    int32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < kPRegs; ++q) {
+      bool first = a[q] >= 0;
+#pragma unroll
+      for (int r = 0; r < q; ++r) first = first && (a[r] != a[q]);
+      c += first;
+    }
+    cnt[i] = c;
+    return;
+  }
   int32_t prev = -1, c = 0;
   for (;;) {
     int32_t J = INT_MAX;
@@ -1314,6 +1364,38 @@ __global__ void k_P_fill(int32_t n, const int32_t *rp, const int32_t *col, const
   SA_ROW_KERNEL_BEGIN(n)
   const double t = (*omega) * invD[i];
   const int32_t ai = agg[i];
+  const int32_t rb = rp[i], re = rp[i + 1];
+  if (re <= rb) return;  // an empty row has no prolongator entries
+  if (re - rb <= kPRegs) {
+    int32_t a[kPRegs];
+    double v[kPRegs];
+#pragma unroll
+    for (int q = 0; q < kPRegs; ++q) {
+      const int32_t k = min(rb + q, re - 1);
+      a[q] = (rb + q < re) ? col[k] : -1;
+      v[q] = (rb + q < re) ? val[k] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kPRegs; ++q) a[q] = (a[q] >= 0) ? agg[a[q]] : -1;
+    // aggregates in ascending order; each sums its entries in ascending position from 0
+    int32_t prev = -1, w = prp[i];
+    for (;;) {
+      int32_t J = INT_MAX;
+#pragma unroll
+      for (int q = 0; q < kPRegs; ++q)
+        if (a[q] > prev && a[q] < J) J = a[q];
+      if (J == INT_MAX) break;
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < kPRegs; ++q)
+        if (a[q] == J) acc += v[q];
+      pcol[w] = J;
+      pval[w] = ((J == ai) ? 1.0 : 0.0) - t * acc;
+      ++w;
+      prev = J;
+    }
+    return;
+  }
   int32_t prev = -1, w = prp[i];
   for (;;) {
     int32_t J = INT_MAX;
