@@ -87,6 +87,8 @@ __global__ __launch_bounds__(kWave) void k_esc_wave(
   __shared__ double vals[kWave];
   __shared__ int32_t skeys[kWave];
   __shared__ double svals[kWave];
+  __shared__ int32_t s_incl[kWave], s_ys[kWave];
+  __shared__ double s_a[kWave];
   const int lane = threadIdx.x;
   if ((int32_t)blockIdx.x >= nrows) return;  // block-uniform
   const int32_t i = rows[blockIdx.x];
@@ -110,13 +112,25 @@ __global__ __launch_bounds__(kWave) void k_esc_wave(
       const int32_t v = __shfl_up(incl, off, kWave);
       if (lane >= off) incl += v;
     }
-    const int32_t excl = incl - len;
     const int32_t tot = __shfl(incl, kWave - 1, kWave);
-    for (int32_t t = 0; t < len; ++t) {
-      const int32_t p = filled + excl + t;
-      keys[p] = ycol[ys + t];
-      vals[p] = a * yval[ys + t];
+    s_incl[lane] = incl;
+    s_ys[lane] = ys;
+    s_a[lane] = a;
+    __syncthreads();
+    // product p of this chunk comes from the first entry s with incl[s] > p, at offset
+    // p - incl[s-1] in its row of Y: one product per lane, loads independent across lanes
+    for (int32_t p = lane; p < tot; p += kWave) {
+      int32_t lo = 0, hi = kWave - 1;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (s_incl[mid] > p) hi = mid;
+        else lo = mid + 1;
+      }
+      const int32_t t = p - (lo > 0 ? s_incl[lo - 1] : 0);
+      keys[filled + p] = ycol[s_ys[lo] + t];
+      vals[filled + p] = s_a[lo] * yval[s_ys[lo] + t];
     }
+    __syncthreads();
     filled += tot;
   }
   __syncthreads();
