@@ -1524,7 +1524,8 @@ void scale_sym(int32_t n, const int32_t *rp, const int32_t *col, const double *v
 
 
 // ---- per-row sort by column --------------------------------------------------------------
-// Rows of up to kSortShort entries: insertion sort by one thread.  Longer rows: one block per
+// Rows of up to kSortShort entries: a register sorting network in one thread (the keys of a
+// row are distinct in every caller).  Longer rows: one block per
 // row, bitonic sort in LDS (kSortLds entries) or, beyond that, in a global scratch region
 // sized for the row.  Keys within a row are distinct, so the order is unique.
 constexpr int32_t kSortShort = 32;
@@ -1541,6 +1542,44 @@ __device__ inline void wave_append(bool pred, int32_t *counter, int32_t *list, i
   if (pred) list[base + __popcll(m & ((1ull << lane) - 1ull))] = value;
 }
 
+// Sorts L <= N (key, value) pairs with distinct keys in registers: a bitonic network of width
+// N over the pairs padded with INT_MAX keys, all indices static so nothing leaves registers.
+template <int N>
+__device__ __forceinline__ void sort_regs(int32_t *c, double *v, int32_t L) {
+  int32_t kk[N];
+  double vv[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    kk[q] = q < L ? c[q] : INT_MAX;
+    vv[q] = (v && q < L) ? v[q] : 0.0;
+  }
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        const int l = q ^ j;
+        if (l > q) {
+          const bool up = (q & k) == 0;
+          if ((kk[q] > kk[l]) == up) {
+            const int32_t tk = kk[q];
+            kk[q] = kk[l];
+            kk[l] = tk;
+            const double tv = vv[q];
+            vv[q] = vv[l];
+            vv[l] = tv;
+          }
+        }
+      }
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+    if (q < L) {
+      c[q] = kk[q];
+      if (v) v[q] = vv[q];
+    }
+}
+
 __global__ void k_sort_short(int32_t n, const int32_t *rp, int32_t *c, double *v,
                              int32_t *nlong, int32_t *longrows) {
   const int64_t i64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1550,18 +1589,11 @@ __global__ void k_sort_short(int32_t n, const int32_t *rp, int32_t *c, double *v
   const bool is_long = live && (e - b > kSortShort);
   wave_append(is_long, nlong, longrows, i);
   if (!live || is_long) return;
-  for (int32_t k = b + 1; k < e; ++k) {
-    const int32_t ck = c[k];
-    const double vk = v ? v[k] : 0.0;
-    int32_t q = k - 1;
-    while (q >= b && c[q] > ck) {
-      c[q + 1] = c[q];
-      if (v) v[q + 1] = v[q];
-      --q;
-    }
-    c[q + 1] = ck;
-    if (v) v[q + 1] = vk;
-  }
+  const int32_t L = e - b;
+  if (L <= 1) return;
+  if (L <= 8) sort_regs<8>(c + b, v ? v + b : nullptr, L);
+  else if (L <= 16) sort_regs<16>(c + b, v ? v + b : nullptr, L);
+  else sort_regs<32>(c + b, v ? v + b : nullptr, L);
 }
 
 __device__ inline void bitonic_kv_any(int32_t *k, double *v, int32_t L) {
