@@ -156,10 +156,10 @@ static void numeric_level(sa_hierarchy *h, int l, bool fresh) {
     return;
   }
   if (fresh) {
-    prolongator(L.Abar, L.invD, L.agg, L.nc, L.omega_d, ar, L.P, s);
+    prolongator(L.Abar, L.invD, L.agg, L.nc, L.omega_d, ar, L.P, s, L.wave_rows);
   } else {
     Csr P;
-    prolongator(L.Abar, L.invD, L.agg, L.nc, L.omega_d, tmp, P, s);
+    prolongator(L.Abar, L.invD, L.agg, L.nc, L.omega_d, tmp, P, s, L.wave_rows);
     take_values(P, L.P, s);
   }
   if (o.variants & SA_CNSTRNT) cnstrnt(L.P, L.agg, s);

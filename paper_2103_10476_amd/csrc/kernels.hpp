@@ -189,9 +189,11 @@ void power_method(const Csr &M, const double *invD, int32_t iters, uint64_t seed
                   int32_t level, int32_t stream_id, double *lam, hipStream_t s);
 // omega = 4/(3 lambda) (or lambda = 1 first when `unit`), err bit 16 if lambda <= 0.
 void damping(double *lam, double *omega, bool unit, int32_t *err, hipStream_t s);
-// P = (I - omega invD Abar) Ptent; returns nnz(P).
+// P = (I - omega invD Abar) Ptent; returns nnz(P).  long_rows: the per-aggregate sums come
+// from a SpGEMM with the 0/1 aggregate matrix (the same sums in the same order).
 int64_t prolongator(const Csr &abar, const double *invD, const int32_t *agg, int32_t nc,
-                    const double *omega, Arena &ar, Csr &P, hipStream_t s);
+                    const double *omega, Arena &ar, Csr &P, hipStream_t s,
+                    bool long_rows = false);
 void cnstrnt(const Csr &P, const int32_t *agg, hipStream_t s);
 void scale_rows(const Csr &P, const double *B, hipStream_t s);
 // R = P^T with ascending columns per row.

@@ -1413,9 +1413,55 @@ __global__ void k_P_fill(int32_t n, const int32_t *rp, const int32_t *col, const
     prev = J;
   }
 }
+// Long rows (the dense coarse levels): the per-aggregate sums of a row of Abar are the row of
+// Abar T, T the 0/1 aggregate matrix (T_kJ = 1 iff agg_k = J): every product is A_ik * 1 =
+// A_ik exactly and the SpGEMM adds them in ascending k from 0, the order of k_P_fill.  Then
+// P_iJ = [J = agg_i] - t_i (Abar T)_iJ in place.
+__global__ void k_agg_matrix(int32_t n, const int32_t *agg, const int32_t *trp, int32_t *tcol,
+                             double *tval) {
+  SA_ROW_KERNEL_BEGIN(n)
+  if (agg[i] >= 0) {
+    tcol[trp[i]] = agg[i];
+    tval[trp[i]] = 1.0;
+  }
+}
+__global__ void k_flag_aggregated(int32_t n, const int32_t *agg, int32_t *f) {
+  SA_ROW_KERNEL_BEGIN(n)
+  f[i] = agg[i] >= 0 ? 1 : 0;
+}
+__global__ void k_P_from_sums(int32_t n, const int32_t *prp, const int32_t *pcol, double *pval,
+                              const double *invD, const int32_t *agg, const double *omega) {
+  SA_ROW_KERNEL_BEGIN(n)
+  const double t = (*omega) * invD[i];
+  const int32_t ai = agg[i];
+  for (int32_t e = prp[i]; e < prp[i + 1]; ++e)
+    pval[e] = ((pcol[e] == ai) ? 1.0 : 0.0) - t * pval[e];
+}
+
 int64_t prolongator(const Csr &abar, const double *invD, const int32_t *agg, int32_t nc,
-                    const double *omega, Arena &ar, Csr &P, hipStream_t s) {
+                    const double *omega, Arena &ar, Csr &P, hipStream_t s, bool long_rows) {
   const int32_t n = abar.n;
+  if (long_rows && n > 0) {
+    Arena tmp;
+    tmp.stream = s;
+    int32_t *f = tmp.alloc<int32_t>(n + 1);
+    k_flag_aggregated<<<grid_for(n), kBlock, 0, s>>>(n, agg, f);
+    SA_LAUNCH_CHECK();
+    Csr T;
+    T.n = n;
+    T.ncols = nc;
+    T.rp = tmp.alloc<int32_t>(n + 1);
+    exclusive_scan_i32(f, T.rp, n, s);
+    T.nnz = read1(T.rp + n, s);
+    T.col = tmp.alloc<int32_t>(T.nnz > 0 ? T.nnz : 1);
+    T.val = tmp.alloc<double>(T.nnz > 0 ? T.nnz : 1);
+    k_agg_matrix<<<grid_for(n), kBlock, 0, s>>>(n, agg, T.rp, T.col, T.val);
+    SA_LAUNCH_CHECK();
+    spgemm(abar, T, ar, P, s);
+    k_P_from_sums<<<grid_for(n), kBlock, 0, s>>>(n, P.rp, P.col, P.val, invD, agg, omega);
+    SA_LAUNCH_CHECK();
+    return P.nnz;
+  }
   int32_t *cnt = (int32_t *)dev_alloc(sizeof(int32_t) * (n + 1), s);
   k_P_count<<<grid_for(n), kBlock, 0, s>>>(n, abar.rp, abar.col, agg, cnt);
   SA_LAUNCH_CHECK();
