@@ -111,11 +111,14 @@ void find_diag(int32_t n, const int32_t *rp, const int32_t *col, const double *v
 }
 
 // ---- strength (Sec. 1.1 criterion, evaluated squared) ----------------------------------
-__global__ void k_strength(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
-                           const double *dval, double th2, uint8_t *mask, int32_t *scount) {
+__global__ void k_strength(int32_t n, const int32_t *__restrict__ rp,
+                           const int32_t *__restrict__ col, const double *__restrict__ val,
+                           const double *__restrict__ dval, double th2,
+                           uint8_t *__restrict__ mask, int32_t *__restrict__ scount) {
   SA_ROW_KERNEL_BEGIN(n)
   const double di = dval[i];
   int32_t cnt = 0;
+#pragma unroll 8
   for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
     const int32_t j = col[k];
     if (j == i) {
@@ -937,23 +940,30 @@ void sprsfy(int32_t n, const int32_t *rp, const int32_t *col, uint8_t *mask, con
 }
 
 // ---- filtered matrix (Sec. 1.1 plain lumping; Sec. 2.3 Algorithm 2) and its diagonal -----
-__global__ void k_lump_count(int32_t n, const int32_t *rp, const int32_t *col,
-                             const uint8_t *mask, int32_t *cnt) {
+__global__ void k_lump_count(int32_t n, const int32_t *__restrict__ rp,
+                             const int32_t *__restrict__ col, const uint8_t *__restrict__ mask,
+                             int32_t *__restrict__ cnt) {
   SA_ROW_KERNEL_BEGIN(n)
   int32_t c = 0;
+#pragma unroll 8
   for (int32_t k = rp[i]; k < rp[i + 1]; ++k) c += (col[k] == i || mask[k] == 1);
   cnt[i] = c;
 }
 
-__global__ void k_lump_fill(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
-                            const uint8_t *mask, const int32_t *arp, int32_t *acol,
-                            double *aval, bool offlmp, double tau, bool one_norm, double mult,
-                            double *invD, int32_t *err) {
+// (restrict: the filtered matrix never overlaps its inputs, so the row's loads can be issued
+// ahead of the stores)
+__global__ void k_lump_fill(int32_t n, const int32_t *__restrict__ rp,
+                            const int32_t *__restrict__ col, const double *__restrict__ val,
+                            const uint8_t *__restrict__ mask, const int32_t *__restrict__ arp,
+                            int32_t *__restrict__ acol, double *__restrict__ aval, bool offlmp,
+                            double tau, bool one_norm, double mult, double *__restrict__ invD,
+                            int32_t *__restrict__ err) {
   SA_ROW_KERNEL_BEGIN(n)
   const int32_t b = rp[i], e = rp[i + 1];
   const int32_t o = arp[i];
   int32_t w = o, ds = o;
   double aii = 0.0, r = 0.0;
+#pragma unroll 8
   for (int32_t k = b; k < e; ++k) {
     const int32_t j = col[k];
     if (j == i) {
