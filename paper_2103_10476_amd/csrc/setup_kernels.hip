@@ -400,11 +400,17 @@ int64_t strength_graph(int32_t n, const int32_t *rp, const int32_t *col, const u
 // own key (it has the best priority among undecided vertices within distance 2).  This
 // reproduces the sequential greedy root choice in priority order exactly.
 //
-// Each round touches only open work: a vertex is "active" while it or a neighbour is
-// undecided (once inactive it stays inactive, so pass 1 skips it after a 1-byte read) and pass
-// 2 skips decided vertices.  Natural order uses 32-bit keys (state << 30 | index); hashed
-// order 64-bit keys (state << 62 | hash30 << 32 | index).  Levels with high average degree
-// use one wavefront per vertex.
+// Rounds are event driven: k1(u) is recomputed only in a round after some key in N[u]
+// changed, and an undecided v re-takes its decision only in a round in which some k1 in N[v]
+// changed; any other vertex would compute the value (or the "wait") it already holds, so the
+// selection is the same as re-evaluating every vertex every round.  The triggers are 1-byte
+// round stamps (round number mod 256): pass 2 stamps N[v] u {v} for pass 1 of the next round
+// when v's key changes, pass 1 stamps N[u] u {u} for pass 2 of the same round when k1(u)
+// changes.  A stale stamp that matches after wrap-around only costs a needless re-evaluation.
+// Round 0 evaluates everything (all stamps start at 0).  A round that changes no key ends
+// the selection: nothing can change after it.  Natural order uses 32-bit keys
+// (state << 30 | index); hashed order 64-bit keys (state << 62 | hash30 << 32 | index).
+// Levels with high average degree use one wavefront per vertex.
 template <class K>
 struct KeyT;
 template <>
@@ -428,7 +434,7 @@ __device__ inline uint64_t stream_key_dev(int stream, int level, int64_t i) {
 
 template <class K>
 __global__ void k_mis_init(int32_t n, const int32_t *grp, int32_t order, uint64_t seed,
-                           int32_t level, K *key, uint8_t *act) {
+                           int32_t level, K *key, uint8_t *st1, uint8_t *st2) {
   SA_ROW_KERNEL_BEGIN(n)
   K pri = (K)i;
   if (order == 1)
@@ -436,40 +442,59 @@ __global__ void k_mis_init(int32_t n, const int32_t *grp, int32_t order, uint64_
               (uint64_t)i);
   const bool open = grp[i + 1] > grp[i];
   key[i] = (open ? KeyT<K>::Und : KeyT<K>::Out) | pri;
-  act[i] = open ? 1 : 0;
+  st1[i] = 0;
+  st2[i] = 0;
 }
 
+// Stamps i and every vertex of gcol[b..e) with s: 8 independent index loads, then 8 stores
+// (the last index repeated past the end: the same byte stored again).
+__device__ inline void stamp_ball(const int32_t *__restrict__ gcol, int32_t b, int32_t e,
+                                  int32_t i, uint8_t *__restrict__ st, uint8_t s) {
+  st[i] = s;
+  for (int32_t k = b; k < e; k += 8) {
+    int32_t c[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) c[q] = gcol[min(k + q, e - 1)];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) st[c[q]] = s;
+  }
+}
+
+// Pass 1 of round r (stamp sr): k1(u) = min key over N[u] for stamped u.
 template <class K, bool WAVE>
-__global__ void k_mis_pass1(int32_t n, const int32_t *grp, const int32_t *gcol, const K *key,
-                            K *k1, uint8_t *act, const int32_t *prev) {
-  if (prev && *prev == 0) return;  // the previous round left nothing undecided
+__global__ void k_mis_pass1(int32_t n, const int32_t *__restrict__ grp,
+                            const int32_t *__restrict__ gcol, const K *__restrict__ key,
+                            K *__restrict__ k1, const uint8_t *__restrict__ st1,
+                            uint8_t *__restrict__ st2, uint8_t sr, bool first,
+                            const int32_t *__restrict__ prev) {
+  if (prev && *prev == 0) return;  // the previous round changed nothing
   if (WAVE) {
     const int lane = threadIdx.x & 63;
     const int64_t v64 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (v64 >= n) return;
     const int32_t v = (int32_t)v64;
-    if (!act[v]) return;  // wave-uniform
+    if (st1[v] != sr) return;  // wave-uniform
+    const int32_t b = grp[v], e = grp[v + 1];
     K m = (lane == 0) ? key[v] : ~(K)0;
-    bool und = (lane == 0) && ((key[v] & KeyT<K>::Mask) == KeyT<K>::Und);
-    for (int32_t k = grp[v] + lane; k < grp[v + 1]; k += 64) {
+    for (int32_t k = b + lane; k < e; k += 64) {
       const K ku = key[gcol[k]];
       m = ku < m ? ku : m;
-      und |= (ku & KeyT<K>::Mask) == KeyT<K>::Und;
     }
     for (int off = 32; off >= 1; off >>= 1) {
       const K o = __shfl_xor(m, off, 64);
       m = o < m ? o : m;
     }
-    const bool anyund = __ballot(und) != 0;
-    if (lane == 0) {
-      k1[v] = m;
-      if (!anyund) act[v] = 0;
+    const K old = first ? m : k1[v];  // read by every lane before lane 0 stores
+    if (lane == 0) k1[v] = m;
+    if (!first && m != old) {
+      for (int32_t k = b + lane; k < e; k += 64) st2[gcol[k]] = sr;
+      if (lane == 0) st2[v] = sr;
     }
   } else {
     SA_ROW_KERNEL_BEGIN(n)
-    if (!act[i]) return;
+    if (st1[i] != sr) return;
     K m = key[i];
-    bool und = (m & KeyT<K>::Mask) == KeyT<K>::Und;
+    const K old = first ? m : k1[i];
     // neighbours 8 at a time: all indices, then all keys, as independent loads (v itself
     // past the end of the list, harmless in the minimum)
     const int32_t b = grp[i], e = grp[i + 1];
@@ -484,29 +509,34 @@ __global__ void k_mis_pass1(int32_t n, const int32_t *grp, const int32_t *gcol, 
 #pragma unroll
       for (int q = 0; q < 8; ++q) kv[q] = key[c[q]];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        m = kv[q] < m ? kv[q] : m;
-        und |= (kv[q] & KeyT<K>::Mask) == KeyT<K>::Und;
-      }
+      for (int q = 0; q < 8; ++q) m = kv[q] < m ? kv[q] : m;
     }
+    if (!first && m != old) stamp_ball(gcol, b, e, i, st2, sr);
     k1[i] = m;
-    if (!und) act[i] = 0;
   }
 }
 
+// Pass 2 of round r: stamped undecided v takes m = min k1 over N[v]; an IN key there makes v
+// OUT, its own key makes it IN.  A change stamps N[v] u {v} with the next round's stamp srn
+// and raises the round's flag.
 template <class K, bool WAVE>
-__global__ void k_mis_pass2(int32_t n, const int32_t *grp, const int32_t *gcol, const K *k1,
-                            K *key, int32_t *flag, const int32_t *prev) {
+__global__ void k_mis_pass2(int32_t n, const int32_t *__restrict__ grp,
+                            const int32_t *__restrict__ gcol, const K *__restrict__ k1,
+                            K *__restrict__ key, const uint8_t *__restrict__ st2,
+                            uint8_t *__restrict__ st1, uint8_t sr, uint8_t srn,
+                            int32_t *__restrict__ flag, const int32_t *__restrict__ prev) {
   if (prev && *prev == 0) return;
   if (WAVE) {
     const int lane = threadIdx.x & 63;
     const int64_t v64 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (v64 >= n) return;
     const int32_t v = (int32_t)v64;
+    if (st2[v] != sr) return;  // wave-uniform
     const K me = key[v];
     if ((me & KeyT<K>::Mask) != KeyT<K>::Und) return;  // wave-uniform
+    const int32_t b = grp[v], e = grp[v + 1];
     K m = (lane == 0) ? k1[v] : ~(K)0;
-    for (int32_t k = grp[v] + lane; k < grp[v + 1]; k += 64) {
+    for (int32_t k = b + lane; k < e; k += 64) {
       const K ku = k1[gcol[k]];
       m = ku < m ? ku : m;
     }
@@ -514,14 +544,21 @@ __global__ void k_mis_pass2(int32_t n, const int32_t *grp, const int32_t *gcol, 
       const K o = __shfl_xor(m, off, 64);
       m = o < m ? o : m;
     }
-    if (lane == 0) {
-      const K pri = me & ~KeyT<K>::Mask;
-      if ((m & KeyT<K>::Mask) == KeyT<K>::In) key[v] = KeyT<K>::Out | pri;
-      else if (m == me) key[v] = KeyT<K>::In | pri;
-      else *flag = 1;
+    const K pri = me & ~KeyT<K>::Mask;
+    K nk = me;
+    if ((m & KeyT<K>::Mask) == KeyT<K>::In) nk = KeyT<K>::Out | pri;
+    else if (m == me) nk = KeyT<K>::In | pri;
+    if (nk != me) {  // wave-uniform
+      for (int32_t k = b + lane; k < e; k += 64) st1[gcol[k]] = srn;
+      if (lane == 0) {
+        key[v] = nk;
+        st1[v] = srn;
+        *flag = 1;
+      }
     }
   } else {
     SA_ROW_KERNEL_BEGIN(n)
+    if (st2[i] != sr) return;
     const K me = key[i];
     if ((me & KeyT<K>::Mask) != KeyT<K>::Und) return;
     K m = k1[i];
@@ -540,9 +577,14 @@ __global__ void k_mis_pass2(int32_t n, const int32_t *grp, const int32_t *gcol, 
       for (int q = 0; q < 8; ++q) m = kv[q] < m ? kv[q] : m;
     }
     const K pri = me & ~KeyT<K>::Mask;
-    if ((m & KeyT<K>::Mask) == KeyT<K>::In) key[i] = KeyT<K>::Out | pri;
-    else if (m == me) key[i] = KeyT<K>::In | pri;
-    else *flag = 1;
+    K nk = me;
+    if ((m & KeyT<K>::Mask) == KeyT<K>::In) nk = KeyT<K>::Out | pri;
+    else if (m == me) nk = KeyT<K>::In | pri;
+    if (nk != me) {
+      key[i] = nk;
+      stamp_ball(gcol, b, e, i, st1, srn);
+      *flag = 1;
+    }
   }
 }
 
@@ -642,15 +684,16 @@ static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const
   tmp.stream = s;
   K *key = tmp.alloc<K>(n);
   K *k1 = tmp.alloc<K>(n);
-  uint8_t *act = tmp.alloc<uint8_t>(n);
-  k_mis_init<K><<<grid_for(n), kBlock, 0, s>>>(n, grp, order, seed, level, key, act);
+  uint8_t *st1 = tmp.alloc<uint8_t>(n);
+  uint8_t *st2 = tmp.alloc<uint8_t>(n);
+  k_mis_init<K><<<grid_for(n), kBlock, 0, s>>>(n, grp, order, seed, level, key, st1, st2);
   SA_LAUNCH_CHECK();
-  // Rounds run in batches between flag checks: flags[q] = 1 iff some vertex was still
-  // undecided after round q of the batch.  A round whose predecessor left nothing undecided
-  // exits at once, so rounds past the end of the selection cost only their launch; batches
-  // grow 16, 32, 64, 64, ... to bound both the readbacks and that overshoot.
+  // Rounds run in batches between flag checks: flags[q] = 1 iff round q of the batch changed
+  // some key.  A round whose predecessor changed nothing exits at once, so rounds past the
+  // end of the selection cost only their launch; batches grow 16, 32, 64, 64, ... to bound
+  // both the readbacks and that overshoot.
   constexpr int kMaxBatch = 64;
-  // every round decides at least one vertex, so this bound is never reached
+  // every round before the last decides at least one vertex, so this bound is never reached
   const int64_t cap = (int64_t)n + 2 + 2 * kMaxBatch;
   int32_t *flags = tmp.alloc<int32_t>(kMaxBatch);
   const int32_t maxdeg = max_row_length(n, grp, s);
@@ -666,19 +709,25 @@ static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const
     fill_i32(flags, 0, batch, s);
     for (int q = 0; q < batch; ++q) {
       const int32_t *prev = q > 0 ? flags + q - 1 : nullptr;
+      const uint8_t sr = (uint8_t)((r + q) & 255), srn = (uint8_t)((r + q + 1) & 255);
+      const bool first = r + q == 0;
       if (wave) {
-        k_mis_pass1<K, true><<<g, kBlock, 0, s>>>(n, grp, gcol, key, k1, act, prev);
-        k_mis_pass2<K, true><<<g, kBlock, 0, s>>>(n, grp, gcol, k1, key, flags + q, prev);
+        k_mis_pass1<K, true><<<g, kBlock, 0, s>>>(n, grp, gcol, key, k1, st1, st2, sr, first,
+                                                   prev);
+        k_mis_pass2<K, true><<<g, kBlock, 0, s>>>(n, grp, gcol, k1, key, st2, st1, sr, srn,
+                                                   flags + q, prev);
       } else {
-        k_mis_pass1<K, false><<<g, kBlock, 0, s>>>(n, grp, gcol, key, k1, act, prev);
-        k_mis_pass2<K, false><<<g, kBlock, 0, s>>>(n, grp, gcol, k1, key, flags + q, prev);
+        k_mis_pass1<K, false><<<g, kBlock, 0, s>>>(n, grp, gcol, key, k1, st1, st2, sr, first,
+                                                    prev);
+        k_mis_pass2<K, false><<<g, kBlock, 0, s>>>(n, grp, gcol, k1, key, st2, st1, sr, srn,
+                                                    flags + q, prev);
       }
     }
     SA_LAUNCH_CHECK();
     readback(hflags, flags, sizeof(int32_t) * batch, s);
     for (int q = 0; q < batch; ++q)
-      if (hflags[q] == 0) {
-        used = (int32_t)(r + q + 1);
+      if (hflags[q] == 0) {  // round r+q changed nothing: r+q rounds made the selection
+        used = (int32_t)(r + q);
         done = true;
         break;
       }
