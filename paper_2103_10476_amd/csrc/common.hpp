@@ -105,6 +105,19 @@ struct Csr {
   int32_t nblk = 0;
 };
 
+// Sliced-ELL copy of a CSR operator for the solve-phase SpMV.  Rows in slices of 64 (one per
+// wavefront); slice s is stored column-major from ptr[s] with width w_s = (ptr[s+1]-ptr[s])/64,
+// entry k of row 64 s + l at ptr[s] + 64 k + l, so the k-th entries of a slice's rows are
+// contiguous.  Rows keep their entry order (ascending columns); the w_s - len tail of a row
+// is padding with col -1 and value 0.
+struct Sell {
+  int32_t nslice = 0;
+  int32_t *ptr = nullptr;  // nslice+1 entry offsets (multiples of 64)
+  int32_t *col = nullptr;
+  double *val = nullptr;
+  float *valf = nullptr;   // FP32 values (FP32 V-cycle only)
+};
+
 struct CsrF {  // float copy of the values for the FP32 V-cycle
   int32_t n = 0, ncols = 0;
   int64_t nnz = 0;

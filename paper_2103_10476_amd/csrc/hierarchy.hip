@@ -370,6 +370,12 @@ static void finish_setup(sa_hierarchy *h, bool fresh) {
         cast_f64_to_f32(L.sm_invD, L.sm_invDf, m, s);
       }
     }
+    // the solve's SpMVs on A: every level but a coarsest one with more than one level (its
+    // dense solve takes no SpMV); level 0 also serves the Krylov method
+    if (l + 1 < nl || l == 0) {
+      if (fresh) sell_build(L.A, L.Aell, f32 && l + 1 < nl, h->ar, s);
+      else sell_values(L.A, L.Aell, s);
+    }
   }
   if (fresh) {
     h->x = h->ar.alloc<double>(n);
@@ -528,12 +534,15 @@ static void prof_begin(sa_hierarchy *h, int l) {
   SA_HIP(hipEventRecord(h->ev[h->nev], h->stream));
 }
 // `vec` = number of n-vectors the launch's epilogue and input read or write (x included).
+// Algorithmic bytes: the entries (index + value; sliced-ELL padding not counted), the row
+// structure the kernel reads (row pointers, or slice offsets) and the vectors.
 static void prof_end(sa_hierarchy *h, int l, int vec, int elem) {
   if (!h->prof || l != 0) return;
   SA_HIP(hipEventRecord(h->ev[h->nev + 1], h->stream));
   const Csr &A = h->lv[0].A;
-  h->ev_bytes[h->nev / 2] = (double)A.nnz * (4 + elem) + 4.0 * (A.n + 1) +
-                            (double)vec * elem * A.n;
+  const Sell &S = h->lv[0].Aell;
+  const double rows = S.ptr ? 4.0 * (S.nslice + 1) : 4.0 * (A.n + 1);
+  h->ev_bytes[h->nev / 2] = (double)A.nnz * (4 + elem) + rows + (double)vec * elem * A.n;
   h->nev += 2;
 }
 // After a synchronisation: fold the recorded pairs into the totals.
@@ -559,7 +568,7 @@ struct LevelView {
 
 static LevelView<double> view64(Level &L) {
   LevelView<double> v;
-  v.A = spmv_args<double>(L.A, L.A.val, nullptr);
+  v.A = with_sell(spmv_args<double>(L.A, L.A.val, nullptr), L.Aell, L.Aell.val);
   v.P = spmv_args<double>(L.P, L.P.val, nullptr);
   v.R = spmv_args<double>(L.R, L.R.val, nullptr);
   v.invD = L.sm_invD;
@@ -572,7 +581,7 @@ static LevelView<double> view64(Level &L) {
 }
 static LevelView<float> view32(Level &L) {
   LevelView<float> v;
-  v.A = spmv_args<float>(L.A, L.Af, nullptr);
+  v.A = with_sell(spmv_args<float>(L.A, L.Af, nullptr), L.Aell, (const float *)L.Aell.valf);
   v.P = spmv_args<float>(L.P, L.Pf, nullptr);
   v.R = spmv_args<float>(L.R, L.Rf, nullptr);
   v.invD = L.sm_invDf;
@@ -729,7 +738,9 @@ static sa_status solve_impl(sa_hierarchy *h, const double *b, double *x, sa_loca
   SA_HIP(hipMemcpyAsync(h->p, h->z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   dot_f64(h->r, h->z, n, &S->rho1, h->dws, s);
   pcg_init_rho(S, s);
-  SpmvArgs<double> A = spmv_args<double>(h->lv[0].A, h->lv[0].A.val, h->p);
+  SpmvArgs<double> A =
+      with_sell(spmv_args<double>(h->lv[0].A, h->lv[0].A.val, h->p), h->lv[0].Aell,
+                h->lv[0].Aell.val);
   for (int32_t k = 1; k <= o.max_iter; ++k) {
     prof_begin(h, 0);
     spmv_store<double>(A, h->q, s);
@@ -817,7 +828,9 @@ static sa_status gmres_impl(sa_hierarchy *h, const double *b, double *x, sa_loca
     return SA_OK;
   }
   const double target = o.rtol * bn;
-  SpmvArgs<double> A = spmv_args<double>(h->lv[0].A, h->lv[0].A.val, nullptr);
+  SpmvArgs<double> A =
+      with_sell(spmv_args<double>(h->lv[0].A, h->lv[0].A.val, nullptr), h->lv[0].Aell,
+                h->lv[0].Aell.val);
   double res = bn;
   int32_t total = 0;
   bool converged = false;

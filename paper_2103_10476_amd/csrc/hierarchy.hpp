@@ -37,6 +37,7 @@ struct Level {
   std::vector<double> cheb_c1, cheb_c2;  // per Chebyshev step m = 1..deg-1
   double jac_w = 0.0;
   double *Ainv = nullptr;  // coarsest only: dense inverse, row-major
+  Sell Aell;  // sliced-ELL copy of A for the solve (when it pays; see sell_build)
   // FP32 copies (FP32 V-cycle)
   float *Af = nullptr, *Pf = nullptr, *Rf = nullptr, *sm_invDf = nullptr;
   // work vectors

@@ -17,6 +17,11 @@ struct SpmvArgs {
   const T *x;
   const int32_t *bstart;  // row partition from spmv_plan: (first row, first entry) pairs
   int32_t nblk;
+  // sliced-ELL copy (see Sell); when sval is set the SpMV runs on it instead of the CSR
+  const int32_t *sptr = nullptr;
+  const int32_t *scol = nullptr;
+  const T *sval = nullptr;
+  int32_t nslice = 0;
 };
 // Row partition for the SpMV kernels: block b owns the rows whose cost rp[r] + 8 r lies in
 // [2048 b, 2048 (b+1)), i.e. at most 256 rows and (long rows aside) at most 2048 entries;
@@ -26,6 +31,23 @@ template <class T>
 inline SpmvArgs<T> spmv_args(const Csr &A, const T *val, const T *x) {
   return SpmvArgs<T>{A.n, A.rp, A.col, val, x, A.bstart, A.nblk};
 }
+// Switches an SpMV to the sliced-ELL copy S with values val (no change when S is not built).
+template <class T>
+inline SpmvArgs<T> with_sell(SpmvArgs<T> a, const Sell &S, const T *val) {
+  if (S.ptr && val) {
+    a.sptr = S.ptr;
+    a.scol = S.col;
+    a.sval = val;
+    a.nslice = S.nslice;
+  }
+  return a;
+}
+// Builds the sliced-ELL copy of A (FP32 values too when f32) if it pays: rows averaging at
+// most 12 entries (longer rows keep the CSR kernel, whose products are formed by the whole
+// block) and padding at most a quarter of the entries.  Returns whether it did.
+bool sell_build(const Csr &A, Sell &S, bool f32, Arena &ar, hipStream_t s);
+// Copies A's current values into a built copy (after a numeric re-setup).
+void sell_values(const Csr &A, const Sell &S, hipStream_t s);
 // Sorts the entries of every row by column (values follow when val != nullptr); keys within a
 // row must be distinct.  Short rows per thread, long rows per block (bitonic in LDS).
 void sort_rows(int32_t n, const int32_t *rp, int32_t *col, double *val, hipStream_t s);

@@ -60,16 +60,38 @@ __device__ __forceinline__ void spmv_block(int32_t b, const int32_t *__restrict_
 #pragma unroll 8
     for (int32_t e = c0 + t; e < c1; e += kBlock) prod[e - c0] = val[e] * x[col[e]];
     __syncthreads();
-    // in-order sum of the row's products in this chunk; loads are issued 8 at a time ahead
-    // of the (sequential) adds so long rows are bound by the add chain, not LDS latency
+    // in-order sum of the row's products in this chunk, software-pipelined over two
+    // register batches: the next 8 products are read from LDS while the current 8 are added,
+    // so long rows are bound by the add chain, not by LDS latency
     int32_t e = max(mb, c0);
     const int32_t en = min(me, c1);
-    for (; e + 8 <= en; e += 8) {
-      T v[8];
+    if (e + 8 <= en) {
+      T v[8], w[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) v[q] = prod[e - c0 + q];
+      e += 8;
+      for (;;) {
+        if (e + 8 > en) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) s += v[q];
+          for (int q = 0; q < 8; ++q) s += v[q];
+          break;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) w[q] = prod[e - c0 + q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s += v[q];
+        e += 8;
+        if (e + 8 > en) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) s += w[q];
+          break;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = prod[e - c0 + q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s += w[q];
+        e += 8;
+      }
     }
     for (; e < en; ++e) s += prod[e - c0];
     __syncthreads();

@@ -22,6 +22,122 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int32_t *__restrict__ bst
   spmv_block<T, Epi>(xcd_block(blockIdx.x, gridDim.x), bstart, rp, col, val, x, epi, prod);
 }
 
+// Sliced-ELL SpMV: one wavefront per 64-row slice, lane l on row 64 s + l.  The k-th entries
+// of the slice's rows are contiguous, so every value and index load is a full 64-lane run;
+// entries are taken 8 at a time (indices and values, then the x gathers, then the in-order
+// adds), the row sum runs in ascending column order from 0 like the CSR kernel's.  The
+// workgroup's 4 slices are consecutive and XCD-grouped like the CSR row blocks.
+template <class T, class Epi>
+__global__ __launch_bounds__(kBlock) void k_spmv_sell(int32_t n, int32_t nslice,
+                                                      const int32_t *__restrict__ sptr,
+                                                      const int32_t *__restrict__ scol,
+                                                      const T *__restrict__ sval,
+                                                      const T *__restrict__ x, Epi epi) {
+  const int32_t sl =
+      xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (int32_t)(threadIdx.x >> 6);
+  if (sl >= nslice) return;  // wave-uniform
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t row = sl * 64 + lane;
+  const int32_t p0 = sptr[sl];
+  const int32_t w = (sptr[sl + 1] - p0) >> 6;
+  typename Epi::Pre pre{};
+  if (row < n) pre = epi.load(row);
+  const int32_t *cb = scol + p0 + lane;
+  const T *vb = sval + p0 + lane;
+  T s = T(0);
+  for (int32_t k = 0; k < w; k += 8) {
+    int32_t c[8];
+    T v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int32_t kk = min(k + q, w - 1);  // in bounds even if loaded eagerly
+      c[q] = (k + q < w) ? cb[kk * 64] : -1;
+      v[q] = vb[kk * 64];
+    }
+    T xv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xv[q] = c[q] >= 0 ? x[c[q]] : T(0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (c[q] >= 0) s += v[q] * xv[q];
+  }
+  if (row < n) epi.store(row, s, pre);
+}
+
+// Slice widths (times 64): a wavefront's maximum row length.  Launched over nslice*64
+// threads, whole wavefronts.
+__global__ void k_sell_width(int32_t n, int32_t nslice, const int32_t *rp, int32_t *w64) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t len = i < n ? rp[i + 1] - rp[i] : 0;
+  for (int off = 32; off >= 1; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
+  if ((threadIdx.x & 63) == 0 && (i >> 6) < nslice) w64[i >> 6] = 64 * len;
+}
+// Thread per (padded) row: its entries into the slice, then padding.
+template <class T>
+__global__ void k_sell_fill(int32_t n, int32_t nslice, const int32_t *rp, const int32_t *col,
+                            const double *val, const int32_t *ptr, int32_t *scol, T *sval) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nslice * 64) return;
+  const int32_t sl = (int32_t)(i >> 6), l = (int32_t)(i & 63);
+  const int32_t p = ptr[sl], w = (ptr[sl + 1] - p) >> 6;
+  int32_t b = 0, len = 0;
+  if (i < n) {
+    b = rp[i];
+    len = rp[i + 1] - b;
+  }
+  for (int32_t k = 0; k < w; ++k) {
+    const int32_t o = p + k * 64 + l;
+    if (k < len) {
+      if (scol) scol[o] = col[b + k];
+      sval[o] = (T)val[b + k];
+    } else {
+      if (scol) scol[o] = -1;
+      sval[o] = T(0);
+    }
+  }
+}
+
+bool sell_build(const Csr &A, Sell &S, bool f32, Arena &ar, hipStream_t s) {
+  S = Sell{};
+  if (A.n <= 0 || A.nnz > 12 * (int64_t)A.n) return false;
+  const int32_t nslice = (int32_t)ceil_div(A.n, 64);
+  const int32_t maxlen = max_row_length(A.n, A.rp, s);
+  if ((int64_t)nslice * 64 * maxlen >= ((int64_t)1 << 31)) return false;
+  Arena tmp;
+  tmp.stream = s;
+  int32_t *w64 = tmp.alloc<int32_t>(nslice + 1);
+  k_sell_width<<<grid_for((int64_t)nslice * 64), kBlock, 0, s>>>(A.n, nslice, A.rp, w64);
+  SA_LAUNCH_CHECK();
+  int32_t *ptr = tmp.alloc<int32_t>(nslice + 1);
+  exclusive_scan_i32(w64, ptr, nslice, s);
+  const int32_t total = read1(ptr + nslice, s);
+  if ((int64_t)total * 4 > A.nnz * 5) return false;  // padding above a quarter
+  S.nslice = nslice;
+  S.ptr = ar.alloc<int32_t>(nslice + 1);
+  SA_HIP(hipMemcpyAsync(S.ptr, ptr, sizeof(int32_t) * (nslice + 1), hipMemcpyDeviceToDevice, s));
+  S.col = ar.alloc<int32_t>(total);
+  S.val = ar.alloc<double>(total);
+  if (f32) S.valf = ar.alloc<float>(total);
+  const unsigned g = grid_for((int64_t)nslice * 64);
+  k_sell_fill<double><<<g, kBlock, 0, s>>>(A.n, nslice, A.rp, A.col, A.val, S.ptr, S.col, S.val);
+  if (f32)
+    k_sell_fill<float><<<g, kBlock, 0, s>>>(A.n, nslice, A.rp, A.col, A.val, S.ptr, nullptr,
+                                            S.valf);
+  SA_LAUNCH_CHECK();
+  return true;
+}
+
+void sell_values(const Csr &A, const Sell &S, hipStream_t s) {
+  if (!S.ptr) return;
+  const unsigned g = grid_for((int64_t)S.nslice * 64);
+  k_sell_fill<double><<<g, kBlock, 0, s>>>(A.n, S.nslice, A.rp, A.col, A.val, S.ptr, nullptr,
+                                           S.val);
+  if (S.valf)
+    k_sell_fill<float><<<g, kBlock, 0, s>>>(A.n, S.nslice, A.rp, A.col, A.val, S.ptr, nullptr,
+                                            S.valf);
+  SA_LAUNCH_CHECK();
+}
+
 // Row partition: block b owns rows plan[2b] .. plan[2b+2]-1, whose entries start at
 // plan[2b+1]; the pairs are stored side by side so a block reads its row and entry ranges
 // with one load.
@@ -54,7 +170,11 @@ void spmv_plan(Csr &A, Arena &ar, hipStream_t s) {
 template <class T, class Epi>
 static void launch_spmv(const SpmvArgs<T> &a, const Epi &epi, hipStream_t s) {
   if (a.n <= 0) return;
-  k_spmv<T, Epi><<<(unsigned)a.nblk, kBlock, 0, s>>>(a.bstart, a.rp, a.col, a.val, a.x, epi);
+  if (a.sval)
+    k_spmv_sell<T, Epi><<<(unsigned)ceil_div(a.nslice, kBlock / 64), kBlock, 0, s>>>(
+        a.n, a.nslice, a.sptr, a.scol, a.sval, a.x, epi);
+  else
+    k_spmv<T, Epi><<<(unsigned)a.nblk, kBlock, 0, s>>>(a.bstart, a.rp, a.col, a.val, a.x, epi);
   SA_LAUNCH_CHECK();
 }
 
