@@ -101,6 +101,9 @@ int orc_lump(int32_t n, const int32_t *rp, const int32_t *col, const double *val
              int32_t *out_col, double *out_val);
 int orc_diag(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
              int32_t one_norm, double sigma, double *invD);
+// y = A x for an nr x nc CSR matrix, in the row-sum order of the oracle's spmv.
+int orc_spmv(int32_t nr, int32_t nc, const int32_t *rp, const int32_t *col, const double *val,
+             const double *x, double *y);
 int orc_power(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
               const double *invD, int32_t iters, uint64_t seed, int32_t level,
               int32_t stream, double *lambda);

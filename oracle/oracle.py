@@ -67,6 +67,7 @@ def _setup_prototypes(L):
     L.orc_sprsfy.argtypes = [C.c_int32, P, P, P, P, P, C.c_int32]
     L.orc_lump.argtypes = [C.c_int32, P, P, P, P, C.c_int32, C.c_double, P, P, P]
     L.orc_diag.argtypes = [C.c_int32, P, P, P, C.c_int32, C.c_double, P]
+    L.orc_spmv.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P]
     L.orc_power.argtypes = [C.c_int32, P, P, P, P, C.c_int32, C.c_uint64, C.c_int32,
                             C.c_int32, P]
     L.orc_prolongator.argtypes = [C.c_int32, P, P, P, P, P, C.c_double, P, P, P]
@@ -329,6 +330,17 @@ def diag(n, rp, col, val, one_norm=False, sigma=1.0 / 3.0):
     d = np.empty(n)
     _check(lib().orc_diag(n, _p(rp), _p(col), _p(val), int(one_norm), sigma, _p(d)))
     return d
+
+
+def spmv(rp, col, val, x, ncols=None):
+    """y = A x in the oracle's row-sum order (rows of more than 64 entries as 64 interleaved
+    in-order partial sums, added in order)."""
+    rp, col, val, x = _i32(rp), _i32(col), _f64(val), _f64(x)
+    nr = len(rp) - 1
+    nc = len(x) if ncols is None else ncols
+    y = np.empty(nr)
+    _check(lib().orc_spmv(nr, nc, _p(rp), _p(col), _p(val), _p(x), _p(y)))
+    return y
 
 
 def power(n, rp, col, val, invD, iters=10, seed=12345, level=0, stream=0):

@@ -8,7 +8,8 @@
 // Readings of the paper where it is silent or ambiguous are marked "Reading:" in the
 // comments.  The arithmetic order of every floating-point reduction is fixed here and
 // stated in the comments (sums run sequentially in ascending index order starting from
-// 0.0; inner products use the canonical 4096/256 tree of canon_sum), because the GPU
+// 0.0, except matrix rows of more than 64 entries, see spmv; inner products use the
+// canonical 4096/256 tree of canon_sum), because the GPU
 // library reproduces those orders to give bit-identical setups.
 //
 // Parity status per function: every step is pinned by tests against printed values,
@@ -125,12 +126,26 @@ double dot(const std::vector<double> &x, const std::vector<double> &y) {
   return canon_sum(p);
 }
 
-// y = A x, each row summed sequentially in ascending column order from 0.0.
+// y = A x.  Reading (summation order; the paper fixes none): a row of L <= 64 entries is
+// summed sequentially in ascending column order from 0.0.  A row of L > 64 entries, at
+// in-row positions k = 0..L-1 in ascending column order, is summed as 64 interleaved partial
+// sums p_l = sum of the products at positions l, l+64, l+128, ... (each sequential from 0.0),
+// followed by p_0 + p_1 + ... + p_63 (sequential from 0.0).  For L <= 64 the second form
+// gives the first exactly, so the split only changes rows longer than 64 entries.
 void spmv(const Csr &A, const std::vector<double> &x, std::vector<double> &y) {
   y.assign(A.nr, 0.0);
   for (int i = 0; i < A.nr; ++i) {
+    const int32_t b = A.rp[i], L = A.rp[i + 1] - b;
     double s = 0.0;
-    for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) s += A.val[e] * x[A.col[e]];
+    if (L <= 64) {
+      for (int32_t k = 0; k < L; ++k) s += A.val[b + k] * x[A.col[b + k]];
+    } else {
+      for (int32_t l = 0; l < 64; ++l) {
+        double p = 0.0;
+        for (int32_t k = l; k < L; k += 64) p += A.val[b + k] * x[A.col[b + k]];
+        s += p;
+      }
+    }
     y[i] = s;
   }
 }
@@ -1800,6 +1815,15 @@ int orc_diag(int32_t n, const int32_t *rp, const int32_t *col, const double *val
   int st = diag(A, one_norm != 0, sigma, d);
   if (st) return st;
   std::memcpy(invD, d.data(), sizeof(double) * n);
+  return ST_OK;
+}
+
+int orc_spmv(int32_t nr, int32_t nc, const int32_t *rp, const int32_t *col, const double *val,
+             const double *x, double *y) {
+  Csr A = make_csr(nr, nc, rp, col, val);
+  std::vector<double> xv(x, x + nc), yv;
+  spmv(A, xv, yv);
+  std::memcpy(y, yv.data(), sizeof(double) * nr);
   return ST_OK;
 }
 

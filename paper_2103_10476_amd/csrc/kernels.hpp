@@ -5,7 +5,8 @@
 namespace sa {
 
 // ---------------- solve-phase kernels (solve_kernels.hip) ------------------------------
-// y = A x with every row summed sequentially in ascending column order from 0 (products
+// y = A x with every row of at most 64 entries summed sequentially in ascending column order
+// from 0, longer rows as 64 interleaved in-order partial sums added in order (products
 // staged through LDS; bit-identical to the row-by-row definition).  Variants fuse the
 // row-local epilogue used by the smoother, residual and transfer steps.
 template <class T>
@@ -44,7 +45,8 @@ inline SpmvArgs<T> with_sell(SpmvArgs<T> a, const Sell &S, const T *val) {
 }
 // Builds the sliced-ELL copy of A (FP32 values too when f32) if it pays: rows averaging at
 // most 12 entries (longer rows keep the CSR kernel, whose products are formed by the whole
-// block) and padding at most a quarter of the entries.  Returns whether it did.
+// block), none longer than 64 (the longer ones are summed in the split order by a
+// wavefront) and padding at most a quarter of the entries.  Returns whether it did.
 bool sell_build(const Csr &A, Sell &S, bool f32, Arena &ar, hipStream_t s);
 // Copies A's current values into a built copy (after a numeric re-setup).
 void sell_values(const Csr &A, const Sell &S, hipStream_t s);

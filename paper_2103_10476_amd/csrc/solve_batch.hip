@@ -44,11 +44,11 @@ struct GSpmv {
 template <class T, class Epi>
 __global__ __launch_bounds__(kBlock) void k_gspmv(const GSpmv<T, Epi> *segs,
                                                   const int32_t *boff, int32_t nseg) {
-  __shared__ T prod[Chunk<T>::value];
+  __shared__ SpmvShared<T> sh;
   const int32_t g = xcd_block(blockIdx.x, gridDim.x);
   const int32_t s = find_seg(boff, nseg, g);
   const GSpmv<T, Epi> a = segs[s];
-  spmv_block<T, Epi>(g - boff[s], a.bstart, a.rp, a.col, a.val, a.x, a.epi, prod);
+  spmv_block<T, Epi>(g - boff[s], a.bstart, a.rp, a.col, a.val, a.x, a.epi, sh);
 }
 
 enum GVecOp : int32_t {

@@ -28,20 +28,49 @@ __device__ __forceinline__ int32_t xcd_block(uint32_t b, uint32_t nb) {
   return (int32_t)(x * q + (x < r ? x : r) + k);
 }
 
+// Row sums.  A row of at most kLongRow = 64 entries is summed in ascending column order from
+// 0.  A longer row, with in-row positions k = 0..L-1 in ascending column order, is summed as
+// 64 interleaved partial sums p_l over the positions l, l+64, l+128, ... (each in order from
+// 0), followed by p_0 + ... + p_63 in order from 0.  For L <= 64 the two forms agree
+// exactly; the split lets lane l of a wavefront form p_l instead of one thread adding all L
+// products in a dependent chain.
+constexpr int32_t kLongRow = 64;
+
+// The rows of a row block start within one window of kPlanWindow cost units (row r costs
+// rp[r] + kPlanRowCost r, at least its entry count), and a chunk holds kPlanWindow entries:
+// every row of a block but its last lies in the block's first chunk, so at most one row (the
+// last) spans chunks.
+static_assert(Chunk<double>::value >= kPlanWindow && Chunk<float>::value >= kPlanWindow,
+              "rows other than a block's last fit its first chunk");
+
+// LDS of one SpMV row block: the chunk's products (a long row that lies in the chunk gets
+// its 64 partial sums written over its own first 64 products), the partials of a long row
+// that spans chunks, and per wavefront the mask of its threads whose rows are long.
+template <class T>
+struct SpmvShared {
+  T prod[Chunk<T>::value];
+  T lastp[64];
+  uint64_t longmask[kBlock / 64];
+};
+
 // One SpMV row block b (rows plan[2b] .. plan[2b+2]-1, entries from plan[2b+1]): the block
 // streams the rows' entries through LDS in coalesced chunks, forming each product
-// val*x[col] once; then every thread adds the products of its own row in ascending column
-// order, starting from 0, and hands the sum to the epilogue.  The sum order is the
-// sequential row sum's.
+// val*x[col] once.  Every thread adds the products of its own short row in ascending column
+// order from 0.  The block's j-th long row is taken by wavefront j mod 4: lane l forms p_l
+// (carried in a register across chunks for the one row that spans chunks) and stores it in
+// LDS; after the chunk's barrier the row's own thread adds its 64 partials in order.  Each
+// row's sum goes to the epilogue from the row's own thread.
 template <class T, class Epi>
 __device__ __forceinline__ void spmv_block(int32_t b, const int32_t *__restrict__ plan,
                                            const int32_t *__restrict__ rp,
                                            const int32_t *__restrict__ col,
                                            const T *__restrict__ val,
                                            const T *__restrict__ x, const Epi &epi,
-                                           T *prod) {
+                                           SpmvShared<T> &sh) {
   constexpr int CH = Chunk<T>::value;
+  constexpr int NW = kBlock / 64;
   const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
   // row and entry ranges: two independent 8-byte loads (one round trip)
   const int2 p0 = ((const int2 *)plan)[b], p1 = ((const int2 *)plan)[b + 1];
   const int32_t r0 = p0.x, e0 = p0.y, r1 = p1.x, e1 = p1.y;
@@ -55,46 +84,85 @@ __device__ __forceinline__ void spmv_block(int32_t b, const int32_t *__restrict_
     pre = epi.load(row);  // the epilogue's vector reads overlap the entry loads
   }
   T s = T(0);
+  T cp = T(0);       // p_lane of the long row that continues into the next chunk
+  bool lng = false;  // this thread's row is long
+  bool any = false;  // block-uniform: the block has long rows
   for (int32_t c0 = e0; c0 < e1; c0 += CH) {
     const int32_t c1 = min(c0 + CH, e1);
 #pragma unroll 8
-    for (int32_t e = c0 + t; e < c1; e += kBlock) prod[e - c0] = val[e] * x[col[e]];
-    __syncthreads();
-    // in-order sum of the row's products in this chunk, software-pipelined over two
-    // register batches: the next 8 products are read from LDS while the current 8 are added,
-    // so long rows are bound by the add chain, not by LDS latency
-    int32_t e = max(mb, c0);
-    const int32_t en = min(me, c1);
-    if (e + 8 <= en) {
-      T v[8], w[8];
+    for (int32_t e = c0 + t; e < c1; e += kBlock) sh.prod[e - c0] = val[e] * x[col[e]];
+    if (c0 == e0) {
+      // classified after the first chunk's loads are issued, so the row-pointer reads
+      // overlap them (the empty asm keeps the compiler from hoisting the test, and with it
+      // the wait for mb and me, above the loop)
+      int32_t b2 = mb, e2 = me;
+      asm volatile("" : "+v"(b2), "+v"(e2));
+      lng = e2 - b2 > kLongRow;
+      const uint64_t lmask = __ballot(lng);
+      if (lane == 0) sh.longmask[wv] = lmask;
+      any = __syncthreads_or(lng) != 0;
+    } else {
+      __syncthreads();
+    }
+    if (!lng) {
+      // in-order sum of the row's products in this chunk; loads are issued 8 at a time
+      // ahead of the (sequential) adds
+      int32_t e = max(mb, c0);
+      const int32_t en = min(me, c1);
+      for (; e + 8 <= en; e += 8) {
+        T v[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = prod[e - c0 + q];
-      e += 8;
-      for (;;) {
-        if (e + 8 > en) {
-#pragma unroll
-          for (int q = 0; q < 8; ++q) s += v[q];
-          break;
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) w[q] = prod[e - c0 + q];
+        for (int q = 0; q < 8; ++q) v[q] = sh.prod[e - c0 + q];
 #pragma unroll
         for (int q = 0; q < 8; ++q) s += v[q];
-        e += 8;
-        if (e + 8 > en) {
-#pragma unroll
-          for (int q = 0; q < 8; ++q) s += w[q];
-          break;
+      }
+      for (; e < en; ++e) s += sh.prod[e - c0];
+    }
+    // long rows: this wavefront's share, in row order (block-uniform masks)
+    int32_t j = 0;
+#pragma unroll 1
+    for (int q = 0; q < (any ? NW : 0); ++q) {
+      uint64_t m = sh.longmask[q];
+      while (m) {
+        const int bit = __builtin_ctzll(m);
+        m &= m - 1;
+        if ((j++ & (NW - 1)) != wv) continue;  // wave-uniform
+        const int32_t rb = rp[r0 + q * 64 + bit], re = rp[r0 + q * 64 + bit + 1];
+        const int32_t lo = max(rb, c0), hi = min(re, c1);
+        if (lo >= hi) continue;  // no entries in this chunk
+        // this lane's positions k = lane (mod 64) in [lo, hi), 4 loads ahead of the adds
+        const int32_t k0 = lo - rb;
+        int32_t e = lo + ((lane - k0) & 63);
+        T acc = rb < c0 ? cp : T(0);
+        for (; e + 192 < hi; e += 256) {
+          const T a0 = sh.prod[e - c0], a1 = sh.prod[e + 64 - c0];
+          const T a2 = sh.prod[e + 128 - c0], a3 = sh.prod[e + 192 - c0];
+          acc += a0;
+          acc += a1;
+          acc += a2;
+          acc += a3;
         }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = prod[e - c0 + q];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) s += w[q];
-        e += 8;
+        for (; e < hi; e += 64) acc += sh.prod[e - c0];
+        if (re > c1) cp = acc;                         // continues into the next chunk
+        else if (rb >= c0) sh.prod[rb - c0 + lane] = acc;  // over this lane's first product
+        else sh.lastp[lane] = acc;                      // a spanning row ends here
       }
     }
-    for (; e < en; ++e) s += prod[e - c0];
     __syncthreads();
+    if (any) {  // block-uniform: long rows ending in this chunk add their partials in order
+      if (lng && me > c0 && me <= c1) {
+        const T *pj = mb >= c0 ? sh.prod + (mb - c0) : sh.lastp;
+#pragma unroll 1
+        for (int l = 0; l < 64; l += 8) {
+          T v[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) v[q] = pj[l + q];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) s += v[q];
+        }
+      }
+      if (c1 < e1) __syncthreads();  // before the next chunk's products
+    }
   }
   if (row < r1) epi.store(row, s, pre);
 }

@@ -4,10 +4,12 @@
 // SpMV layout: a block of 256 threads owns a run of at most 256 consecutive rows, chosen by
 // the row plan so that every block carries about the same number of entries plus a per-row
 // cost.  The block streams the rows' entries through LDS in coalesced chunks, forming each
-// product val*x[col] once; then
-// every thread adds the products of its own row in ascending column order.  The sum order
-// equals the sequential row sum, so results are bit-identical to it, while the global loads
-// stay fully coalesced (HBM-bound: ~12 B/entry for FP64, ~8 B/entry for FP32).
+// product val*x[col] once; then every thread adds the products of its own row (at most 64
+// entries) in ascending column order, and longer rows are summed by a wavefront as 64
+// interleaved in-order partial sums added in order (the row-sum order defined with
+// spmv_block).  Results are bit-identical to that row-by-row definition, while the global
+// loads stay fully coalesced (HBM-bound: ~12 B/entry for FP64, ~8 B/entry for FP32).
+// Operators with short rows use a sliced-ELL copy instead (k_spmv_sell).
 #include "solve_device.hpp"
 
 namespace sa {
@@ -18,14 +20,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int32_t *__restrict__ bst
                                                  const int32_t *__restrict__ col,
                                                  const T *__restrict__ val,
                                                  const T *__restrict__ x, Epi epi) {
-  __shared__ T prod[Chunk<T>::value];
-  spmv_block<T, Epi>(xcd_block(blockIdx.x, gridDim.x), bstart, rp, col, val, x, epi, prod);
+  __shared__ SpmvShared<T> sh;
+  spmv_block<T, Epi>(xcd_block(blockIdx.x, gridDim.x), bstart, rp, col, val, x, epi, sh);
 }
 
 // Sliced-ELL SpMV: one wavefront per 64-row slice, lane l on row 64 s + l.  The k-th entries
 // of the slice's rows are contiguous, so every value and index load is a full 64-lane run;
 // entries are taken 8 at a time (indices and values, then the x gathers, then the in-order
-// adds), the row sum runs in ascending column order from 0 like the CSR kernel's.  The
+// adds); rows are at most 64 entries, summed in ascending column order from 0 like the CSR
+// kernel's short rows.  The
 // workgroup's 4 slices are consecutive and XCD-grouped like the CSR row blocks.
 template <class T, class Epi>
 __global__ __launch_bounds__(kBlock) void k_spmv_sell(int32_t n, int32_t nslice,
@@ -102,7 +105,9 @@ bool sell_build(const Csr &A, Sell &S, bool f32, Arena &ar, hipStream_t s) {
   if (A.n <= 0 || A.nnz > 12 * (int64_t)A.n) return false;
   const int32_t nslice = (int32_t)ceil_div(A.n, 64);
   const int32_t maxlen = max_row_length(A.n, A.rp, s);
-  if ((int64_t)nslice * 64 * maxlen >= ((int64_t)1 << 31)) return false;
+  // a thread sums its row in order: the layout only serves rows of the plain order
+  if (maxlen > kLongRow) return false;
+  if ((int64_t)nslice * 64 * maxlen >= ((int64_t)1 << 31)) return false;  // int32 offsets
   Arena tmp;
   tmp.stream = s;
   int32_t *w64 = tmp.alloc<int32_t>(nslice + 1);
