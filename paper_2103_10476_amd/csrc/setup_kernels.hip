@@ -467,13 +467,15 @@ __global__ void k_mis_pass1(int32_t n, const int32_t *__restrict__ grp,
                             K *__restrict__ k1, const uint8_t *__restrict__ st1,
                             uint8_t *__restrict__ st2, uint8_t sr, bool first,
                             const int32_t *__restrict__ prev) {
-  if (prev && *prev == 0) return;  // the previous round changed nothing
+  // the stamp and the previous round's flag are read together (one round trip); a round
+  // whose predecessor changed nothing exits
   if (WAVE) {
     const int lane = threadIdx.x & 63;
     const int64_t v64 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (v64 >= n) return;
     const int32_t v = (int32_t)v64;
-    if (st1[v] != sr) return;  // wave-uniform
+    const uint8_t st = st1[v];
+    if ((prev && *prev == 0) | (st != sr)) return;  // wave-uniform
     const int32_t b = grp[v], e = grp[v + 1];
     K m = (lane == 0) ? key[v] : ~(K)0;
     for (int32_t k = b + lane; k < e; k += 64) {
@@ -492,12 +494,17 @@ __global__ void k_mis_pass1(int32_t n, const int32_t *__restrict__ grp,
     }
   } else {
     SA_ROW_KERNEL_BEGIN(n)
-    if (st1[i] != sr) return;
+    const uint8_t st = st1[i];
+    if ((prev && *prev == 0) | (st != sr)) return;
+    const int32_t b = grp[i], e = grp[i + 1];
     K m = key[i];
     const K old = first ? m : k1[i];
-    // neighbours 8 at a time: all indices, then all keys, as independent loads (v itself
-    // past the end of the list, harmless in the minimum)
-    const int32_t b = grp[i], e = grp[i + 1];
+    // neighbours 8 at a time: all indices, then all keys, as independent loads (i itself
+    // past the end of the list, harmless in the minimum); the first 8 indices are kept for
+    // the stamps
+    int32_t c0[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) c0[q] = i;
     for (int32_t k = b; k < e; k += 8) {
       int32_t c[8];
 #pragma unroll
@@ -510,8 +517,20 @@ __global__ void k_mis_pass1(int32_t n, const int32_t *__restrict__ grp,
       for (int q = 0; q < 8; ++q) kv[q] = key[c[q]];
 #pragma unroll
       for (int q = 0; q < 8; ++q) m = kv[q] < m ? kv[q] : m;
+      if (k == b) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c0[q] = c[q];
+      }
     }
-    if (!first && m != old) stamp_ball(gcol, b, e, i, st2, sr);
+    if (!first && m != old) {
+      if (e - b <= 8) {
+        st2[i] = sr;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) st2[c0[q]] = sr;
+      } else {
+        stamp_ball(gcol, b, e, i, st2, sr);
+      }
+    }
     k1[i] = m;
   }
 }
@@ -525,16 +544,16 @@ __global__ void k_mis_pass2(int32_t n, const int32_t *__restrict__ grp,
                             K *__restrict__ key, const uint8_t *__restrict__ st2,
                             uint8_t *__restrict__ st1, uint8_t sr, uint8_t srn,
                             int32_t *__restrict__ flag, const int32_t *__restrict__ prev) {
-  if (prev && *prev == 0) return;
   if (WAVE) {
     const int lane = threadIdx.x & 63;
     const int64_t v64 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (v64 >= n) return;
     const int32_t v = (int32_t)v64;
-    if (st2[v] != sr) return;  // wave-uniform
+    const uint8_t st = st2[v];
+    if ((prev && *prev == 0) | (st != sr)) return;  // wave-uniform
     const K me = key[v];
-    if ((me & KeyT<K>::Mask) != KeyT<K>::Und) return;  // wave-uniform
     const int32_t b = grp[v], e = grp[v + 1];
+    if (((me & KeyT<K>::Mask) != KeyT<K>::Und) | (e < b)) return;  // wave-uniform
     K m = (lane == 0) ? k1[v] : ~(K)0;
     for (int32_t k = b + lane; k < e; k += 64) {
       const K ku = k1[gcol[k]];
@@ -558,11 +577,17 @@ __global__ void k_mis_pass2(int32_t n, const int32_t *__restrict__ grp,
     }
   } else {
     SA_ROW_KERNEL_BEGIN(n)
-    if (st2[i] != sr) return;
+    const uint8_t st = st2[i];
+    if ((prev && *prev == 0) | (st != sr)) return;
+    // the key, the row range and k1 together (the test below uses them all, so none of the
+    // loads waits for the state test)
     const K me = key[i];
-    if ((me & KeyT<K>::Mask) != KeyT<K>::Und) return;
     K m = k1[i];
     const int32_t b = grp[i], e = grp[i + 1];
+    if (((me & KeyT<K>::Mask) != KeyT<K>::Und) | (e < b)) return;
+    int32_t c0[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) c0[q] = i;
     for (int32_t k = b; k < e; k += 8) {
       int32_t c[8];
 #pragma unroll
@@ -575,6 +600,10 @@ __global__ void k_mis_pass2(int32_t n, const int32_t *__restrict__ grp,
       for (int q = 0; q < 8; ++q) kv[q] = k1[c[q]];
 #pragma unroll
       for (int q = 0; q < 8; ++q) m = kv[q] < m ? kv[q] : m;
+      if (k == b) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c0[q] = c[q];
+      }
     }
     const K pri = me & ~KeyT<K>::Mask;
     K nk = me;
@@ -582,7 +611,13 @@ __global__ void k_mis_pass2(int32_t n, const int32_t *__restrict__ grp,
     else if (m == me) nk = KeyT<K>::In | pri;
     if (nk != me) {
       key[i] = nk;
-      stamp_ball(gcol, b, e, i, st1, srn);
+      if (e - b <= 8) {
+        st1[i] = srn;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) st1[c0[q]] = srn;
+      } else {
+        stamp_ball(gcol, b, e, i, st1, srn);
+      }
       *flag = 1;
     }
   }
