@@ -5,7 +5,8 @@
 // lane in order.  Output rows are sorted; cancellations stay stored.
 //
 // Rows are binned by their product count T:
-//   T <= 64      one wavefront per row: one product per lane, rank sort in LDS;
+//   T <= 64      16, 32 or 64 lanes per row (4, 2 or 1 rows per wavefront): one product per
+//                lane, rank sort in LDS;
 //   T > 64       one 256-thread block per row: chunks of 1024 products, bitonic sort of
 //                (column, position) keys in LDS; a single chunk is reduced and written
 //                directly, longer rows accumulate chunk by chunk into an LDS hash table
@@ -78,11 +79,19 @@ __device__ inline void wave_push(bool pred, int32_t *counter, int32_t *list, int
   if (pred) list[base + __popcll(msk & ((1ull << lane) - 1ull))] = value;
 }
 
-// ---- one wavefront per row (T <= 64) ------------------------------------------------------
-__global__ __launch_bounds__(kWave) void k_esc_wave(
+// ---- G lanes per row (T <= G), 64/G rows per wavefront ---------------------------------------
+// A wavefront takes 64/G rows, G lanes each (G = 16, 32 or 64): short rows share a
+// wavefront instead of leaving most of its lanes idle.  Per row: the X entries G at a time
+// (a segmented scan of their Y-row lengths), one product per lane by binary search over the
+// scan, a rank sort of the T <= G products in LDS, and one lane per run of equal columns
+// summing it in order.  The chunk loop runs to the longest X row of the wavefront, so every
+// lane passes every barrier.
+template <int G>
+__global__ __launch_bounds__(kWave) void k_esc_group(
     const int32_t *rows, int32_t nrows, const int32_t *xrp, const int32_t *xcol,
     const double *xval, const int32_t *yrp, const int32_t *ycol, const double *yval,
     const int64_t *poff, int32_t *ocol, double *oval, int32_t *ucnt) {
+  static_assert(G == 16 || G == 32 || G == 64, "group width");
   __shared__ int32_t keys[kWave];
   __shared__ double vals[kWave];
   __shared__ int32_t skeys[kWave];
@@ -90,79 +99,84 @@ __global__ __launch_bounds__(kWave) void k_esc_wave(
   __shared__ int32_t s_incl[kWave], s_ys[kWave];
   __shared__ double s_a[kWave];
   const int lane = threadIdx.x;
-  if ((int32_t)blockIdx.x >= nrows) return;  // block-uniform
-  const int32_t i = rows[blockIdx.x];
-  const int64_t base = poff[i];
-  const int32_t T = (int32_t)(poff[i + 1] - base);
+  const int gl = lane % G, gb = lane - gl;  // lane in the group, the group's first lane
+  const int64_t r64 = (int64_t)blockIdx.x * (kWave / G) + lane / G;
+  const bool live = r64 < nrows;
+  const int32_t i = live ? rows[r64] : 0;
+  const int64_t base = live ? poff[i] : 0;
+  const int32_t T = live ? (int32_t)(poff[i + 1] - base) : 0;
+  const int32_t xb = live ? xrp[i] : 0, xe = live ? xrp[i + 1] : 0;
+  int32_t nch = (xe - xb + G - 1) / G;  // chunks of this row; the wavefront runs the most
+  for (int off = 32; off >= 1; off >>= 1) nch = max(nch, __shfl_xor(nch, off, kWave));
   // expansion in Gustavson order: position = products of earlier X entries + offset in Y row
   int32_t filled = 0;
-  for (int32_t g = xrp[i]; g < xrp[i + 1]; g += kWave) {
-    const int32_t e = g + lane;
+  for (int32_t c = 0; c < nch; ++c) {
+    const int32_t e = xb + c * G + gl;
     int32_t len = 0, ys = 0;
     double a = 0.0;
-    if (e < xrp[i + 1]) {
+    if (e < xe) {
       const int32_t k = xcol[e];
       a = xval[e];
       ys = yrp[k];
       len = yrp[k + 1] - ys;
     }
-    // inclusive wave scan of len
+    // inclusive scan of len within the group
     int32_t incl = len;
-    for (int off = 1; off < kWave; off <<= 1) {
-      const int32_t v = __shfl_up(incl, off, kWave);
-      if (lane >= off) incl += v;
+    for (int off = 1; off < G; off <<= 1) {
+      const int32_t v = __shfl_up(incl, off, G);
+      if (gl >= off) incl += v;
     }
-    const int32_t tot = __shfl(incl, kWave - 1, kWave);
+    const int32_t tot = __shfl(incl, G - 1, G);
     s_incl[lane] = incl;
     s_ys[lane] = ys;
     s_a[lane] = a;
     __syncthreads();
     // product p of this chunk comes from the first entry s with incl[s] > p, at offset
     // p - incl[s-1] in its row of Y: one product per lane, loads independent across lanes
-    for (int32_t p = lane; p < tot; p += kWave) {
-      int32_t lo = 0, hi = kWave - 1;
+    for (int32_t p = gl; p < tot; p += G) {
+      int32_t lo = 0, hi = G - 1;
       while (lo < hi) {
         const int32_t mid = (lo + hi) >> 1;
-        if (s_incl[mid] > p) hi = mid;
+        if (s_incl[gb + mid] > p) hi = mid;
         else lo = mid + 1;
       }
-      const int32_t t = p - (lo > 0 ? s_incl[lo - 1] : 0);
-      keys[filled + p] = ycol[s_ys[lo] + t];
-      vals[filled + p] = s_a[lo] * yval[s_ys[lo] + t];
+      const int32_t t = p - (lo > 0 ? s_incl[gb + lo - 1] : 0);
+      keys[gb + filled + p] = ycol[s_ys[gb + lo] + t];
+      vals[gb + filled + p] = s_a[gb + lo] * yval[s_ys[gb + lo] + t];
     }
     __syncthreads();
     filled += tot;
   }
-  __syncthreads();
   int32_t key = 0;
   double v = 0.0;
-  if (lane < T) {
-    key = keys[lane];
-    v = vals[lane];
+  if (gl < T) {
+    key = keys[gb + gl];
+    v = vals[gb + gl];
     int32_t rank = 0;
     for (int32_t q = 0; q < T; ++q) {
-      const int32_t kq = keys[q];
-      rank += (kq < key) || (kq == key && q < lane);
+      const int32_t kq = keys[gb + q];
+      rank += (kq < key) || (kq == key && q < gl);
     }
-    skeys[rank] = key;
-    svals[rank] = v;
+    skeys[gb + rank] = key;
+    svals[gb + rank] = v;
   }
   __syncthreads();
   bool head = false;
   double sum = 0.0;
-  if (lane < T) {
-    key = skeys[lane];
-    head = (lane == 0) || (skeys[lane - 1] != key);
+  if (gl < T) {
+    key = skeys[gb + gl];
+    head = (gl == 0) || (skeys[gb + gl - 1] != key);
     if (head)
-      for (int32_t r = lane; r < T && skeys[r] == key; ++r) sum += svals[r];
+      for (int32_t r = gl; r < T && skeys[gb + r] == key; ++r) sum += svals[gb + r];
   }
-  const unsigned long long hm = __ballot(head);
-  const int32_t idx = __popcll(hm & ((1ull << lane) - 1ull));
+  const unsigned long long gm =
+      (__ballot(head) >> gb) & (~0ull >> (64 - G));  // this group's heads
+  const int32_t idx = __popcll(gm & ((1ull << gl) - 1ull));
   if (head) {
     ocol[base + idx] = key;
     oval[base + idx] = sum;
   }
-  if (lane == 0) ucnt[i] = __popcll(hm);
+  if (live && gl == 0) ucnt[i] = __popcll(gm);
 }
 
 // ---- block-level rows (T > 64) -------------------------------------------------------------
@@ -602,13 +616,17 @@ __global__ void k_compact(int32_t m, int64_t nnz, const int64_t *poff, const int
   cval[e] = oval[src];
 }
 
-__global__ void k_bin_rows4(int32_t m, const int64_t *poff, int32_t *lists, int32_t *counters) {
+// Bins by product count: <= 16, <= 32, <= 64 (rows sharing wavefronts), <= 256, <= 1024
+// (block per row, one chunk), longer.
+constexpr int kBins = 6;
+__global__ void k_bin_rows(int32_t m, const int64_t *poff, int32_t *lists, int32_t *counters) {
   const int64_t i64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i64 < m;
   const int32_t i = live ? (int32_t)i64 : 0;
   const int64_t T = live ? poff[i + 1] - poff[i] : 0;
-  const int bin = T <= kWave ? 0 : T <= 256 ? 1 : T <= kChunk ? 2 : 3;
-  for (int b = 0; b < 4; ++b) wave_push(live && bin == b, &counters[b], lists + (int64_t)b * m, i);
+  const int bin = T <= 16 ? 0 : T <= 32 ? 1 : T <= kWave ? 2 : T <= 256 ? 3 : T <= kChunk ? 4 : 5;
+  for (int b = 0; b < kBins; ++b)
+    wave_push(live && bin == b, &counters[b], lists + (int64_t)b * m, i);
 }
 
 void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
@@ -632,45 +650,52 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
   int32_t *ocol = tmp.alloc<int32_t>(total > 0 ? total : 1);
   double *oval = tmp.alloc<double>(total > 0 ? total : 1);
   int32_t *ucnt = tmp.alloc<int32_t>(m + 1);
-  int32_t *lists = tmp.alloc<int32_t>(4 * (int64_t)(m > 0 ? m : 1));
-  int32_t *counters = tmp.alloc<int32_t>(8);
+  int32_t *lists = tmp.alloc<int32_t>(kBins * (int64_t)(m > 0 ? m : 1));
+  int32_t *counters = tmp.alloc<int32_t>(8);  // kBins bin sizes, then the overflow count
   fill_i32(counters, 0, 8, s);
   if (m > 0) {
-    k_bin_rows4<<<grid_for(m), kBlock, 0, s>>>(m, poff, lists, counters);
+    k_bin_rows<<<grid_for(m), kBlock, 0, s>>>(m, poff, lists, counters);
     SA_LAUNCH_CHECK();
   }
   int32_t hc[8];
   readback(hc, counters, sizeof(hc), s);
-  const int32_t *l0 = lists, *l1 = lists + m, *l2 = lists + 2 * (int64_t)m,
-                *l3 = lists + 3 * (int64_t)m;
-  if (hc[0] > 0) {
-    k_esc_wave<<<(unsigned)hc[0], kWave, 0, s>>>(l0, hc[0], X.rp, X.col, X.val, Y.rp, Y.col,
-                                                  Y.val, poff, ocol, oval, ucnt);
-    SA_LAUNCH_CHECK();
-  }
-  if (hc[1] > 0) {
-    k_esc_single<64><<<(unsigned)hc[1], 64, 0, s>>>(l1, hc[1], X.rp, X.col, X.val, xpref, Y.rp,
+  const int32_t *lg[3] = {lists, lists + m, lists + 2 * (int64_t)m};
+  const int32_t *l1 = lists + 3 * (int64_t)m, *l2 = lists + 4 * (int64_t)m,
+                *l3 = lists + 5 * (int64_t)m;
+  if (hc[0] > 0)
+    k_esc_group<16><<<(unsigned)ceil_div(hc[0], kWave / 16), kWave, 0, s>>>(
+        lg[0], hc[0], X.rp, X.col, X.val, Y.rp, Y.col, Y.val, poff, ocol, oval, ucnt);
+  if (hc[1] > 0)
+    k_esc_group<32><<<(unsigned)ceil_div(hc[1], kWave / 32), kWave, 0, s>>>(
+        lg[1], hc[1], X.rp, X.col, X.val, Y.rp, Y.col, Y.val, poff, ocol, oval, ucnt);
+  if (hc[2] > 0)
+    k_esc_group<64><<<(unsigned)hc[2], kWave, 0, s>>>(lg[2], hc[2], X.rp, X.col, X.val, Y.rp,
+                                                      Y.col, Y.val, poff, ocol, oval, ucnt);
+  SA_LAUNCH_CHECK();
+  const int32_t n256 = hc[3], n1024 = hc[4], nlong = hc[5];  // block-level bins
+  if (n256 > 0) {
+    k_esc_single<64><<<(unsigned)n256, 64, 0, s>>>(l1, n256, X.rp, X.col, X.val, xpref, Y.rp,
                                                     Y.col, Y.val, poff, ocol, oval, ucnt);
     SA_LAUNCH_CHECK();
   }
-  if (hc[2] > 0) {
-    k_esc_single<256><<<(unsigned)hc[2], 256, 0, s>>>(l2, hc[2], X.rp, X.col, X.val, xpref,
+  if (n1024 > 0) {
+    k_esc_single<256><<<(unsigned)n1024, 256, 0, s>>>(l2, n1024, X.rp, X.col, X.val, xpref,
                                                       Y.rp, Y.col, Y.val, poff, ocol, oval,
                                                       ucnt);
     SA_LAUNCH_CHECK();
   }
-  if (hc[3] > 0 && Y.ncols <= lds_cols_max()) {
+  if (nlong > 0 && Y.ncols <= lds_cols_max()) {
     const size_t lds = (size_t)Y.ncols * sizeof(double) + (size_t)((Y.ncols + 31) / 32) * 4;
-    k_esc_lds<<<(unsigned)hc[3], 64, lds, s>>>(l3, hc[3], X.rp, X.col, X.val, Y.rp, Y.col, Y.val,
+    k_esc_lds<<<(unsigned)nlong, 64, lds, s>>>(l3, nlong, X.rp, X.col, X.val, Y.rp, Y.col, Y.val,
                                               Y.ncols, poff, ocol, oval, ucnt);
     SA_LAUNCH_CHECK();
-  } else if (hc[3] > 0) {
-    int32_t *ovf = tmp.alloc<int32_t>(hc[3]);
-    k_esc_hash<<<(unsigned)hc[3], kBlock, 0, s>>>(l3, hc[3], X.rp, X.col, X.val, xpref, Y.rp,
+  } else if (nlong > 0) {
+    int32_t *ovf = tmp.alloc<int32_t>(nlong);
+    k_esc_hash<<<(unsigned)nlong, kBlock, 0, s>>>(l3, nlong, X.rp, X.col, X.val, xpref, Y.rp,
                                                   Y.col, Y.val, poff, ocol, oval, ucnt, ovf,
-                                                  counters + 4);
+                                                  counters + kBins);
     SA_LAUNCH_CHECK();
-    const int32_t nov = read1(counters + 4, s);
+    const int32_t nov = read1(counters + kBins, s);
     if (nov > 0) {
       // dense accumulators: at most ~2 GiB of them at once
       const int64_t per = (int64_t)Y.ncols * 12;
