@@ -67,18 +67,6 @@ __global__ __launch_bounds__(64) void k_count_products_w(int32_t m, const int32_
   if (lane == 0) cnt[i] = base;
 }
 
-// One atomic per wavefront and bin (ballot + popcount), not per row.
-__device__ inline void wave_push(bool pred, int32_t *counter, int32_t *list, int32_t value) {
-  const unsigned long long msk = __ballot(pred);
-  if (!msk) return;
-  const int lane = threadIdx.x & 63;
-  const int leader = __ffsll((long long)msk) - 1;
-  int32_t base = 0;
-  if (lane == leader) base = atomicAdd(counter, __popcll(msk));
-  base = __shfl(base, leader, 64);
-  if (pred) list[base + __popcll(msk & ((1ull << lane) - 1ull))] = value;
-}
-
 // ---- G lanes per row (T <= G), 64/G rows per wavefront ---------------------------------------
 // A wavefront takes 64/G rows, G lanes each (G = 16, 32 or 64): short rows share a
 // wavefront instead of leaving most of its lanes idle.  Per row: the X entries G at a time
@@ -599,8 +587,39 @@ static int32_t lds_cols_max() {
   return cache[dev];
 }
 
+// Short rows: a wavefront takes 64 consecutive rows, whose entries are one contiguous run of
+// C; lanes copy consecutive entries (coalesced writes), each finding its row by binary
+// search over the 64 row starts held in LDS.
+__global__ __launch_bounds__(kBlock) void k_compact_w(int32_t m, const int64_t *poff,
+                                                      const int32_t *crp, const int32_t *ocol,
+                                                      const double *oval, int32_t *ccol,
+                                                      double *cval) {
+  constexpr int NW = kBlock / 64;
+  __shared__ int32_t s_rp[NW][65];
+  __shared__ int64_t s_po[NW][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t r0 = ((int64_t)blockIdx.x * NW + w) * 64;  // this wavefront's first row
+  const int64_t row = r0 + lane;
+  s_rp[w][lane] = crp[row < m ? row : m];  // rows past the end: empty, at C's end
+  if (lane == 0) s_rp[w][64] = crp[r0 + 64 < m ? r0 + 64 : m];
+  s_po[w][lane] = row < m ? poff[row] : 0;
+  __syncthreads();
+  const int32_t d1 = s_rp[w][64];
+  for (int32_t d = s_rp[w][0] + lane; d < d1; d += 64) {
+    int32_t lo = 0, hi = 63;  // last row r with s_rp[r] <= d (empty rows share starts)
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (s_rp[w][mid] <= d) lo = mid;
+      else hi = mid - 1;
+    }
+    const int64_t src = s_po[w][lo] + (d - s_rp[w][lo]);
+    ccol[d] = ocol[src];
+    cval[d] = oval[src];
+  }
+}
+
 // One thread per output entry: find the entry's row by binary search over C's row pointers
-// and copy from the row's slot area (coalesced writes).
+// and copy from the row's slot area (coalesced writes; long rows).
 __global__ void k_compact(int32_t m, int64_t nnz, const int64_t *poff, const int32_t *crp,
                           const int32_t *ocol, const double *oval, int32_t *ccol, double *cval) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -619,14 +638,24 @@ __global__ void k_compact(int32_t m, int64_t nnz, const int64_t *poff, const int
 // Bins by product count: <= 16, <= 32, <= 64 (rows sharing wavefronts), <= 256, <= 1024
 // (block per row, one chunk), longer.
 constexpr int kBins = 6;
+// A block counts its rows per bin in LDS and reserves each non-empty bin's share with one
+// global atomic (the order inside a list is immaterial: rows are independent).
 __global__ void k_bin_rows(int32_t m, const int64_t *poff, int32_t *lists, int32_t *counters) {
+  __shared__ int32_t s_cnt[kBins], s_base[kBins];
+  if (threadIdx.x < kBins) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
   const int64_t i64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i64 < m;
   const int32_t i = live ? (int32_t)i64 : 0;
   const int64_t T = live ? poff[i + 1] - poff[i] : 0;
   const int bin = T <= 16 ? 0 : T <= 32 ? 1 : T <= kWave ? 2 : T <= 256 ? 3 : T <= kChunk ? 4 : 5;
-  for (int b = 0; b < kBins; ++b)
-    wave_push(live && bin == b, &counters[b], lists + (int64_t)b * m, i);
+  int32_t local = 0;
+  if (live) local = atomicAdd(&s_cnt[bin], 1);
+  __syncthreads();
+  if (threadIdx.x < kBins && s_cnt[threadIdx.x] > 0)
+    s_base[threadIdx.x] = atomicAdd(&counters[threadIdx.x], s_cnt[threadIdx.x]);
+  __syncthreads();
+  if (live) lists[(int64_t)bin * m + s_base[bin] + local] = i;
 }
 
 void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
@@ -715,8 +744,12 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
   C.col = ar.alloc<int32_t>(C.nnz);
   C.val = ar.alloc<double>(C.nnz);
   if (C.nnz > 0) {
-    k_compact<<<grid_for(C.nnz), kBlock, 0, s>>>(m, C.nnz, poff, C.rp, ocol, oval, C.col,
-                                                 C.val);
+    if (C.nnz <= 32 * (int64_t)m)
+      k_compact_w<<<(unsigned)ceil_div(m, kBlock), kBlock, 0, s>>>(m, poff, C.rp, ocol, oval,
+                                                                 C.col, C.val);
+    else
+      k_compact<<<grid_for(C.nnz), kBlock, 0, s>>>(m, C.nnz, poff, C.rp, ocol, oval, C.col,
+                                                   C.val);
     SA_LAUNCH_CHECK();
   }
 }
