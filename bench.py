@@ -25,7 +25,7 @@ PRECISION_WORKLOAD = "fd7_160_a1000"
 PEAK_HBM_GBS = 8000.0
 # rocprofv3 counter summary of the SpMV kernel on the default workload; its traffic figure is
 # reported only while the kernel's sources still hash to the value recorded with it
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_spmv_fd7_128_a1000_hbm_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_spmv_sell_fd7_128_a1000_hbm_traffic.md")
 # the SpMV kernel body and epilogues live in solve_device.hpp, its launch and row partition in
 # solve_kernels.hip; build.py holds the compile flags
 KERNEL_SOURCES = ["paper_2103_10476_amd/csrc/solve_device.hpp",
@@ -285,16 +285,17 @@ def measured_traffic(workload):
 
 
 def roofline(tot, workload=WORKLOAD):
-    """Fine-level CSR SpMV (the kernel with the largest share of the step): algorithmic bytes
-    per launch (12 B per entry + row pointers + the vectors its fused epilogue reads/writes)
-    over the launch duration from HIP events recorded around every such launch of the timed
-    steps, on the library's stream."""
+    """Fine-level SpMV (sliced ELL; the kernel with the largest share of the solve):
+    algorithmic bytes per launch (12 B per entry + slice offsets + the vectors its fused
+    epilogue reads/writes; padding not counted) over the launch duration from HIP events
+    recorded around every such launch of the timed steps, on the library's stream."""
     if not tot["launches"]:
         return None
     avg_ms = tot["ms"] / tot["launches"]
     bytes_per = tot["bytes"] / tot["launches"]
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9
-    return {"bound": "hbm", "kernel": "k_spmv (fine-level operator, all fused epilogues)",
+    return {"bound": "hbm",
+            "kernel": "k_spmv_sell (fine-level operator, sliced ELL, all fused epilogues)",
             "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(workload),
             "launches": tot["launches"], "avg_us": round(avg_ms * 1e3, 2),

@@ -28,8 +28,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int32_t *__restrict__ bst
 // of the slice's rows are contiguous, so every value and index load is a full 64-lane run;
 // entries are taken 8 at a time (indices and values, then the x gathers, then the in-order
 // adds); rows are at most 64 entries, summed in ascending column order from 0 like the CSR
-// kernel's short rows.  The
-// workgroup's 4 slices are consecutive and XCD-grouped like the CSR row blocks.
+// kernel's short rows.  The workgroup's 4 slices are consecutive and XCD-grouped like the
+// CSR row blocks.
 template <class T, class Epi>
 __global__ __launch_bounds__(kBlock) void k_spmv_sell(int32_t n, int32_t nslice,
                                                       const int32_t *__restrict__ sptr,
