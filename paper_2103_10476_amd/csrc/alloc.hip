@@ -214,6 +214,12 @@ void *pinned_staging(size_t bytes) {
   return p;
 }
 
+// Small readbacks: one workgroup copies the words straight into the pinned staging buffer
+// through its device mapping (cheaper than the runtime's copy kernel for a few bytes).
+__global__ void k_copy_words(uint32_t *dst, const uint32_t *src, int32_t nw) {
+  for (int32_t i = threadIdx.x; i < nw; i += blockDim.x) dst[i] = src[i];
+}
+
 void readback(void *host, const void *dev, size_t bytes, hipStream_t s) {
   if (bytes == 0) return;
   if (bytes > (size_t(1) << 20)) {  // bulk copies: straight into the caller's memory
@@ -222,7 +228,15 @@ void readback(void *host, const void *dev, size_t bytes, hipStream_t s) {
     return;
   }
   void *st = pinned_staging(bytes);
-  SA_HIP(hipMemcpyAsync(st, dev, bytes, hipMemcpyDeviceToHost, s));
+  if (bytes <= 4096 && bytes % 4 == 0 && (uintptr_t)dev % 4 == 0) {
+    void *dst = nullptr;
+    SA_HIP(hipHostGetDevicePointer(&dst, st, 0));
+    k_copy_words<<<1, kBlock, 0, s>>>((uint32_t *)dst, (const uint32_t *)dev,
+                                      (int32_t)(bytes / 4));
+    SA_LAUNCH_CHECK();
+  } else {
+    SA_HIP(hipMemcpyAsync(st, dev, bytes, hipMemcpyDeviceToHost, s));
+  }
   SA_HIP(hipStreamSynchronize(s));
   std::memcpy(host, st, bytes);
 }

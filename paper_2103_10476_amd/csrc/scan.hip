@@ -81,21 +81,45 @@ __global__ void k_scan_apply(const T *in, T *out, int64_t n, const T *offsets) {
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kBlock - 1) out[n] = run;
 }
 
+// n <= kScanTile: the whole scan in one block (out may equal in: every thread reads its items
+// before the block scan's barriers, and writes after them).
+template <class T>
+__global__ void k_scan_single(const T *in, T *out, int64_t n) {
+  __shared__ T sh[kBlock];
+  const int64_t base = (int64_t)threadIdx.x * kScanItems;
+  T vals[kScanItems];
+  T s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    vals[k] = (base + k < n) ? in[base + k] : T(0);
+    s += vals[k];
+  }
+  T tot;
+  T run = block_exclusive<T>(s, sh, tot);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += vals[k];
+  }
+  if (threadIdx.x == 0) out[n] = tot;
+}
+
 template <class T>
 static void scan_impl(const T *in, T *out, int64_t n, hipStream_t s) {
   if (n <= 0) {
     fill(out, T(0), 1, s);
     return;
   }
+  if (n <= kScanTile) {
+    k_scan_single<T><<<1, kBlock, 0, s>>>(in, out, n);
+    SA_LAUNCH_CHECK();
+    return;
+  }
   int64_t nb = ceil_div(n, kScanTile);
   T *tot = (T *)dev_alloc(sizeof(T) * (nb + 1), s);
   k_scan_totals<T><<<(unsigned)nb, kBlock, 0, s>>>(in, n, tot);
   SA_LAUNCH_CHECK();
-  if (nb > 1) {
-    scan_impl<T>(tot, tot, nb, s);  // in place: tot has nb+1 slots
-  } else {
-    fill(tot, T(0), 1, s);
-  }
+  scan_impl<T>(tot, tot, nb, s);  // in place: tot has nb+1 slots (nb >= 2 here)
   k_scan_apply<T><<<(unsigned)nb, kBlock, 0, s>>>(in, out, n, tot);
   SA_LAUNCH_CHECK();
   dev_free(tot, s);
