@@ -12,6 +12,9 @@
 #include <string>
 #include <vector>
 
+#include <map>
+#include <mutex>
+
 #include "hierarchy.hpp"
 
 namespace sa {
@@ -43,6 +46,32 @@ static int32_t read_err(sa_hierarchy *h) { return read1(h->err, h->stream); }
 static void check_err(sa_hierarchy *h, int32_t mask_bits, sa_status code, const char *what) {
   const int32_t e = read_err(h);
   if (e & mask_bits) throw Error(code, what);
+}
+
+// Side stream of a main stream, one per (device, main stream) and kept for the process (the
+// allocator caches blocks per stream).  The smoother set-up of a finished level runs there
+// while the main stream builds the next levels; default priority, non-blocking.
+static hipStream_t side_stream(hipStream_t main) {
+  static std::mutex mu;
+  static std::map<std::pair<int, hipStream_t>, hipStream_t> streams;
+  int dev = 0;
+  SA_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = streams.find({dev, main});
+  if (it != streams.end()) return it->second;
+  hipStream_t s2 = nullptr;
+  SA_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+  streams[{dev, main}] = s2;
+  return s2;
+}
+
+// `waiter` runs its later work after everything already queued on `first`.
+static void stream_after(hipStream_t waiter, hipStream_t first) {
+  hipEvent_t ev;
+  SA_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  SA_HIP(hipEventRecord(ev, first));
+  SA_HIP(hipStreamWaitEvent(waiter, ev, 0));
+  SA_HIP(hipEventDestroy(ev));
 }
 
 static double safeguard_mult(double sigma) {
@@ -295,6 +324,35 @@ static void galerkin(sa_hierarchy *h, int l, bool fresh, const double *dB) {
   }
 }
 
+// GPU part of level l's smoother set-up on stream s: the inverse diagonal of A_l and the
+// power method for its largest eigenvalue (non-positive diagonals flag E_DIAG in *err).
+static void smoother_gpu(sa_hierarchy *h, int l, bool fresh, hipStream_t s, int32_t *err) {
+  Level &L = h->lv[l];
+  Arena tmp;
+  tmp.stream = s;
+  double *dval = tmp.alloc<double>(L.A.n);
+  find_diag(L.A.n, L.A.rp, L.A.col, L.A.val, dval, s);
+  if (fresh && !L.sm_invD) {
+    L.sm_invD = h->ar.alloc<double>(L.A.n);
+    L.sm_lam_d = h->ar.alloc<double>(1);
+  }
+  inv_diag(L.A.n, dval, L.sm_invD, err, s);
+  power_method(L.A, L.sm_invD, h->opt.power_iters, h->opt.seed, l, 1, L.sm_lam_d, s);
+}
+
+// Queues level l's smoother set-up on the side stream (level l is known not to be the
+// coarsest): after the main stream's work so far (A_l, and any earlier use of blocks handed
+// out below), with its own error word; finish_setup joins it.
+static void smoother_async(sa_hierarchy *h, int l) {
+  Level &L = h->lv[l];
+  L.sm_invD = h->ar.alloc<double>(L.A.n);  // main-stream blocks: allocated before the wait
+  L.sm_lam_d = h->ar.alloc<double>(1);
+  if (!h->side) h->side = side_stream(h->stream);
+  stream_after(h->side, h->stream);
+  smoother_gpu(h, l, true, h->side, h->err + 1);
+  L.sm_pending = true;
+}
+
 // Smoothers of every level but the coarsest, the coarsest level's dense inverse, the FP32
 // copies and the solve workspace.  fresh: allocate; otherwise recompute in place.
 static void finish_setup(sa_hierarchy *h, bool fresh) {
@@ -302,19 +360,23 @@ static void finish_setup(sa_hierarchy *h, bool fresh) {
   const sa_options &o = h->opt;
   const int nl = (int)h->lv.size();
   const int32_t n = h->n;
+  bool joined = false;
   for (int l = 0; l + 1 < nl; ++l) {
     Level &L = h->lv[l];
-    Arena tmp;
-    tmp.stream = s;
-    double *dval = tmp.alloc<double>(L.A.n);
-    find_diag(L.A.n, L.A.rp, L.A.col, L.A.val, dval, s);
-    if (fresh) {
-      L.sm_invD = h->ar.alloc<double>(L.A.n);
-      L.sm_lam_d = h->ar.alloc<double>(1);
+    if (!L.sm_pending) smoother_gpu(h, l, fresh, s, h->err);
+    else if (!joined) {  // the levels queued on the side stream: join them once
+      stream_after(s, h->side);
+      joined = true;
     }
-    inv_diag(L.A.n, dval, L.sm_invD, h->err, s);
+  }
+  if (joined) {
+    const int32_t e = read1(h->err + 1, s);  // the side stream's error word
+    if (e & E_DIAG) throw Error(SA_ERR_NONPOSITIVE_DIAG, "non-positive diagonal in a level operator");
+  }
+  for (int l = 0; l + 1 < nl; ++l) {
+    Level &L = h->lv[l];
+    L.sm_pending = false;
     check_err(h, E_DIAG, SA_ERR_NONPOSITIVE_DIAG, "non-positive diagonal in a level operator");
-    power_method(L.A, L.sm_invD, o.power_iters, o.seed, l, 1, L.sm_lam_d, s);
     const double lam = read1(L.sm_lam_d, s);
     if (!(lam > 0.0) || !std::isfinite(lam))
       throw Error(SA_ERR_NEGATIVE_EIGENVALUE, "smoother eigenvalue estimate not positive");
@@ -491,6 +553,7 @@ static void setup_impl(sa_hierarchy *h, const sa_csr *A, const double *B,
       Lc.is_root = nullptr;
       break;
     }
+    smoother_async(h, l);  // overlaps the Galerkin product and the next levels
     galerkin(h, l, true, dB);
   }
   finish_setup(h, true);
@@ -963,6 +1026,7 @@ sa_status sa_setup_coords(const sa_context *ctx, const sa_csr *A, const double *
       setup_impl(h.get(), A, nullspace, coords, dim);
     } catch (...) {
       (void)hipStreamSynchronize(h->stream);
+      if (h->side) (void)hipStreamSynchronize(h->side);
       throw;
     }
     *out = h.release();
@@ -991,6 +1055,7 @@ sa_status sa_setup_system(const sa_context *ctx, const sa_csr *A, int32_t block_
       setup_impl(h.get(), A, nullptr, coords, dim, block_size, nullspace, k);
     } catch (...) {
       (void)hipStreamSynchronize(h->stream);
+      if (h->side) (void)hipStreamSynchronize(h->side);
       throw;
     }
     *out = h.release();

@@ -33,6 +33,7 @@ struct Level {
   double *sm_invD = nullptr;
   double *sm_lam_d = nullptr;
   double sm_lam = 0.0;
+  bool sm_pending = false;  // sm_invD / sm_lam_d queued on the side stream, not yet joined
   double cheb_theta = 0.0;
   std::vector<double> cheb_c1, cheb_c2;  // per Chebyshev step m = 1..deg-1
   double jac_w = 0.0;
@@ -49,6 +50,7 @@ struct Level {
 
 struct sa_hierarchy {
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;   // side stream used during the setup (see side_stream)
   sa_options opt{};
   sa::Arena ar;
   std::vector<sa::Level> lv;
