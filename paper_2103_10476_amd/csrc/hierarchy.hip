@@ -143,7 +143,10 @@ static void take_values(const Csr &src, Csr &dst, hipStream_t s) {
 // (plain or OffLmp lumping) and smoothing diagonal, eigenvalue estimate and damping,
 // prolongator smoothing and Cnstrnt.  fresh: allocate the level's arrays (setup); otherwise
 // overwrite the values of the existing ones, whose patterns do not change (re-setup).
-static void numeric_level(sa_hierarchy *h, int l, bool fresh) {
+// Numeric part of level l, in three steps (the second can run on the side stream):
+// lumping into Abar and the smoothing diagonal; the damping factor from the power method on
+// D^-1 Abar; the prolongator.
+static void numeric_lump(sa_hierarchy *h, int l, bool fresh) {
   const hipStream_t s = h->stream;
   const sa_options &o = h->opt;
   Level &L = h->lv[l];
@@ -157,22 +160,30 @@ static void numeric_level(sa_hierarchy *h, int l, bool fresh) {
     L.lam_d = ar.alloc<double>(2);
     L.omega_d = L.lam_d + 1;
   }
-  {
-    Csr abar;
-    lump(n, L.As.rp, L.As.col, L.As.val, L.mask, (o.variants & SA_OFFLMP) != 0, o.tau, one_norm,
-         safeguard_mult(o.sigma), L.wave_rows, fresh ? ar : tmp, abar, L.invD, h->err, s);
-    check_err(h, E_ZERO_FDIAG, SA_ERR_NONPOSITIVE_DIAG, "zero diagonal in the filtered matrix");
-    if (fresh) {
-      L.Abar = abar;
-      spmv_plan(L.Abar, ar, s);
-    } else {
-      take_values(abar, L.Abar, s);
-    }
+  Csr abar;
+  lump(n, L.As.rp, L.As.col, L.As.val, L.mask, (o.variants & SA_OFFLMP) != 0, o.tau, one_norm,
+       safeguard_mult(o.sigma), L.wave_rows, fresh ? ar : tmp, abar, L.invD, h->err, s);
+  if (fresh) {
+    L.Abar = abar;
+    spmv_plan(L.Abar, ar, s);
+  } else {
+    take_values(abar, L.Abar, s);
   }
-  const bool unit = one_norm && o.one_norm_power == 0;
+}
+static void numeric_damping(sa_hierarchy *h, int l, hipStream_t s, int32_t *err) {
+  const sa_options &o = h->opt;
+  Level &L = h->lv[l];
+  const bool unit = (o.variants & SA_1NORM) != 0 && o.one_norm_power == 0;
   if (!unit) power_method(L.Abar, L.invD, o.power_iters, o.seed, l, 0, L.lam_d, s);
-  damping(L.lam_d, L.omega_d, unit, h->err, s);
-  check_err(h, E_LAMBDA, SA_ERR_NEGATIVE_EIGENVALUE, "eigenvalue estimate not positive");
+  damping(L.lam_d, L.omega_d, unit, err, s);
+}
+static void numeric_prolong(sa_hierarchy *h, int l, bool fresh) {
+  const hipStream_t s = h->stream;
+  const sa_options &o = h->opt;
+  Level &L = h->lv[l];
+  Arena &ar = h->ar;
+  Arena tmp;
+  tmp.stream = s;
   if (h->k > 0) {  // systems: P = P_t - omega D^-1 Abar P_t
     if (fresh) {
       smooth_tentative(L.Abar, L.Pt, L.invD, L.omega_d, ar, L.P, s);
@@ -193,6 +204,13 @@ static void numeric_level(sa_hierarchy *h, int l, bool fresh) {
   }
   if (o.variants & SA_CNSTRNT) cnstrnt(L.P, L.agg, s);
   if (fresh) spmv_plan(L.P, ar, s);
+}
+static void numeric_level(sa_hierarchy *h, int l, bool fresh) {
+  numeric_lump(h, l, fresh);
+  check_err(h, E_ZERO_FDIAG, SA_ERR_NONPOSITIVE_DIAG, "zero diagonal in the filtered matrix");
+  numeric_damping(h, l, h->stream, h->err);
+  check_err(h, E_LAMBDA, SA_ERR_NEGATIVE_EIGENVALUE, "eigenvalue estimate not positive");
+  numeric_prolong(h, l, fresh);
 }
 
 // Builds level l's strength labels and aggregates, then its numeric part.  Returns false when
@@ -274,12 +292,36 @@ static bool build_level(sa_hierarchy *h, int l) {
   L.agg = ar.alloc<int32_t>(n);
   L.is_root = ar.alloc<uint8_t>(n);
   int32_t *root_vertex = nullptr;
+  if (o.variants & SA_SPRSFY) {  // the drops change the labels lumping reads: in sequence
+    L.nc = aggregate(n, nnzG, grp, gcol, o.agg_order, o.seed, l, L.agg, L.is_root, tmp,
+                     &root_vertex, &L.mis_rounds, s);
+    if (L.nc == 0) return false;
+    if (L.nc >= n) throw Error(SA_ERR_COARSEN_STALLED, "coarsening stalled");
+    sprsfy(n, L.As.rp, L.As.col, L.mask, L.agg, root_vertex, L.nc, s);
+    numeric_level(h, l, true);
+    return true;
+  }
+  // Lumping needs the labels only, so it runs before the aggregation, and the power method
+  // for the damping factor runs on the side stream (its own error word) while the root
+  // selection runs here.  Errors are checked in the sequential order afterwards; a level that
+  // turns out to be the coarsest ignores the lumping.
+  numeric_lump(h, l, true);
+  if (!h->side) h->side = side_stream(s);
+  stream_after(h->side, s);
+  numeric_damping(h, l, h->side, h->err + 2);
   L.nc = aggregate(n, nnzG, grp, gcol, o.agg_order, o.seed, l, L.agg, L.is_root, tmp, &root_vertex,
                    &L.mis_rounds, s);
-  if (L.nc == 0) return false;
+  stream_after(s, h->side);
+  if (L.nc == 0) {  // the coarsest level keeps no numeric part
+    L.Abar = Csr{};
+    L.invD = L.lam_d = L.omega_d = nullptr;
+    return false;
+  }
   if (L.nc >= n) throw Error(SA_ERR_COARSEN_STALLED, "coarsening stalled");
-  if (o.variants & SA_SPRSFY) sprsfy(n, L.As.rp, L.As.col, L.mask, L.agg, root_vertex, L.nc, s);
-  numeric_level(h, l, true);
+  check_err(h, E_ZERO_FDIAG, SA_ERR_NONPOSITIVE_DIAG, "zero diagonal in the filtered matrix");
+  if (read1(h->err + 2, s) & E_LAMBDA)
+    throw Error(SA_ERR_NEGATIVE_EIGENVALUE, "eigenvalue estimate not positive");
+  numeric_prolong(h, l, true);
   return true;
 }
 
