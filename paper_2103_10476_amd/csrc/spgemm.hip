@@ -588,8 +588,9 @@ static int32_t lds_cols_max() {
 }
 
 // Short rows: a wavefront takes 64 consecutive rows, whose entries are one contiguous run of
-// C; lanes copy consecutive entries (coalesced writes), each finding its row by binary
-// search over the 64 row starts held in LDS.
+// C.  At most 16 entries per row on average: lanes copy consecutive entries (coalesced
+// writes), each finding its row by binary search over the 64 row starts held in LDS; more:
+// row by row, 64 lanes per row (both sides contiguous).
 __global__ __launch_bounds__(kBlock) void k_compact_w(int32_t m, const int64_t *poff,
                                                       const int32_t *crp, const int32_t *ocol,
                                                       const double *oval, int32_t *ccol,
@@ -604,17 +605,28 @@ __global__ __launch_bounds__(kBlock) void k_compact_w(int32_t m, const int64_t *
   if (lane == 0) s_rp[w][64] = crp[r0 + 64 < m ? r0 + 64 : m];
   s_po[w][lane] = row < m ? poff[row] : 0;
   __syncthreads();
-  const int32_t d1 = s_rp[w][64];
-  for (int32_t d = s_rp[w][0] + lane; d < d1; d += 64) {
-    int32_t lo = 0, hi = 63;  // last row r with s_rp[r] <= d (empty rows share starts)
-    while (lo < hi) {
-      const int32_t mid = (lo + hi + 1) >> 1;
-      if (s_rp[w][mid] <= d) lo = mid;
-      else hi = mid - 1;
+  const int32_t d0 = s_rp[w][0], d1 = s_rp[w][64];
+  if (d1 - d0 <= 64 * 16) {  // wave-uniform: short rows, one search per entry
+    for (int32_t d = d0 + lane; d < d1; d += 64) {
+      int32_t lo = 0, hi = 63;  // last row r with s_rp[r] <= d (empty rows share starts)
+      while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (s_rp[w][mid] <= d) lo = mid;
+        else hi = mid - 1;
+      }
+      const int64_t src = s_po[w][lo] + (d - s_rp[w][lo]);
+      ccol[d] = ocol[src];
+      cval[d] = oval[src];
     }
-    const int64_t src = s_po[w][lo] + (d - s_rp[w][lo]);
-    ccol[d] = ocol[src];
-    cval[d] = oval[src];
+  } else {  // longer rows: row by row, 64 lanes per row
+    for (int r = 0; r < 64; ++r) {
+      const int32_t rb = s_rp[w][r], re = s_rp[w][r + 1];
+      const int64_t shift = s_po[w][r] - rb;
+      for (int32_t d = rb + lane; d < re; d += 64) {
+        ccol[d] = ocol[shift + d];
+        cval[d] = oval[shift + d];
+      }
+    }
   }
 }
 
@@ -744,7 +756,7 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
   C.col = ar.alloc<int32_t>(C.nnz);
   C.val = ar.alloc<double>(C.nnz);
   if (C.nnz > 0) {
-    if (C.nnz <= 32 * (int64_t)m)
+    if (C.nnz <= 20 * (int64_t)m)  // short rows on average: wavefronts over 64 rows
       k_compact_w<<<(unsigned)ceil_div(m, kBlock), kBlock, 0, s>>>(m, poff, C.rp, ocol, oval,
                                                                  C.col, C.val);
     else
