@@ -103,6 +103,7 @@ struct Csr {
   double *val = nullptr;
   int32_t *bstart = nullptr;  // SpMV plan: nblk+1 pairs (first row, first entry)
   int32_t nblk = 0;
+  int32_t maxrow = -1;        // longest row when known (the pattern's, kept by value updates)
 };
 
 // Sliced-ELL copy of a CSR operator for the solve-phase SpMV.  Rows in slices of 64 (one per

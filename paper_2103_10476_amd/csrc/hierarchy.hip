@@ -240,7 +240,8 @@ static bool build_level_system(sa_hierarchy *h, int l) {
   } else {
     block_strength(L.As, bs, L.Gn, o.theta, L.nmask, scount, s);
   }
-  L.wave_rows = max_row_length(n, L.As.rp, s) > 64 || L.As.nnz > 24 * (int64_t)n;
+  L.As.maxrow = L.A.maxrow = max_row_length(n, L.As.rp, s);  // A and As share the pattern
+  L.wave_rows = L.As.maxrow > 64 || L.As.nnz > 24 * (int64_t)n;
   L.mask = ar.alloc<uint8_t>(L.As.nnz);
   dof_mask(L.As, bs, L.Gn, L.nmask, L.mask, s);
   int32_t *grp = nullptr, *gcol = nullptr;
@@ -281,7 +282,8 @@ static bool build_level(sa_hierarchy *h, int l) {
     find_diag(n, L.As.rp, L.As.col, L.As.val, dval, s);
   }
   // rows long enough to leave thread-per-row kernels serial: one wavefront per row instead
-  L.wave_rows = max_row_length(n, L.As.rp, s) > 64 || L.As.nnz > 24 * (int64_t)n;
+  L.As.maxrow = L.A.maxrow = max_row_length(n, L.As.rp, s);  // A and As share the pattern
+  L.wave_rows = L.As.maxrow > 64 || L.As.nnz > 24 * (int64_t)n;
   L.mask = ar.alloc<uint8_t>(L.As.nnz);
   int32_t *scount = tmp.alloc<int32_t>(n + 1);
   strength(n, L.As.rp, L.As.col, sval, dval, o.theta * o.theta, L.mask, scount, L.wave_rows,
@@ -318,9 +320,11 @@ static bool build_level(sa_hierarchy *h, int l) {
     return false;
   }
   if (L.nc >= n) throw Error(SA_ERR_COARSEN_STALLED, "coarsening stalled");
-  check_err(h, E_ZERO_FDIAG, SA_ERR_NONPOSITIVE_DIAG, "zero diagonal in the filtered matrix");
-  if (read1(h->err + 2, s) & E_LAMBDA)
-    throw Error(SA_ERR_NEGATIVE_EIGENVALUE, "eigenvalue estimate not positive");
+  int32_t ew[4];  // main word (lumping) and the damping word, in one readback
+  readback(ew, h->err, sizeof(ew), s);
+  if (ew[0] & E_ZERO_FDIAG)
+    throw Error(SA_ERR_NONPOSITIVE_DIAG, "zero diagonal in the filtered matrix");
+  if (ew[2] & E_LAMBDA) throw Error(SA_ERR_NEGATIVE_EIGENVALUE, "eigenvalue estimate not positive");
   numeric_prolong(h, l, true);
   return true;
 }
@@ -364,6 +368,17 @@ static void galerkin(sa_hierarchy *h, int l, bool fresh, const double *dB) {
     spgemm(L.R, AP, tmp, Ac, s);
     take_values(Ac, h->lv[l + 1].A, s);  // As shares A's arrays on coarse levels
   }
+}
+
+// Scalars scattered over the levels, copied into one buffer for a single readback.
+constexpr int kMaxGather = 48;  // 3 per level, at most 16 levels
+struct ScalarGather {
+  const double *p[kMaxGather];
+  int32_t n;
+};
+__global__ void k_gather_scalars(ScalarGather g, double *out) {
+  const int i = threadIdx.x;
+  if (i < g.n) out[i] = g.p[i] ? *g.p[i] : 0.0;
 }
 
 // GPU part of level l's smoother set-up on stream s: the inverse diagonal of A_l and the
@@ -411,24 +426,40 @@ static void finish_setup(sa_hierarchy *h, bool fresh) {
       joined = true;
     }
   }
-  if (joined) {
-    const int32_t e = read1(h->err + 1, s);  // the side stream's error word
-    if (e & E_DIAG) throw Error(SA_ERR_NONPOSITIVE_DIAG, "non-positive diagonal in a level operator");
+  // the error words (main and side stream) and every level's eigenvalue and damping scalars
+  // in two readbacks; the checks keep the level-by-level order
+  int32_t ew[4];
+  readback(ew, h->err, sizeof(ew), s);
+  if ((ew[0] | ew[1]) & E_DIAG)
+    throw Error(SA_ERR_NONPOSITIVE_DIAG, "non-positive diagonal in a level operator");
+  std::vector<double> sc;
+  if (nl > 1) {
+    ScalarGather g{};
+    for (int l = 0; l + 1 < nl; ++l) {
+      g.p[3 * l] = h->lv[l].sm_lam_d;
+      g.p[3 * l + 1] = h->lv[l].lam_d;
+      g.p[3 * l + 2] = h->lv[l].lam_d ? h->lv[l].lam_d + 1 : nullptr;
+    }
+    g.n = 3 * (nl - 1);
+    Arena tmp;
+    tmp.stream = s;
+    double *d = tmp.alloc<double>(g.n);
+    k_gather_scalars<<<1, 64, 0, s>>>(g, d);
+    SA_LAUNCH_CHECK();
+    sc.resize(g.n);
+    readback(sc.data(), d, sizeof(double) * g.n, s);
   }
   for (int l = 0; l + 1 < nl; ++l) {
     Level &L = h->lv[l];
     L.sm_pending = false;
-    check_err(h, E_DIAG, SA_ERR_NONPOSITIVE_DIAG, "non-positive diagonal in a level operator");
-    const double lam = read1(L.sm_lam_d, s);
+    const double lam = sc[3 * l];
     if (!(lam > 0.0) || !std::isfinite(lam))
       throw Error(SA_ERR_NEGATIVE_EIGENVALUE, "smoother eigenvalue estimate not positive");
     L.sm_lam = lam * o.cheb_boost;
     chebyshev_scalars(L, o);
     if (L.lam_d) {
-      double lo[2];
-      readback(lo, L.lam_d, sizeof(lo), s);
-      L.lam = lo[0];
-      L.omega = lo[1];
+      L.lam = sc[3 * l + 1];
+      L.omega = sc[3 * l + 2];
     }
   }
   Level &Lc = h->lv[nl - 1];

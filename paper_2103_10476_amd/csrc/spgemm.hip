@@ -674,13 +674,14 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
   const int32_t m = X.n;
   C.n = m;
   C.ncols = Y.ncols;
+  C.maxrow = -1;
   Arena tmp;
   tmp.stream = s;
   int64_t *cnt = tmp.alloc<int64_t>(m + 1);
   int32_t *xpref = tmp.alloc<int32_t>(X.nnz > 0 ? X.nnz : 1);
   int64_t *poff = tmp.alloc<int64_t>(m + 1);
   if (m > 0) {
-    if (max_row_length(m, X.rp, s) > 64)
+    if ((X.maxrow >= 0 ? X.maxrow : max_row_length(m, X.rp, s)) > 64)
       k_count_products_w<<<(unsigned)m, 64, 0, s>>>(m, X.rp, X.col, Y.rp, cnt, xpref);
     else
       k_count_products<<<grid_for(m), kBlock, 0, s>>>(m, X.rp, X.col, Y.rp, cnt, xpref);
