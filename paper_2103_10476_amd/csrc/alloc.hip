@@ -165,54 +165,61 @@ void dev_cache_stats(size_t *in_use, size_t *cached) {
 // ---- pinned staging for readbacks ---------------------------------------------------------
 // Copies into pageable host memory go through a driver bounce buffer and cost ~100 us each;
 // each thread stages readbacks in a pinned buffer of its own instead.  Buffers are recycled
-// through a process-wide list when their thread ends (no HIP call at thread exit).
+// through a process-wide list when their thread ends (no HIP call at thread exit).  A second
+// per-thread buffer, coherent (fine-grained: kernels' system-scope stores reach it without a
+// synchronise), holds status words that the thread polls while kernels run.
 namespace {
 struct PinnedPool {
   std::mutex mu;
-  std::vector<std::pair<void *, size_t>> spare;
+  std::vector<std::pair<void *, size_t>> spare[2];  // [0] default, [1] coherent
 };
 PinnedPool &pinned_pool() {
   static PinnedPool *p = new PinnedPool;
   return *p;
 }
 struct PinnedHolder {
+  int kind;  // 0 default, 1 coherent
   void *p = nullptr;
   size_t n = 0;
+  explicit PinnedHolder(int k) : kind(k) {}
   ~PinnedHolder() {
     if (!p) return;
     PinnedPool &pp = pinned_pool();
     std::lock_guard<std::mutex> lk(pp.mu);
-    pp.spare.emplace_back(p, n);
+    pp.spare[kind].emplace_back(p, n);
   }
 };
-thread_local PinnedHolder t_pinned;
-}  // namespace
+thread_local PinnedHolder t_pinned(0), t_status(1);
 
-void *pinned_staging(size_t bytes) {
-  PinnedHolder &h = t_pinned;
+void *pinned_buffer(PinnedHolder &h, size_t bytes) {
   if (h.p && h.n >= bytes) return h.p;
   {
     PinnedPool &pp = pinned_pool();
     std::lock_guard<std::mutex> lk(pp.mu);
-    if (h.p) pp.spare.emplace_back(h.p, h.n);
+    auto &spare = pp.spare[h.kind];
+    if (h.p) spare.emplace_back(h.p, h.n);
     h.p = nullptr;
     h.n = 0;
-    for (size_t i = 0; i < pp.spare.size(); ++i)
-      if (pp.spare[i].second >= bytes) {
-        h.p = pp.spare[i].first;
-        h.n = pp.spare[i].second;
-        pp.spare.erase(pp.spare.begin() + (ptrdiff_t)i);
+    for (size_t i = 0; i < spare.size(); ++i)
+      if (spare[i].second >= bytes) {
+        h.p = spare[i].first;
+        h.n = spare[i].second;
+        spare.erase(spare.begin() + (ptrdiff_t)i);
         return h.p;
       }
   }
   size_t n = 4096;
   while (n < bytes) n *= 2;
   void *p = nullptr;
-  SA_HIP(hipHostMalloc(&p, n, hipHostMallocDefault));
+  SA_HIP(hipHostMalloc(&p, n, h.kind ? hipHostMallocCoherent : hipHostMallocDefault));
   h.p = p;
   h.n = n;
   return p;
 }
+}  // namespace
+
+void *pinned_staging(size_t bytes) { return pinned_buffer(t_pinned, bytes); }
+void *pinned_status(size_t bytes) { return pinned_buffer(t_status, bytes); }
 
 // Small readbacks: one workgroup copies the words straight into the pinned staging buffer
 // through its device mapping (cheaper than the runtime's copy kernel for a few bytes).

@@ -60,6 +60,9 @@ void meter_end();
 void meter_read(const Meter *m, int64_t *live, int64_t *peak);  // consistent snapshot
 // Blocking device-to-host copy staged through a per-thread pinned buffer.
 void readback(void *host, const void *dev, size_t bytes, hipStream_t s);
+// A per-thread pinned host buffer of at least `bytes`, separate from the readback staging:
+// kernels write it through its device mapping while the calling thread polls it.
+void *pinned_status(size_t bytes);
 
 // A typed device buffer owned by an Arena or held as a temporary.
 template <class T>

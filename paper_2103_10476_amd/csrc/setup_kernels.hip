@@ -7,6 +7,7 @@
 // time, so the setup is deterministic and equal to the sequential definition bit for bit.
 // Setup kernels are one thread per row (rows hold 5-30 entries on the fine levels); they
 // run once per level and are bound by HBM traffic or by the level's size.
+#include <chrono>
 #include <climits>
 
 #include "kernels.hpp"
@@ -466,7 +467,16 @@ __global__ void k_mis_pass1(int32_t n, const int32_t *__restrict__ grp,
                             const int32_t *__restrict__ gcol, const K *__restrict__ key,
                             K *__restrict__ k1, const uint8_t *__restrict__ st1,
                             uint8_t *__restrict__ st2, uint8_t sr, bool first,
-                            const int32_t *__restrict__ prev) {
+                            const int32_t *__restrict__ prev, int32_t *__restrict__ cur,
+                            uint32_t *hstat, uint32_t tag) {
+  // one thread clears this round's flag (pass 2 raises it) and posts the previous round's
+  // outcome to the host's status word: tag | 1 if it changed a key, tag | 2 if not
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *cur = 0;
+    if (hstat)
+      __hip_atomic_store(hstat, tag | (*prev == 0 ? 2u : 1u), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+  }
   // the stamp and the previous round's flag are read together (one round trip); a round
   // whose predecessor changed nothing exits
   if (WAVE) {
@@ -723,51 +733,83 @@ static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const
   uint8_t *st2 = tmp.alloc<uint8_t>(n);
   k_mis_init<K><<<grid_for(n), kBlock, 0, s>>>(n, grp, order, seed, level, key, st1, st2);
   SA_LAUNCH_CHECK();
-  // Rounds run in batches between flag checks: flags[q] = 1 iff round q of the batch changed
-  // some key.  A round whose predecessor changed nothing exits at once, so rounds past the
-  // end of the selection cost only their launch; batches grow 16, 32, 64, 64, ... to bound
-  // both the readbacks and that overshoot.
-  constexpr int kMaxBatch = 64;
+  // Rounds are launched back to back, at most kAhead past the last round whose outcome the
+  // host has seen.  Pass 1 of round r+1 posts round r's outcome into a pinned status ring
+  // (slot r mod kRing, tagged with r); the first round that changed nothing ends the
+  // selection, and the rounds still queued behind it exit at once.  Device flags live in a
+  // ring of the same size: pass 1 of round r clears slot r, pass 2 raises it.  If a status
+  // word is not seen within kSpinNs, the stream is synchronised and the device flags read
+  // instead, so the outcome never depends on the host mapping alone.
+  constexpr int kRing = 256, kAhead = 6;
+  constexpr int64_t kSpinNs = 20000000;
   // every round before the last decides at least one vertex, so this bound is never reached
-  const int64_t cap = (int64_t)n + 2 + 2 * kMaxBatch;
-  int32_t *flags = tmp.alloc<int32_t>(kMaxBatch);
+  const int64_t cap = (int64_t)n + 2 + 2 * kAhead;
+  int32_t *flags = tmp.alloc<int32_t>(kRing);
+  volatile uint32_t *hs = (volatile uint32_t *)pinned_status(sizeof(uint32_t) * kRing);
+  for (int q = 0; q < kRing; ++q) hs[q] = ~0u;
+  uint32_t *hs_dev = nullptr;
+  SA_HIP(hipHostGetDevicePointer((void **)&hs_dev, (void *)hs, 0));
   const int32_t maxdeg = max_row_length(n, grp, s);
   const bool wave = maxdeg > 64 || nnzG > 24 * (int64_t)n;
   const unsigned g = wave ? grid_for((int64_t)n * 64) : grid_for(n);
-  int32_t hflags[kMaxBatch];
-  int64_t r = 0;
-  int32_t used = 0;
-  int batch = 16;
-  bool done = nnzG == 0;
-  while (!done) {
-    if (r >= cap) throw Error(SA_ERR_COARSEN_STALLED, "root selection did not end");
-    fill_i32(flags, 0, batch, s);
-    for (int q = 0; q < batch; ++q) {
-      const int32_t *prev = q > 0 ? flags + q - 1 : nullptr;
-      const uint8_t sr = (uint8_t)((r + q) & 255), srn = (uint8_t)((r + q + 1) & 255);
-      const bool first = r + q == 0;
-      if (wave) {
-        k_mis_pass1<K, true><<<g, kBlock, 0, s>>>(n, grp, gcol, key, k1, st1, st2, sr, first,
-                                                   prev);
-        k_mis_pass2<K, true><<<g, kBlock, 0, s>>>(n, grp, gcol, k1, key, st2, st1, sr, srn,
-                                                   flags + q, prev);
-      } else {
-        k_mis_pass1<K, false><<<g, kBlock, 0, s>>>(n, grp, gcol, key, k1, st1, st2, sr, first,
-                                                    prev);
-        k_mis_pass2<K, false><<<g, kBlock, 0, s>>>(n, grp, gcol, k1, key, st2, st1, sr, srn,
-                                                    flags + q, prev);
-      }
+  auto launch_round = [&](int64_t r) {
+    const uint8_t sr = (uint8_t)(r & 255), srn = (uint8_t)((r + 1) & 255);
+    const bool first = r == 0;
+    const int32_t *prev = first ? nullptr : flags + ((r - 1) & (kRing - 1));
+    int32_t *cur = flags + (r & (kRing - 1));
+    uint32_t *post = first ? nullptr : hs_dev + ((r - 1) & (kRing - 1));
+    const uint32_t tag = (uint32_t)(r - 1) << 2;
+    if (wave) {
+      k_mis_pass1<K, true><<<g, kBlock, 0, s>>>(n, grp, gcol, key, k1, st1, st2, sr, first,
+                                                 prev, cur, post, tag);
+      k_mis_pass2<K, true><<<g, kBlock, 0, s>>>(n, grp, gcol, k1, key, st2, st1, sr, srn, cur,
+                                                 prev);
+    } else {
+      k_mis_pass1<K, false><<<g, kBlock, 0, s>>>(n, grp, gcol, key, k1, st1, st2, sr, first,
+                                                  prev, cur, post, tag);
+      k_mis_pass2<K, false><<<g, kBlock, 0, s>>>(n, grp, gcol, k1, key, st2, st1, sr, srn,
+                                                  cur, prev);
     }
     SA_LAUNCH_CHECK();
-    readback(hflags, flags, sizeof(int32_t) * batch, s);
-    for (int q = 0; q < batch; ++q)
-      if (hflags[q] == 0) {  // round r+q changed nothing: r+q rounds made the selection
-        used = (int32_t)(r + q);
-        done = true;
-        break;
+  };
+  int64_t launched = 0, seen = 0;  // rounds launched; rounds whose outcome is known
+  int32_t used = 0;
+  bool done = nnzG == 0;
+  auto wait_from = std::chrono::steady_clock::now();
+  while (!done) {
+    // round `seen`'s status is posted by pass 1 of round seen+1
+    if (launched >= seen + 2) {
+      const uint32_t v = hs[seen & (kRing - 1)];
+      if ((v & ~3u) == ((uint32_t)seen << 2) && (v & 3u) != 0 && v != ~0u) {
+        if ((v & 3u) == 2u) {
+          used = (int32_t)seen;
+          done = true;
+        } else {
+          ++seen;
+        }
+        wait_from = std::chrono::steady_clock::now();
+        continue;
       }
-    r += batch;
-    batch = batch * 2 > kMaxBatch ? kMaxBatch : batch * 2;
+    }
+    if (launched < seen + kAhead) {
+      if (launched >= cap) throw Error(SA_ERR_COARSEN_STALLED, "root selection did not end");
+      launch_round(launched++);
+      continue;
+    }
+    const auto now = std::chrono::steady_clock::now();
+    if (std::chrono::duration_cast<std::chrono::nanoseconds>(now - wait_from).count() <
+        kSpinNs)
+      continue;
+    // status not seen in time: every launched round's flag is final after a synchronise
+    int32_t hf[kRing];
+    readback(hf, flags, sizeof(hf), s);
+    for (; seen < launched && !done; ++seen)
+      if (hf[seen & (kRing - 1)] == 0) {
+        used = (int32_t)seen;
+        done = true;
+      }
+    if (done) break;
+    wait_from = std::chrono::steady_clock::now();
   }
   if (rounds_out) *rounds_out = used;
   int32_t *isr = tmp.alloc<int32_t>(n + 1);
