@@ -9,6 +9,7 @@
 // run once per level and are bound by HBM traffic or by the level's size.
 #include <chrono>
 #include <climits>
+#include <cstdlib>
 
 #include "kernels.hpp"
 
@@ -738,10 +739,12 @@ static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const
   // (slot r mod kRing, tagged with r); the first round that changed nothing ends the
   // selection, and the rounds still queued behind it exit at once.  Device flags live in a
   // ring of the same size: pass 1 of round r clears slot r, pass 2 raises it.  If a status
-  // word is not seen within kSpinNs, the stream is synchronised and the device flags read
-  // instead, so the outcome never depends on the host mapping alone.
+  // word is not seen within spin_ns (20 ms; the environment variable SAAMG_STATUS_SPIN_NS
+  // overrides it, 0 taking the fallback at every wait), the stream is synchronised and the
+  // device flags read instead, so the outcome never depends on the host mapping alone.
   constexpr int kRing = 256, kAhead = 6;
-  constexpr int64_t kSpinNs = 20000000;
+  int64_t spin_ns = 20000000;
+  if (const char *e = std::getenv("SAAMG_STATUS_SPIN_NS")) spin_ns = std::atoll(e);
   // every round before the last decides at least one vertex, so this bound is never reached
   const int64_t cap = (int64_t)n + 2 + 2 * kAhead;
   int32_t *flags = tmp.alloc<int32_t>(kRing);
@@ -798,7 +801,7 @@ static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const
     }
     const auto now = std::chrono::steady_clock::now();
     if (std::chrono::duration_cast<std::chrono::nanoseconds>(now - wait_from).count() <
-        kSpinNs)
+        spin_ns)
       continue;
     // status not seen in time: every launched round's flag is final after a synchronise
     int32_t hf[kRing];
