@@ -844,6 +844,20 @@ int32_t aggregate(int32_t n, int64_t nnzG, const int32_t *grp, const int32_t *gc
 // ---- Sprsfy (Sec. 2.5) --------------------------------------------------------------------
 constexpr int32_t kSprsfyShort = 32;   // root rows up to this length: one thread per aggregate
 constexpr int32_t kSprsfyLds = 4096;   // longer root rows (up to this): one block per aggregate
+// ... unless the non-root members' rows hold more than this many entries in all: a thread
+// scans them once per candidate, so such aggregates also take the block path
+constexpr int32_t kSprsfyMemberWork = 256;
+
+// Entries in the rows of J's non-root members (both Sprsfy kernels route on it).
+__device__ inline int32_t sprsfy_member_entries(int32_t J, int32_t r, const int32_t *rp,
+                                                const int32_t *mrp, const int32_t *mem) {
+  int32_t w = 0;
+  for (int32_t m = mrp[J]; m < mrp[J + 1]; ++m) {
+    const int32_t v = mem[m];
+    if (v != r) w += rp[v + 1] - rp[v];
+  }
+  return w;
+}
 // One thread per aggregate J with root r.  Candidates: aggregates reached by r's weak
 // connections but by none of its strong ones, J excluded.  For a candidate c, a single strong
 // connection from a non-root member of J into c is dropped with its transpose.  Decisions read
@@ -857,7 +871,10 @@ __global__ void k_sprsfy(int32_t nc, const int32_t *rp, const int32_t *col, uint
   const int32_t J = (int32_t)J64;
   const int32_t r = root_vertex[J];
   const int32_t rb = rp[r], re = rp[r + 1];
-  if (re - rb > kSprsfyShort) return;  // long root rows: k_sprsfy_block
+  // long root rows and heavy members: k_sprsfy_block
+  if (re - rb > kSprsfyShort ||
+      sprsfy_member_entries(J, r, rp, mrp, mem) > kSprsfyMemberWork)
+    return;
   for (int32_t k = rb; k < re; ++k) {
     const int32_t u0 = col[k];
     if (u0 == r || mask[k] != 0) continue;  // weak connections of the root only
@@ -944,7 +961,9 @@ __global__ __launch_bounds__(kBlock) void k_sprsfy_block(int32_t nc, const int32
   const int32_t r = root_vertex[J];
   const int32_t rb = rp[r], re = rp[r + 1];
   const int32_t len = re - rb;
-  if (len <= kSprsfyShort) return;
+  // the aggregates k_sprsfy leaves (every thread computes the same sum: block-uniform)
+  if (len <= kSprsfyShort && sprsfy_member_entries(J, r, rp, mrp, mem) <= kSprsfyMemberWork)
+    return;
   if (len > kSprsfyLds) {
     if (threadIdx.x == 0) atomicOr(overflow, 1);
     return;
@@ -1059,7 +1078,10 @@ void sprsfy(int32_t n, const int32_t *rp, const int32_t *col, uint8_t *mask, con
   fill_i32(ovf, 0, 1, s);
   k_sprsfy<<<grid_for(nc), kBlock, 0, s>>>(nc, rp, col, mask, agg, root_vertex, mrp, mem);
   SA_LAUNCH_CHECK();
-  if (max_row_length(n, rp, s) > kSprsfyShort) {
+  // the block kernel has work if a root row is long or some members' entries can exceed
+  // kSprsfyMemberWork (bounded by the longest row times the largest aggregate)
+  const int64_t maxrow = max_row_length(n, rp, s);
+  if (maxrow > kSprsfyShort || maxrow * max_row_length(nc, mrp, s) > kSprsfyMemberWork) {
     k_sprsfy_block<<<(unsigned)nc, kBlock, 0, s>>>(nc, rp, col, mask, agg, root_vertex, mrp,
                                                    mem, ovf);
     SA_LAUNCH_CHECK();
