@@ -846,35 +846,32 @@ constexpr int32_t kSprsfyShort = 32;   // root rows up to this length: one threa
 constexpr int32_t kSprsfyLds = 4096;   // longer root rows (up to this): one block per aggregate
 // ... unless the non-root members' rows hold more than this many entries in all: a thread
 // scans them once per candidate, so such aggregates also take the block path
-constexpr int32_t kSprsfyMemberWork = 256;
-
-// Entries in the rows of J's non-root members (both Sprsfy kernels route on it).
-__device__ inline int32_t sprsfy_member_entries(int32_t J, int32_t r, const int32_t *rp,
-                                                const int32_t *mrp, const int32_t *mem) {
-  int32_t w = 0;
-  for (int32_t m = mrp[J]; m < mrp[J + 1]; ++m) {
-    const int32_t v = mem[m];
-    if (v != r) w += rp[v + 1] - rp[v];
-  }
-  return w;
-}
+constexpr int32_t kSprsfyMemberWork = 128;
 // One thread per aggregate J with root r.  Candidates: aggregates reached by r's weak
 // connections but by none of its strong ones, J excluded.  For a candidate c, a single strong
 // connection from a non-root member of J into c is dropped with its transpose.  Decisions read
 // "strong" as mask 1 or 2, so concurrent drops by other aggregates do not change them; the
-// result does not depend on member order.
+// result depends neither on member order nor on the order in which aggregates are taken.
+// Aggregates with a long root row or heavy members are appended to heavy[] (count in *nheavy)
+// for k_sprsfy_block.
 __global__ void k_sprsfy(int32_t nc, const int32_t *rp, const int32_t *col, uint8_t *mask,
                          const int32_t *agg, const int32_t *root_vertex, const int32_t *mrp,
-                         const int32_t *mem) {
+                         const int32_t *mem, int32_t *heavy, int32_t *nheavy) {
   const int64_t J64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (J64 >= nc) return;
   const int32_t J = (int32_t)J64;
   const int32_t r = root_vertex[J];
   const int32_t rb = rp[r], re = rp[r + 1];
-  // long root rows and heavy members: k_sprsfy_block
-  if (re - rb > kSprsfyShort ||
-      sprsfy_member_entries(J, r, rp, mrp, mem) > kSprsfyMemberWork)
+  bool long_row = re - rb > kSprsfyShort;
+  int32_t w = 0;  // entries in the non-root members' rows
+  for (int32_t m = mrp[J]; m < mrp[J + 1] && !long_row; ++m) {
+    const int32_t v = mem[m];
+    if (v != r) w += rp[v + 1] - rp[v];
+  }
+  if (long_row || w > kSprsfyMemberWork) {
+    heavy[atomicAdd(nheavy, 1)] = J;
     return;
+  }
   for (int32_t k = rb; k < re; ++k) {
     const int32_t u0 = col[k];
     if (u0 == r || mask[k] != 0) continue;  // weak connections of the root only
@@ -922,11 +919,11 @@ __global__ void k_sprsfy(int32_t nc, const int32_t *rp, const int32_t *col, uint
   }
 }
 
-// Aggregates whose root row is long: the root row's (aggregate, strong) pairs are sorted in
-// LDS; a candidate is an aggregate reached only through weak entries (not J, not unaggregated).
-// Strong entries of the non-root members are counted per candidate (binary search in the
-// sorted candidate list); a count of 1 drops that entry and its transpose.  Same decisions
-// as k_sprsfy.
+// The aggregates k_sprsfy lists (a long root row or heavy members), one block each: the root
+// row's (aggregate, strong) pairs are sorted in LDS; a candidate is an aggregate reached only
+// through weak entries (not J, not unaggregated).  Strong entries of the non-root members are
+// counted per candidate (binary search in the sorted candidate list); a count of 1 drops that
+// entry and its transpose.  Same decisions as k_sprsfy.
 __device__ inline void bitonic_u64_blk(uint64_t *a, int32_t L) {
   for (int32_t k = 2; k <= L; k <<= 1) {
     for (int32_t j = k >> 1; j > 0; j >>= 1) {
@@ -945,7 +942,8 @@ __device__ inline void bitonic_u64_blk(uint64_t *a, int32_t L) {
     }
   }
 }
-__global__ __launch_bounds__(kBlock) void k_sprsfy_block(int32_t nc, const int32_t *rp,
+__global__ __launch_bounds__(kBlock) void k_sprsfy_block(const int32_t *heavy,
+                                                         const int32_t *rp,
                                                          const int32_t *col, uint8_t *mask,
                                                          const int32_t *agg,
                                                          const int32_t *root_vertex,
@@ -956,14 +954,10 @@ __global__ __launch_bounds__(kBlock) void k_sprsfy_block(int32_t nc, const int32
   __shared__ int32_t cnt[kSprsfyLds];
   __shared__ int32_t edge[kSprsfyLds];
   __shared__ int32_t s_nc;
-  const int32_t J = blockIdx.x;
-  if (J >= nc) return;
+  const int32_t J = heavy[blockIdx.x];
   const int32_t r = root_vertex[J];
   const int32_t rb = rp[r], re = rp[r + 1];
   const int32_t len = re - rb;
-  // the aggregates k_sprsfy leaves (every thread computes the same sum: block-uniform)
-  if (len <= kSprsfyShort && sprsfy_member_entries(J, r, rp, mrp, mem) <= kSprsfyMemberWork)
-    return;
   if (len > kSprsfyLds) {
     if (threadIdx.x == 0) atomicOr(overflow, 1);
     return;
@@ -1074,20 +1068,20 @@ void sprsfy(int32_t n, const int32_t *rp, const int32_t *col, uint8_t *mask, con
   tmp.stream = s;
   int32_t *mrp, *mem;
   member_lists(n, agg, nc, false, tmp, &mrp, &mem, s);  // decisions ignore member order
-  int32_t *ovf = tmp.alloc<int32_t>(1);
-  fill_i32(ovf, 0, 1, s);
-  k_sprsfy<<<grid_for(nc), kBlock, 0, s>>>(nc, rp, col, mask, agg, root_vertex, mrp, mem);
+  int32_t *words = tmp.alloc<int32_t>(2);  // [0] heavy count, [1] overflow
+  int32_t *heavy = tmp.alloc<int32_t>(nc);
+  fill_i32(words, 0, 2, s);
+  k_sprsfy<<<grid_for(nc), kBlock, 0, s>>>(nc, rp, col, mask, agg, root_vertex, mrp, mem,
+                                           heavy, words);
   SA_LAUNCH_CHECK();
-  // the block kernel has work if a root row is long or some members' entries can exceed
-  // kSprsfyMemberWork (bounded by the longest row times the largest aggregate)
-  const int64_t maxrow = max_row_length(n, rp, s);
-  if (maxrow > kSprsfyShort || maxrow * max_row_length(nc, mrp, s) > kSprsfyMemberWork) {
-    k_sprsfy_block<<<(unsigned)nc, kBlock, 0, s>>>(nc, rp, col, mask, agg, root_vertex, mrp,
-                                                   mem, ovf);
+  const int32_t nheavy = read1(words, s);
+  if (nheavy > 0) {
+    k_sprsfy_block<<<(unsigned)nheavy, kBlock, 0, s>>>(heavy, rp, col, mask, agg, root_vertex,
+                                                       mrp, mem, words + 1);
     SA_LAUNCH_CHECK();
+    if (read1(words + 1, s))
+      throw Error(SA_ERR_INVALID_ARG, "Sprsfy: a root row exceeds the supported length");
   }
-  if (read1(ovf, s))
-    throw Error(SA_ERR_INVALID_ARG, "Sprsfy: a root row exceeds the supported length");
 }
 
 // ---- filtered matrix (Sec. 1.1 plain lumping; Sec. 2.3 Algorithm 2) and its diagonal -----
