@@ -140,9 +140,12 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(int32_t ld, int32_t kb, int32
 }
 
 // ---- blocked inverse of the triangular factor, Li = L^{-1} ------------------------------------
-// Step 0 inverts every 64 x 64 diagonal block; step d computes every block at distance d below
-// the diagonal, Li[ib][kb] = -Li[ib][ib] * sum_{kb <= jb < ib} L[ib][jb] Li[jb][kb] (ib = kb+d),
-// from blocks of earlier steps: all column blocks advance together, one launch per step.
+// Step 0 inverts every 64 x 64 diagonal block.  Then L X = I is solved by right-looking block
+// forward substitution with the whole identity as right-hand side, in place in Li (zero
+// below the diagonal blocks to start with): for block row ib = 0, 1, ..., its tiles are
+// finalised, X[ib][kb] = Li[ib][ib] B[ib][kb] (kb < ib), and every later block row is
+// updated, B[i][kb] -= L[i][ib] X[ib][kb] (i > ib, kb <= ib).  Each launch is one tile
+// product deep, so the dependent chain is two launches per block row.
 
 // 64 x 64 product on the matrix cores: wavefront w accumulates rows 16w..16w+15 of As * Bs
 // (As[r][k] = A[r][k], Bs[k][c] = B[k][c]) into acc[ct] for column tile ct.
@@ -189,48 +192,68 @@ __global__ __launch_bounds__(256) void k_trtri_diag(int32_t ld, const double *L,
   }
 }
 
-__global__ __launch_bounds__(256) void k_trinv_step(int32_t ld, int32_t d, const double *L,
-                                                    double *Li) {
+// X[ib][kb] = Li[ib][ib] B[ib][kb] for kb = blockIdx.x < ib.
+__global__ __launch_bounds__(256) void k_trinv_finalize(int32_t ld, int32_t ib, double *Li) {
   __shared__ double As[kNB][kNB + 1];
   __shared__ double Bs[kNB][kNB + 1];
   const int tid = threadIdx.x;
-  const int32_t kb = blockIdx.x, ib = kb + d;  // the grid holds kb = 0 .. nbk-d-1
-  const int64_t r0 = (int64_t)ib * kNB, c0 = (int64_t)kb * kNB;
+  const int64_t r0 = (int64_t)ib * kNB, c0 = (int64_t)blockIdx.x * kNB;
+  for (int q = tid; q < kNB * kNB; q += 256) {
+    const int r = q / kNB, k = q % kNB;
+    As[r][k] = Li[(r0 + r) * ld + r0 + k];  // Li[ib][ib] (zero above its diagonal)
+    Bs[r][k] = Li[(r0 + r) * ld + c0 + k];  // B[ib][kb]
+  }
+  __syncthreads();
   v4d acc[4];
 #pragma unroll
   for (int ct = 0; ct < 4; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int32_t jb = kb; jb < ib; ++jb) {
-    const int64_t j0 = (int64_t)jb * kNB;
-    for (int q = tid; q < kNB * kNB; q += 256) {
-      const int r = q / kNB, k = q % kNB;
-      As[r][k] = L[(r0 + r) * ld + j0 + k];   // L[ib][jb]
-      Bs[r][k] = Li[(j0 + r) * ld + c0 + k];  // Li[jb][kb]
-    }
-    __syncthreads();
-    mfma_64(As, Bs, acc);
-    __syncthreads();
-  }
-  // T = the sum, into Bs; then Li[ib][kb] = -Li[ib][ib] T
+  mfma_64(As, Bs, acc);
   const int w = tid >> 6, lane = tid & 63;
   const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Bs[16 * w + 4 * v + lk][16 * ct + lr] = acc[ct][v];
+    for (int v = 0; v < 4; ++v)
+      Li[(r0 + 16 * w + 4 * v + lk) * ld + c0 + 16 * ct + lr] = acc[ct][v];
+}
+
+// B[i][kb] -= L[i][ib] X[ib][kb] for every tile i > ib, kb <= ib (block t: i = ib+1+t/(ib+1),
+// kb = t mod (ib+1)); each tile has one writer per launch.
+__global__ __launch_bounds__(256) void k_trinv_update(int32_t ld, int32_t ib, const double *L,
+                                                      double *Li) {
+  __shared__ double As[kNB][kNB + 1];
+  __shared__ double Bs[kNB][kNB + 1];
+  const int tid = threadIdx.x;
+  const int32_t i = ib + 1 + (int32_t)(blockIdx.x / (unsigned)(ib + 1));
+  const int32_t kb = (int32_t)(blockIdx.x % (unsigned)(ib + 1));
+  const int64_t r0 = (int64_t)i * kNB, j0 = (int64_t)ib * kNB, c0 = (int64_t)kb * kNB;
   for (int q = tid; q < kNB * kNB; q += 256) {
     const int r = q / kNB, k = q % kNB;
-    As[r][k] = Li[(r0 + r) * ld + r0 + k];  // Li[ib][ib] (zero above its diagonal)
+    As[r][k] = L[(r0 + r) * ld + j0 + k];   // L[i][ib]
+    Bs[r][k] = Li[(j0 + r) * ld + c0 + k];  // X[ib][kb]
   }
   __syncthreads();
-  v4d out[4];
+  v4d acc[4];
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) out[ct] = v4d{0.0, 0.0, 0.0, 0.0};
-  mfma_64(As, Bs, out);
+  for (int ct = 0; ct < 4; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+  mfma_64(As, Bs, acc);
+  const int w = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
     for (int v = 0; v < 4; ++v)
-      Li[(r0 + 16 * w + 4 * v + lk) * ld + c0 + 16 * ct + lr] = -out[ct][v];
+      Li[(r0 + 16 * w + 4 * v + lk) * ld + c0 + 16 * ct + lr] -= acc[ct][v];
+}
+
+// Li = L^{-1} (Li zero outside the diagonal blocks, which k_trtri_diag has filled).
+static void trinv_blocks(int32_t ld, int32_t nbk, const double *L, double *Li, hipStream_t s) {
+  for (int32_t ib = 0; ib < nbk; ++ib) {
+    if (ib > 0) k_trinv_finalize<<<(unsigned)ib, 256, 0, s>>>(ld, ib, Li);
+    const int64_t tiles = (int64_t)(nbk - ib - 1) * (ib + 1);
+    if (tiles > 0) k_trinv_update<<<(unsigned)tiles, 256, 0, s>>>(ld, ib, L, Li);
+  }
+  SA_LAUNCH_CHECK();
 }
 
 // C = X^T Y on 16x16 tiles, one wavefront per tile, K in steps of 4 (Cholesky: X = Y = L^{-1};
@@ -420,10 +443,10 @@ static void lu_inverse(int32_t ld, int32_t nbk, int32_t n, double *D, double *Li
   // Li = Lb^{-1}; then W = Ut^{-1} into D (the factor is no longer needed)
   fill_f64(Li, 0.0, cnt, s);
   k_trtri_diag<<<(unsigned)nbk, 256, 0, s>>>(ld, Lb, Li, true);
-  for (int32_t d = 1; d < nbk; ++d) k_trinv_step<<<(unsigned)(nbk - d), 256, 0, s>>>(ld, d, Lb, Li);
+  trinv_blocks(ld, nbk, Lb, Li, s);
   fill_f64(D, 0.0, cnt, s);
   k_trtri_diag<<<(unsigned)nbk, 256, 0, s>>>(ld, Ut, D, false);
-  for (int32_t d = 1; d < nbk; ++d) k_trinv_step<<<(unsigned)(nbk - d), 256, 0, s>>>(ld, d, Ut, D);
+  trinv_blocks(ld, nbk, Ut, D, s);
   SA_LAUNCH_CHECK();
   dim3 g(ld / 16, ld / 16);
   k_gram_mfma<<<g, 64, 0, s>>>(n, ld, D, Li, Ainv);
@@ -474,7 +497,7 @@ void coarse_inverse(const Csr &A, double *Ainv, int32_t *err, bool lu, hipStream
     SA_LAUNCH_CHECK();
   }
   k_trtri_diag<<<(unsigned)nbk, 256, 0, s>>>(ld, D, Li, false);
-  for (int32_t d = 1; d < nbk; ++d) k_trinv_step<<<(unsigned)(nbk - d), 256, 0, s>>>(ld, d, D, Li);
+  trinv_blocks(ld, nbk, D, Li, s);
   SA_LAUNCH_CHECK();
   dim3 g(ld / 16, ld / 16);
   k_gram_mfma<<<g, 64, 0, s>>>(n, ld, Li, Li, Ainv);
