@@ -55,9 +55,11 @@ __global__ __launch_bounds__(256) void k_potrf_diag(int32_t ld, int32_t k0, doub
     const double ljj = a[j][j];
     for (int i = j + 1 + tid; i < kNB; i += 256) a[i][j] /= ljj;
     __syncthreads();
-    for (int q = tid; q < kNB * kNB; q += 256) {
-      const int i = q / kNB, k = q % kNB;
-      if (k > j && k <= i) a[i][k] -= a[i][j] * a[k][j];
+    // trailing update over the (63-j)^2 square below and right of (j, j) only
+    const int m = kNB - 1 - j;
+    for (int q = tid; q < m * m; q += 256) {
+      const int i = j + 1 + q / m, k = j + 1 + q % m;
+      if (k <= i) a[i][k] -= a[i][j] * a[k][j];
     }
     __syncthreads();
   }
@@ -256,29 +258,66 @@ static void trinv_blocks(int32_t ld, int32_t nbk, const double *L, double *Li, h
   SA_LAUNCH_CHECK();
 }
 
-// C = X^T Y on 16x16 tiles, one wavefront per tile, K in steps of 4 (Cholesky: X = Y = L^{-1};
-// LU: X = (U^T)^{-1}, Y = L^{-1}).  Operand layout of v_mfma_f64_16x16x4f64: lane l supplies
-// A[l%16][l/16] and B[l/16][l%16]; it receives D[4v + l/16][l%16] in result register
-// v = 0..3 (checked against a dense inverse on the GPU).  X and Y are zero-padded to ld (a
-// multiple of 16).
-__global__ __launch_bounds__(64) void k_gram_mfma(int32_t n, int32_t ld, const double *X,
-                                                  const double *Y, double *C) {
-  const int lane = threadIdx.x;
-  const int32_t i = blockIdx.x * 16 + (lane & 15);
-  const int32_t j = blockIdx.y * 16 + (lane & 15);
-  const int32_t kk = lane >> 4;
-  v4d acc = {0.0, 0.0, 0.0, 0.0};
-  for (int32_t k0 = 0; k0 < ld; k0 += 4) {
-    const double a = X[(int64_t)(k0 + kk) * ld + i];  // A[i][k] = X[k][i]
-    const double b = Y[(int64_t)(k0 + kk) * ld + j];  // B[k][j] = Y[k][j]
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+// C = X^T Y for lower-triangular X and Y (ld x ld, zero above the diagonal; Cholesky:
+// X = Y = L^{-1}; LU: X = (U^T)^{-1}, Y = L^{-1}), n x n row-major output.  Tile (ib, jb)
+// of 64 x 64 sums X[kb][ib]^T Y[kb][jb] over kb >= max(ib, jb) (the other tiles are zero),
+// both tiles staged in LDS (X transposed on the way in) and multiplied on the matrix cores.
+// sym: X = Y, so only tiles ib >= jb are computed and the off-diagonal ones are also written
+// transposed.
+// Block t enumerates the tile pairs row-major (the lower triangle when sym).
+__global__ __launch_bounds__(256) void k_gram_tiles(int32_t n, int32_t ld, int32_t nbk,
+                                                    const double *X, const double *Y,
+                                                    double *C, bool sym) {
+  __shared__ double As[kNB][kNB + 1];
+  __shared__ double Bs[kNB][kNB + 1];
+  const int64_t t = blockIdx.x;
+  int32_t ib, jb;
+  if (sym) {
+    int32_t a = (int32_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((int64_t)a * (a + 1) / 2 > t) --a;
+    while ((int64_t)(a + 1) * (a + 2) / 2 <= t) ++a;
+    ib = a;
+    jb = (int32_t)(t - (int64_t)a * (a + 1) / 2);
+  } else {
+    ib = (int32_t)(t / nbk);
+    jb = (int32_t)(t % nbk);
   }
-  const int32_t col = blockIdx.y * 16 + (lane & 15);
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)ib * kNB, j0 = (int64_t)jb * kNB;
+  v4d acc[4];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int32_t row = blockIdx.x * 16 + 4 * v + (lane >> 4);
-    if (row < n && col < n) C[(int64_t)row * n + col] = acc[v];
+  for (int ct = 0; ct < 4; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int32_t kb = ib > jb ? ib : jb; kb < nbk; ++kb) {
+    const int64_t k0 = (int64_t)kb * kNB;
+    for (int q = tid; q < kNB * kNB; q += 256) {
+      const int k = q / kNB, c = q % kNB;
+      As[c][k] = X[(k0 + k) * ld + i0 + c];  // A[r][k] = X[k][r]
+      Bs[k][c] = Y[(k0 + k) * ld + j0 + c];
+    }
+    __syncthreads();
+    mfma_64(As, Bs, acc);
+    __syncthreads();
   }
+  const int w = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = i0 + 16 * w + 4 * v + lk, col = j0 + 16 * ct + lr;
+      if (row < n && col < n) {
+        C[row * n + col] = acc[ct][v];
+        // a diagonal tile holds both (r, c) and (c, r): each is written once, by its own lane
+        if (sym && ib != jb) C[col * n + row] = acc[ct][v];
+      }
+    }
+}
+
+static void gram(int32_t n, int32_t ld, int32_t nbk, const double *X, const double *Y,
+                 double *C, bool sym, hipStream_t s) {
+  const int64_t tiles = sym ? (int64_t)nbk * (nbk + 1) / 2 : (int64_t)nbk * nbk;
+  k_gram_tiles<<<(unsigned)tiles, 256, 0, s>>>(n, ld, nbk, X, Y, C, sym);
+  SA_LAUNCH_CHECK();
 }
 
 // ---- blocked right-looking LU without pivoting, 64 x 64 blocks --------------------------------
@@ -448,9 +487,7 @@ static void lu_inverse(int32_t ld, int32_t nbk, int32_t n, double *D, double *Li
   k_trtri_diag<<<(unsigned)nbk, 256, 0, s>>>(ld, Ut, D, false);
   trinv_blocks(ld, nbk, Ut, D, s);
   SA_LAUNCH_CHECK();
-  dim3 g(ld / 16, ld / 16);
-  k_gram_mfma<<<g, 64, 0, s>>>(n, ld, D, Li, Ainv);
-  SA_LAUNCH_CHECK();
+  gram(n, ld, nbk, D, Li, Ainv, false, s);
   dev_free(Lb, s);
   dev_free(Ut, s);
 }
@@ -499,9 +536,7 @@ void coarse_inverse(const Csr &A, double *Ainv, int32_t *err, bool lu, hipStream
   k_trtri_diag<<<(unsigned)nbk, 256, 0, s>>>(ld, D, Li, false);
   trinv_blocks(ld, nbk, D, Li, s);
   SA_LAUNCH_CHECK();
-  dim3 g(ld / 16, ld / 16);
-  k_gram_mfma<<<g, 64, 0, s>>>(n, ld, Li, Li, Ainv);
-  SA_LAUNCH_CHECK();
+  gram(n, ld, nbk, Li, Li, Ainv, true, s);
   dev_free(D, s);
   dev_free(Li, s);
 }
