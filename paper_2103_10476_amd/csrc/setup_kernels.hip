@@ -847,13 +847,15 @@ constexpr int32_t kSprsfyLds = 4096;   // longer root rows (up to this): one blo
 // ... unless the non-root members' rows hold more than this many entries in all: a thread
 // scans them once per candidate, so such aggregates also take the block path
 constexpr int32_t kSprsfyMemberWork = 128;
+constexpr int32_t kSprsfySmall = 64;   // block path with LDS for root rows up to this length
 // One thread per aggregate J with root r.  Candidates: aggregates reached by r's weak
 // connections but by none of its strong ones, J excluded.  For a candidate c, a single strong
 // connection from a non-root member of J into c is dropped with its transpose.  Decisions read
 // "strong" as mask 1 or 2, so concurrent drops by other aggregates do not change them; the
 // result depends neither on member order nor on the order in which aggregates are taken.
-// Aggregates with a long root row or heavy members are appended to heavy[] (count in *nheavy)
-// for k_sprsfy_block.
+// Aggregates with a long root row or heavy members are listed for k_sprsfy_block: those with
+// root rows up to kSprsfySmall in heavy[0, nc) (count nheavy[0]), the others in heavy[nc, 2nc)
+// (count nheavy[1]).
 __global__ void k_sprsfy(int32_t nc, const int32_t *rp, const int32_t *col, uint8_t *mask,
                          const int32_t *agg, const int32_t *root_vertex, const int32_t *mrp,
                          const int32_t *mem, int32_t *heavy, int32_t *nheavy) {
@@ -869,7 +871,9 @@ __global__ void k_sprsfy(int32_t nc, const int32_t *rp, const int32_t *col, uint
     if (v != r) w += rp[v + 1] - rp[v];
   }
   if (long_row || w > kSprsfyMemberWork) {
-    heavy[atomicAdd(nheavy, 1)] = J;
+    // root rows up to kSprsfySmall: the small-LDS list; longer ones: the second list
+    const int which = re - rb > kSprsfySmall ? 1 : 0;
+    heavy[which * (int64_t)nc + atomicAdd(nheavy + which, 1)] = J;
     return;
   }
   for (int32_t k = rb; k < re; ++k) {
@@ -942,6 +946,7 @@ __device__ inline void bitonic_u64_blk(uint64_t *a, int32_t L) {
     }
   }
 }
+template <int CAP>
 __global__ __launch_bounds__(kBlock) void k_sprsfy_block(const int32_t *heavy,
                                                          const int32_t *rp,
                                                          const int32_t *col, uint8_t *mask,
@@ -949,16 +954,16 @@ __global__ __launch_bounds__(kBlock) void k_sprsfy_block(const int32_t *heavy,
                                                          const int32_t *root_vertex,
                                                          const int32_t *mrp, const int32_t *mem,
                                                          int32_t *overflow) {
-  __shared__ uint64_t pairs[kSprsfyLds];
-  __shared__ int32_t cand[kSprsfyLds];
-  __shared__ int32_t cnt[kSprsfyLds];
-  __shared__ int32_t edge[kSprsfyLds];
+  __shared__ uint64_t pairs[CAP];
+  __shared__ int32_t cand[CAP];
+  __shared__ int32_t cnt[CAP];
+  __shared__ int32_t edge[CAP];
   __shared__ int32_t s_nc;
   const int32_t J = heavy[blockIdx.x];
   const int32_t r = root_vertex[J];
   const int32_t rb = rp[r], re = rp[r + 1];
   const int32_t len = re - rb;
-  if (len > kSprsfyLds) {
+  if (len > CAP) {
     if (threadIdx.x == 0) atomicOr(overflow, 1);
     return;
   }
@@ -1009,10 +1014,11 @@ __global__ __launch_bounds__(kBlock) void k_sprsfy_block(const int32_t *heavy,
     edge[q] = -1;
   }
   __syncthreads();
-  for (int32_t mm = mrp[J]; mm < mrp[J + 1]; ++mm) {
+  // one wavefront per member (4 members at a time), lanes over the member's row
+  for (int32_t mm = mrp[J] + (int32_t)(threadIdx.x >> 6); mm < mrp[J + 1]; mm += kBlock / 64) {
     const int32_t v = mem[mm];
     if (v == r) continue;
-    for (int32_t k = rp[v] + threadIdx.x; k < rp[v + 1]; k += blockDim.x) {
+    for (int32_t k = rp[v] + (int32_t)(threadIdx.x & 63); k < rp[v + 1]; k += 64) {
       const int32_t u = col[k];
       if (u == v) continue;
       const uint8_t m = mask[k];
@@ -1068,20 +1074,24 @@ void sprsfy(int32_t n, const int32_t *rp, const int32_t *col, uint8_t *mask, con
   tmp.stream = s;
   int32_t *mrp, *mem;
   member_lists(n, agg, nc, false, tmp, &mrp, &mem, s);  // decisions ignore member order
-  int32_t *words = tmp.alloc<int32_t>(2);  // [0] heavy count, [1] overflow
-  int32_t *heavy = tmp.alloc<int32_t>(nc);
-  fill_i32(words, 0, 2, s);
+  // words: [0] heavy aggregates with root rows <= kSprsfySmall, [1] the longer ones, [2] overflow
+  int32_t *words = tmp.alloc<int32_t>(3);
+  int32_t *heavy = tmp.alloc<int32_t>(2 * (int64_t)nc);  // [0, nc) short roots, [nc, 2nc) long
+  fill_i32(words, 0, 3, s);
   k_sprsfy<<<grid_for(nc), kBlock, 0, s>>>(nc, rp, col, mask, agg, root_vertex, mrp, mem,
                                            heavy, words);
   SA_LAUNCH_CHECK();
-  const int32_t nheavy = read1(words, s);
-  if (nheavy > 0) {
-    k_sprsfy_block<<<(unsigned)nheavy, kBlock, 0, s>>>(heavy, rp, col, mask, agg, root_vertex,
-                                                       mrp, mem, words + 1);
-    SA_LAUNCH_CHECK();
-    if (read1(words + 1, s))
-      throw Error(SA_ERR_INVALID_ARG, "Sprsfy: a root row exceeds the supported length");
-  }
+  int32_t nh[2];
+  readback(nh, words, sizeof(nh), s);
+  if (nh[0] > 0)
+    k_sprsfy_block<kSprsfySmall><<<(unsigned)nh[0], kBlock, 0, s>>>(
+        heavy, rp, col, mask, agg, root_vertex, mrp, mem, words + 2);
+  if (nh[1] > 0)
+    k_sprsfy_block<kSprsfyLds><<<(unsigned)nh[1], kBlock, 0, s>>>(
+        heavy + nc, rp, col, mask, agg, root_vertex, mrp, mem, words + 2);
+  SA_LAUNCH_CHECK();
+  if (nh[1] > 0 && read1(words + 2, s))
+    throw Error(SA_ERR_INVALID_ARG, "Sprsfy: a root row exceeds the supported length");
 }
 
 // ---- filtered matrix (Sec. 1.1 plain lumping; Sec. 2.3 Algorithm 2) and its diagonal -----
