@@ -484,15 +484,47 @@ __device__ __forceinline__ void lds_add(double *acc, uint32_t *bits, int32_t j, 
   acc[j] = acc[j] + v;
   atomicOr(&bits[j >> 5], 1u << (j & 31));
 }
+// Column window of each long row (rows[slot]): from the smallest first column to the largest
+// last column of the Y rows it touches (Y's rows are sorted, as every matrix the setup
+// builds); win[slot] = (first column, width), and *maxw the largest width.
+// One wavefront per row (X rows of the long bin reach thousands of entries): lanes take the
+// row's entries, then a shuffle minimum / maximum.
+__global__ void k_row_window(const int32_t *rows, int32_t nrows, const int32_t *xrp,
+                             const int32_t *xcol, const int32_t *yrp, const int32_t *ycol,
+                             int2 *win, int32_t *maxw) {
+  const int64_t slot = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (slot >= nrows) return;  // wave-uniform
+  const int lane = threadIdx.x & 63;
+  const int32_t i = rows[slot];
+  int32_t lo = 0x7fffffff, hi = -1;
+  for (int32_t e = xrp[i] + lane; e < xrp[i + 1]; e += 64) {
+    const int32_t k = xcol[e];
+    const int32_t b = yrp[k], en = yrp[k + 1];
+    if (b < en) {
+      lo = min(lo, ycol[b]);
+      hi = max(hi, ycol[en - 1]);
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    lo = min(lo, __shfl_xor(lo, off, 64));
+    hi = max(hi, __shfl_xor(hi, off, 64));
+  }
+  if (lane == 0) {
+    const int32_t w = hi >= lo ? hi - lo + 1 : 0;
+    win[slot] = make_int2(hi >= lo ? lo : 0, w);
+    atomicMax(maxw, w);
+  }
+}
+
 __global__ __launch_bounds__(64) void k_esc_lds(const int32_t *rows, int32_t nrows,
                                                 const int32_t *xrp, const int32_t *xcol,
                                                 const double *xval, const int32_t *yrp,
                                                 const int32_t *ycol, const double *yval,
-                                                int32_t ncols, const int64_t *poff,
-                                                int32_t *ocol, double *oval, int32_t *ucnt) {
+                                                int32_t ncols, const int2 *win,
+                                                const int64_t *poff, int32_t *ocol,
+                                                double *oval, int32_t *ucnt) {
   extern __shared__ double lds_acc[];
   double *acc = lds_acc;
-  const int32_t nw = (ncols + 31) >> 5;
   uint32_t *bits = (uint32_t *)(acc + ncols);
   __shared__ double s_a[64];
   __shared__ int32_t s_b[64], s_e[64];
@@ -500,7 +532,12 @@ __global__ __launch_bounds__(64) void k_esc_lds(const int32_t *rows, int32_t nro
   const int32_t slot = blockIdx.x;
   if (slot >= nrows) return;  // block-uniform
   const int32_t i = rows[slot];
-  for (int32_t c = lane; c < ncols; c += 64) acc[c] = 0.0;
+  // the row's window: accumulator index j - lo for output column j, rw <= ncols entries
+  // (no windows: the whole width)
+  const int2 wn = win ? win[slot] : make_int2(0, ncols);
+  const int32_t lo = wn.x, rw = wn.y;
+  const int32_t nw = (rw + 31) >> 5;
+  for (int32_t c = lane; c < rw; c += 64) acc[c] = 0.0;
   for (int32_t c = lane; c < nw; c += 64) bits[c] = 0u;
   const int32_t xb = xrp[i], xe = xrp[i + 1];
   for (int32_t e0 = xb; e0 < xe; e0 += 64) {
@@ -535,7 +572,7 @@ __global__ __launch_bounds__(64) void k_esc_lds(const int32_t *rows, int32_t nro
         jn = ycol[q2 + lane];
         vn = yval[q2 + lane];
       }
-      if (j >= 0) lds_add(acc, bits, j, a * v);
+      if ((uint32_t)(j - lo) < (uint32_t)rw) lds_add(acc, bits, j - lo, a * v);  // j >= 0
       if (g2 != g) __syncthreads();  // (one wavefront) orders row g's adds before row g2's
       g = g2;
       q0 = q2;
@@ -544,13 +581,13 @@ __global__ __launch_bounds__(64) void k_esc_lds(const int32_t *rows, int32_t nro
   __syncthreads();
   const int64_t base = poff[i];
   int32_t w = 0;
-  for (int32_t c0 = 0; c0 < ncols; c0 += 64) {
+  for (int32_t c0 = 0; c0 < rw; c0 += 64) {
     const int32_t c = c0 + lane;
-    const bool f = c < ncols && ((bits[c >> 5] >> (c & 31)) & 1u);
+    const bool f = c < rw && ((bits[c >> 5] >> (c & 31)) & 1u);
     const unsigned long long bm = __ballot(f);
     if (f) {
       const int32_t pos = w + __popcll(bm & ((1ull << lane) - 1ull));
-      ocol[base + pos] = c;
+      ocol[base + pos] = lo + c;
       oval[base + pos] = acc[c];
     }
     w += __popcll(bm);
@@ -726,10 +763,26 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
                                                       ucnt);
     SA_LAUNCH_CHECK();
   }
-  if (nlong > 0 && Y.ncols <= lds_cols_max()) {
-    const size_t lds = (size_t)Y.ncols * sizeof(double) + (size_t)((Y.ncols + 31) / 32) * 4;
+  // long rows: the LDS accumulator when Y's width fits the LDS (wider outputs take the hash:
+  // there, windows of up to ~19k columns leave 1-2 wavefronts per CU, slower than the hash),
+  // sized to the widest row window (far below Y's width on the systems levels)
+  const bool lds_bin = Y.ncols <= lds_cols_max();
+  int32_t wmax = Y.ncols;  // up to 2048 columns the whole width keeps 8 wavefronts per CU
+  int2 *win = nullptr;
+  if (nlong > 0 && lds_bin && Y.ncols > 2048) {
+    win = tmp.alloc<int2>(nlong);
+    fill_i32(counters + kBins + 1, 0, 1, s);
+    k_row_window<<<grid_for((int64_t)nlong * 64), kBlock, 0, s>>>(l3, nlong, X.rp, X.col, Y.rp,
+                                                                  Y.col, win,
+                                                    counters + kBins + 1);
+    SA_LAUNCH_CHECK();
+    wmax = read1(counters + kBins + 1, s);
+  }
+  if (nlong > 0 && lds_bin) {
+    const int32_t wl = (wmax + 31) & ~31;
+    const size_t lds = (size_t)wl * sizeof(double) + (size_t)(wl / 32) * 4;
     k_esc_lds<<<(unsigned)nlong, 64, lds, s>>>(l3, nlong, X.rp, X.col, X.val, Y.rp, Y.col, Y.val,
-                                              Y.ncols, poff, ocol, oval, ucnt);
+                                              wl, win, poff, ocol, oval, ucnt);
     SA_LAUNCH_CHECK();
   } else if (nlong > 0) {
     int32_t *ovf = tmp.alloc<int32_t>(nlong);
