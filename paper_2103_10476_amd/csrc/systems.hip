@@ -250,6 +250,104 @@ __global__ void k_agg_qr(int32_t nc, int32_t bs, int32_t k, const int32_t *mrp,
   }
 }
 
+// The same QR with one wavefront per aggregate and M, V, Q in LDS (rows x k each, rows <=
+// maxrows): every sum keeps k_agg_qr's order (one lane runs it from i = j upward), so the
+// results are bitwise the same.  Lane 0 forms each Householder vector; the column loops,
+// independent across columns, run one lane per column.
+__global__ __launch_bounds__(64) void k_agg_qr_lds(int32_t nc, int32_t bs, int32_t k,
+                                                   int32_t maxrows, const int32_t *mrp,
+                                                   const int32_t *mem, const double *B,
+                                                   const int32_t *ptrp, int32_t *ptcol,
+                                                   double *ptval, double *Bc, int32_t *err,
+                                                   int32_t ebit) {
+  extern __shared__ double qr_lds[];
+  __shared__ double s_vv[kMaxBs];
+  __shared__ int s_skip;
+  const int32_t J = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int32_t m0 = mrp[J], cntn = mrp[J + 1] - m0;
+  const int32_t rows = cntn * bs;
+  if (rows < k) {  // block-uniform
+    if (lane == 0) atomicOr(err, ebit);
+    return;
+  }
+  double *M = qr_lds, *V = qr_lds + (int64_t)maxrows * k, *Q = V + (int64_t)maxrows * k;
+  auto dof = [&](int32_t q) -> int64_t { return (int64_t)mem[m0 + q / bs] * bs + q % bs; };
+  for (int32_t e = lane; e < rows * k; e += 64) {
+    const int32_t q = e / k, c = e % k;
+    M[e] = B[dof(q) * k + c];
+    V[e] = 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (lane == 0) {
+      double vvj = 0.0;
+      int skip = 1;
+      double sigma = 0.0;
+      for (int32_t i = j; i < rows; ++i) sigma = sigma + M[(int64_t)i * k + j] * M[(int64_t)i * k + j];
+      const double nrm = sqrt(sigma);
+      if (nrm != 0.0) {
+        const double ajj = M[(int64_t)j * k + j];
+        const double alpha = ajj > 0.0 ? -nrm : nrm;
+        for (int32_t i = j; i < rows; ++i) V[(int64_t)i * k + j] = M[(int64_t)i * k + j];
+        V[(int64_t)j * k + j] = ajj - alpha;
+        double d = 0.0;
+        for (int32_t i = j; i < rows; ++i) d = d + V[(int64_t)i * k + j] * V[(int64_t)i * k + j];
+        vvj = d;
+        skip = d == 0.0;
+      }
+      s_vv[j] = vvj;
+      s_skip = skip;
+    }
+    __syncthreads();
+    if (!s_skip) {
+      const int c = j + lane;
+      if (c < k) {
+        const double d = s_vv[j];
+        double t = 0.0;
+        for (int32_t i = j; i < rows; ++i) t = t + V[(int64_t)i * k + j] * M[(int64_t)i * k + c];
+        const double f = (t + t) / d;
+        for (int32_t i = j; i < rows; ++i)
+          M[(int64_t)i * k + c] = M[(int64_t)i * k + c] - f * V[(int64_t)i * k + j];
+      }
+    }
+    __syncthreads();
+  }
+  for (int32_t e = lane; e < rows * k; e += 64) Q[e] = (e / k == e % k) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int j = k - 1; j >= 0; --j) {
+    const double vj = s_vv[j];
+    if (vj == 0.0) continue;  // block-uniform
+    const int c = lane;
+    if (c < k) {
+      double t = 0.0;
+      for (int32_t i = j; i < rows; ++i) t = t + V[(int64_t)i * k + j] * Q[(int64_t)i * k + c];
+      const double f = (t + t) / vj;
+      for (int32_t i = j; i < rows; ++i)
+        Q[(int64_t)i * k + c] = Q[(int64_t)i * k + c] - f * V[(int64_t)i * k + j];
+    }
+    __syncthreads();
+  }
+  if (lane < k) {  // row r = lane of R, and the sign of Q's column r
+    const int r = lane;
+    const bool flip = M[(int64_t)r * k + r] < 0.0;
+    for (int c = 0; c < k; ++c) {
+      double rv = (c >= r) ? M[(int64_t)r * k + c] : 0.0;
+      if (flip) rv = -rv;
+      Bc[((int64_t)J * k + r) * k + c] = rv;
+    }
+    if (flip)
+      for (int32_t q = 0; q < rows; ++q) Q[(int64_t)q * k + r] = -Q[(int64_t)q * k + r];
+  }
+  __syncthreads();
+  for (int32_t e = lane; e < rows * k; e += 64) {
+    const int32_t q = e / k, c = e % k;
+    const int64_t i = dof(q);
+    ptcol[ptrp[i] + c] = J * k + c;
+    ptval[ptrp[i] + c] = Q[e];
+  }
+}
+
 void tentative_qr(int32_t n, int32_t bs, int32_t k, const int32_t *agg, int32_t nc,
                   const double *B, Arena &ar, Csr &Pt, double *Bc, int32_t *err, int32_t ebit,
                   hipStream_t s) {
@@ -270,6 +368,15 @@ void tentative_qr(int32_t n, int32_t bs, int32_t k, const int32_t *agg, int32_t 
   if (nc <= 0) return;
   int32_t *mrp, *mem;
   member_lists(m, agg, nc, true, tmp, &mrp, &mem, s);
+  // one wavefront per aggregate with M, V, Q in LDS when the largest aggregate fits 64 KB
+  const int64_t maxrows = (int64_t)max_row_length(nc, mrp, s) * bs;
+  const int64_t lds = 3 * maxrows * k * (int64_t)sizeof(double);
+  if (lds <= (48 << 10)) {
+    k_agg_qr_lds<<<(unsigned)nc, 64, (size_t)lds, s>>>(nc, bs, k, (int32_t)maxrows, mrp, mem, B,
+                                                        Pt.rp, Pt.col, Pt.val, Bc, err, ebit);
+    SA_LAUNCH_CHECK();
+    return;
+  }
   const int64_t sz = (int64_t)n * k;
   double *Ms = tmp.alloc<double>(sz), *Vs = tmp.alloc<double>(sz), *Qs = tmp.alloc<double>(sz);
   k_agg_qr<<<grid_for(nc), kBlock, 0, s>>>(nc, bs, k, mrp, mem, B, Pt.rp, Pt.col, Pt.val, Bc, Ms,
