@@ -144,7 +144,12 @@ void sa_default_options(sa_options *o);
  *  out        receives the new hierarchy; owned by the caller until sa_destroy.
  * Errors: SA_ERR_INVALID_ARG, SA_ERR_BAD_CSR, SA_ERR_NONPOSITIVE_DIAG,
  * SA_ERR_NEGATIVE_EIGENVALUE, SA_ERR_COARSEN_STALLED, SA_ERR_COARSE_FACTOR, SA_ERR_OOM,
- * SA_ERR_HIP.  On failure *out is NULL and nothing is leaked. */
+ * SA_ERR_HIP.  On failure *out is NULL and nothing is leaked.
+ * The root selection's rounds are launched back to back while the calling thread polls a
+ * pinned status word written by the kernels (it spins on one host core meanwhile); if a word
+ * does not arrive within SAAMG_STATUS_SPIN_NS nanoseconds (environment, default 20000000),
+ * the thread synchronises the stream and reads the device flags instead.  The result is the
+ * same either way. */
 sa_status sa_setup(const sa_context *ctx, const sa_csr *A, const double *nullspace,
                    const sa_options *o, sa_hierarchy **out);
 
