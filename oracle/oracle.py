@@ -333,8 +333,7 @@ def diag(n, rp, col, val, one_norm=False, sigma=1.0 / 3.0):
 
 
 def spmv(rp, col, val, x, ncols=None):
-    """y = A x in the oracle's row-sum order (rows of more than 64 entries as 64 interleaved
-    in-order partial sums, added in order)."""
+    """y = A x, each row's products added sequentially in ascending column order from 0.0."""
     rp, col, val, x = _i32(rp), _i32(col), _f64(val), _f64(x)
     nr = len(rp) - 1
     nc = len(x) if ncols is None else ncols

@@ -7,10 +7,9 @@
 //
 // Readings of the paper where it is silent or ambiguous are marked "Reading:" in the
 // comments.  The arithmetic order of every floating-point reduction is fixed here and
-// stated in the comments (sums run sequentially in ascending index order starting from
-// 0.0, except matrix rows of more than 64 entries, see spmv; inner products use the
-// canonical 4096/256 tree of canon_sum), because the GPU
-// library reproduces those orders to give bit-identical setups.
+// stated in the comments (every row sum, y = A x included, runs sequentially in ascending
+// column order starting from 0.0; inner products use the canonical 4096/256 tree of
+// canon_sum), because the GPU library reproduces those orders to give bit-identical setups.
 //
 // Parity status per function: every step is pinned by tests against printed values,
 // closed forms, invariants or dense brute force, except the aggregation order reading (a
@@ -126,26 +125,14 @@ double dot(const std::vector<double> &x, const std::vector<double> &y) {
   return canon_sum(p);
 }
 
-// y = A x.  Reading (summation order; the paper fixes none): a row of L <= 64 entries is
-// summed sequentially in ascending column order from 0.0.  A row of L > 64 entries, at
-// in-row positions k = 0..L-1 in ascending column order, is summed as 64 interleaved partial
-// sums p_l = sum of the products at positions l, l+64, l+128, ... (each sequential from 0.0),
-// followed by p_0 + p_1 + ... + p_63 (sequential from 0.0).  For L <= 64 the second form
-// gives the first exactly, so the split only changes rows longer than 64 entries.
+// y = A x, the plain definition: y_i = sum over the row's stored entries of A_ij x_j, the
+// products added sequentially in ascending column order from 0.0 (the paper fixes no order;
+// this is the textbook one).
 void spmv(const Csr &A, const std::vector<double> &x, std::vector<double> &y) {
   y.assign(A.nr, 0.0);
   for (int i = 0; i < A.nr; ++i) {
-    const int32_t b = A.rp[i], L = A.rp[i + 1] - b;
     double s = 0.0;
-    if (L <= 64) {
-      for (int32_t k = 0; k < L; ++k) s += A.val[b + k] * x[A.col[b + k]];
-    } else {
-      for (int32_t l = 0; l < 64; ++l) {
-        double p = 0.0;
-        for (int32_t k = l; k < L; k += 64) p += A.val[b + k] * x[A.col[b + k]];
-        s += p;
-      }
-    }
+    for (int32_t e = A.rp[i]; e < A.rp[i + 1]; ++e) s += A.val[e] * x[A.col[e]];
     y[i] = s;
   }
 }
@@ -286,14 +273,16 @@ std::vector<std::vector<int>> strength_graph(const Csr &A, const std::vector<uin
 // Reading (leftovers): every still-unaggregated vertex joins the phase-1 aggregate it has
 // the most strong connections to, ties to the smaller aggregate number; phase 1 leaves no
 // vertex without an aggregated neighbour, so no new aggregates are needed.
-// Reading (isolated vertices): a vertex with no strong connection at all joins no
-// aggregate (agg = -1, a zero row of the tentative prolongator); the smoother alone treats
-// it.  Making it a singleton aggregate instead would carry it unchanged to every coarser
-// level and stall the coarsening (observed on the random-coefficient Q1 cube).
+// Isolated vertices (no strong connection at all): the aggregates cover every vertex (Sec.
+// 1.1, aggregates), and the root rule applies to them as to any other vertex -- nothing
+// around an isolated vertex is aggregated -- so each becomes the root of a singleton
+// aggregate in phase 1.  With `singletons` false (systems SA, where a single node carries
+// fewer unknowns than nullspace vectors) such a vertex joins no aggregate instead (agg = -1,
+// a zero row of the tentative prolongator).
 // Reading (numbering): aggregate number = rank of its root's vertex index among roots.
 // ------------------------------------------------------------------------------------
 int aggregate(const std::vector<std::vector<int>> &G, int order, uint64_t seed, int level,
-              std::vector<int32_t> &agg, std::vector<uint8_t> &is_root) {
+              bool singletons, std::vector<int32_t> &agg, std::vector<uint8_t> &is_root) {
   int n = (int)G.size();
   std::vector<int> vis(n);
   for (int v = 0; v < n; ++v) vis[v] = v;
@@ -306,7 +295,7 @@ int aggregate(const std::vector<std::vector<int>> &G, int order, uint64_t seed, 
   std::vector<int> owner(n, -1);  // root vertex of the phase-1 aggregate, -1 = free
   is_root.assign(n, 0);
   for (int v : vis) {
-    if (owner[v] != -1 || G[v].empty()) continue;
+    if (owner[v] != -1 || (G[v].empty() && !singletons)) continue;
     bool all_free = true;
     for (int u : G[v])
       if (owner[u] != -1) {
@@ -1090,7 +1079,7 @@ int build_level_system(Hier &H, int l) {
   auto G = strength_graph(L.Gn, L.nmask);
   L.nnzG = 0;
   for (auto &g : G) L.nnzG += (int64_t)g.size();
-  int nc = aggregate(G, o.agg_order, o.seed, l, L.agg, L.is_root);
+  int nc = aggregate(G, o.agg_order, o.seed, l, false, L.agg, L.is_root);
   if (nc < 0) return nc;
   L.nc = nc;
   if (nc == 0) return 1;
@@ -1117,10 +1106,11 @@ int build_level(Hier &H, int l) {
   auto G = strength_graph(L.As, L.mask);
   L.nnzG = 0;
   for (auto &g : G) L.nnzG += (int64_t)g.size();
-  int nc = aggregate(G, o.agg_order, o.seed, l, L.agg, L.is_root);
+  int nc = aggregate(G, o.agg_order, o.seed, l, true, L.agg, L.is_root);
   if (nc < 0) return nc;
   L.nc = nc;
-  if (nc == 0) return 1;  // no strong connection left: this level becomes the coarsest
+  // no strong connection left (every aggregate a singleton): this level becomes the coarsest
+  if (nc == L.A.nr) return 1;
   if (nc >= L.A.nr) return fail(ST_STALLED, "coarsening stalled");
   if (o.variants & V_SPRSFY) sprsfy(L.As, L.mask, L.agg, L.is_root, nc);
   return numeric_level(H, l);
@@ -1777,7 +1767,7 @@ int orc_aggregate(int32_t n, const int32_t *rp, const int32_t *col, const uint8_
   auto G = strength_graph(A, m);
   std::vector<int32_t> a;
   std::vector<uint8_t> r;
-  int c = aggregate(G, order, seed, level, a, r);
+  int c = aggregate(G, order, seed, level, true, a, r);
   if (c < 0) return c;
   std::memcpy(agg, a.data(), sizeof(int32_t) * n);
   std::memcpy(is_root, r.data(), n);

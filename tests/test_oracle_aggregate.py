@@ -26,11 +26,11 @@ def graph_from_mask(p, mask):
 def mis2_rounds(g, prio):
     """Independent route to the aggregation roots: rounds of the distance-2 maximal
     independent set rule (a vertex enters when it has the best priority among the undecided
-    vertices within distance 2 and no entered vertex is within distance 2).  Isolated vertices
-    never enter."""
+    vertices within distance 2 and no entered vertex is within distance 2).  An isolated
+    vertex is alone in its ball, so it enters in the first round."""
     n = len(g)
     UND, IN, OUT = 1, 0, 2
-    state = [UND if g[v] else OUT for v in range(n)]
+    state = [UND] * n
     while any(s == UND for s in state):
         key = [(state[v], prio[v]) for v in range(n)]
         k1 = [min([key[v]] + [key[u] for u in g[v]]) for v in range(n)]
@@ -61,11 +61,13 @@ def check_partition(g, agg, root, nc):
     assert sorted(agg[v] for v in roots) == list(range(nc))
     # numbering = rank of the root's index
     assert [agg[v] for v in roots] == list(range(nc))
+    # eq. (aggregates): the aggregates are disjoint (agg is a function) and cover every
+    # vertex, none of them empty
+    assert all(0 <= agg[v] < nc for v in range(n))
+    assert set(agg) == set(range(nc))
     for v in range(n):
         if not g[v]:
-            assert agg[v] == -1 and not root[v]
-        else:
-            assert 0 <= agg[v] < nc
+            assert root[v] and list(agg).count(agg[v]) == 1  # an isolated vertex: singleton
     for a, ra in enumerate(roots):
         for rb in roots[a + 1:]:
             assert rb not in dist2_ball(g, ra)  # roots at graph distance >= 3
@@ -156,28 +158,48 @@ def test_fig1_vertical_strong_gives_3x1_lines(orc):
 
 
 def test_tentative_prolongator_properties(orc):
-    """Sec. 1.1: Ptent has one unit entry per aggregated row, reproduces the constant, and its
+    """Sec. 1.1: Ptent has one unit entry per row, reproduces the constant, and its
     column-normalised form Q has orthonormal columns (one nullspace vector: QR = scaling)."""
     p = pb.fd5_stretched(20, 20, 100.0)
     mask = orc.strength(p.n, p.rp, p.col, p.val, 0.02)
     agg, root, nc = orc.aggregate(p.n, p.rp, p.col, mask)
+    assert np.all((agg >= 0) & (agg < nc))
     Pt = np.zeros((p.n, nc))
-    rows = np.nonzero(agg >= 0)[0]
-    Pt[rows, agg[rows]] = 1.0
-    assert np.all(Pt.sum(axis=1)[rows] == 1.0)
-    assert np.array_equal(Pt @ np.ones(nc), (agg >= 0).astype(float))
+    Pt[np.arange(p.n), agg] = 1.0
+    assert np.all(Pt.sum(axis=1) == 1.0)
+    assert np.array_equal(Pt @ np.ones(nc), np.ones(p.n))
     Q = Pt / np.sqrt(Pt.sum(axis=0))
     np.testing.assert_allclose(Q.T @ Q, np.eye(nc), atol=1e-15)
 
 
-def test_isolated_vertex_not_aggregated(orc):
-    """Reading: a vertex without strong connections joins no aggregate."""
-    d = np.array([[2.0, -1.0, 0.0, -1e-6], [-1.0, 2.0, -1.0, 0.0], [0.0, -1.0, 2.0, 0.0],
-                  [-1e-6, 0.0, 0.0, 1.0]])
+def test_isolated_vertex_is_a_singleton_aggregate(orc):
+    """Sec. 1.1, eq. (aggregates): the aggregates cover every vertex.  A vertex without strong
+    connections has nothing aggregated around it, so the root rule makes it the root of an
+    aggregate of its own; its number is the rank of its index among the roots."""
+    d = np.array([[1.0, 0.0, 0.0, -1e-6], [0.0, 2.0, -1.0, 0.0], [0.0, -1.0, 2.0, -1.0],
+                  [-1e-6, 0.0, -1.0, 2.0]])
     p = pb.from_dense(d)
     mask = orc.strength(p.n, p.rp, p.col, p.val, 0.1)
     agg, root, nc = orc.aggregate(p.n, p.rp, p.col, mask)
-    assert agg[3] == -1 and not root[3] and nc == 1 and list(agg[:3]) == [0, 0, 0]
+    assert nc == 2 and list(agg) == [0, 1, 1, 1] and list(root) == [1, 1, 0, 0]
+
+
+def test_isolated_vertices_keep_coarsening_going(orc):
+    """A level whose strong graph leaves some vertices isolated still coarsens (the others
+    aggregate), each isolated vertex becoming one coarse unknown; the hierarchy converges."""
+    p = pb.q1_random_kappa(12, seed=3)
+    h = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, theta=0.02, variants=["offlmp", "1norm"],
+                            max_coarse=50, rtol=1e-8)
+    L0 = h.levels[0]
+    g = graph_from_mask(pb.CsrProblem(p.n, p.rp, p.col, p.val, "q1"), L0.mask)
+    iso = [v for v in range(p.n) if not g[v]]
+    assert iso, "the random-coefficient cube has vertices without strong connections"
+    assert np.all((L0.agg >= 0) & (L0.agg < L0.nc))
+    for v in iso:
+        assert L0.is_root[v] and np.count_nonzero(L0.agg == L0.agg[v]) == 1
+    assert h.levels[1].n == L0.nc < p.n
+    r = h.solve(pb.random_rhs(p.n, 4))
+    assert r["converged"] and r["iterations"] < 40
 
 
 def _sprsfy_grid(nx=6, ny=6, special=((1, 1), (2, 1))):
