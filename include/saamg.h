@@ -68,7 +68,7 @@ typedef struct {
   uint32_t struct_size;
   uint32_t variants;      /* OR of SA_SPRSFY | SA_OFFLMP | SA_1NORM | SA_CNSTRNT [0]        */
   double theta;           /* strength threshold, Sec. 1.1 [0.02]                            */
-  double tau;             /* OffLmp ddom growth bound, Sec. 2.3/4.1 [1.1]                   */
+  double tau;             /* OffLmp ddom growth bound, Sec. 2.3 (value: Sec. 3.1) [1.1]    */
   double sigma;           /* 1Norm root-value safeguard, Sec. 2.2 [1/3]                     */
   int32_t one_norm_power; /* 0: lambda = 1 for 1Norm (Sec. 2.1); 1: power method [0]        */
   int32_t power_iters;    /* power-method steps for every eigenvalue estimate [10]          */
@@ -326,7 +326,8 @@ sa_status sa_server_create(const sa_context *ctx, size_t hbm_budget, int32_t max
 /* Queues a request: A (validated by sa_setup when the request runs), b (n values) and the
  * options (NULL = defaults) are copied to host memory before the call returns (A->loc gives
  * where A and b live).  *ticket receives the request's id.  Errors: SA_ERR_INVALID_ARG
- * (bad arguments, or a request whose estimate alone exceeds the budget), SA_ERR_HIP. */
+ * (bad arguments, or the server shutting down), SA_ERR_OOM (a request whose estimate alone
+ * exceeds the budget: it could never be admitted), SA_ERR_HIP. */
 sa_status sa_server_submit(sa_server *s, const sa_csr *A, const double *b, const sa_options *o,
                            uint64_t *ticket);
 

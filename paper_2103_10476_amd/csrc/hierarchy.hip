@@ -250,7 +250,7 @@ static bool build_level_system(sa_hierarchy *h, int l) {
   L.agg = ar.alloc<int32_t>(m);
   L.is_root = ar.alloc<uint8_t>(m);
   int32_t *root_vertex = nullptr;
-  L.nc = aggregate(m, nnzG, grp, gcol, o.agg_order, o.seed, l, L.agg, L.is_root, tmp,
+  L.nc = aggregate(m, nnzG, grp, gcol, o.agg_order, o.seed, l, false, L.agg, L.is_root, tmp,
                    &root_vertex, &L.mis_rounds, s);
   if (L.nc == 0) return false;
   if ((int64_t)L.nc * h->k >= n) throw Error(SA_ERR_COARSEN_STALLED, "coarsening stalled");
@@ -295,9 +295,9 @@ static bool build_level(sa_hierarchy *h, int l) {
   L.is_root = ar.alloc<uint8_t>(n);
   int32_t *root_vertex = nullptr;
   if (o.variants & SA_SPRSFY) {  // the drops change the labels lumping reads: in sequence
-    L.nc = aggregate(n, nnzG, grp, gcol, o.agg_order, o.seed, l, L.agg, L.is_root, tmp,
+    L.nc = aggregate(n, nnzG, grp, gcol, o.agg_order, o.seed, l, true, L.agg, L.is_root, tmp,
                      &root_vertex, &L.mis_rounds, s);
-    if (L.nc == 0) return false;
+    if (L.nc == n) return false;  // no strong connection: every aggregate a singleton
     if (L.nc >= n) throw Error(SA_ERR_COARSEN_STALLED, "coarsening stalled");
     sprsfy(n, L.As.rp, L.As.col, L.mask, L.agg, root_vertex, L.nc, s);
     numeric_level(h, l, true);
@@ -311,10 +311,12 @@ static bool build_level(sa_hierarchy *h, int l) {
   if (!h->side) h->side = side_stream(s);
   stream_after(h->side, s);
   numeric_damping(h, l, h->side, h->err + 2);
-  L.nc = aggregate(n, nnzG, grp, gcol, o.agg_order, o.seed, l, L.agg, L.is_root, tmp, &root_vertex,
-                   &L.mis_rounds, s);
+  L.nc = aggregate(n, nnzG, grp, gcol, o.agg_order, o.seed, l, true, L.agg, L.is_root, tmp,
+                   &root_vertex, &L.mis_rounds, s);
   stream_after(s, h->side);
-  if (L.nc == 0) {  // the coarsest level keeps no numeric part
+  // no strong connection (every aggregate a singleton): the coarsest level, which keeps no
+  // numeric part
+  if (L.nc == n) {
     L.Abar = Csr{};
     L.invD = L.lam_d = L.omega_d = nullptr;
     return false;

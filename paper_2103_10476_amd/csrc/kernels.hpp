@@ -6,9 +6,12 @@ namespace sa {
 
 // ---------------- solve-phase kernels (solve_kernels.hip) ------------------------------
 // y = A x with every row of at most 64 entries summed sequentially in ascending column order
-// from 0, longer rows as 64 interleaved in-order partial sums added in order (products
-// staged through LDS; bit-identical to the row-by-row definition).  Variants fuse the
-// row-local epilogue used by the smoother, residual and transfer steps.
+// from 0 (products staged through LDS).  A longer row is summed the same way when `plain` is
+// set -- the setup's eigenvalue estimates, whose results decide the hierarchy bit for bit --
+// and otherwise, in the solve, as 64 interleaved in-order partial sums added in order, which
+// cuts the row's dependent chain of adds from L to about L/64 + 64 (a rounding-level
+// difference from the sequential sum).  Variants fuse the row-local epilogue used by the
+// smoother, residual and transfer steps.
 template <class T>
 struct SpmvArgs {
   int32_t n;
@@ -23,6 +26,7 @@ struct SpmvArgs {
   const int32_t *scol = nullptr;
   const T *sval = nullptr;
   int32_t nslice = 0;
+  bool plain = false;  // long rows in sequential order too (see above)
 };
 // Row partition for the SpMV kernels: block b owns the rows whose cost rp[r] + 8 r lies in
 // [2048 b, 2048 (b+1)), i.e. at most 256 rows and (long rows aside) at most 2048 entries;
@@ -196,10 +200,14 @@ int64_t strength_graph(int32_t n, const int32_t *rp, const int32_t *col, const u
                        const int32_t *scount, bool wave, Arena &ar, int32_t **grp,
                        int32_t **gcol, hipStream_t s);
 // Aggregation (roots = lexicographically-first distance-2 MIS in priority order; phase-2
-// join; isolated vertices unaggregated).  Returns nc; agg[n], is_root[n], root_vertex[nc].
+// join).  A vertex without strong connections is the root of a singleton aggregate when
+// `singletons` is set (the scalar method: the aggregates cover every vertex), and joins no
+// aggregate (agg -1) otherwise (systems, where one node carries fewer unknowns than nullspace
+// vectors).  Returns nc; agg[n], is_root[n], root_vertex[nc].
 int32_t aggregate(int32_t n, int64_t nnzG, const int32_t *grp, const int32_t *gcol, int32_t order,
-                  uint64_t seed, int32_t level, int32_t *agg, uint8_t *is_root, Arena &ar,
-                  int32_t **root_vertex, int32_t *rounds, hipStream_t s);
+                  uint64_t seed, int32_t level, bool singletons, int32_t *agg,
+                  uint8_t *is_root, Arena &ar, int32_t **root_vertex, int32_t *rounds,
+                  hipStream_t s);
 // Sprsfy: marks dropped strong entries (mask 1 -> 2).
 void sprsfy(int32_t n, const int32_t *rp, const int32_t *col, uint8_t *mask,
             const int32_t *agg, const int32_t *root_vertex, int32_t nc, hipStream_t s);

@@ -339,7 +339,7 @@ sa_status sa_server_submit(sa_server *s, const sa_csr *A, const double *b, const
     else sa_default_options(&q->opt);
     q->res.reserved_bytes = sa_estimate_bytes(A->n, A->nnz);
     if (q->res.reserved_bytes > s->budget)
-      throw Error(SA_ERR_INVALID_ARG, "request estimate exceeds the server's memory budget");
+      throw Error(SA_ERR_OOM, "request estimate exceeds the server's memory budget");
     copy_host(q->rp, A->row_ptr, (size_t)A->n + 1, A->loc);
     copy_host(q->col, A->col, (size_t)A->nnz, A->loc);
     copy_host(q->val, A->val, (size_t)A->nnz, A->loc);

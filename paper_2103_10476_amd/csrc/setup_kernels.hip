@@ -434,16 +434,19 @@ __device__ inline uint64_t stream_key_dev(int stream, int level, int64_t i) {
   return ((uint64_t)stream << 56) | ((uint64_t)level << 40) | (uint64_t)i;
 }
 
+// A vertex without neighbours is decided at once: nothing near it can ever be aggregated, so
+// the sequential rule makes it a root whatever its priority (singletons), or it is left out.
+// Its key never enters another vertex's neighbourhood minimum.
 template <class K>
 __global__ void k_mis_init(int32_t n, const int32_t *grp, int32_t order, uint64_t seed,
-                           int32_t level, K *key, uint8_t *st1, uint8_t *st2) {
+                           int32_t level, bool singletons, K *key, uint8_t *st1, uint8_t *st2) {
   SA_ROW_KERNEL_BEGIN(n)
   K pri = (K)i;
   if (order == 1)
     pri = (K)((((uint64_t)splitmix64_dev(seed, stream_key_dev(2, level, i)) >> 34) << 32) |
               (uint64_t)i);
   const bool open = grp[i + 1] > grp[i];
-  key[i] = (open ? KeyT<K>::Und : KeyT<K>::Out) | pri;
+  key[i] = (open ? KeyT<K>::Und : singletons ? KeyT<K>::In : KeyT<K>::Out) | pri;
   st1[i] = 0;
   st2[i] = 0;
 }
@@ -723,7 +726,8 @@ __global__ void k_agg_phase2(int32_t n, const int32_t *grp, const int32_t *gcol,
 
 template <class K>
 static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const int32_t *gcol,
-                              int32_t order, uint64_t seed, int32_t level, int32_t *agg,
+                              int32_t order, uint64_t seed, int32_t level, bool singletons,
+                              int32_t *agg,
                               uint8_t *is_root, Arena &ar, int32_t **root_vertex,
                               int32_t *rounds_out, hipStream_t s) {
   Arena tmp;
@@ -732,7 +736,8 @@ static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const
   K *k1 = tmp.alloc<K>(n);
   uint8_t *st1 = tmp.alloc<uint8_t>(n);
   uint8_t *st2 = tmp.alloc<uint8_t>(n);
-  k_mis_init<K><<<grid_for(n), kBlock, 0, s>>>(n, grp, order, seed, level, key, st1, st2);
+  k_mis_init<K><<<grid_for(n), kBlock, 0, s>>>(n, grp, order, seed, level, singletons, key, st1,
+                                               st2);
   SA_LAUNCH_CHECK();
   // Rounds are launched back to back, at most kAhead past the last round whose outcome the
   // host has seen.  Pass 1 of round r+1 posts round r's outcome into a pinned status ring
@@ -832,13 +837,14 @@ static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const
 }
 
 int32_t aggregate(int32_t n, int64_t nnzG, const int32_t *grp, const int32_t *gcol,
-                  int32_t order, uint64_t seed, int32_t level, int32_t *agg, uint8_t *is_root,
-                  Arena &ar, int32_t **root_vertex, int32_t *rounds, hipStream_t s) {
+                  int32_t order, uint64_t seed, int32_t level, bool singletons, int32_t *agg,
+                  uint8_t *is_root, Arena &ar, int32_t **root_vertex, int32_t *rounds,
+                  hipStream_t s) {
   if (order == 0 && n < (1 << 30))
-    return aggregate_impl<uint32_t>(n, nnzG, grp, gcol, order, seed, level, agg, is_root, ar,
-                                    root_vertex, rounds, s);
-  return aggregate_impl<uint64_t>(n, nnzG, grp, gcol, order, seed, level, agg, is_root, ar,
-                                  root_vertex, rounds, s);
+    return aggregate_impl<uint32_t>(n, nnzG, grp, gcol, order, seed, level, singletons, agg,
+                                    is_root, ar, root_vertex, rounds, s);
+  return aggregate_impl<uint64_t>(n, nnzG, grp, gcol, order, seed, level, singletons, agg,
+                                  is_root, ar, root_vertex, rounds, s);
 }
 
 // ---- Sprsfy (Sec. 2.5) --------------------------------------------------------------------
@@ -1451,6 +1457,7 @@ void power_method(const Csr &M, const double *invD, int32_t iters, uint64_t seed
   k_power_init<<<grid_for(n), kBlock, 0, s>>>(n, seed, level, stream_id, x);
   SA_LAUNCH_CHECK();
   SpmvArgs<double> a = spmv_args<double>(M, M.val, x);
+  a.plain = true;  // the estimate decides the hierarchy: every row in sequential order
   for (int32_t t = 1; t <= iters; ++t) {
     spmv_scale<double>(a, invD, y, s);
     if (t == iters) {

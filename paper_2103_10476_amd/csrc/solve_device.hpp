@@ -29,11 +29,13 @@ __device__ __forceinline__ int32_t xcd_block(uint32_t b, uint32_t nb) {
 }
 
 // Row sums.  A row of at most kLongRow = 64 entries is summed in ascending column order from
-// 0.  A longer row, with in-row positions k = 0..L-1 in ascending column order, is summed as
-// 64 interleaved partial sums p_l over the positions l, l+64, l+128, ... (each in order from
-// 0), followed by p_0 + ... + p_63 in order from 0.  For L <= 64 the two forms agree
-// exactly; the split lets lane l of a wavefront form p_l instead of one thread adding all L
-// products in a dependent chain.
+// 0.  A longer row is summed the same way by its own thread when Split is false (the plain
+// definition, used where the result must equal the sequential sum bit for bit), and
+// otherwise, with in-row positions k = 0..L-1 in ascending column order, as 64 interleaved
+// partial sums p_l over the positions l, l+64, l+128, ... (each in order from 0), followed by
+// p_0 + ... + p_63 in order from 0.  For L <= 64 the two forms agree exactly; the split lets
+// lane l of a wavefront form p_l instead of one thread adding all L products in a dependent
+// chain.
 constexpr int32_t kLongRow = 64;
 
 // The rows of a row block start within one window of kPlanWindow cost units (row r costs
@@ -60,7 +62,7 @@ struct SpmvShared {
 // (carried in a register across chunks for the one row that spans chunks) and stores it in
 // LDS; after the chunk's barrier the row's own thread adds its 64 partials in order.  Each
 // row's sum goes to the epilogue from the row's own thread.
-template <class T, class Epi>
+template <class T, class Epi, bool Split = true>
 __device__ __forceinline__ void spmv_block(int32_t b, const int32_t *__restrict__ plan,
                                            const int32_t *__restrict__ rp,
                                            const int32_t *__restrict__ col,
@@ -97,7 +99,7 @@ __device__ __forceinline__ void spmv_block(int32_t b, const int32_t *__restrict_
       // the wait for mb and me, above the loop)
       int32_t b2 = mb, e2 = me;
       asm volatile("" : "+v"(b2), "+v"(e2));
-      lng = e2 - b2 > kLongRow;
+      lng = Split && e2 - b2 > kLongRow;
       const uint64_t lmask = __ballot(lng);
       if (lane == 0) sh.longmask[wv] = lmask;
       any = __syncthreads_or(lng) != 0;

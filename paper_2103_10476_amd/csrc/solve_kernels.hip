@@ -5,23 +5,25 @@
 // the row plan so that every block carries about the same number of entries plus a per-row
 // cost.  The block streams the rows' entries through LDS in coalesced chunks, forming each
 // product val*x[col] once; then every thread adds the products of its own row (at most 64
-// entries) in ascending column order, and longer rows are summed by a wavefront as 64
-// interleaved in-order partial sums added in order (the row-sum order defined with
-// spmv_block).  Results are bit-identical to that row-by-row definition, while the global
+// entries, or any length in the plain order) in ascending column order, and longer rows are
+// otherwise summed by a wavefront as 64 interleaved in-order partial sums added in order (the
+// row-sum orders defined with spmv_block).  Results are bit-identical to that row-by-row
+// definition, while the global
 // loads stay fully coalesced (HBM-bound: ~12 B/entry for FP64, ~8 B/entry for FP32).
 // Operators with short rows use a sliced-ELL copy instead (k_spmv_sell).
 #include "solve_device.hpp"
 
 namespace sa {
 
-template <class T, class Epi>
+template <class T, class Epi, bool Split>
 __global__ __launch_bounds__(kBlock) void k_spmv(const int32_t *__restrict__ bstart,
                                                  const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ col,
                                                  const T *__restrict__ val,
                                                  const T *__restrict__ x, Epi epi) {
   __shared__ SpmvShared<T> sh;
-  spmv_block<T, Epi>(xcd_block(blockIdx.x, gridDim.x), bstart, rp, col, val, x, epi, sh);
+  spmv_block<T, Epi, Split>(xcd_block(blockIdx.x, gridDim.x), bstart, rp, col, val, x, epi,
+                            sh);
 }
 
 // Sliced-ELL SpMV: one wavefront per 64-row slice, lane l on row 64 s + l.  The k-th entries
@@ -178,8 +180,12 @@ static void launch_spmv(const SpmvArgs<T> &a, const Epi &epi, hipStream_t s) {
   if (a.sval)
     k_spmv_sell<T, Epi><<<(unsigned)ceil_div(a.nslice, kBlock / 64), kBlock, 0, s>>>(
         a.n, a.nslice, a.sptr, a.scol, a.sval, a.x, epi);
+  else if (a.plain)
+    k_spmv<T, Epi, false><<<(unsigned)a.nblk, kBlock, 0, s>>>(a.bstart, a.rp, a.col, a.val, a.x,
+                                                              epi);
   else
-    k_spmv<T, Epi><<<(unsigned)a.nblk, kBlock, 0, s>>>(a.bstart, a.rp, a.col, a.val, a.x, epi);
+    k_spmv<T, Epi, true><<<(unsigned)a.nblk, kBlock, 0, s>>>(a.bstart, a.rp, a.col, a.val, a.x,
+                                                             epi);
   SA_LAUNCH_CHECK();
 }
 

@@ -73,10 +73,14 @@ def test_mix_is_bitwise_equal_to_alone():
 
 
 def test_served_requests_match_oracle():
+    """Small requests of both families, plus one of each family with side >= 64."""
     from oracle import oracle as orc
     from paper_2103_10476_amd import solver
     reqs = []
-    for (req, p, b, _) in _requests(6, 10, 18, seed=12):
+    large = pb.serving_requests(12, seed=15, smin=64, smax=72)
+    pick = [next(r for r in large if r["kind"] == k) for k in ("fd7", "q1")]
+    both = [(req, *pb.build_request(req), None) for req in pick]
+    for (req, p, b, _) in _requests(6, 10, 18, seed=12) + both:
         kw = dict(pb.serving_method(req), precision="fp64")  # the oracle computes in FP64
         reqs.append((req, p, b, solver.Options(**kw)))
     served, _ = _serve(reqs, budget=8 << 30, slots=3)
@@ -151,5 +155,5 @@ def test_failure_is_isolated_and_oversize_rejected():
     small = solver.Server(hbm_budget=1 << 20, max_slots=1)
     with pytest.raises(SaError) as e:
         small.submit(good, b_good)
-    assert e.value.code == -1
+    assert e.value.code == -7  # SA_ERR_OOM: larger than the whole budget
     small.close()
