@@ -23,11 +23,10 @@ sys.path.insert(0, ROOT)
 WORKLOAD = "fd7_128_a1000"
 PRECISION_WORKLOAD = "fd7_160_a1000"
 PEAK_HBM_GBS = 8000.0
-# rocprofv3 counter summary of the SpMV kernel on the default workload; its traffic figure is
-# reported only while the kernel's sources still hash to the value recorded with it
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_spmv_sell_fd7_128_a1000_hbm_traffic.md")
-# the SpMV kernel body and epilogues live in solve_device.hpp, its launch and row partition in
-# solve_kernels.hip; build.py holds the compile flags
+# rocprofv3 counter summaries of the fine-level SpMV kernel, one per workload and precision
+# (profiles/k_spmv_sell_<workload>_<f64|f32>_hbm_traffic.md); a traffic figure is reported only
+# while the kernel's sources still hash to the value recorded with it
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_spmv_sell_{workload}_{dtype}_hbm_traffic.md")
 KERNEL_SOURCES = ["paper_2103_10476_amd/csrc/solve_device.hpp",
                   "paper_2103_10476_amd/csrc/solve_kernels.hip",
                   "paper_2103_10476_amd/build.py"]
@@ -88,7 +87,10 @@ def main():
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the FP32 and variant legs (profiling runs)")
+                    help="skip the timed FP32-vs-FP64 repetitions and the other legs "
+                         "(profiling runs); the 160^3 roofline solves still run")
+    ap.add_argument("--legs-out", default=None, metavar="PATH",
+                    help="also write every leg's full results to PATH (JSON)")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-rates", default="0.35,0.7,1.0",
                     help="open-loop arrival rates as fractions of the closed-loop rate")
@@ -136,6 +138,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log(f"[bench] copy probe: {args.copy_probe} bytes read and written per copy")
+        del src, dst
     p = problems.workload(args.workload)
     b = problems.random_rhs(p.n, problems.RHS_SEED.get(args.workload, 2))
     drp = torch.from_numpy(p.rp).cuda()
@@ -146,33 +149,26 @@ def main():
     torch.cuda.synchronize()
     opts = solver.Options(theta=0.02, rtol=1e-8)
 
-    prof_totals = {"launches": 0, "ms": 0.0, "bytes": 0.0}
-
-    def step(o=opts, profile=False):
+    def step(o=opts):
         h = solver.Hierarchy(p.n, drp, dcol, dval, options=o)
-        if profile:
-            h.profile(True)
         ts = time.perf_counter()
         _, it, rr, st = h.solve(db, x)
         torch.cuda.synchronize()
         te = time.perf_counter() - ts
-        if profile:
-            pr = h.profile_read()
-            for k in prof_totals:
-                prof_totals[k] += pr[k]
         return h, it, rr, st, te
 
     log(f"[bench] {p.name} n={p.n} nnz={p.nnz}: warmup {args.warmup}")
     for _ in range(args.warmup):
         h, *_ = step()
         h.close()
+    # timed steps: nothing instrumented inside the timed region
     times, setups, solves = [], [], []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
     for k in range(args.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        h, it, rr, st, tsolve = step(profile=True)
+        h, it, rr, st, tsolve = step()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         times.append(dt)
@@ -186,7 +182,16 @@ def main():
             f"{tsolve * 1e3:.2f}, {it} its, {st})")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_all
+    x_main = x.cpu().numpy()
+    # one more pass, outside the timed region, with HIP events around the fine-level SpMVs
+    h, *_ = step()
+    h.profile(True)
+    h.solve(db, x)
+    torch.cuda.synchronize()
+    prof_main = h.profile_read()
+    h.close()
     value = pct(times, 50)
+    legs = {}
     result = {
         "metric": "setup+solve s & HBM GB/s, 128³ stretched; FP32-Vcycle vs FP64; p50/p99",
         "value": round(value, 6),
@@ -206,28 +211,118 @@ def main():
                    "n": p.n, "nnz": p.nnz, "levels": info["levels"],
                    "operator_complexity": round(info["operator_complexity"], 4),
                    "iterations": it},
-        "setup_s": {"p50": pct(setups, 50), "p99": pct(setups, 99)},
-        "solve_s": {"p50": pct(solves, 50), "p99": pct(solves, 99)},
-        "setup_plus_solve_s": {"p50": pct(times, 50), "p99": pct(times, 99),
-                               "min": min(times)},
+        "setup_s": {"p50": round(pct(setups, 50), 6), "p99": round(pct(setups, 99), 6)},
+        "solve_s": {"p50": round(pct(solves, 50), 6), "p99": round(pct(solves, 99), 6)},
+        "setup_plus_solve_s": {"p50": round(pct(times, 50), 6), "p99": round(pct(times, 99), 6),
+                               "min": round(min(times), 6)},
     }
     sb = solve_bytes_model(info) * (it + 1)
     result["solve_hbm_gbs"] = round(sb / pct(solves, 50) / 1e9, 1)
-    result["roofline"] = roofline(prof_totals, args.workload)
+    # the 128^3 fine operator (217-246 MB per launch) can stay in the 256 MB Infinity Cache
+    # between launches; the headline roofline is taken on the 160^3 cube (424 MB per launch)
+    c4 = c4_leg(solver, problems, PRECISION_WORKLOAD, reps=1 if args.no_extras else 5)
+    legs["fp32_vcycle_vs_fp64"] = c4
+    result["roofline"] = c4["roofline_fp64"]
     if result["roofline"] is not None:
         result["roofline"]["stream_probe_gbs"] = stream_probe()
+    result["roofline_fp32"] = c4["roofline_fp32"]
+    result["roofline_128_mall_assisted"] = roofline(
+        prof_main, args.workload, note="128^3 fine operator, small enough to be served "
+        "partly from the 256 MB Infinity Cache")
     if not args.no_extras:
-        result["fp32_vcycle_vs_fp64"] = precision_leg(solver, problems, PRECISION_WORKLOAD)
-        result["variants"] = variants_leg(solver, p, drp, dcol, dval, db)
-        result["numeric_resetup"] = resetup_leg(solver, p, drp, dcol, dval, db)
-        result["variant_sweep"] = variant_sweep_leg(solver, problems)
-        result["mesh_families"] = families_leg(solver, problems, seeds=args.family_seeds)
-        result["gmres"] = gmres_leg(solver, problems)
-        result["systems"] = systems_leg(solver, problems)
-        result["serving"] = serving_leg(solver, problems, args)
+        legs["variants"] = variants_leg(solver, p, drp, dcol, dval, db)
+        legs["numeric_resetup"] = resetup_leg(solver, p, drp, dcol, dval, db)
+        legs["variant_sweep"] = variant_sweep_leg(solver, problems)
+        legs["mesh_families"] = families_leg(solver, problems, seeds=args.family_seeds)
+        legs["gmres"] = gmres_leg(solver, problems)
+        legs["systems"] = systems_leg(solver, problems)
+        legs["serving"] = serving_leg(solver, problems, args)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(p, b)
-    print(json.dumps(result), flush=True)
+        result["cpu_baseline"] = cpu_baseline(p, b, x_main, c4)
+    result["fp32_vcycle_vs_fp64"] = summarise_precision(c4)
+    result.update(summarise_legs(legs))
+    if args.legs_out:
+        os.makedirs(os.path.dirname(os.path.abspath(args.legs_out)), exist_ok=True)
+        with open(args.legs_out, "w") as f:
+            json.dump({"headline": result, "legs": legs}, f, indent=1)
+    log("[bench] legs " + json.dumps(legs))
+    print(json.dumps(result, separators=(",", ":")), flush=True)
+
+
+def summarise_precision(c4):
+    """The FP32-vs-FP64 leg in a few numbers: p50 setup+solve and solve seconds, iterations,
+    the speed-up and each solution's error against the FP64 oracle's (when computed)."""
+    out = {"workload": c4["workload_short"]}
+    for prec in ("fp64", "fp32"):
+        r = c4[prec]
+        out[prec] = {"setup_plus_solve_s_p50": r["setup_plus_solve_s"]["p50"],
+                     "solve_s_p50": r["solve_s"]["p50"], "iterations": r["iterations"],
+                     "true_rel_residual": float(f"{r['true_rel_residual']:.3e}"),
+                     "rel_err_vs_oracle": r.get("rel_err_vs_oracle")}
+    out["solve_speedup_fp32"] = c4["solve_speedup_fp32"]
+    out["setup_plus_solve_speedup_fp32"] = c4["setup_plus_solve_speedup_fp32"]
+    out["rel_err_fp32_vs_fp64"] = float(f"{c4['rel_err_fp32_vs_fp64']:.3e}")
+    return out
+
+
+def summarise_legs(legs):
+    """One short entry per further leg (their full results go to --legs-out and stderr)."""
+    out = {}
+    if "variants" in legs:
+        out["variants"] = {k: [v.get("iterations"), v.get("operator_complexity"),
+                               v.get("setup_s"), v.get("solve_s")] if "iterations" in v
+                           else v["status"] for k, v in legs["variants"].items()}
+        out["variants_fields"] = "iterations, operator complexity, setup s, solve s"
+    if "numeric_resetup" in legs:
+        r = legs["numeric_resetup"]
+        out["numeric_resetup"] = {"resetup_s_p50": r["resetup_s"]["p50"],
+                                  "fresh_setup_s_p50": r["fresh_setup_same_values_s"]["p50"],
+                                  "speedup": r["speedup_vs_setup"], "iterations": r["iterations"]}
+    if "variant_sweep" in legs:
+        sw = {}
+        for case, v in legs["variant_sweep"].items():
+            its = [t["iterations"] for t in v["table"].values() if "iterations" in t]
+            sw[case] = {"combinations": len(v["table"]), "failed": len(v["table"]) - len(its),
+                        "iterations_min": min(its) if its else None,
+                        "iterations_max": max(its) if its else None}
+        out["variant_sweep"] = sw
+    if "mesh_families" in legs:
+        mf = legs["mesh_families"]
+        pc = mf["perturbed_cube"]
+        fam = {}
+        for w in ("weight_1/d^1", "weight_1/d^2"):
+            t = pc[w]
+            fam[f"perturbed_{w}"] = {k: [t[k]["mean_iterations"], t[k]["failures"]]
+                                     for k in ("plain", "offlmp", "1norm", "offlmp+1norm")
+                                     if k in t}
+            sc = mf["stretched_cube"][w]
+            fam[f"stretched_{w}"] = {"plain_failures": sc["plain_failures"],
+                                     "more_iterations_than_plain": {
+                                         k: (v["plain_minus_it"] or {}).get("more_than_plain")
+                                         for k, v in sc["vs_plain"].items()}}
+        fam["fields"] = "perturbed: [mean iterations, failures] per variant"
+        out["mesh_families"] = fam
+    if "gmres" in legs:
+        out["gmres"] = {k: [v.get("steps", v.get("gmres_steps")),
+                            v.get("solve_s_p50", v.get("gmres_solve_s_p50"))]
+                        for k, v in legs["gmres"].items()}
+    if "systems" in legs:
+        out["systems"] = {k: [v["iterations"], v["setup_s_p50"], v["solve_s_p50"]]
+                          for k, v in legs["systems"].items() if k != "problem"}
+    if "serving" in legs:
+        sv = legs["serving"]
+        c = sv["closed_loop"]
+        srv = {"closed_loop_solves_per_s": c["solves_per_s"], "failed": c["failed"],
+               "closed_loop_latency_s": [c["latency_s"]["p50"], c["latency_s"]["p99"]]}
+        for k, v in sv.items():
+            if k.startswith("open_loop_"):
+                srv[k + "_latency_s"] = [v["latency_s"]["p50"], v["latency_s"]["p99"],
+                                         v["arrival_rate_per_s"]]
+        t = sv["closed_loop_tight_budget"]
+        srv["tight_budget_solves_per_s"] = t["solves_per_s"]
+        srv["fields"] = "latency [p50, p99] (open loop: and arrivals per s)"
+        out["serving"] = srv
+    return out
 
 
 def stream_probe(nbytes=512 << 20, reps=10):
@@ -263,12 +358,12 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, dtype="f64"):
     """HBM bytes per fine-level SpMV launch from the committed counter summary, or None when
     the summary is missing, covers another workload, or the kernel has changed since."""
     kv = {}
     try:
-        with open(TRAFFIC_PROFILE) as f:
+        with open(TRAFFIC_PROFILE.format(workload=workload, dtype=dtype)) as f:
             for line in f:
                 k, sep, v = line.partition(":")
                 k = k.strip().strip("-*` ")
@@ -284,30 +379,39 @@ def measured_traffic(workload):
         return None
 
 
-def roofline(tot, workload=WORKLOAD):
+def roofline(tot, workload=WORKLOAD, dtype="f64", note=None):
     """Fine-level SpMV (sliced ELL; the kernel with the largest share of the solve):
-    algorithmic bytes per launch (12 B per entry + slice offsets + the vectors its fused
-    epilogue reads/writes; padding not counted) over the launch duration from HIP events
-    recorded around every such launch of the timed steps, on the library's stream."""
+    algorithmic bytes per launch (entries x (value + 4 B index) + slice offsets + x once + the
+    vectors its fused epilogue reads/writes; padding not counted) over the launch duration from
+    HIP events recorded around every such launch of one profiled solve, on the library's
+    stream."""
     if not tot["launches"]:
         return None
     avg_ms = tot["ms"] / tot["launches"]
     bytes_per = tot["bytes"] / tot["launches"]
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9
-    return {"bound": "hbm",
-            "kernel": "k_spmv_sell (fine-level operator, sliced ELL, all fused epilogues)",
-            "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(workload),
-            "launches": tot["launches"], "avg_us": round(avg_ms * 1e3, 2),
-            "algorithmic_bytes_per_launch": round(bytes_per)}
+    out = {"bound": "hbm",
+           "kernel": f"k_spmv_sell<{'double' if dtype == 'f64' else 'float'}> (fine-level "
+                     "operator, sliced ELL, all fused epilogues)",
+           "input": workload,
+           "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(workload, dtype),
+           "launches": tot["launches"], "avg_us": round(avg_ms * 1e3, 2),
+           "algorithmic_bytes_per_launch": round(bytes_per)}
+    if note:
+        out["note"] = note
+    return out
 
 
-def precision_leg(solver, problems, workload, reps=5):
+def c4_leg(solver, problems, workload, reps=5):
     """FP32-stored/applied V-cycle inside FP64 PCG against the all-FP64 solve on the 160^3
     z-stretched cube (4.1M unknowns), same GPU, same input, relative residual 1e-10 for both.
     One untimed setup+solve per precision first; then `reps` timed setup+solve pairs (p50 and
-    p99 reported).  Accuracy: the true residual ||b - A x|| / ||b|| (host, scipy) and the
-    relative difference between the two solutions."""
+    p99 reported), with nothing instrumented; then one more solve with HIP events around the
+    fine-level SpMV launches (the roofline: 424 MB per FP64 launch, more than the 256 MB
+    Infinity Cache holds).  Accuracy: the true residual ||b - A x|| / ||b|| (host, scipy), the
+    relative difference between the two solutions, and (added by the CPU-baseline leg) each
+    one's error against the FP64 oracle's solution."""
     import torch
     import scipy.sparse as sp
     p = problems.workload(workload)
@@ -319,7 +423,8 @@ def precision_leg(solver, problems, workload, reps=5):
     A = sp.csr_matrix((p.val, p.col, p.rp), shape=(p.n, p.n))
     out = {"workload": f"{workload}: 3-D 7-point FV Laplacian, 160^3 unknowns, z-stretched "
                        "1:1000, plain SA theta=0.02, Chebyshev(2), rtol 1e-10",
-           "n": p.n, "nnz": p.nnz}
+           "workload_short": f"{workload}, rtol 1e-10", "n": p.n, "nnz": p.nnz,
+           "problem": p, "b": b}
     xs = {}
     for prec in ("fp64", "fp32"):
         o = solver.Options(theta=0.02, rtol=1e-10, precision=prec)
@@ -339,7 +444,17 @@ def precision_leg(solver, problems, workload, reps=5):
             setups.append(t1 - t0)
             solves.append(t2 - t1)
             info = h.info()
-            h.close()
+            if len(setups) < reps:
+                h.close()
+        h.profile(True)
+        h.solve(db)
+        torch.cuda.synchronize()
+        dt = "f64" if prec == "fp64" else "f32"
+        out[f"roofline_{prec}"] = roofline(
+            h.profile_read(), workload, dt,
+            note=f"160^3 fine operator in {dt}: {'424' if dt == 'f64' else '277'} MB of "
+                 "compulsory bytes per launch, more than the 256 MB Infinity Cache holds")
+        h.close()
         xs[prec] = x.clone()
         xh = x.cpu().numpy()
         res = np.linalg.norm(b - A @ xh) / np.linalg.norm(b)
@@ -352,14 +467,18 @@ def precision_leg(solver, problems, workload, reps=5):
                      "levels": info["levels"],
                      "operator_complexity": round(info["operator_complexity"], 4),
                      "solve_hbm_gbs": round(solve_bytes_model(info, prec) * (it + 1)
-                                            / pct(solves, 50) / 1e9, 1)}
+                                            / pct(solves, 50) / 1e9, 1),
+                     "x": xh}
     out["rel_err_fp32_vs_fp64"] = float(torch.linalg.norm(xs["fp32"] - xs["fp64"]) /
                                         torch.linalg.norm(xs["fp64"]))
     out["solve_speedup_fp32"] = round(out["fp64"]["solve_s"]["p50"] /
                                       out["fp32"]["solve_s"]["p50"], 3)
     out["setup_plus_solve_speedup_fp32"] = round(out["fp64"]["setup_plus_solve_s"]["p50"] /
                                                  out["fp32"]["setup_plus_solve_s"]["p50"], 3)
-    del drp, dcol, dval, db
+    log(f"[bench] 160^3: fp64 {out['fp64']['iterations']} its "
+        f"{out['fp64']['setup_plus_solve_s']['p50'] * 1e3:.1f} ms, fp32 "
+        f"{out['fp32']['iterations']} its {out['fp32']['setup_plus_solve_s']['p50'] * 1e3:.1f} ms")
+    del drp, dcol, dval, db, xs
     torch.cuda.empty_cache()
     return out
 
@@ -436,6 +555,13 @@ def variant_sweep_leg(solver, problems):
             f"{k} {v.get('iterations', v['status'])}" for k, v in table.items()))
         del drp, dcol, dval, b
     return out
+
+
+def _spawn():
+    """Worker processes for host-side input generation are spawned, not forked: a fork of a
+    process that has initialised the GPU runtime would inherit its state."""
+    import multiprocessing
+    return multiprocessing.get_context("spawn")
 
 
 def _to_device(p, b, X):
@@ -536,7 +662,7 @@ def families_leg(solver, problems, seeds=10, ne=60):
     powers = (1, 2)
     out = {}
     t0 = time.perf_counter()
-    with ProcessPoolExecutor(max_workers=workers) as ex:
+    with ProcessPoolExecutor(max_workers=workers, mp_context=_spawn()) as ex:
         meshes = list(ex.map(_perturbed_mesh, [(ne, s) for s in range(seeds)]))
     t_mesh = time.perf_counter() - t0
     runs = {pw: {"+".join(v) or "plain": [] for v in combos} for pw in powers}
@@ -564,7 +690,7 @@ def families_leg(solver, problems, seeds=10, ne=60):
                 "cnstrnt": ("cnstrnt",), "sprsfy": ("sprsfy",)}
     res = {pw: {k: [] for k in variants} for pw in powers}
     t0 = time.perf_counter()
-    with ProcessPoolExecutor(max_workers=workers) as ex:
+    with ProcessPoolExecutor(max_workers=workers, mp_context=_spawn()) as ex:
         for mesh in ex.map(_stretched_mesh, cases):
             dev = _to_device(*mesh)
             for pw in powers:
@@ -733,7 +859,7 @@ def _build_requests(problems, count):
     from concurrent.futures import ProcessPoolExecutor
     reqs = problems.serving_requests(count)
     workers = max(1, min(16, len(os.sched_getaffinity(0))))
-    with ProcessPoolExecutor(max_workers=workers) as ex:
+    with ProcessPoolExecutor(max_workers=workers, mp_context=_spawn()) as ex:
         built = list(ex.map(problems.build_request, reqs, chunksize=4))
     return reqs, built
 
@@ -828,24 +954,47 @@ def serving_leg(solver, problems, args):
     return out
 
 
-def cpu_baseline(p, b):
-    """The CPU oracle (plain single-threaded C++) on the same workload: one full setup and
-    solve (about 10-15 s on one core), in seconds per setup+solve."""
+def cpu_baseline(p, b, x_gpu, c4):
+    """The CPU oracle (plain single-threaded C++) on the same workload, timed: full setups and
+    solves of the 128^3 cube (two, about 7 s on one core), in seconds per setup+solve.  The same
+    runs give the reference solutions the GPU's are compared with: the 128^3 FP64 solve, and
+    (one untimed oracle run on the 160^3 cube, rtol 1e-10) the FP64 and FP32-V-cycle solves of
+    the precision leg, whose errors are written into `c4`."""
     from oracle import oracle as orc
     try:
         cores = len(os.sched_getaffinity(0))
     except Exception:
         cores = os.cpu_count()
-    t0 = time.perf_counter()
-    h = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, theta=0.02, rtol=1e-8)
-    t1 = time.perf_counter()
-    r = h.solve(b)
-    t2 = time.perf_counter()
-    return {"value": round(t2 - t0, 3), "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": f"one full setup + PCG solve of the same workload on one thread "
-                      f"({cores} host cores available); setup {t1 - t0:.2f} s, solve "
-                      f"{t2 - t1:.2f} s, {r['iterations']} iterations",
-            "higher_is_better": False}
+    reps = 2
+    ts, tso = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        h = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, theta=0.02, rtol=1e-8)
+        t1 = time.perf_counter()
+        r = h.solve(b)
+        t2 = time.perf_counter()
+        ts.append(t2 - t0)
+        tso.append(t2 - t1)
+        del h
+    err_main = float(np.linalg.norm(x_gpu - r["x"]) / np.linalg.norm(r["x"]))
+    q, bq = c4.pop("problem"), c4.pop("b")
+    h = orc.OracleHierarchy(q.n, q.rp, q.col, q.val, theta=0.02, rtol=1e-10)
+    rq = h.solve(bq)
+    del h
+    for prec in ("fp64", "fp32"):
+        xg = c4[prec].pop("x")
+        c4[prec]["rel_err_vs_oracle"] = float(f"{np.linalg.norm(xg - rq['x']) / np.linalg.norm(rq['x']):.3e}")
+    c4["oracle_iterations"] = rq["iterations"]
+    log(f"[bench] oracle: 128^3 setup+solve {np.mean(ts):.2f} s ({r['iterations']} its), GPU "
+        f"error {err_main:.2e}; 160^3: fp64 error {c4['fp64']['rel_err_vs_oracle']}, fp32 "
+        f"error {c4['fp32']['rel_err_vs_oracle']}")
+    return {"value": round(float(np.mean(ts)), 3), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} full setups + PCG solves of the same workload on one thread "
+                      f"({cores} host cores available); solve {np.mean(tso):.2f} s of it; "
+                      f"{r['iterations']} iterations",
+            "higher_is_better": False,
+            "gpu_rel_err_vs_oracle": float(f"{err_main:.3e}"),
+            "oracle_iterations": r["iterations"]}
 
 
 if __name__ == "__main__":
