@@ -61,6 +61,7 @@ enum { SA_CHEBYSHEV = 0, SA_JACOBI = 1 };
 enum { SA_FP64 = 0, SA_FP32_VCYCLE = 1 };
 enum { SA_BETA_FR = 0, SA_BETA_PR = 1 };
 enum { SA_COARSE_CHOLESKY = 0, SA_COARSE_LU = 1 };
+enum { SA_ISOLATED_LEFT_OUT = 0, SA_ISOLATED_SINGLETON = 1 };
 
 /* Options.  struct_size must be sizeof(sa_options); sa_default_options fills the defaults
  * given in brackets (the paper's settings where it states them). */
@@ -88,6 +89,11 @@ typedef struct {
   int32_t coarse_solver;  /* SA_COARSE_CHOLESKY (symmetric coarsest operator; a nonsymmetric
                              one is SA_ERR_COARSE_FACTOR) | SA_COARSE_LU (no pivoting; for
                              nonsymmetric matrices solved with GMRES, Sec. 3.4) [Cholesky]     */
+  int32_t isolated;       /* a vertex without strong connections: SA_ISOLATED_LEFT_OUT (in no
+                             aggregate, a zero row of the tentative prolongator; smoothed
+                             only) | SA_ISOLATED_SINGLETON (an aggregate of its own, so the
+                             aggregates cover every vertex as in Sec. 1.1) [left out].  Systems
+                             SA always leaves such nodes out                                   */
 } sa_options;
 
 typedef struct {

@@ -40,6 +40,8 @@ typedef struct {
   int32_t pcg_beta;       /* 0 Fletcher-Reeves, 1 Polak-Ribiere (flexible)                 */
   int32_t dist_power;     /* distance-Laplacian weight 1/d^p: 1 (the text of Sec. 3.1) or 2 */
   int32_t coarse_solver;  /* 0 Cholesky (symmetric coarsest operator), 1 LU without pivoting */
+  int32_t singletons;     /* vertices without strong connections: 0 left out of every
+                             aggregate, 1 a singleton aggregate each (Sec. 1.1 covering)    */
 } orc_options;
 
 void orc_default_options(orc_options *o);
@@ -91,8 +93,8 @@ int orc_distance_strength(int32_t n, const int32_t *rp, const int32_t *col,
                           const double *coords, int32_t dim, double theta, int32_t dist_power,
                           uint8_t *mask);
 int orc_aggregate(int32_t n, const int32_t *rp, const int32_t *col, const uint8_t *mask,
-                  int32_t order, uint64_t seed, int32_t level, int32_t *agg, uint8_t *is_root,
-                  int32_t *nc);
+                  int32_t order, uint64_t seed, int32_t level, int32_t singletons,
+                  int32_t *agg, uint8_t *is_root, int32_t *nc);
 int orc_sprsfy(int32_t n, const int32_t *rp, const int32_t *col, uint8_t *mask,
                const int32_t *agg, const uint8_t *is_root, int32_t nc);
 /* filtered matrix; out_rp [n+1], out_col/out_val capacity nnz(A) */

@@ -23,7 +23,7 @@ class OrcOptions(C.Structure):
                 ("max_coarse", C.c_int32), ("smoother", C.c_int32), ("degree", C.c_int32),
                 ("cheb_ratio", C.c_double), ("cheb_boost", C.c_double), ("rtol", C.c_double),
                 ("max_iter", C.c_int32), ("pcg_beta", C.c_int32), ("dist_power", C.c_int32),
-                ("coarse_solver", C.c_int32)]
+                ("coarse_solver", C.c_int32), ("singletons", C.c_int32)]
 
 
 _lib = None
@@ -63,7 +63,8 @@ def _setup_prototypes(L):
     L.orc_strength.argtypes = [C.c_int32, P, P, P, C.c_double, P]
     L.orc_distance_strength.argtypes = [C.c_int32, P, P, P, C.c_int32, C.c_double, C.c_int32,
                                         P]
-    L.orc_aggregate.argtypes = [C.c_int32, P, P, P, C.c_int32, C.c_uint64, C.c_int32, P, P, P]
+    L.orc_aggregate.argtypes = [C.c_int32, P, P, P, C.c_int32, C.c_uint64, C.c_int32, C.c_int32,
+                                P, P, P]
     L.orc_sprsfy.argtypes = [C.c_int32, P, P, P, P, P, C.c_int32]
     L.orc_lump.argtypes = [C.c_int32, P, P, P, P, C.c_int32, C.c_double, P, P, P]
     L.orc_diag.argtypes = [C.c_int32, P, P, P, C.c_int32, C.c_double, P]
@@ -111,7 +112,7 @@ def make_options(theta=0.02, variants=(), one_norm_power=0, tau=1.1, sigma=1.0 /
                  power_iters=10, agg_order=0, seed=12345, max_levels=10, max_coarse=1000,
                  smoother="chebyshev", degree=2, cheb_ratio=10.0, cheb_boost=1.0, rtol=1e-8,
                  max_iter=500, pcg_beta="fr", dist_power=1, coarse_solver="cholesky",
-                 **_ignored) -> OrcOptions:
+                 isolated="left_out", **_ignored) -> OrcOptions:
     o = OrcOptions()
     lib().orc_default_options(C.byref(o))
     o.theta = theta
@@ -136,6 +137,7 @@ def make_options(theta=0.02, variants=(), one_norm_power=0, tau=1.1, sigma=1.0 /
     o.pcg_beta = 1 if pcg_beta in (1, "pr") else 0
     o.dist_power = dist_power
     o.coarse_solver = 1 if coarse_solver in (1, "lu") else 0
+    o.singletons = 1 if isolated in (1, "singleton") else 0
     return o
 
 
@@ -297,13 +299,16 @@ def distance_strength(n, rp, col, coords, theta, dist_power=1):
     return m
 
 
-def aggregate(n, rp, col, mask, order=0, seed=12345, level=0):
+def aggregate(n, rp, col, mask, order=0, seed=12345, level=0, isolated="left_out"):
+    """isolated: "left_out" (agg -1 for a vertex without strong connections) or "singleton"
+    (a singleton aggregate each)."""
     rp, col, mask = _i32(rp), _i32(col), _u8(mask)
     agg = np.empty(n, dtype=np.int32)
     root = np.empty(n, dtype=np.uint8)
     nc = C.c_int32()
-    _check(lib().orc_aggregate(n, _p(rp), _p(col), _p(mask), order, seed, level, _p(agg),
-                               _p(root), C.byref(nc)))
+    _check(lib().orc_aggregate(n, _p(rp), _p(col), _p(mask), order, seed, level,
+                               1 if isolated in (1, "singleton") else 0, _p(agg), _p(root),
+                               C.byref(nc)))
     return agg, root, nc.value
 
 

@@ -273,12 +273,14 @@ std::vector<std::vector<int>> strength_graph(const Csr &A, const std::vector<uin
 // Reading (leftovers): every still-unaggregated vertex joins the phase-1 aggregate it has
 // the most strong connections to, ties to the smaller aggregate number; phase 1 leaves no
 // vertex without an aggregated neighbour, so no new aggregates are needed.
-// Isolated vertices (no strong connection at all): the aggregates cover every vertex (Sec.
-// 1.1, aggregates), and the root rule applies to them as to any other vertex -- nothing
-// around an isolated vertex is aggregated -- so each becomes the root of a singleton
-// aggregate in phase 1.  With `singletons` false (systems SA, where a single node carries
-// fewer unknowns than nullspace vectors) such a vertex joins no aggregate instead (agg = -1,
-// a zero row of the tentative prolongator).
+// Reading (isolated vertices, no strong connection at all): by default such a vertex joins
+// no aggregate (agg = -1, a zero row of the tentative prolongator) and the smoother alone
+// treats it.  This departs from the covering property of Sec. 1.1 (aggregates): with
+// `singletons` set, the root rule is applied to it as to any other vertex -- nothing around
+// it is aggregated -- so it becomes the root of a singleton aggregate, as the paper's text
+// has it.  The covering form carries such vertices unchanged to every coarser level, where
+// a whole plane of them (the stretched cubes) stalls the coarsening above the dense coarse
+// solver's limit and their zero row sums give zero or negative filtered diagonals.
 // Reading (numbering): aggregate number = rank of its root's vertex index among roots.
 // ------------------------------------------------------------------------------------
 int aggregate(const std::vector<std::vector<int>> &G, int order, uint64_t seed, int level,
@@ -1106,11 +1108,10 @@ int build_level(Hier &H, int l) {
   auto G = strength_graph(L.As, L.mask);
   L.nnzG = 0;
   for (auto &g : G) L.nnzG += (int64_t)g.size();
-  int nc = aggregate(G, o.agg_order, o.seed, l, true, L.agg, L.is_root);
+  int nc = aggregate(G, o.agg_order, o.seed, l, o.singletons != 0, L.agg, L.is_root);
   if (nc < 0) return nc;
   L.nc = nc;
-  // no strong connection left (every aggregate a singleton): this level becomes the coarsest
-  if (nc == L.A.nr) return 1;
+  if (L.nnzG == 0) return 1;  // no strong connection left: this level becomes the coarsest
   if (nc >= L.A.nr) return fail(ST_STALLED, "coarsening stalled");
   if (o.variants & V_SPRSFY) sprsfy(L.As, L.mask, L.agg, L.is_root, nc);
   return numeric_level(H, l);
@@ -1243,6 +1244,7 @@ void orc_default_options(orc_options *o) {
   o->pcg_beta = 0;
   o->dist_power = 1;
   o->coarse_solver = 0;
+  o->singletons = 0;
 }
 
 uint64_t orc_splitmix64(uint64_t seed, uint64_t k) { return splitmix64(seed, k); }
@@ -1760,14 +1762,14 @@ int orc_strength(int32_t n, const int32_t *rp, const int32_t *col, const double 
 }
 
 int orc_aggregate(int32_t n, const int32_t *rp, const int32_t *col, const uint8_t *mask,
-                  int32_t order, uint64_t seed, int32_t level, int32_t *agg, uint8_t *is_root,
-                  int32_t *nc) {
+                  int32_t order, uint64_t seed, int32_t level, int32_t singletons,
+                  int32_t *agg, uint8_t *is_root, int32_t *nc) {
   Csr A = make_csr(n, n, rp, col, nullptr);
   std::vector<uint8_t> m(mask, mask + rp[n]);
   auto G = strength_graph(A, m);
   std::vector<int32_t> a;
   std::vector<uint8_t> r;
-  int c = aggregate(G, order, seed, level, true, a, r);
+  int c = aggregate(G, order, seed, level, singletons != 0, a, r);
   if (c < 0) return c;
   std::memcpy(agg, a.data(), sizeof(int32_t) * n);
   std::memcpy(is_root, r.data(), n);

@@ -49,7 +49,7 @@ class SaOptions(C.Structure):
                 ("degree", C.c_int32), ("precision", C.c_int32), ("cheb_ratio", C.c_double),
                 ("cheb_boost", C.c_double), ("rtol", C.c_double), ("max_iter", C.c_int32),
                 ("pcg_beta", C.c_int32), ("dist_power", C.c_int32),
-                ("coarse_solver", C.c_int32)]
+                ("coarse_solver", C.c_int32), ("isolated", C.c_int32)]
 
 
 class SaCsr(C.Structure):

@@ -92,6 +92,8 @@ static void validate_options(const sa_options &o) {
   if (o.dist_power != 1 && o.dist_power != 2) throw Error(SA_ERR_INVALID_ARG, "dist_power");
   if (o.coarse_solver != SA_COARSE_CHOLESKY && o.coarse_solver != SA_COARSE_LU)
     throw Error(SA_ERR_INVALID_ARG, "coarse_solver");
+  if (o.isolated != SA_ISOLATED_LEFT_OUT && o.isolated != SA_ISOLATED_SINGLETON)
+    throw Error(SA_ERR_INVALID_ARG, "isolated");
 }
 
 static void copy_in(void *dst, const void *src, size_t bytes, sa_location loc, hipStream_t s) {
@@ -295,9 +297,10 @@ static bool build_level(sa_hierarchy *h, int l) {
   L.is_root = ar.alloc<uint8_t>(n);
   int32_t *root_vertex = nullptr;
   if (o.variants & SA_SPRSFY) {  // the drops change the labels lumping reads: in sequence
-    L.nc = aggregate(n, nnzG, grp, gcol, o.agg_order, o.seed, l, true, L.agg, L.is_root, tmp,
-                     &root_vertex, &L.mis_rounds, s);
-    if (L.nc == n) return false;  // no strong connection: every aggregate a singleton
+    L.nc = aggregate(n, nnzG, grp, gcol, o.agg_order, o.seed, l,
+                     o.isolated == SA_ISOLATED_SINGLETON, L.agg, L.is_root, tmp, &root_vertex,
+                     &L.mis_rounds, s);
+    if (nnzG == 0) return false;  // no strong connection: the coarsest level
     if (L.nc >= n) throw Error(SA_ERR_COARSEN_STALLED, "coarsening stalled");
     sprsfy(n, L.As.rp, L.As.col, L.mask, L.agg, root_vertex, L.nc, s);
     numeric_level(h, l, true);
@@ -311,12 +314,11 @@ static bool build_level(sa_hierarchy *h, int l) {
   if (!h->side) h->side = side_stream(s);
   stream_after(h->side, s);
   numeric_damping(h, l, h->side, h->err + 2);
-  L.nc = aggregate(n, nnzG, grp, gcol, o.agg_order, o.seed, l, true, L.agg, L.is_root, tmp,
-                   &root_vertex, &L.mis_rounds, s);
+  L.nc = aggregate(n, nnzG, grp, gcol, o.agg_order, o.seed, l,
+                   o.isolated == SA_ISOLATED_SINGLETON, L.agg, L.is_root, tmp, &root_vertex,
+                   &L.mis_rounds, s);
   stream_after(s, h->side);
-  // no strong connection (every aggregate a singleton): the coarsest level, which keeps no
-  // numeric part
-  if (L.nc == n) {
+  if (nnzG == 0) {  // no strong connection: the coarsest level, which keeps no numeric part
     L.Abar = Csr{};
     L.invD = L.lam_d = L.omega_d = nullptr;
     return false;
@@ -1084,6 +1086,7 @@ void sa_default_options(sa_options *o) {
   o->pcg_beta = -1;
   o->dist_power = 1;
   o->coarse_solver = SA_COARSE_CHOLESKY;
+  o->isolated = SA_ISOLATED_LEFT_OUT;
 }
 
 sa_status sa_setup_coords(const sa_context *ctx, const sa_csr *A, const double *nullspace,

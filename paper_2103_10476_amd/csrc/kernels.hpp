@@ -200,10 +200,9 @@ int64_t strength_graph(int32_t n, const int32_t *rp, const int32_t *col, const u
                        const int32_t *scount, bool wave, Arena &ar, int32_t **grp,
                        int32_t **gcol, hipStream_t s);
 // Aggregation (roots = lexicographically-first distance-2 MIS in priority order; phase-2
-// join).  A vertex without strong connections is the root of a singleton aggregate when
-// `singletons` is set (the scalar method: the aggregates cover every vertex), and joins no
-// aggregate (agg -1) otherwise (systems, where one node carries fewer unknowns than nullspace
-// vectors).  Returns nc; agg[n], is_root[n], root_vertex[nc].
+// join).  A vertex without strong connections joins no aggregate (agg -1), or is the root of
+// a singleton aggregate when `singletons` is set (the covering reading).  Returns nc;
+// agg[n], is_root[n], root_vertex[nc].
 int32_t aggregate(int32_t n, int64_t nnzG, const int32_t *grp, const int32_t *gcol, int32_t order,
                   uint64_t seed, int32_t level, bool singletons, int32_t *agg,
                   uint8_t *is_root, Arena &ar, int32_t **root_vertex, int32_t *rounds,

@@ -39,6 +39,7 @@ class Options:
     pcg_beta: str = "auto"
     dist_power: int = 1
     coarse_solver: str = "cholesky"
+    isolated: str = "left_out"
 
     def to_c(self) -> _lib.SaOptions:
         o = _lib.SaOptions()
@@ -66,6 +67,7 @@ class Options:
         o.pcg_beta = {"auto": -1, "fr": 0, "pr": 1}[self.pcg_beta]
         o.dist_power = self.dist_power
         o.coarse_solver = 1 if self.coarse_solver in ("lu", 1) else 0
+        o.isolated = 1 if self.isolated in ("singleton", 1) else 0
         return o
 
     def as_dict(self) -> dict:

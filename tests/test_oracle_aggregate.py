@@ -23,14 +23,15 @@ def graph_from_mask(p, mask):
     return g
 
 
-def mis2_rounds(g, prio):
+def mis2_rounds(g, prio, singletons=False):
     """Independent route to the aggregation roots: rounds of the distance-2 maximal
     independent set rule (a vertex enters when it has the best priority among the undecided
     vertices within distance 2 and no entered vertex is within distance 2).  An isolated
-    vertex is alone in its ball, so it enters in the first round."""
+    vertex is alone in its ball: it enters in the first round when isolated vertices are
+    singleton aggregates, and never takes part otherwise."""
     n = len(g)
     UND, IN, OUT = 1, 0, 2
-    state = [UND] * n
+    state = [UND if (g[v] or singletons) else OUT for v in range(n)]
     while any(s == UND for s in state):
         key = [(state[v], prio[v]) for v in range(n)]
         k1 = [min([key[v]] + [key[u] for u in g[v]]) for v in range(n)]
@@ -54,20 +55,24 @@ def dist2_ball(g, v):
     return out
 
 
-def check_partition(g, agg, root, nc):
+def check_partition(g, agg, root, nc, singletons=False):
     n = len(g)
     roots = [v for v in range(n) if root[v]]
     assert len(roots) == nc
     assert sorted(agg[v] for v in roots) == list(range(nc))
     # numbering = rank of the root's index
     assert [agg[v] for v in roots] == list(range(nc))
-    # eq. (aggregates): the aggregates are disjoint (agg is a function) and cover every
-    # vertex, none of them empty
-    assert all(0 <= agg[v] < nc for v in range(n))
-    assert set(agg) == set(range(nc))
+    # eq. (aggregates): the aggregates are disjoint (agg is a function), none is empty, and
+    # they cover every vertex with a strong connection -- every vertex at all when isolated
+    # vertices are singleton aggregates, which the left-out reading drops
+    assert set(a for a in agg if a >= 0) == set(range(nc))
     for v in range(n):
-        if not g[v]:
-            assert root[v] and list(agg).count(agg[v]) == 1  # an isolated vertex: singleton
+        if g[v]:
+            assert 0 <= agg[v] < nc
+        elif singletons:
+            assert root[v] and list(agg).count(agg[v]) == 1
+        else:
+            assert agg[v] == -1 and not root[v]
     for a, ra in enumerate(roots):
         for rb in roots[a + 1:]:
             assert rb not in dist2_ball(g, ra)  # roots at graph distance >= 3
@@ -83,26 +88,29 @@ def random_sym_pattern(rng, n, density):
     return pb.from_dense(d)
 
 
+@pytest.mark.parametrize("isolated", ["left_out", "singleton"])
 @pytest.mark.parametrize("order", [0, 1])
-def test_greedy_equals_mis2_rounds(orc, order):
+def test_greedy_equals_mis2_rounds(orc, order, isolated):
     """The greedy root choice is the lexicographically-first distance-2 MIS; brute force by
-    rounds on random graphs, natural and hashed priority."""
+    rounds on random graphs (isolated vertices among them), natural and hashed priority."""
     rng = np.random.default_rng(5 + order)
+    sing = isolated == "singleton"
     for trial in range(60):
         n = int(rng.integers(2, 40))
         p = random_sym_pattern(rng, n, rng.uniform(0.02, 0.3))
         mask = np.where(p.col == rows_of(p.rp), 3, 1).astype(np.uint8)
         seed = int(rng.integers(0, 2**63))
-        agg, root, nc = orc.aggregate(p.n, p.rp, p.col, mask, order=order, seed=seed, level=2)
+        agg, root, nc = orc.aggregate(p.n, p.rp, p.col, mask, order=order, seed=seed, level=2,
+                                      isolated=isolated)
         g = graph_from_mask(p, mask)
         if order == 0:
             prio = list(range(n))
         else:
             prio = [((orc.splitmix64(seed, (2 << 56) | (2 << 40) | v) >> 34) << 32) | v
                     for v in range(n)]
-        expect = mis2_rounds(g, prio)
+        expect = mis2_rounds(g, prio, sing)
         assert [bool(x) for x in root] == expect
-        check_partition(g, list(agg), list(root), nc)
+        check_partition(g, list(agg), list(root), nc, sing)
         # leftovers join the aggregate they have the most strong edges to (ties: smaller id)
         owner = {}
         for v in range(n):
@@ -158,38 +166,42 @@ def test_fig1_vertical_strong_gives_3x1_lines(orc):
 
 
 def test_tentative_prolongator_properties(orc):
-    """Sec. 1.1: Ptent has one unit entry per row, reproduces the constant, and its
-    column-normalised form Q has orthonormal columns (one nullspace vector: QR = scaling)."""
+    """Sec. 1.1: Ptent has one unit entry per aggregated row, reproduces the constant there,
+    and its column-normalised form Q has orthonormal columns (one nullspace vector: QR =
+    scaling)."""
     p = pb.fd5_stretched(20, 20, 100.0)
     mask = orc.strength(p.n, p.rp, p.col, p.val, 0.02)
     agg, root, nc = orc.aggregate(p.n, p.rp, p.col, mask)
-    assert np.all((agg >= 0) & (agg < nc))
     Pt = np.zeros((p.n, nc))
-    Pt[np.arange(p.n), agg] = 1.0
-    assert np.all(Pt.sum(axis=1) == 1.0)
-    assert np.array_equal(Pt @ np.ones(nc), np.ones(p.n))
+    rows = np.nonzero(agg >= 0)[0]
+    Pt[rows, agg[rows]] = 1.0
+    assert np.all(Pt.sum(axis=1)[rows] == 1.0)
+    assert np.array_equal(Pt @ np.ones(nc), (agg >= 0).astype(float))
     Q = Pt / np.sqrt(Pt.sum(axis=0))
     np.testing.assert_allclose(Q.T @ Q, np.eye(nc), atol=1e-15)
 
 
-def test_isolated_vertex_is_a_singleton_aggregate(orc):
-    """Sec. 1.1, eq. (aggregates): the aggregates cover every vertex.  A vertex without strong
-    connections has nothing aggregated around it, so the root rule makes it the root of an
-    aggregate of its own; its number is the rank of its index among the roots."""
+def test_isolated_vertex_left_out_or_singleton(orc):
+    """A vertex without strong connections joins no aggregate by default (a zero row of the
+    tentative prolongator).  With the covering reading of Sec. 1.1, eq. (aggregates), the
+    root rule makes it the root of an aggregate of its own (nothing around it is
+    aggregated), numbered by the rank of its index among the roots."""
     d = np.array([[1.0, 0.0, 0.0, -1e-6], [0.0, 2.0, -1.0, 0.0], [0.0, -1.0, 2.0, -1.0],
                   [-1e-6, 0.0, -1.0, 2.0]])
     p = pb.from_dense(d)
     mask = orc.strength(p.n, p.rp, p.col, p.val, 0.1)
     agg, root, nc = orc.aggregate(p.n, p.rp, p.col, mask)
+    assert nc == 1 and list(agg) == [-1, 0, 0, 0] and list(root) == [0, 1, 0, 0]
+    agg, root, nc = orc.aggregate(p.n, p.rp, p.col, mask, isolated="singleton")
     assert nc == 2 and list(agg) == [0, 1, 1, 1] and list(root) == [1, 1, 0, 0]
 
 
-def test_isolated_vertices_keep_coarsening_going(orc):
-    """A level whose strong graph leaves some vertices isolated still coarsens (the others
-    aggregate), each isolated vertex becoming one coarse unknown; the hierarchy converges."""
+def test_singleton_reading_on_a_random_coefficient_cube(orc):
+    """Covering reading: a random-coefficient cube with isolated vertices still coarsens
+    (the others aggregate), each isolated vertex a coarse unknown of its own; it converges."""
     p = pb.q1_random_kappa(12, seed=3)
     h = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, theta=0.02, variants=["offlmp", "1norm"],
-                            max_coarse=50, rtol=1e-8)
+                            max_coarse=50, rtol=1e-8, isolated="singleton")
     L0 = h.levels[0]
     g = graph_from_mask(pb.CsrProblem(p.n, p.rp, p.col, p.val, "q1"), L0.mask)
     iso = [v for v in range(p.n) if not g[v]]
@@ -200,6 +212,29 @@ def test_isolated_vertices_keep_coarsening_going(orc):
     assert h.levels[1].n == L0.nc < p.n
     r = h.solve(pb.random_rhs(p.n, 4))
     assert r["converged"] and r["iterations"] < 40
+
+
+def test_left_out_reading_keeps_the_stretched_cube_coarsening(orc):
+    """What leaving isolated vertices out buys, on the benchmark family (64^3 z-stretched
+    7-point cube, aspect 1:1000, 1Norm): on level 2 a whole z-plane of 64 x 64 vertices has
+    no strong connection.  As singleton aggregates (the covering reading) those 4096 vertices
+    are carried to every coarser level, so the coarsening stalls: the last levels shrink by
+    well under 1% and the coarsest keeps more than 4096 unknowns.  Left out, the plane is
+    treated by the smoother alone and the hierarchy reaches a small coarsest level; both
+    converge."""
+    p = pb.fd7_stretched(64, 1000.0)
+    b = pb.random_rhs(p.n, 2)
+    kw = dict(theta=0.02, variants=["1norm"], rtol=1e-8)
+    left = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, **kw)
+    iso = [int(np.count_nonzero(L.agg < 0)) for L in left.levels[:-1]]
+    assert 4096 in iso
+    plane = np.nonzero(left.levels[iso.index(4096)].agg < 0)[0]
+    sing = orc.OracleHierarchy(p.n, p.rp, p.col, p.val, isolated="singleton", **kw)
+    ns = [L.n for L in sing.levels]
+    assert ns[-1] > 4096 and ns[-2] - ns[-1] < 0.01 * ns[-2]
+    assert left.levels[-1].n < 1000 and len(left.levels) < len(sing.levels)
+    assert left.solve(b)["converged"] and sing.solve(b)["converged"]
+    assert len(plane) == 4096
 
 
 def _sprsfy_grid(nx=6, ny=6, special=((1, 1), (2, 1))):
