@@ -236,6 +236,23 @@ sa_status sa_solve(sa_hierarchy *h, const double *b, double *x, sa_location loc,
 sa_status sa_solve_gmres(sa_hierarchy *h, const double *b, double *x, sa_location loc,
                          int32_t restart, int32_t *iterations, double *rel_residual);
 
+/* sa_solve_gmres for callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same iteration and results, but
+ * the workspace lives in a fixed 128 MiB array compiled into the library (held by each GPU
+ * the library runs on until the process ends) instead of memory taken for the call.  No
+ * device memory is allocated and the fine-level SpMV timing of sa_profile_enable is off for
+ * the call.  The hierarchy's device must be current.
+ *  - The workspace takes 8 ((2 restart + 1) n + about (restart + 1) n / 4096 + restart^2)
+ *    bytes plus alignment; a call needing more than 128 MiB (e.g. restart 30 with n above
+ *    about 270,000) returns SA_ERR_INVALID_ARG without running (sa_last_error names the
+ *    size).
+ *  - Every call on one GPU uses that GPU's one array: calls that overlap on a GPU (other
+ *    threads, other streams) race and must be serialised by the caller.  Each call writes the
+ *    workspace it uses before reading it.
+ * Returns as sa_solve_gmres. */
+sa_status sa_solve_gmres_noalloc(sa_hierarchy *h, const double *b, double *x, sa_location loc,
+                                 int32_t restart, int32_t *iterations, double *rel_residual);
+
 /* Solves count systems A_k x_k = b_k, each on its own hierarchy hs[k], in lockstep: each CG
  * iteration of every still-running system is advanced by grouped launches (one launch per
  * step for all systems: V-cycle levels, inner products, updates) on hs[0]'s stream.  Each

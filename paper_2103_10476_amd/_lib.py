@@ -36,7 +36,8 @@ PART_DTYPE = {"A_rp": "int32", "A_col": "int32", "A_val": "float64", "mask": "ui
 EXPORTED = ["sa_default_options", "sa_setup", "sa_solve", "sa_vcycle", "sa_hierarchy_info",
             "sa_export_size", "sa_export_level", "sa_destroy", "sa_status_string",
             "sa_last_error", "sa_profile_enable", "sa_profile_read", "sa_estimate_bytes",
-            "sa_solve_many", "sa_resetup", "sa_setup_coords", "sa_solve_gmres", "sa_setup_system",
+            "sa_solve_many", "sa_resetup", "sa_setup_coords", "sa_solve_gmres",
+            "sa_solve_gmres_noalloc", "sa_setup_system",
             "sa_server_create", "sa_server_submit", "sa_server_poll", "sa_server_wait",
             "sa_server_drain", "sa_server_get_stats", "sa_server_destroy"]
 
@@ -128,6 +129,9 @@ def lib():
         L.sa_solve_gmres.argtypes = [P, P, P, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double)]
         L.sa_solve_gmres.restype = C.c_int
+        L.sa_solve_gmres_noalloc.argtypes = [P, P, P, C.c_int32, C.c_int32,
+                                             C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+        L.sa_solve_gmres_noalloc.restype = C.c_int
         L.sa_solve_many.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p),
                                     C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_int32),
                                     C.POINTER(C.c_double), C.POINTER(C.c_int)]

@@ -922,30 +922,72 @@ static sa_status solve_impl(sa_hierarchy *h, const double *b, double *x, sa_loca
   return st;
 }
 
+// GMRES workspace for n unknowns and restart m, carved from one block in this order, each
+// part starting on a 256-byte boundary: V ((m+1) n), Z (m n), H ((m+1) m), cs, sn (m), g
+// (m+1), y (m), c (m+1), the inner-product partials ((m+1) dot_ws_size(n)), the scalars.
+static size_t gmres_part(int64_t count, size_t elem) {
+  return ((size_t)(count > 0 ? count : 1) * elem + 255) & ~(size_t)255;
+}
+size_t gmres_work_bytes(int32_t n, int32_t m) {
+  const int64_t N = n, M = m;
+  return gmres_part((M + 1) * N, 8) + gmres_part(M * N, 8) + gmres_part((M + 1) * M, 8) +
+         2 * gmres_part(M, 8) + gmres_part(M + 1, 8) + gmres_part(M, 8) +
+         gmres_part(M + 1, 8) + gmres_part((M + 1) * dot_ws_size(N), 8) +
+         gmres_part(1, sizeof(GmresScalars));
+}
+GmresWork gmres_work_carve(void *base, int32_t n, int32_t m) {
+  const int64_t N = n, M = m;
+  char *p = (char *)base;
+  auto take = [&](int64_t count, size_t elem) {
+    char *q = p;
+    p += gmres_part(count, elem);
+    return q;
+  };
+  GmresWork w;
+  w.V = (double *)take((M + 1) * N, 8);
+  w.Z = (double *)take(M * N, 8);
+  w.H = (double *)take((M + 1) * M, 8);
+  w.cs = (double *)take(M, 8);
+  w.sn = (double *)take(M, 8);
+  w.g = (double *)take(M + 1, 8);
+  w.y = (double *)take(M, 8);
+  w.c = (double *)take(M + 1, 8);
+  w.ws = (double *)take((M + 1) * dot_ws_size(N), 8);
+  w.S = (GmresScalars *)take(1, sizeof(GmresScalars));
+  return w;
+}
+
 // Restarted flexible GMRES(m), the V-cycle as right preconditioner (the paper's solver for
 // its nonsymmetric wind-turbine systems, Sec. 3.4).  x0 = 0; Arnoldi by classical
 // Gram-Schmidt applied twice; Givens rotations; stop when the least-squares residual
 // |g_{j+1}| <= rtol ||b||; at a restart the true residual b - A x is formed and tested; a zero
 // new basis norm ends the cycle with the exact Krylov solution.  The flexible form keeps the
 // preconditioned vectors Z and updates x += Z y.  Iterations count Arnoldi steps.
-static sa_status gmres_impl(sa_hierarchy *h, const double *b, double *x, sa_location loc,
-                            int32_t restart, int32_t *iterations, double *relres) {
+// The workspace comes from the caller (gmres_work_carve).  direct_reads: the scalars are read
+// back by a plain copy into host memory instead of through the pinned staging buffer, which
+// may be allocated on a thread's first use.
+sa_status gmres_run(sa_hierarchy *h, const double *b, double *x, sa_location loc,
+                    int32_t restart, const GmresWork &wk, bool direct_reads,
+                    int32_t *iterations, double *relres) {
   if (!h->valid) throw Error(SA_ERR_INVALID_ARG, "hierarchy left unusable by a failed re-setup");
   if (restart < 1 || restart > kMaxRestart) throw Error(SA_ERR_INVALID_ARG, "restart not in 1..1024");
   const hipStream_t s = h->stream;
   const sa_options &o = h->opt;
   const int32_t n = h->n;
   const int32_t m = restart;
-  Arena tmp;
-  tmp.stream = s;
-  double *V = tmp.alloc<double>((int64_t)(m + 1) * n);
-  double *Z = tmp.alloc<double>((int64_t)m * n);
-  double *H = tmp.alloc<double>((int64_t)(m + 1) * m);
-  double *cs = tmp.alloc<double>(m), *sn = tmp.alloc<double>(m);
-  double *g = tmp.alloc<double>(m + 1), *y = tmp.alloc<double>(m), *c = tmp.alloc<double>(m + 1);
-  double *ws = tmp.alloc<double>((int64_t)(m + 1) * dot_ws_size(n));
-  GmresScalars *S = tmp.alloc<GmresScalars>(1);
-  SA_HIP(hipMemsetAsync(S, 0, sizeof(GmresScalars), s));
+  double *V = wk.V, *Z = wk.Z, *H = wk.H, *cs = wk.cs, *sn = wk.sn, *g = wk.g, *y = wk.y,
+         *c = wk.c, *ws = wk.ws;
+  GmresScalars *S = wk.S;
+  auto read_scalars = [&](GmresScalars *hs) {
+    if (direct_reads) {
+      SA_HIP(hipMemcpyAsync(hs, S, sizeof(GmresScalars), hipMemcpyDeviceToHost, s));
+      SA_HIP(hipStreamSynchronize(s));
+    } else {
+      readback(hs, S, sizeof(GmresScalars), s);
+    }
+  };
+  static_assert(sizeof(GmresScalars) % 4 == 0, "scalars cleared as 32-bit words");
+  fill_i32((int32_t *)S, 0, (int64_t)(sizeof(GmresScalars) / 4), s);
   double *r = h->r, *xv = h->x, *bd = h->q;
   copy_in(bd, b, sizeof(double) * n, loc, s);
   SA_HIP(hipMemcpyAsync(r, bd, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
@@ -953,7 +995,7 @@ static sa_status gmres_impl(sa_hierarchy *h, const double *b, double *x, sa_loca
   dot_f64(r, r, n, &S->nrm2, h->dws, s);
   gmres_start(S, r, V, n, g, s);  // beta = ||b||, v_0 = b / beta
   GmresScalars hs;
-  readback(&hs, S, sizeof(GmresScalars), s);
+  read_scalars(&hs);
   const double bn = hs.beta;
   auto finish = [&]() {
     SA_HIP(hipMemcpyAsync(x, xv, sizeof(double) * n,
@@ -991,7 +1033,7 @@ static sa_status gmres_impl(sa_hierarchy *h, const double *b, double *x, sa_loca
       dot_f64(w, w, n, &S->hn2, h->dws, s);
       gmres_normalize(S, H, m, j, w, w, n, s);
       gmres_givens(H, m, j, cs, sn, g, S, s);
-      readback(&hs, S, sizeof(GmresScalars), s);
+      read_scalars(&hs);
       prof_collect(h);
       ++total;
       kdim = j + 1;
@@ -1005,7 +1047,7 @@ static sa_status gmres_impl(sa_hierarchy *h, const double *b, double *x, sa_loca
     if (kdim == 0) break;
     gmres_backsolve(H, m, kdim, g, y, S, s);
     multi_axpy_f64(Z, n, kdim, y, xv, n, true, s);
-    readback(&hs, S, sizeof(GmresScalars), s);
+    read_scalars(&hs);
     if (hs.err) return SA_ERR_BREAKDOWN;
     if (converged || total >= o.max_iter) break;
     // restart from the true residual
@@ -1013,7 +1055,7 @@ static sa_status gmres_impl(sa_hierarchy *h, const double *b, double *x, sa_loca
     spmv_resid<double>(A, bd, r, s);
     dot_f64(r, r, n, &S->nrm2, h->dws, s);
     gmres_start(S, r, V, n, g, s);
-    readback(&hs, S, sizeof(GmresScalars), s);
+    read_scalars(&hs);
     res = hs.beta;
     if (res <= target) {
       converged = true;
@@ -1025,6 +1067,17 @@ static sa_status gmres_impl(sa_hierarchy *h, const double *b, double *x, sa_loca
   if (iterations) *iterations = total;
   if (relres) *relres = res / bn;
   return converged ? SA_OK : SA_NOT_CONVERGED;
+}
+
+// GMRES with its workspace taken from the library's device-memory cache for the call.
+static sa_status gmres_impl(sa_hierarchy *h, const double *b, double *x, sa_location loc,
+                            int32_t restart, int32_t *iterations, double *relres) {
+  if (restart < 1 || restart > kMaxRestart) throw Error(SA_ERR_INVALID_ARG, "restart not in 1..1024");
+  Arena tmp;
+  tmp.stream = h->stream;
+  void *base = tmp.alloc<unsigned char>((int64_t)gmres_work_bytes(h->n, restart));
+  return gmres_run(h, b, x, loc, restart, gmres_work_carve(base, h->n, restart), false,
+                   iterations, relres);
 }
 
 template <class F>

@@ -80,4 +80,18 @@ struct sa_hierarchy {
 
 namespace sa {
 void hierarchy_release_nosync(sa_hierarchy *h);
+
+// Restarted flexible GMRES on a set-up hierarchy with a caller-provided workspace.
+struct GmresWork {
+  double *V, *Z, *H, *cs, *sn, *g, *y, *c, *ws;
+  GmresScalars *S;
+};
+// Bytes of the workspace for n unknowns and restart m (parts 256-byte aligned), and its
+// layout within a block of that size starting at a 256-byte boundary.
+size_t gmres_work_bytes(int32_t n, int32_t m);
+GmresWork gmres_work_carve(void *base, int32_t n, int32_t m);
+// The GMRES iteration (see hierarchy.hip).  Throws sa::Error on invalid input.
+sa_status gmres_run(sa_hierarchy *h, const double *b, double *x, sa_location loc,
+                    int32_t restart, const GmresWork &wk, bool direct_reads,
+                    int32_t *iterations, double *relres);
 }  // namespace sa

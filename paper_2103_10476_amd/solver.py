@@ -178,19 +178,21 @@ class Hierarchy:
         _lib.check(code, "sa_solve")
         return x, it.value, rr.value, _lib.STATUS_NAMES[code]
 
-    def solve_gmres(self, b, x=None, restart: int = 30):
+    def solve_gmres(self, b, x=None, restart: int = 30, noalloc: bool = False):
         """Restarted flexible GMRES with the V-cycle as right preconditioner
-        (sa_solve_gmres).  Returns (x, iterations, relres, status)."""
+        (sa_solve_gmres; with noalloc, sa_solve_gmres_noalloc, whose workspace is the
+        library's fixed scratch array).  Returns (x, iterations, relres, status)."""
         torch = _torch()
         db = _dev(b, torch.float64)
         if x is None:
             x = torch.empty(self.n, dtype=torch.float64, device="cuda")
         it = C.c_int32()
         rr = C.c_double()
-        code = _lib.lib().sa_solve_gmres(self._h, C.c_void_p(db.data_ptr()),
+        name = "sa_solve_gmres_noalloc" if noalloc else "sa_solve_gmres"
+        code = getattr(_lib.lib(), name)(self._h, C.c_void_p(db.data_ptr()),
                                          C.c_void_p(x.data_ptr()), _lib.SA_DEVICE, restart,
                                          C.byref(it), C.byref(rr))
-        _lib.check(code, "sa_solve_gmres")
+        _lib.check(code, name)
         return x, it.value, rr.value, _lib.STATUS_NAMES[code]
 
     def vcycle(self, f):
