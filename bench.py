@@ -225,10 +225,11 @@ def main():
     result["roofline"] = c4["roofline_fp64"]
     if result["roofline"] is not None:
         result["roofline"]["stream_probe_gbs"] = stream_probe()
-    result["roofline_fp32"] = c4["roofline_fp32"]
-    result["roofline_128_mall_assisted"] = roofline(
+    result["roofline_fp32"] = _slim(c4["roofline_fp32"])
+    legs["roofline_128_mall_assisted"] = roofline(
         prof_main, args.workload, note="128^3 fine operator, small enough to be served "
         "partly from the 256 MB Infinity Cache")
+    result["roofline_128_mall_assisted"] = _slim(legs["roofline_128_mall_assisted"])
     if not args.no_extras:
         legs["variants"] = variants_leg(solver, p, drp, dcol, dval, db)
         legs["numeric_resetup"] = resetup_leg(solver, p, drp, dcol, dval, db)
@@ -239,6 +240,10 @@ def main():
         legs["serving"] = serving_leg(solver, problems, args)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(p, b, x_main, c4)
+    for k in ("problem", "b"):  # inputs kept for the oracle comparison, not results
+        c4.pop(k, None)
+    for prec in ("fp64", "fp32"):
+        c4[prec].pop("x", None)
     result["fp32_vcycle_vs_fp64"] = summarise_precision(c4)
     result.update(summarise_legs(legs))
     if args.legs_out:
@@ -247,6 +252,14 @@ def main():
             json.dump({"headline": result, "legs": legs}, f, indent=1)
     log("[bench] legs " + json.dumps(legs))
     print(json.dumps(result, separators=(",", ":")), flush=True)
+
+
+def _slim(roof):
+    """A secondary roofline figure in a few fields (the full object goes to the legs)."""
+    if roof is None:
+        return None
+    return {k: roof[k] for k in ("input", "achieved", "frac", "avg_us",
+                                 "algorithmic_bytes_per_launch", "traffic")}
 
 
 def summarise_precision(c4):
@@ -452,8 +465,9 @@ def c4_leg(solver, problems, workload, reps=5):
         dt = "f64" if prec == "fp64" else "f32"
         out[f"roofline_{prec}"] = roofline(
             h.profile_read(), workload, dt,
-            note=f"160^3 fine operator in {dt}: {'424' if dt == 'f64' else '277'} MB of "
-                 "compulsory bytes per launch, more than the 256 MB Infinity Cache holds")
+            note=f"160^3 fine operator in {dt}: {'424' if dt == 'f64' else '277'} MB per "
+                 "launch for the matrix and x alone (more with the epilogue's vectors), more "
+                 "than the 256 MB Infinity Cache holds")
         h.close()
         xs[prec] = x.clone()
         xh = x.cpu().numpy()
