@@ -1,18 +1,22 @@
 // Sparse matrix-matrix product C = X*Y for the Galerkin operator (Sec. 1.1), in Gustavson
 // order: every output entry C_ij accumulates X_ik*Y_kj over the row's entries k in ascending
-// order, from 0.  No floating-point atomics: each output row is expanded into its products in
-// that order, stably sorted by output column, and every run of equal columns is summed by one
-// lane in order.  Output rows are sorted; cancellations stay stored.
+// order, from 0.  No floating-point atomics: each output row's products are ordered by
+// (column, position) and every run of equal columns is summed in order by one lane.  Output
+// rows are sorted; cancellations stay stored.
 //
 // Rows are binned by their product count T:
 //   T <= 64      16, 32 or 64 lanes per row (4, 2 or 1 rows per wavefront): one product per
 //                lane, rank sort in LDS;
-//   T > 64       one 256-thread block per row: chunks of 1024 products, bitonic sort of
-//                (column, position) keys in LDS; a single chunk is reduced and written
-//                directly, longer rows accumulate chunk by chunk into an LDS hash table
-//                (same order per entry), which is sorted by column at the end;
-//   hash > 1/2   rows whose distinct columns overflow the LDS table are redone with a table
-//                in global memory sized for the row.
+//   T <= 256     one wavefront per row, 64 products per step sorted in registers, each run
+//                added to its column's sum in an LDS hash table;
+//   T <= 1024    one 256-thread block per row: the row's products sorted by (column,
+//                position) in LDS, each run reduced in order and written at its rank;
+//   T > 1024     the row's dense column window in LDS when the output width fits (products
+//                taken 64 per step and sorted, or, for long Y rows, one X entry per step with
+//                its Y row across the lanes), else the wavefront kernel with a 2048-slot
+//                hash table;
+//   hash > 1/2   long rows with more than 1024 distinct columns are redone with a dense
+//                accumulator in global memory.
 // Results go to per-row slots at the row's product offset (room for T >= distinct entries)
 // and are compacted into CSR afterwards.
 #include <algorithm>
@@ -199,29 +203,6 @@ __device__ inline void bitonic_u64(uint64_t *a, int32_t L) {
   }
 }
 
-// Sorts (key, value) pairs by key as unsigned (empty slots hold -1 and go last).
-__device__ inline void bitonic_kv(int32_t *k, double *v, int32_t L) {
-  for (int32_t kk = 2; kk <= L; kk <<= 1) {
-    for (int32_t j = kk >> 1; j > 0; j >>= 1) {
-      for (int32_t idx = threadIdx.x; idx < L; idx += blockDim.x) {
-        const int32_t ixj = idx ^ j;
-        if (ixj > idx) {
-          const uint32_t x = (uint32_t)k[idx], y = (uint32_t)k[ixj];
-          const bool up = (idx & kk) == 0;
-          if ((x > y) == up) {
-            k[idx] = (int32_t)y;
-            k[ixj] = (int32_t)x;
-            const double t = v[idx];
-            v[idx] = v[ixj];
-            v[ixj] = t;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
 __device__ inline int32_t next_pow2(int32_t x) {
   int32_t p = 1;
   while (p < x) p <<= 1;
@@ -298,115 +279,6 @@ __global__ __launch_bounds__(BS) void k_esc_single(
     }
   }
   if (tid == BS - 1) ucnt[i] = s_scan[BS - 1];
-}
-
-// Long rows (T > kChunk): chunks of kChunk products; each distinct column of a chunk is
-// accumulated in position order by its first lane into an LDS hash table (one lane per key per
-// chunk, so per key the adds follow position order across chunks too); the table is sorted
-// by column at the end.  Rows whose distinct columns pass half the table are left to
-// k_esc_dense.
-constexpr int kHashL = 4096;
-__global__ __launch_bounds__(kBlock) void k_esc_hash(
-    const int32_t *rows, int32_t nrows, const int32_t *xrp, const int32_t *xcol,
-    const double *xval, const int32_t *xpref, const int32_t *yrp, const int32_t *ycol,
-    const double *yval, const int64_t *poff, int32_t *ocol, double *oval, int32_t *ucnt,
-    int32_t *ovf, int32_t *novf) {
-  // sk/sv hold one chunk while accumulating; the final sort of the (at most kHashL/2)
-  // distinct entries reuses the table's own storage: hk as 64-bit sort keys, hv for values
-  // (rows with more distinct entries go to k_esc_dense).  65 KB of LDS: two blocks per CU.
-  __shared__ uint64_t sk[kChunk];
-  __shared__ double sv[kChunk];
-  __shared__ uint64_t hk64[kHashL / 2];
-  int32_t *hk = reinterpret_cast<int32_t *>(hk64);
-  __shared__ double hv[kHashL];
-  __shared__ int32_t s_scan[kBlock];
-  __shared__ int32_t s_cnt, s_ovf;
-  const int tid = threadIdx.x;
-  if ((int32_t)blockIdx.x >= nrows) return;
-  const int32_t i = rows[blockIdx.x];
-  const int32_t xb = xrp[i], xe = xrp[i + 1];
-  const int64_t base = poff[i];
-  const int32_t T = (int32_t)(poff[i + 1] - base);
-  if (tid == 0) {
-    s_cnt = 0;
-    s_ovf = 0;
-  }
-  for (int32_t q = tid; q < kHashL; q += kBlock) hk[q] = -1;
-  __syncthreads();
-  const uint32_t msk = kHashL - 1;
-  for (int32_t c0 = 0; c0 < T; c0 += kChunk) {
-    const int32_t L = min(kChunk, T - c0);
-    load_sorted_chunk(c0, L, xb, xe, xpref, xcol, xval, yrp, ycol, yval, sk, sv);
-    for (int32_t r = tid; r < L; r += kBlock) {
-      const uint32_t key = key_of(sk[r]);
-      if (r > 0 && key_of(sk[r - 1]) == key) continue;
-      uint32_t h = hash_slot((int32_t)key, msk);
-      bool fresh = false;
-      for (int32_t probe = 0; probe < kHashL; ++probe) {
-        const int32_t old = atomicCAS(&hk[h], -1, (int32_t)key);
-        if (old == -1) {
-          fresh = true;
-          break;
-        }
-        if (old == (int32_t)key) break;
-        h = (h + 1) & msk;
-      }
-      double acc = fresh ? 0.0 : hv[h];
-      for (int32_t q = r; q < L && key_of(sk[q]) == key; ++q) acc += sv[(uint32_t)sk[q]];
-      hv[h] = acc;
-      if (fresh) {
-        const int32_t c = atomicAdd(&s_cnt, 1);
-        if (2 * (c + 1) > kHashL) s_ovf = 1;
-      }
-    }
-    __syncthreads();
-    if (s_ovf) break;  // block-uniform
-  }
-  if (s_ovf) {
-    if (tid == 0) ovf[atomicAdd(novf, 1)] = i;
-    return;
-  }
-  // compact the occupied slots (slot order) into the table's storage, then sort only those
-  // U entries: every thread first takes its slots into registers, so the compacted writes
-  // cannot overwrite a slot not yet read
-  const int32_t U = s_cnt;
-  constexpr int per = kHashL / kBlock;
-  int32_t kk[per];
-  double vv[per];
-  int32_t nloc = 0;
-#pragma unroll
-  for (int q = 0; q < per; ++q) {
-    kk[q] = hk[tid * per + q];
-    vv[q] = hv[tid * per + q];
-    nloc += kk[q] >= 0;
-  }
-  s_scan[tid] = nloc;
-  __syncthreads();
-  for (int off = 1; off < kBlock; off <<= 1) {
-    const int32_t add = (tid >= off) ? s_scan[tid - off] : 0;
-    __syncthreads();
-    s_scan[tid] += add;
-    __syncthreads();
-  }
-  int32_t w = s_scan[tid] - nloc;
-#pragma unroll
-  for (int q = 0; q < per; ++q) {
-    if (kk[q] >= 0) {
-      hk64[w] = ((uint64_t)(uint32_t)kk[q] << 32) | (uint32_t)w;
-      hv[w] = vv[q];
-      ++w;
-    }
-  }
-  __syncthreads();
-  const int32_t Up = next_pow2(U);  // U <= kHashL / 2 (overflowing rows left above)
-  for (int32_t q = U + tid; q < Up; q += kBlock) hk64[q] = ~0ull;
-  __syncthreads();
-  bitonic_u64(hk64, Up);
-  for (int32_t r = tid; r < U; r += kBlock) {
-    ocol[base + r] = (int32_t)key_of(hk64[r]);
-    oval[base + r] = hv[(uint32_t)hk64[r]];
-  }
-  if (tid == 0) ucnt[i] = U;
 }
 
 // Rows with more distinct columns than the LDS table holds: a dense accumulator of ncols
@@ -595,6 +467,211 @@ __global__ __launch_bounds__(64) void k_esc_lds(const int32_t *rows, int32_t nro
   if (lane == 0) ucnt[i] = w;
 }
 
+// ---- wavefront-per-row bins (T > 64) ------------------------------------------------------
+// One wavefront (a 64-thread block) per row.  The row's products are taken 64 at a time in
+// Gustavson order: its X entries are staged 64 at a time with a wave scan of their Y-row
+// lengths, and each lane finds its product's entry by binary search over the scan.  A step's
+// 64 products are sorted in registers by (column, lane) -- lane order is product order -- and
+// the first lane of each run of equal columns adds the run, in order, to that column's
+// accumulator in LDS.  Steps follow each other in product order, so every output entry
+// receives its products in ascending k, from 0.
+//   DENSE  the accumulator is the row's column window (values and a touched bitmap), read
+//          out in column order with ballots;
+//   HASH   an open-addressing table of H slots (every column claimed by an LDS compare-and-
+//          swap, its sum starting from 0); a row whose distinct columns pass H/2 is listed in
+//          ovf[] for k_esc_dense.  At the end the occupied slots are compacted and sorted by
+//          column (bitonic, in LDS).
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  const uint32_t lo = __shfl_xor((uint32_t)v, m, 64);
+  const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+// Ascending bitonic sort of one 64-bit key per lane across the wavefront (keys distinct).
+__device__ __forceinline__ uint64_t wave_sort_u64(uint64_t key, int lane) {
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint64_t other = shfl_xor_u64(key, j);
+      const bool up = (lane & k) == 0;
+      const bool lower = (lane & j) == 0;
+      key = (lower == up) ? (key < other ? key : other) : (key > other ? key : other);
+    }
+  }
+  return key;
+}
+
+template <bool DENSE, int H>
+__global__ __launch_bounds__(64) void k_esc_wave(
+    const int32_t *rows, int32_t nrows, const int32_t *xrp, const int32_t *xcol,
+    const double *xval, const int32_t *yrp, const int32_t *ycol, const double *yval,
+    int32_t width, const int2 *win, const int64_t *poff, int32_t *ocol, double *oval,
+    int32_t *ucnt, int32_t *ovf, int32_t *novf) {
+  extern __shared__ double lds_dyn[];
+  __shared__ int32_t s_incl[64], s_ys[64], s_col[64];
+  __shared__ double s_a[64], s_v[64];
+  __shared__ int32_t s_cnt;
+  const int lane = threadIdx.x;
+  if ((int32_t)blockIdx.x >= nrows) return;  // block-uniform
+  const int32_t i = rows[blockIdx.x];
+  const int64_t base = poff[i];
+  // DENSE: acc[width] then the bitmap; HASH: hv[H], hk[H], then the sort keys (H/2)
+  double *acc = lds_dyn;
+  uint32_t *bits = reinterpret_cast<uint32_t *>(acc + width);
+  double *hv = lds_dyn;
+  int32_t *hk = reinterpret_cast<int32_t *>(hv + H);
+  uint64_t *sk = reinterpret_cast<uint64_t *>(hk + H);
+  int32_t lo = 0, rw = width;
+  if (DENSE) {
+    if (win) {
+      const int2 w = win[blockIdx.x];
+      lo = w.x;
+      rw = w.y;
+    }
+    for (int32_t c = lane; c < rw; c += 64) acc[c] = 0.0;
+    for (int32_t c = lane; c < ((rw + 31) >> 5); c += 64) bits[c] = 0u;
+  } else {
+    for (int32_t c = lane; c < H; c += 64) {
+      hk[c] = -1;
+      hv[c] = 0.0;
+    }
+    if (lane == 0) s_cnt = 0;
+  }
+  __syncthreads();
+  bool over = false;  // block-uniform
+  const int32_t xb = xrp[i], xe = xrp[i + 1];
+  for (int32_t e0 = xb; e0 < xe && !over; e0 += 64) {
+    const int32_t cnt = min(64, xe - e0);
+    int32_t len = 0, ys = 0;
+    double a = 0.0;
+    if (lane < cnt) {
+      const int32_t k = xcol[e0 + lane];
+      a = xval[e0 + lane];
+      ys = yrp[k];
+      len = yrp[k + 1] - ys;
+    }
+    int32_t incl = len;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t v = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += v;
+    }
+    const int32_t tot = __shfl(incl, 63, 64);
+    __syncthreads();  // the previous chunk's searches are done
+    s_incl[lane] = incl;
+    s_ys[lane] = ys;
+    s_a[lane] = a;
+    __syncthreads();
+    for (int32_t p0 = 0; p0 < tot; p0 += 64) {
+      const int32_t p = p0 + lane;
+      uint64_t key = ~0ull;
+      double v = 0.0;
+      if (p < tot) {
+        int32_t l0 = 0, h0 = cnt - 1;  // first staged entry g with s_incl[g] > p
+        while (l0 < h0) {
+          const int32_t mid = (l0 + h0) >> 1;
+          if (s_incl[mid] > p) h0 = mid;
+          else l0 = mid + 1;
+        }
+        const int32_t q = s_ys[l0] + p - (l0 > 0 ? s_incl[l0 - 1] : 0);
+        const int32_t j = ycol[q];
+        v = s_a[l0] * yval[q];
+        key = ((uint64_t)(uint32_t)j << 6) | (uint32_t)lane;
+      }
+      key = wave_sort_u64(key, lane);
+      const double sv = __shfl(v, (int)(key & 63u), 64);
+      const int32_t col = key == ~0ull ? -1 : (int32_t)(key >> 6);
+      s_col[lane] = col;
+      s_v[lane] = sv;
+      __syncthreads();
+      if (col >= 0 && (lane == 0 || s_col[lane - 1] != col)) {  // first of its run
+        if (DENSE) {
+          const int32_t c = col - lo;  // inside the window by construction
+          double t = acc[c];
+          for (int r = lane; r < 64 && s_col[r] == col; ++r) t += s_v[r];
+          acc[c] = t;
+          atomicOr(&bits[c >> 5], 1u << (c & 31));
+        } else {
+          uint32_t h = hash_slot(col, H - 1);
+          for (int probe = 0; probe < H; ++probe) {
+            const int32_t old = atomicCAS(&hk[h], -1, col);
+            if (old == -1) {
+              atomicAdd(&s_cnt, 1);
+              break;
+            }
+            if (old == col) break;
+            h = (h + 1) & (H - 1);
+          }
+          double t = hv[h];
+          for (int r = lane; r < 64 && s_col[r] == col; ++r) t += s_v[r];
+          hv[h] = t;
+        }
+      }
+      __syncthreads();
+      if (!DENSE && 2 * s_cnt > H) {  // block-uniform: too many columns for the table
+        over = true;
+        break;
+      }
+    }
+  }
+  if (over) {
+    if (lane == 0) ovf[atomicAdd(novf, 1)] = i;
+    return;
+  }
+  if (DENSE) {
+    int32_t w = 0;
+    for (int32_t c0 = 0; c0 < rw; c0 += 64) {
+      const int32_t c = c0 + lane;
+      const bool f = c < rw && ((bits[c >> 5] >> (c & 31)) & 1u);
+      const unsigned long long bm = __ballot(f);
+      if (f) {
+        const int32_t pos = w + __popcll(bm & ((1ull << lane) - 1ull));
+        ocol[base + pos] = lo + c;
+        oval[base + pos] = acc[c];
+      }
+      w += __popcll(bm);
+    }
+    if (lane == 0) ucnt[i] = w;
+  } else {
+    // compact the occupied slots as (column << 32 | slot) keys, sort them, write in order
+    int32_t u = 0;
+    for (int32_t c0 = 0; c0 < H; c0 += 64) {
+      const int32_t c = c0 + lane;
+      const int32_t kc = hk[c];
+      const bool f = kc >= 0;
+      const unsigned long long bm = __ballot(f);
+      if (f)
+        sk[u + __popcll(bm & ((1ull << lane) - 1ull))] =
+            ((uint64_t)(uint32_t)kc << 32) | (uint32_t)c;
+      u += __popcll(bm);
+    }
+    int32_t up = 1;
+    while (up < u) up <<= 1;
+    for (int32_t q = u + lane; q < up; q += 64) sk[q] = ~0ull;
+    __syncthreads();
+    for (int32_t kk = 2; kk <= up; kk <<= 1) {
+      for (int32_t j = kk >> 1; j > 0; j >>= 1) {
+        for (int32_t idx = lane; idx < up; idx += 64) {
+          const int32_t ixj = idx ^ j;
+          if (ixj > idx) {
+            const uint64_t x = sk[idx], y = sk[ixj];
+            if ((x > y) == ((idx & kk) == 0)) {
+              sk[idx] = y;
+              sk[ixj] = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int32_t r = lane; r < u; r += 64) {
+      ocol[base + r] = (int32_t)(sk[r] >> 32);
+      oval[base + r] = hv[(uint32_t)sk[r]];
+    }
+    if (lane == 0) ucnt[i] = u;
+  }
+}
+
 // Largest output width the LDS bin takes on this device: the opt-in LDS per workgroup less
 // the kernel's static LDS, at 8 bytes plus one bit per column (queried once per device).
 static int32_t lds_cols_max() {
@@ -611,13 +688,16 @@ static int32_t lds_cols_max() {
             hipSuccess ||
         optin <= 0)
       optin = 64 << 10;
-    const int64_t avail = (int64_t)optin - 2048;  // the kernel's static LDS is 1 KB
+    const int64_t avail = (int64_t)optin - 4096;  // the kernel's static LDS is under 2 KB
     int32_t cols = (int32_t)((avail * 8) / 65);     // 8 bytes + 1 bit per column
     cols &= ~31;
+    const int bytes = (int)(((int64_t)cols * 65 + 7) / 8);
     if (cols > (64 << 10) / 9 &&
-        hipFuncSetAttribute((const void *)k_esc_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(((int64_t)cols * 65 + 7) / 8)) != hipSuccess)
-      cols = (((64 << 10) - 2048) * 8 / 65) & ~31;
+        (hipFuncSetAttribute((const void *)k_esc_wave<true, 1>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess ||
+         hipFuncSetAttribute((const void *)k_esc_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             bytes) != hipSuccess))
+      cols = (((64 << 10) - 4096) * 8 / 65) & ~31;
     cache[dev] = cols;
     done[dev] = true;
   }
@@ -751,10 +831,15 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
     k_esc_group<64><<<(unsigned)hc[2], kWave, 0, s>>>(lg[2], hc[2], X.rp, X.col, X.val, Y.rp,
                                                       Y.col, Y.val, poff, ocol, oval, ucnt);
   SA_LAUNCH_CHECK();
-  const int32_t n256 = hc[3], n1024 = hc[4], nlong = hc[5];  // block-level bins
+  const int32_t n256 = hc[3], n1024 = hc[4], nlong = hc[5];  // wavefront-per-row bins
+  int32_t *ovf = nullptr;
+  if (n256 > 0 || n1024 > 0 || nlong > 0) ovf = tmp.alloc<int32_t>(n256 + n1024 + nlong);
+  // T <= 256: the wavefront kernel with a 512-slot hash table (at least 2T slots: it never
+  // overflows); T <= 1024: one block per row, the whole row sorted in LDS
   if (n256 > 0) {
-    k_esc_single<64><<<(unsigned)n256, 64, 0, s>>>(l1, n256, X.rp, X.col, X.val, xpref, Y.rp,
-                                                    Y.col, Y.val, poff, ocol, oval, ucnt);
+    k_esc_wave<false, 512><<<(unsigned)n256, 64, 16 * 512, s>>>(
+        l1, n256, X.rp, X.col, X.val, Y.rp, Y.col, Y.val, 0, nullptr, poff, ocol, oval, ucnt,
+        ovf, counters + kBins);
     SA_LAUNCH_CHECK();
   }
   if (n1024 > 0) {
@@ -763,32 +848,38 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
                                                       ucnt);
     SA_LAUNCH_CHECK();
   }
-  // long rows: the LDS accumulator when Y's width fits the LDS (wider outputs take the hash:
-  // there, windows of up to ~19k columns leave 1-2 wavefronts per CU, slower than the hash),
-  // sized to the widest row window (far below Y's width on the systems levels)
+  // long rows: the dense window accumulator when Y's width fits the LDS (sized to the widest
+  // row window; up to 2048 columns the whole width), else a 2048-slot hash table whose
+  // overflowing rows (more than 1024 distinct columns) go to k_esc_dense
   const bool lds_bin = Y.ncols <= lds_cols_max();
-  int32_t wmax = Y.ncols;  // up to 2048 columns the whole width keeps 8 wavefronts per CU
+  int32_t wmax = Y.ncols;
   int2 *win = nullptr;
   if (nlong > 0 && lds_bin && Y.ncols > 2048) {
     win = tmp.alloc<int2>(nlong);
     fill_i32(counters + kBins + 1, 0, 1, s);
     k_row_window<<<grid_for((int64_t)nlong * 64), kBlock, 0, s>>>(l3, nlong, X.rp, X.col, Y.rp,
                                                                   Y.col, win,
-                                                    counters + kBins + 1);
+                                                                  counters + kBins + 1);
     SA_LAUNCH_CHECK();
     wmax = read1(counters + kBins + 1, s);
   }
   if (nlong > 0 && lds_bin) {
     const int32_t wl = (wmax + 31) & ~31;
     const size_t lds = (size_t)wl * sizeof(double) + (size_t)(wl / 32) * 4;
-    k_esc_lds<<<(unsigned)nlong, 64, lds, s>>>(l3, nlong, X.rp, X.col, X.val, Y.rp, Y.col, Y.val,
-                                              wl, win, poff, ocol, oval, ucnt);
+    // Y rows of 16 entries or more on average (R (AP)): one X entry per step, its Y row
+    // across the lanes; shorter Y rows (A P): 64 products per step, sorted
+    if (Y.nnz >= 16 * (int64_t)Y.n)
+      k_esc_lds<<<(unsigned)nlong, 64, lds, s>>>(l3, nlong, X.rp, X.col, X.val, Y.rp, Y.col,
+                                                Y.val, wl, win, poff, ocol, oval, ucnt);
+    else
+      k_esc_wave<true, 1><<<(unsigned)nlong, 64, lds, s>>>(l3, nlong, X.rp, X.col, X.val, Y.rp,
+                                                           Y.col, Y.val, wl, win, poff, ocol,
+                                                           oval, ucnt, ovf, counters + kBins);
     SA_LAUNCH_CHECK();
   } else if (nlong > 0) {
-    int32_t *ovf = tmp.alloc<int32_t>(nlong);
-    k_esc_hash<<<(unsigned)nlong, kBlock, 0, s>>>(l3, nlong, X.rp, X.col, X.val, xpref, Y.rp,
-                                                  Y.col, Y.val, poff, ocol, oval, ucnt, ovf,
-                                                  counters + kBins);
+    k_esc_wave<false, 2048><<<(unsigned)nlong, 64, 16 * 2048, s>>>(
+        l3, nlong, X.rp, X.col, X.val, Y.rp, Y.col, Y.val, 0, nullptr, poff, ocol, oval, ucnt,
+        ovf, counters + kBins);
     SA_LAUNCH_CHECK();
     const int32_t nov = read1(counters + kBins, s);
     if (nov > 0) {
