@@ -163,8 +163,9 @@ static void numeric_lump(sa_hierarchy *h, int l, bool fresh) {
     L.omega_d = L.lam_d + 1;
   }
   Csr abar;
-  lump(n, L.As.rp, L.As.col, L.As.val, L.mask, (o.variants & SA_OFFLMP) != 0, o.tau, one_norm,
-       safeguard_mult(o.sigma), L.wave_rows, fresh ? ar : tmp, abar, L.invD, h->err, s);
+  lump(n, L.As.nnz, L.As.rp, L.As.col, L.As.val, L.mask, (o.variants & SA_OFFLMP) != 0, o.tau,
+       one_norm, safeguard_mult(o.sigma), L.wave_rows, fresh ? ar : tmp, abar, L.invD, h->err,
+       s);
   if (fresh) {
     L.Abar = abar;
     spmv_plan(L.Abar, ar, s);

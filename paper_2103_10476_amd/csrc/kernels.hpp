@@ -210,9 +210,9 @@ int32_t aggregate(int32_t n, int64_t nnzG, const int32_t *grp, const int32_t *gc
 // Sprsfy: marks dropped strong entries (mask 1 -> 2).
 void sprsfy(int32_t n, const int32_t *rp, const int32_t *col, uint8_t *mask,
             const int32_t *agg, const int32_t *root_vertex, int32_t nc, hipStream_t s);
-// Filtered matrix (plain or OffLmp) and the smoothing diagonal inverse; returns nnz(Abar).
-// err bit 8: zero filtered diagonal with the plain diagonal.
-int64_t lump(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+// Filtered matrix (plain or OffLmp) and the smoothing diagonal inverse of the n-row CSR with
+// nnz_a entries; returns nnz(Abar).  err bit 8: zero filtered diagonal with the plain diagonal.
+int64_t lump(int32_t n, int64_t nnz_a, const int32_t *rp, const int32_t *col, const double *val,
              const uint8_t *mask, bool offlmp, double tau, bool one_norm, double mult,
              bool wave, Arena &ar, Csr &abar, double *invD, int32_t *err, hipStream_t s);
 // Power method; writes the estimate to *lam (device).  ws: 3n doubles + dot workspace.

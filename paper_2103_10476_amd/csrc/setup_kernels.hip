@@ -113,27 +113,50 @@ void find_diag(int32_t n, const int32_t *rp, const int32_t *col, const double *v
 }
 
 // ---- strength (Sec. 1.1 criterion, evaluated squared) ----------------------------------
-__global__ void k_strength(int32_t n, const int32_t *__restrict__ rp,
-                           const int32_t *__restrict__ col, const double *__restrict__ val,
-                           const double *__restrict__ dval, double th2,
-                           uint8_t *__restrict__ mask, int32_t *__restrict__ scount) {
-  SA_ROW_KERNEL_BEGIN(n)
-  const double di = dval[i];
-  int32_t cnt = 0;
-#pragma unroll 8
-  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-    const int32_t j = col[k];
-    if (j == i) {
-      mask[k] = 3;
-      continue;
-    }
-    const double a = val[k];
-    const double p = di * dval[j];
-    const bool strong = (p > 0.0) && (a * a >= th2 * p);
-    mask[k] = strong ? 1 : 0;
-    cnt += strong;
+// Entry-parallel: block b owns rows [256 b, 256 b + 256), whose entries are one contiguous run;
+// consecutive threads take consecutive entries (coalesced loads and mask stores), each finding
+// its row by binary search over the block's row pointers in LDS; strong entries are counted per
+// row with LDS integer atomics.
+__global__ __launch_bounds__(kBlock) void k_strength(int32_t n, const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ col,
+                                                     const double *__restrict__ val,
+                                                     const double *__restrict__ dval, double th2,
+                                                     uint8_t *__restrict__ mask,
+                                                     int32_t *__restrict__ scount) {
+  __shared__ int32_t s_rp[kBlock + 1];
+  __shared__ double s_d[kBlock];
+  __shared__ int32_t s_cnt[kBlock];
+  const int t = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * kBlock;
+  const int32_t nr = (int32_t)min<int64_t>(kBlock, (int64_t)n - r0);
+  if (t < nr) {
+    s_rp[t] = rp[r0 + t];
+    s_d[t] = dval[r0 + t];
   }
-  scount[i] = cnt;
+  if (t == 0) s_rp[nr] = rp[r0 + nr];  // nr can be kBlock: no thread t == nr
+  s_cnt[t] = 0;
+  __syncthreads();
+  const int32_t e0 = s_rp[0], e1 = s_rp[nr];
+  for (int32_t e = e0 + t; e < e1; e += kBlock) {
+    int32_t lo = 0, hi = nr - 1;  // the entry's row: the last r with s_rp[r] <= e
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (s_rp[mid] <= e) lo = mid;
+      else hi = mid - 1;
+    }
+    const int32_t j = col[e];
+    uint8_t m = 3;
+    if (j != (int32_t)r0 + lo) {
+      const double a = val[e];
+      const double p = s_d[lo] * dval[j];
+      const bool strong = (p > 0.0) && (a * a >= th2 * p);
+      m = strong ? 1 : 0;
+      if (strong) atomicAdd(&s_cnt[lo], 1);
+    }
+    mask[e] = m;
+  }
+  __syncthreads();
+  if (t < nr) scount[r0 + t] = s_cnt[t];
 }
 __global__ __launch_bounds__(kW) void k_strength_w(int32_t n, const int32_t *rp,
                                                    const int32_t *col, const double *val,
@@ -1101,55 +1124,73 @@ void sprsfy(int32_t n, const int32_t *rp, const int32_t *col, uint8_t *mask, con
 }
 
 // ---- filtered matrix (Sec. 1.1 plain lumping; Sec. 2.3 Algorithm 2) and its diagonal -----
-__global__ void k_lump_count(int32_t n, const int32_t *__restrict__ rp,
-                             const int32_t *__restrict__ col, const uint8_t *__restrict__ mask,
-                             int32_t *__restrict__ cnt) {
-  SA_ROW_KERNEL_BEGIN(n)
-  int32_t c = 0;
-#pragma unroll 8
-  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) c += (col[k] == i || mask[k] == 1);
-  cnt[i] = c;
+// Kept entries per row (the diagonal and the strong entries), entry-parallel like k_strength.
+__global__ __launch_bounds__(kBlock) void k_lump_count(int32_t n, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ col,
+                                                       const uint8_t *__restrict__ mask,
+                                                       int32_t *__restrict__ cnt) {
+  __shared__ int32_t s_rp[kBlock + 1];
+  __shared__ int32_t s_cnt[kBlock];
+  const int t = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * kBlock;
+  const int32_t nr = (int32_t)min<int64_t>(kBlock, (int64_t)n - r0);
+  if (t < nr) s_rp[t] = rp[r0 + t];
+  if (t == 0) s_rp[nr] = rp[r0 + nr];  // nr can be kBlock: no thread t == nr
+  s_cnt[t] = 0;
+  __syncthreads();
+  const int32_t e0 = s_rp[0], e1 = s_rp[nr];
+  for (int32_t e = e0 + t; e < e1; e += kBlock) {
+    const uint8_t m = mask[e];
+    if (m == 1 || m == 3) {  // strong, or the diagonal
+      int32_t lo = 0, hi = nr - 1;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (s_rp[mid] <= e) lo = mid;
+        else hi = mid - 1;
+      }
+      atomicAdd(&s_cnt[lo], 1);
+    }
+  }
+  __syncthreads();
+  if (t < nr) cnt[r0 + t] = s_cnt[t];
 }
 
-// (restrict: the filtered matrix never overlaps its inputs, so the row's loads can be issued
-// ahead of the stores)
-__global__ void k_lump_fill(int32_t n, const int32_t *__restrict__ rp,
-                            const int32_t *__restrict__ col, const double *__restrict__ val,
-                            const uint8_t *__restrict__ mask, const int32_t *__restrict__ arp,
-                            int32_t *__restrict__ acol, double *__restrict__ aval, bool offlmp,
-                            double tau, bool one_norm, double mult, double *__restrict__ invD,
-                            int32_t *__restrict__ err) {
-  SA_ROW_KERNEL_BEGIN(n)
-  const int32_t b = rp[i], e = rp[i + 1];
-  const int32_t o = arp[i];
+// One row of the filtered matrix and its smoothing diagonal.  A's row i is read at
+// col/val/mask[k - ko] for k in [b, e); the filtered row is written at acol/aval[w - wo] for
+// w from o (its row pointer) on -- global arrays (offsets 0) or a block's LDS copies.
+__device__ __forceinline__ void lump_row(int32_t i, int32_t b, int32_t e, const int32_t *col,
+                                         const double *val, const uint8_t *mask, int32_t ko,
+                                         int32_t o, int32_t *acol, double *aval, int32_t wo,
+                                         bool offlmp, double tau, bool one_norm, double mult,
+                                         double *__restrict__ invD, int32_t *__restrict__ err) {
   int32_t w = o, ds = o;
   double aii = 0.0, r = 0.0;
 #pragma unroll 8
   for (int32_t k = b; k < e; ++k) {
-    const int32_t j = col[k];
+    const int32_t j = col[k - ko];
     if (j == i) {
-      aii = val[k];
+      aii = val[k - ko];
       ds = w;
-      acol[w] = j;
-      aval[w] = val[k];
+      acol[w - wo] = j;
+      aval[w - wo] = val[k - ko];
       ++w;
-    } else if (mask[k] == 1) {
-      acol[w] = j;
-      aval[w] = val[k];
+    } else if (mask[k - ko] == 1) {
+      acol[w - wo] = j;
+      aval[w - wo] = val[k - ko];
       ++w;
     } else {
-      r += val[k];
+      r += val[k - ko];
     }
   }
   const int32_t wend = w;
   if (!offlmp || r >= 0.0 || !(aii > 0.0)) {
-    aval[ds] = aii + r;
+    aval[ds - wo] = aii + r;
   } else {
     double kp = 0.0, km = 0.0;
     bool has_kp = false, has_km = false;
     for (int32_t t = o; t < wend; ++t) {
       if (t == ds) continue;
-      const double v = aval[t];
+      const double v = aval[t - wo];
       if (v > 0.0) {
         kp += v;
         has_kp = true;
@@ -1161,18 +1202,18 @@ __global__ void k_lump_fill(int32_t n, const int32_t *__restrict__ rp,
     if (-r <= kp) {
       const double delta = r / kp;
       for (int32_t t = o; t < wend; ++t)
-        if (t != ds && aval[t] > 0.0) aval[t] = aval[t] * (1.0 + delta);
+        if (t != ds && aval[t - wo] > 0.0) aval[t - wo] = aval[t - wo] * (1.0 + delta);
     } else {
       double offsum = 0.0;
       for (int32_t k = b; k < e; ++k)
-        if (col[k] != i) offsum += fabs(val[k]);
+        if (col[k - ko] != i) offsum += fabs(val[k - ko]);
       const double T = tau * (offsum / aii);
       const double rhat = r + kp;
       if (!has_km) {
         if (has_kp && fabs(r + kp) / aii <= T) {
           const double delta = r / kp;
           for (int32_t t = o; t < wend; ++t)
-            if (t != ds && aval[t] > 0.0) aval[t] = aval[t] * (1.0 + delta);
+            if (t != ds && aval[t - wo] > 0.0) aval[t - wo] = aval[t - wo] * (1.0 + delta);
         }
       } else {
         const double a = aii;
@@ -1197,30 +1238,73 @@ __global__ void k_lump_fill(int32_t n, const int32_t *__restrict__ rp,
         const double delta = (rhat + rs) / km;
         for (int32_t t = o; t < wend; ++t) {
           if (t == ds) continue;
-          const double v = aval[t];
-          if (v > 0.0) aval[t] = 0.0;
-          else if (v < 0.0) aval[t] = v * (1.0 + delta);
+          const double v = aval[t - wo];
+          if (v > 0.0) aval[t - wo] = 0.0;
+          else if (v < 0.0) aval[t - wo] = v * (1.0 + delta);
         }
-        aval[ds] = a - rs;
+        aval[ds - wo] = a - rs;
       }
     }
   }
   double D;
   if (one_norm) {
     D = 0.0;
-    for (int32_t t = o; t < wend; ++t) D += fabs(aval[t]);
+    for (int32_t t = o; t < wend; ++t) D += fabs(aval[t - wo]);
     if (D == 0.0) {
       D = 1.0;
     } else {
       double sum = 0.0;
-      for (int32_t t = o; t < wend; ++t) sum += aval[t];
+      for (int32_t t = o; t < wend; ++t) sum += aval[t - wo];
       if (D < mult * sum) D = mult * sum;
     }
   } else {
-    D = aval[ds];
+    D = aval[ds - wo];
     if (D == 0.0) atomicOr(err, 8);
   }
   invD[i] = 1.0 / D;
+}
+
+// Block b owns rows [R b, R b + R) (R <= 256 chosen so that the rows' entries usually fit
+// kLumpCap).  When they fit, the entries are staged in LDS by all 256 threads with coalesced
+// loads, threads t < R build their rows there, and the filtered rows (one contiguous run of
+// Abar) are written back with coalesced stores; otherwise thread t works on row R b + t in
+// global memory directly.
+constexpr int32_t kLumpCap = 2048;
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_lump_fill(
+    int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+    const double *__restrict__ val, const uint8_t *__restrict__ mask,
+    const int32_t *__restrict__ arp, int32_t *__restrict__ acol, double *__restrict__ aval,
+    bool offlmp, double tau, bool one_norm, double mult, double *__restrict__ invD,
+    int32_t *__restrict__ err) {
+  __shared__ int32_t s_col[kLumpCap], s_acol[kLumpCap];
+  __shared__ double s_val[kLumpCap], s_aval[kLumpCap];
+  __shared__ uint8_t s_mask[kLumpCap];
+  const int t = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * R;
+  const int32_t nr = (int32_t)min<int64_t>(R, (int64_t)n - r0);
+  const int32_t e0 = rp[r0], e1 = rp[r0 + nr];
+  const int32_t a0 = arp[r0], a1 = arp[r0 + nr];
+  const int32_t i = (int32_t)r0 + t;
+  if (e1 - e0 <= kLumpCap) {  // block-uniform; the filtered rows are no longer than A's
+    for (int32_t k = e0 + t; k < e1; k += kBlock) {
+      s_col[k - e0] = col[k];
+      s_val[k - e0] = val[k];
+      s_mask[k - e0] = mask[k];
+    }
+    __syncthreads();
+    if (t < nr)
+      lump_row(i, rp[i], rp[i + 1], s_col, s_val, s_mask, e0, arp[i], s_acol, s_aval, a0,
+               offlmp, tau, one_norm, mult, invD, err);
+    __syncthreads();
+    for (int32_t w = a0 + t; w < a1; w += kBlock) {
+      acol[w] = s_acol[w - a0];
+      aval[w] = s_aval[w - a0];
+    }
+  } else if (t < nr) {
+    lump_row(i, rp[i], rp[i + 1], col, val, mask, 0, arp[i], acol, aval, 0, offlmp, tau,
+             one_norm, mult, invD, err);
+  }
 }
 
 __global__ __launch_bounds__(kW) void k_lump_count_w(int32_t n, const int32_t *rp,
@@ -1361,7 +1445,7 @@ __global__ __launch_bounds__(kW) void k_lump_fill_w(int32_t n, const int32_t *rp
   if (lane == 0) invD[i] = 1.0 / D;
 }
 
-int64_t lump(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
+int64_t lump(int32_t n, int64_t nnz_a, const int32_t *rp, const int32_t *col, const double *val,
              const uint8_t *mask, bool offlmp, double tau, bool one_norm, double mult,
              bool wave, Arena &ar, Csr &abar, double *invD, int32_t *err, hipStream_t s) {
   int32_t *cnt = (int32_t *)dev_alloc(sizeof(int32_t) * (n + 1), s);
@@ -1378,9 +1462,18 @@ int64_t lump(int32_t n, const int32_t *rp, const int32_t *col, const double *val
   if (wave)
     k_lump_fill_w<<<(unsigned)n, kW, 0, s>>>(n, rp, col, val, mask, abar.rp, abar.col, abar.val,
                                              offlmp, tau, one_norm, mult, invD, err);
+  else if (nnz_a <= 7 * (int64_t)n)
+    k_lump_fill<256><<<(unsigned)ceil_div(n, 256), kBlock, 0, s>>>(
+        n, rp, col, val, mask, abar.rp, abar.col, abar.val, offlmp, tau, one_norm, mult, invD,
+        err);
+  else if (nnz_a <= 15 * (int64_t)n)
+    k_lump_fill<128><<<(unsigned)ceil_div(n, 128), kBlock, 0, s>>>(
+        n, rp, col, val, mask, abar.rp, abar.col, abar.val, offlmp, tau, one_norm, mult, invD,
+        err);
   else
-    k_lump_fill<<<grid_for(n), kBlock, 0, s>>>(n, rp, col, val, mask, abar.rp, abar.col,
-                                               abar.val, offlmp, tau, one_norm, mult, invD, err);
+    k_lump_fill<64><<<(unsigned)ceil_div(n, 64), kBlock, 0, s>>>(
+        n, rp, col, val, mask, abar.rp, abar.col, abar.val, offlmp, tau, one_norm, mult, invD,
+        err);
   SA_LAUNCH_CHECK();
   return abar.nnz;
 }
