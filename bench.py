@@ -27,8 +27,11 @@ PEAK_HBM_GBS = 8000.0
 # (profiles/k_spmv_sell_<workload>_<f64|f32>_hbm_traffic.md); a traffic figure is reported only
 # while the kernel's sources still hash to the value recorded with it
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_spmv_sell_{workload}_{dtype}_hbm_traffic.md")
+# the SpMV kernel body and epilogues live in solve_device.hpp, its launch and row partition in
+# solve_kernels.hip, the block-to-XCD mapping in common.hpp; build.py holds the compile flags
 KERNEL_SOURCES = ["paper_2103_10476_amd/csrc/solve_device.hpp",
                   "paper_2103_10476_amd/csrc/solve_kernels.hip",
+                  "paper_2103_10476_amd/csrc/common.hpp",
                   "paper_2103_10476_amd/build.py"]
 
 
@@ -404,8 +407,9 @@ def roofline(tot, workload=WORKLOAD, dtype="f64", note=None):
     bytes_per = tot["bytes"] / tot["launches"]
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9
     out = {"bound": "hbm",
-           "kernel": f"k_spmv_sell<{'double' if dtype == 'f64' else 'float'}> (fine-level "
-                     "operator, sliced ELL, all fused epilogues)",
+           "kernel": ("k_spmv_sell<double>" if dtype == "f64" else
+                      "k_spmv_sell<float> (V-cycle) and <double> (CG)") +
+                     " on the fine-level operator: sliced ELL, all fused epilogues",
            "input": workload,
            "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(workload, dtype),

@@ -33,6 +33,18 @@ struct Error : std::runtime_error {
 constexpr int kBlock = 256;
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Workgroups are handed to the 8 XCDs round-robin (workgroup b runs on XCD b mod 8), and
+// each XCD has its own L2.  Renumbering so that XCD x takes one contiguous run of row blocks
+// keeps the x entries a block gathers from neighbouring rows (stencil planes) in that XCD's
+// L2 instead of fetching them once per XCD.  A bijection on [0, nb).
+__device__ __forceinline__ int32_t xcd_block(uint32_t b, uint32_t nb) {
+  constexpr uint32_t kXcd = 8;
+  const uint32_t q = nb / kXcd, r = nb % kXcd;
+  const uint32_t x = b % kXcd, k = b / kXcd;
+  return (int32_t)(x * q + (x < r ? x : r) + k);
+}
+
 inline unsigned grid_for(int64_t n, int block = kBlock) {
   int64_t g = ceil_div(n, block);
   return (unsigned)(g < 1 ? 1 : g);

@@ -17,17 +17,6 @@ struct Chunk {
 constexpr int32_t kPlanWindow = 2048;  // cost units per SpMV block
 constexpr int32_t kPlanRowCost = 8;     // cost of a row besides its entries
 
-// Workgroups are handed to the 8 XCDs round-robin (workgroup b runs on XCD b mod 8), and
-// each XCD has its own L2.  Renumbering so that XCD x takes one contiguous run of row blocks
-// keeps the x entries a block gathers from neighbouring rows (stencil planes) in that XCD's
-// L2 instead of fetching them once per XCD.  A bijection on [0, nb).
-__device__ __forceinline__ int32_t xcd_block(uint32_t b, uint32_t nb) {
-  constexpr uint32_t kXcd = 8;
-  const uint32_t q = nb / kXcd, r = nb % kXcd;
-  const uint32_t x = b % kXcd, k = b / kXcd;
-  return (int32_t)(x * q + (x < r ? x : r) + k);
-}
-
 // Row sums.  A row of at most kLongRow = 64 entries is summed in ascending column order from
 // 0.  A longer row is summed the same way by its own thread when Split is false (the plain
 // definition, used where the result must equal the sequential sum bit for bit), and

@@ -92,7 +92,9 @@ __global__ __launch_bounds__(kWave) void k_esc_group(
   __shared__ double s_a[kWave];
   const int lane = threadIdx.x;
   const int gl = lane % G, gb = lane - gl;  // lane in the group, the group's first lane
-  const int64_t r64 = (int64_t)blockIdx.x * (kWave / G) + lane / G;
+  // consecutive rows share the Y rows of their neighbours: each XCD takes a contiguous run of
+  // the bin's rows (bins list rows roughly in row order), so those reads hit its L2
+  const int64_t r64 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (kWave / G) + lane / G;
   const bool live = r64 < nrows;
   const int32_t i = live ? rows[r64] : 0;
   const int64_t base = live ? poff[i] : 0;
@@ -251,8 +253,9 @@ __global__ __launch_bounds__(BS) void k_esc_single(
   __shared__ double sv[CH];
   __shared__ int32_t s_scan[BS];
   const int tid = threadIdx.x;
-  if ((int32_t)blockIdx.x >= nrows) return;
-  const int32_t i = rows[blockIdx.x];
+  const int32_t slot = blockIdx.x;
+  if (slot >= nrows) return;
+  const int32_t i = rows[slot];
   const int64_t base = poff[i];
   const int32_t L = (int32_t)(poff[i + 1] - base);
   load_sorted_chunk(0, L, xrp[i], xrp[i + 1], xpref, xcol, xval, yrp, ycol, yval, sk, sv);
@@ -512,8 +515,9 @@ __global__ __launch_bounds__(64) void k_esc_wave(
   __shared__ double s_a[64], s_v[64];
   __shared__ int32_t s_cnt;
   const int lane = threadIdx.x;
-  if ((int32_t)blockIdx.x >= nrows) return;  // block-uniform
-  const int32_t i = rows[blockIdx.x];
+  const int32_t slot = blockIdx.x;
+  if (slot >= nrows) return;  // block-uniform
+  const int32_t i = rows[slot];
   const int64_t base = poff[i];
   // DENSE: acc[width] then the bitmap; HASH: hv[H], hk[H], then the sort keys (H/2)
   double *acc = lds_dyn;
@@ -524,7 +528,7 @@ __global__ __launch_bounds__(64) void k_esc_wave(
   int32_t lo = 0, rw = width;
   if (DENSE) {
     if (win) {
-      const int2 w = win[blockIdx.x];
+      const int2 w = win[slot];
       lo = w.x;
       rw = w.y;
     }
