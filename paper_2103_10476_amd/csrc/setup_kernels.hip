@@ -660,6 +660,186 @@ __global__ void k_mis_pass2(int32_t n, const int32_t *__restrict__ grp,
   }
 }
 
+// ---- root selection in one workgroup --------------------------------------------------------
+// On levels of at most kMisWgMaxN vertices, every round after the first runs inside a single
+// workgroup of kMisWg threads: the same two passes, triggers and early end as above, with
+// __syncthreads() between passes instead of kernel boundaries.  The triggered vertices of a
+// pass are kept as lists; a vertex enters a list once, through a bit in an LDS bitmap (bm1
+// for pass-1 lists, bm2 for pass-2 lists) that is set with an atomic or and cleared when the
+// entry is taken, so list lengths stay within n.  Round 1's pass-1 list is read from the byte
+// stamps that the grid round 0 left (value 1).  G lanes share a vertex (lane j takes entries
+// j, j+G, ...).  The round count and the keys equal the grid path's.
+// result[0] = the first round that changed nothing, result[1] = 1 if max_rounds was reached;
+// the same word goes to the host-mapped post (bit 31 set on that error).
+constexpr int kMisWg = 1024;
+constexpr int64_t kMisWgMaxN = 4096;  // default level size limit (SAAMG_MIS_WG_MAX_N)
+constexpr int64_t kMisWgLdsMaxN = 131072;  // the bitmaps' limit: 2 x 16 KiB of LDS
+
+// Appends the slots q with take[q] of every active lane to list: one LDS atomic per
+// wavefront, slots in lane-major order of the ballots.
+template <int Q>
+__device__ inline void wave_append(const int32_t (&w)[Q], const bool (&take)[Q],
+                                   int32_t *list, int32_t *cnt) {
+  uint32_t off[Q];
+  uint32_t total = 0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const uint64_t m = __ballot(take[q]);
+    off[q] = total + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    total += (uint32_t)__popcll(m);
+  }
+  if (total == 0) return;  // uniform over the active lanes
+  const uint64_t act = __ballot(true);
+  int32_t base = 0;
+  if ((int)__lane_id() == __ffsll((unsigned long long)act) - 1)
+    base = atomicAdd(cnt, (int32_t)total);
+  base = __builtin_amdgcn_readfirstlane(base);
+#pragma unroll
+  for (int q = 0; q < Q; ++q)
+    if (take[q]) list[base + (int32_t)off[q]] = w[q];
+}
+
+template <class K, int G>
+__global__ __launch_bounds__(kMisWg) void k_mis_rounds_wg(
+    int32_t n, const int32_t *__restrict__ grp, const int32_t *__restrict__ gcol, K *key, K *k1,
+    const uint8_t *__restrict__ st1, const int32_t *__restrict__ flag0, int32_t *l1,
+    int32_t *l2, int32_t max_rounds, int32_t *result, uint32_t *hpost) {
+  extern __shared__ uint32_t bm[];  // bm1 = bm[0, nwb), bm2 = bm[nwb, 2 nwb)
+  __shared__ int32_t c1, c2, chg[2];
+  const int tid = threadIdx.x;
+  const int j = tid % G;     // lane within the vertex's group
+  const int grp0 = tid / G;  // group number
+  constexpr int kGroups = kMisWg / G;
+  const int32_t nwb = (n + 31) >> 5;
+  uint32_t *bm1 = bm, *bm2 = bm + nwb;
+  for (int32_t w = tid; w < 2 * nwb; w += kMisWg) bm[w] = 0u;
+  if (tid == 0) {
+    c1 = 0;
+    c2 = 0;
+    chg[0] = 0;
+    chg[1] = 0;
+  }
+  __syncthreads();
+  // min of x over v (lane 0) and N[v] = gcol[b..e), 8 independent loads per step
+  auto ball_min = [&](const K *x, int32_t v, int32_t b, int32_t e) {
+    K m = (j == 0) ? x[v] : ~(K)0;
+    for (int32_t k = b + j; k < e; k += 8 * G) {
+      int32_t c[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) c[q] = gcol[min(k + q * G, e - 1)];
+      K kv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) kv[q] = x[c[q]];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) m = kv[q] < m ? kv[q] : m;
+    }
+#pragma unroll
+    for (int off = G / 2; off >= 1; off >>= 1) {
+      const K o = __shfl_xor(m, off, G);
+      m = o < m ? o : m;
+    }
+    return m;
+  };
+  // lists v and N[v] (slot b-1 stands for v) unless their bit is set; slots past the end
+  // take a no-op or on v's word
+  auto push_ball = [&](int32_t v, int32_t b, int32_t e, uint32_t *bmx, int32_t *list,
+                       int32_t *cnt) {
+    for (int32_t k = b - 1 + j; k < e; k += 8 * G) {
+      int32_t w[8];
+      bool take[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int32_t kk = k + q * G;
+        w[q] = (kk < b || kk >= e) ? v : gcol[kk];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const uint32_t bit = (k + q * G < e) ? 1u << (w[q] & 31) : 0u;
+        take[q] = bit != 0u && (atomicOr(bmx + (w[q] >> 5), bit) & bit) == 0u;
+      }
+      wave_append<8>(w, take, list, cnt);
+    }
+  };
+  uint32_t used = 0, err = 0;
+  if (*flag0 != 0) {
+    // round 1's pass-1 list: the vertices stamped 1 by round 0 (4 stamps per word; the byte
+    // array is padded to a multiple of 16)
+    const int32_t nw = (n + 3) >> 2;
+    for (int32_t w0 = tid; w0 - tid < nw; w0 += kMisWg) {  // every lane runs every step
+      const uint32_t word = w0 < nw ? reinterpret_cast<const uint32_t *>(st1)[w0] : 0u;
+      int32_t w[4];
+      bool take[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        w[q] = 4 * w0 + q;
+        take[q] = w[q] < n && ((word >> (8 * q)) & 0xffu) == 1u;
+      }
+      wave_append<4>(w, take, l1, &c1);
+    }
+    __syncthreads();
+    for (uint32_t r = 1;; ++r) {
+      // pass 1: k1(u) = min key over N[u] for listed u; a change lists N[u] u {u} for pass 2
+      const int32_t n1 = c1;
+      for (int32_t idx = grp0; idx < n1; idx += kGroups) {
+        const int32_t u = l1[idx];
+        if (j == 0) atomicAnd(bm1 + (u >> 5), ~(1u << (u & 31)));
+        const int32_t b = grp[u], e = grp[u + 1];
+        const K old = k1[u];
+        const K m = ball_min(key, u, b, e);
+        if (j == 0) k1[u] = m;
+        if (m != old) push_ball(u, b, e, bm2, l2, &c2);
+      }
+      __syncthreads();
+      const int32_t n2 = c2;
+      __syncthreads();  // every thread holds n1 and n2: both counters may restart
+      if (tid == 0) {
+        c1 = 0;
+        c2 = 0;
+        chg[r & 1] = 0;
+      }
+      __syncthreads();
+      // pass 2: a listed undecided v takes m = min k1 over N[v]; a change lists N[v] u {v}
+      // for pass 1 of the next round
+      for (int32_t idx = grp0; idx < n2; idx += kGroups) {
+        const int32_t v = l2[idx];
+        if (j == 0) atomicAnd(bm2 + (v >> 5), ~(1u << (v & 31)));
+        const K me = key[v];
+        const int32_t b = grp[v], e = grp[v + 1];
+        if ((me & KeyT<K>::Mask) != KeyT<K>::Und) continue;  // group-uniform
+        const K m = ball_min(k1, v, b, e);
+        const K pri = me & ~KeyT<K>::Mask;
+        K nk = me;
+        if ((m & KeyT<K>::Mask) == KeyT<K>::In) nk = KeyT<K>::Out | pri;
+        else if (m == me) nk = KeyT<K>::In | pri;
+        if (nk != me) {  // group-uniform
+          if (j == 0) {
+            key[v] = nk;
+            chg[r & 1] = 1;
+          }
+          push_ball(v, b, e, bm1, l1, &c1);
+        }
+      }
+      __syncthreads();
+      if (chg[r & 1] == 0) {  // workgroup-uniform
+        used = r;
+        break;
+      }
+      if ((int64_t)r >= (int64_t)max_rounds) {
+        used = r;
+        err = 1;
+        break;
+      }
+    }
+  }
+  if (tid == 0) {
+    result[0] = (int32_t)used;
+    result[1] = (int32_t)err;
+    if (hpost)
+      __hip_atomic_store(hpost, used | (err << 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 // Largest row length of a CSR (two-stage maximum, no contended atomics).
 __global__ void k_rowlen_max_stage(int32_t n, const int32_t *rp, int32_t *part) {
   __shared__ int32_t sh[kBlock];
@@ -757,8 +937,12 @@ static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const
   tmp.stream = s;
   K *key = tmp.alloc<K>(n);
   K *k1 = tmp.alloc<K>(n);
-  uint8_t *st1 = tmp.alloc<uint8_t>(n);
-  uint8_t *st2 = tmp.alloc<uint8_t>(n);
+  uint8_t *st1 = tmp.alloc<uint8_t>((n + 15) & ~15);  // padded for word reads
+  uint8_t *st2 = tmp.alloc<uint8_t>((n + 15) & ~15);
+  // levels up to wg_max_n vertices run the rounds after the first in one workgroup
+  int64_t wg_max_n = kMisWgMaxN;
+  if (const char *e = std::getenv("SAAMG_MIS_WG_MAX_N")) wg_max_n = std::atoll(e);
+  const bool one_wg = nnzG > 0 && n <= std::min(wg_max_n, kMisWgLdsMaxN);
   k_mis_init<K><<<grid_for(n), kBlock, 0, s>>>(n, grp, order, seed, level, singletons, key, st1,
                                                st2);
   SA_LAUNCH_CHECK();
@@ -806,6 +990,24 @@ static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const
   int64_t launched = 0, seen = 0;  // rounds launched; rounds whose outcome is known
   int32_t used = 0;
   bool done = nnzG == 0;
+  int32_t *wg_result = nullptr;
+  if (one_wg) {
+    // round 0 on the grid (every vertex), the rest in one workgroup
+    wg_result = tmp.alloc<int32_t>(2);
+    int32_t *l12 = tmp.alloc<int32_t>(2 * (int64_t)n);
+    launch_round(0);
+    const int32_t max_rounds = (int32_t)std::min<int64_t>((int64_t)n + 2, INT32_MAX);
+    // rows past 16 entries: 4 lanes per vertex
+    const size_t lds = sizeof(uint32_t) * 2 * (size_t)((n + 31) / 32);
+    if (maxdeg > 16)
+      k_mis_rounds_wg<K, 4><<<1, kMisWg, lds, s>>>(n, grp, gcol, key, k1, st1, flags, l12,
+                                                   l12 + n, max_rounds, wg_result, hs_dev);
+    else
+      k_mis_rounds_wg<K, 1><<<1, kMisWg, lds, s>>>(n, grp, gcol, key, k1, st1, flags, l12,
+                                                   l12 + n, max_rounds, wg_result, hs_dev);
+    SA_LAUNCH_CHECK();
+    done = true;
+  }
   auto wait_from = std::chrono::steady_clock::now();
   while (!done) {
     // round `seen`'s status is posted by pass 1 of round seen+1
@@ -842,13 +1044,24 @@ static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const
     if (done) break;
     wait_from = std::chrono::steady_clock::now();
   }
-  if (rounds_out) *rounds_out = used;
   int32_t *isr = tmp.alloc<int32_t>(n + 1);
   k_roots<K><<<grid_for(n), kBlock, 0, s>>>(n, key, isr);
   SA_LAUNCH_CHECK();
   int32_t *rid = tmp.alloc<int32_t>(n + 1);
   exclusive_scan_i32(isr, rid, n, s);
-  const int32_t nc = read1(rid + n, s);
+  const int32_t nc = read1(rid + n, s);  // synchronises the stream
+  if (one_wg) {
+    // the workgroup's outcome, posted to the host-mapped word (read back if it is not seen)
+    uint32_t v = hs[0];
+    if (v == ~0u) {
+      int32_t r2[2];
+      readback(r2, wg_result, sizeof(r2), s);
+      v = (uint32_t)r2[0] | ((uint32_t)r2[1] << 31);
+    }
+    if (v >> 31) throw Error(SA_ERR_COARSEN_STALLED, "root selection did not end");
+    used = (int32_t)v;
+  }
+  if (rounds_out) *rounds_out = used;
   int32_t *rv = ar.alloc<int32_t>(nc > 0 ? nc : 1);
   int32_t *agg1 = tmp.alloc<int32_t>(n);
   k_agg_phase1<K><<<grid_for(n), kBlock, 0, s>>>(n, grp, gcol, key, rid, agg1, is_root, rv);

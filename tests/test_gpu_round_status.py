@@ -1,12 +1,13 @@
-"""GPU parity of the root selection's end detection.
+"""GPU parity of the root selection's ways of running rounds.
 
-Rounds are launched back to back and the host learns where the selection ends from status
-words that the first pass of each round writes into pinned host memory; when a word does not
-arrive in time, the host synchronises and reads the device flags instead.  With
-SAAMG_STATUS_SPIN_NS=0 the fallback is taken at every wait, so both ways of finding the end
-are compared with the oracle (aggregates, roots and every setup array bitwise) and with each
-other (rounds per level), on the 64 x 64 stretched 5-point grid, a 24^3 stretched 7-point cube
-and a 14^3 random-coefficient 27-point cube.
+On the grid, rounds are launched back to back and the host learns where the selection ends
+from status words that the first pass of each round writes into pinned host memory; when a
+word does not arrive in time, the host synchronises and reads the device flags instead
+(SAAMG_STATUS_SPIN_NS=0 takes that fallback at every wait).  Levels up to
+SAAMG_MIS_WG_MAX_N vertices run every round after the first in one workgroup instead.  All
+three are compared with the oracle (aggregates, roots and every setup array bitwise) and with
+each other (rounds per level), on the 64 x 64 stretched 5-point grid, a 24^3 stretched
+7-point cube, a 14^3 random-coefficient 27-point cube and, in hashed order, a 20^3 cube.
 """
 import os
 
@@ -32,23 +33,34 @@ CASES = [
     (lambda: pb.fd7_stretched(24, 1000.0), dict(theta=0.02, max_coarse=50)),
     (lambda: pb.q1_random_kappa(14, seed=3), dict(theta=0.02, variants=["offlmp", "1norm"],
                                                   max_coarse=40)),
+    (lambda: pb.fd7_stretched(20, 1000.0), dict(theta=0.02, max_coarse=50, agg_order="hashed",
+                                                seed=31)),
 ]
+
+ENV = ("SAAMG_MIS_WG_MAX_N", "SAAMG_STATUS_SPIN_NS")
+MODES = {  # values for ENV (None: unset)
+    "grid, status ring": ("0", None),
+    "grid, device flags": ("0", "0"),
+    "one workgroup": ("1073741824", None),
+}
 
 
 @pytest.mark.parametrize("case", range(len(CASES)))
-def test_status_ring_and_fallback_agree(case, monkeypatch):
+def test_round_paths_agree(case, monkeypatch):
     make, opts = CASES[case]
     p = make()
     rounds = {}
-    for spin in (None, "0"):
-        if spin is None:
-            monkeypatch.delenv("SAAMG_STATUS_SPIN_NS", raising=False)
-        else:
-            monkeypatch.setenv("SAAMG_STATUS_SPIN_NS", spin)
+    for mode, values in MODES.items():
+        for var, v in zip(ENV, values):
+            if v is None:
+                monkeypatch.delenv(var, raising=False)
+            else:
+                monkeypatch.setenv(var, v)
         g, h = run_both(p, **opts)
         compare_setup(g, h)
-        rounds[spin] = list(g.info()["mis_rounds"])
-        log(f"[status] spin {spin}: rounds {rounds[spin]}")
+        rounds[mode] = list(g.info()["mis_rounds"])
+        log(f"[rounds] {mode}: {rounds[mode]}")
         g.close()
-    assert rounds[None] == rounds["0"]
-    assert max(rounds[None]) > 6  # more rounds than the launch-ahead window
+    first = rounds["grid, status ring"]
+    assert all(r == first for r in rounds.values()), rounds
+    assert max(first) > 6  # more rounds than the launch-ahead window
