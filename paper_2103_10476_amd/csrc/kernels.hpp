@@ -60,6 +60,13 @@ void sort_rows(int32_t n, const int32_t *rp, int32_t *col, double *val, hipStrea
 
 template <class T> void spmv_store(const SpmvArgs<T> &a, T *y, hipStream_t s);
 template <class T> void spmv_scale(const SpmvArgs<T> &a, const T *d, T *y, hipStream_t s);
+// y = d (A x), plus max |y_i| (bit patterns of non-negative doubles) maximised atomically
+// into slots[0..kMaxSlots), one atomic per row block of the CSR kernels (the sliced-ELL copy,
+// if set, is not used)
+constexpr int kMaxSlots = 256;
+template <class T>
+void spmv_scale_max(const SpmvArgs<T> &a, const T *d, T *y, unsigned long long *slots,
+                    hipStream_t s);
 template <class T> void spmv_resid(const SpmvArgs<T> &a, const T *f, T *r, hipStream_t s);
 template <class T> void spmv_add(const SpmvArgs<T> &a, T *u, hipStream_t s);
 // r = f - A u; d = (invD .* r) / theta

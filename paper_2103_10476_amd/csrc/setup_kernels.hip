@@ -1699,48 +1699,33 @@ __global__ void k_power_init(int32_t n, uint64_t seed, int32_t level, int32_t st
   const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
   x[i] = 2.0 * u - 1.0;
 }
-// max |y| as the bit pattern of a non-negative double (monotone for non-negative values);
-// per-block partials, then one block reduces them (no contended atomics).
-__global__ void k_absmax(int32_t n, const double *y, unsigned long long *part) {
-  __shared__ unsigned long long sh[kBlock];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long m = 0;
-  if (i < n) {
-    const double a = fabs(y[i]);
-    m = (a == a) ? (unsigned long long)__double_as_longlong(a) : 0ull;  // NaN ignored
+// x = y / 2^ilogb(m) with m = max |y_i|: every block reduces the kMaxSlots maxima that the
+// SpMV left (bit patterns of non-negative doubles, monotone), and block 0 clears the other
+// slot set, which the next iteration's SpMV fills.  A zero or non-finite maximum marks the
+// iteration dead.
+__global__ __launch_bounds__(kBlock) void k_normalize(int32_t n, const double *y,
+                                                      const unsigned long long *slots,
+                                                      unsigned long long *next, double *x,
+                                                      int32_t *dead) {
+  static_assert(kMaxSlots == kBlock, "one slot per thread");
+  __shared__ unsigned long long wm[kBlock / 64];
+  unsigned long long m = slots[threadIdx.x];
+  for (int off = 32; off >= 1; off >>= 1) {
+    const unsigned long long o = __shfl_xor(m, off, 64);
+    m = o > m ? o : m;
   }
-  sh[threadIdx.x] = m;
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  if (blockIdx.x == 0) next[threadIdx.x] = 0ull;
   __syncthreads();
-  for (int w = kBlock / 2; w >= 1; w >>= 1) {
-    if ((int)threadIdx.x < w && sh[threadIdx.x + w] > sh[threadIdx.x])
-      sh[threadIdx.x] = sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
-}
-__global__ void k_absmax_final(int32_t nb, const unsigned long long *part,
-                               unsigned long long *out) {
-  __shared__ unsigned long long sh[kBlock];
-  unsigned long long m = 0;
-  for (int32_t i = threadIdx.x; i < nb; i += blockDim.x) m = part[i] > m ? part[i] : m;
-  sh[threadIdx.x] = m;
-  __syncthreads();
-  for (int w = kBlock / 2; w >= 1; w >>= 1) {
-    if ((int)threadIdx.x < w && sh[threadIdx.x + w] > sh[threadIdx.x])
-      sh[threadIdx.x] = sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *out = sh[0];
-}
-__global__ void k_normalize(int32_t n, const double *y, const unsigned long long *mx,
-                            double *x, int32_t *dead) {
+#pragma unroll
+  for (int q = 0; q < kBlock / 64; ++q) m = wm[q] > m ? wm[q] : m;
   SA_ROW_KERNEL_BEGIN(n)
-  const double m = __longlong_as_double((long long)*mx);
-  if (!(m > 0.0) || !isfinite(m)) {
+  const double mv = __longlong_as_double((long long)m);
+  if (!(mv > 0.0) || !isfinite(mv)) {
     if (i == 0) *dead = 1;
     return;
   }
-  x[i] = ldexp(y[i], -ilogb(m));
+  x[i] = ldexp(y[i], -ilogb(mv));
 }
 __global__ void k_rayleigh(const double *xy, const double *xx, const int32_t *dead,
                            double *lam) {
@@ -1756,16 +1741,18 @@ void power_method(const Csr &M, const double *invD, int32_t iters, uint64_t seed
   double *y = tmp.alloc<double>(n);
   double *ws = tmp.alloc<double>(dot_ws_size(n));
   double *sc = tmp.alloc<double>(4);
-  const unsigned nbmax = grid_for(n);
-  unsigned long long *mx = tmp.alloc<unsigned long long>(nbmax + 1);
-  int32_t *dead = tmp.alloc<int32_t>(1);
-  fill_i32(dead, 0, 1, s);
+  // two sets of kMaxSlots maxima (iteration t fills set t mod 2), then the dead flag
+  unsigned long long *mx = tmp.alloc<unsigned long long>(2 * kMaxSlots + 1);
+  int32_t *dead = (int32_t *)(mx + 2 * kMaxSlots);
+  fill_i32((int32_t *)mx, 0, 2 * (2 * kMaxSlots + 1), s);
   k_power_init<<<grid_for(n), kBlock, 0, s>>>(n, seed, level, stream_id, x);
   SA_LAUNCH_CHECK();
   SpmvArgs<double> a = spmv_args<double>(M, M.val, x);
   a.plain = true;  // the estimate decides the hierarchy: every row in sequential order
   for (int32_t t = 1; t <= iters; ++t) {
-    spmv_scale<double>(a, invD, y, s);
+    unsigned long long *cur = mx + (t & 1) * kMaxSlots, *nxt = mx + ((t + 1) & 1) * kMaxSlots;
+    if (t == iters) spmv_scale<double>(a, invD, y, s);
+    else spmv_scale_max<double>(a, invD, y, cur, s);
     if (t == iters) {
       dot_f64(x, y, n, sc + 0, ws, s);
       dot_f64(x, x, n, sc + 1, ws, s);
@@ -1773,9 +1760,7 @@ void power_method(const Csr &M, const double *invD, int32_t iters, uint64_t seed
       SA_LAUNCH_CHECK();
       break;
     }
-    k_absmax<<<nbmax, kBlock, 0, s>>>(n, y, mx + 1);
-    k_absmax_final<<<1, kBlock, 0, s>>>((int32_t)nbmax, mx + 1, mx);
-    k_normalize<<<grid_for(n), kBlock, 0, s>>>(n, y, mx, x, dead);
+    k_normalize<<<grid_for(n), kBlock, 0, s>>>(n, y, cur, nxt, x, dead);
     SA_LAUNCH_CHECK();
   }
 }

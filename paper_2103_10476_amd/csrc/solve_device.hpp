@@ -5,9 +5,18 @@
 // (solve_batch.hip).  Both call the functions below with the segment's own arguments, so a
 // hierarchy's arithmetic is the same whichever way its work was launched.
 #pragma once
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace sa {
+
+// Epilogues with a block_max member also reduce a per-row value over the row block:
+// row_max(has_row, s, pre) is called by every thread, block_max(b, m) once per block.
+template <class E, class = void>
+struct HasBlockMax : std::false_type {};
+template <class E>
+struct HasBlockMax<E, std::void_t<decltype(&E::block_max)>> : std::true_type {};
 
 template <class T>
 struct Chunk {
@@ -65,7 +74,11 @@ __device__ __forceinline__ void spmv_block(int32_t b, const int32_t *__restrict_
   // row and entry ranges: two independent 8-byte loads (one round trip)
   const int2 p0 = ((const int2 *)plan)[b], p1 = ((const int2 *)plan)[b + 1];
   const int32_t r0 = p0.x, e0 = p0.y, r1 = p1.x, e1 = p1.y;
-  if (r0 >= r1) return;  // block-uniform
+  if (r0 >= r1) {  // block-uniform: no rows (a block max, if any, is 0)
+    if constexpr (HasBlockMax<Epi>::value)
+      if (t == 0) epi.block_max(b, 0ull);
+    return;
+  }
   const int32_t row = r0 + t;
   int32_t mb = 0, me = 0;
   typename Epi::Pre pre{};
@@ -156,6 +169,23 @@ __device__ __forceinline__ void spmv_block(int32_t b, const int32_t *__restrict_
     }
   }
   if (row < r1) epi.store(row, s, pre);
+  if constexpr (HasBlockMax<Epi>::value) {
+    // the block's largest epilogue value: wavefront maxima, then thread 0 over the four (the
+    // long-row masks' words are free by now)
+    unsigned long long m = epi.row_max(row < r1, s, pre);
+    for (int off = 32; off >= 1; off >>= 1) {
+      const unsigned long long o = __shfl_xor(m, off, 64);
+      m = o > m ? o : m;
+    }
+    if (lane == 0) sh.longmask[wv] = m;
+    __syncthreads();
+    if (t == 0) {
+      unsigned long long mb2 = sh.longmask[0];
+#pragma unroll
+      for (int q = 1; q < NW; ++q) mb2 = sh.longmask[q] > mb2 ? sh.longmask[q] : mb2;
+      epi.block_max(b, mb2);
+    }
+  }
 }
 
 // ---- fused SpMV epilogues: row i receives s = (A x)_i ------------------------------------
@@ -178,6 +208,28 @@ struct EpScale {
   };
   __device__ Pre load(int32_t i) const { return {d[i]}; }
   __device__ void store(int32_t i, T s, const Pre &p) const { y[i] = p.d * s; }
+};
+// y = d (A x) as EpScale, and the largest |y_i| (NaN left out) as the bit pattern of a
+// non-negative double (monotone for non-negative values): each row block adds its maximum
+// with one atomic maximum to slot (block mod kMaxSlots).
+template <class T>
+struct EpScaleMax {
+  const T *d;
+  T *y;
+  unsigned long long *slots;
+  struct Pre {
+    T d;
+  };
+  __device__ Pre load(int32_t i) const { return {d[i]}; }
+  __device__ void store(int32_t i, T s, const Pre &p) const { y[i] = p.d * s; }
+  __device__ unsigned long long row_max(bool has, T s, const Pre &p) const {
+    if (!has) return 0ull;
+    const double a = fabs((double)(p.d * s));
+    return (a == a) ? (unsigned long long)__double_as_longlong(a) : 0ull;
+  }
+  __device__ void block_max(int32_t b, unsigned long long m) const {
+    if (m != 0ull) atomicMax(slots + (b % kMaxSlots), m);
+  }
 };
 template <class T>
 struct EpResid {

@@ -198,6 +198,13 @@ void spmv_scale(const SpmvArgs<T> &a, const T *d, T *y, hipStream_t s) {
   launch_spmv(a, EpScale<T>{d, y}, s);
 }
 template <class T>
+void spmv_scale_max(const SpmvArgs<T> &a, const T *d, T *y, unsigned long long *part,
+                    hipStream_t s) {
+  SpmvArgs<T> c = a;
+  c.sval = nullptr;  // the CSR kernels carry the maximum
+  launch_spmv(c, EpScaleMax<T>{d, y, part}, s);
+}
+template <class T>
 void spmv_resid(const SpmvArgs<T> &a, const T *f, T *r, hipStream_t s) {
   launch_spmv(a, EpResid<T>{f, r}, s);
 }
@@ -223,6 +230,8 @@ void spmv_jacobi(const SpmvArgs<T> &a, const T *f, const T *invD, T w, T *u2, hi
 #define SA_INST_SPMV(T)                                                                     \
   template void spmv_store<T>(const SpmvArgs<T> &, T *, hipStream_t);                       \
   template void spmv_scale<T>(const SpmvArgs<T> &, const T *, T *, hipStream_t);            \
+  template void spmv_scale_max<T>(const SpmvArgs<T> &, const T *, T *, unsigned long long *, \
+                                  hipStream_t);                                             \
   template void spmv_resid<T>(const SpmvArgs<T> &, const T *, T *, hipStream_t);            \
   template void spmv_add<T>(const SpmvArgs<T> &, T *, hipStream_t);                         \
   template void spmv_cheb_start<T>(const SpmvArgs<T> &, const T *, const T *, T, T *, T *,   \
