@@ -1096,8 +1096,9 @@ constexpr int32_t kSprsfySmall = 64;   // block path with LDS for root rows up t
 // "strong" as mask 1 or 2, so concurrent drops by other aggregates do not change them; the
 // result depends neither on member order nor on the order in which aggregates are taken.
 // Aggregates with a long root row or heavy members are listed for k_sprsfy_block: those with
-// root rows up to kSprsfySmall in heavy[0, nc) (count nheavy[0]), the others in heavy[nc, 2nc)
-// (count nheavy[1]).
+// root rows up to kSprsfySmall in heavy[0, nc) (count nheavy[0]), those up to kSprsfyLds in
+// heavy[nc, 2nc) (count nheavy[1]), longer ones for k_sprsfy_long in heavy[2nc, 3nc) (count
+// nheavy[2]).
 __global__ void k_sprsfy(int32_t nc, const int32_t *rp, const int32_t *col, uint8_t *mask,
                          const int32_t *agg, const int32_t *root_vertex, const int32_t *mrp,
                          const int32_t *mem, int32_t *heavy, int32_t *nheavy) {
@@ -1113,8 +1114,9 @@ __global__ void k_sprsfy(int32_t nc, const int32_t *rp, const int32_t *col, uint
     if (v != r) w += rp[v + 1] - rp[v];
   }
   if (long_row || w > kSprsfyMemberWork) {
-    // root rows up to kSprsfySmall: the small-LDS list; longer ones: the second list
-    const int which = re - rb > kSprsfySmall ? 1 : 0;
+    // root rows up to kSprsfySmall: the small-LDS list; up to kSprsfyLds: the second list;
+    // longer ones: the third
+    const int which = re - rb > kSprsfyLds ? 2 : re - rb > kSprsfySmall ? 1 : 0;
     heavy[which * (int64_t)nc + atomicAdd(nheavy + which, 1)] = J;
     return;
   }
@@ -1194,8 +1196,8 @@ __global__ __launch_bounds__(kBlock) void k_sprsfy_block(const int32_t *heavy,
                                                          const int32_t *col, uint8_t *mask,
                                                          const int32_t *agg,
                                                          const int32_t *root_vertex,
-                                                         const int32_t *mrp, const int32_t *mem,
-                                                         int32_t *overflow) {
+                                                         const int32_t *mrp,
+                                                         const int32_t *mem) {
   __shared__ uint64_t pairs[CAP];
   __shared__ int32_t cand[CAP];
   __shared__ int32_t cnt[CAP];
@@ -1205,10 +1207,7 @@ __global__ __launch_bounds__(kBlock) void k_sprsfy_block(const int32_t *heavy,
   const int32_t r = root_vertex[J];
   const int32_t rb = rp[r], re = rp[r + 1];
   const int32_t len = re - rb;
-  if (len > CAP) {
-    if (threadIdx.x == 0) atomicOr(overflow, 1);
-    return;
-  }
+  if (len > CAP) return;  // never: k_sprsfy lists longer root rows for k_sprsfy_long
   int32_t L = 1;
   while (L < len) L <<= 1;
   // key = (aggregate + 1) << 1 | strong ; entries that cannot be candidates sort first as 0
@@ -1309,6 +1308,65 @@ __global__ __launch_bounds__(kBlock) void k_sprsfy_block(const int32_t *heavy,
   }
 }
 
+// Aggregates whose root row is longer than kSprsfyLds, one block each: k_sprsfy's decisions
+// from global memory, the root row's entries shared out over the block's threads.  The thread
+// holding a candidate's first weak entry decides that candidate (the others skip it as not
+// first), so each candidate is decided once, as in k_sprsfy, for any row length.
+__global__ __launch_bounds__(kBlock) void k_sprsfy_long(const int32_t *list, const int32_t *rp,
+                                                        const int32_t *col, uint8_t *mask,
+                                                        const int32_t *agg,
+                                                        const int32_t *root_vertex,
+                                                        const int32_t *mrp,
+                                                        const int32_t *mem) {
+  const int32_t J = list[blockIdx.x];
+  const int32_t r = root_vertex[J];
+  const int32_t rb = rp[r], re = rp[r + 1];
+  for (int32_t k = rb + (int32_t)threadIdx.x; k < re; k += blockDim.x) {
+    const int32_t u0 = col[k];
+    if (u0 == r || mask[k] != 0) continue;  // weak connections of the root only
+    const int32_t c = agg[u0];
+    if (c < 0 || c == J) continue;
+    bool first = true, strong_reached = false;
+    for (int32_t q = rb; q < re && first && !strong_reached; ++q) {
+      const int32_t uq = col[q];
+      if (uq == r || agg[uq] != c) continue;
+      const uint8_t mq = mask[q];
+      if (mq == 1 || mq == 2) strong_reached = true;
+      else if (q < k) first = false;  // an earlier weak connection already reached c
+    }
+    if (!first || strong_reached) continue;
+    int32_t count = 0, ev = -1, vv = -1;
+    for (int32_t m = mrp[J]; m < mrp[J + 1] && count < 2; ++m) {
+      const int32_t v = mem[m];
+      if (v == r) continue;
+      for (int32_t q = rp[v]; q < rp[v + 1]; ++q) {
+        const int32_t u = col[q];
+        if (u == v) continue;
+        const uint8_t mq = mask[q];
+        if ((mq == 1 || mq == 2) && agg[u] == c) {
+          ++count;
+          ev = q;
+          vv = v;
+        }
+      }
+    }
+    if (count != 1) continue;
+    mask[ev] = 2;
+    const int32_t u = col[ev];
+    int32_t lo = rp[u], hi = rp[u + 1] - 1;
+    while (lo <= hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      const int32_t cm = col[mid];
+      if (cm == vv) {
+        if (mask[mid] == 1) mask[mid] = 2;
+        break;
+      }
+      if (cm < vv) lo = mid + 1;
+      else hi = mid - 1;
+    }
+  }
+}
+
 void sprsfy(int32_t n, const int32_t *rp, const int32_t *col, uint8_t *mask, const int32_t *agg,
             const int32_t *root_vertex, int32_t nc, hipStream_t s) {
   if (nc <= 0) return;
@@ -1316,24 +1374,26 @@ void sprsfy(int32_t n, const int32_t *rp, const int32_t *col, uint8_t *mask, con
   tmp.stream = s;
   int32_t *mrp, *mem;
   member_lists(n, agg, nc, false, tmp, &mrp, &mem, s);  // decisions ignore member order
-  // words: [0] heavy aggregates with root rows <= kSprsfySmall, [1] the longer ones, [2] overflow
+  // words: heavy aggregates with root rows [0] up to kSprsfySmall, [1] up to kSprsfyLds,
+  // [2] longer; heavy holds the three lists at offsets 0, nc and 2 nc
   int32_t *words = tmp.alloc<int32_t>(3);
-  int32_t *heavy = tmp.alloc<int32_t>(2 * (int64_t)nc);  // [0, nc) short roots, [nc, 2nc) long
+  int32_t *heavy = tmp.alloc<int32_t>(3 * (int64_t)nc);
   fill_i32(words, 0, 3, s);
   k_sprsfy<<<grid_for(nc), kBlock, 0, s>>>(nc, rp, col, mask, agg, root_vertex, mrp, mem,
                                            heavy, words);
   SA_LAUNCH_CHECK();
-  int32_t nh[2];
+  int32_t nh[3];
   readback(nh, words, sizeof(nh), s);
   if (nh[0] > 0)
     k_sprsfy_block<kSprsfySmall><<<(unsigned)nh[0], kBlock, 0, s>>>(
-        heavy, rp, col, mask, agg, root_vertex, mrp, mem, words + 2);
+        heavy, rp, col, mask, agg, root_vertex, mrp, mem);
   if (nh[1] > 0)
     k_sprsfy_block<kSprsfyLds><<<(unsigned)nh[1], kBlock, 0, s>>>(
-        heavy + nc, rp, col, mask, agg, root_vertex, mrp, mem, words + 2);
+        heavy + nc, rp, col, mask, agg, root_vertex, mrp, mem);
+  if (nh[2] > 0)
+    k_sprsfy_long<<<(unsigned)nh[2], kBlock, 0, s>>>(heavy + 2 * (int64_t)nc, rp, col, mask,
+                                                     agg, root_vertex, mrp, mem);
   SA_LAUNCH_CHECK();
-  if (nh[1] > 0 && read1(words + 2, s))
-    throw Error(SA_ERR_INVALID_ARG, "Sprsfy: a root row exceeds the supported length");
 }
 
 // ---- filtered matrix (Sec. 1.1 plain lumping; Sec. 2.3 Algorithm 2) and its diagonal -----

@@ -10,7 +10,8 @@ row sum plus 1/10, so the matrix is a symmetric M-matrix.  Both power methods of
 (D^-1 Abar for the damping factor, D^-1 A for the smoother) run through the SpMV, and their
 results are compared bitwise with the oracle, as is every setup array; the solve compares
 iterations and x.  The FP32 V-cycle (float products, the same split order) is compared with the
-FP64 solve.
+FP64 solve.  A second matrix gives Sprsfy a root row of 5200 entries, longer than its block
+kernels hold in LDS.
 """
 import numpy as np
 import pytest
@@ -99,7 +100,8 @@ def test_hub_matrix_shape():
     assert np.all(p.val[off] < 0) and np.all(p.val[~off] > 0)
 
 
-@pytest.mark.parametrize("var", [[], ["offlmp", "1norm"]], ids=lambda v: "+".join(v) or "plain")
+@pytest.mark.parametrize("var", [[], ["offlmp", "1norm"], ["sprsfy"]],
+                         ids=lambda v: "+".join(v) or "plain")
 def test_hub_matrix_parity(var):
     p, _ = hub_problem()
     g, h = run_both(p, theta=0.02, variants=var, rtol=1e-10, max_coarse=200)
@@ -122,3 +124,49 @@ def test_hub_matrix_fp32_vcycle():
         g.close()
     err = np.linalg.norm(xs["fp32"] - xs["fp64"]) / np.linalg.norm(xs["fp64"])
     assert err < 1e-8, err
+
+
+def long_root_problem(nx=100, ny=200, span=5200, w=0.01):
+    """A 100 x 200 five-point Laplacian whose corner vertex 0 is also coupled weakly (weight
+    -w) to every vertex of index below span but its grid neighbours: a 5200-entry row whose grid
+    couplings stay strong (at theta = 0.02), so vertex 0 is the first root and its aggregate's
+    Sprsfy decisions read a root row longer than the block kernels' LDS holds."""
+    n = nx * ny
+    nb = [dict() for _ in range(n)]
+
+    def link(i, j, v):
+        nb[i][j] = v
+        nb[j][i] = v
+
+    for y in range(ny):
+        for x in range(nx):
+            i = x + nx * y
+            if x + 1 < nx:
+                link(i, i + 1, -1.0)
+            if y + 1 < ny:
+                link(i, i + nx, -1.0)
+    for j in range(2, span):
+        if j != nx:
+            link(0, j, -w)
+    rp = np.zeros(n + 1, dtype=np.int32)
+    cols, vals = [], []
+    for i in range(n):
+        d = sum(abs(v) for v in nb[i].values()) + 0.1
+        ent = sorted(list(nb[i].items()) + [(i, d)])
+        rp[i + 1] = rp[i] + len(ent)
+        cols += [j for j, _ in ent]
+        vals += [v for _, v in ent]
+    return pb.CsrProblem(n, rp, np.asarray(cols, dtype=np.int32), np.asarray(vals), "longroot")
+
+
+def test_sprsfy_long_root_row():
+    """Sprsfy on an aggregate whose root row has 5200 entries: every setup array (the drop
+    marks among them) bitwise equal to the oracle's, and the solve."""
+    p = long_root_problem()
+    assert p.rp[1] - p.rp[0] == 5200
+    g, h = run_both(p, theta=0.02, variants=["sprsfy"], rtol=1e-10, max_coarse=200)
+    L0 = h.levels[0]
+    assert L0.is_root[0] == 1 and int(np.sum(L0.mask == 2)) > 0  # the path is exercised
+    compare_setup(g, h)
+    compare_solve(g, h, pb.random_rhs(p.n, 7))
+
