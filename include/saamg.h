@@ -207,8 +207,13 @@ sa_status sa_setup_system(const sa_context *ctx, const sa_csr *A, int32_t block_
  * the Galerkin products, the smoothers and the coarsest inverse.  The result is bit-identical
  * to what sa_setup gives on the new values whenever that setup would take the same symbolic
  * decisions.  For a sequence of systems with one pattern (time steps, repeated requests) this
- * skips the strength test and root selection.  Errors as for sa_setup (values only); after a
- * failure the hierarchy can only be destroyed or re-set up again (solves return
+ * skips the strength test and root selection.  The first re-setup also builds, per level, the
+ * lists of products that form every entry of A P and R (A P) (in Gustavson order) and keeps
+ * A P; later re-setups then take R, A P and the coarse operators through those lists, without
+ * the products' symbolic passes (bitwise the same values).  This costs device memory of about
+ * 8 bytes per Galerkin product plus A P (held until sa_destroy); the environment variable
+ * SAAMG_RESETUP_PLAN=0 keeps the full products instead.  Errors as for sa_setup (values
+ * only); after a failure the hierarchy can only be destroyed or re-set up again (solves return
  * SA_ERR_INVALID_ARG).  A systems hierarchy keeps its nullspace (nullspace must be NULL). */
 sa_status sa_resetup(sa_hierarchy *h, const double *val, const double *nullspace,
                      sa_location loc);

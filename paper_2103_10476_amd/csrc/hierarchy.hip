@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -31,7 +32,8 @@ enum ErrBits {
   E_CHOL = 64,
   E_COORD = 128,
   E_ASYM = 256,
-  E_QR = 512
+  E_QR = 512,
+  E_PLAN = 1024
 };
 
 constexpr int32_t kMaxRestart = 1024;  // GMRES restart length limit
@@ -336,10 +338,40 @@ static bool build_level(sa_hierarchy *h, int l) {
 
 // R_l = P_l^T and A_{l+1} = R_l (A_l P_l); P_1 first gets the nullspace scaling.  fresh:
 // allocate level l+1; otherwise overwrite the values of R_l and A_{l+1}.
+static bool resetup_plans_enabled() {
+  const char *e = std::getenv("SAAMG_RESETUP_PLAN");
+  return !(e && e[0] == '0');
+}
+static Csr keep_copy(const Csr &src, Arena &ar, hipStream_t s) {
+  Csr d = src;
+  d.rp = ar.alloc<int32_t>(src.n + 1);
+  d.col = ar.alloc<int32_t>(src.nnz > 0 ? src.nnz : 1);
+  d.val = ar.alloc<double>(src.nnz > 0 ? src.nnz : 1);
+  d.bstart = nullptr;
+  d.nblk = 0;
+  SA_HIP(hipMemcpyAsync(d.rp, src.rp, sizeof(int32_t) * (src.n + 1), hipMemcpyDeviceToDevice, s));
+  if (src.nnz > 0) {
+    SA_HIP(hipMemcpyAsync(d.col, src.col, sizeof(int32_t) * src.nnz, hipMemcpyDeviceToDevice, s));
+    SA_HIP(hipMemcpyAsync(d.val, src.val, sizeof(double) * src.nnz, hipMemcpyDeviceToDevice, s));
+  }
+  return d;
+}
+
+// A re-setup (fresh false) after the first takes the values of R, A P and A_{l+1} through the
+// plans the first one built (R from P by the position map, each product entry summed over
+// its list in Gustavson order): bitwise the values the full products give, without their
+// symbolic passes.  SAAMG_RESETUP_PLAN=0 keeps the full products.
 static void galerkin(sa_hierarchy *h, int l, bool fresh, const double *dB) {
   const hipStream_t s = h->stream;
   Level &L = h->lv[l];
   if (l == 0 && dB) scale_rows(L.P, dB, s);
+  const bool plans = !fresh && resetup_plans_enabled();
+  if (plans && L.planned) {
+    transpose_values(L.P, L.rperm, L.R, s);
+    spgemm_numeric(L.A, L.P, L.pap, L.APk, s);
+    spgemm_numeric(L.R, L.APk, L.prap, h->lv[l + 1].A, s);
+    return;
+  }
   Arena tmp;
   tmp.stream = s;
   if (fresh) {
@@ -372,6 +404,14 @@ static void galerkin(sa_hierarchy *h, int l, bool fresh, const double *dB) {
   } else {
     spgemm(L.R, AP, tmp, Ac, s);
     take_values(Ac, h->lv[l + 1].A, s);  // As shares A's arrays on coarse levels
+    if (plans) {  // the first re-setup: keep A P and build the plans for the next ones
+      L.APk = keep_copy(AP, h->ar, s);
+      spgemm_plan(L.A, L.P, L.APk, h->ar, L.pap, h->err, E_PLAN, s);
+      spgemm_plan(L.R, L.APk, h->lv[l + 1].A, h->ar, L.prap, h->err, E_PLAN, s);
+      transpose_perm(L.P, L.R, h->ar, &L.rperm, s);
+      check_err(h, E_PLAN, SA_ERR_INVALID_ARG, "re-setup plan: a product outside the pattern");
+      L.planned = true;
+    }
   }
 }
 

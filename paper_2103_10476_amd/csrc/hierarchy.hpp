@@ -39,6 +39,12 @@ struct Level {
   double jac_w = 0.0;
   double *Ainv = nullptr;  // coarsest only: dense inverse, row-major
   Sell Aell;  // sliced-ELL copy of A for the solve (when it pays; see sell_build)
+  // re-setup plans, built by the first numeric re-setup: A P kept with its pattern, the
+  // numeric plans of A P and R (A P), and the positions of P's entries in R
+  bool planned = false;
+  Csr APk;
+  SpgemmPlan pap, prap;
+  int32_t *rperm = nullptr;
   // FP32 copies (FP32 V-cycle)
   float *Af = nullptr, *Pf = nullptr, *Rf = nullptr, *sm_invDf = nullptr;
   // work vectors

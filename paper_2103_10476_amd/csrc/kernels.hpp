@@ -246,6 +246,24 @@ void scale_sym(int32_t n, const int32_t *rp, const int32_t *col, const double *v
 // C = X * Y with Gustavson-order accumulation per output entry (ascending inner index);
 // output rows sorted; cancellations stored.  C's arrays are allocated from `ar`.
 void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s);
+// Numeric plan of C = X Y on a fixed pattern (re-setup): for each entry p of C, the products
+// that form it in ascending position of X's row (ascending inner index), as pairs of an X
+// entry le[t] and a Y entry lq[t] for t in [lrp[p], lrp[p+1]).
+struct SpgemmPlan {
+  int64_t *lrp = nullptr;
+  int32_t *le = nullptr, *lq = nullptr;
+  int64_t nprod = 0;
+};
+// Builds the plan from X, Y and the pattern of C (C = X Y as spgemm formed it); err bit
+// `bit` if a product's column is missing from C's row (never, for that C).
+void spgemm_plan(const Csr &X, const Csr &Y, const Csr &C, Arena &ar, SpgemmPlan &pl,
+                 int32_t *err, int32_t bit, hipStream_t s);
+// C.val from X.val and Y.val through the plan: every entry summed over its list in order,
+// from 0 (Gustavson order, as spgemm: bitwise the same values).
+void spgemm_numeric(const Csr &X, const Csr &Y, const SpgemmPlan &pl, Csr &C, hipStream_t s);
+// Position of every P entry in R = P^T (R's rows sorted), and R.val from P.val through it.
+void transpose_perm(const Csr &P, const Csr &R, Arena &ar, int32_t **perm, hipStream_t s);
+void transpose_values(const Csr &P, const int32_t *perm, Csr &R, hipStream_t s);
 
 // ---------------- coarsest level (coarse.hip) ------------------------------------------
 // Dense inverse of the coarsest operator via Cholesky (err bit 64 on a pivot <= 0).

@@ -915,4 +915,253 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
   }
 }
 
+// ---- numeric plan for a fixed pattern (re-setup) ---------------------------------------------
+// Built once from the patterns of X, Y and C, in parallel over X's entries (a thread per
+// entry, or a wavefront per entry when Y's rows are long): every product (e, q) finds its
+// column in C's sorted row i by binary search.  Pass 1 counts the products of every C entry
+// (atomically), pass 2 lists them in arrival order, and a last pass sorts every list by X
+// position e, i.e. by inner index: within one list each e occurs once, so the order is total.
+__device__ inline int32_t plan_find(const int32_t *ccol, int32_t lo, int32_t hi, int32_t j) {
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (ccol[mid] < j) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+__global__ void k_entry_rows(int32_t m, const int32_t *rp, int32_t *row) {
+  const int64_t i64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i64 >= m) return;
+  const int32_t i = (int32_t)i64;
+  for (int32_t e = rp[i]; e < rp[i + 1]; ++e) row[e] = i;
+}
+// G lanes per X entry (1 or 64); FILL: place (e, q) at lrp[p] + the next free slot of p.
+template <int G, bool FILL>
+__global__ void k_plan_entries(int64_t nx, const int32_t *__restrict__ xrow,
+                               const int32_t *__restrict__ xcol, const int32_t *__restrict__ yrp,
+                               const int32_t *__restrict__ ycol,
+                               const int32_t *__restrict__ crp,
+                               const int32_t *__restrict__ ccol, int32_t *cnt,
+                               const int64_t *__restrict__ lrp, int32_t *le, int32_t *lq,
+                               int32_t *err, int32_t bit) {
+  const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int32_t lane = G == 1 ? 0 : (int32_t)(threadIdx.x % G);
+  if (g >= nx) return;
+  const int32_t e = (int32_t)g;
+  const int32_t i = xrow[e], k = xcol[e];
+  const int32_t cb = crp[i], ce = crp[i + 1];
+  for (int32_t q = yrp[k] + lane; q < yrp[k + 1]; q += G) {
+    const int32_t j = ycol[q];
+    const int32_t p = plan_find(ccol, cb, ce, j);
+    if (p >= ce || ccol[p] != j) {
+      atomicOr(err, bit);
+      continue;
+    }
+    const int32_t slot = atomicAdd(cnt + p, 1);
+    if (FILL) {
+      le[lrp[p] + slot] = e;
+      lq[lrp[p] + slot] = q;
+    }
+  }
+}
+// Thread per C entry: a list of up to kPlanShort entries sorted by X position in place
+// (insertion); longer lists are listed for k_plan_sort_long.
+constexpr int32_t kPlanShort = 32;
+constexpr int32_t kPlanLds = 4096;  // a list is at most as long as X's longest row
+__global__ void k_plan_sort(int32_t nnzc, const int64_t *__restrict__ lrp, int32_t *le,
+                            int32_t *lq, int32_t *longs, int32_t *nlong) {
+  const int64_t p64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p64 >= nnzc) return;
+  const int64_t b = lrp[p64], en = lrp[p64 + 1];
+  if (en - b > kPlanShort) {
+    longs[atomicAdd(nlong, 1)] = (int32_t)p64;
+    return;
+  }
+  for (int64_t t = b + 1; t < en; ++t) {
+    const int32_t ke = le[t], kq = lq[t];
+    int64_t u = t - 1;
+    while (u >= b && le[u] > ke) {
+      le[u + 1] = le[u];
+      lq[u + 1] = lq[u];
+      --u;
+    }
+    le[u + 1] = ke;
+    lq[u + 1] = kq;
+  }
+}
+// Block per long list (grid-stride over them): keys (e << 32 | q) sorted by a bitonic sort in
+// LDS (e is unique within a list, so the order is that of e); a list past kPlanLds entries (X
+// rows that long) falls back to thread 0's insertion sort.
+__global__ __launch_bounds__(kBlock) void k_plan_sort_long(const int32_t *__restrict__ longs,
+                                                           const int32_t *__restrict__ nlong,
+                                                           const int64_t *__restrict__ lrp,
+                                                           int32_t *le, int32_t *lq) {
+  __shared__ uint64_t key[kPlanLds];
+  const int32_t nl = *nlong;
+  for (int32_t idx = blockIdx.x; idx < nl; idx += gridDim.x) {
+    const int32_t p = longs[idx];
+    const int64_t b = lrp[p];
+    const int32_t len = (int32_t)(lrp[p + 1] - b);
+    if (len > kPlanLds) {  // block-uniform
+      if (threadIdx.x == 0) {
+        for (int32_t t = 1; t < len; ++t) {
+          const int32_t ke = le[b + t], kq = lq[b + t];
+          int32_t u = t - 1;
+          while (u >= 0 && le[b + u] > ke) {
+            le[b + u + 1] = le[b + u];
+            lq[b + u + 1] = lq[b + u];
+            --u;
+          }
+          le[b + u + 1] = ke;
+          lq[b + u + 1] = kq;
+        }
+      }
+      __syncthreads();
+      continue;
+    }
+    int32_t L = 1;
+    while (L < len) L <<= 1;
+    for (int32_t t = threadIdx.x; t < L; t += blockDim.x)
+      key[t] = t < len ? (((uint64_t)(uint32_t)le[b + t] << 32) | (uint32_t)lq[b + t]) : ~0ull;
+    __syncthreads();
+    for (int32_t kk = 2; kk <= L; kk <<= 1) {
+      for (int32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+        for (int32_t t = threadIdx.x; t < L; t += blockDim.x) {
+          const int32_t u = t ^ jj;
+          if (u > t) {
+            const uint64_t x = key[t], y = key[u];
+            if ((x > y) == ((t & kk) == 0)) {
+              key[t] = y;
+              key[u] = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int32_t t = threadIdx.x; t < len; t += blockDim.x) {
+      le[b + t] = (int32_t)(key[t] >> 32);
+      lq[b + t] = (int32_t)(uint32_t)key[t];
+    }
+    __syncthreads();
+  }
+}
+__global__ void k_plan_numeric(int32_t nnzc, const int64_t *__restrict__ lrp,
+                               const int32_t *__restrict__ le, const int32_t *__restrict__ lq,
+                               const double *__restrict__ xv, const double *__restrict__ yv,
+                               double *__restrict__ cv) {
+  const int64_t p64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p64 >= nnzc) return;
+  const int32_t p = (int32_t)p64;
+  double s = 0.0;
+  for (int64_t t = lrp[p]; t < lrp[p + 1]; ++t) s += xv[le[t]] * yv[lq[t]];
+  cv[p] = s;
+}
+
+__global__ void k_widen_i32(int64_t n, const int32_t *a, int64_t *b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+static void widen_i32(const int32_t *a, int64_t *b, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_widen_i32<<<grid_for(n), kBlock, 0, s>>>(n, a, b);
+  SA_LAUNCH_CHECK();
+}
+
+void spgemm_plan(const Csr &X, const Csr &Y, const Csr &C, Arena &ar, SpgemmPlan &pl,
+                 int32_t *err, int32_t bit, hipStream_t s) {
+  pl = SpgemmPlan{};
+  Arena tmp;
+  tmp.stream = s;
+  const int64_t nx = X.nnz;
+  int32_t *xrow = tmp.alloc<int32_t>(nx > 0 ? nx : 1);
+  int32_t *cnt = tmp.alloc<int32_t>(C.nnz + 1);
+  pl.lrp = ar.alloc<int64_t>(C.nnz + 1);
+  int64_t *cnt64 = tmp.alloc<int64_t>(C.nnz + 1);
+  fill_i32(cnt, 0, C.nnz + 1, s);
+  if (X.n > 0) {
+    k_entry_rows<<<grid_for(X.n), kBlock, 0, s>>>(X.n, X.rp, xrow);
+    SA_LAUNCH_CHECK();
+  }
+  // long Y rows: a wavefront per X entry
+  const bool wide = (Y.maxrow >= 0 ? Y.maxrow : max_row_length(Y.n, Y.rp, s)) > 32;
+  auto pass = [&](bool fill) {
+    if (nx <= 0) return;
+    if (wide) {
+      if (fill)
+        k_plan_entries<64, true><<<grid_for(nx * 64), kBlock, 0, s>>>(
+            nx, xrow, X.col, Y.rp, Y.col, C.rp, C.col, cnt, pl.lrp, pl.le, pl.lq, err, bit);
+      else
+        k_plan_entries<64, false><<<grid_for(nx * 64), kBlock, 0, s>>>(
+            nx, xrow, X.col, Y.rp, Y.col, C.rp, C.col, cnt, nullptr, nullptr, nullptr, err,
+            bit);
+    } else {
+      if (fill)
+        k_plan_entries<1, true><<<grid_for(nx), kBlock, 0, s>>>(
+            nx, xrow, X.col, Y.rp, Y.col, C.rp, C.col, cnt, pl.lrp, pl.le, pl.lq, err, bit);
+      else
+        k_plan_entries<1, false><<<grid_for(nx), kBlock, 0, s>>>(
+            nx, xrow, X.col, Y.rp, Y.col, C.rp, C.col, cnt, nullptr, nullptr, nullptr, err,
+            bit);
+    }
+    SA_LAUNCH_CHECK();
+  };
+  pass(false);
+  widen_i32(cnt, cnt64, C.nnz, s);
+  exclusive_scan_i64(cnt64, pl.lrp, C.nnz, s);
+  pl.nprod = read1(pl.lrp + C.nnz, s);
+  pl.le = ar.alloc<int32_t>(pl.nprod > 0 ? pl.nprod : 1);
+  pl.lq = ar.alloc<int32_t>(pl.nprod > 0 ? pl.nprod : 1);
+  fill_i32(cnt, 0, C.nnz + 1, s);
+  pass(true);
+  if (C.nnz > 0) {
+    int32_t *longs = tmp.alloc<int32_t>(C.nnz);
+    int32_t *nlong = tmp.alloc<int32_t>(1);
+    fill_i32(nlong, 0, 1, s);
+    k_plan_sort<<<grid_for(C.nnz), kBlock, 0, s>>>((int32_t)C.nnz, pl.lrp, pl.le, pl.lq, longs,
+                                                   nlong);
+    k_plan_sort_long<<<1024, kBlock, 0, s>>>(longs, nlong, pl.lrp, pl.le, pl.lq);
+    SA_LAUNCH_CHECK();
+  }
+}
+
+void spgemm_numeric(const Csr &X, const Csr &Y, const SpgemmPlan &pl, Csr &C, hipStream_t s) {
+  if (C.nnz <= 0) return;
+  k_plan_numeric<<<grid_for(C.nnz), kBlock, 0, s>>>((int32_t)C.nnz, pl.lrp, pl.le, pl.lq, X.val,
+                                                    Y.val, C.val);
+  SA_LAUNCH_CHECK();
+}
+
+// R = P^T: entry k of P (row i, column c) sits in R's row c at column i.
+__global__ void k_transpose_perm(int32_t n, const int32_t *__restrict__ prp,
+                                 const int32_t *__restrict__ pcol,
+                                 const int32_t *__restrict__ rrp,
+                                 const int32_t *__restrict__ rcol, int32_t *perm) {
+  const int64_t i64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i64 >= n) return;
+  const int32_t i = (int32_t)i64;
+  for (int32_t k = prp[i]; k < prp[i + 1]; ++k) {
+    const int32_t c = pcol[k];
+    const int32_t p = plan_find(rcol, rrp[c], rrp[c + 1], i);
+    perm[k] = (p < rrp[c + 1] && rcol[p] == i) ? p : -1;  // -1: never, for R = P^T
+  }
+}
+__global__ void k_transpose_values(int64_t nnz, const int32_t *__restrict__ perm,
+                                   const double *__restrict__ pv, double *__restrict__ rv) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nnz && perm[k] >= 0) rv[perm[k]] = pv[k];
+}
+void transpose_perm(const Csr &P, const Csr &R, Arena &ar, int32_t **perm, hipStream_t s) {
+  *perm = ar.alloc<int32_t>(P.nnz > 0 ? P.nnz : 1);
+  if (P.n > 0) {
+    k_transpose_perm<<<grid_for(P.n), kBlock, 0, s>>>(P.n, P.rp, P.col, R.rp, R.col, *perm);
+    SA_LAUNCH_CHECK();
+  }
+}
+void transpose_values(const Csr &P, const int32_t *perm, Csr &R, hipStream_t s) {
+  if (P.nnz <= 0) return;
+  k_transpose_values<<<grid_for(P.nnz), kBlock, 0, s>>>(P.nnz, perm, P.val, R.val);
+  SA_LAUNCH_CHECK();
+}
+
 }  // namespace sa

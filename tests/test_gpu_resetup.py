@@ -112,5 +112,47 @@ def test_resetup_full_size_fd7_128():
     h.resetup(val2)
     compare_setup(g, h)
     compare_solve(g, h, pb.random_rhs(p.n, 2))
+    # the second re-setup takes the Galerkin values through the plans the first one built
+    val3 = _dad(p, 6)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.resetup(val3)
+    torch.cuda.synchronize()
+    t_re2 = time.perf_counter() - t0
+    h.resetup(val3)
+    compare_setup(g, h)
+    compare_solve(g, h, pb.random_rhs(p.n, 3))
     log(f"[resetup] 128^3: setup {t_setup * 1e3:.1f} ms (first, cold), re-setup "
-        f"{t_re * 1e3:.1f} ms")
+        f"{t_re * 1e3:.1f} ms (builds the plans), next re-setup {t_re2 * 1e3:.1f} ms")
+
+
+PARTS = ("A_val", "P_val", "R_val", "Abar_val", "invD", "sm_invD", "coarse_inv")
+
+
+@pytest.mark.parametrize("name,make,kw", CASES[1:3], ids=[c[0] for c in CASES[1:3]])
+def test_planned_resetups_equal_full_ones(name, make, kw, monkeypatch):
+    """Four re-setups in a row with the Galerkin plans (built by the first, used by the
+    others) against the same four with the full products (SAAMG_RESETUP_PLAN=0): every level
+    array bit for bit."""
+    from paper_2103_10476_amd import solver
+    p = make()
+    vals = [_dad(p, 11), 2.0 * p.val, _dad(p, 12), _dad(p, 13)]
+    out = {}
+    for mode in ("plans", "full"):
+        if mode == "full":
+            monkeypatch.setenv("SAAMG_RESETUP_PLAN", "0")
+        else:
+            monkeypatch.delenv("SAAMG_RESETUP_PLAN", raising=False)
+        g = solver.Hierarchy.from_problem(p, options=solver.Options(**kw))
+        nl = g.info()["levels"]
+        out[mode] = []
+        for v in vals:
+            g.resetup(v)
+            out[mode].append([[g.export(l, part) for part in PARTS] for l in range(nl)])
+        g.close()
+    for k in range(len(vals)):
+        for l, (a_l, b_l) in enumerate(zip(out["plans"][k], out["full"][k])):
+            for part, a, b in zip(PARTS, a_l, b_l):
+                a, b = np.asarray(a), np.asarray(b)
+                assert a.shape == b.shape, (k, l, part)
+                assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), (k, l, part)
