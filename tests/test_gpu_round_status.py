@@ -63,4 +63,5 @@ def test_round_paths_agree(case, monkeypatch):
         g.close()
     first = rounds["grid, status ring"]
     assert all(r == first for r in rounds.values()), rounds
-    assert max(first) > 6  # more rounds than the launch-ahead window
+    if opts.get("agg_order") != "hashed":  # hashed order needs few rounds
+        assert max(first) > 6  # more rounds than the launch-ahead window
