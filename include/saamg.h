@@ -359,6 +359,15 @@ sa_status sa_server_create(const sa_context *ctx, size_t hbm_budget, int32_t max
 sa_status sa_server_submit(sa_server *s, const sa_csr *A, const double *b, const sa_options *o,
                            uint64_t *ticket);
 
+/* As sa_server_submit, but nothing is copied at submission: the request keeps A's arrays and
+ * b (host or device memory, A->loc) and reads them when its setup starts and during its solve.
+ * The caller must keep them valid and unchanged until sa_server_poll or sa_server_wait has
+ * returned the request's result, or sa_server_destroy has returned.  For clients whose inputs
+ * already sit in memory they own: submission then costs no copy of the matrix (a host copy of
+ * a large request runs at memcpy speed, about 0.1 s per GB).  Errors as sa_server_submit. */
+sa_status sa_server_submit_borrowed(sa_server *s, const sa_csr *A, const double *b,
+                                    const sa_options *o, uint64_t *ticket);
+
 /* Non-blocking: SA_PENDING while the request is queued or running.  Once it has finished,
  * writes x (n values in `loc` memory; may be NULL) and *r (may be NULL), forgets the ticket
  * and returns the request's status (SA_OK, SA_NOT_CONVERGED or its error; sa_last_error then

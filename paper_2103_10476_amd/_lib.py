@@ -38,8 +38,8 @@ EXPORTED = ["sa_default_options", "sa_setup", "sa_solve", "sa_vcycle", "sa_hiera
             "sa_last_error", "sa_profile_enable", "sa_profile_read", "sa_estimate_bytes",
             "sa_solve_many", "sa_resetup", "sa_setup_coords", "sa_solve_gmres",
             "sa_solve_gmres_noalloc", "sa_setup_system",
-            "sa_server_create", "sa_server_submit", "sa_server_poll", "sa_server_wait",
-            "sa_server_drain", "sa_server_get_stats", "sa_server_destroy"]
+            "sa_server_create", "sa_server_submit", "sa_server_submit_borrowed",
+            "sa_server_poll", "sa_server_wait", "sa_server_drain", "sa_server_get_stats", "sa_server_destroy"]
 
 
 class SaOptions(C.Structure):
@@ -154,9 +154,9 @@ def lib():
         L.sa_server_create.argtypes = [C.POINTER(SaContext), C.c_size_t, C.c_int32,
                                        C.POINTER(C.c_void_p)]
         L.sa_server_create.restype = C.c_int
-        L.sa_server_submit.argtypes = [P, C.POINTER(SaCsr), P, C.POINTER(SaOptions),
-                                       C.POINTER(C.c_uint64)]
-        L.sa_server_submit.restype = C.c_int
+        for f in (L.sa_server_submit, L.sa_server_submit_borrowed):
+            f.argtypes = [P, C.POINTER(SaCsr), P, C.POINTER(SaOptions), C.POINTER(C.c_uint64)]
+            f.restype = C.c_int
         for f in (L.sa_server_poll, L.sa_server_wait):
             f.argtypes = [P, C.c_uint64, P, C.c_int32, C.POINTER(SaResult)]
             f.restype = C.c_int

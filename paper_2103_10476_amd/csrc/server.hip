@@ -43,12 +43,24 @@ double now_s() {
       .count();
 }
 
+// A host copy of an input array, left uninitialised before the copy (no zero-fill pass).
+template <class T>
+struct HostCopy {
+  std::unique_ptr<T[]> p;
+  void reset() { p.reset(); }
+};
+
 struct Request {
   uint64_t ticket = 0;
   int32_t n = 0;
   int64_t nnz = 0;
-  std::vector<int32_t> rp, col;
-  std::vector<double> val, b;
+  // The inputs the setup and solve read: the request's own host copies (sa_server_submit) or
+  // the caller's arrays (sa_server_submit_borrowed), in `loc` memory.
+  const int32_t *rp = nullptr, *col = nullptr;
+  const double *val = nullptr, *b = nullptr;
+  sa_location loc = SA_HOST;
+  HostCopy<int32_t> rp_copy, col_copy;
+  HostCopy<double> val_copy, b_copy;
   sa_options opt{};
   std::vector<double> x;
   sa_result res{};
@@ -86,10 +98,12 @@ struct sa_server {
 namespace {
 
 void drop_inputs(Request &q) {
-  std::vector<int32_t>().swap(q.rp);
-  std::vector<int32_t>().swap(q.col);
-  std::vector<double>().swap(q.val);
-  std::vector<double>().swap(q.b);
+  q.rp_copy.reset();
+  q.col_copy.reset();
+  q.val_copy.reset();
+  q.b_copy.reset();
+  q.rp = q.col = nullptr;
+  q.val = q.b = nullptr;
 }
 
 // Marks a request finished (its memory already released) and wakes waiters and workers.
@@ -120,7 +134,7 @@ void run_setup(sa_server *s, hipStream_t stream, const std::shared_ptr<Request> 
   q.meter.parent = &s->total;
   sa::meter_begin(&q.meter);
   sa_context ctx{stream};
-  sa_csr A{q.n, q.nnz, q.rp.data(), q.col.data(), q.val.data(), SA_HOST};
+  sa_csr A{q.n, q.nnz, q.rp, q.col, q.val, q.loc};
   sa_hierarchy *h = nullptr;
   const sa_status st = sa_setup(&ctx, &A, nullptr, &q.opt, &h);
   sa::meter_end();
@@ -134,15 +148,17 @@ void run_setup(sa_server *s, hipStream_t stream, const std::shared_ptr<Request> 
   }
   sa_info info;
   if (sa_hierarchy_info(h, &info) == SA_OK) q.res.levels = info.levels;
-  std::vector<int32_t>().swap(q.rp);  // the matrix now lives in the hierarchy
-  std::vector<int32_t>().swap(q.col);
-  std::vector<double>().swap(q.val);
+  q.rp_copy.reset();  // the matrix now lives in the hierarchy
+  q.col_copy.reset();
+  q.val_copy.reset();
+  q.rp = q.col = nullptr;
+  q.val = nullptr;
   q.h = h;
   q.x.assign((size_t)q.n, 0.0);
   q.sys.h = h;
-  q.sys.b = q.b.data();
+  q.sys.b = q.b;
   q.sys.x = q.x.data();
-  q.sys.loc = SA_HOST;
+  q.sys.loc = q.loc;
   q.sys.user = &q;
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -256,15 +272,16 @@ sa_status guarded_server(F &&f) {
 }
 
 template <class T>
-void copy_host(std::vector<T> &dst, const T *src, size_t count, sa_location loc) {
-  dst.resize(count);
-  if (count == 0) return;
+const T *copy_host(HostCopy<T> &dst, const T *src, size_t count, sa_location loc) {
+  if (count == 0) return nullptr;
   if (!src) throw Error(SA_ERR_INVALID_ARG, "null array");
+  dst.p.reset(new T[count]);
   if (loc == SA_DEVICE) {
-    SA_HIP(hipMemcpy(dst.data(), src, sizeof(T) * count, hipMemcpyDeviceToHost));
+    SA_HIP(hipMemcpy(dst.p.get(), src, sizeof(T) * count, hipMemcpyDeviceToHost));
   } else {
-    std::memcpy(dst.data(), src, sizeof(T) * count);
+    std::memcpy(dst.p.get(), src, sizeof(T) * count);
   }
+  return dst.p.get();
 }
 
 // Writes a finished request's result and returns its status; the caller holds s->mu and
@@ -325,11 +342,19 @@ sa_status sa_server_create(const sa_context *ctx, size_t hbm_budget, int32_t max
   });
 }
 
-sa_status sa_server_submit(sa_server *s, const sa_csr *A, const double *b, const sa_options *o,
-                           uint64_t *ticket) {
+}  // extern "C"
+
+namespace {
+
+// Common part of the two submission calls: checks, admission estimate, inputs (copied or
+// borrowed), queueing.
+sa_status submit_request(sa_server *s, const sa_csr *A, const double *b, const sa_options *o,
+                         uint64_t *ticket, bool borrow) {
   if (!s || !A || !b || !ticket) return SA_ERR_INVALID_ARG;
   if (A->n <= 0 || A->nnz < 0 || A->nnz >= (int64_t)INT32_MAX || !A->row_ptr)
     return SA_ERR_INVALID_ARG;
+  if (A->nnz > 0 && (!A->col || !A->val)) return SA_ERR_INVALID_ARG;
+  if (A->loc != SA_HOST && A->loc != SA_DEVICE) return SA_ERR_INVALID_ARG;
   if (o && o->struct_size != sizeof(sa_options)) return SA_ERR_INVALID_ARG;
   return guarded_server([&]() -> sa_status {
     auto q = std::make_shared<Request>();
@@ -340,10 +365,19 @@ sa_status sa_server_submit(sa_server *s, const sa_csr *A, const double *b, const
     q->res.reserved_bytes = sa_estimate_bytes(A->n, A->nnz);
     if (q->res.reserved_bytes > s->budget)
       throw Error(SA_ERR_OOM, "request estimate exceeds the server's memory budget");
-    copy_host(q->rp, A->row_ptr, (size_t)A->n + 1, A->loc);
-    copy_host(q->col, A->col, (size_t)A->nnz, A->loc);
-    copy_host(q->val, A->val, (size_t)A->nnz, A->loc);
-    copy_host(q->b, b, (size_t)A->n, A->loc);
+    if (borrow) {
+      q->rp = A->row_ptr;
+      q->col = A->col;
+      q->val = A->val;
+      q->b = b;
+      q->loc = A->loc;
+    } else {
+      q->rp = copy_host(q->rp_copy, A->row_ptr, (size_t)A->n + 1, A->loc);
+      q->col = copy_host(q->col_copy, A->col, (size_t)A->nnz, A->loc);
+      q->val = copy_host(q->val_copy, A->val, (size_t)A->nnz, A->loc);
+      q->b = copy_host(q->b_copy, b, (size_t)A->n, A->loc);
+      q->loc = SA_HOST;
+    }
     q->t_submit = now_s();
     {
       std::lock_guard<std::mutex> lk(s->mu);
@@ -357,6 +391,20 @@ sa_status sa_server_submit(sa_server *s, const sa_csr *A, const double *b, const
     s->cv_work.notify_all();
     return SA_OK;
   });
+}
+
+}  // namespace
+
+extern "C" {
+
+sa_status sa_server_submit(sa_server *s, const sa_csr *A, const double *b, const sa_options *o,
+                           uint64_t *ticket) {
+  return submit_request(s, A, b, o, ticket, false);
+}
+
+sa_status sa_server_submit_borrowed(sa_server *s, const sa_csr *A, const double *b,
+                                    const sa_options *o, uint64_t *ticket) {
+  return submit_request(s, A, b, o, ticket, true);
 }
 
 sa_status sa_server_poll(sa_server *s, uint64_t ticket, double *x, sa_location loc,

@@ -282,15 +282,17 @@ def estimate_bytes(n: int, nnz: int) -> int:
 class Server:
     """Many independent setup+solve requests on one GPU (sa_server_*): FIFO admission under
     an HBM budget, max_slots requests in flight, each on its own stream.  Inputs are host
-    numpy arrays (copied at submit); results come back as host numpy arrays."""
+    numpy arrays, copied at submit, or with borrow=True (sa_server_submit_borrowed) kept by
+    reference until the result has been collected; results come back as host numpy arrays."""
 
     def __init__(self, hbm_budget: int = 8 << 30, max_slots: int = 4):
         h = C.c_void_p()
         _lib.check(_lib.lib().sa_server_create(None, int(hbm_budget), int(max_slots),
                                                C.byref(h)), "sa_server_create")
         self._s = h
+        self._held = {}  # ticket -> the borrowed arrays, alive until the result is collected
 
-    def submit(self, A, b, options: Options | None = None) -> int:
+    def submit(self, A, b, options: Options | None = None, borrow: bool = False) -> int:
         """A: CsrProblem or (n, rp, col, val) of host arrays; returns the ticket."""
         if hasattr(A, "rp"):
             n, rp, col, val = A.n, A.rp, A.col, A.val
@@ -304,9 +306,11 @@ class Server:
                          val.ctypes.data, _lib.SA_HOST)
         opts = (options or Options()).to_c()
         t = C.c_uint64()
-        _lib.check(_lib.lib().sa_server_submit(self._s, C.byref(csr),
-                                               C.c_void_p(b.ctypes.data), C.byref(opts),
-                                               C.byref(t)), "sa_server_submit")
+        fn = _lib.lib().sa_server_submit_borrowed if borrow else _lib.lib().sa_server_submit
+        _lib.check(fn(self._s, C.byref(csr), C.c_void_p(b.ctypes.data), C.byref(opts),
+                      C.byref(t)), "sa_server_submit")
+        if borrow:
+            self._held[t.value] = (rp, col, val, b)
         return t.value
 
     def _collect(self, fn, ticket, n):
@@ -319,6 +323,7 @@ class Server:
     def wait(self, ticket: int, n: int):
         """Blocks until the request is done: (x, result dict).  A failed request raises."""
         code, x, r = self._collect(_lib.lib().sa_server_wait, ticket, n)
+        self._held.pop(ticket, None)
         _lib.check(code, "sa_server_wait")
         return x, r.as_dict()
 
@@ -327,6 +332,7 @@ class Server:
         code, x, r = self._collect(_lib.lib().sa_server_poll, ticket, n)
         if code == _lib.SA_PENDING:
             return None
+        self._held.pop(ticket, None)
         _lib.check(code, "sa_server_poll")
         return x, r.as_dict()
 
@@ -342,6 +348,7 @@ class Server:
         if getattr(self, "_s", None):
             _lib.lib().sa_server_destroy(self._s)
             self._s = None
+        self._held = {}  # destroy has returned: no request reads the borrowed arrays any more
 
     def __del__(self):
         try:

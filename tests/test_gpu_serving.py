@@ -47,10 +47,10 @@ def _alone(p, b, o):
     return xh, it, rr, st
 
 
-def _serve(reqs, budget, slots):
+def _serve(reqs, budget, slots, borrow=False):
     from paper_2103_10476_amd import solver
     srv = solver.Server(hbm_budget=budget, max_slots=slots)
-    tickets = [srv.submit(p, b, o) for (_, p, b, o) in reqs]
+    tickets = [srv.submit(p, b, o, borrow=borrow) for (_, p, b, o) in reqs]
     out = [srv.wait(t, p.n) for t, (_, p, _, _) in zip(tickets, reqs)]
     st = srv.stats()
     srv.close()
@@ -70,6 +70,18 @@ def test_mix_is_bitwise_equal_to_alone():
         assert 0 < r["peak_bytes"] <= r["reserved_bytes"], r
         assert r["latency_seconds"] >= r["setup_seconds"] + r["solve_seconds"]
     assert st["peak_reserved_bytes"] <= st["budget_bytes"]
+
+
+def test_borrowed_inputs_match_copied_ones():
+    """sa_server_submit_borrowed reads the caller's arrays instead of copies: same bits."""
+    reqs = _requests(8, 10, 24, seed=23)
+    copied, _ = _serve(reqs, budget=8 << 30, slots=3)
+    borrowed, st = _serve(reqs, budget=8 << 30, slots=3, borrow=True)
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    for req, (xc, rc), (xb, rb) in zip(reqs, copied, borrowed):
+        assert rb["status"] == rc["status"] and rb["iterations"] == rc["iterations"], req
+        assert rb["rel_residual"] == rc["rel_residual"], req
+        assert np.array_equal(xb.view(np.uint64), xc.view(np.uint64)), req
 
 
 def test_served_requests_match_oracle():
