@@ -5,7 +5,7 @@
 // rows are sorted; cancellations stay stored.
 //
 // Rows are binned by their product count T:
-//   T <= 64      16, 32 or 64 lanes per row (4, 2 or 1 rows per wavefront): one product per
+//   T <= 64      8, 16 or 32 lanes per row (8, 4 or 2 rows per wavefront): two products per
 //                lane, rank sort in LDS;
 //   T <= 256     one wavefront per row, 64 products per step sorted in registers, each run
 //                added to its column's sum in an LDS hash table;
@@ -71,27 +71,31 @@ __global__ __launch_bounds__(64) void k_count_products_w(int32_t m, const int32_
   if (lane == 0) cnt[i] = base;
 }
 
-// ---- G lanes per row (T <= G), 64/G rows per wavefront ---------------------------------------
-// A wavefront takes 64/G rows, G lanes each (G = 16, 32 or 64): short rows share a
-// wavefront instead of leaving most of its lanes idle.  Per row: the X entries G at a time
-// (a segmented scan of their Y-row lengths), one product per lane by binary search over the
-// scan, a rank sort of the T <= G products in LDS, and one lane per run of equal columns
-// summing it in order.  The chunk loop runs to the longest X row of the wavefront, so every
-// lane passes every barrier.
-template <int G>
+// ---- G lanes per row (T <= G P), 64/G rows per wavefront -----------------------------------
+// A wavefront takes 64/G rows, G lanes each, P products per lane: short rows share a
+// wavefront instead of leaving most of its lanes idle, and the more rows a wavefront holds,
+// the more of their (dependent) loads are in flight together.  Per row: the X entries G at a
+// time (a segmented scan of their Y-row lengths), the products by binary search over the scan
+// (lane l takes products l, l+G, ...), a rank sort of the T <= G P products in LDS by
+// (column, position), and one lane per run of equal columns summing it in order.  The chunk
+// loop runs to the longest X row of the wavefront, so every lane passes every barrier.
+template <int G, int P>
 __global__ __launch_bounds__(kWave) void k_esc_group(
     const int32_t *rows, int32_t nrows, const int32_t *xrp, const int32_t *xcol,
     const double *xval, const int32_t *yrp, const int32_t *ycol, const double *yval,
     const int64_t *poff, int32_t *ocol, double *oval, int32_t *ucnt) {
-  static_assert(G == 16 || G == 32 || G == 64, "group width");
-  __shared__ int32_t keys[kWave];
-  __shared__ double vals[kWave];
-  __shared__ int32_t skeys[kWave];
-  __shared__ double svals[kWave];
+  static_assert((G == 8 || G == 16 || G == 32 || G == 64) && (P == 1 || P == 2),
+                "group width, products per lane");
+  constexpr int CAP = G * P;  // products of one row at most
+  __shared__ int32_t keys[kWave * P];
+  __shared__ double vals[kWave * P];
+  __shared__ int32_t skeys[kWave * P];
+  __shared__ double svals[kWave * P];
   __shared__ int32_t s_incl[kWave], s_ys[kWave];
   __shared__ double s_a[kWave];
   const int lane = threadIdx.x;
   const int gl = lane % G, gb = lane - gl;  // lane in the group, the group's first lane
+  const int pb = (lane / G) * CAP;          // the row's product slots in keys/vals
   // consecutive rows share the Y rows of their neighbours: each XCD takes a contiguous run of
   // the bin's rows (bins list rows roughly in row order), so those reads hit its L2
   const int64_t r64 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (kWave / G) + lane / G;
@@ -126,7 +130,7 @@ __global__ __launch_bounds__(kWave) void k_esc_group(
     s_a[lane] = a;
     __syncthreads();
     // product p of this chunk comes from the first entry s with incl[s] > p, at offset
-    // p - incl[s-1] in its row of Y: one product per lane, loads independent across lanes
+    // p - incl[s-1] in its row of Y: loads independent across lanes
     for (int32_t p = gl; p < tot; p += G) {
       int32_t lo = 0, hi = G - 1;
       while (lo < hi) {
@@ -135,42 +139,52 @@ __global__ __launch_bounds__(kWave) void k_esc_group(
         else lo = mid + 1;
       }
       const int32_t t = p - (lo > 0 ? s_incl[gb + lo - 1] : 0);
-      keys[gb + filled + p] = ycol[s_ys[gb + lo] + t];
-      vals[gb + filled + p] = s_a[gb + lo] * yval[s_ys[gb + lo] + t];
+      keys[pb + filled + p] = ycol[s_ys[gb + lo] + t];
+      vals[pb + filled + p] = s_a[gb + lo] * yval[s_ys[gb + lo] + t];
     }
     __syncthreads();
     filled += tot;
   }
-  int32_t key = 0;
-  double v = 0.0;
-  if (gl < T) {
-    key = keys[gb + gl];
-    v = vals[gb + gl];
-    int32_t rank = 0;
-    for (int32_t q = 0; q < T; ++q) {
-      const int32_t kq = keys[gb + q];
-      rank += (kq < key) || (kq == key && q < gl);
+  // rank sort: positions q G + gl of the row, ordered by (column, position)
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    const int32_t pos = q * G + gl;
+    if (pos < T) {
+      const int32_t key = keys[pb + pos];
+      int32_t rank = 0;
+      for (int32_t r = 0; r < T; ++r) {
+        const int32_t kr = keys[pb + r];
+        rank += (kr < key) || (kr == key && r < pos);
+      }
+      skeys[pb + rank] = key;
+      svals[pb + rank] = vals[pb + pos];
     }
-    skeys[gb + rank] = key;
-    svals[gb + rank] = v;
   }
   __syncthreads();
-  bool head = false;
-  double sum = 0.0;
-  if (gl < T) {
-    key = skeys[gb + gl];
-    head = (gl == 0) || (skeys[gb + gl - 1] != key);
-    if (head)
-      for (int32_t r = gl; r < T && skeys[gb + r] == key; ++r) sum += svals[gb + r];
+  // one lane per run of equal columns adds it in order from 0 and writes it at the run's rank
+  int32_t before = 0;  // runs in the earlier position slices of the row
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    const int32_t pos = q * G + gl;
+    bool head = false;
+    int32_t key = 0;
+    double sum = 0.0;
+    if (pos < T) {
+      key = skeys[pb + pos];
+      head = (pos == 0) || (skeys[pb + pos - 1] != key);
+      if (head)
+        for (int32_t r = pos; r < T && skeys[pb + r] == key; ++r) sum += svals[pb + r];
+    }
+    const unsigned long long gm =
+        (__ballot(head) >> gb) & (~0ull >> (64 - G));  // this group's heads in slice q
+    const int32_t idx = before + __popcll(gm & ((1ull << gl) - 1ull));
+    if (head) {
+      ocol[base + idx] = key;
+      oval[base + idx] = sum;
+    }
+    before += __popcll(gm);
   }
-  const unsigned long long gm =
-      (__ballot(head) >> gb) & (~0ull >> (64 - G));  // this group's heads
-  const int32_t idx = __popcll(gm & ((1ull << gl) - 1ull));
-  if (head) {
-    ocol[base + idx] = key;
-    oval[base + idx] = sum;
-  }
-  if (live && gl == 0) ucnt[i] = __popcll(gm);
+  if (live && gl == 0) ucnt[i] = before;
 }
 
 // ---- block-level rows (T > 64) -------------------------------------------------------------
@@ -825,15 +839,16 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
   const int32_t *lg[3] = {lists, lists + m, lists + 2 * (int64_t)m};
   const int32_t *l1 = lists + 3 * (int64_t)m, *l2 = lists + 4 * (int64_t)m,
                 *l3 = lists + 5 * (int64_t)m;
+  // two products per lane: 8, 4 and 2 rows per wavefront for the <= 16, <= 32, <= 64 bins
   if (hc[0] > 0)
-    k_esc_group<16><<<(unsigned)ceil_div(hc[0], kWave / 16), kWave, 0, s>>>(
+    k_esc_group<8, 2><<<(unsigned)ceil_div(hc[0], kWave / 8), kWave, 0, s>>>(
         lg[0], hc[0], X.rp, X.col, X.val, Y.rp, Y.col, Y.val, poff, ocol, oval, ucnt);
   if (hc[1] > 0)
-    k_esc_group<32><<<(unsigned)ceil_div(hc[1], kWave / 32), kWave, 0, s>>>(
+    k_esc_group<16, 2><<<(unsigned)ceil_div(hc[1], kWave / 16), kWave, 0, s>>>(
         lg[1], hc[1], X.rp, X.col, X.val, Y.rp, Y.col, Y.val, poff, ocol, oval, ucnt);
   if (hc[2] > 0)
-    k_esc_group<64><<<(unsigned)hc[2], kWave, 0, s>>>(lg[2], hc[2], X.rp, X.col, X.val, Y.rp,
-                                                      Y.col, Y.val, poff, ocol, oval, ucnt);
+    k_esc_group<32, 2><<<(unsigned)ceil_div(hc[2], kWave / 32), kWave, 0, s>>>(
+        lg[2], hc[2], X.rp, X.col, X.val, Y.rp, Y.col, Y.val, poff, ocol, oval, ucnt);
   SA_LAUNCH_CHECK();
   const int32_t n256 = hc[3], n1024 = hc[4], nlong = hc[5];  // wavefront-per-row bins
   int32_t *ovf = nullptr;
