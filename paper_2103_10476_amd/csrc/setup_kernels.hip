@@ -488,14 +488,64 @@ __device__ inline void stamp_ball(const int32_t *__restrict__ gcol, int32_t b, i
   }
 }
 
-// Pass 1 of round r (stamp sr): k1(u) = min key over N[u] for stamped u.
-template <class K, bool WAVE>
+// Pass 1 for one stamped vertex i (thread per vertex): k1(i) = min key over N[i] u {i}; a
+// changed minimum stamps N[i] u {i} for pass 2.
+template <class K>
+__device__ __forceinline__ void mis1_vertex(int32_t i, const int32_t *__restrict__ grp,
+                                            const int32_t *__restrict__ gcol,
+                                            const K *__restrict__ key, K *__restrict__ k1,
+                                            uint8_t *__restrict__ st2, uint8_t sr, bool first) {
+  const int32_t b = grp[i], e = grp[i + 1];
+  K m = key[i];
+  const K old = first ? m : k1[i];
+  // neighbours 8 at a time: all indices, then all keys, as independent loads (i itself
+  // past the end of the list, harmless in the minimum); the first 8 indices are kept for
+  // the stamps
+  int32_t c0[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) c0[q] = i;
+  for (int32_t k = b; k < e; k += 8) {
+    int32_t c[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int32_t g = gcol[min(k + q, e - 1)];  // in bounds even if loaded eagerly
+      c[q] = (k + q < e) ? g : i;
+    }
+    K kv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) kv[q] = key[c[q]];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) m = kv[q] < m ? kv[q] : m;
+    if (k == b) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) c0[q] = c[q];
+    }
+  }
+  if (!first && m != old) {
+    if (e - b <= 8) {
+      st2[i] = sr;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) st2[c0[q]] = sr;
+    } else {
+      stamp_ball(gcol, b, e, i, st2, sr);
+    }
+  }
+  k1[i] = m;
+}
+
+constexpr int kMisV = 4;                // vertices per thread on large levels
+constexpr int64_t kMisVMinN = 524288;   // from this level size on
+
+// Pass 1 of round r (stamp sr): k1(u) = min key over N[u] for stamped u.  V > 1 (thread
+// per vertex only): each thread takes V vertices, for levels with many vertices.
+template <class K, bool WAVE, int V = 1>
 __global__ void k_mis_pass1(int32_t n, const int32_t *__restrict__ grp,
                             const int32_t *__restrict__ gcol, const K *__restrict__ key,
                             K *__restrict__ k1, const uint8_t *__restrict__ st1,
                             uint8_t *__restrict__ st2, uint8_t sr, bool first,
                             const int32_t *__restrict__ prev, int32_t *__restrict__ cur,
                             uint32_t *hstat, uint32_t tag) {
+  static_assert(!(WAVE && V > 1), "a wavefront per vertex takes one vertex");
   // one thread clears this round's flag (pass 2 raises it) and posts the previous round's
   // outcome to the host's status word: tag | 1 if it changed a key, tag | 2 if not
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -529,58 +579,92 @@ __global__ void k_mis_pass1(int32_t n, const int32_t *__restrict__ grp,
       for (int32_t k = b + lane; k < e; k += 64) st2[gcol[k]] = sr;
       if (lane == 0) st2[v] = sr;
     }
-  } else {
+  } else if (V == 1) {
     SA_ROW_KERNEL_BEGIN(n)
     const uint8_t st = st1[i];
     if ((prev && *prev == 0) | (st != sr)) return;
-    const int32_t b = grp[i], e = grp[i + 1];
-    K m = key[i];
-    const K old = first ? m : k1[i];
-    // neighbours 8 at a time: all indices, then all keys, as independent loads (i itself
-    // past the end of the list, harmless in the minimum); the first 8 indices are kept for
-    // the stamps
-    int32_t c0[8];
+    mis1_vertex<K>(i, grp, gcol, key, k1, st2, sr, first);
+  } else {
+    // V vertices per thread at a stride of the grid's thread count (neighbouring vertices,
+    // which tend to be stamped together, stay on different lanes); their stamps and the
+    // previous round's flag are read together
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint8_t st[V];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) c0[q] = i;
-    for (int32_t k = b; k < e; k += 8) {
-      int32_t c[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int32_t g = gcol[min(k + q, e - 1)];  // in bounds even if loaded eagerly
-        c[q] = (k + q < e) ? g : i;
-      }
-      K kv[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) kv[q] = key[c[q]];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) m = kv[q] < m ? kv[q] : m;
-      if (k == b) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) c0[q] = c[q];
-      }
+    for (int j = 0; j < V; ++j) {
+      const int64_t v = t + j * nt;
+      st[j] = v < n ? st1[v] : (uint8_t)(sr + 1);
     }
-    if (!first && m != old) {
-      if (e - b <= 8) {
-        st2[i] = sr;
+    if (prev && *prev == 0) return;
+#pragma unroll 1
+    for (int j = 0; j < V; ++j)
+      if (st[j] == sr) mis1_vertex<K>((int32_t)(t + j * nt), grp, gcol, key, k1, st2, sr, first);
+  }
+}
+
+// Pass 2 for one stamped vertex i (thread per vertex): an undecided i takes m = min k1 over
+// N[i] u {i}; an IN key there makes it OUT, its own key makes it IN.  A change stamps
+// N[i] u {i} with srn and raises the round's flag.
+template <class K>
+__device__ __forceinline__ void mis2_vertex(int32_t i, const int32_t *__restrict__ grp,
+                                            const int32_t *__restrict__ gcol,
+                                            const K *__restrict__ k1, K *__restrict__ key,
+                                            uint8_t *__restrict__ st1, uint8_t srn,
+                                            int32_t *__restrict__ flag) {
+  // the key, the row range and k1 together (the test below uses them all, so none of the
+  // loads waits for the state test)
+  const K me = key[i];
+  K m = k1[i];
+  const int32_t b = grp[i], e = grp[i + 1];
+  if (((me & KeyT<K>::Mask) != KeyT<K>::Und) | (e < b)) return;
+  int32_t c0[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) st2[c0[q]] = sr;
-      } else {
-        stamp_ball(gcol, b, e, i, st2, sr);
-      }
+  for (int q = 0; q < 8; ++q) c0[q] = i;
+  for (int32_t k = b; k < e; k += 8) {
+    int32_t c[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int32_t g = gcol[min(k + q, e - 1)];  // in bounds even if loaded eagerly
+      c[q] = (k + q < e) ? g : i;
     }
-    k1[i] = m;
+    K kv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) kv[q] = k1[c[q]];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) m = kv[q] < m ? kv[q] : m;
+    if (k == b) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) c0[q] = c[q];
+    }
+  }
+  const K pri = me & ~KeyT<K>::Mask;
+  K nk = me;
+  if ((m & KeyT<K>::Mask) == KeyT<K>::In) nk = KeyT<K>::Out | pri;
+  else if (m == me) nk = KeyT<K>::In | pri;
+  if (nk != me) {
+    key[i] = nk;
+    if (e - b <= 8) {
+      st1[i] = srn;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) st1[c0[q]] = srn;
+    } else {
+      stamp_ball(gcol, b, e, i, st1, srn);
+    }
+    *flag = 1;
   }
 }
 
 // Pass 2 of round r: stamped undecided v takes m = min k1 over N[v]; an IN key there makes v
 // OUT, its own key makes it IN.  A change stamps N[v] u {v} with the next round's stamp srn
-// and raises the round's flag.
-template <class K, bool WAVE>
+// and raises the round's flag.  V > 1: V vertices per thread, as in pass 1.
+template <class K, bool WAVE, int V = 1>
 __global__ void k_mis_pass2(int32_t n, const int32_t *__restrict__ grp,
                             const int32_t *__restrict__ gcol, const K *__restrict__ k1,
                             K *__restrict__ key, const uint8_t *__restrict__ st2,
                             uint8_t *__restrict__ st1, uint8_t sr, uint8_t srn,
                             int32_t *__restrict__ flag, const int32_t *__restrict__ prev) {
+  static_assert(!(WAVE && V > 1), "a wavefront per vertex takes one vertex");
   if (WAVE) {
     const int lane = threadIdx.x & 63;
     const int64_t v64 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -612,51 +696,25 @@ __global__ void k_mis_pass2(int32_t n, const int32_t *__restrict__ grp,
         *flag = 1;
       }
     }
-  } else {
+  } else if (V == 1) {
     SA_ROW_KERNEL_BEGIN(n)
     const uint8_t st = st2[i];
     if ((prev && *prev == 0) | (st != sr)) return;
-    // the key, the row range and k1 together (the test below uses them all, so none of the
-    // loads waits for the state test)
-    const K me = key[i];
-    K m = k1[i];
-    const int32_t b = grp[i], e = grp[i + 1];
-    if (((me & KeyT<K>::Mask) != KeyT<K>::Und) | (e < b)) return;
-    int32_t c0[8];
+    mis2_vertex<K>(i, grp, gcol, k1, key, st1, srn, flag);
+  } else {
+    // V vertices per thread at a stride of the grid's thread count, as in pass 1
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint8_t st[V];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) c0[q] = i;
-    for (int32_t k = b; k < e; k += 8) {
-      int32_t c[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int32_t g = gcol[min(k + q, e - 1)];  // in bounds even if loaded eagerly
-        c[q] = (k + q < e) ? g : i;
-      }
-      K kv[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) kv[q] = k1[c[q]];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) m = kv[q] < m ? kv[q] : m;
-      if (k == b) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) c0[q] = c[q];
-      }
+    for (int j = 0; j < V; ++j) {
+      const int64_t v = t + j * nt;
+      st[j] = v < n ? st2[v] : (uint8_t)(sr + 1);
     }
-    const K pri = me & ~KeyT<K>::Mask;
-    K nk = me;
-    if ((m & KeyT<K>::Mask) == KeyT<K>::In) nk = KeyT<K>::Out | pri;
-    else if (m == me) nk = KeyT<K>::In | pri;
-    if (nk != me) {
-      key[i] = nk;
-      if (e - b <= 8) {
-        st1[i] = srn;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) st1[c0[q]] = srn;
-      } else {
-        stamp_ball(gcol, b, e, i, st1, srn);
-      }
-      *flag = 1;
-    }
+    if (prev && *prev == 0) return;
+#pragma unroll 1
+    for (int j = 0; j < V; ++j)
+      if (st[j] == sr) mis2_vertex<K>((int32_t)(t + j * nt), grp, gcol, k1, key, st1, srn, flag);
   }
 }
 
@@ -967,6 +1025,12 @@ static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const
   const int32_t maxdeg = max_row_length(n, grp, s);
   const bool wave = maxdeg > 64 || nnzG > 24 * (int64_t)n;
   const unsigned g = wave ? grid_for((int64_t)n * 64) : grid_for(n);
+  // large thread-per-vertex levels: kMisV vertices per thread (grid gv), fewer workgroups to
+  // dispatch per pass; SAAMG_MIS_V_MIN_N overrides the level size from which they are used
+  int64_t v_min_n = kMisVMinN;
+  if (const char *e = std::getenv("SAAMG_MIS_V_MIN_N")) v_min_n = std::atoll(e);
+  const unsigned gv =
+      (!wave && n >= v_min_n) ? (unsigned)ceil_div(n, (int64_t)kBlock * kMisV) : 0u;
   auto launch_round = [&](int64_t r) {
     const uint8_t sr = (uint8_t)(r & 255), srn = (uint8_t)((r + 1) & 255);
     const bool first = r == 0;
@@ -979,6 +1043,11 @@ static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const
                                                  prev, cur, post, tag);
       k_mis_pass2<K, true><<<g, kBlock, 0, s>>>(n, grp, gcol, k1, key, st2, st1, sr, srn, cur,
                                                  prev);
+    } else if (gv > 0) {
+      k_mis_pass1<K, false, kMisV><<<gv, kBlock, 0, s>>>(n, grp, gcol, key, k1, st1, st2, sr,
+                                                         first, prev, cur, post, tag);
+      k_mis_pass2<K, false, kMisV><<<gv, kBlock, 0, s>>>(n, grp, gcol, k1, key, st2, st1, sr,
+                                                         srn, cur, prev);
     } else {
       k_mis_pass1<K, false><<<g, kBlock, 0, s>>>(n, grp, gcol, key, k1, st1, st2, sr, first,
                                                   prev, cur, post, tag);

@@ -4,9 +4,10 @@ On the grid, rounds are launched back to back and the host learns where the sele
 from status words that the first pass of each round writes into pinned host memory; when a
 word does not arrive in time, the host synchronises and reads the device flags instead
 (SAAMG_STATUS_SPIN_NS=0 takes that fallback at every wait).  Levels up to
-SAAMG_MIS_WG_MAX_N vertices run every round after the first in one workgroup instead.  All
-three are compared with the oracle (aggregates, roots and every setup array bitwise) and with
-each other (rounds per level), on the 64 x 64 stretched 5-point grid, a 24^3 stretched
+SAAMG_MIS_WG_MAX_N vertices run every round after the first in one workgroup instead, and
+grid levels from SAAMG_MIS_V_MIN_N vertices on give each thread 4 vertices.  All four are
+compared with the oracle (aggregates, roots and every setup array bitwise) and with each
+other (rounds per level), on the 64 x 64 stretched 5-point grid, a 24^3 stretched
 7-point cube, a 14^3 random-coefficient 27-point cube and, in hashed order, a 20^3 cube.
 """
 import os
@@ -37,11 +38,12 @@ CASES = [
                                                 seed=31)),
 ]
 
-ENV = ("SAAMG_MIS_WG_MAX_N", "SAAMG_STATUS_SPIN_NS")
+ENV = ("SAAMG_MIS_WG_MAX_N", "SAAMG_STATUS_SPIN_NS", "SAAMG_MIS_V_MIN_N")
 MODES = {  # values for ENV (None: unset)
-    "grid, status ring": ("0", None),
-    "grid, device flags": ("0", "0"),
-    "one workgroup": ("1073741824", None),
+    "grid, status ring": ("0", None, None),
+    "grid, device flags": ("0", "0", None),
+    "one workgroup": ("1073741824", None, None),
+    "grid, 4 vertices per thread": ("0", None, "0"),
 }
 
 
