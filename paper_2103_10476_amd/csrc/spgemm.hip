@@ -580,20 +580,35 @@ __global__ __launch_bounds__(64) void k_esc_wave(
     s_ys[lane] = ys;
     s_a[lane] = a;
     __syncthreads();
-    for (int32_t p0 = 0; p0 < tot; p0 += 64) {
-      const int32_t p = p0 + lane;
-      uint64_t key = ~0ull;
-      double v = 0.0;
+    // product p of the chunk: the first staged entry g with s_incl[g] > p, at offset
+    // p - s_incl[g-1] in its row of Y.  The next step's entry is loaded before this step is
+    // sorted and added, so its latency overlaps them (the product is formed when it is used).
+    int32_t jn = -1;
+    double yn = 0.0, an = 0.0;
+    auto fetch = [&](int32_t p) {
+      jn = -1;
       if (p < tot) {
-        int32_t l0 = 0, h0 = cnt - 1;  // first staged entry g with s_incl[g] > p
+        int32_t l0 = 0, h0 = cnt - 1;
         while (l0 < h0) {
           const int32_t mid = (l0 + h0) >> 1;
           if (s_incl[mid] > p) h0 = mid;
           else l0 = mid + 1;
         }
         const int32_t q = s_ys[l0] + p - (l0 > 0 ? s_incl[l0 - 1] : 0);
-        const int32_t j = ycol[q];
-        v = s_a[l0] * yval[q];
+        jn = ycol[q];
+        yn = yval[q];
+        an = s_a[l0];
+      }
+    };
+    fetch(lane);
+    for (int32_t p0 = 0; p0 < tot; p0 += 64) {
+      const int32_t j = jn;
+      const double y = yn, a = an;
+      fetch(p0 + 64 + lane);
+      uint64_t key = ~0ull;
+      double v = 0.0;
+      if (j >= 0) {
+        v = a * y;
         key = ((uint64_t)(uint32_t)j << 6) | (uint32_t)lane;
       }
       key = wave_sort_u64(key, lane);
