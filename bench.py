@@ -312,11 +312,12 @@ def summarise_legs(legs):
                                      for k in ("plain", "offlmp", "1norm", "offlmp+1norm")
                                      if k in t}
             sc = mf["stretched_cube"][w]
-            fam[f"stretched_{w}"] = {"plain_failures": sc["plain_failures"],
-                                     "more_iterations_than_plain": {
-                                         k: (v["plain_minus_it"] or {}).get("more_than_plain")
-                                         for k, v in sc["vs_plain"].items()}}
-        fam["fields"] = "perturbed: [mean iterations, failures] per variant"
+            fam[f"stretched_{w}"] = [sc["plain_failures"]] + [
+                (sc["vs_plain"][k]["plain_minus_it"] or {}).get("more_than_plain")
+                for k in ("1norm", "offlmp", "cnstrnt", "sprsfy") if k in sc["vs_plain"]]
+        fam["fields"] = ("perturbed: [mean iterations, failures]; stretched: [plain failures, "
+                         "problems with more iterations than plain: 1norm, offlmp, cnstrnt, "
+                         "sprsfy]")
         out["mesh_families"] = fam
     if "gmres" in legs:
         out["gmres"] = {k: [v.get("steps", v.get("gmres_steps")),
@@ -411,7 +412,7 @@ def roofline(tot, workload=WORKLOAD, dtype="f64", note=None):
     out = {"bound": "hbm",
            "kernel": ("k_spmv_sell<double>" if dtype == "f64" else
                       "k_spmv_sell<float> (V-cycle) and <double> (CG)") +
-                     " on the fine-level operator: sliced ELL, all fused epilogues",
+                     ", fine level, sliced ELL, fused epilogues",
            "input": workload,
            "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(workload, dtype),
@@ -471,9 +472,8 @@ def c4_leg(solver, problems, workload, reps=5):
         dt = "f64" if prec == "fp64" else "f32"
         out[f"roofline_{prec}"] = roofline(
             h.profile_read(), workload, dt,
-            note=f"160^3 fine operator in {dt}: {'424' if dt == 'f64' else '277'} MB per "
-                 "launch for the matrix and x alone (more with the epilogue's vectors), more "
-                 "than the 256 MB Infinity Cache holds")
+            note=f"matrix and x alone {'424' if dt == 'f64' else '277'} MB per launch, "
+                 "over the 256 MB Infinity Cache")
         h.close()
         xs[prec] = x.clone()
         xh = x.cpu().numpy()
