@@ -30,18 +30,50 @@ namespace sa {
 constexpr int kWave = 64;
 constexpr int kChunk = 1024;  // products per block-level chunk
 
-__global__ void k_count_products(int32_t m, const int32_t *xrp, const int32_t *xcol,
-                                 const int32_t *yrp, int64_t *cnt, int32_t *xpref) {
+// Bins by product count: <= 16, <= 32, <= 64 (rows sharing wavefronts), <= 256, <= 1024
+// (block per row, one chunk), longer.
+constexpr int kBins = 6;
+__device__ __forceinline__ int bin_of(int64_t T) {
+  return T <= 16 ? 0 : T <= 32 ? 1 : T <= kWave ? 2 : T <= 256 ? 3 : T <= kChunk ? 4 : 5;
+}
+
+// A block lists its rows per bin: counted in LDS, each non-empty bin's share reserved with one
+// global atomic (the order inside a list is immaterial: rows are independent).
+__device__ __forceinline__ void bin_row(bool live, int32_t i, int64_t T, int32_t m,
+                                        int32_t *lists, int32_t *counters) {
+  __shared__ int32_t s_cnt[kBins], s_base[kBins];
+  if (threadIdx.x < kBins) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int bin = bin_of(T);
+  int32_t local = 0;
+  if (live) local = atomicAdd(&s_cnt[bin], 1);
+  __syncthreads();
+  if (threadIdx.x < kBins && s_cnt[threadIdx.x] > 0)
+    s_base[threadIdx.x] = atomicAdd(&counters[threadIdx.x], s_cnt[threadIdx.x]);
+  __syncthreads();
+  if (live) lists[(int64_t)bin * m + s_base[bin] + local] = i;
+}
+
+// Thread per row of X: the row's product count T, the products before each of its entries
+// (xpref), and the row's place in its bin's list.
+__global__ __launch_bounds__(kBlock) void k_count_products(int32_t m, const int32_t *xrp,
+                                                           const int32_t *xcol,
+                                                           const int32_t *yrp, int64_t *cnt,
+                                                           int32_t *xpref, int32_t *lists,
+                                                           int32_t *counters) {
   const int64_t i64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i64 >= m) return;
-  const int32_t i = (int32_t)i64;
+  const bool live = i64 < m;
+  const int32_t i = live ? (int32_t)i64 : 0;
   int64_t t = 0;
-  for (int32_t e = xrp[i]; e < xrp[i + 1]; ++e) {
-    xpref[e] = (int32_t)t;  // products before entry e within the row (T < 2^31 checked)
-    const int32_t k = xcol[e];
-    t += yrp[k + 1] - yrp[k];
+  if (live) {
+    for (int32_t e = xrp[i]; e < xrp[i + 1]; ++e) {
+      xpref[e] = (int32_t)t;  // products before entry e within the row (T < 2^31 checked)
+      const int32_t k = xcol[e];
+      t += yrp[k + 1] - yrp[k];
+    }
+    cnt[i] = t;
   }
-  cnt[i] = t;
+  bin_row(live, i, t, m, lists, counters);  // every thread passes the barriers
 }
 
 // One wavefront per row of X (long rows): xpref by a wavefront prefix sum.
@@ -797,27 +829,13 @@ __global__ void k_compact(int32_t m, int64_t nnz, const int64_t *poff, const int
   cval[e] = oval[src];
 }
 
-// Bins by product count: <= 16, <= 32, <= 64 (rows sharing wavefronts), <= 256, <= 1024
-// (block per row, one chunk), longer.
-constexpr int kBins = 6;
-// A block counts its rows per bin in LDS and reserves each non-empty bin's share with one
-// global atomic (the order inside a list is immaterial: rows are independent).
-__global__ void k_bin_rows(int32_t m, const int64_t *poff, int32_t *lists, int32_t *counters) {
-  __shared__ int32_t s_cnt[kBins], s_base[kBins];
-  if (threadIdx.x < kBins) s_cnt[threadIdx.x] = 0;
-  __syncthreads();
+// Bins the rows counted by k_count_products_w (one block per row there).
+__global__ __launch_bounds__(kBlock) void k_bin_rows(int32_t m, const int64_t *poff,
+                                                     int32_t *lists, int32_t *counters) {
   const int64_t i64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i64 < m;
   const int32_t i = live ? (int32_t)i64 : 0;
-  const int64_t T = live ? poff[i + 1] - poff[i] : 0;
-  const int bin = T <= 16 ? 0 : T <= 32 ? 1 : T <= kWave ? 2 : T <= 256 ? 3 : T <= kChunk ? 4 : 5;
-  int32_t local = 0;
-  if (live) local = atomicAdd(&s_cnt[bin], 1);
-  __syncthreads();
-  if (threadIdx.x < kBins && s_cnt[threadIdx.x] > 0)
-    s_base[threadIdx.x] = atomicAdd(&counters[threadIdx.x], s_cnt[threadIdx.x]);
-  __syncthreads();
-  if (live) lists[(int64_t)bin * m + s_base[bin] + local] = i;
+  bin_row(live, i, live ? poff[i + 1] - poff[i] : 0, m, lists, counters);
 }
 
 void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
@@ -830,25 +848,28 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
   int64_t *cnt = tmp.alloc<int64_t>(m + 1);
   int32_t *xpref = tmp.alloc<int32_t>(X.nnz > 0 ? X.nnz : 1);
   int64_t *poff = tmp.alloc<int64_t>(m + 1);
-  if (m > 0) {
-    if ((X.maxrow >= 0 ? X.maxrow : max_row_length(m, X.rp, s)) > 64)
-      k_count_products_w<<<(unsigned)m, 64, 0, s>>>(m, X.rp, X.col, Y.rp, cnt, xpref);
-    else
-      k_count_products<<<grid_for(m), kBlock, 0, s>>>(m, X.rp, X.col, Y.rp, cnt, xpref);
+  int32_t *lists = tmp.alloc<int32_t>(kBins * (int64_t)(m > 0 ? m : 1));
+  int32_t *counters = tmp.alloc<int32_t>(8);  // kBins bin sizes, then the overflow count
+  fill_i32(counters, 0, 8, s);
+  // rows of up to 64 entries: a thread per row, which also bins the row; longer: a
+  // wavefront per row, binned after the scan
+  const bool wave_count =
+      m > 0 && (X.maxrow >= 0 ? X.maxrow : max_row_length(m, X.rp, s)) > 64;
+  if (wave_count)
+    k_count_products_w<<<(unsigned)m, 64, 0, s>>>(m, X.rp, X.col, Y.rp, cnt, xpref);
+  else if (m > 0)
+    k_count_products<<<grid_for(m), kBlock, 0, s>>>(m, X.rp, X.col, Y.rp, cnt, xpref, lists,
+                                                    counters);
+  SA_LAUNCH_CHECK();
+  exclusive_scan_i64(cnt, poff, m, s);
+  if (wave_count) {
+    k_bin_rows<<<grid_for(m), kBlock, 0, s>>>(m, poff, lists, counters);
     SA_LAUNCH_CHECK();
   }
-  exclusive_scan_i64(cnt, poff, m, s);
   const int64_t total = read1(poff + m, s);
   int32_t *ocol = tmp.alloc<int32_t>(total > 0 ? total : 1);
   double *oval = tmp.alloc<double>(total > 0 ? total : 1);
   int32_t *ucnt = tmp.alloc<int32_t>(m + 1);
-  int32_t *lists = tmp.alloc<int32_t>(kBins * (int64_t)(m > 0 ? m : 1));
-  int32_t *counters = tmp.alloc<int32_t>(8);  // kBins bin sizes, then the overflow count
-  fill_i32(counters, 0, 8, s);
-  if (m > 0) {
-    k_bin_rows<<<grid_for(m), kBlock, 0, s>>>(m, poff, lists, counters);
-    SA_LAUNCH_CHECK();
-  }
   int32_t hc[8];
   readback(hc, counters, sizeof(hc), s);
   const int32_t *lg[3] = {lists, lists + m, lists + 2 * (int64_t)m};
