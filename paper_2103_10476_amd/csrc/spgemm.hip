@@ -20,6 +20,7 @@
 // Results go to per-row slots at the row's product offset (room for T >= distinct entries)
 // and are compacted into CSR afterwards.
 #include <algorithm>
+#include <cstring>
 
 #include <mutex>
 
@@ -829,6 +830,8 @@ __global__ void k_compact(int32_t m, int64_t nnz, const int64_t *poff, const int
   cval[e] = oval[src];
 }
 
+__global__ void k_put_total(const int64_t *src, int64_t *dst) { *dst = *src; }
+
 // Bins the rows counted by k_count_products_w (one block per row there).
 __global__ __launch_bounds__(kBlock) void k_bin_rows(int32_t m, const int64_t *poff,
                                                      int32_t *lists, int32_t *counters) {
@@ -849,7 +852,9 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
   int32_t *xpref = tmp.alloc<int32_t>(X.nnz > 0 ? X.nnz : 1);
   int64_t *poff = tmp.alloc<int64_t>(m + 1);
   int32_t *lists = tmp.alloc<int32_t>(kBins * (int64_t)(m > 0 ? m : 1));
-  int32_t *counters = tmp.alloc<int32_t>(8);  // kBins bin sizes, then the overflow count
+  // kBins bin sizes, the overflow count, the widest row window, then the product total (64
+  // bits)
+  int32_t *counters = tmp.alloc<int32_t>(10);
   fill_i32(counters, 0, 8, s);
   // rows of up to 64 entries: a thread per row, which also bins the row; longer: a
   // wavefront per row, binned after the scan
@@ -866,12 +871,16 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
     k_bin_rows<<<grid_for(m), kBlock, 0, s>>>(m, poff, lists, counters);
     SA_LAUNCH_CHECK();
   }
-  const int64_t total = read1(poff + m, s);
+  // the bin sizes and the product total in one readback
+  k_put_total<<<1, 1, 0, s>>>(poff + m, (int64_t *)(counters + 8));
+  SA_LAUNCH_CHECK();
+  int32_t hc[10];
+  readback(hc, counters, sizeof(hc), s);
+  int64_t total = 0;
+  std::memcpy(&total, hc + 8, sizeof(total));
   int32_t *ocol = tmp.alloc<int32_t>(total > 0 ? total : 1);
   double *oval = tmp.alloc<double>(total > 0 ? total : 1);
   int32_t *ucnt = tmp.alloc<int32_t>(m + 1);
-  int32_t hc[8];
-  readback(hc, counters, sizeof(hc), s);
   const int32_t *lg[3] = {lists, lists + m, lists + 2 * (int64_t)m};
   const int32_t *l1 = lists + 3 * (int64_t)m, *l2 = lists + 4 * (int64_t)m,
                 *l3 = lists + 5 * (int64_t)m;
