@@ -20,6 +20,7 @@
 // Results go to per-row slots at the row's product offset (room for T >= distinct entries)
 // and are compacted into CSR afterwards.
 #include <algorithm>
+#include <climits>
 #include <cstring>
 
 #include <mutex>
@@ -294,14 +295,15 @@ template <int BS>
 __global__ __launch_bounds__(BS) void k_esc_single(
     const int32_t *rows, int32_t nrows, const int32_t *xrp, const int32_t *xcol,
     const double *xval, const int32_t *xpref, const int32_t *yrp, const int32_t *ycol,
-    const double *yval, const int64_t *poff, int32_t *ocol, double *oval, int32_t *ucnt) {
+    const double *yval, const int64_t *poff, int32_t *ocol, double *oval, int32_t *ucnt,
+    const int32_t *dcount) {
   constexpr int CH = 4 * BS;
   __shared__ uint64_t sk[CH];
   __shared__ double sv[CH];
   __shared__ int32_t s_scan[BS];
   const int tid = threadIdx.x;
   const int32_t slot = blockIdx.x;
-  if (slot >= nrows) return;
+  if (slot >= (dcount ? *dcount : nrows)) return;  // block-uniform
   const int32_t i = rows[slot];
   const int64_t base = poff[i];
   const int32_t L = (int32_t)(poff[i + 1] - base);
@@ -517,6 +519,124 @@ __global__ __launch_bounds__(64) void k_esc_lds(const int32_t *rows, int32_t nro
   if (lane == 0) ucnt[i] = w;
 }
 
+// ---- rank accumulator (257..1024 products, narrow output rows) -----------------------------
+// One wavefront per row.  The row's products are staged in LDS at their Gustavson positions
+// (X entry by X entry, each its Y row's columns and X_ik Y_kj), the distinct columns marked in
+// a bitmap over the row's column window, and each X entry's products then added, in X order,
+// into an accumulator indexed by the column's rank among the row's distinct columns: the
+// columns of one Y row are distinct, so the adds of one X entry never collide, and the X
+// entries follow each other in the wavefront's program order, so every output entry receives
+// its products in ascending k, from 0, as in the sort-based bins.  Rows outside the stage's
+// limits are listed in rov for the sort-based kernel of their bin.
+constexpr int32_t kRankT = 1024;    // products
+constexpr int32_t kRankX = 64;      // X entries (the adds take one step per X entry)
+constexpr int32_t kRankW = 65536;   // column window
+constexpr int32_t kRankD = 256;     // distinct columns
+__global__ __launch_bounds__(64) void k_esc_rank(const int32_t *rows, int32_t nrows,
+                                                 const int32_t *xrp, const int32_t *xcol,
+                                                 const double *xval, const int32_t *xpref,
+                                                 const int32_t *yrp, const int32_t *ycol,
+                                                 const double *yval, const int64_t *poff,
+                                                 int32_t *ocol, double *oval, int32_t *ucnt,
+                                                 int32_t *rov, int32_t *nrov) {
+  __shared__ int32_t s_c[kRankT];       // staged columns, then their ranks
+  __shared__ double s_v[kRankT];        // staged products
+  __shared__ uint32_t s_bits[kRankW / 32];
+  __shared__ uint16_t s_pre[kRankW / 32];  // set bits in the words before
+  __shared__ double s_acc[kRankD];
+  __shared__ int32_t s_xo[kRankX + 1];  // X entries' first positions, then T
+  const int lane = threadIdx.x;
+  const int32_t slot = blockIdx.x;
+  if (slot >= nrows) return;  // block-uniform
+  const int32_t i = rows[slot];
+  const int64_t base = poff[i];
+  const int32_t T = (int32_t)(poff[i + 1] - base);
+  const int32_t xb = xrp[i], nx = xrp[i + 1] - xb;
+  auto overflow = [&]() {
+    if (lane == 0) rov[atomicAdd(nrov, 1)] = i;
+  };
+  if (nx > kRankX || T > kRankT || T == 0) {  // wavefront-uniform
+    overflow();
+    return;
+  }
+  // stage: lane l takes X entries l, l+64, ...
+  int32_t lo = INT_MAX, hi = -1;
+  for (int32_t e = lane; e < nx; e += 64) {
+    const int32_t k = xcol[xb + e];
+    const double xv = xval[xb + e];
+    const int32_t o = xpref[xb + e];
+    const int32_t yb = yrp[k], ye = yrp[k + 1];
+    s_xo[e] = o;
+    for (int32_t q = yb; q < ye; ++q) {
+      const int32_t c = ycol[q];
+      s_c[o + q - yb] = c;
+      s_v[o + q - yb] = xv * yval[q];
+      lo = min(lo, c);
+      hi = max(hi, c);
+    }
+  }
+  if (lane == 0) s_xo[nx] = T;
+  for (int off = 32; off >= 1; off >>= 1) {
+    lo = min(lo, __shfl_xor(lo, off, 64));
+    hi = max(hi, __shfl_xor(hi, off, 64));
+  }
+  const int32_t W = hi - lo + 1;
+  if (W > kRankW) {  // wavefront-uniform; nothing written to global memory yet
+    overflow();
+    return;
+  }
+  const int32_t nw = (W + 31) >> 5;
+  for (int32_t w = lane; w < nw; w += 64) s_bits[w] = 0u;
+  __syncthreads();
+  for (int32_t p = lane; p < T; p += 64) {
+    const int32_t c = s_c[p] - lo;
+    atomicOr(&s_bits[c >> 5], 1u << (c & 31));
+  }
+  __syncthreads();
+  // popcount prefix over the words: lane l takes a contiguous run of them
+  const int32_t wl = (nw + 63) >> 6;
+  const int32_t w0 = min(nw, lane * wl), w1 = min(nw, w0 + wl);
+  int32_t cnt = 0;
+  for (int32_t w = w0; w < w1; ++w) cnt += __popc(s_bits[w]);
+  int32_t incl = cnt;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
+  }
+  const int32_t D = __shfl(incl, 63, 64);
+  if (D > kRankD) {  // wavefront-uniform
+    overflow();
+    return;
+  }
+  int32_t run = incl - cnt;
+  for (int32_t w = w0; w < w1; ++w) {
+    s_pre[w] = (uint16_t)run;
+    run += __popc(s_bits[w]);
+  }
+  for (int32_t r = lane; r < D; r += 64) s_acc[r] = 0.0;
+  __syncthreads();
+  // ranks (each position's own lane reads and overwrites it); the columns go out at theirs
+  for (int32_t p = lane; p < T; p += 64) {
+    const int32_t c = s_c[p] - lo;
+    const int32_t w = c >> 5;
+    const int32_t r = (int32_t)s_pre[w] + __popc(s_bits[w] & ((1u << (c & 31)) - 1u));
+    s_c[p] = r;
+    ocol[base + r] = c + lo;  // every position of a column writes the same value
+  }
+  __syncthreads();
+  // the X entries in order; within one, each lane adds its product to its column's sum
+  for (int32_t e = 0; e < nx; ++e) {
+    const int32_t o0 = s_xo[e], o1 = s_xo[e + 1];
+    for (int32_t j = o0 + lane; j < o1; j += 64) {
+      const int32_t r = s_c[j];
+      s_acc[r] = s_acc[r] + s_v[j];
+    }
+  }
+  __syncthreads();
+  for (int32_t r = lane; r < D; r += 64) oval[base + r] = s_acc[r];
+  if (lane == 0) ucnt[i] = D;
+}
+
 // ---- wavefront-per-row bins (T > 64) ------------------------------------------------------
 // One wavefront (a 64-thread block) per row.  The row's products are taken 64 at a time in
 // Gustavson order: its X entries are staged 64 at a time with a wave scan of their Y-row
@@ -556,14 +676,14 @@ __global__ __launch_bounds__(64) void k_esc_wave(
     const int32_t *rows, int32_t nrows, const int32_t *xrp, const int32_t *xcol,
     const double *xval, const int32_t *yrp, const int32_t *ycol, const double *yval,
     int32_t width, const int2 *win, const int64_t *poff, int32_t *ocol, double *oval,
-    int32_t *ucnt, int32_t *ovf, int32_t *novf) {
+    int32_t *ucnt, int32_t *ovf, int32_t *novf, const int32_t *dcount) {
   extern __shared__ double lds_dyn[];
   __shared__ int32_t s_incl[64], s_ys[64], s_col[64];
   __shared__ double s_a[64], s_v[64];
   __shared__ int32_t s_cnt;
   const int lane = threadIdx.x;
   const int32_t slot = blockIdx.x;
-  if (slot >= nrows) return;  // block-uniform
+  if (slot >= (dcount ? *dcount : nrows)) return;  // block-uniform
   const int32_t i = rows[slot];
   const int64_t base = poff[i];
   // DENSE: acc[width] then the bitmap; HASH: hv[H], hk[H], then the sort keys (H/2)
@@ -899,17 +1019,32 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
   int32_t *ovf = nullptr;
   if (n256 > 0 || n1024 > 0 || nlong > 0) ovf = tmp.alloc<int32_t>(n256 + n1024 + nlong);
   // T <= 256: the wavefront kernel with a 512-slot hash table (at least 2T slots: it never
-  // overflows); T <= 1024: one block per row, the whole row sorted in LDS
+  // overflows); T <= 1024: one block per row, the whole row sorted in LDS.  With Y rows of 8
+  // entries or more on average (R (AP)), the rank-accumulator kernel takes the rows of the
+  // second bin first and leaves those outside its limits to the block sort (their count read
+  // on the device).
+  const bool rank = Y.nnz >= 8 * (int64_t)Y.n && n1024 > 0;
+  const int32_t *r1024 = l2, *c1024 = nullptr;
+  if (rank) {
+    int32_t *rov = tmp.alloc<int32_t>(n1024);
+    int32_t *rc = tmp.alloc<int32_t>(1);
+    fill_i32(rc, 0, 1, s);
+    k_esc_rank<<<(unsigned)n1024, 64, 0, s>>>(l2, n1024, X.rp, X.col, X.val, xpref, Y.rp, Y.col,
+                                              Y.val, poff, ocol, oval, ucnt, rov, rc);
+    SA_LAUNCH_CHECK();
+    r1024 = rov;
+    c1024 = rc;
+  }
   if (n256 > 0) {
     k_esc_wave<false, 512><<<(unsigned)n256, 64, 16 * 512, s>>>(
         l1, n256, X.rp, X.col, X.val, Y.rp, Y.col, Y.val, 0, nullptr, poff, ocol, oval, ucnt,
-        ovf, counters + kBins);
+        ovf, counters + kBins, nullptr);
     SA_LAUNCH_CHECK();
   }
   if (n1024 > 0) {
-    k_esc_single<256><<<(unsigned)n1024, 256, 0, s>>>(l2, n1024, X.rp, X.col, X.val, xpref,
+    k_esc_single<256><<<(unsigned)n1024, 256, 0, s>>>(r1024, n1024, X.rp, X.col, X.val, xpref,
                                                       Y.rp, Y.col, Y.val, poff, ocol, oval,
-                                                      ucnt);
+                                                      ucnt, c1024);
     SA_LAUNCH_CHECK();
   }
   // long rows: the dense window accumulator when Y's width fits the LDS (sized to the widest
@@ -938,12 +1073,13 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
     else
       k_esc_wave<true, 1><<<(unsigned)nlong, 64, lds, s>>>(l3, nlong, X.rp, X.col, X.val, Y.rp,
                                                            Y.col, Y.val, wl, win, poff, ocol,
-                                                           oval, ucnt, ovf, counters + kBins);
+                                                           oval, ucnt, ovf, counters + kBins,
+                                                           nullptr);
     SA_LAUNCH_CHECK();
   } else if (nlong > 0) {
     k_esc_wave<false, 2048><<<(unsigned)nlong, 64, 16 * 2048, s>>>(
         l3, nlong, X.rp, X.col, X.val, Y.rp, Y.col, Y.val, 0, nullptr, poff, ocol, oval, ucnt,
-        ovf, counters + kBins);
+        ovf, counters + kBins, nullptr);
     SA_LAUNCH_CHECK();
     const int32_t nov = read1(counters + kBins, s);
     if (nov > 0) {
