@@ -57,25 +57,39 @@ __device__ __forceinline__ void bin_row(bool live, int32_t i, int64_t T, int32_t
 }
 
 // Thread per row of X: the row's product count T, the products before each of its entries
-// (xpref), and the row's place in its bin's list.
+// (xpref), and the row's place in its bin's list.  The block's prefixes are gathered in LDS
+// and written out as one contiguous run (a thread's own entries are a short strided run, whose
+// partial-line writes cost several times their bytes), unless the block's X entries exceed
+// the buffer.
+constexpr int32_t kCountLds = 4096;
 __global__ __launch_bounds__(kBlock) void k_count_products(int32_t m, const int32_t *xrp,
                                                            const int32_t *xcol,
                                                            const int32_t *yrp, int64_t *cnt,
                                                            int32_t *xpref, int32_t *lists,
                                                            int32_t *counters) {
-  const int64_t i64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ int32_t s_xp[kCountLds];
+  const int64_t r0 = (int64_t)blockIdx.x * blockDim.x;
+  const int32_t e0 = xrp[r0], e1 = xrp[min((int64_t)m, r0 + blockDim.x)];
+  const bool staged = e1 - e0 <= kCountLds;  // block-uniform
+  const int64_t i64 = r0 + threadIdx.x;
   const bool live = i64 < m;
   const int32_t i = live ? (int32_t)i64 : 0;
   int64_t t = 0;
   if (live) {
     for (int32_t e = xrp[i]; e < xrp[i + 1]; ++e) {
-      xpref[e] = (int32_t)t;  // products before entry e within the row (T < 2^31 checked)
+      // products before entry e within the row (T < 2^31 checked)
+      if (staged) s_xp[e - e0] = (int32_t)t;
+      else xpref[e] = (int32_t)t;
       const int32_t k = xcol[e];
       t += yrp[k + 1] - yrp[k];
     }
     cnt[i] = t;
   }
   bin_row(live, i, t, m, lists, counters);  // every thread passes the barriers
+  if (staged) {
+    __syncthreads();
+    for (int32_t q = threadIdx.x; q < e1 - e0; q += blockDim.x) xpref[e0 + q] = s_xp[q];
+  }
 }
 
 // One wavefront per row of X (long rows): xpref by a wavefront prefix sum.
