@@ -962,25 +962,58 @@ __global__ void k_agg_phase1(int32_t n, const int32_t *grp, const int32_t *gcol,
   is_root[i] = root ? 1 : 0;
 }
 // Leftover vertices join the phase-1 aggregate with the most strong connections to them,
-// ties to the smaller aggregate number.
+// ties to the smaller aggregate number (a total order on the candidates: the choice does not
+// depend on the order they are looked at in).
+// Rows of up to R entries: the neighbours' phase-1 aggregates are loaded once, in one batch
+// (-1 past the end of the row), and counted in registers.
+template <int R>
+__device__ __forceinline__ int32_t agg_join_regs(int32_t b, int32_t e,
+                                                 const int32_t *__restrict__ gcol,
+                                                 const int32_t *__restrict__ agg1) {
+  int32_t g[R], c[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) g[q] = gcol[min(b + q, e - 1)];
+#pragma unroll
+  for (int q = 0; q < R; ++q) c[q] = (b + q < e) ? agg1[g[q]] : -1;
+  int32_t best = -1, bestc = 0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (c[k] < 0) continue;
+    int32_t cnt = 0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) cnt += (c[q] == c[k]);
+    if (cnt > bestc || (cnt == bestc && c[k] < best)) {
+      best = c[k];
+      bestc = cnt;
+    }
+  }
+  return best;
+}
+
 __global__ void k_agg_phase2(int32_t n, const int32_t *grp, const int32_t *gcol,
                              const int32_t *agg1, int32_t *agg) {
   SA_ROW_KERNEL_BEGIN(n)
   int32_t a = agg1[i];
   const int32_t b = grp[i], e = grp[i + 1];
   if (a < 0 && e > b) {
-    int32_t best = -1, bestc = 0;
-    for (int32_t k = b; k < e; ++k) {
-      const int32_t c = agg1[gcol[k]];
-      if (c < 0) continue;
-      int32_t cnt = 0;
-      for (int32_t q = b; q < e; ++q) cnt += (agg1[gcol[q]] == c);
-      if (cnt > bestc || (cnt == bestc && c < best)) {
-        best = c;
-        bestc = cnt;
+    if (e - b <= 8) {
+      a = agg_join_regs<8>(b, e, gcol, agg1);
+    } else if (e - b <= 32) {
+      a = agg_join_regs<32>(b, e, gcol, agg1);
+    } else {
+      int32_t best = -1, bestc = 0;
+      for (int32_t k = b; k < e; ++k) {
+        const int32_t c = agg1[gcol[k]];
+        if (c < 0) continue;
+        int32_t cnt = 0;
+        for (int32_t q = b; q < e; ++q) cnt += (agg1[gcol[q]] == c);
+        if (cnt > bestc || (cnt == bestc && c < best)) {
+          best = c;
+          bestc = cnt;
+        }
       }
+      a = best;
     }
-    a = best;
   }
   agg[i] = a;
 }
