@@ -193,8 +193,9 @@ void strength(int32_t n, const int32_t *rp, const int32_t *col, const double *va
 // The strength test can be taken on a Laplacian built from node coordinates instead of on A:
 // same pattern, off-diagonal weight w = 1/d^P with d the distance (the squared distance d2
 // summed over the coordinates in order from 0; P = 1: 1/sqrt(d2), both correctly rounded;
-// P = 2: 1/d2), diagonal Ld[i] = the row's weights summed in ascending column order from 0.  k_strength then runs on (w, Ld) unchanged: |L_ij| >= theta sqrt(L_ii L_jj)
-// squared is w^2 >= theta^2 Ld_i Ld_j.  A zero (or NaN) distance between two connected nodes
+// P = 2: 1/d2), diagonal Ld[i] = the row's weights summed in ascending column order from 0.
+// k_strength then runs on (w, Ld) unchanged: |L_ij| >= theta sqrt(L_ii L_jj) squared is
+// w^2 >= theta^2 Ld_i Ld_j.  A zero (or NaN) distance between two connected nodes
 // sets err bit `ebit`.
 template <int D>
 __device__ inline double dist2(const double *__restrict__ xyz, int32_t i, int32_t j) {
@@ -1944,6 +1945,64 @@ void damping(double *lam, double *omega, bool unit, int32_t *err, hipStream_t s)
 // Rows of at most kPRegs entries keep their aggregates (and values) in registers, loaded as
 // independent loads up front; longer rows re-read them per distinct aggregate.
 constexpr int kPRegs = 16;
+// Rows of up to R entries: the entries' aggregates (and values) loaded once, in one batch,
+// and the distinct aggregates counted, or summed in ascending aggregate order, in registers.
+template <int R>
+__device__ __forceinline__ int32_t p_count_regs(int32_t b, int32_t e,
+                                                const int32_t *__restrict__ col,
+                                                const int32_t *__restrict__ agg) {
+  int32_t a[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) a[q] = (b + q < e) ? col[min(b + q, e - 1)] : -1;
+#pragma unroll
+  for (int q = 0; q < R; ++q) a[q] = (a[q] >= 0) ? agg[a[q]] : -1;
+  // distinct aggregates = entries whose aggregate does not occur earlier in the row
+  int32_t c = 0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    bool first = a[q] >= 0;
+#pragma unroll
+    for (int r = 0; r < q; ++r) first = first && (a[r] != a[q]);
+    c += first;
+  }
+  return c;
+}
+template <int R>
+__device__ __forceinline__ void p_fill_regs(int32_t rb, int32_t re,
+                                            const int32_t *__restrict__ col,
+                                            const double *__restrict__ val,
+                                            const int32_t *__restrict__ agg, int32_t ai, double t,
+                                            int32_t w, int32_t *__restrict__ pcol,
+                                            double *__restrict__ pval) {
+  int32_t a[R];
+  double v[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int32_t k = min(rb + q, re - 1);
+    a[q] = (rb + q < re) ? col[k] : -1;
+    v[q] = (rb + q < re) ? val[k] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) a[q] = (a[q] >= 0) ? agg[a[q]] : -1;
+  // aggregates in ascending order; each sums its entries in ascending position from 0
+  int32_t prev = -1;
+  for (;;) {
+    int32_t J = INT_MAX;
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      if (a[q] > prev && a[q] < J) J = a[q];
+    if (J == INT_MAX) break;
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      if (a[q] == J) acc += v[q];
+    pcol[w] = J;
+    pval[w] = ((J == ai) ? 1.0 : 0.0) - t * acc;
+    ++w;
+    prev = J;
+  }
+}
+
 __global__ void k_P_count(int32_t n, const int32_t *rp, const int32_t *col, const int32_t *agg,
                           int32_t *cnt) {
   SA_ROW_KERNEL_BEGIN(n)
@@ -1953,21 +2012,11 @@ __global__ void k_P_count(int32_t n, const int32_t *rp, const int32_t *col, cons
     return;
   }
   if (e - b <= kPRegs) {
-    int32_t a[kPRegs];
-#pragma unroll
-    for (int q = 0; q < kPRegs; ++q) a[q] = (b + q < e) ? col[min(b + q, e - 1)] : -1;
-#pragma unroll
-    for (int q = 0; q < kPRegs; ++q) a[q] = (a[q] >= 0) ? agg[a[q]] : -1;
-    // distinct aggregates = entries whose aggregate does not occur earlier in the row
-    int32_t c = 0;
-#pragma unroll
-    for (int q = 0; q < kPRegs; ++q) {
-      bool first = a[q] >= 0;
-#pragma unroll
-      for (int r = 0; r < q; ++r) first = first && (a[r] != a[q]);
-      c += first;
-    }
-    cnt[i] = c;
+    cnt[i] = p_count_regs<kPRegs>(b, e, col, agg);
+    return;
+  }
+  if (e - b <= 2 * kPRegs) {
+    cnt[i] = p_count_regs<2 * kPRegs>(b, e, col, agg);
     return;
   }
   int32_t prev = -1, c = 0;
@@ -1992,33 +2041,11 @@ __global__ void k_P_fill(int32_t n, const int32_t *rp, const int32_t *col, const
   const int32_t rb = rp[i], re = rp[i + 1];
   if (re <= rb) return;  // an empty row has no prolongator entries
   if (re - rb <= kPRegs) {
-    int32_t a[kPRegs];
-    double v[kPRegs];
-#pragma unroll
-    for (int q = 0; q < kPRegs; ++q) {
-      const int32_t k = min(rb + q, re - 1);
-      a[q] = (rb + q < re) ? col[k] : -1;
-      v[q] = (rb + q < re) ? val[k] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < kPRegs; ++q) a[q] = (a[q] >= 0) ? agg[a[q]] : -1;
-    // aggregates in ascending order; each sums its entries in ascending position from 0
-    int32_t prev = -1, w = prp[i];
-    for (;;) {
-      int32_t J = INT_MAX;
-#pragma unroll
-      for (int q = 0; q < kPRegs; ++q)
-        if (a[q] > prev && a[q] < J) J = a[q];
-      if (J == INT_MAX) break;
-      double acc = 0.0;
-#pragma unroll
-      for (int q = 0; q < kPRegs; ++q)
-        if (a[q] == J) acc += v[q];
-      pcol[w] = J;
-      pval[w] = ((J == ai) ? 1.0 : 0.0) - t * acc;
-      ++w;
-      prev = J;
-    }
+    p_fill_regs<kPRegs>(rb, re, col, val, agg, ai, t, prp[i], pcol, pval);
+    return;
+  }
+  if (re - rb <= 2 * kPRegs) {
+    p_fill_regs<2 * kPRegs>(rb, re, col, val, agg, ai, t, prp[i], pcol, pval);
     return;
   }
   int32_t prev = -1, w = prp[i];
