@@ -33,7 +33,8 @@ enum ErrBits {
   E_COORD = 128,
   E_ASYM = 256,
   E_QR = 512,
-  E_PLAN = 1024
+  E_PLAN = 1024,
+  E_SPAN = 2048
 };
 
 constexpr int32_t kMaxRestart = 1024;  // GMRES restart length limit
@@ -600,10 +601,13 @@ static double *apply_nullspace(sa_hierarchy *h, const double *B, sa_location loc
   return h->dB;
 }
 
+// The input matrix's structure and values, one readback: row pointers spanning [0, nnz]
+// first, then values, columns and diagonals.
 static void validate_values(sa_hierarchy *h) {
   Level &L0 = h->lv[0];
-  validate_csr(h->n, L0.A.rp, L0.A.col, L0.A.val, h->err, h->stream);
+  validate_csr(h->n, L0.A.nnz, L0.A.rp, L0.A.col, L0.A.val, h->err, h->stream);
   const int32_t e = read_err(h);
+  if (e & E_SPAN) throw Error(SA_ERR_BAD_CSR, "row pointers do not span nnz");
   if (e & E_NONFINITE) throw Error(SA_ERR_INVALID_ARG, "non-finite matrix value");
   if (e & E_STRUCT) throw Error(SA_ERR_BAD_CSR, "columns out of range or not ascending");
   if (e & E_NODIAG) throw Error(SA_ERR_BAD_CSR, "missing diagonal");
@@ -634,8 +638,6 @@ static void setup_impl(sa_hierarchy *h, const sa_csr *A, const double *B,
   copy_in(L0.A.rp, A->row_ptr, sizeof(int32_t) * (n + 1), A->loc, s);
   copy_in(L0.A.col, A->col, sizeof(int32_t) * A->nnz, A->loc, s);
   copy_in(L0.A.val, A->val, sizeof(double) * A->nnz, A->loc, s);
-  const int32_t rp0 = read1(L0.A.rp, s), rpn = read1(L0.A.rp + n, s);
-  if (rp0 != 0 || (int64_t)rpn != A->nnz) throw Error(SA_ERR_BAD_CSR, "row pointers do not span nnz");
   validate_values(h);
   if (k > 0) {  // systems SA
     if (bs < 1 || bs > 16 || n % bs != 0)

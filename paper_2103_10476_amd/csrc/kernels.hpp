@@ -154,9 +154,10 @@ void pcg_init_rho(PcgScalars *S, hipStream_t s);
 
 // ---------------- setup kernels (setup_kernels.hip) ------------------------------------
 // Validates a CSR (ascending in-range columns, diagonal present, finite values); flags
-// bits in *err: 1 bad structure, 2 missing diagonal, 4 non-finite value.
-void validate_csr(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
-                  int32_t *err, hipStream_t s);
+// bits in *err: 1 bad structure, 2 missing diagonal, 4 non-finite value, 2048 row pointers
+// not spanning [0, nnz] (nnz: the length of col and val).
+void validate_csr(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
+                  const double *val, int32_t *err, hipStream_t s);
 // dval[i] = A_ii.
 void find_diag(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
                double *dval, hipStream_t s);

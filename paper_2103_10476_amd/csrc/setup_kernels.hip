@@ -59,35 +59,57 @@ __device__ inline int32_t wave_sum_i32(int32_t v) {
 __device__ inline bool wave_any(bool p) { return __ballot(p) != 0; }
 
 // ---- validation -----------------------------------------------------------------------
-__global__ void k_validate(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
-                           const double *val, int32_t *err) {
-  SA_ROW_KERNEL_BEGIN(n)
-  const int32_t b = rp[i], e = rp[i + 1];
-  if (b < 0 || e < b || (int64_t)e > nnz) {
-    atomicOr(err, 1);
+// Entry-parallel (a block owns kBlock rows, whose row pointers it stages in LDS and checks
+// first; coalesced reads of col and val): bit 1 a row pointer or column out of range or
+// columns not ascending, 2 a row without its diagonal entry, 4 a non-finite value, 2048 row
+// pointers that do not start at 0 and end at nnz.
+__global__ __launch_bounds__(kBlock) void k_validate(int32_t n, int64_t nnz,
+                                                     const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ col,
+                                                     const double *__restrict__ val,
+                                                     int32_t *err) {
+  __shared__ int32_t s_rp[kBlock + 1];
+  __shared__ uint8_t s_diag[kBlock];
+  const int t = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * kBlock;
+  const int32_t nr = (int32_t)min<int64_t>(kBlock, (int64_t)n - r0);
+  if (blockIdx.x == 0 && t == 0 && (rp[0] != 0 || (int64_t)rp[n] != nnz)) atomicOr(err, 2048);
+  if (t < nr) s_rp[t] = rp[r0 + t];
+  if (t == 0) s_rp[nr] = rp[r0 + nr];
+  s_diag[t] = 0;
+  __syncthreads();
+  // the block's row pointers: within [0, nnz] and not decreasing, else nothing is read
+  const bool bad = t < nr && (s_rp[t] < 0 || s_rp[t + 1] < s_rp[t] || (int64_t)s_rp[t + 1] > nnz);
+  if (__syncthreads_or(bad)) {
+    if (t == 0) atomicOr(err, 1);
     return;
   }
+  const int32_t e0 = s_rp[0], e1 = s_rp[nr];
   int32_t flags = 0;
-  bool diag = false;
-  for (int32_t k = b; k < e; ++k) {
-    const int32_t c = col[k];
+  for (int32_t e = e0 + t; e < e1; e += kBlock) {
+    int32_t lo = 0, hi = nr - 1;  // the entry's row: the last r with s_rp[r] <= e
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (s_rp[mid] <= e) lo = mid;
+      else hi = mid - 1;
+    }
+    const int32_t c = col[e];
     if (c < 0 || c >= n) flags |= 1;
-    if (k > b && c <= col[k - 1]) flags |= 1;
-    if (c == i) diag = true;
-    if (val && !isfinite(val[k])) flags |= 4;
+    if (e > s_rp[lo] && c <= col[e - 1]) flags |= 1;
+    if (c == (int32_t)r0 + lo) s_diag[lo] = 1;
+    if (val && !isfinite(val[e])) flags |= 4;
   }
-  if (!diag) flags |= 2;
+  __syncthreads();
+  if (t < nr && !s_diag[t]) flags |= 2;
   if (flags) atomicOr(err, flags);
 }
 
-void validate_csr(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
-                  int32_t *err, hipStream_t s) {
-  // rp[0] == 0 and rp[n] == nnz are checked by the caller before this launch.
-  int32_t nnz = read1(rp + n, s);
+// nnz: the length of col and val (rp[n] is checked against it on the device).
+void validate_csr(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
+                  const double *val, int32_t *err, hipStream_t s) {
   k_validate<<<grid_for(n), kBlock, 0, s>>>(n, nnz, rp, col, val, err);
   SA_LAUNCH_CHECK();
 }
-
 __global__ void k_find_diag(int32_t n, const int32_t *rp, const int32_t *col, const double *val,
                             double *dval) {
   SA_ROW_KERNEL_BEGIN(n)

@@ -53,6 +53,17 @@ def test_bad_csr_rejected():
     n, rp, col, val = (x.copy() if hasattr(x, "copy") else x for x in base)
     rp[-1] -= 1
     assert _code(lambda: _setup((n, rp, col[:-1], val[:-1]))) in (-2,)
+    # row pointers not starting at 0, or ending short of the arrays' length
+    n, rp, col, val = (x.copy() if hasattr(x, "copy") else x for x in base)
+    rp[0] = 1
+    assert _code(lambda: _setup((n, rp, col, val))) == -2
+    n, rp, col, val = (x.copy() if hasattr(x, "copy") else x for x in base)
+    assert _code(lambda: _setup((n, rp, np.append(col, 0).astype(np.int32),
+                                 np.append(val, 1.0)))) == -2
+    # a decreasing row pointer inside the matrix
+    n, rp, col, val = (x.copy() if hasattr(x, "copy") else x for x in base)
+    rp[6] = rp[5] - 1
+    assert _code(lambda: _setup((n, rp, col, val))) == -2
     # non-finite value
     n, rp, col, val = (x.copy() if hasattr(x, "copy") else x for x in base)
     val[3] = np.nan
