@@ -1,8 +1,9 @@
 // Sparse matrix-matrix product C = X*Y for the Galerkin operator (Sec. 1.1), in Gustavson
 // order: every output entry C_ij accumulates X_ik*Y_kj over the row's entries k in ascending
-// order, from 0.  No floating-point atomics: each output row's products are ordered by
-// (column, position) and every run of equal columns is summed in order by one lane.  Output
-// rows are sorted; cancellations stay stored.
+// order, from 0.  No floating-point atomics: each output row's products are either ordered by
+// (column, position), every run of equal columns summed in order by one lane, or added X entry
+// by X entry, in order, to per-column accumulators of one wavefront.  Output rows are sorted;
+// cancellations stay stored.
 //
 // Rows are binned by their product count T:
 //   T <= 64      8, 16 or 32 lanes per row (8, 4 or 2 rows per wavefront): two products per
@@ -10,7 +11,8 @@
 //   T <= 256     one wavefront per row, 64 products per step sorted in registers, each run
 //                added to its column's sum in an LDS hash table;
 //   T <= 1024    one 256-thread block per row: the row's products sorted by (column,
-//                position) in LDS, each run reduced in order and written at its rank;
+//                position) in LDS, each run reduced in order and written at its rank; for
+//                R (A P) the rank accumulator (k_esc_rank) takes these rows first;
 //   T > 1024     the row's dense column window in LDS when the output width fits (products
 //                taken 64 per step and sorted, or, for long Y rows, one X entry per step with
 //                its Y row across the lanes), else the wavefront kernel with a 2048-slot
