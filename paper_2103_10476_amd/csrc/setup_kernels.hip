@@ -10,6 +10,7 @@
 #include <chrono>
 #include <climits>
 #include <cstdlib>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -755,6 +756,7 @@ __global__ void k_mis_pass2(int32_t n, const int32_t *__restrict__ grp,
 constexpr int kMisWg = 1024;
 constexpr int64_t kMisWgMaxN = 4096;  // default level size limit (SAAMG_MIS_WG_MAX_N)
 constexpr int64_t kMisWgLdsMaxN = 131072;  // the bitmaps' limit: 2 x 16 KiB of LDS
+constexpr size_t kMisWgKeyLds = 64 << 10;  // keys and k1 in LDS up to this many bytes
 
 // Appends the slots q with take[q] of every active lane to list: one LDS atomic per
 // wavefront, slots in lane-major order of the ballots.
@@ -781,12 +783,15 @@ __device__ inline void wave_append(const int32_t (&w)[Q], const bool (&take)[Q],
     if (take[q]) list[base + (int32_t)off[q]] = w[q];
 }
 
-template <class K, int G>
+// KL: the keys and k1 live in LDS during the rounds (after the bitmaps, at an 8-byte
+// boundary), read from and written back to global memory around them.
+template <class K, int G, bool KL>
 __global__ __launch_bounds__(kMisWg) void k_mis_rounds_wg(
-    int32_t n, const int32_t *__restrict__ grp, const int32_t *__restrict__ gcol, K *key, K *k1,
-    const uint8_t *__restrict__ st1, const int32_t *__restrict__ flag0, int32_t *l1,
+    int32_t n, const int32_t *__restrict__ grp, const int32_t *__restrict__ gcol, K *gkey,
+    K *gk1, const uint8_t *__restrict__ st1, const int32_t *__restrict__ flag0, int32_t *l1,
     int32_t *l2, int32_t max_rounds, int32_t *result, uint32_t *hpost) {
-  extern __shared__ uint32_t bm[];  // bm1 = bm[0, nwb), bm2 = bm[nwb, 2 nwb)
+  extern __shared__ uint64_t lds_wg[];  // 8-byte aligned: the keys may be 64-bit
+  uint32_t *bm = reinterpret_cast<uint32_t *>(lds_wg);  // bm1 = bm[0, nwb), bm2 = bm[nwb, 2 nwb)
   __shared__ int32_t c1, c2, chg[2];
   const int tid = threadIdx.x;
   const int j = tid % G;     // lane within the vertex's group
@@ -794,6 +799,15 @@ __global__ __launch_bounds__(kMisWg) void k_mis_rounds_wg(
   constexpr int kGroups = kMisWg / G;
   const int32_t nwb = (n + 31) >> 5;
   uint32_t *bm1 = bm, *bm2 = bm + nwb;
+  K *key = gkey, *k1 = gk1;
+  if constexpr (KL) {
+    key = reinterpret_cast<K *>(bm + ((2 * nwb + 1) & ~1));
+    k1 = key + n;
+    for (int32_t v = tid; v < n; v += kMisWg) {
+      key[v] = gkey[v];
+      k1[v] = gk1[v];
+    }
+  }
   for (int32_t w = tid; w < 2 * nwb; w += kMisWg) bm[w] = 0u;
   if (tid == 0) {
     c1 = 0;
@@ -912,6 +926,10 @@ __global__ __launch_bounds__(kMisWg) void k_mis_rounds_wg(
         break;
       }
     }
+  }
+  if constexpr (KL) {  // the keys back to global memory (k1 is not read after the rounds)
+    __syncthreads();
+    for (int32_t v = tid; v < n; v += kMisWg) gkey[v] = key[v];
   }
   if (tid == 0) {
     result[0] = (int32_t)used;
@@ -1123,13 +1141,26 @@ static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const
     launch_round(0);
     const int32_t max_rounds = (int32_t)std::min<int64_t>((int64_t)n + 2, INT32_MAX);
     // rows past 16 entries: 4 lanes per vertex
-    const size_t lds = sizeof(uint32_t) * 2 * (size_t)((n + 31) / 32);
-    if (maxdeg > 16)
-      k_mis_rounds_wg<K, 4><<<1, kMisWg, lds, s>>>(n, grp, gcol, key, k1, st1, flags, l12,
-                                                   l12 + n, max_rounds, wg_result, hs_dev);
-    else
-      k_mis_rounds_wg<K, 1><<<1, kMisWg, lds, s>>>(n, grp, gcol, key, k1, st1, flags, l12,
-                                                   l12 + n, max_rounds, wg_result, hs_dev);
+    const size_t bits = sizeof(uint32_t) * (size_t)((2 * ((n + 31) / 32) + 1) & ~1);
+    // the keys and k1 go to LDS too while they fit kMisWgKeyLds bytes
+    const size_t keys = 2 * sizeof(K) * (size_t)n;
+    const bool kl = keys <= kMisWgKeyLds;
+    const size_t lds = bits + (kl ? keys : 0);
+    auto go = [&](auto g, auto klc) {
+      constexpr int G = decltype(g)::value;
+      constexpr bool KL = decltype(klc)::value;
+      k_mis_rounds_wg<K, G, KL><<<1, kMisWg, lds, s>>>(n, grp, gcol, key, k1, st1, flags, l12,
+                                                       l12 + n, max_rounds, wg_result, hs_dev);
+    };
+    using G1 = std::integral_constant<int, 1>;
+    using G4 = std::integral_constant<int, 4>;
+    if (maxdeg > 16) {
+      if (kl) go(G4{}, std::true_type{});
+      else go(G4{}, std::false_type{});
+    } else {
+      if (kl) go(G1{}, std::true_type{});
+      else go(G1{}, std::false_type{});
+    }
     SA_LAUNCH_CHECK();
     done = true;
   }
