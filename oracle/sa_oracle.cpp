@@ -91,7 +91,7 @@ uint64_t stream_key(int stream, int level, int64_t i) {
   return ((uint64_t)stream << 56) | ((uint64_t)level << 40) | (uint64_t)i;
 }
 
-// Canonical reduction tree used for every inner product (a convention of this build, the
+// Canonical reduction tree used for every inner product (a fixed convention, since the
 // paper does not fix summation order): blocks of 4096 terms; within a block, lane t of 256
 // sums terms t, t+256, ..., t+15*256 sequentially from 0.0; then s[t] += s[t+w] for
 // w = 128, 64, ..., 1; the block results are reduced again by the same rule until one
