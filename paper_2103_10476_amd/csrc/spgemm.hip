@@ -23,6 +23,7 @@
 // and are compacted into CSR afterwards.
 #include <algorithm>
 #include <climits>
+#include <cstdlib>
 #include <cstring>
 
 #include <mutex>
@@ -667,18 +668,24 @@ __global__ __launch_bounds__(64) void k_esc_rank(const int32_t *rows, int32_t nr
 //          swap, its sum starting from 0); a row whose distinct columns pass H/2 is listed in
 //          ovf[] for k_esc_dense.  At the end the occupied slots are compacted and sorted by
 //          column (bitonic, in LDS).
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+__device__ __forceinline__ uint32_t shfl_xor_key(uint32_t v, int m) {
+  return (uint32_t)__shfl_xor((int)v, m, 64);
+}
+__device__ __forceinline__ uint64_t shfl_xor_key(uint64_t v, int m) {
   const uint32_t lo = __shfl_xor((uint32_t)v, m, 64);
   const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
   return ((uint64_t)hi << 32) | lo;
 }
-// Ascending bitonic sort of one 64-bit key per lane across the wavefront (keys distinct).
-__device__ __forceinline__ uint64_t wave_sort_u64(uint64_t key, int lane) {
+// Ascending bitonic sort of one key per lane across the wavefront (keys distinct).  Keys are
+// (column << 6 | lane): 32 bits while the columns stay below 2^26 (one cross-lane move per
+// stage), else 64.
+template <typename KT>
+__device__ __forceinline__ KT wave_sort(KT key, int lane) {
 #pragma unroll
   for (int k = 2; k <= 64; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      const uint64_t other = shfl_xor_u64(key, j);
+      const KT other = shfl_xor_key(key, j);
       const bool up = (lane & k) == 0;
       const bool lower = (lane & j) == 0;
       key = (lower == up) ? (key < other ? key : other) : (key > other ? key : other);
@@ -687,14 +694,14 @@ __device__ __forceinline__ uint64_t wave_sort_u64(uint64_t key, int lane) {
   return key;
 }
 
-template <bool DENSE, int H>
+template <bool DENSE, int H, typename KT>
 __global__ __launch_bounds__(64) void k_esc_wave(
     const int32_t *rows, int32_t nrows, const int32_t *xrp, const int32_t *xcol,
     const double *xval, const int32_t *yrp, const int32_t *ycol, const double *yval,
     int32_t width, const int2 *win, const int64_t *poff, int32_t *ocol, double *oval,
     int32_t *ucnt, int32_t *ovf, int32_t *novf, const int32_t *dcount) {
   extern __shared__ double lds_dyn[];
-  __shared__ int32_t s_incl[64], s_ys[64], s_col[64];
+  __shared__ int32_t s_incl[64], s_ys[64];
   __shared__ double s_a[64], s_v[64];
   __shared__ int32_t s_cnt;
   const int lane = threadIdx.x;
@@ -774,23 +781,31 @@ __global__ __launch_bounds__(64) void k_esc_wave(
       const int32_t j = jn;
       const double y = yn, a = an;
       fetch(p0 + 64 + lane);
-      uint64_t key = ~0ull;
+      constexpr KT kNone = ~KT(0);
+      KT key = kNone;
       double v = 0.0;
       if (j >= 0) {
         v = a * y;
-        key = ((uint64_t)(uint32_t)j << 6) | (uint32_t)lane;
+        key = ((KT)(uint32_t)j << 6) | (KT)lane;
       }
-      key = wave_sort_u64(key, lane);
+      key = wave_sort<KT>(key, lane);
       const double sv = __shfl(v, (int)(key & 63u), 64);
-      const int32_t col = key == ~0ull ? -1 : (int32_t)(key >> 6);
-      s_col[lane] = col;
+      const int32_t col = key == kNone ? -1 : (int32_t)(key >> 6);
+      // runs of equal columns: a run starts where the column differs from the lane below;
+      // it ends at the next start or at the last product (empty keys sort last)
+      const int32_t below = __shfl_up(col, 1, 64);
+      const bool head = col >= 0 && (lane == 0 || below != col);
+      const uint64_t heads = __ballot(head);
+      const int32_t nprod = __popcll(__ballot(col >= 0));
+      const uint64_t later = lane < 63 ? heads >> (lane + 1) : 0ull;
+      const int32_t end = later ? lane + 1 + (int32_t)__builtin_ctzll(later) : nprod;
       s_v[lane] = sv;
       __syncthreads();
-      if (col >= 0 && (lane == 0 || s_col[lane - 1] != col)) {  // first of its run
+      if (head) {
         if (DENSE) {
           const int32_t c = col - lo;  // inside the window by construction
           double t = acc[c];
-          for (int r = lane; r < 64 && s_col[r] == col; ++r) t += s_v[r];
+          for (int r = lane; r < end; ++r) t += s_v[r];
           acc[c] = t;
           atomicOr(&bits[c >> 5], 1u << (c & 31));
         } else {
@@ -805,7 +820,7 @@ __global__ __launch_bounds__(64) void k_esc_wave(
             h = (h + 1) & (H - 1);
           }
           double t = hv[h];
-          for (int r = lane; r < 64 && s_col[r] == col; ++r) t += s_v[r];
+          for (int r = lane; r < end; ++r) t += s_v[r];
           hv[h] = t;
         }
       }
@@ -895,7 +910,9 @@ static int32_t lds_cols_max() {
     cols &= ~31;
     const int bytes = (int)(((int64_t)cols * 65 + 7) / 8);
     if (cols > (64 << 10) / 9 &&
-        (hipFuncSetAttribute((const void *)k_esc_wave<true, 1>,
+        (hipFuncSetAttribute((const void *)k_esc_wave<true, 1, uint32_t>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess ||
+         hipFuncSetAttribute((const void *)k_esc_wave<true, 1, uint64_t>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess ||
          hipFuncSetAttribute((const void *)k_esc_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                              bytes) != hipSuccess))
@@ -977,6 +994,18 @@ __global__ __launch_bounds__(kBlock) void k_bin_rows(int32_t m, const int64_t *p
   bin_row(live, i, live ? poff[i + 1] - poff[i] : 0, m, lists, counters);
 }
 
+// k_esc_wave with 32-bit sort keys when every column of Y fits in 26 bits, else 64-bit keys
+// (the environment variable SAAMG_SPGEMM_KEY64=1 takes the 64-bit keys at any width).
+template <bool DENSE, int H, typename... Args>
+void launch_esc_wave(int32_t ncols, unsigned grid, size_t lds, hipStream_t s, Args... args) {
+  const char *e = std::getenv("SAAMG_SPGEMM_KEY64");
+  const bool key64 = e && std::atoi(e) != 0;
+  if (ncols < (1 << 26) && !key64)
+    k_esc_wave<DENSE, H, uint32_t><<<grid, 64, lds, s>>>(args...);
+  else
+    k_esc_wave<DENSE, H, uint64_t><<<grid, 64, lds, s>>>(args...);
+}
+
 void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
   const int32_t m = X.n;
   C.n = m;
@@ -1052,9 +1081,9 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
     c1024 = rc;
   }
   if (n256 > 0) {
-    k_esc_wave<false, 512><<<(unsigned)n256, 64, 16 * 512, s>>>(
-        l1, n256, X.rp, X.col, X.val, Y.rp, Y.col, Y.val, 0, nullptr, poff, ocol, oval, ucnt,
-        ovf, counters + kBins, nullptr);
+    launch_esc_wave<false, 512>(Y.ncols, (unsigned)n256, 16 * 512, s, l1, n256, X.rp, X.col,
+                                X.val, Y.rp, Y.col, Y.val, 0, nullptr, poff, ocol, oval, ucnt,
+                                ovf, counters + kBins, nullptr);
     SA_LAUNCH_CHECK();
   }
   if (n1024 > 0) {
@@ -1087,15 +1116,14 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
       k_esc_lds<<<(unsigned)nlong, 64, lds, s>>>(l3, nlong, X.rp, X.col, X.val, Y.rp, Y.col,
                                                 Y.val, wl, win, poff, ocol, oval, ucnt);
     else
-      k_esc_wave<true, 1><<<(unsigned)nlong, 64, lds, s>>>(l3, nlong, X.rp, X.col, X.val, Y.rp,
-                                                           Y.col, Y.val, wl, win, poff, ocol,
-                                                           oval, ucnt, ovf, counters + kBins,
-                                                           nullptr);
+      launch_esc_wave<true, 1>(Y.ncols, (unsigned)nlong, lds, s, l3, nlong, X.rp, X.col, X.val,
+                               Y.rp, Y.col, Y.val, wl, win, poff, ocol, oval, ucnt, ovf,
+                               counters + kBins, nullptr);
     SA_LAUNCH_CHECK();
   } else if (nlong > 0) {
-    k_esc_wave<false, 2048><<<(unsigned)nlong, 64, 16 * 2048, s>>>(
-        l3, nlong, X.rp, X.col, X.val, Y.rp, Y.col, Y.val, 0, nullptr, poff, ocol, oval, ucnt,
-        ovf, counters + kBins, nullptr);
+    launch_esc_wave<false, 2048>(Y.ncols, (unsigned)nlong, 16 * 2048, s, l3, nlong, X.rp,
+                                 X.col, X.val, Y.rp, Y.col, Y.val, 0, nullptr, poff, ocol, oval,
+                                 ucnt, ovf, counters + kBins, nullptr);
     SA_LAUNCH_CHECK();
     const int32_t nov = read1(counters + kBins, s);
     if (nov > 0) {
