@@ -17,8 +17,9 @@
 //                taken 64 per step and sorted, or, for long Y rows, one X entry per step with
 //                its Y row across the lanes), else the wavefront kernel with a 2048-slot
 //                hash table;
-//   hash > 1/2   long rows with more than 1024 distinct columns are redone with a dense
-//                accumulator in global memory.
+//   hash > 1/2   long rows with more than 1024 distinct columns are redone over their column
+//                windows in LDS tiles (one launch per tile, up to 8), or with a dense
+//                accumulator in global memory when the windows need more tiles.
 // Results go to per-row slots at the row's product offset (room for T >= distinct entries)
 // and are compacted into CSR afterwards.
 #include <algorithm>
@@ -418,9 +419,13 @@ __global__ __launch_bounds__(kBlock) void k_esc_dense(
 // into their own columns (distinct within a row of Y), and the adds of successive k are
 // ordered (one wavefront executes them in program order; a wave barrier separates them), so
 // every output entry receives its products in ascending k from 0, as in the sort-based bins.
-// The row's X entries and Y row ranges are staged in LDS 64 at a time, and the next chunk of
-// Y is loaded before the current one is added, so its latency overlaps the adds.  The result
-// is extracted in column order with ballots.
+// The row's X entries and Y row ranges are staged in LDS 64 at a time, and the steps (64-entry
+// slices of Y rows) are taken D at a time, their loads issued together before they are added,
+// so D steps share one memory latency even at one wavefront per CU (the widest windows fill
+// the LDS).
+// The result is extracted in column order with ballots.  Rows wider than the LDS (those that
+// overflow the hash bin) are taken in column tiles, one launch per tile, each appending its
+// entries to the row's earlier ones.
 __device__ __forceinline__ void lds_add(double *acc, uint32_t *bits, int32_t j, double v) {
   acc[j] = acc[j] + v;
   atomicOr(&bits[j >> 5], 1u << (j & 31));
@@ -457,13 +462,16 @@ __global__ void k_row_window(const int32_t *rows, int32_t nrows, const int32_t *
   }
 }
 
+constexpr int kLdsDepth = 8;  // steps whose loads k_esc_lds issues together
+template <int D>
 __global__ __launch_bounds__(64) void k_esc_lds(const int32_t *rows, int32_t nrows,
                                                 const int32_t *xrp, const int32_t *xcol,
                                                 const double *xval, const int32_t *yrp,
                                                 const int32_t *ycol, const double *yval,
                                                 int32_t ncols, const int2 *win,
                                                 const int64_t *poff, int32_t *ocol,
-                                                double *oval, int32_t *ucnt) {
+                                                double *oval, int32_t *ucnt, int32_t tile,
+                                                int32_t tw) {
   extern __shared__ double lds_acc[];
   double *acc = lds_acc;
   uint32_t *bits = (uint32_t *)(acc + ncols);
@@ -474,9 +482,17 @@ __global__ __launch_bounds__(64) void k_esc_lds(const int32_t *rows, int32_t nro
   if (slot >= nrows) return;  // block-uniform
   const int32_t i = rows[slot];
   // the row's window: accumulator index j - lo for output column j, rw <= ncols entries
-  // (no windows: the whole width)
+  // (no windows: the whole width); with tiles (tw > 0) this pass takes columns
+  // [lo + tile tw, lo + (tile + 1) tw) of the window and appends to the earlier tiles' entries
   const int2 wn = win ? win[slot] : make_int2(0, ncols);
-  const int32_t lo = wn.x, rw = wn.y;
+  int32_t lo = wn.x, rw = wn.y, prior = 0;
+  if (tw > 0) {
+    const int32_t off = tile * tw;
+    if (tile > 0 && off >= rw) return;  // block-uniform: the row's window ended earlier
+    lo += off;
+    rw = min(tw, rw - off);
+    if (tile > 0) prior = ucnt[i];
+  }
   const int32_t nw = (rw + 31) >> 5;
   for (int32_t c = lane; c < rw; c += 64) acc[c] = 0.0;
   for (int32_t c = lane; c < nw; c += 64) bits[c] = 0u;
@@ -491,36 +507,46 @@ __global__ __launch_bounds__(64) void k_esc_lds(const int32_t *rows, int32_t nro
       s_e[lane] = yrp[k + 1];
     }
     __syncthreads();
-    // steps (g, chunk) in order; the loads of the next step are issued before the adds
-    int32_t g = 0, q0 = s_b[0];
-    int32_t jn = -1;
-    double vn = 0.0;
-    if (q0 + lane < s_e[0]) {
-      jn = ycol[q0 + lane];
-      vn = yval[q0 + lane];
-    }
-    while (g < cnt) {
-      const int32_t j = jn;
-      const double v = vn;
-      const double a = s_a[g];
-      int32_t g2 = g, q2 = q0 + 64;
-      if (q2 >= s_e[g2]) {
-        ++g2;
-        q2 = (g2 < cnt) ? s_b[g2] : 0;
+    // steps (g, 64-entry slice of Y's row k_g) in order, D at a time: the D steps' loads are
+    // issued together, then the steps are added in order (steps past the chunk are empty).
+    // Every lane loads (lanes past the Y row, or steps past the chunk, read the chunk's first
+    // Y entry and discard it), so each step waits only for its own loads.  The block is one
+    // wavefront, whose LDS operations complete in program order, and one step's adds go to
+    // distinct columns (one Y row's): no barrier between steps, which would also wait for the
+    // loads in flight.
+    const int32_t qsafe = s_b[0] < s_e[0] ? s_b[0] : 0;
+    int32_t gp = 0, qp = s_b[0];
+    while (gp < cnt) {
+      int32_t jq[D], gq[D];
+      double vq[D];
+      bool okq[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        gq[d] = gp;
+        const bool live = gp < cnt;
+        const int32_t ge = live ? s_e[gp] : 0;
+        okq[d] = live && qp + lane < ge;
+        const int32_t q = okq[d] ? qp + lane : qsafe;
+        jq[d] = ycol[q];
+        vq[d] = yval[q];
+        if (live) {
+          qp += 64;
+          if (qp >= ge) {
+            ++gp;
+            qp = (gp < cnt) ? s_b[gp] : 0;
+          }
+        }
       }
-      jn = -1;
-      if (g2 < cnt && q2 + lane < s_e[g2]) {
-        jn = ycol[q2 + lane];
-        vn = yval[q2 + lane];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int32_t j = jq[d];
+        if (okq[d] && (uint32_t)(j - lo) < (uint32_t)rw)
+          lds_add(acc, bits, j - lo, s_a[gq[d]] * vq[d]);
       }
-      if ((uint32_t)(j - lo) < (uint32_t)rw) lds_add(acc, bits, j - lo, a * v);  // j >= 0
-      if (g2 != g) __syncthreads();  // (one wavefront) orders row g's adds before row g2's
-      g = g2;
-      q0 = q2;
     }
   }
   __syncthreads();
-  const int64_t base = poff[i];
+  const int64_t base = poff[i] + prior;
   int32_t w = 0;
   for (int32_t c0 = 0; c0 < rw; c0 += 64) {
     const int32_t c = c0 + lane;
@@ -533,7 +559,7 @@ __global__ __launch_bounds__(64) void k_esc_lds(const int32_t *rows, int32_t nro
     }
     w += __popcll(bm);
   }
-  if (lane == 0) ucnt[i] = w;
+  if (lane == 0) ucnt[i] = prior + w;
 }
 
 // ---- rank accumulator (257..1024 products, narrow output rows) -----------------------------
@@ -663,7 +689,9 @@ __global__ __launch_bounds__(64) void k_esc_rank(const int32_t *rows, int32_t nr
 // accumulator in LDS.  Steps follow each other in product order, so every output entry
 // receives its products in ascending k, from 0.
 //   DENSE  the accumulator is the row's column window (values and a touched bitmap), read
-//          out in column order with ballots;
+//          out in column order with ballots; rows wider than the LDS (those that overflow the
+//          hash bin) are taken in column tiles, one launch per tile, each appending its
+//          entries to the row's earlier ones;
 //   HASH   an open-addressing table of H slots (every column claimed by an LDS compare-and-
 //          swap, its sum starting from 0); a row whose distinct columns pass H/2 is listed in
 //          ovf[] for k_esc_dense.  At the end the occupied slots are compacted and sorted by
@@ -699,7 +727,8 @@ __global__ __launch_bounds__(64) void k_esc_wave(
     const int32_t *rows, int32_t nrows, const int32_t *xrp, const int32_t *xcol,
     const double *xval, const int32_t *yrp, const int32_t *ycol, const double *yval,
     int32_t width, const int2 *win, const int64_t *poff, int32_t *ocol, double *oval,
-    int32_t *ucnt, int32_t *ovf, int32_t *novf, const int32_t *dcount) {
+    int32_t *ucnt, int32_t *ovf, int32_t *novf, const int32_t *dcount, int32_t tile,
+    int32_t tw) {
   extern __shared__ double lds_dyn[];
   __shared__ int32_t s_incl[64], s_ys[64];
   __shared__ double s_a[64], s_v[64];
@@ -715,12 +744,19 @@ __global__ __launch_bounds__(64) void k_esc_wave(
   double *hv = lds_dyn;
   int32_t *hk = reinterpret_cast<int32_t *>(hv + H);
   uint64_t *sk = reinterpret_cast<uint64_t *>(hk + H);
-  int32_t lo = 0, rw = width;
+  int32_t lo = 0, rw = width, prior = 0;
   if (DENSE) {
     if (win) {
       const int2 w = win[slot];
       lo = w.x;
       rw = w.y;
+    }
+    if (tw > 0) {  // column tile `tile` of the window, appended to the earlier tiles' entries
+      const int32_t off = tile * tw;
+      if (tile > 0 && off >= rw) return;  // block-uniform: the row's window ended earlier
+      lo += off;
+      rw = min(tw, rw - off);
+      if (tile > 0) prior = ucnt[i];
     }
     for (int32_t c = lane; c < rw; c += 64) acc[c] = 0.0;
     for (int32_t c = lane; c < ((rw + 31) >> 5); c += 64) bits[c] = 0u;
@@ -803,11 +839,13 @@ __global__ __launch_bounds__(64) void k_esc_wave(
       __syncthreads();
       if (head) {
         if (DENSE) {
-          const int32_t c = col - lo;  // inside the window by construction
-          double t = acc[c];
-          for (int r = lane; r < end; ++r) t += s_v[r];
-          acc[c] = t;
-          atomicOr(&bits[c >> 5], 1u << (c & 31));
+          const int32_t c = col - lo;  // outside the window only with tiles
+          if ((uint32_t)c < (uint32_t)rw) {
+            double t = acc[c];
+            for (int r = lane; r < end; ++r) t += s_v[r];
+            acc[c] = t;
+            atomicOr(&bits[c >> 5], 1u << (c & 31));
+          }
         } else {
           uint32_t h = hash_slot(col, H - 1);
           for (int probe = 0; probe < H; ++probe) {
@@ -843,12 +881,12 @@ __global__ __launch_bounds__(64) void k_esc_wave(
       const unsigned long long bm = __ballot(f);
       if (f) {
         const int32_t pos = w + __popcll(bm & ((1ull << lane) - 1ull));
-        ocol[base + pos] = lo + c;
-        oval[base + pos] = acc[c];
+        ocol[base + prior + pos] = lo + c;
+        oval[base + prior + pos] = acc[c];
       }
       w += __popcll(bm);
     }
-    if (lane == 0) ucnt[i] = w;
+    if (lane == 0) ucnt[i] = prior + w;
   } else {
     // compact the occupied slots as (column << 32 | slot) keys, sort them, write in order
     int32_t u = 0;
@@ -914,8 +952,8 @@ static int32_t lds_cols_max() {
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess ||
          hipFuncSetAttribute((const void *)k_esc_wave<true, 1, uint64_t>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess ||
-         hipFuncSetAttribute((const void *)k_esc_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             bytes) != hipSuccess))
+         hipFuncSetAttribute((const void *)k_esc_lds<kLdsDepth>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess))
       cols = (((64 << 10) - 4096) * 8 / 65) & ~31;
     cache[dev] = cols;
     done[dev] = true;
@@ -992,6 +1030,13 @@ __global__ __launch_bounds__(kBlock) void k_bin_rows(int32_t m, const int64_t *p
   const bool live = i64 < m;
   const int32_t i = live ? (int32_t)i64 : 0;
   bin_row(live, i, live ? poff[i + 1] - poff[i] : 0, m, lists, counters);
+}
+
+// Column tiles that the hash bin's overflowing rows may take in LDS (environment variable
+// SAAMG_SPGEMM_MAX_TILES; 0 sends them to the dense accumulator in global memory).
+static int32_t max_tiles() {
+  const char *e = std::getenv("SAAMG_SPGEMM_MAX_TILES");
+  return e ? std::atoi(e) : 8;
 }
 
 // k_esc_wave with 32-bit sort keys when every column of Y fits in 26 bits, else 64-bit keys
@@ -1083,7 +1128,7 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
   if (n256 > 0) {
     launch_esc_wave<false, 512>(Y.ncols, (unsigned)n256, 16 * 512, s, l1, n256, X.rp, X.col,
                                 X.val, Y.rp, Y.col, Y.val, 0, nullptr, poff, ocol, oval, ucnt,
-                                ovf, counters + kBins, nullptr);
+                                ovf, counters + kBins, nullptr, 0, 0);
     SA_LAUNCH_CHECK();
   }
   if (n1024 > 0) {
@@ -1113,20 +1158,50 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
     // Y rows of 16 entries or more on average (R (AP)): one X entry per step, its Y row
     // across the lanes; shorter Y rows (A P): 64 products per step, sorted
     if (Y.nnz >= 16 * (int64_t)Y.n)
-      k_esc_lds<<<(unsigned)nlong, 64, lds, s>>>(l3, nlong, X.rp, X.col, X.val, Y.rp, Y.col,
-                                                Y.val, wl, win, poff, ocol, oval, ucnt);
+      k_esc_lds<kLdsDepth><<<(unsigned)nlong, 64, lds, s>>>(l3, nlong, X.rp, X.col, X.val, Y.rp,
+                                                           Y.col, Y.val, wl, win, poff, ocol,
+                                                           oval, ucnt, 0, 0);
     else
       launch_esc_wave<true, 1>(Y.ncols, (unsigned)nlong, lds, s, l3, nlong, X.rp, X.col, X.val,
                                Y.rp, Y.col, Y.val, wl, win, poff, ocol, oval, ucnt, ovf,
-                               counters + kBins, nullptr);
+                               counters + kBins, nullptr, 0, 0);
     SA_LAUNCH_CHECK();
   } else if (nlong > 0) {
     launch_esc_wave<false, 2048>(Y.ncols, (unsigned)nlong, 16 * 2048, s, l3, nlong, X.rp,
                                  X.col, X.val, Y.rp, Y.col, Y.val, 0, nullptr, poff, ocol, oval,
-                                 ucnt, ovf, counters + kBins, nullptr);
+                                 ucnt, ovf, counters + kBins, nullptr, 0, 0);
     SA_LAUNCH_CHECK();
     const int32_t nov = read1(counters + kBins, s);
+    // rows over 1024 distinct columns: their column windows in LDS tiles (one launch per tile,
+    // at most kMaxTiles), else a dense accumulator in global memory
+    int32_t ntile = 0, tw = 0;
+    int2 *owin = nullptr;
     if (nov > 0) {
+      owin = tmp.alloc<int2>(nov);
+      fill_i32(counters + kBins + 1, 0, 1, s);
+      k_row_window<<<grid_for((int64_t)nov * 64), kBlock, 0, s>>>(ovf, nov, X.rp, X.col, Y.rp,
+                                                                 Y.col, owin,
+                                                                 counters + kBins + 1);
+      SA_LAUNCH_CHECK();
+      const int32_t wmax = read1(counters + kBins + 1, s);
+      tw = std::min(lds_cols_max(), (wmax + 31) & ~31);
+      ntile = tw > 0 ? (int32_t)ceil_div(wmax, tw) : 0;
+      if (ntile > max_tiles()) ntile = 0;
+    }
+    if (ntile > 0) {
+      const size_t lds = (size_t)tw * sizeof(double) + (size_t)(tw / 32) * 4;
+      for (int32_t t = 0; t < ntile; ++t) {
+        if (Y.nnz >= 16 * (int64_t)Y.n)
+          k_esc_lds<kLdsDepth><<<(unsigned)nov, 64, lds, s>>>(ovf, nov, X.rp, X.col, X.val,
+                                                             Y.rp, Y.col, Y.val, tw, owin, poff,
+                                                             ocol, oval, ucnt, t, tw);
+        else
+          launch_esc_wave<true, 1>(Y.ncols, (unsigned)nov, lds, s, ovf, nov, X.rp, X.col, X.val,
+                                   Y.rp, Y.col, Y.val, tw, owin, poff, ocol, oval, ucnt,
+                                   nullptr, nullptr, nullptr, t, tw);
+        SA_LAUNCH_CHECK();
+      }
+    } else if (nov > 0) {
       // dense accumulators: at most ~2 GiB of them at once
       const int64_t per = (int64_t)Y.ncols * 12;
       int64_t nb = std::min<int64_t>(nov, std::max<int64_t>(1, (int64_t(2) << 30) / per));
