@@ -696,30 +696,53 @@ __global__ __launch_bounds__(64) void k_esc_rank(const int32_t *rows, int32_t nr
 //          swap, its sum starting from 0); a row whose distinct columns pass H/2 is listed in
 //          ovf[] for k_esc_dense.  At the end the occupied slots are compacted and sorted by
 //          column (bitonic, in LDS).
-__device__ __forceinline__ uint32_t shfl_xor_key(uint32_t v, int m) {
-  return (uint32_t)__shfl_xor((int)v, m, 64);
+// Value of lane (lane ^ J) of the wavefront.  J = 1, 2: a quad permutation (DPP); J = 4, 8:
+// the row shifts by J toward the lower lanes (row_shl, lane i reads i + J) and the higher
+// lanes (row_shr, lane i reads i - J), of which each lane keeps the one inside its J-group
+// pair (both stay inside the 16-lane row); J = 16, 32: an LDS permute.
+template <int J>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v, int lane) {
+  if constexpr (J == 1) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
+  } else if constexpr (J == 2) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
+  } else if constexpr (J == 4 || J == 8) {
+    const uint32_t from_up =
+        (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x100 + J, 0xF, 0xF, false);  // row_shl
+    const uint32_t from_dn =
+        (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x110 + J, 0xF, 0xF, false);  // row_shr
+    return (lane & J) ? from_dn : from_up;
+  } else {
+    return (uint32_t)__shfl_xor((int)v, J, 64);
+  }
 }
-__device__ __forceinline__ uint64_t shfl_xor_key(uint64_t v, int m) {
-  const uint32_t lo = __shfl_xor((uint32_t)v, m, 64);
-  const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
+template <int J>
+__device__ __forceinline__ uint64_t xor_lane(uint64_t v, int lane) {
+  const uint32_t lo = xor_lane<J>((uint32_t)v, lane);
+  const uint32_t hi = xor_lane<J>((uint32_t)(v >> 32), lane);
   return ((uint64_t)hi << 32) | lo;
 }
 // Ascending bitonic sort of one key per lane across the wavefront (keys distinct).  Keys are
 // (column << 6 | lane): 32 bits while the columns stay below 2^26 (one cross-lane move per
-// stage), else 64.
-template <typename KT>
+// stage), else 64.  Merge K's stage J pairs lanes i and i ^ J.
+template <int K, int J, typename KT>
+__device__ __forceinline__ KT bitonic_merge(KT key, int lane) {
+  const KT other = xor_lane<J>(key, lane);
+  const bool up = (lane & K) == 0;
+  const bool lower = (lane & J) == 0;
+  key = (lower == up) ? (key < other ? key : other) : (key > other ? key : other);
+  if constexpr (J > 1)
+    return bitonic_merge<K, J / 2>(key, lane);
+  else
+    return key;
+}
+template <typename KT, int K = 2>
 __device__ __forceinline__ KT wave_sort(KT key, int lane) {
-#pragma unroll
-  for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      const KT other = shfl_xor_key(key, j);
-      const bool up = (lane & k) == 0;
-      const bool lower = (lane & j) == 0;
-      key = (lower == up) ? (key < other ? key : other) : (key > other ? key : other);
-    }
-  }
-  return key;
+  key = bitonic_merge<K, K / 2>(key, lane);
+  if constexpr (K < 64)
+    return wave_sort<KT, K * 2>(key, lane);
+  else
+    return key;
 }
 
 template <bool DENSE, int H, typename KT>
