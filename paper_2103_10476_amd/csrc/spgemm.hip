@@ -722,6 +722,18 @@ __device__ __forceinline__ uint64_t xor_lane(uint64_t v, int lane) {
   const uint32_t hi = xor_lane<J>((uint32_t)(v >> 32), lane);
   return ((uint64_t)hi << 32) | lo;
 }
+// Inclusive prefix maximum over the wavefront's lanes: row shifts by 1, 2, 4 and 8 within
+// each 16-lane row (lanes shifted in from outside the row read -1), then the last lane of
+// row 0 (of row 2) into row 1 (row 3), then the last lane of row 1 into rows 2 and 3.
+__device__ __forceinline__ int32_t wave_prefix_max(int32_t x) {
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xF, 0xF, false));  // row_shr:1
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xF, 0xF, false));  // row_shr:2
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xF, 0xF, false));  // row_shr:4
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xF, 0xF, false));  // row_shr:8
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x142, 0xA, 0xF, false));  // row_bcast:15
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x143, 0xC, 0xF, false));  // row_bcast:31
+  return x;
+}
 // Ascending bitonic sort of one key per lane across the wavefront (keys distinct).  Keys are
 // (column << 6 | lane): 32 bits while the columns stay below 2^26 (one cross-lane move per
 // stage), else 64.  Merge K's stage J pairs lanes i and i ^ J.
@@ -753,10 +765,11 @@ __global__ __launch_bounds__(64) void k_esc_wave(
     int32_t *ucnt, int32_t *ovf, int32_t *novf, const int32_t *dcount, int32_t tile,
     int32_t tw) {
   extern __shared__ double lds_dyn[];
-  __shared__ int32_t s_incl[64], s_ys[64];
+  __shared__ int32_t s_incl[64], s_ys[64], s_mark[64];
   __shared__ double s_a[64], s_v[64];
   __shared__ int32_t s_cnt;
   const int lane = threadIdx.x;
+  s_mark[lane] = -1;
   const int32_t slot = blockIdx.x;
   if (slot >= (dcount ? *dcount : nrows)) return;  // block-uniform
   const int32_t i = rows[slot];
@@ -815,31 +828,39 @@ __global__ __launch_bounds__(64) void k_esc_wave(
     s_ys[lane] = ys;
     s_a[lane] = a;
     __syncthreads();
-    // product p of the chunk: the first staged entry g with s_incl[g] > p, at offset
-    // p - s_incl[g-1] in its row of Y.  The next step's entry is loaded before this step is
-    // sorted and added, so its latency overlaps them (the product is formed when it is used).
+    // product p of the chunk belongs to the last staged entry g that starts at or before it
+    // (among entries with products), at offset p - s_incl[g-1] in its row of Y.  For a step
+    // of 64 products, each entry starting inside the step marks its first product's lane, and
+    // a prefix maximum over the lanes, from the entry of the step's preceding product, gives
+    // every lane its entry.  The next step's entry is loaded before this step is sorted and
+    // added, so its latency overlaps them (the product is formed when it is used).
+    const int32_t ex = incl - len;  // this lane's entry's first product
+    const bool starts = lane < cnt && len > 0;
+    int32_t carry = -1;  // entry of the product before the step being fetched (wave-uniform)
     int32_t jn = -1;
     double yn = 0.0, an = 0.0;
-    auto fetch = [&](int32_t p) {
+    auto fetch = [&](int32_t p0) {
       jn = -1;
+      if (p0 >= tot) return;  // wave-uniform
+      if (starts && ex >= p0 && ex < p0 + 64) s_mark[ex - p0] = lane;
+      __syncthreads();
+      int32_t g = s_mark[lane];
+      s_mark[lane] = -1;  // every slot is -1 again for the next step
+      g = max(wave_prefix_max(g), carry);
+      carry = __builtin_amdgcn_readlane(g, 63);
+      const int32_t p = p0 + lane;
       if (p < tot) {
-        int32_t l0 = 0, h0 = cnt - 1;
-        while (l0 < h0) {
-          const int32_t mid = (l0 + h0) >> 1;
-          if (s_incl[mid] > p) h0 = mid;
-          else l0 = mid + 1;
-        }
-        const int32_t q = s_ys[l0] + p - (l0 > 0 ? s_incl[l0 - 1] : 0);
+        const int32_t q = s_ys[g] + p - (g > 0 ? s_incl[g - 1] : 0);
         jn = ycol[q];
         yn = yval[q];
-        an = s_a[l0];
+        an = s_a[g];
       }
     };
-    fetch(lane);
+    fetch(0);
     for (int32_t p0 = 0; p0 < tot; p0 += 64) {
       const int32_t j = jn;
       const double y = yn, a = an;
-      fetch(p0 + 64 + lane);
+      fetch(p0 + 64);
       constexpr KT kNone = ~KT(0);
       KT key = kNone;
       double v = 0.0;
