@@ -562,9 +562,23 @@ __global__ __launch_bounds__(64) void k_esc_lds(const int32_t *rows, int32_t nro
   if (lane == 0) ucnt[i] = prior + w;
 }
 
+// Inclusive prefix maximum over the wavefront's lanes: row shifts by 1, 2, 4 and 8 within
+// each 16-lane row (lanes shifted in from outside the row read -1), then the last lane of
+// row 0 (of row 2) into row 1 (row 3), then the last lane of row 1 into rows 2 and 3.
+__device__ __forceinline__ int32_t wave_prefix_max(int32_t x) {
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xF, 0xF, false));  // row_shr:1
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xF, 0xF, false));  // row_shr:2
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xF, 0xF, false));  // row_shr:4
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xF, 0xF, false));  // row_shr:8
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x142, 0xA, 0xF, false));  // row_bcast:15
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x143, 0xC, 0xF, false));  // row_bcast:31
+  return x;
+}
+
 // ---- rank accumulator (257..1024 products, narrow output rows) -----------------------------
 // One wavefront per row.  The row's products are staged in LDS at their Gustavson positions
-// (X entry by X entry, each its Y row's columns and X_ik Y_kj), the distinct columns marked in
+// (consecutive products on consecutive lanes: each its Y entry's column and X_ik Y_kj, the
+// loads of several 64-product steps in flight together), the distinct columns marked in
 // a bitmap over the row's column window, and each X entry's products then added, in X order,
 // into an accumulator indexed by the column's rank among the row's distinct columns: the
 // columns of one Y row are distinct, so the adds of one X entry never collide, and the X
@@ -575,6 +589,8 @@ constexpr int32_t kRankT = 1024;    // products
 constexpr int32_t kRankX = 64;      // X entries (the adds take one step per X entry)
 constexpr int32_t kRankW = 65536;   // column window
 constexpr int32_t kRankD = 256;     // distinct columns
+constexpr int kRankSteps = 8;       // 64-product steps whose loads are issued together
+static_assert(kRankX <= 64, "one X entry per lane while staging");
 __global__ __launch_bounds__(64) void k_esc_rank(const int32_t *rows, int32_t nrows,
                                                  const int32_t *xrp, const int32_t *xcol,
                                                  const double *xval, const int32_t *xpref,
@@ -588,6 +604,8 @@ __global__ __launch_bounds__(64) void k_esc_rank(const int32_t *rows, int32_t nr
   __shared__ uint16_t s_pre[kRankW / 32];  // set bits in the words before
   __shared__ double s_acc[kRankD];
   __shared__ int32_t s_xo[kRankX + 1];  // X entries' first positions, then T
+  __shared__ int32_t s_yb[kRankX], s_mark[64];
+  __shared__ double s_xv[kRankX];
   const int lane = threadIdx.x;
   const int32_t slot = blockIdx.x;
   if (slot >= nrows) return;  // block-uniform
@@ -602,23 +620,66 @@ __global__ __launch_bounds__(64) void k_esc_rank(const int32_t *rows, int32_t nr
     overflow();
     return;
   }
-  // stage: lane l takes X entries l, l+64, ...
-  int32_t lo = INT_MAX, hi = -1;
-  for (int32_t e = lane; e < nx; e += 64) {
-    const int32_t k = xcol[xb + e];
-    const double xv = xval[xb + e];
-    const int32_t o = xpref[xb + e];
-    const int32_t yb = yrp[k], ye = yrp[k + 1];
-    s_xo[e] = o;
-    for (int32_t q = yb; q < ye; ++q) {
-      const int32_t c = ycol[q];
-      s_c[o + q - yb] = c;
-      s_v[o + q - yb] = xv * yval[q];
-      lo = min(lo, c);
-      hi = max(hi, c);
-    }
+  // stage the X entries (lane e holds entry e), then the products in Gustavson order, lane l
+  // taking products l, l + 64, ...: product p belongs to the last entry that starts at or
+  // before it (among entries with products).  Per 64-product step, each entry starting
+  // inside the step marks its first product's lane and a prefix maximum over the lanes, from
+  // the entry of the step's preceding product, gives every lane its entry.  kRankSteps steps'
+  // entries are found first, then their loads issued together, then their products staged.
+  int32_t my_o = 0, my_len = 0;
+  if (lane < nx) {
+    const int32_t k = xcol[xb + lane];
+    my_o = xpref[xb + lane];
+    const int32_t yb = yrp[k];
+    my_len = yrp[k + 1] - yb;
+    s_xo[lane] = my_o;
+    s_yb[lane] = yb;
+    s_xv[lane] = xval[xb + lane];
   }
   if (lane == 0) s_xo[nx] = T;
+  s_mark[lane] = -1;
+  __syncthreads();
+  const bool starts = lane < nx && my_len > 0;
+  int32_t lo = INT_MAX, hi = -1, carry = -1;
+  for (int32_t g0 = 0; g0 < T; g0 += 64 * kRankSteps) {
+    int32_t ed[kRankSteps], qd[kRankSteps];
+#pragma unroll
+    for (int d = 0; d < kRankSteps; ++d) {
+      const int32_t p0 = g0 + 64 * d;
+      ed[d] = 0;
+      qd[d] = 0;  // lanes past T load Y's first entry and discard it (T > 0: Y has entries)
+      if (p0 < T) {  // wavefront-uniform
+        if (starts && my_o >= p0 && my_o < p0 + 64) s_mark[my_o - p0] = lane;
+        __syncthreads();
+        int32_t e = s_mark[lane];
+        s_mark[lane] = -1;  // every slot is -1 again for the next step
+        e = max(wave_prefix_max(e), carry);
+        carry = __builtin_amdgcn_readlane(e, 63);
+        const int32_t p = p0 + lane;
+        if (p < T) {
+          ed[d] = e;
+          qd[d] = s_yb[e] + p - s_xo[e];
+        }
+      }
+    }
+    int32_t cd[kRankSteps];
+    double vd[kRankSteps];
+#pragma unroll
+    for (int d = 0; d < kRankSteps; ++d) {
+      cd[d] = ycol[qd[d]];
+      vd[d] = yval[qd[d]];
+    }
+#pragma unroll
+    for (int d = 0; d < kRankSteps; ++d) {
+      const int32_t p = g0 + 64 * d + lane;
+      if (p < T) {
+        s_c[p] = cd[d];
+        s_v[p] = s_xv[ed[d]] * vd[d];
+        lo = min(lo, cd[d]);
+        hi = max(hi, cd[d]);
+      }
+    }
+  }
   for (int off = 32; off >= 1; off >>= 1) {
     lo = min(lo, __shfl_xor(lo, off, 64));
     hi = max(hi, __shfl_xor(hi, off, 64));
@@ -721,18 +782,6 @@ __device__ __forceinline__ uint64_t xor_lane(uint64_t v, int lane) {
   const uint32_t lo = xor_lane<J>((uint32_t)v, lane);
   const uint32_t hi = xor_lane<J>((uint32_t)(v >> 32), lane);
   return ((uint64_t)hi << 32) | lo;
-}
-// Inclusive prefix maximum over the wavefront's lanes: row shifts by 1, 2, 4 and 8 within
-// each 16-lane row (lanes shifted in from outside the row read -1), then the last lane of
-// row 0 (of row 2) into row 1 (row 3), then the last lane of row 1 into rows 2 and 3.
-__device__ __forceinline__ int32_t wave_prefix_max(int32_t x) {
-  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xF, 0xF, false));  // row_shr:1
-  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xF, 0xF, false));  // row_shr:2
-  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xF, 0xF, false));  // row_shr:4
-  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xF, 0xF, false));  // row_shr:8
-  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x142, 0xA, 0xF, false));  // row_bcast:15
-  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x143, 0xC, 0xF, false));  // row_bcast:31
-  return x;
 }
 // Ascending bitonic sort of one key per lane across the wavefront (keys distinct).  Keys are
 // (column << 6 | lane): 32 bits while the columns stay below 2^26 (one cross-lane move per
