@@ -182,17 +182,41 @@ __global__ __launch_bounds__(kWave) void k_esc_group(
     s_a[lane] = a;
     __syncthreads();
     // product p of this chunk comes from the first entry s with incl[s] > p, at offset
-    // p - incl[s-1] in its row of Y: loads independent across lanes
-    for (int32_t p = gl; p < tot; p += G) {
-      int32_t lo = 0, hi = G - 1;
-      while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (s_incl[gb + mid] > p) hi = mid;
-        else lo = mid + 1;
+    // p - incl[s-1] in its row of Y: loads independent across lanes.  A lane's products are
+    // gl, gl + G, ... (at most P, since tot <= T <= G P): all are located first, then their
+    // loads issued together
+    int32_t qu[P], su[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      const int32_t p = gl + u * G;
+      su[u] = -1;
+      if (p < tot) {
+        int32_t lo = 0, hi = G - 1;
+        while (lo < hi) {
+          const int32_t mid = (lo + hi) >> 1;
+          if (s_incl[gb + mid] > p) hi = mid;
+          else lo = mid + 1;
+        }
+        su[u] = lo;
+        qu[u] = s_ys[gb + lo] + p - (lo > 0 ? s_incl[gb + lo - 1] : 0);
       }
-      const int32_t t = p - (lo > 0 ? s_incl[gb + lo - 1] : 0);
-      keys[pb + filled + p] = ycol[s_ys[gb + lo] + t];
-      vals[pb + filled + p] = s_a[gb + lo] * yval[s_ys[gb + lo] + t];
+    }
+    int32_t cu[P];
+    double yu[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      if (su[u] >= 0) {
+        cu[u] = ycol[qu[u]];
+        yu[u] = yval[qu[u]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      if (su[u] >= 0) {
+        const int32_t p = gl + u * G;
+        keys[pb + filled + p] = cu[u];
+        vals[pb + filled + p] = s_a[gb + su[u]] * yu[u];
+      }
     }
     __syncthreads();
     filled += tot;
