@@ -375,9 +375,10 @@ __global__ __launch_bounds__(BS) void k_esc_single(
   if (tid == BS - 1) ucnt[i] = s_scan[BS - 1];
 }
 
-// Rows with more distinct columns than the LDS table holds: a dense accumulator of ncols
-// entries per block in global memory (first touch starts from 0, adds in position order as
-// above); the result is extracted in column order by a block-wide scan of the touched flags.
+// Rows with more distinct columns than the LDS table holds, when their column windows need
+// more LDS tiles than the limit: a dense accumulator of ncols entries per block in global
+// memory (first touch starts from 0, adds in position order as above); the result is
+// extracted in column order by a block-wide scan of the touched flags.
 __global__ __launch_bounds__(kBlock) void k_esc_dense(
     const int32_t *rows, int32_t nrows, const int32_t *xrp, const int32_t *xcol,
     const double *xval, const int32_t *xpref, const int32_t *yrp, const int32_t *ycol,
@@ -779,8 +780,8 @@ __global__ __launch_bounds__(64) void k_esc_rank(const int32_t *rows, int32_t nr
 //          entries to the row's earlier ones;
 //   HASH   an open-addressing table of H slots (every column claimed by an LDS compare-and-
 //          swap, its sum starting from 0); a row whose distinct columns pass H/2 is listed in
-//          ovf[] for k_esc_dense.  At the end the occupied slots are compacted and sorted by
-//          column (bitonic, in LDS).
+//          ovf[] to be redone (LDS column tiles, or k_esc_dense).  At the end the occupied
+//          slots are compacted and sorted by column (bitonic, in LDS).
 // Value of lane (lane ^ J) of the wavefront.  J = 1, 2: a quad permutation (DPP); J = 4, 8:
 // the row shifts by J toward the lower lanes (row_shl, lane i reads i + J) and the higher
 // lanes (row_shr, lane i reads i - J), of which each lane keeps the one inside its J-group
@@ -1256,7 +1257,7 @@ void spgemm(const Csr &X, const Csr &Y, Arena &ar, Csr &C, hipStream_t s) {
   }
   // long rows: the dense window accumulator when Y's width fits the LDS (sized to the widest
   // row window; up to 2048 columns the whole width), else a 2048-slot hash table whose
-  // overflowing rows (more than 1024 distinct columns) go to k_esc_dense
+  // overflowing rows (more than 1024 distinct columns) are redone below
   const bool lds_bin = Y.ncols <= lds_cols_max();
   int32_t wmax = Y.ncols;
   int2 *win = nullptr;
