@@ -154,10 +154,12 @@ void sa_default_options(sa_options *o);
  * The root selection's rounds are launched back to back while the calling thread polls a
  * pinned status word written by the kernels (it spins on one host core meanwhile); if a word
  * does not arrive within SAAMG_STATUS_SPIN_NS nanoseconds (environment, default 20000000),
- * the thread synchronises the stream and reads the device flags instead.  Levels of at most
- * SAAMG_MIS_WG_MAX_N vertices (default 4096) run their rounds after the first inside one
- * workgroup, and levels from SAAMG_MIS_V_MIN_N vertices on (default 524288) give each thread
- * of a round's passes four vertices.  The result is the same in every case. */
+ * the thread synchronises the stream and reads the device flags instead.  The small readbacks
+ * of sizes and scalars (here and in the solves) are polled the same way, from a tag word the
+ * copy writes after its data, with the same limit before the stream is synchronised.  Levels
+ * of at most SAAMG_MIS_WG_MAX_N vertices (default 4096) run their rounds after the first
+ * inside one workgroup, and levels from SAAMG_MIS_V_MIN_N vertices on (default 524288) give
+ * each thread of a round's passes four vertices.  The result is the same in every case. */
 sa_status sa_setup(const sa_context *ctx, const sa_csr *A, const double *nullspace,
                    const sa_options *o, sa_hierarchy **out);
 

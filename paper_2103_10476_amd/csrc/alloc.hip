@@ -9,6 +9,9 @@
 // that used it has finished before its next owner's kernels start; no event is needed.
 // When hipMalloc fails, every cached block is returned to the driver (after a device
 // synchronisation) and the allocation is retried once.
+#include <atomic>
+#include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -165,20 +168,21 @@ void dev_cache_stats(size_t *in_use, size_t *cached) {
 // ---- pinned staging for readbacks ---------------------------------------------------------
 // Copies into pageable host memory go through a driver bounce buffer and cost ~100 us each;
 // each thread stages readbacks in a pinned buffer of its own instead.  Buffers are recycled
-// through a process-wide list when their thread ends (no HIP call at thread exit).  A second
-// per-thread buffer, coherent (fine-grained: kernels' system-scope stores reach it without a
-// synchronise), holds status words that the thread polls while kernels run.
+// through a process-wide list when their thread ends (no HIP call at thread exit).  Two more
+// per-thread buffers are coherent (fine-grained: kernels' system-scope stores reach them
+// without a synchronise): one holds status words that the thread polls while kernels run, the
+// other the small readbacks, whose arrival the thread sees from a tag word written after them.
 namespace {
 struct PinnedPool {
   std::mutex mu;
-  std::vector<std::pair<void *, size_t>> spare[2];  // [0] default, [1] coherent
+  std::vector<std::pair<void *, size_t>> spare[3];  // [0] default, [1], [2] coherent
 };
 PinnedPool &pinned_pool() {
   static PinnedPool *p = new PinnedPool;
   return *p;
 }
 struct PinnedHolder {
-  int kind;  // 0 default, 1 coherent
+  int kind;  // 0 default, 1 and 2 coherent
   void *p = nullptr;
   size_t n = 0;
   explicit PinnedHolder(int k) : kind(k) {}
@@ -189,7 +193,7 @@ struct PinnedHolder {
     pp.spare[kind].emplace_back(p, n);
   }
 };
-thread_local PinnedHolder t_pinned(0), t_status(1);
+thread_local PinnedHolder t_pinned(0), t_status(1), t_words(2);
 
 void *pinned_buffer(PinnedHolder &h, size_t bytes) {
   if (h.p && h.n >= bytes) return h.p;
@@ -221,10 +225,18 @@ void *pinned_buffer(PinnedHolder &h, size_t bytes) {
 void *pinned_staging(size_t bytes) { return pinned_buffer(t_pinned, bytes); }
 void *pinned_status(size_t bytes) { return pinned_buffer(t_status, bytes); }
 
-// Small readbacks: one workgroup copies the words straight into the pinned staging buffer
-// through its device mapping (cheaper than the runtime's copy kernel for a few bytes).
-__global__ void k_copy_words(uint32_t *dst, const uint32_t *src, int32_t nw) {
+// Small readbacks: one workgroup copies the words straight into the thread's coherent buffer
+// through its device mapping (cheaper than the runtime's copy kernel for a few bytes), then,
+// after a system-scope fence, writes the readback's tag; the host polls the tag instead of
+// synchronising the stream (~3 us less per readback, and the stream's earlier work is done by
+// then: the copy runs after it).
+constexpr int32_t kWordsMax = 1024;  // words per small readback; the tag follows them
+__global__ void k_copy_words(uint32_t *dst, const uint32_t *src, int32_t nw, uint32_t *tag,
+                             uint32_t seq) {
   for (int32_t i = threadIdx.x; i < nw; i += blockDim.x) dst[i] = src[i];
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) *(volatile uint32_t *)tag = seq;
 }
 
 void readback(void *host, const void *dev, size_t bytes, hipStream_t s) {
@@ -234,16 +246,45 @@ void readback(void *host, const void *dev, size_t bytes, hipStream_t s) {
     SA_HIP(hipStreamSynchronize(s));
     return;
   }
-  void *st = pinned_staging(bytes);
-  if (bytes <= 4096 && bytes % 4 == 0 && (uintptr_t)dev % 4 == 0) {
-    void *dst = nullptr;
-    SA_HIP(hipHostGetDevicePointer(&dst, st, 0));
-    k_copy_words<<<1, kBlock, 0, s>>>((uint32_t *)dst, (const uint32_t *)dev,
-                                      (int32_t)(bytes / 4));
+  if (bytes <= 4 * (size_t)kWordsMax && bytes % 4 == 0 && (uintptr_t)dev % 4 == 0) {
+    uint32_t *st = (uint32_t *)pinned_buffer(t_words, 4 * (kWordsMax + 1));
+    uint32_t *dst = nullptr;
+    SA_HIP(hipHostGetDevicePointer((void **)&dst, st, 0));
+    // a nonzero tag of this thread's own; the word is cleared first, so a tag left by an
+    // earlier readback (or an earlier owner of the buffer) is never taken for this one
+    static thread_local uint32_t seq = 0;
+    seq = seq + 1 == 0 ? 1 : seq + 1;
+    volatile uint32_t *tag = st + kWordsMax;
+    *tag = 0;
+    k_copy_words<<<1, kBlock, 0, s>>>(dst, (const uint32_t *)dev, (int32_t)(bytes / 4),
+                                      dst + kWordsMax, seq);
     SA_LAUNCH_CHECK();
-  } else {
-    SA_HIP(hipMemcpyAsync(st, dev, bytes, hipMemcpyDeviceToHost, s));
+    // wait at most SAAMG_STATUS_SPIN_NS (default 20 ms; 0: synchronise at once), then
+    // synchronise the stream, which also reports an earlier kernel's failure
+    int64_t spin_ns = 20000000;
+    if (const char *e = std::getenv("SAAMG_STATUS_SPIN_NS")) spin_ns = std::atoll(e);
+    bool seen = false;
+    if (spin_ns > 0) {
+      const auto t0 = std::chrono::steady_clock::now();
+      for (uint32_t polls = 0;; ++polls) {
+        if (*tag == seq) {
+          seen = true;
+          break;
+        }
+        if ((polls & 255u) == 255u &&
+            std::chrono::duration_cast<std::chrono::nanoseconds>(
+                std::chrono::steady_clock::now() - t0)
+                    .count() >= spin_ns)
+          break;
+      }
+    }
+    if (!seen) SA_HIP(hipStreamSynchronize(s));
+    std::atomic_thread_fence(std::memory_order_acquire);
+    std::memcpy(host, st, bytes);
+    return;
   }
+  void *st = pinned_staging(bytes);
+  SA_HIP(hipMemcpyAsync(st, dev, bytes, hipMemcpyDeviceToHost, s));
   SA_HIP(hipStreamSynchronize(s));
   std::memcpy(host, st, bytes);
 }
