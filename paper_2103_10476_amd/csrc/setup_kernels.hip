@@ -1189,7 +1189,8 @@ static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const
     if (std::chrono::duration_cast<std::chrono::nanoseconds>(now - wait_from).count() <
         spin_ns)
       continue;
-    // status not seen in time: every launched round's flag is final after a synchronise
+    // status not seen in time: every launched round's flag is final when the readback's copy
+    // runs (after them on the stream)
     int32_t hf[kRing];
     readback(hf, flags, sizeof(hf), s);
     for (; seen < launched && !done; ++seen)
@@ -1205,7 +1206,7 @@ static int32_t aggregate_impl(int32_t n, int64_t nnzG, const int32_t *grp, const
   SA_LAUNCH_CHECK();
   int32_t *rid = tmp.alloc<int32_t>(n + 1);
   exclusive_scan_i32(isr, rid, n, s);
-  const int32_t nc = read1(rid + n, s);  // synchronises the stream
+  const int32_t nc = read1(rid + n, s);  // returns once the stream's work so far is done
   if (one_wg) {
     // the workgroup's outcome, posted to the host-mapped word (read back if it is not seen)
     uint32_t v = hs[0];
